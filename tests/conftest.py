@@ -1,0 +1,25 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+@pytest.fixture(scope="session")
+def basis3():
+    import oracle
+    return oracle.load_basis(os.path.join(ROOT, "paper_2512_23569_amd", "data", "basis_ps8_c3.f64"), 8, 3)
+
+
+@pytest.fixture(scope="session")
+def basis1():
+    import oracle
+    return oracle.load_basis(os.path.join(ROOT, "paper_2512_23569_amd", "data", "basis_ps8_c1.f64"), 8, 1)

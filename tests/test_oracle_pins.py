@@ -1,0 +1,381 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix
+(no GPU).  Each test names the passage it pins."""
+import os
+
+import numpy as np
+import pytest
+import scipy.fft
+
+import oracle
+import synth
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+R2 = 1.0 / np.sqrt(2.0)
+
+
+def _read_rows(name):
+    rows = []
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# ---- Haar matrix: Sec. II-D, Eq. 7-8 -------------------------------------------
+
+def test_haar_h2_printed_eq7():
+    H = oracle.haar(2)
+    gold = np.array([[float(v) for v in r] for r in _read_rows("haar_h2.txt")]) * R2
+    assert np.array_equal(H, gold)
+
+
+def test_haar_h4_by_hand_from_eq8():
+    val = {"h": 0.5, "-h": -0.5, "r": R2, "-r": -R2, "0": 0.0}
+    gold = np.array([[val[v] for v in r] for r in _read_rows("haar_h4.txt")])
+    assert np.allclose(oracle.haar(4), gold, atol=1e-15, rtol=0)
+
+
+@pytest.mark.parametrize("K", [2, 4, 8, 16, 32, 64])
+def test_haar_orthonormal_and_dc_row(K):
+    H = oracle.haar(K)
+    assert np.allclose(H @ H.T, np.eye(K), atol=1e-14)
+    # first row equals the dominant circulant eigenvector 1/sqrt(K) (Eq. 18 remark)
+    assert np.allclose(H[0], 1.0 / np.sqrt(K), atol=1e-15)
+    # rows K/2.. are the finest differences of adjacent pairs (I (x) [1,-1] / sqrt 2)
+    for i in range(K // 2):
+        row = np.zeros(K)
+        row[2 * i], row[2 * i + 1] = R2, -R2
+        assert np.allclose(H[K // 2 + i], row)
+
+
+def test_haar_rejects_non_power_of_two():
+    with pytest.raises(oracle.OracleError):
+        oracle.haar(12)
+
+
+# ---- t-product: Sec. II-C, Eq. 2-6 -------------------------------------------
+
+def _rand_tensor(seed, c=3, ps=8):
+    return np.random.default_rng(seed).standard_normal((ps, ps, c))
+
+
+def test_bcirc_layout_eq2():
+    A = np.arange(2 * 2 * 3, dtype=float).reshape(2, 2, 3)
+    B = oracle.bcirc(A)
+    s = [A[:, :, k] for k in range(3)]
+    exp = np.block([[s[0], s[2], s[1]], [s[1], s[0], s[2]], [s[2], s[1], s[0]]])
+    assert np.array_equal(B, exp)
+
+
+def test_bcirc_route_equals_fft_route(basis3):
+    """Eq. 3 (block-circulant products) and Eq. 4-5 (slice products after an FFT) agree."""
+    U, V = basis3
+    for seed in range(3):
+        P = np.random.default_rng(seed).integers(0, 256, (8, 8, 3)).astype(float)
+        S = oracle.patch_forward(U, V, P)
+        S_fft = oracle.tprod_fft(oracle.tprod_fft(oracle.ttranspose(U), P), V)
+        assert np.max(np.abs(S - S_fft)) < 1e-10
+
+
+def test_identity_tensor_and_orthogonality(basis3):
+    U, V = basis3
+    Id = np.zeros((8, 8, 3))
+    Id[:, :, 0] = np.eye(8)
+    P = _rand_tensor(5)
+    assert np.allclose(oracle.patch_forward(Id, Id, P), P, atol=1e-13)
+    S = oracle.patch_forward(U, V, P)
+    assert abs(np.linalg.norm(S) - np.linalg.norm(P)) < 1e-10  # orthogonal tensors keep the norm
+    assert np.allclose(oracle.patch_inverse(U, V, S), P, atol=1e-10)
+
+
+def test_channel_shift_tensor_hand_derived():
+    """U^(1) = I, U^(0) = U^(2) = 0: from Eq. 2-3, (U^T * P)^(i) = P^((i+1) mod 3)."""
+    U = np.zeros((8, 8, 3))
+    U[:, :, 1] = np.eye(8)
+    Id = np.zeros((8, 8, 3))
+    Id[:, :, 0] = np.eye(8)
+    P = _rand_tensor(7)
+    S = oracle.patch_forward(U, Id, P)
+    for i in range(3):
+        assert np.allclose(S[:, :, i], P[:, :, (i + 1) % 3], atol=1e-14)
+
+
+def test_dct_basis_matches_scipy_dctn():
+    """With U = V = D^T (D = orthonormal DCT-II matrix) in slice 0, S = U^T P V is the 2-D DCT of each channel."""
+    D = scipy.fft.dct(np.eye(8), norm="ortho", axis=0)  # D @ x = dct(x)
+    U = np.zeros((8, 8, 3))
+    U[:, :, 0] = D.T
+    P = _rand_tensor(9)
+    S = oracle.patch_forward(U, U, P)
+    for ch in range(3):
+        assert np.allclose(S[:, :, ch], scipy.fft.dctn(P[:, :, ch], norm="ortho"), atol=1e-12)
+
+
+def test_c1_reduces_to_matrix_product(basis1):
+    U, V = basis1
+    P = _rand_tensor(11, c=1)
+    S = oracle.patch_forward(U, V, P)
+    assert np.allclose(S[:, :, 0], U[:, :, 0].T @ P[:, :, 0] @ V[:, :, 0], atol=1e-12)
+
+
+def test_learned_basis_is_orthogonal_and_real(basis3, basis1):
+    """Sec. III-B: U, V are orthogonal tensors (U^T * U = I)."""
+    for (U, V), c in ((basis3, 3), (basis1, 1)):
+        Id = np.zeros((8, 8, c))
+        Id[:, :, 0] = np.eye(8)
+        for T in (U, V):
+            assert np.isrealobj(T)
+            assert np.allclose(oracle.tprod_fft(oracle.ttranspose(T), T), Id, atol=1e-12)
+
+
+# ---- grouping: Sec. III-A, Eq. 9 ---------------------------------------------
+
+def _brute_groups(img, ps, s, W, K, gnum=6, gden=5):
+    """Brute force on tiny inputs with Python tuples, independent of the C loops."""
+    a = img.astype(np.int64) if img.ndim == 3 else img.astype(np.int64)[:, :, None]
+    h, w, c = a.shape
+    ys = list(range(0, h - ps + 1, s))
+    if ys[-1] != h - ps:
+        ys.append(h - ps)
+    xs = list(range(0, w - ps + 1, s))
+    if xs[-1] != w - ps:
+        xs.append(w - ps)
+    R = (W - 1) // 2
+    out_i, out_d = [], []
+    for y in ys:
+        for x in xs:
+            ref = a[y:y + ps, x:x + ps]
+            if c == 3:
+                n = [(ref[:, :, k] ** 2).sum() for k in range(3)]
+                green = gnum * gnum * n[1] >= gden * gden * max(n[0], n[2])
+                rp = ref[:, :, 1] if green else ref.sum(axis=2)
+            else:
+                green, rp = True, ref[:, :, 0]
+            cands = []
+            for yc in range(max(0, y - R), min(h - ps, y + R) + 1):
+                for xc in range(max(0, x - R), min(w - ps, x + R) + 1):
+                    p = a[yc:yc + ps, xc:xc + ps]
+                    pp = p[:, :, 1] if (c == 3 and green) else (p.sum(axis=2) if c == 3 else p[:, :, 0])
+                    cands.append((int(((rp - pp) ** 2).sum()), yc, xc))
+            cands.sort()
+            out_i.append([yc * w + xc for _, yc, xc in cands[:K]])
+            out_d.append([d for d, _, _ in cands[:K]])
+    return np.array(out_i), np.array(out_d)
+
+
+@pytest.mark.parametrize("h,w,c,K,W,s,seed", [(16, 16, 1, 4, 5, 2, 0), (24, 40, 3, 8, 7, 3, 1),
+                                               (20, 18, 3, 16, 9, 4, 2), (17, 23, 1, 8, 9, 5, 3)])
+def test_block_match_brute_force_with_planted_ties(h, w, c, K, W, s, seed):
+    rng = np.random.default_rng(seed)
+    img = rng.integers(0, 4, (h, w, c) if c == 3 else (h, w)).astype(np.uint8) * 60  # many ties
+    img[:4, :] = 0            # clipped-black region: zero distances
+    img[-3:, -5:] = 255       # clipped-white region
+    img[8:16, 2:10] = img[0:8, 8:16] if w >= 16 else img[8:16, 2:10]  # planted duplicate
+    idx, dist = oracle.block_match(img, 8, s, W, K)
+    bi, bd = _brute_groups(img, 8, s, W, K)
+    assert np.array_equal(idx, bi)
+    assert np.array_equal(dist, bd)
+
+
+def test_flat_image_groups_are_raster_order():
+    img = np.full((20, 20), 77, np.uint8)
+    idx, dist = oracle.block_match(img, 8, 4, 5, 8)
+    assert np.all(dist == 0)
+    # reference (0,0): clipped window rows 0..2, cols 0..2 -> raster order
+    assert list(idx[0]) == [0, 1, 2, 20, 21, 22, 40, 41]
+
+
+def test_reference_is_first_and_distances_symmetric():
+    clean, noisy, _ = synth.make_cfg("gray256_awgn25", h=48, w=48)
+    idx, dist = oracle.block_match(noisy, 8, 4, 9, 8)
+    ys = oracle.ref_grid(48, 8, 4)
+    r = 0
+    for y in ys:
+        for x in ys:
+            assert dist[r, 0] == 0 and idx[r, 0] == y * 48 + x
+            r += 1
+    assert np.all(np.diff(dist, axis=1) >= 0)
+
+
+def test_gcp_branch_exact_boundary():
+    """36 ||G||^2 >= 25 max(||R||^2, ||B||^2) selects the green distance (Eq. 9, gamma = 6/5)."""
+    img = np.zeros((8, 8, 3), np.uint8)
+    img[:, :, 1] = 5      # ||G||^2 = 64*25
+    img[:, :, 0] = 6      # ||R||^2 = 64*36 -> 36*25 == 25*36: boundary, green wins
+    assert oracle.gcp_green(img, 0, 0)
+    img[0, 0, 0] = 7      # R grows by 13 -> below the boundary
+    assert not oracle.gcp_green(img, 0, 0)
+
+
+def test_gcp_branch_changes_group_order():
+    """A case where green and channel-sum distances order candidates differently."""
+    h, w = 8, 10
+    img = np.zeros((h, w, 3), np.uint8)
+    img[:, :, 1] = 100
+    img[:, 1, 0] = 200   # candidate x=1 differs from the reference in red only
+    img[:, 9, 1] = 90    # candidate x=2 differs in green only (column 9 is inside it)
+    # reference (0,0): strong green -> green distance: x=1 is identical in green (d=0)
+    idx, dist = oracle.block_match(img, 8, 8, 5, 2)
+    assert oracle.gcp_green(img, 0, 0)
+    assert list(idx[0]) == [0, 1] and list(dist[0]) == [0, 0]
+    # make red dominant at the reference: channel-sum distance, x=1 now differs in column 0 of the patch
+    img2 = img.copy()
+    img2[:, 0, 0] = 250
+    img2[:, 2:, 0] = 250
+    assert not oracle.gcp_green(img2, 0, 0)
+    idx2, dist2 = oracle.block_match(img2, 8, 8, 5, 2)
+    bi, bd = _brute_groups(img2, 8, 8, 5, 2)
+    assert np.array_equal(idx2, bi) and np.array_equal(dist2, bd)
+
+
+def test_too_few_candidates_is_an_error():
+    img = np.zeros((9, 9), np.uint8)
+    with pytest.raises(oracle.OracleError):
+        oracle.block_match(img, 8, 1, 3, 8)  # 4 candidates < K = 8
+
+
+# ---- one-step filtering and aggregation: Eq. 19-21, Algorithm 1 -----------------
+
+def test_perfect_reconstruction_at_zero_threshold(basis3):
+    clean, noisy, _ = synth.make_cfg("rgb512_awgn50", h=40, w=48)
+    U, V = basis3
+    out = oracle.denoise(noisy, U, V, 0.0, s=4, W=9, K=8)
+    assert np.max(np.abs(out - noisy)) < 1e-9
+
+
+def test_infinite_threshold_kills_everything(basis1):
+    clean, noisy, _ = synth.make_cfg("gray256_awgn25", h=32, w=40)
+    U, V = basis1
+    out = oracle.denoise(noisy, U, V, np.inf, s=4, W=9, K=8)
+    assert np.max(np.abs(out)) == 0.0
+
+
+def test_uniform_aggregation_hand_computed():
+    """8x9 ramp, identity basis, K = 2, refs x = 0, 1.  tau = 10 keeps the Haar DC
+    ((p0+p1)/sqrt 2 ~ 300) and kills the differences (1/sqrt 2), so every patch
+    becomes m = (p0+p1)/2; column j of the output is then the average of the
+    patches covering it: 100.5 at j=0, 100+j inside, 107.5 at j=8."""
+    img = np.tile(100 + np.arange(9, dtype=np.uint8), (8, 1))
+    Id = np.zeros((8, 8, 1))
+    Id[:, :, 0] = np.eye(8)
+    out = oracle.denoise(img, Id, Id, 10.0, s=1, W=3, K=2)
+    exp = np.array([100.5] + [100.0 + j for j in range(1, 8)] + [107.5])
+    assert np.allclose(out, np.tile(exp, (8, 1)), atol=1e-12)
+
+
+def test_threshold_tie_is_kept():
+    """Eq. 20 keeps |S| >= tau: a flat group's only nonzero coefficient is the DC sqrt(K)*v."""
+    img = np.full((8, 12), 50, np.uint8)
+    Id = np.zeros((8, 8, 1))
+    Id[:, :, 0] = np.eye(8)
+    K = 4
+    H = oracle.haar(K)
+    dc = 0.0
+    for k in range(K):  # the DC exactly as accumulated (member order), so tau can equal it
+        dc += H[0, k] * 50.0
+    out_eq = oracle.denoise(img, Id, Id, abs(dc), s=1, W=7, K=K)
+    assert np.allclose(out_eq, 50.0)
+    out_above = oracle.denoise(img, Id, Id, np.nextafter(abs(dc), np.inf), s=1, W=7, K=K)
+    assert np.allclose(out_above, 0.0)
+
+
+def test_denoising_improves_psnr(basis1):
+    clean, noisy, _ = synth.make_cfg("gray256_awgn25", h=96, w=96)
+    U, V = basis1
+    out = oracle.denoise(noisy, U, V, 25 * oracle.tau_multiplier(1, 16), s=4, W=21, K=16)
+    assert synth.psnr(clean, out) > synth.psnr(clean, noisy) + 5.0
+
+
+def test_tau_multiplier_values():
+    """tau = sigma sqrt(2 log(c K ps^2)) (Sec. IV-A)."""
+    assert abs(oracle.tau_multiplier(1, 16) - np.sqrt(2 * np.log(1024))) < 1e-15
+    assert abs(oracle.tau_multiplier(3, 32) - 4.1768960) < 1e-6
+
+
+# ---- noise estimation: Sec. III-C-2 (Eq. 13-18), Sec. III-E-1 (Eq. 22-23) -----
+
+def _circ_eq13(P):
+    K = P.shape[0]
+    # row i (0-based) = (p_{i}, p_{i-1}, ..., p_{i+1}) as in the displayed matrix of Eq. 13
+    return np.stack([np.concatenate([P[(i - j) % K] for j in range(K)]) for i in range(K)])
+
+
+def _circ_eq14(P):
+    K = P.shape[0]
+    # r_i = [p_{(j+i-2 mod K)+1}]_j (1-based) of Eq. 14
+    return np.stack([np.concatenate([P[(j + i) % K] for j in range(K)]) for i in range(K)])
+
+
+@pytest.mark.parametrize("K", [4, 8, 16, 32])
+def test_circulant_spectrum_matches_eigh_both_conventions(K):
+    P = np.random.default_rng(K).integers(0, 256, (K, 24)).astype(np.int64)
+    lam, _ = oracle.circulant_spectrum(P)
+    full = np.array([lam[min(k, K - k)] for k in range(K)])
+    for circ in (_circ_eq13, _circ_eq14):
+        C = circ(P).astype(float)
+        ev = np.linalg.eigvalsh(C @ C.T)
+        assert np.allclose(np.sort(ev), np.sort(full), rtol=1e-9, atol=1e-6 * ev.max())
+    # Eq. 18: lambda_max = ||sum p||^2 ; Eq. 22: lambda_hat = ||sum (-1)^i p_i||^2
+    s = P.sum(axis=0)
+    alt = (P * ((-1) ** np.arange(K))[:, None]).sum(axis=0)
+    assert lam[0] == pytest.approx(float(s @ s), rel=1e-12)
+    assert lam[K // 2] == pytest.approx(float(alt @ alt), rel=1e-12)
+    assert lam[0] >= lam.max() - 1e-6  # nonnegative data: the DC pair is dominant
+
+
+def test_rank_identical_and_alternating_groups():
+    K = 32
+    base = np.random.default_rng(1).integers(50, 200, 192)
+    same = np.tile(base, (K, 1))
+    assert oracle.rank_position(same) == 1     # all non-DC eigenvalues are 0 = lambda_hat
+    delta = np.random.default_rng(2).integers(1, 5, 192)
+    alt = base[None, :] + ((-1) ** np.arange(K))[:, None] * delta[None, :]
+    assert oracle.rank_position(alt) == K - 1  # every eigenvalue except the DC lies below lambda_hat
+
+
+def test_rank_grows_with_noise_fig7(basis3):
+    """Fig. 7 trend: the rank of the alternating eigenvalue grows with the noise level."""
+    clean = synth.make_clean(64, 64, 3, seed=12)
+    means = []
+    for sigma in (2.0, 60.0):
+        noisy = synth.add_awgn(clean, sigma, 13)
+        idx, _ = oracle.block_match(noisy, 8, 4, 15, 32)
+        from oracle.estimator import group_vectors
+        ranks = [oracle.rank_position(group_vectors(noisy, idx[r])) for r in range(0, idx.shape[0], 3)]
+        means.append(np.mean(ranks))
+    assert means[1] > means[0] + 3
+
+
+def test_chen_rule_on_constructed_spectra():
+    # a pure-noise spectrum: all equal -> the first tail already has mean == median
+    assert oracle.chen_tail_sigma2(np.full(64, 9.0)) == 9.0
+    # large signal eigenvalues on top of a symmetric noise tail
+    lam = np.concatenate([[1000.0, 500.0, 300.0], 9.0 + np.linspace(-1, 1, 61)])
+    assert oracle.chen_tail_sigma2(lam) == pytest.approx(9.0, abs=1e-12)
+
+
+def test_sigma_est_flat_image_awgn():
+    """Flat image + AWGN: the covariance is sigma^2 I up to sampling; within 3%."""
+    for sigma in (10.0, 30.0):
+        clean = np.full((256, 256, 3), 128, np.uint8)
+        noisy = synth.add_awgn(clean, sigma, 5)
+        est = oracle.sigma_est_tiles(noisy)
+        assert np.all(np.abs(est / sigma - 1) < 0.03), est
+
+
+def test_splitmix64_published_outputs():
+    vals = [int(r[0], 16) for r in _read_rows("splitmix64.txt")]
+    from oracle.estimator import GOLDEN, MASK64
+    assert [oracle.splitmix64((n * GOLDEN) & MASK64) for n in (1, 2, 3)] == vals
+
+
+def test_vote_majority_and_adjustment():
+    clean = synth.make_clean(128, 128, 3, seed=21)
+    noisy = synth.add_awgn(clean, 10.0, 22)
+    idx, _ = oracle.block_match(noisy, 8, 4, 15, 32)
+    sig, votes, nv, ranks = oracle.sigma_hat_tiles(noisy, idx, np.array([10.0]), 8, 4, return_votes=True)
+    yes = sum(1 for a in ranks[0] if a <= 13)
+    assert votes[0] == yes and nv[0] == 15
+    assert sig[0] == (10.0 / 1.2 if 2 * yes > 15 else 10.0)
