@@ -1,0 +1,155 @@
+/*
+ * htsvd.h -- C ABI of the MI355X (gfx950) Haar-tSVD denoising library.
+ *
+ * Method: "Image Denoising Using Global and Local Circulant Representation"
+ * (Kong, Yang, Zhang).  For every reference patch on a regular grid the
+ * library groups the K most similar patches inside a search window
+ * (Sec. III-A, Eq. 9), projects the group with the shared t-SVD basis and a
+ * Haar transform along the group (Sec. III-D, Eq. 19), hard-thresholds the
+ * coefficients (Eq. 20), inverts the transform (Eq. 21) and averages the
+ * patches back into the image (Algorithm 1).  The noise level comes from the
+ * caller, from a plain patch-covariance estimator adjusted by the
+ * circulant-eigenvalue vote of Eq. 22-23 (Sec. III-E-1), or from a small
+ * learned network.
+ *
+ * Conventions for every entry point:
+ *  - Image pointers named d_* are DEVICE pointers (HIP global memory) owned
+ *    by the caller; h_* pointers are host memory.  Buffers must not alias.
+ *  - Input images are uint8, row-major, channels interleaved (HWC):
+ *    pixel (y, x, ch) at d_in[y*in_stride + x*c + ch]; in_stride is in bytes
+ *    and >= w*c.  Outputs are float32 HWC on the 0..255 scale, unclipped,
+ *    out_stride in elements and >= w*c.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *    work asynchronously on it and return a status synchronously for
+ *    argument errors; device faults surface from the next call or from
+ *    htsvd_sync().  A context is not thread-safe; use one per thread.
+ *  - On any non-OK status nothing has been enqueued, and
+ *    htsvd_last_error() returns a message for the calling thread.
+ *  - The context owns its workspace (grown on demand, freed by
+ *    htsvd_destroy); buffers passed in are never freed by the library.
+ */
+#ifndef HTSVD_H
+#define HTSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HTSVD_OK = 0,
+    HTSVD_EINVAL = -1,  /* null pointer, bad parameter value */
+    HTSVD_ESHAPE = -2,  /* image too small, too few candidates for K, stride too small */
+    HTSVD_ENOMEM = -3,  /* device allocation failed */
+    HTSVD_EDEVICE = -4, /* HIP runtime error (including deferred kernel faults) */
+    HTSVD_ENOTSUP = -5, /* parameter combination this build does not support */
+    HTSVD_ESTATE = -6   /* missing basis or network weights */
+} htsvd_status;
+
+/* Pass as `sigma` to estimate the noise level from the image. */
+#define HTSVD_SIGMA_AUTO (-1.0f)
+
+/* Method parameters (htsvd_default_params fills the paper's defaults). */
+typedef struct {
+    int32_t ps;          /* patch side; 8 (Sec. IV-A) is the only supported value */
+    int32_t stride;      /* reference-grid step in pixels, >= 1 (grid: 0, s, 2s, ..., plus the last position) */
+    int32_t window;      /* odd search-window side W, 3..31, clipped at the image border */
+    int32_t K;           /* group size, a power of two in {4, 8, 16, 32} (Sec. III-C-2 needs 2^n) */
+    double tau_mult;     /* tau = sigma * tau_mult; <= 0 selects sqrt(2 ln(c K ps^2)) (Sec. IV-A) */
+    int32_t adaptive;    /* 1: adjust sigma per sub-image by the vote of Eq. 23 */
+    double beta;         /* Eq. 23 divisor, 1.2 */
+    int32_t gamma_rank;  /* Eq. 23 rank bound, 13 */
+    int32_t gcp_num;     /* Eq. 9 green-prior weight gamma = gcp_num/gcp_den (6/5 = 1.2) */
+    int32_t gcp_den;
+    int32_t estimator;   /* sigma source under HTSVD_SIGMA_AUTO: 0 plain covariance-eigenvalue estimator,
+                            1 learned per-block sigma map (plain estimator as fallback) */
+    int32_t subimage;    /* sub-image side for sigma estimation and votes, 128 */
+    int32_t n_vote;      /* sampled groups per sub-image for the vote, 15 */
+    uint64_t vote_seed;  /* seed of the counter-based SplitMix64 sampler of the vote */
+} htsvd_params;
+
+typedef struct htsvd_ctx htsvd_ctx;
+
+/* Creates a context on HIP device `device` (allocates nothing large). */
+htsvd_status htsvd_create(htsvd_ctx **out, int device);
+/* Frees the context, its workspace, graphs and weights.  NULL is ignored. */
+void htsvd_destroy(htsvd_ctx *ctx);
+/* Fills `out` with the defaults for c channels: ps 8, stride 4, window 31 (c=3) or 21 (c=1),
+ * K 32 (c=3) or 16 (c=1), tau_mult 0, adaptive 0, beta 1.2, gamma_rank 13, gcp 6/5,
+ * estimator 0, subimage 128, n_vote 15, vote_seed 0. */
+htsvd_status htsvd_default_params(int32_t c, htsvd_params *out);
+
+/* Sets the shared t-SVD basis pair (U, V) for c channels (Sec. III-B, "globally reused"
+ * bases, Eq. 11): host FP64 arrays of ps*ps*c values each, slice-major:
+ * U[(k*ps + i)*ps + j] = U(i, j, k).  Both tensors must be orthogonal (U^T * U = I);
+ * the library copies them (FP32 Fourier-domain slices for the transform, FP64 for the
+ * threshold guard band).  Returns HTSVD_EINVAL if they are not orthogonal to 1e-9. */
+htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double *h_U, const double *h_V);
+
+/* Number of reference positions along a side of length n (grid 0, s, 2s, ..., n-ps). */
+int32_t htsvd_ref_count(int32_t n, int32_t ps, int32_t stride);
+
+/* Grouping only (Sec. III-A, Eq. 9; Algorithm 1 "Grouping"): for every reference
+ * r = iy*nx + ix, the K most similar patches in ascending (distance, row, column) order.
+ * d_idx[r*K + k] = y*w + x (int32) of member k; d_dist[r*K + k] = its squared distance
+ * (green-channel or channel-sum distance, chosen per reference by Eq. 9), may be NULL.
+ * Distances are exact integers (int8 / fp16 matrix-core dot products). */
+htsvd_status htsvd_block_match(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                               int64_t in_stride, const htsvd_params *p, int32_t *d_idx, int32_t *d_dist,
+                               void *stream);
+
+/* Full denoising (Algorithm 1 with Eq. 19-21).  sigma > 0: known noise level;
+ * HTSVD_SIGMA_AUTO: estimated (p->estimator).  With p->adaptive the per-sub-image vote of
+ * Eq. 23 adjusts it.  d_out: h*w*c float32 (HWC, out_stride elements per row). */
+htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                           int64_t in_stride, float sigma, const htsvd_params *p, float *d_out,
+                           int64_t out_stride, void *stream);
+
+/* Denoising with a caller-provided threshold per reference (tau of reference r in
+ * d_tau_ref[r], FP64, n_ref entries).  Used to check the transform path against the oracle. */
+htsvd_status htsvd_denoise_tau(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                               int64_t in_stride, const double *d_tau_ref, const htsvd_params *p, float *d_out,
+                               int64_t out_stride, void *stream);
+
+/* Noise levels per sub-image (ceil(h/S) * ceil(w/S) tiles, S = p->subimage, row-major):
+ * d_sigma_est: plain estimate before the vote (FP64), d_sigma_hat: after Eq. 23 (FP64,
+ * equals d_sigma_est when p->adaptive is 0), d_votes: "adjust" votes per tile (int32).
+ * sigma > 0 uses the known level as sigma_est.  Any output pointer may be NULL. */
+htsvd_status htsvd_estimate_sigma(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                                  int64_t in_stride, float sigma, const htsvd_params *p, double *d_sigma_est,
+                                  double *d_sigma_hat, int32_t *d_votes, void *stream);
+
+/* Waits for `stream` and reports deferred device errors. */
+htsvd_status htsvd_sync(htsvd_ctx *ctx, void *stream);
+
+/* Message for the last non-OK status of the calling thread ("" if none). */
+const char *htsvd_last_error(void);
+
+/* Counters of the last denoise call, copied to the host (synchronises the device):
+ * h_count[0] = coefficients re-decided in FP64 because they fell within the guard band of
+ * tau, h_count[1] = near-threshold coefficients beyond the per-group FP64 list (decided in
+ * FP32).  h_count must hold 2 values. */
+htsvd_status htsvd_last_guard_count(htsvd_ctx *ctx, int64_t *h_count);
+
+/* Stage timing.  With timing enabled each call records a HIP event pair around each of its
+ * stages on its stream; htsvd_stage_times() waits for the pending pairs and returns, per
+ * stage, the summed milliseconds and the number of timed calls since htsvd_set_timing().
+ * h_ms (and h_calls if not NULL) must hold HTSVD_N_STAGES values. */
+enum {
+    HTSVD_STAGE_BM = 0,        /* grouping (block matching + top-K) */
+    HTSVD_STAGE_CLEAR = 1,     /* clearing the accumulators */
+    HTSVD_STAGE_FILTER = 2,    /* transform, threshold, inverse, aggregation */
+    HTSVD_STAGE_NORMALIZE = 3, /* division by the patch counts */
+    HTSVD_STAGE_SIGMA = 4,     /* noise estimation (plain or learned) and the vote */
+    HTSVD_N_STAGES = 5
+};
+htsvd_status htsvd_set_timing(htsvd_ctx *ctx, int32_t enable);
+htsvd_status htsvd_stage_times(htsvd_ctx *ctx, double *h_ms, int64_t *h_calls);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HTSVD_H */

@@ -1,0 +1,277 @@
+"""Python binding of libhtsvd (MI355X Haar-tSVD denoising).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libhtsvd.so.  PyTorch supplies device memory and the current stream.  The
+functions named htsvd_* mirror the C ABI of include/htsvd.h one to one; the
+Denoiser class is a small convenience layer over them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhtsvd.so")
+DATA_DIR = os.path.join(_HERE, "data")
+
+HTSVD_OK, HTSVD_EINVAL, HTSVD_ESHAPE, HTSVD_ENOMEM, HTSVD_EDEVICE, HTSVD_ENOTSUP, HTSVD_ESTATE = 0, -1, -2, -3, -4, -5, -6
+HTSVD_SIGMA_AUTO = -1.0
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EDEVICE", -5: "ENOTSUP", -6: "ESTATE"}
+
+
+class htsvd_params(ctypes.Structure):
+    _fields_ = [
+        ("ps", ctypes.c_int32), ("stride", ctypes.c_int32), ("window", ctypes.c_int32), ("K", ctypes.c_int32),
+        ("tau_mult", ctypes.c_double), ("adaptive", ctypes.c_int32), ("beta", ctypes.c_double),
+        ("gamma_rank", ctypes.c_int32), ("gcp_num", ctypes.c_int32), ("gcp_den", ctypes.c_int32),
+        ("estimator", ctypes.c_int32), ("subimage", ctypes.c_int32), ("n_vote", ctypes.c_int32),
+        ("vote_seed", ctypes.c_uint64),
+    ]
+
+    def replace(self, **kw) -> "htsvd_params":
+        p = htsvd_params()
+        ctypes.pointer(p)[0] = self
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class HtsvdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (%d): %s" % (_STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+_lib = None
+
+# C signatures: name -> (restype, argtypes)
+_i32, _i64, _f32, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p
+_PP = ctypes.POINTER(htsvd_params)
+_SIGS = {
+    "htsvd_create": (_i32, [ctypes.POINTER(_vp), ctypes.c_int]),
+    "htsvd_destroy": (None, [_vp]),
+    "htsvd_default_params": (_i32, [_i32, _PP]),
+    "htsvd_set_basis": (_i32, [_vp, _i32, _i32, _vp, _vp]),
+    "htsvd_ref_count": (_i32, [_i32, _i32, _i32]),
+    "htsvd_block_match": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _PP, _vp, _vp, _vp]),
+    "htsvd_denoise": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _i64, _vp]),
+    "htsvd_denoise_tau": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _vp, _PP, _vp, _i64, _vp]),
+    "htsvd_estimate_sigma": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _vp, _vp, _vp]),
+    "htsvd_sync": (_i32, [_vp, _vp]),
+    "htsvd_last_error": (ctypes.c_char_p, []),
+    "htsvd_last_guard_count": (_i32, [_vp, _vp]),
+    "htsvd_set_timing": (_i32, [_vp, _i32]),
+    "htsvd_stage_times": (_i32, [_vp, _vp, _vp]),
+}
+STAGES = ["bm", "clear", "filter", "normalize", "sigma"]
+
+
+def lib():
+    """Loads libhtsvd.so; raises if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libhtsvd.so is not built (run __graft_entry__.build() or "
+                              "python -m paper_2512_23569_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS.keys())
+
+
+def _check(status: int):
+    if status != HTSVD_OK:
+        raise HtsvdError(status, lib().htsvd_last_error().decode())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t, dtype=None, name="tensor"):
+    """Device pointer of a contiguous CUDA (HIP) tensor, or None."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _img_dims(t):
+    if t.dim() == 2:
+        h, w = t.shape
+        c = 1
+    elif t.dim() == 3:
+        h, w, c = t.shape
+    else:
+        raise ValueError("image must be (h, w) or (h, w, c)")
+    if t.stride(-1) != 1 and c > 1:
+        raise ValueError("channels must be contiguous")
+    if c > 1 and t.stride(1) != c:
+        raise ValueError("pixels of a row must be contiguous")
+    in_stride = t.stride(0)
+    return int(h), int(w), int(c), int(in_stride)
+
+
+# ---- one-to-one mirrors of the C ABI -------------------------------------------
+
+def htsvd_create(device: int = 0):
+    h = ctypes.c_void_p()
+    _check(lib().htsvd_create(ctypes.byref(h), device))
+    return h
+
+
+def htsvd_destroy(ctx):
+    lib().htsvd_destroy(ctx)
+
+
+def htsvd_default_params(c: int) -> htsvd_params:
+    p = htsvd_params()
+    _check(lib().htsvd_default_params(c, ctypes.byref(p)))
+    return p
+
+
+def htsvd_set_basis(ctx, ps: int, c: int, U_slices: np.ndarray, V_slices: np.ndarray):
+    u = np.ascontiguousarray(U_slices, dtype=np.float64).reshape(-1)
+    v = np.ascontiguousarray(V_slices, dtype=np.float64).reshape(-1)
+    _check(lib().htsvd_set_basis(ctx, ps, c, u.ctypes.data_as(_vp), v.ctypes.data_as(_vp)))
+
+
+def htsvd_ref_count(n: int, ps: int, stride: int) -> int:
+    return int(lib().htsvd_ref_count(n, ps, stride))
+
+
+def htsvd_block_match(ctx, d_in, h, w, c, in_stride, params, d_idx, d_dist=None, stream=None):
+    import torch
+    _check(lib().htsvd_block_match(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, c, in_stride, ctypes.byref(params),
+                                   _dptr(d_idx, torch.int32, "d_idx"), _dptr(d_dist, torch.int32, "d_dist"),
+                                   _stream(stream)))
+
+
+def htsvd_denoise(ctx, d_in, h, w, c, in_stride, sigma, params, d_out, out_stride, stream=None):
+    import torch
+    _check(lib().htsvd_denoise(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, c, in_stride, float(sigma),
+                               ctypes.byref(params), _dptr(d_out, torch.float32, "d_out"), out_stride,
+                               _stream(stream)))
+
+
+def htsvd_denoise_tau(ctx, d_in, h, w, c, in_stride, d_tau_ref, params, d_out, out_stride, stream=None):
+    import torch
+    _check(lib().htsvd_denoise_tau(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, c, in_stride,
+                                   _dptr(d_tau_ref, torch.float64, "d_tau_ref"), ctypes.byref(params),
+                                   _dptr(d_out, torch.float32, "d_out"), out_stride, _stream(stream)))
+
+
+def htsvd_estimate_sigma(ctx, d_in, h, w, c, in_stride, sigma, params, d_sigma_est=None, d_sigma_hat=None,
+                         d_votes=None, stream=None):
+    import torch
+    _check(lib().htsvd_estimate_sigma(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, c, in_stride, float(sigma),
+                                      ctypes.byref(params), _dptr(d_sigma_est, torch.float64, "d_sigma_est"),
+                                      _dptr(d_sigma_hat, torch.float64, "d_sigma_hat"),
+                                      _dptr(d_votes, torch.int32, "d_votes"), _stream(stream)))
+
+
+def htsvd_sync(ctx, stream=None):
+    _check(lib().htsvd_sync(ctx, _stream(stream)))
+
+
+def htsvd_last_error() -> str:
+    return lib().htsvd_last_error().decode()
+
+
+def htsvd_last_guard_count(ctx):
+    out = (ctypes.c_int64 * 2)()
+    _check(lib().htsvd_last_guard_count(ctx, ctypes.cast(out, _vp)))
+    return int(out[0]), int(out[1])
+
+
+def htsvd_set_timing(ctx, enable: bool):
+    _check(lib().htsvd_set_timing(ctx, 1 if enable else 0))
+
+
+def htsvd_stage_times(ctx):
+    """{stage: (total ms, timed calls)} since timing was enabled."""
+    ms = (ctypes.c_double * len(STAGES))()
+    calls = (ctypes.c_int64 * len(STAGES))()
+    _check(lib().htsvd_stage_times(ctx, ctypes.cast(ms, _vp), ctypes.cast(calls, _vp)))
+    return {s: (float(ms[i]), int(calls[i])) for i, s in enumerate(STAGES)}
+
+
+# ---- convenience layer ------------------------------------------------------------
+
+def load_basis_slices(c: int, ps: int = 8):
+    """The shipped basis pair for c channels as slice-major (c, ps, ps) FP64 arrays."""
+    raw = np.fromfile(os.path.join(DATA_DIR, "basis_ps8_c%d.f64" % c), dtype="<f8")
+    n = ps * ps * c
+    return raw[:n].reshape(c, ps, ps), raw[n:].reshape(c, ps, ps)
+
+
+class Denoiser:
+    """Owns one library context on one device, with the shipped bases loaded."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.ctx = htsvd_create(device)
+        for c in (1, 3):
+            U, V = load_basis_slices(c)
+            htsvd_set_basis(self.ctx, 8, c, U, V)
+
+    def close(self):
+        if self.ctx is not None:
+            htsvd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def params(c: int, **kw) -> htsvd_params:
+        return htsvd_default_params(c).replace(**kw)
+
+    def block_match(self, img, params, with_dist=True, stream=None):
+        import torch
+        h, w, c, st = _img_dims(img)
+        n_ref = htsvd_ref_count(h, 8, params.stride) * htsvd_ref_count(w, 8, params.stride)
+        idx = torch.empty((n_ref, params.K), dtype=torch.int32, device=img.device)
+        dist = torch.empty((n_ref, params.K), dtype=torch.int32, device=img.device) if with_dist else None
+        htsvd_block_match(self.ctx, img, h, w, c, st, params, idx, dist, stream)
+        return idx, dist
+
+    def denoise(self, img, sigma, params, out=None, stream=None):
+        import torch
+        h, w, c, st = _img_dims(img)
+        if out is None:
+            out = torch.empty(img.shape, dtype=torch.float32, device=img.device)
+        htsvd_denoise(self.ctx, img, h, w, c, st, sigma, params, out, out.stride(0), stream)
+        return out
+
+    def denoise_tau(self, img, tau_ref, params, out=None, stream=None):
+        import torch
+        h, w, c, st = _img_dims(img)
+        if out is None:
+            out = torch.empty(img.shape, dtype=torch.float32, device=img.device)
+        htsvd_denoise_tau(self.ctx, img, h, w, c, st, tau_ref, params, out, out.stride(0), stream)
+        return out
+
+    def guard_count(self):
+        return htsvd_last_guard_count(self.ctx)

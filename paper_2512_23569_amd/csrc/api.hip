@@ -1,0 +1,527 @@
+// Host runtime behind the C ABI of include/htsvd.h: argument validation, the context's
+// workspace and basis constants, and the stream-ordered launch sequence of one call.
+#include <math.h>
+#include <string.h>
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "../../include/htsvd.h"
+#include "common.h"
+
+namespace htsvd {
+hipError_t launch_denoise_groups_impl(const ImageGeom &g, int K, const BasisDev &b, const int32_t *idx,
+                                      const double *tau_ref, float *num, int64_t num_stride, int32_t *hits,
+                                      unsigned long long *gc, hipStream_t st);
+hipError_t launch_zero_rows(float *p, int64_t rows, int64_t cols, int64_t stride, hipStream_t st);
+hipError_t launch_fill_const(double *p, int n, double v, hipStream_t st);
+int bm_lds_bytes(int s, int W, int h, int w);
+}  // namespace htsvd
+
+using namespace htsvd;
+
+struct htsvd_ctx {
+    int device = 0;
+    BasisDev basis[2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [0]: c=1, [1]: c=3
+    bool has_basis[2] = {false, false};
+    void *ws = nullptr;
+    size_t ws_size = 0;
+    unsigned long long *d_guard = nullptr;  // [0] re-decided in FP64, [1] past the per-group list
+    // Optional per-stage timing with HIP events recorded on the call's stream.
+    bool timing = false;
+    hipEvent_t ev[2 * HTSVD_N_STAGES] = {};
+    bool ev_pending[HTSVD_N_STAGES] = {};
+    double stage_ms[HTSVD_N_STAGES] = {};
+    int64_t stage_calls[HTSVD_N_STAGES] = {};
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+htsvd_status fail(htsvd_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+htsvd_status hip_fail(hipError_t e, const char *what) {
+    return fail(HTSVD_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Validates image geometry and method parameters; fills geometry and parameters.
+htsvd_status validate(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c, int64_t in_stride,
+                      const htsvd_params *p, ImageGeom *g, MethodParams *mp, bool need_basis) {
+    if (!ctx) return fail(HTSVD_EINVAL, "null context");
+    if (!d_in) return fail(HTSVD_EINVAL, "null input image");
+    if (!p) return fail(HTSVD_EINVAL, "null params");
+    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    if (p->ps != PS) return fail(HTSVD_ENOTSUP, "only ps = 8 is supported");
+    if (p->window < 3 || p->window > MAX_WINDOW || (p->window & 1) == 0)
+        return fail(HTSVD_EINVAL, "window must be odd and in [3, 31]");
+    if (!(p->K == 4 || p->K == 8 || p->K == 16 || p->K == 32))
+        return fail(HTSVD_ENOTSUP, "K must be 4, 8, 16 or 32");
+    if (p->stride < 1) return fail(HTSVD_EINVAL, "stride must be >= 1");
+    if ((REF_TILE - 1) * p->stride + p->window > MAX_UNION)
+        return fail(HTSVD_ENOTSUP, "3*stride + window must not exceed 64");
+    if (p->gcp_num < 1 || p->gcp_den < 1 || p->gcp_num > 1000 || p->gcp_den > 1000)
+        return fail(HTSVD_EINVAL, "gcp_num/gcp_den must be in [1, 1000]");
+    if (h < PS || w < PS) return fail(HTSVD_ESHAPE, "image smaller than one patch");
+    if (in_stride < (int64_t)w * c) return fail(HTSVD_EINVAL, "in_stride < w*c");
+    if ((int64_t)h * w > (int64_t)1 << 30) return fail(HTSVD_ENOTSUP, "image larger than 2^30 pixels");
+    const int R = (p->window - 1) / 2;
+    const int mh = (R < h - PS ? R : h - PS) + 1, mw = (R < w - PS ? R : w - PS) + 1;
+    if (mh * mw < p->K) return fail(HTSVD_ESHAPE, "a clipped search window holds fewer than K candidates");
+    if (need_basis && !ctx->has_basis[c == 3]) return fail(HTSVD_ESTATE, "no basis set for this channel count");
+    if (p->subimage != 128) return fail(HTSVD_ENOTSUP, "subimage must be 128");
+    if (p->adaptive) {
+        if (p->n_vote < 1 || p->n_vote > 1024) return fail(HTSVD_EINVAL, "n_vote must be in [1, 1024]");
+        if (!(p->beta > 0.0)) return fail(HTSVD_EINVAL, "beta must be > 0");
+    }
+    g->img = d_in;
+    g->stride = in_stride;
+    g->h = h;
+    g->w = w;
+    g->c = c;
+    g->s = p->stride;
+    g->ny = ref_count(h, p->stride);
+    g->nx = ref_count(w, p->stride);
+    mp->W = p->window;
+    mp->K = p->K;
+    mp->gnum = p->gcp_num;
+    mp->gden = p->gcp_den;
+    return HTSVD_OK;
+}
+
+// Grows the context workspace to at least `bytes` (synchronises the device before freeing).
+htsvd_status ensure_ws(htsvd_ctx *ctx, size_t bytes) {
+    if (ctx->ws_size >= bytes) return HTSVD_OK;
+    hipError_t e;
+    if (ctx->ws) {
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "synchronise before workspace growth");
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_size = 0;
+    }
+    size_t sz = bytes + (bytes >> 3);
+    e = hipMalloc(&ctx->ws, sz);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HTSVD_ENOMEM, "workspace allocation failed");
+    }
+    ctx->ws_size = sz;
+    return HTSVD_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+double default_mult(int c, int K) { return sqrt(2.0 * log((double)c * K * PS * PS)); }
+
+// Workspace carve-up for one denoise call.
+struct Ws {
+    int32_t *idx;
+    int32_t *hits;
+    double *tau;
+    double *sig_est;
+    double *sig_hat;
+    int32_t *votes;
+    double *cov;
+    size_t total;
+};
+
+Ws plan_ws(void *base, const ImageGeom &g, int K, int tile) {
+    Ws w;
+    const int64_t n_ref = (int64_t)g.ny * g.nx;
+    const int64_t n_tiles = (int64_t)((g.h + tile - 1) / tile) * ((g.w + tile - 1) / tile);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return (char *)base + o;
+    };
+    w.idx = (int32_t *)take(sizeof(int32_t) * n_ref * K);
+    w.hits = (int32_t *)take(sizeof(int32_t) * (size_t)g.h * g.w);
+    w.tau = (double *)take(sizeof(double) * n_ref);
+    w.sig_est = (double *)take(sizeof(double) * n_tiles);
+    w.sig_hat = (double *)take(sizeof(double) * n_tiles);
+    w.votes = (int32_t *)take(sizeof(int32_t) * n_tiles);
+    w.cov = (double *)take(sizeof(double) * n_tiles * g.c);  // per-channel tail variances
+    w.total = off;
+    return w;
+}
+
+// Stage timing: an event pair per stage; the elapsed time of the previous pair is
+// harvested (after it completed) when the stage is recorded again or on request.
+void harvest(htsvd_ctx *ctx, int s) {
+    if (!ctx->ev_pending[s]) return;
+    float ms = 0.f;
+    if (hipEventSynchronize(ctx->ev[2 * s + 1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, ctx->ev[2 * s], ctx->ev[2 * s + 1]) == hipSuccess) {
+        ctx->stage_ms[s] += ms;
+        ctx->stage_calls[s] += 1;
+    }
+    ctx->ev_pending[s] = false;
+}
+
+struct StageScope {
+    htsvd_ctx *ctx;
+    int s;
+    hipStream_t st;
+    StageScope(htsvd_ctx *c, int stage, hipStream_t stream) : ctx(c), s(stage), st(stream) {
+        if (!ctx->timing) return;
+        harvest(ctx, s);
+        (void)hipEventRecord(ctx->ev[2 * s], st);
+    }
+    ~StageScope() {
+        if (!ctx->timing) return;
+        (void)hipEventRecord(ctx->ev[2 * s + 1], st);
+        ctx->ev_pending[s] = true;
+    }
+};
+
+// The denoising sequence after tau is known: grouping, filtering, aggregation, normalisation.
+htsvd_status run_bm(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &mp, const Ws &w, hipStream_t st) {
+    StageScope sc(ctx, HTSVD_STAGE_BM, st);
+    hipError_t e = launch_block_match(g, mp, w.idx, nullptr, st);
+    if (e != hipSuccess) return hip_fail(e, "block matching");
+    return HTSVD_OK;
+}
+
+// Noise level per sub-image: sigma_est (known or plain estimator), then the Eq. 23 vote.
+// Needs the groups (w.idx) when p->adaptive is set.  Leaves sigma_hat in w.sig_hat.
+htsvd_status run_sigma(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &mp, const htsvd_params *p,
+                       float sigma, const Ws &w, hipStream_t st) {
+    StageScope sc(ctx, HTSVD_STAGE_SIGMA, st);
+    const int T = p->subimage;
+    const int n_tiles = ((g.h + T - 1) / T) * ((g.w + T - 1) / T);
+    hipError_t e;
+    if (sigma > 0.f) {
+        if ((e = launch_fill_const(w.sig_est, n_tiles, (double)sigma, st)) != hipSuccess) return hip_fail(e, "sigma");
+    } else {
+        if ((e = launch_sigma_est(g, T, w.cov, w.sig_est, st)) != hipSuccess) return hip_fail(e, "sigma estimation");
+    }
+    if (p->adaptive) {
+        if ((e = launch_vote(g, mp, w.idx, T, p->n_vote, p->vote_seed, p->gamma_rank, p->beta, w.sig_est,
+                             w.sig_hat, w.votes, st)) != hipSuccess)
+            return hip_fail(e, "vote");
+    } else {
+        if ((e = hipMemcpyAsync(w.sig_hat, w.sig_est, sizeof(double) * n_tiles, hipMemcpyDeviceToDevice, st)) !=
+            hipSuccess)
+            return hip_fail(e, "sigma copy");
+        if ((e = launch_zero(w.votes, sizeof(int32_t) * n_tiles, st)) != hipSuccess) return hip_fail(e, "votes");
+    }
+    return HTSVD_OK;
+}
+
+htsvd_status run_filter(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &mp, const Ws &w,
+                        const double *tau, float *d_out, int64_t out_stride, hipStream_t st) {
+    hipError_t e;
+    {
+        StageScope sc(ctx, HTSVD_STAGE_CLEAR, st);
+        if ((e = launch_zero_rows(d_out, g.h, (int64_t)g.w * g.c, out_stride, st)) != hipSuccess)
+            return hip_fail(e, "zero output");
+        if ((e = launch_zero(w.hits, sizeof(int32_t) * (size_t)g.h * g.w, st)) != hipSuccess)
+            return hip_fail(e, "zero hits");
+        if ((e = launch_zero(ctx->d_guard, 2 * sizeof(unsigned long long), st)) != hipSuccess)
+            return hip_fail(e, "zero counters");
+    }
+    {
+        StageScope sc(ctx, HTSVD_STAGE_FILTER, st);
+        if ((e = launch_denoise_groups_impl(g, mp.K, ctx->basis[g.c == 3], w.idx, tau, d_out, out_stride, w.hits,
+                                            ctx->d_guard, st)) != hipSuccess)
+            return hip_fail(e, "filtering");
+    }
+    {
+        StageScope sc(ctx, HTSVD_STAGE_NORMALIZE, st);
+        if ((e = launch_normalize(g, w.hits, d_out, out_stride, st)) != hipSuccess) return hip_fail(e, "normalise");
+    }
+    return HTSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+htsvd_status htsvd_create(htsvd_ctx **out, int device) {
+    if (!out) return fail(HTSVD_EINVAL, "null output pointer");
+    *out = nullptr;
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    htsvd_ctx *ctx = new htsvd_ctx();
+    ctx->device = device;
+    e = hipMalloc(&ctx->d_guard, 2 * sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        delete ctx;
+        return hip_fail(e, "counter allocation");
+    }
+    *out = ctx;
+    return HTSVD_OK;
+}
+
+void htsvd_destroy(htsvd_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (int i = 0; i < 2 * HTSVD_N_STAGES; ++i)
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    for (int i = 0; i < 2; ++i) {
+        if (ctx->basis[i].f32) (void)hipFree(ctx->basis[i].f32);
+        if (ctx->basis[i].T64) (void)hipFree(ctx->basis[i].T64);
+    }
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->d_guard) (void)hipFree(ctx->d_guard);
+    delete ctx;
+}
+
+htsvd_status htsvd_default_params(int32_t c, htsvd_params *out) {
+    if (!out) return fail(HTSVD_EINVAL, "null output pointer");
+    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    memset(out, 0, sizeof(*out));
+    out->ps = PS;
+    out->stride = 4;
+    out->window = c == 3 ? 31 : 21;
+    out->K = c == 3 ? 32 : 16;
+    out->tau_mult = 0.0;
+    out->adaptive = 0;
+    out->beta = 1.2;
+    out->gamma_rank = 13;
+    out->gcp_num = 6;
+    out->gcp_den = 5;
+    out->estimator = 0;
+    out->subimage = 128;
+    out->n_vote = 15;
+    out->vote_seed = 0;
+    return HTSVD_OK;
+}
+
+int32_t htsvd_ref_count(int32_t n, int32_t ps, int32_t stride) {
+    if (ps != PS) return 0;
+    return ref_count(n, stride);
+}
+
+htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double *h_U, const double *h_V) {
+    typedef std::complex<double> cd;
+    if (!ctx || !h_U || !h_V) return fail(HTSVD_EINVAL, "null argument");
+    if (ps != PS) return fail(HTSVD_ENOTSUP, "only ps = 8 is supported");
+    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    // Fourier-domain slices (DFT along the channel mode, Eq. 5): X_hat^(f) = sum_k X^(k) w^(f k).
+    const cd wv = std::polar(1.0, -2.0 * M_PI / c);
+    cd Uh[3][64], Vh[3][64];
+    for (int f = 0; f < c; ++f)
+        for (int e = 0; e < 64; ++e) {
+            cd u = 0, v = 0;
+            for (int k = 0; k < c; ++k) {
+                const cd tw = std::pow(wv, (double)((f * k) % c));
+                u += h_U[k * 64 + e] * tw;
+                v += h_V[k * 64 + e] * tw;
+            }
+            Uh[f][e] = u;
+            Vh[f][e] = v;
+        }
+    // Orthogonality: U_hat^(f)^H U_hat^(f) = I for every slice.
+    for (int f = 0; f < c; ++f)
+        for (int i = 0; i < 8; ++i)
+            for (int j = 0; j < 8; ++j) {
+                cd su = 0, sv = 0;
+                for (int a = 0; a < 8; ++a) {
+                    su += std::conj(Uh[f][a * 8 + i]) * Uh[f][a * 8 + j];
+                    sv += std::conj(Vh[f][a * 8 + i]) * Vh[f][a * 8 + j];
+                }
+                const double t = i == j ? 1.0 : 0.0;
+                if (std::abs(su - t) > 1e-9 || std::abs(sv - t) > 1e-9)
+                    return fail(HTSVD_EINVAL, "basis tensors are not orthogonal");
+            }
+    std::vector<float> f32(6 * 64, 0.f);
+    for (int e = 0; e < 64; ++e) {
+        f32[e] = (float)Uh[0][e].real();
+        f32[64 + e] = (float)Vh[0][e].real();
+        if (c == 3) {
+            f32[128 + e] = (float)Uh[1][e].real();
+            f32[192 + e] = (float)Uh[1][e].imag();
+            f32[256 + e] = (float)Vh[1][e].real();
+            f32[320 + e] = (float)Vh[1][e].imag();
+        }
+    }
+    // FP64 matrix of the forward patch transform S = U^T * G * V on slice-major vectors,
+    // built column by column from unit patches (Eq. 4: slice products in the Fourier domain).
+    const int P = 64 * c;
+    std::vector<double> T((size_t)P * P);
+    for (int p = 0; p < P; ++p) {
+        cd Gh[3][64];
+        for (int f = 0; f < c; ++f)
+            for (int e = 0; e < 64; ++e) Gh[f][e] = 0;
+        const int kin = p / 64, ein = p % 64;
+        for (int f = 0; f < c; ++f) Gh[f][ein] = std::pow(wv, (double)((f * kin) % c));
+        cd Sh[3][64];
+        for (int f = 0; f < c; ++f)
+            for (int i = 0; i < 8; ++i)
+                for (int j = 0; j < 8; ++j) {
+                    cd acc = 0;
+                    for (int a = 0; a < 8; ++a)
+                        for (int b = 0; b < 8; ++b)
+                            acc += std::conj(Uh[f][a * 8 + i]) * Gh[f][a * 8 + b] * Vh[f][b * 8 + j];
+                    Sh[f][i * 8 + j] = acc;
+                }
+        for (int k = 0; k < c; ++k)
+            for (int e = 0; e < 64; ++e) {
+                cd acc = 0;
+                for (int f = 0; f < c; ++f) acc += Sh[f][e] * std::pow(wv, -(double)((f * k) % c));
+                T[(size_t)(k * 64 + e) * P + p] = acc.real() / c;
+            }
+    }
+    const int slot = c == 3;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (!ctx->basis[slot].f32) {
+        if ((e = hipMalloc(&ctx->basis[slot].f32, sizeof(float) * 6 * 64)) != hipSuccess)
+            return fail(HTSVD_ENOMEM, "basis allocation");
+        if ((e = hipMalloc(&ctx->basis[slot].T64, sizeof(double) * 192 * 192)) != hipSuccess)
+            return fail(HTSVD_ENOMEM, "basis allocation");
+    }
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronise before basis upload");
+    if ((e = hipMemcpy(ctx->basis[slot].f32, f32.data(), sizeof(float) * 6 * 64, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "basis upload");
+    if ((e = hipMemcpy(ctx->basis[slot].T64, T.data(), sizeof(double) * P * P, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "basis upload");
+    ctx->has_basis[slot] = true;
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_block_match(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                               int64_t in_stride, const htsvd_params *p, int32_t *d_idx, int32_t *d_dist,
+                               void *stream) {
+    ImageGeom g;
+    MethodParams mp;
+    htsvd_status s = validate(ctx, d_in, h, w, c, in_stride, p, &g, &mp, false);
+    if (s != HTSVD_OK) return s;
+    if (!d_idx) return fail(HTSVD_EINVAL, "null index output");
+    hipError_t e = launch_block_match(g, mp, d_idx, d_dist, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "block matching");
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_denoise_tau(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                               int64_t in_stride, const double *d_tau_ref, const htsvd_params *p, float *d_out,
+                               int64_t out_stride, void *stream) {
+    ImageGeom g;
+    MethodParams mp;
+    htsvd_status s = validate(ctx, d_in, h, w, c, in_stride, p, &g, &mp, true);
+    if (s != HTSVD_OK) return s;
+    if (!d_tau_ref || !d_out) return fail(HTSVD_EINVAL, "null tau or output");
+    if (out_stride < (int64_t)w * c) return fail(HTSVD_EINVAL, "out_stride < w*c");
+    const int tile = p->subimage > 0 ? p->subimage : 128;
+    Ws w0 = plan_ws(nullptr, g, mp.K, tile);
+    if ((s = ensure_ws(ctx, w0.total)) != HTSVD_OK) return s;
+    Ws wk = plan_ws(ctx->ws, g, mp.K, tile);
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = run_bm(ctx, g, mp, wk, st)) != HTSVD_OK) return s;
+    return run_filter(ctx, g, mp, wk, d_tau_ref, d_out, out_stride, st);
+}
+
+htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                           int64_t in_stride, float sigma, const htsvd_params *p, float *d_out,
+                           int64_t out_stride, void *stream) {
+    ImageGeom g;
+    MethodParams mp;
+    htsvd_status s = validate(ctx, d_in, h, w, c, in_stride, p, &g, &mp, true);
+    if (s != HTSVD_OK) return s;
+    if (!d_out) return fail(HTSVD_EINVAL, "null output");
+    if (out_stride < (int64_t)w * c) return fail(HTSVD_EINVAL, "out_stride < w*c");
+    if (!(sigma > 0.f) && sigma != HTSVD_SIGMA_AUTO) return fail(HTSVD_EINVAL, "sigma must be > 0 or AUTO");
+    if (sigma == HTSVD_SIGMA_AUTO && p->estimator != 0) return fail(HTSVD_ENOTSUP, "learned estimator not built yet");
+    const int tile = p->subimage;
+    Ws w0 = plan_ws(nullptr, g, mp.K, tile);
+    if ((s = ensure_ws(ctx, w0.total)) != HTSVD_OK) return s;
+    Ws wk = plan_ws(ctx->ws, g, mp.K, tile);
+    const double mult = p->tau_mult > 0.0 ? p->tau_mult : default_mult(c, mp.K);
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = run_bm(ctx, g, mp, wk, st)) != HTSVD_OK) return s;
+    hipError_t e;
+    if (sigma > 0.f && !p->adaptive) {
+        e = launch_fill_tau(wk.tau, (int64_t)g.ny * g.nx, nullptr, (double)sigma, mult, g, tile, st);
+    } else {
+        if ((s = run_sigma(ctx, g, mp, p, sigma, wk, st)) != HTSVD_OK) return s;
+        e = launch_fill_tau(wk.tau, (int64_t)g.ny * g.nx, wk.sig_hat, 0.0, mult, g, tile, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "tau");
+    return run_filter(ctx, g, mp, wk, wk.tau, d_out, out_stride, st);
+}
+
+htsvd_status htsvd_estimate_sigma(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                                  int64_t in_stride, float sigma, const htsvd_params *p, double *d_sigma_est,
+                                  double *d_sigma_hat, int32_t *d_votes, void *stream) {
+    ImageGeom g;
+    MethodParams mp;
+    htsvd_status s = validate(ctx, d_in, h, w, c, in_stride, p, &g, &mp, false);
+    if (s != HTSVD_OK) return s;
+    if (!(sigma > 0.f) && sigma != HTSVD_SIGMA_AUTO) return fail(HTSVD_EINVAL, "sigma must be > 0 or AUTO");
+    if (sigma == HTSVD_SIGMA_AUTO && p->estimator != 0) return fail(HTSVD_ENOTSUP, "learned estimator not built yet");
+    const int tile = p->subimage;
+    Ws w0 = plan_ws(nullptr, g, mp.K, tile);
+    if ((s = ensure_ws(ctx, w0.total)) != HTSVD_OK) return s;
+    Ws wk = plan_ws(ctx->ws, g, mp.K, tile);
+    hipStream_t st = (hipStream_t)stream;
+    if (p->adaptive && (s = run_bm(ctx, g, mp, wk, st)) != HTSVD_OK) return s;
+    if ((s = run_sigma(ctx, g, mp, p, sigma, wk, st)) != HTSVD_OK) return s;
+    const int n_tiles = ((h + tile - 1) / tile) * ((w + tile - 1) / tile);
+    hipError_t e;
+    if (d_sigma_est &&
+        (e = hipMemcpyAsync(d_sigma_est, wk.sig_est, sizeof(double) * n_tiles, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return hip_fail(e, "copy sigma_est");
+    if (d_sigma_hat &&
+        (e = hipMemcpyAsync(d_sigma_hat, wk.sig_hat, sizeof(double) * n_tiles, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return hip_fail(e, "copy sigma_hat");
+    if (d_votes &&
+        (e = hipMemcpyAsync(d_votes, wk.votes, sizeof(int32_t) * n_tiles, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return hip_fail(e, "copy votes");
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_sync(htsvd_ctx *ctx, void *stream) {
+    if (!ctx) return fail(HTSVD_EINVAL, "null context");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronise");
+    return HTSVD_OK;
+}
+
+const char *htsvd_last_error(void) { return g_err.c_str(); }
+
+htsvd_status htsvd_set_timing(htsvd_ctx *ctx, int32_t enable) {
+    if (!ctx) return fail(HTSVD_EINVAL, "null context");
+    if (enable && !ctx->ev[0]) {
+        for (int i = 0; i < 2 * HTSVD_N_STAGES; ++i) {
+            hipError_t e = hipEventCreate(&ctx->ev[i]);
+            if (e != hipSuccess) return hip_fail(e, "event creation");
+        }
+    }
+    for (int s = 0; s < HTSVD_N_STAGES; ++s) {
+        ctx->ev_pending[s] = false;
+        ctx->stage_ms[s] = 0.0;
+        ctx->stage_calls[s] = 0;
+    }
+    ctx->timing = enable != 0;
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_stage_times(htsvd_ctx *ctx, double *h_ms, int64_t *h_calls) {
+    if (!ctx || !h_ms) return fail(HTSVD_EINVAL, "null argument");
+    for (int s = 0; s < HTSVD_N_STAGES; ++s) {
+        harvest(ctx, s);
+        h_ms[s] = ctx->stage_ms[s];
+        if (h_calls) h_calls[s] = ctx->stage_calls[s];
+    }
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_last_guard_count(htsvd_ctx *ctx, int64_t *h_count) {
+    if (!ctx || !h_count) return fail(HTSVD_EINVAL, "null argument");
+    unsigned long long v[2];
+    hipError_t e = hipMemcpy(v, ctx->d_guard, sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "counter copy");
+    h_count[0] = (int64_t)v[0];
+    h_count[1] = (int64_t)v[1];
+    return HTSVD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,462 @@
+// Block matching (grouping) for Haar-tSVD on gfx950.
+//
+// Sec. III-A, Eq. 9: the distance between the reference patch and a candidate is the
+// green-channel distance when gamma^2 ||G_ref||^2 >= max(||R_ref||^2, ||B_ref||^2), and the
+// distance of the channel averages otherwise (here the channel sum: same order and ties).
+// Distances are squared Euclidean and exact.  Algorithm 1 "Grouping" keeps the K
+// smallest, ordered by (distance, row, column).
+//
+// Mapping.  One workgroup (4 waves) owns a 4x4 tile of references.  The union of their
+// search windows (at most 64x64 candidate positions) is staged in LDS as
+//   - the shifted green (or gray) plane x-128 in int8, in 4 byte-shifted copies so any
+//     8-pixel row segment is a 4-byte-aligned pair of dwords, and
+//   - the shifted channel-sum plane R+G+B-384 in fp16 (exact: |v| <= 384), in 2 copies.
+// ||a-b||^2 = ||a||^2 + ||b||^2 - 2 a.b, where a.b for 16 references x 16 candidates is one
+// v_mfma_i32_16x16x64_i8 (one 8x8 patch = the whole k = 64 contraction), or two
+// v_mfma_f32_16x16x32_f16 for the sum plane (all partial sums are integers < 2^24, so the
+// fp32 accumulation is exact).  Distances of each reference land in an LDS table indexed
+// by the raster position inside its clipped window, so (distance, position) orders like
+// (distance, row, column).  Each wave then selects the K smallest keys of 4 references:
+// the K-th smallest of the 64 lane minima bounds the answer from above, the keys under
+// that bound are compacted and sorted with a wave bitonic network.
+#include "common.h"
+
+namespace htsvd {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int NREF = REF_TILE * REF_TILE;  // 16
+constexpr int SEL_CAP = 512;               // >= K * ceil(MAX_CAND / 64) for K <= 32
+
+struct TileInfo {
+    int ry[NREF], rx[NREF];        // reference position, ry = -1 if the slot is empty
+    int wy0[NREF], wx0[NREF];      // clipped window origin (candidate positions)
+    int wh[NREF], ww[NREF];        // clipped window size
+    int green[NREF];               // Eq. 9 branch: 1 green/gray distance, 0 channel-sum distance
+    int uy0, ux0, uh, uw;          // union of the windows
+    int any_sum;                   // some reference uses the channel-sum distance
+};
+
+// Byte layout of the dynamic LDS for one launch.
+struct BmLds {
+    int pitch8;     // bytes per row of one int8 plane copy
+    int pitch16;    // halves per row of one fp16 plane copy
+    int rows;       // plane rows (union rows + 7)
+    int off_p8, off_p16, off_n8, off_n16, off_tab, off_sel, total;
+};
+
+__device__ inline uint32_t lds_u32(const unsigned char *base, int byte_off) {
+    return *reinterpret_cast<const uint32_t *>(base + byte_off);
+}
+
+__device__ inline void wave_lds_sync() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = __shfl_xor(lo, m);
+    hi = __shfl_xor(hi, m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t readlane_u64(uint64_t v, int l) {
+    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of one u64 per lane across the 64 lanes of a wave.
+__device__ inline uint64_t wave_sort64(uint64_t v, int lane) {
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            uint64_t p = shfl_xor_u64(v, j);
+            bool up = (lane & k) == 0;
+            bool lower = (lane & j) == 0;
+            uint64_t mn = v < p ? v : p, mx = v < p ? p : v;
+            v = (lower == up) ? mn : mx;
+        }
+    }
+    return v;
+}
+
+__device__ inline int wave_excl_scan(int v, int lane, int *total) {
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    *total = __shfl(x, 63);
+    return x - v;
+}
+
+// Ascending bitonic sort of P (power of two <= SEL_CAP) u64 keys in LDS by one wave.
+__device__ void lds_sort(uint64_t *a, int P, int lane) {
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < P / 2; t += 64) {
+                int i = 2 * t - (t & (j - 1));
+                int m = i + j;
+                uint64_t x = a[i], y = a[m];
+                bool up = (i & k) == 0;
+                if ((x > y) == up) {
+                    a[i] = y;
+                    a[m] = x;
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void bm_kernel(ImageGeom g, MethodParams mp, int tiles_x, int n_tiles,
+                                                 BmLds L, int32_t *__restrict__ idx_out,
+                                                 int32_t *__restrict__ dist_out) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ TileInfo ti;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    // XCD-aware order: consecutive workgroups are dealt round-robin over the 8 XCDs; give
+    // each XCD a contiguous run of tiles so neighbouring tiles share its L2.
+    // The grid has 8*ceil(n_tiles/8) workgroups; b -> (b%8)*per + b/8 is a bijection on it.
+    int b;
+    {
+        const int per = (n_tiles + 7) / 8;
+        b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+        if (b >= n_tiles) return;
+    }
+    const int tyi = b / tiles_x, txi = b % tiles_x;
+    const int R = (mp.W - 1) / 2;
+
+    // ---- tile geometry ----
+    if (tid < NREF) {
+        const int iy = tyi * REF_TILE + tid / REF_TILE, ix = txi * REF_TILE + tid % REF_TILE;
+        if (iy < g.ny && ix < g.nx) {
+            const int y = ref_pos(iy, g.ny, g.h, g.s), x = ref_pos(ix, g.nx, g.w, g.s);
+            const int y0 = max(0, y - R), y1 = min(g.h - PS, y + R);
+            const int x0 = max(0, x - R), x1 = min(g.w - PS, x + R);
+            ti.ry[tid] = y; ti.rx[tid] = x;
+            ti.wy0[tid] = y0; ti.wx0[tid] = x0;
+            ti.wh[tid] = y1 - y0 + 1; ti.ww[tid] = x1 - x0 + 1;
+        } else {
+            ti.ry[tid] = -1; ti.rx[tid] = -1;
+            ti.wy0[tid] = 0; ti.wx0[tid] = 0; ti.wh[tid] = 0; ti.ww[tid] = 0;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int uy0 = 1 << 30, ux0 = 1 << 30, uy1 = -1, ux1 = -1;
+        for (int i = 0; i < NREF; ++i) {
+            if (ti.ry[i] < 0) continue;
+            uy0 = min(uy0, ti.wy0[i]); ux0 = min(ux0, ti.wx0[i]);
+            uy1 = max(uy1, ti.wy0[i] + ti.wh[i] - 1); ux1 = max(ux1, ti.wx0[i] + ti.ww[i] - 1);
+        }
+        ti.uy0 = uy0; ti.ux0 = ux0; ti.uh = uy1 - uy0 + 1; ti.uw = ux1 - ux0 + 1;
+    }
+    // Eq. 9 branch per reference from the raw channel norms (16 threads per reference).
+    if (g.c == 3) {
+        const int i = tid >> 4, sub = tid & 15;
+        int nr = 0, ng = 0, nb = 0;
+        if (ti.ry[i] >= 0) {
+            for (int p = sub; p < PS * PS; p += 16) {
+                const uint8_t *px = g.img + (int64_t)(ti.ry[i] + p / PS) * g.stride + (int64_t)(ti.rx[i] + p % PS) * 3;
+                nr += px[0] * px[0]; ng += px[1] * px[1]; nb += px[2] * px[2];
+            }
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+            nr += __shfl_xor(nr, o); ng += __shfl_xor(ng, o); nb += __shfl_xor(nb, o);
+        }
+        if (sub == 0) {
+            const int64_t mx = nr > nb ? nr : nb;
+            ti.green[i] = (int64_t)mp.gnum * mp.gnum * ng >= (int64_t)mp.gden * mp.gden * mx ? 1 : 0;
+        }
+    } else if (tid < NREF) {
+        ti.green[tid] = 1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int any = 0;
+        for (int i = 0; i < NREF; ++i) any |= (ti.ry[i] >= 0 && !ti.green[i]);
+        ti.any_sum = any;
+    }
+    const int uy0 = ti.uy0, ux0 = ti.ux0, uh = ti.uh, uw = ti.uw;
+    const int prow = uh + PS - 1, pcol = uw + PS - 1;
+
+    unsigned char *p8 = smem + L.off_p8;
+    _Float16 *p16 = reinterpret_cast<_Float16 *>(smem + L.off_p16);
+    int32_t *n8 = reinterpret_cast<int32_t *>(smem + L.off_n8);
+    int32_t *n16 = reinterpret_cast<int32_t *>(smem + L.off_n16);
+    uint32_t *tab = reinterpret_cast<uint32_t *>(smem + L.off_tab);
+    const int plane8 = L.rows * L.pitch8;
+    const int plane16 = L.rows * L.pitch16;
+
+    // ---- stage the shifted planes ----
+    for (int e = tid; e < prow * pcol; e += 256) {
+        const int r = e / pcol, col = e % pcol;
+        const uint8_t *px = g.img + (int64_t)(uy0 + r) * g.stride + (int64_t)(ux0 + col) * g.c;
+        int v8, vs = 0;
+        if (g.c == 3) {
+            v8 = (int)px[1] - 128;
+            vs = (int)px[0] + (int)px[1] + (int)px[2] - 384;
+        } else {
+            v8 = (int)px[0] - 128;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (col >= k) p8[k * plane8 + r * L.pitch8 + col - k] = (unsigned char)(int8_t)v8;
+        if (g.c == 3) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if (col >= k) p16[k * plane16 + r * L.pitch16 + col - k] = (_Float16)vs;
+        }
+    }
+    __syncthreads();
+
+    // ---- squared norms at every candidate position (horizontal then vertical 8-sums) ----
+    {
+        int32_t *rs8 = reinterpret_cast<int32_t *>(tab);          // prow x uw, tab is free now
+        int32_t *rs16 = rs8 + prow * uw;
+        for (int e = tid; e < prow * uw; e += 256) {
+            const int r = e / uw, col = e % uw;
+            int a = 0, s = 0;
+#pragma unroll
+            for (int j = 0; j < PS; ++j) {
+                const int v = (int8_t)p8[r * L.pitch8 + col + j];
+                a += v * v;
+                if (g.c == 3) {
+                    const int t = (int)p16[r * L.pitch16 + col + j];
+                    s += t * t;
+                }
+            }
+            rs8[e] = a;
+            rs16[e] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < uh * uw; e += 256) {
+            const int r = e / uw, col = e % uw;
+            int a = 0, s = 0;
+#pragma unroll
+            for (int i = 0; i < PS; ++i) {
+                a += rs8[(r + i) * uw + col];
+                s += rs16[(r + i) * uw + col];
+            }
+            n8[e] = a;
+            n16[e] = s;
+        }
+        __syncthreads();
+    }
+
+    // ---- distances on the matrix cores ----
+    {
+        const int i16 = lane & 15, q = lane >> 4;
+        // A fragments: reference i16, rows 2q, 2q+1 (int8) and rows q, q+4 (fp16).
+        int ar = ti.ry[i16] >= 0 ? ti.ry[i16] - uy0 : 0;
+        int ac = ti.ry[i16] >= 0 ? ti.rx[i16] - ux0 : 0;
+        v4i a8;
+        {
+            const int k = ac & 3;
+            const unsigned char *base = p8 + k * plane8;
+            const int o0 = (ar + 2 * q) * L.pitch8 + ac - k, o1 = o0 + L.pitch8;
+            a8[0] = (int)lds_u32(base, o0); a8[1] = (int)lds_u32(base, o0 + 4);
+            a8[2] = (int)lds_u32(base, o1); a8[3] = (int)lds_u32(base, o1 + 4);
+        }
+        v8h a16a = {}, a16b = {};
+        const bool any_sum = ti.any_sum != 0;
+        if (any_sum) {
+            const int k = ac & 1;
+            const _Float16 *base = p16 + k * plane16;
+            const _Float16 *ra = base + (ar + q) * L.pitch16 + ac - k;
+            const _Float16 *rb = base + (ar + q + 4) * L.pitch16 + ac - k;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) { a16a[t] = ra[t]; a16b[t] = rb[t]; }
+        }
+        // Per-lane info of the 4 references this lane's accumulators belong to.
+        int rwy0[4], rwx0[4], rwh[4], rww[4], rgreen[4], rn[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ii = 4 * q + r;
+            rwy0[r] = ti.wy0[ii]; rwx0[r] = ti.wx0[ii];
+            rwh[r] = ti.wh[ii]; rww[r] = ti.ww[ii];
+            rgreen[r] = ti.green[ii];
+            if (ti.ry[ii] >= 0) {
+                const int pe = (ti.ry[ii] - uy0) * uw + (ti.rx[ii] - ux0);
+                rn[r] = rgreen[r] ? n8[pe] : n16[pe];
+            } else {
+                rn[r] = 0;
+                rwh[r] = 0;
+            }
+        }
+        const int nU = uh * uw;
+        const int nchunks = (nU + 15) >> 4;
+        for (int chunk = wave; chunk < nchunks; chunk += 4) {
+            const int j = chunk * 16 + i16;
+            const int jj = j < nU ? j : 0;
+            const int cr = jj / uw, cc = jj % uw;
+            v4i b8;
+            {
+                const int k = cc & 3;
+                const unsigned char *base = p8 + k * plane8;
+                const int o0 = (cr + 2 * q) * L.pitch8 + cc - k, o1 = o0 + L.pitch8;
+                b8[0] = (int)lds_u32(base, o0); b8[1] = (int)lds_u32(base, o0 + 4);
+                b8[2] = (int)lds_u32(base, o1); b8[3] = (int)lds_u32(base, o1 + 4);
+            }
+            v4i acc8 = {0, 0, 0, 0};
+            acc8 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a8, b8, acc8, 0, 0, 0);
+            v4f acc16 = {0.f, 0.f, 0.f, 0.f};
+            if (any_sum) {
+                const int k = cc & 1;
+                const _Float16 *base = p16 + k * plane16;
+                const _Float16 *ra = base + (cr + q) * L.pitch16 + cc - k;
+                const _Float16 *rb = base + (cr + q + 4) * L.pitch16 + cc - k;
+                v8h b16a, b16b;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) { b16a[t] = ra[t]; b16b[t] = rb[t]; }
+                acc16 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a16a, b16a, acc16, 0, 0, 0);
+                acc16 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a16b, b16b, acc16, 0, 0, 0);
+            }
+            if (j < nU) {
+                const int cy = uy0 + cr, cx = ux0 + cc;
+                const int nb8 = n8[j], nb16 = n16[j];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int dy = cy - rwy0[r], dx = cx - rwx0[r];
+                    if ((unsigned)dy < (unsigned)rwh[r] && (unsigned)dx < (unsigned)rww[r]) {
+                        const int d = rgreen[r] ? rn[r] + nb8 - 2 * acc8[r] : rn[r] + nb16 - 2 * (int)acc16[r];
+                        tab[(4 * q + r) * MAX_CAND + dy * rww[r] + dx] = (uint32_t)d;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- top-K per reference ----
+    uint64_t *sel = reinterpret_cast<uint64_t *>(smem + L.off_sel) + wave * SEL_CAP;
+    const int K = mp.K;
+    for (int ii = wave; ii < NREF; ii += 4) {
+        if (ti.ry[ii] < 0) continue;
+        const int n = ti.wh[ii] * ti.ww[ii];
+        const uint32_t *row = tab + ii * MAX_CAND;
+        uint64_t lmin = ~0ull;
+        for (int p = lane; p < n; p += 64) {
+            const uint64_t key = ((uint64_t)row[p] << 10) | (uint64_t)p;
+            lmin = key < lmin ? key : lmin;
+        }
+        const uint64_t sorted = wave_sort64(lmin, lane);
+        const uint64_t theta = readlane_u64(sorted, K - 1);
+        int cnt = 0;
+        for (int p = lane; p < n; p += 64) {
+            const uint64_t key = ((uint64_t)row[p] << 10) | (uint64_t)p;
+            cnt += key <= theta;
+        }
+        int total;
+        int off = wave_excl_scan(cnt, lane, &total);
+        for (int p = lane; p < n; p += 64) {
+            const uint64_t key = ((uint64_t)row[p] << 10) | (uint64_t)p;
+            if (key <= theta) sel[off++] = key;
+        }
+        wave_lds_sync();
+        uint64_t mine;
+        if (total <= 64) {
+            uint64_t v = lane < total ? sel[lane] : ~0ull;
+            mine = wave_sort64(v, lane);
+        } else {
+            int P = 64;
+            while (P < total) P <<= 1;
+            for (int t = total + lane; t < P; t += 64) sel[t] = ~0ull;
+            wave_lds_sync();
+            lds_sort(sel, P, lane);
+            mine = lane < K ? sel[lane] : ~0ull;
+        }
+        if (lane < K) {
+            const int p = (int)(mine & 1023u);
+            const int y = ti.wy0[ii] + p / ti.ww[ii], x = ti.wx0[ii] + p % ti.ww[ii];
+            const int iy = tyi * REF_TILE + ii / REF_TILE, ix = txi * REF_TILE + ii % REF_TILE;
+            const int64_t r = (int64_t)iy * g.nx + ix;
+            idx_out[r * K + lane] = y * g.w + x;
+            if (dist_out) dist_out[r * K + lane] = (int32_t)(mine >> 10);
+        }
+        wave_lds_sync();
+    }
+}
+
+BmLds bm_lds_layout(int uh_max, int uw_max) {
+    BmLds L;
+    L.rows = uh_max + PS - 1;
+    L.pitch8 = ((uw_max + PS + 3) / 4) * 4 + 4;
+    L.pitch16 = ((uw_max + PS + 1) / 2) * 2 + 2;
+    int off = 0;
+    L.off_p8 = off;  off += 4 * L.rows * L.pitch8;
+    off = (off + 15) & ~15;
+    L.off_p16 = off; off += 2 * L.rows * L.pitch16 * 2;
+    off = (off + 15) & ~15;
+    L.off_n8 = off;  off += uh_max * uw_max * 4;
+    L.off_n16 = off; off += uh_max * uw_max * 4;
+    off = (off + 15) & ~15;
+    // the selection scratch reuses the plane/norm region once the distances are in the table
+    const int sel_bytes = 4 * SEL_CAP * 8;
+    int region = off;
+    L.off_sel = 0;
+    if (region < sel_bytes) region = sel_bytes;
+    off = (region + 15) & ~15;
+    L.off_tab = off;
+    int tab_bytes = NREF * MAX_CAND * 4;
+    const int rs_bytes = 2 * L.rows * uw_max * 4;  // row sums of the norm pass live in the table
+    if (tab_bytes < rs_bytes) tab_bytes = rs_bytes;
+    off += tab_bytes;
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+hipError_t launch_block_match(const ImageGeom &g, const MethodParams &mp, int32_t *idx, int32_t *dist,
+                              hipStream_t st) {
+    const int tiles_y = (g.ny + REF_TILE - 1) / REF_TILE, tiles_x = (g.nx + REF_TILE - 1) / REF_TILE;
+    const int n_tiles = tiles_y * tiles_x;
+    // largest union of windows over a tile: 3 grid steps plus the window, capped by the image
+    const int span = (REF_TILE - 1) * g.s + mp.W;
+    const int uh = span < g.h - PS + 1 ? span : g.h - PS + 1;
+    const int uw = span < g.w - PS + 1 ? span : g.w - PS + 1;
+    BmLds L = bm_lds_layout(uh, uw);
+    hipError_t e = prepare_dynamic_lds((const void *)bm_kernel, L.total, (int)sizeof(TileInfo));
+    if (e != hipSuccess) return e;
+    // round the grid up to a multiple of 8 so the XCD remap is a bijection onto [0, 8*per)
+    const int per = (n_tiles + 7) / 8;
+    hipLaunchKernelGGL(bm_kernel, dim3(8 * per), dim3(256), L.total, st, g, mp, tiles_x, n_tiles, L, idx, dist);
+    return hipGetLastError();
+}
+
+int bm_lds_bytes(int s, int W, int h, int w) {
+    const int span = (REF_TILE - 1) * s + W;
+    const int uh = span < h - PS + 1 ? span : h - PS + 1;
+    const int uw = span < w - PS + 1 ? span : w - PS + 1;
+    return bm_lds_layout(uh, uw).total;
+}
+
+hipError_t prepare_dynamic_lds(const void *kernel, int bytes, int static_bytes) {
+    int dev = 0, max_lds = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    if (bytes + static_bytes > max_lds) return hipErrorInvalidValue;
+    if (bytes > 64 * 1024) {
+        // opt-in for large dynamic LDS where the runtime asks for it; a runtime that does not
+        // need the opt-in may reject the attribute, which is harmless
+        if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
+            (void)hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+}  // namespace htsvd

@@ -1,0 +1,73 @@
+// Internal declarations shared by the HIP translation units of libhtsvd.
+// Not part of the public ABI (include/htsvd.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace htsvd {
+
+constexpr int PS = 8;             // patch side (Sec. IV-A); the kernels are written for 8
+constexpr int MAX_WINDOW = 31;    // largest supported odd search-window side
+constexpr int MAX_CAND = MAX_WINDOW * MAX_WINDOW;
+constexpr int REF_TILE = 4;       // references per tile side in block matching (4 x 4 = 16 = MFMA M)
+constexpr int MAX_UNION = 64;     // largest union of search windows per tile side (candidates)
+
+// Geometry of one image and its reference grid.
+struct ImageGeom {
+    const uint8_t *img;  // HWC uint8
+    int64_t stride;      // bytes per row
+    int h, w, c;
+    int ny, nx;          // reference grid size
+    int s;               // grid step
+};
+
+// Method parameters after validation.
+struct MethodParams {
+    int W, K, gnum, gden;
+};
+
+// Basis constants for the FP32 transform (device memory):
+//   c = 3: U0, V0 (slice f=0, real 8x8), U1r, U1i, V1r, V1i (slice f=1, complex 8x8),
+//          row-major [row][col]; slice f=2 is the conjugate of f=1.
+//   c = 1: U0, V0 only.
+// Plus the FP64 matrix T (P x P, P = 64c) with s = T g for one patch in slice-major
+// vector form, used to re-decide coefficients near the threshold.
+struct BasisDev {
+    float *f32;     // 6*64 floats
+    double *T64;    // P*P doubles
+};
+
+// Reference position along one side: 0, s, 2s, ... and the last position n-ps.
+__host__ __device__ inline int ref_pos(int i, int n_ref, int n, int s) {
+    return (i == n_ref - 1) ? (n - PS) : i * s;
+}
+
+__host__ __device__ inline int ref_count(int n, int s) {
+    if (n < PS || s < 1) return 0;
+    int c = (n - PS) / s + 1;
+    if ((n - PS) % s) c += 1;
+    return c;
+}
+
+// Makes `bytes` of dynamic LDS available to `kernel` (static LDS comes on top); fails with
+// hipErrorInvalidValue if the device cannot give a workgroup that much.
+hipError_t prepare_dynamic_lds(const void *kernel, int bytes, int static_bytes);
+
+// Launchers (stream-ordered, no synchronisation).
+hipError_t launch_block_match(const ImageGeom &g, const MethodParams &mp, int32_t *idx, int32_t *dist,
+                              hipStream_t st);
+hipError_t launch_normalize(const ImageGeom &g, const int32_t *hits, float *out, int64_t out_stride,
+                            hipStream_t st);
+hipError_t launch_fill_tau(double *tau_ref, int64_t n_ref, const double *sigma_tile, double sigma_const,
+                           double mult, const ImageGeom &g, int tile, hipStream_t st);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+
+// Noise estimation (plain): per sub-image covariance eigenvalues and the tail rule.
+hipError_t launch_sigma_est(const ImageGeom &g, int tile, double *cov_work, double *sigma_est,
+                            hipStream_t st);
+hipError_t launch_vote(const ImageGeom &g, const MethodParams &mp, const int32_t *idx, int tile, int n_vote,
+                       uint64_t seed, int gamma_rank, double beta, const double *sigma_est, double *sigma_hat,
+                       int32_t *votes, hipStream_t st);
+
+}  // namespace htsvd

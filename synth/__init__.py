@@ -104,7 +104,7 @@ def gray_layer(h: int, w: int, rng: np.random.Generator, texture: bool = False) 
 
 
 def _quantise(x: np.ndarray) -> np.ndarray:
-    return np.rint(np.clip(x, 0.0, 255.0)).astype(np.uint8)
+    return np.ascontiguousarray(np.rint(np.clip(x, 0.0, 255.0)).astype(np.uint8))
 
 
 def make_clean(h: int, w: int, c: int, seed: int, texture: bool = False) -> np.ndarray:
