@@ -11,10 +11,10 @@
 #include "common.h"
 
 namespace htsvd {
-hipError_t launch_denoise_groups_impl(const ImageGeom &g, int K, const BasisDev &b, const int32_t *idx,
-                                      const double *tau_ref, float *num, int64_t num_stride, int32_t *hits,
-                                      unsigned long long *gc, hipStream_t st);
-hipError_t launch_zero_rows(float *p, int64_t rows, int64_t cols, int64_t stride, hipStream_t st);
+hipError_t launch_filter(const ImageGeom &g, int W, int K, const BasisDev &b, const int32_t *idx,
+                         const double *tau_ref, float *regions, unsigned long long *gc, float *out, int64_t out_stride,
+                         hipStream_t st, bool gather);
+size_t filter_region_bytes(const ImageGeom &g, int W, int K);
 hipError_t launch_fill_const(double *p, int n, double v, hipStream_t st);
 int bm_lds_bytes(int s, int W, int h, int w);
 }  // namespace htsvd
@@ -121,7 +121,7 @@ double default_mult(int c, int K) { return sqrt(2.0 * log((double)c * K * PS * P
 // Workspace carve-up for one denoise call.
 struct Ws {
     int32_t *idx;
-    int32_t *hits;
+    float *regions;
     double *tau;
     double *sig_est;
     double *sig_hat;
@@ -130,7 +130,7 @@ struct Ws {
     size_t total;
 };
 
-Ws plan_ws(void *base, const ImageGeom &g, int K, int tile) {
+Ws plan_ws(void *base, const ImageGeom &g, int W, int K, int tile) {
     Ws w;
     const int64_t n_ref = (int64_t)g.ny * g.nx;
     const int64_t n_tiles = (int64_t)((g.h + tile - 1) / tile) * ((g.w + tile - 1) / tile);
@@ -141,7 +141,7 @@ Ws plan_ws(void *base, const ImageGeom &g, int K, int tile) {
         return (char *)base + o;
     };
     w.idx = (int32_t *)take(sizeof(int32_t) * n_ref * K);
-    w.hits = (int32_t *)take(sizeof(int32_t) * (size_t)g.h * g.w);
+    w.regions = (float *)take(filter_region_bytes(g, W, K));
     w.tau = (double *)take(sizeof(double) * n_ref);
     w.sig_est = (double *)take(sizeof(double) * n_tiles);
     w.sig_hat = (double *)take(sizeof(double) * n_tiles);
@@ -219,22 +219,20 @@ htsvd_status run_filter(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &
     hipError_t e;
     {
         StageScope sc(ctx, HTSVD_STAGE_CLEAR, st);
-        if ((e = launch_zero_rows(d_out, g.h, (int64_t)g.w * g.c, out_stride, st)) != hipSuccess)
-            return hip_fail(e, "zero output");
-        if ((e = launch_zero(w.hits, sizeof(int32_t) * (size_t)g.h * g.w, st)) != hipSuccess)
-            return hip_fail(e, "zero hits");
         if ((e = launch_zero(ctx->d_guard, 2 * sizeof(unsigned long long), st)) != hipSuccess)
             return hip_fail(e, "zero counters");
     }
     {
         StageScope sc(ctx, HTSVD_STAGE_FILTER, st);
-        if ((e = launch_denoise_groups_impl(g, mp.K, ctx->basis[g.c == 3], w.idx, tau, d_out, out_stride, w.hits,
-                                            ctx->d_guard, st)) != hipSuccess)
+        if ((e = launch_filter(g, mp.W, mp.K, ctx->basis[g.c == 3], w.idx, tau, w.regions, ctx->d_guard, d_out,
+                               out_stride, st, false)) != hipSuccess)
             return hip_fail(e, "filtering");
     }
     {
         StageScope sc(ctx, HTSVD_STAGE_NORMALIZE, st);
-        if ((e = launch_normalize(g, w.hits, d_out, out_stride, st)) != hipSuccess) return hip_fail(e, "normalise");
+        if ((e = launch_filter(g, mp.W, mp.K, ctx->basis[g.c == 3], w.idx, tau, w.regions, ctx->d_guard, d_out,
+                               out_stride, st, true)) != hipSuccess)
+            return hip_fail(e, "aggregation");
     }
     return HTSVD_OK;
 }
@@ -411,9 +409,9 @@ htsvd_status htsvd_denoise_tau(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, i
     if (!d_tau_ref || !d_out) return fail(HTSVD_EINVAL, "null tau or output");
     if (out_stride < (int64_t)w * c) return fail(HTSVD_EINVAL, "out_stride < w*c");
     const int tile = p->subimage > 0 ? p->subimage : 128;
-    Ws w0 = plan_ws(nullptr, g, mp.K, tile);
+    Ws w0 = plan_ws(nullptr, g, mp.W, mp.K, tile);
     if ((s = ensure_ws(ctx, w0.total)) != HTSVD_OK) return s;
-    Ws wk = plan_ws(ctx->ws, g, mp.K, tile);
+    Ws wk = plan_ws(ctx->ws, g, mp.W, mp.K, tile);
     hipStream_t st = (hipStream_t)stream;
     if ((s = run_bm(ctx, g, mp, wk, st)) != HTSVD_OK) return s;
     return run_filter(ctx, g, mp, wk, d_tau_ref, d_out, out_stride, st);
@@ -431,9 +429,9 @@ htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32
     if (!(sigma > 0.f) && sigma != HTSVD_SIGMA_AUTO) return fail(HTSVD_EINVAL, "sigma must be > 0 or AUTO");
     if (sigma == HTSVD_SIGMA_AUTO && p->estimator != 0) return fail(HTSVD_ENOTSUP, "learned estimator not built yet");
     const int tile = p->subimage;
-    Ws w0 = plan_ws(nullptr, g, mp.K, tile);
+    Ws w0 = plan_ws(nullptr, g, mp.W, mp.K, tile);
     if ((s = ensure_ws(ctx, w0.total)) != HTSVD_OK) return s;
-    Ws wk = plan_ws(ctx->ws, g, mp.K, tile);
+    Ws wk = plan_ws(ctx->ws, g, mp.W, mp.K, tile);
     const double mult = p->tau_mult > 0.0 ? p->tau_mult : default_mult(c, mp.K);
     hipStream_t st = (hipStream_t)stream;
     if ((s = run_bm(ctx, g, mp, wk, st)) != HTSVD_OK) return s;
@@ -458,9 +456,9 @@ htsvd_status htsvd_estimate_sigma(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h
     if (!(sigma > 0.f) && sigma != HTSVD_SIGMA_AUTO) return fail(HTSVD_EINVAL, "sigma must be > 0 or AUTO");
     if (sigma == HTSVD_SIGMA_AUTO && p->estimator != 0) return fail(HTSVD_ENOTSUP, "learned estimator not built yet");
     const int tile = p->subimage;
-    Ws w0 = plan_ws(nullptr, g, mp.K, tile);
+    Ws w0 = plan_ws(nullptr, g, mp.W, mp.K, tile);
     if ((s = ensure_ws(ctx, w0.total)) != HTSVD_OK) return s;
-    Ws wk = plan_ws(ctx->ws, g, mp.K, tile);
+    Ws wk = plan_ws(ctx->ws, g, mp.W, mp.K, tile);
     hipStream_t st = (hipStream_t)stream;
     if (p->adaptive && (s = run_bm(ctx, g, mp, wk, st)) != HTSVD_OK) return s;
     if ((s = run_sigma(ctx, g, mp, p, sigma, wk, st)) != HTSVD_OK) return s;
