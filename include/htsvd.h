@@ -63,8 +63,9 @@ typedef struct {
     int32_t gamma_rank;  /* Eq. 23 rank bound, 13 */
     int32_t gcp_num;     /* Eq. 9 green-prior weight gamma = gcp_num/gcp_den (6/5 = 1.2) */
     int32_t gcp_den;
-    int32_t estimator;   /* sigma source under HTSVD_SIGMA_AUTO: 0 plain covariance-eigenvalue estimator,
-                            1 learned per-block sigma map (plain estimator as fallback) */
+    int32_t estimator;   /* sigma source under HTSVD_SIGMA_AUTO: 0 plain covariance-eigenvalue estimator
+                            per sub-image; 1 learned per-8x8-block sigma map, judged per sub-image by the
+                            plain estimator, which replaces it where they differ by more than 1.5x */
     int32_t subimage;    /* sub-image side for sigma estimation and votes, 128 */
     int32_t n_vote;      /* sampled groups per sub-image for the vote, 15 */
     uint64_t vote_seed;  /* seed of the counter-based SplitMix64 sampler of the vote */
@@ -132,6 +133,36 @@ const char *htsvd_last_error(void);
  * tau, h_count[1] = near-threshold coefficients beyond the per-group FP64 list (decided in
  * FP32).  h_count must hold 2 values. */
 htsvd_status htsvd_last_guard_count(htsvd_ctx *ctx, int64_t *h_count);
+
+/* ---- Learned noise-level network (replaces the paper's CNN estimator, Sec. III-E-1) ----
+ * Six 3x3 convolutions, 32 channels, ReLU: C->32 stride 2, 32->32 stride 2, 32->32 stride 2,
+ * 32->32, 32->32, 32->1; the output z is log(sigma) (0..255 scale) for every 8x8 block, i.e.
+ * a ceil(h/8) x ceil(w/8) map.  Input normalisation (u8 - 128) / 64.  Weights are kept in
+ * FP32 (master copy and Adam moments) and used in bf16; activations are bf16 with FP32
+ * accumulation.  Parameter layout: per layer w[co][ky][kx][ci] then b[co]. */
+int32_t htsvd_cnn_param_count(int32_t c);
+/* He-normal weights from a counter-based generator of `seed`, zero biases (last bias log 20),
+ * Adam state and step counter reset.  Makes c (1 or 3) the network's channel count. */
+htsvd_status htsvd_cnn_init(htsvd_ctx *ctx, int32_t c, uint64_t seed);
+/* Host FP32 parameters in, n = htsvd_cnn_param_count(c); resets Adam state. */
+htsvd_status htsvd_cnn_set_weights(htsvd_ctx *ctx, int32_t c, const float *h_params, int64_t n);
+/* Host FP32 master parameters out (synchronises the device). */
+htsvd_status htsvd_cnn_get_weights(htsvd_ctx *ctx, float *h_params, int64_t n);
+/* Inference on one image: d_log_sigma = ceil(h/8)*ceil(w/8) floats, row-major. */
+htsvd_status htsvd_cnn_forward(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                               int64_t in_stride, float *d_log_sigma, void *stream);
+/* Forward and backward on a batch of n crops (device, contiguous NHWC u8, each h x w x c) with
+ * per-block targets d_target_log (n * ceil(h/8) * ceil(w/8) floats, log sigma): mean absolute
+ * error in *h_loss (synchronises; may be NULL) and its gradient in d_grad (device, FP32,
+ * htsvd_cnn_param_count(c) values). */
+htsvd_status htsvd_cnn_gradients(htsvd_ctx *ctx, const uint8_t *d_crops, int32_t n, int32_t h, int32_t w,
+                                 int32_t c, const float *d_target_log, float *d_grad, double *h_loss, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr on a batch, as above. */
+htsvd_status htsvd_cnn_train_step(htsvd_ctx *ctx, const uint8_t *d_crops, int32_t n, int32_t h, int32_t w,
+                                  int32_t c, const float *d_target_log, float lr, double *h_loss, void *stream);
+/* Checkpoint: parameters, Adam moments and the step counter (binary file). */
+htsvd_status htsvd_cnn_save(htsvd_ctx *ctx, const char *path);
+htsvd_status htsvd_cnn_load(htsvd_ctx *ctx, const char *path);
 
 /* Stage timing.  With timing enabled each call records a HIP event pair around each of its
  * stages on its stream; htsvd_stage_times() waits for the pending pairs and returns, per

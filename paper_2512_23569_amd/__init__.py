@@ -65,6 +65,15 @@ _SIGS = {
     "htsvd_sync": (_i32, [_vp, _vp]),
     "htsvd_last_error": (ctypes.c_char_p, []),
     "htsvd_last_guard_count": (_i32, [_vp, _vp]),
+    "htsvd_cnn_param_count": (_i32, [_i32]),
+    "htsvd_cnn_init": (_i32, [_vp, _i32, ctypes.c_uint64]),
+    "htsvd_cnn_set_weights": (_i32, [_vp, _i32, _vp, _i64]),
+    "htsvd_cnn_get_weights": (_i32, [_vp, _vp, _i64]),
+    "htsvd_cnn_forward": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _vp, _vp]),
+    "htsvd_cnn_gradients": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "htsvd_cnn_train_step": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _vp, _f32, _vp, _vp]),
+    "htsvd_cnn_save": (_i32, [_vp, ctypes.c_char_p]),
+    "htsvd_cnn_load": (_i32, [_vp, ctypes.c_char_p]),
     "htsvd_set_timing": (_i32, [_vp, _i32]),
     "htsvd_stage_times": (_i32, [_vp, _vp, _vp]),
 }
@@ -214,6 +223,57 @@ def htsvd_stage_times(ctx):
     return {s: (float(ms[i]), int(calls[i])) for i, s in enumerate(STAGES)}
 
 
+def htsvd_cnn_param_count(c: int) -> int:
+    return int(lib().htsvd_cnn_param_count(c))
+
+
+def htsvd_cnn_init(ctx, c: int, seed: int = 0):
+    _check(lib().htsvd_cnn_init(ctx, c, seed))
+
+
+def htsvd_cnn_set_weights(ctx, c: int, params: np.ndarray):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().htsvd_cnn_set_weights(ctx, c, a.ctypes.data_as(_vp), a.size))
+
+
+def htsvd_cnn_get_weights(ctx, c: int) -> np.ndarray:
+    a = np.zeros(htsvd_cnn_param_count(c), dtype=np.float32)
+    _check(lib().htsvd_cnn_get_weights(ctx, a.ctypes.data_as(_vp), a.size))
+    return a
+
+
+def htsvd_cnn_forward(ctx, d_in, h, w, c, in_stride, d_log_sigma, stream=None):
+    import torch
+    _check(lib().htsvd_cnn_forward(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, c, in_stride,
+                                   _dptr(d_log_sigma, torch.float32, "d_log_sigma"), _stream(stream)))
+
+
+def htsvd_cnn_gradients(ctx, d_crops, n, h, w, c, d_target_log, d_grad, stream=None) -> float:
+    import torch
+    loss = ctypes.c_double(0.0)
+    _check(lib().htsvd_cnn_gradients(ctx, _dptr(d_crops, torch.uint8, "d_crops"), n, h, w, c,
+                                     _dptr(d_target_log, torch.float32, "d_target_log"),
+                                     _dptr(d_grad, torch.float32, "d_grad"), ctypes.byref(loss), _stream(stream)))
+    return float(loss.value)
+
+
+def htsvd_cnn_train_step(ctx, d_crops, n, h, w, c, d_target_log, lr, want_loss=True, stream=None):
+    import torch
+    loss = ctypes.c_double(0.0)
+    _check(lib().htsvd_cnn_train_step(ctx, _dptr(d_crops, torch.uint8, "d_crops"), n, h, w, c,
+                                      _dptr(d_target_log, torch.float32, "d_target_log"), float(lr),
+                                      ctypes.byref(loss) if want_loss else None, _stream(stream)))
+    return float(loss.value) if want_loss else None
+
+
+def htsvd_cnn_save(ctx, path: str):
+    _check(lib().htsvd_cnn_save(ctx, path.encode()))
+
+
+def htsvd_cnn_load(ctx, path: str):
+    _check(lib().htsvd_cnn_load(ctx, path.encode()))
+
+
 # ---- convenience layer ------------------------------------------------------------
 
 def load_basis_slices(c: int, ps: int = 8):
@@ -226,12 +286,15 @@ def load_basis_slices(c: int, ps: int = 8):
 class Denoiser:
     """Owns one library context on one device, with the shipped bases loaded."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, load_network: bool = True):
         self.device = device
         self.ctx = htsvd_create(device)
         for c in (1, 3):
             U, V = load_basis_slices(c)
             htsvd_set_basis(self.ctx, 8, c, U, V)
+        net = os.path.join(DATA_DIR, "sigma_cnn_c3.ckpt")
+        if load_network and os.path.exists(net):
+            htsvd_cnn_load(self.ctx, net)
 
     def close(self):
         if self.ctx is not None:
@@ -275,3 +338,11 @@ class Denoiser:
 
     def guard_count(self):
         return htsvd_last_guard_count(self.ctx)
+
+    def sigma_map(self, img, stream=None):
+        """Learned log(sigma) per 8x8 block, shape (ceil(h/8), ceil(w/8))."""
+        import torch
+        h, w, c, st = _img_dims(img)
+        out = torch.empty(((h + 7) // 8, (w + 7) // 8), dtype=torch.float32, device=img.device)
+        htsvd_cnn_forward(self.ctx, img, h, w, c, st, out, stream)
+        return out

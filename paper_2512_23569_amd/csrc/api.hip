@@ -1,6 +1,7 @@
 // Host runtime behind the C ABI of include/htsvd.h: argument validation, the context's
 // workspace and basis constants, and the stream-ordered launch sequence of one call.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <complex>
@@ -21,6 +22,17 @@ int bm_lds_bytes(int s, int W, int h, int w);
 
 using namespace htsvd;
 
+// Learned noise-level network state (device buffers) and its activation workspace.
+struct CnnState {
+    int c = 0, n = 0;
+    float *w = nullptr, *m = nullptr, *v = nullptr, *wq = nullptr, *grad = nullptr;
+    uint16_t *wbf = nullptr;
+    int64_t step = 0;
+    void *ws = nullptr;
+    size_t ws_size = 0;
+    double *d_loss = nullptr;
+};
+
 struct htsvd_ctx {
     int device = 0;
     BasisDev basis[2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [0]: c=1, [1]: c=3
@@ -34,6 +46,7 @@ struct htsvd_ctx {
     bool ev_pending[HTSVD_N_STAGES] = {};
     double stage_ms[HTSVD_N_STAGES] = {};
     int64_t stage_calls[HTSVD_N_STAGES] = {};
+    CnnState cnn;
 };
 
 namespace {
@@ -127,6 +140,8 @@ struct Ws {
     double *sig_hat;
     int32_t *votes;
     double *cov;
+    int32_t *use_plain;
+    double *sig_plain;
     size_t total;
 };
 
@@ -147,6 +162,8 @@ Ws plan_ws(void *base, const ImageGeom &g, int W, int K, int tile) {
     w.sig_hat = (double *)take(sizeof(double) * n_tiles);
     w.votes = (int32_t *)take(sizeof(int32_t) * n_tiles);
     w.cov = (double *)take(sizeof(double) * n_tiles * g.c);  // per-channel tail variances
+    w.use_plain = (int32_t *)take(sizeof(int32_t) * n_tiles);
+    w.sig_plain = (double *)take(sizeof(double) * n_tiles);
     w.total = off;
     return w;
 }
@@ -181,6 +198,146 @@ struct StageScope {
 };
 
 // The denoising sequence after tau is known: grouping, filtering, aggregation, normalisation.
+// ---- learned network helpers ----
+struct CnnWs {
+    uint16_t *act[6];
+    float *z, *d0, *d1;
+    size_t total;
+};
+
+CnnWs plan_cnn_ws(void *base, int N, int H, int W, int c, bool train) {
+    CnnWs w;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return (char *)base + o;
+    };
+    w.act[0] = nullptr;
+    for (int l = 1; l <= 5; ++l) w.act[l] = (uint16_t *)take(sizeof(uint16_t) * cnn_act_elems(l, N, H, W, c));
+    w.z = (float *)take(sizeof(float) * cnn_act_elems(6, N, H, W, c));
+    const size_t dbig = train ? cnn_act_elems(1, N, H, W, c) : 0;
+    w.d0 = (float *)take(sizeof(float) * dbig);
+    w.d1 = (float *)take(sizeof(float) * dbig);
+    w.total = off;
+    return w;
+}
+
+htsvd_status ensure_cnn_ws(htsvd_ctx *ctx, size_t bytes) {
+    CnnState &cs = ctx->cnn;
+    if (cs.ws_size >= bytes) return HTSVD_OK;
+    hipError_t e;
+    if (cs.ws) {
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronise before workspace growth");
+        (void)hipFree(cs.ws);
+        cs.ws = nullptr;
+        cs.ws_size = 0;
+    }
+    const size_t sz = bytes + (bytes >> 3);
+    if (hipMalloc(&cs.ws, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HTSVD_ENOMEM, "network workspace allocation failed");
+    }
+    cs.ws_size = sz;
+    return HTSVD_OK;
+}
+
+CnnBuffers cnn_buffers(const CnnState &cs, const CnnWs &w) {
+    CnnBuffers b;
+    b.wq = cs.wq;
+    b.wbf = cs.wbf;
+    for (int l = 0; l < 6; ++l) b.act[l] = w.act[l];
+    b.z = w.z;
+    return b;
+}
+
+void cnn_free(CnnState &cs) {
+    float *fs[5] = {cs.w, cs.m, cs.v, cs.wq, cs.grad};
+    for (float *f : fs)
+        if (f) (void)hipFree(f);
+    if (cs.wbf) (void)hipFree(cs.wbf);
+    if (cs.ws) (void)hipFree(cs.ws);
+    if (cs.d_loss) (void)hipFree(cs.d_loss);
+    cs = CnnState();
+}
+
+// Allocates the parameter buffers for c channels (keeps them when the size already matches).
+htsvd_status cnn_alloc(htsvd_ctx *ctx, int c) {
+    CnnState &cs = ctx->cnn;
+    int wo[6], bo[6], n;
+    cnn_layout(c, wo, bo, &n);
+    if (cs.w && cs.c == c) return HTSVD_OK;
+    if ((hipSetDevice(ctx->device)) != hipSuccess) return fail(HTSVD_EDEVICE, "hipSetDevice");
+    (void)hipDeviceSynchronize();
+    void *ws = cs.ws;
+    size_t ws_size = cs.ws_size;
+    cs.ws = nullptr;
+    cnn_free(cs);
+    cs.ws = ws;
+    cs.ws_size = ws_size;
+    cs.c = c;
+    cs.n = n;
+    float **fs[5] = {&cs.w, &cs.m, &cs.v, &cs.wq, &cs.grad};
+    for (float **f : fs)
+        if (hipMalloc(f, sizeof(float) * n) != hipSuccess) return fail(HTSVD_ENOMEM, "network allocation");
+    if (hipMalloc(&cs.wbf, sizeof(uint16_t) * n) != hipSuccess) return fail(HTSVD_ENOMEM, "network allocation");
+    if (hipMalloc(&cs.d_loss, sizeof(double)) != hipSuccess) return fail(HTSVD_ENOMEM, "network allocation");
+    return HTSVD_OK;
+}
+
+// Uploads master weights, clears Adam state, refreshes the bf16 copies (synchronous).
+htsvd_status cnn_upload(htsvd_ctx *ctx, const float *h, int n) {
+    CnnState &cs = ctx->cnn;
+    hipError_t e;
+    if ((e = hipMemcpy(cs.w, h, sizeof(float) * n, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "upload");
+    if ((e = hipMemset(cs.m, 0, sizeof(float) * n)) != hipSuccess) return hip_fail(e, "clear");
+    if ((e = hipMemset(cs.v, 0, sizeof(float) * n)) != hipSuccess) return hip_fail(e, "clear");
+    if ((e = cnn_quantize(cs.w, n, cs.wq, cs.wbf, nullptr)) != hipSuccess) return hip_fail(e, "quantise");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "upload");
+    cs.step = 0;
+    return HTSVD_OK;
+}
+
+// One draw of a standard normal from the counter-based SplitMix64 stream (Box-Muller).
+double counter_normal(uint64_t seed, uint64_t i) {
+    auto mix = [](uint64_t z) {
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    const uint64_t a = mix(seed + (2 * i + 1) * 0x9E3779B97F4A7C15ull);
+    const uint64_t b = mix(seed + (2 * i + 2) * 0x9E3779B97F4A7C15ull);
+    const double u1 = ((a >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+    const double u2 = (b >> 11) * (1.0 / 9007199254740992.0);
+    return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
+htsvd_status validate_crops(htsvd_ctx *ctx, const uint8_t *d, int32_t n, int32_t h, int32_t w, int32_t c) {
+    if (!ctx) return fail(HTSVD_EINVAL, "null context");
+    if (!d) return fail(HTSVD_EINVAL, "null input");
+    if (!ctx->cnn.w) return fail(HTSVD_ESTATE, "network weights not set");
+    if (c != ctx->cnn.c) return fail(HTSVD_EINVAL, "channel count differs from the network's");
+    if (n < 1 || h < 1 || w < 1) return fail(HTSVD_ESHAPE, "empty batch");
+    if ((int64_t)n * h * w > (int64_t)1 << 31) return fail(HTSVD_ENOTSUP, "batch too large");
+    return HTSVD_OK;
+}
+
+// Learned log-sigma map of one image into the network workspace; returns its device pointer.
+htsvd_status run_cnn_map(htsvd_ctx *ctx, const ImageGeom &g, hipStream_t st, const float **zmap) {
+    CnnState &cs = ctx->cnn;
+    if (!cs.w) return fail(HTSVD_ESTATE, "learned estimator requested but no network weights are set");
+    if (cs.c != g.c) return fail(HTSVD_EINVAL, "network channel count differs from the image's");
+    CnnWs w0 = plan_cnn_ws(nullptr, 1, g.h, g.w, g.c, false);
+    htsvd_status s = ensure_cnn_ws(ctx, w0.total);
+    if (s != HTSVD_OK) return s;
+    CnnWs w = plan_cnn_ws(cs.ws, 1, g.h, g.w, g.c, false);
+    StageScope sc(ctx, HTSVD_STAGE_SIGMA, st);
+    hipError_t e = cnn_forward(cnn_buffers(cs, w), g.img, g.stride, 0, 1, g.h, g.w, g.c, st);
+    if (e != hipSuccess) return hip_fail(e, "network forward");
+    *zmap = w.z;
+    return HTSVD_OK;
+}
+
 htsvd_status run_bm(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &mp, const Ws &w, hipStream_t st) {
     StageScope sc(ctx, HTSVD_STAGE_BM, st);
     hipError_t e = launch_block_match(g, mp, w.idx, nullptr, st);
@@ -191,13 +348,18 @@ htsvd_status run_bm(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &mp, 
 // Noise level per sub-image: sigma_est (known or plain estimator), then the Eq. 23 vote.
 // Needs the groups (w.idx) when p->adaptive is set.  Leaves sigma_hat in w.sig_hat.
 htsvd_status run_sigma(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &mp, const htsvd_params *p,
-                       float sigma, const Ws &w, hipStream_t st) {
+                       float sigma, const Ws &w, const float *zmap, hipStream_t st) {
     StageScope sc(ctx, HTSVD_STAGE_SIGMA, st);
     const int T = p->subimage;
     const int n_tiles = ((g.h + T - 1) / T) * ((g.w + T - 1) / T);
     hipError_t e;
     if (sigma > 0.f) {
         if ((e = launch_fill_const(w.sig_est, n_tiles, (double)sigma, st)) != hipSuccess) return hip_fail(e, "sigma");
+    } else if (p->estimator == 1) {
+        // learned map (already in zmap) judged per tile by the plain estimate
+        if ((e = launch_sigma_est(g, T, w.cov, w.sig_plain, st)) != hipSuccess) return hip_fail(e, "sigma estimation");
+        if ((e = launch_learned_judge(g, T, zmap, w.sig_plain, 1.5, w.use_plain, w.sig_est, st)) != hipSuccess)
+            return hip_fail(e, "sigma judge");
     } else {
         if ((e = launch_sigma_est(g, T, w.cov, w.sig_est, st)) != hipSuccess) return hip_fail(e, "sigma estimation");
     }
@@ -269,6 +431,7 @@ void htsvd_destroy(htsvd_ctx *ctx) {
     }
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->d_guard) (void)hipFree(ctx->d_guard);
+    cnn_free(ctx->cnn);
     delete ctx;
 }
 
@@ -427,20 +590,26 @@ htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32
     if (!d_out) return fail(HTSVD_EINVAL, "null output");
     if (out_stride < (int64_t)w * c) return fail(HTSVD_EINVAL, "out_stride < w*c");
     if (!(sigma > 0.f) && sigma != HTSVD_SIGMA_AUTO) return fail(HTSVD_EINVAL, "sigma must be > 0 or AUTO");
-    if (sigma == HTSVD_SIGMA_AUTO && p->estimator != 0) return fail(HTSVD_ENOTSUP, "learned estimator not built yet");
+    if (p->estimator != 0 && p->estimator != 1) return fail(HTSVD_EINVAL, "estimator must be 0 or 1");
+    const bool learned = sigma == HTSVD_SIGMA_AUTO && p->estimator == 1;
     const int tile = p->subimage;
     Ws w0 = plan_ws(nullptr, g, mp.W, mp.K, tile);
     if ((s = ensure_ws(ctx, w0.total)) != HTSVD_OK) return s;
     Ws wk = plan_ws(ctx->ws, g, mp.W, mp.K, tile);
     const double mult = p->tau_mult > 0.0 ? p->tau_mult : default_mult(c, mp.K);
     hipStream_t st = (hipStream_t)stream;
+    const float *zmap = nullptr;
+    if (learned && (s = run_cnn_map(ctx, g, st, &zmap)) != HTSVD_OK) return s;
     if ((s = run_bm(ctx, g, mp, wk, st)) != HTSVD_OK) return s;
     hipError_t e;
     if (sigma > 0.f && !p->adaptive) {
         e = launch_fill_tau(wk.tau, (int64_t)g.ny * g.nx, nullptr, (double)sigma, mult, g, tile, st);
     } else {
-        if ((s = run_sigma(ctx, g, mp, p, sigma, wk, st)) != HTSVD_OK) return s;
-        e = launch_fill_tau(wk.tau, (int64_t)g.ny * g.nx, wk.sig_hat, 0.0, mult, g, tile, st);
+        if ((s = run_sigma(ctx, g, mp, p, sigma, wk, zmap, st)) != HTSVD_OK) return s;
+        if (learned)
+            e = launch_fill_tau_learned(wk.tau, g, tile, zmap, wk.use_plain, wk.sig_est, wk.sig_hat, mult, st);
+        else
+            e = launch_fill_tau(wk.tau, (int64_t)g.ny * g.nx, wk.sig_hat, 0.0, mult, g, tile, st);
     }
     if (e != hipSuccess) return hip_fail(e, "tau");
     return run_filter(ctx, g, mp, wk, wk.tau, d_out, out_stride, st);
@@ -454,14 +623,17 @@ htsvd_status htsvd_estimate_sigma(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h
     htsvd_status s = validate(ctx, d_in, h, w, c, in_stride, p, &g, &mp, false);
     if (s != HTSVD_OK) return s;
     if (!(sigma > 0.f) && sigma != HTSVD_SIGMA_AUTO) return fail(HTSVD_EINVAL, "sigma must be > 0 or AUTO");
-    if (sigma == HTSVD_SIGMA_AUTO && p->estimator != 0) return fail(HTSVD_ENOTSUP, "learned estimator not built yet");
+    if (p->estimator != 0 && p->estimator != 1) return fail(HTSVD_EINVAL, "estimator must be 0 or 1");
+    const bool learned = sigma == HTSVD_SIGMA_AUTO && p->estimator == 1;
     const int tile = p->subimage;
     Ws w0 = plan_ws(nullptr, g, mp.W, mp.K, tile);
     if ((s = ensure_ws(ctx, w0.total)) != HTSVD_OK) return s;
     Ws wk = plan_ws(ctx->ws, g, mp.W, mp.K, tile);
     hipStream_t st = (hipStream_t)stream;
+    const float *zmap = nullptr;
+    if (learned && (s = run_cnn_map(ctx, g, st, &zmap)) != HTSVD_OK) return s;
     if (p->adaptive && (s = run_bm(ctx, g, mp, wk, st)) != HTSVD_OK) return s;
-    if ((s = run_sigma(ctx, g, mp, p, sigma, wk, st)) != HTSVD_OK) return s;
+    if ((s = run_sigma(ctx, g, mp, p, sigma, wk, zmap, st)) != HTSVD_OK) return s;
     const int n_tiles = ((h + tile - 1) / tile) * ((w + tile - 1) / tile);
     hipError_t e;
     if (d_sigma_est &&
@@ -473,6 +645,165 @@ htsvd_status htsvd_estimate_sigma(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h
     if (d_votes &&
         (e = hipMemcpyAsync(d_votes, wk.votes, sizeof(int32_t) * n_tiles, hipMemcpyDeviceToDevice, st)) != hipSuccess)
         return hip_fail(e, "copy votes");
+    return HTSVD_OK;
+}
+
+int32_t htsvd_cnn_param_count(int32_t c) {
+    if (c != 1 && c != 3) return 0;
+    int wo[6], bo[6], n;
+    cnn_layout(c, wo, bo, &n);
+    return n;
+}
+
+htsvd_status htsvd_cnn_init(htsvd_ctx *ctx, int32_t c, uint64_t seed) {
+    if (!ctx) return fail(HTSVD_EINVAL, "null context");
+    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    int wo[6], bo[6], n;
+    cnn_layout(c, wo, bo, &n);
+    std::vector<float> h(n, 0.f);
+    const int ci[6] = {c, 32, 32, 32, 32, 32}, co[6] = {32, 32, 32, 32, 32, 1};
+    uint64_t ctr = 0;
+    for (int l = 0; l < 6; ++l) {
+        const double sd = sqrt(2.0 / (9.0 * ci[l])) * (l == 5 ? 0.1 : 1.0);
+        for (int k = 0; k < co[l] * 9 * ci[l]; ++k) h[wo[l] + k] = (float)(sd * counter_normal(seed, ctr++));
+    }
+    h[bo[5]] = (float)log(20.0);
+    htsvd_status s = cnn_alloc(ctx, c);
+    if (s != HTSVD_OK) return s;
+    return cnn_upload(ctx, h.data(), n);
+}
+
+htsvd_status htsvd_cnn_set_weights(htsvd_ctx *ctx, int32_t c, const float *h_params, int64_t n) {
+    if (!ctx || !h_params) return fail(HTSVD_EINVAL, "null argument");
+    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    if (n != htsvd_cnn_param_count(c)) return fail(HTSVD_EINVAL, "wrong parameter count");
+    htsvd_status s = cnn_alloc(ctx, c);
+    if (s != HTSVD_OK) return s;
+    return cnn_upload(ctx, h_params, (int)n);
+}
+
+htsvd_status htsvd_cnn_get_weights(htsvd_ctx *ctx, float *h_params, int64_t n) {
+    if (!ctx || !h_params) return fail(HTSVD_EINVAL, "null argument");
+    if (!ctx->cnn.w) return fail(HTSVD_ESTATE, "network weights not set");
+    if (n != ctx->cnn.n) return fail(HTSVD_EINVAL, "wrong parameter count");
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "synchronise");
+    if ((e = hipMemcpy(h_params, ctx->cnn.w, sizeof(float) * n, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "download");
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_cnn_forward(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                               int64_t in_stride, float *d_log_sigma, void *stream) {
+    htsvd_status s = validate_crops(ctx, d_in, 1, h, w, c);
+    if (s != HTSVD_OK) return s;
+    if (!d_log_sigma) return fail(HTSVD_EINVAL, "null output");
+    if (in_stride < (int64_t)w * c) return fail(HTSVD_EINVAL, "in_stride < w*c");
+    CnnState &cs = ctx->cnn;
+    CnnWs w0 = plan_cnn_ws(nullptr, 1, h, w, c, false);
+    if ((s = ensure_cnn_ws(ctx, w0.total)) != HTSVD_OK) return s;
+    CnnWs wk = plan_cnn_ws(cs.ws, 1, h, w, c, false);
+    CnnBuffers b = cnn_buffers(cs, wk);
+    b.z = d_log_sigma;
+    hipError_t e = cnn_forward(b, d_in, in_stride, 0, 1, h, w, c, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "network forward");
+    return HTSVD_OK;
+}
+
+htsvd_status cnn_grad_impl(htsvd_ctx *ctx, const uint8_t *d_crops, int32_t n, int32_t h, int32_t w, int32_t c,
+                           const float *d_target, float *d_grad, double *h_loss, hipStream_t st) {
+    htsvd_status s = validate_crops(ctx, d_crops, n, h, w, c);
+    if (s != HTSVD_OK) return s;
+    if (!d_target || !d_grad) return fail(HTSVD_EINVAL, "null target or gradient");
+    CnnState &cs = ctx->cnn;
+    CnnWs w0 = plan_cnn_ws(nullptr, n, h, w, c, true);
+    if ((s = ensure_cnn_ws(ctx, w0.total)) != HTSVD_OK) return s;
+    CnnWs wk = plan_cnn_ws(cs.ws, n, h, w, c, true);
+    CnnBuffers b = cnn_buffers(cs, wk);
+    const int64_t sb = (int64_t)w * c, bb = (int64_t)h * w * c;
+    hipError_t e = cnn_forward(b, d_crops, sb, bb, n, h, w, c, st);
+    if (e != hipSuccess) return hip_fail(e, "network forward");
+    e = cnn_backward(b, d_crops, sb, bb, n, h, w, c, d_target, d_grad, wk.d0, wk.d1, cs.d_loss, st);
+    if (e != hipSuccess) return hip_fail(e, "network backward");
+    if (h_loss) {
+        double v = 0.0;
+        if ((e = hipMemcpyAsync(&v, cs.d_loss, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return hip_fail(e, "loss copy");
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "synchronise");
+        *h_loss = v / (double)cnn_act_elems(6, n, h, w, c);
+    }
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_cnn_gradients(htsvd_ctx *ctx, const uint8_t *d_crops, int32_t n, int32_t h, int32_t w,
+                                 int32_t c, const float *d_target_log, float *d_grad, double *h_loss, void *stream) {
+    return cnn_grad_impl(ctx, d_crops, n, h, w, c, d_target_log, d_grad, h_loss, (hipStream_t)stream);
+}
+
+htsvd_status htsvd_cnn_train_step(htsvd_ctx *ctx, const uint8_t *d_crops, int32_t n, int32_t h, int32_t w,
+                                  int32_t c, const float *d_target_log, float lr, double *h_loss, void *stream) {
+    if (!ctx) return fail(HTSVD_EINVAL, "null context");
+    if (!(lr > 0.f)) return fail(HTSVD_EINVAL, "lr must be > 0");
+    hipStream_t st = (hipStream_t)stream;
+    htsvd_status s = cnn_grad_impl(ctx, d_crops, n, h, w, c, d_target_log, ctx->cnn.grad, h_loss, st);
+    if (s != HTSVD_OK) return s;
+    CnnState &cs = ctx->cnn;
+    cs.step += 1;
+    hipError_t e = cnn_adam(cs.w, cs.m, cs.v, cs.grad, cs.n, lr, cs.step, cs.wq, cs.wbf, st);
+    if (e != hipSuccess) return hip_fail(e, "adam");
+    return HTSVD_OK;
+}
+
+// Checkpoint file: "HTCN", version 1, c, n, step, then w, m, v (FP32, n each).
+htsvd_status htsvd_cnn_save(htsvd_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(HTSVD_EINVAL, "null argument");
+    CnnState &cs = ctx->cnn;
+    if (!cs.w) return fail(HTSVD_ESTATE, "network weights not set");
+    std::vector<float> buf((size_t)3 * cs.n);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "synchronise");
+    float *src[3] = {cs.w, cs.m, cs.v};
+    for (int i = 0; i < 3; ++i)
+        if ((e = hipMemcpy(buf.data() + (size_t)i * cs.n, src[i], sizeof(float) * cs.n, hipMemcpyDeviceToHost)) !=
+            hipSuccess)
+            return hip_fail(e, "download");
+    FILE *f = fopen(path, "wb");
+    if (!f) return fail(HTSVD_EINVAL, std::string("cannot open ") + path);
+    const int32_t hdr[4] = {0x4E435448 /* "HTCN" */, 1, cs.c, cs.n};
+    bool ok = fwrite(hdr, sizeof(hdr), 1, f) == 1 && fwrite(&cs.step, sizeof(cs.step), 1, f) == 1 &&
+              fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) return fail(HTSVD_EINVAL, std::string("cannot write ") + path);
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_cnn_load(htsvd_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(HTSVD_EINVAL, "null argument");
+    FILE *f = fopen(path, "rb");
+    if (!f) return fail(HTSVD_EINVAL, std::string("cannot open ") + path);
+    int32_t hdr[4];
+    int64_t step = 0;
+    bool ok = fread(hdr, sizeof(hdr), 1, f) == 1 && fread(&step, sizeof(step), 1, f) == 1;
+    if (!ok || hdr[0] != 0x4E435448 || hdr[1] != 1 || (hdr[2] != 1 && hdr[2] != 3) ||
+        hdr[3] != htsvd_cnn_param_count(hdr[2])) {
+        fclose(f);
+        return fail(HTSVD_EINVAL, std::string("not a network checkpoint: ") + path);
+    }
+    const int n = hdr[3];
+    std::vector<float> buf((size_t)3 * n);
+    ok = fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    fclose(f);
+    if (!ok) return fail(HTSVD_EINVAL, std::string("truncated checkpoint: ") + path);
+    htsvd_status s = cnn_alloc(ctx, hdr[2]);
+    if (s != HTSVD_OK) return s;
+    if ((s = cnn_upload(ctx, buf.data(), n)) != HTSVD_OK) return s;
+    CnnState &cs = ctx->cnn;
+    hipError_t e;
+    if ((e = hipMemcpy(cs.m, buf.data() + n, sizeof(float) * n, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "upload");
+    if ((e = hipMemcpy(cs.v, buf.data() + 2 * (size_t)n, sizeof(float) * n, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "upload");
+    cs.step = step;
     return HTSVD_OK;
 }
 

@@ -273,6 +273,7 @@ void cnn_layout(int c, int *w_off, int *b_off, int *total) {
 }
 
 static ConvShape shape_of(int l, int N, int H, int W, int c) {
+    // l = 0..5: the layer; its input size is the output size of the layers before it
     // spatial size entering layer l
     int h = H, w = W;
     const int strides[6] = {2, 2, 2, 1, 1, 1};
@@ -295,13 +296,6 @@ size_t cnn_act_elems(int l, int N, int H, int W, int c) {
     ConvShape cs = shape_of(l - 1, N, H, W, c);
     return (size_t)cs.N * cs.Ho * cs.Wo * cs.Co;
 }
-
-struct CnnBuffers {
-    const float *wq;      // bf16-rounded weights as FP32
-    const uint16_t *wbf;  // bf16 weights
-    uint16_t *act[6];     // act[1..5]
-    float *z;
-};
 
 hipError_t cnn_forward(const CnnBuffers &b, const uint8_t *img, int64_t img_stride, int64_t img_batch_stride,
                        int N, int H, int W, int c, hipStream_t st) {

@@ -68,4 +68,29 @@ hipError_t launch_vote(const ImageGeom &g, const MethodParams &mp, const int32_t
                        uint64_t seed, int gamma_rank, double beta, const double *sigma_est, double *sigma_hat,
                        int32_t *votes, hipStream_t st);
 
+// ---- learned noise-level network ----
+void cnn_layout(int c, int *w_off, int *b_off, int *total);
+size_t cnn_act_elems(int l, int N, int H, int W, int c);   // elements of activation l (1..6)
+struct CnnBuffers {
+    const float *wq;      // bf16-rounded weights as FP32
+    const uint16_t *wbf;  // bf16 weights
+    uint16_t *act[6];     // act[1..5], NHWC bf16, 32 channels
+    float *z;             // layer-6 output (log sigma per block)
+};
+hipError_t cnn_forward(const CnnBuffers &b, const uint8_t *img, int64_t img_stride, int64_t img_batch_stride,
+                       int N, int H, int W, int c, hipStream_t st);
+hipError_t cnn_backward(const CnnBuffers &b, const uint8_t *img, int64_t img_stride, int64_t img_batch_stride,
+                        int N, int H, int W, int c, const float *target, float *grads, float *d0, float *d1,
+                        double *loss_sum, hipStream_t st);
+hipError_t cnn_adam(float *w, float *m, float *v, const float *g, int n, float lr, int64_t step, float *wq,
+                    uint16_t *wbf, hipStream_t st);
+hipError_t cnn_quantize(const float *w, int n, float *wq, uint16_t *wbf, hipStream_t st);
+
+// Learned sigma map -> thresholds: per-tile judge against the plain estimate, per-reference tau.
+hipError_t launch_learned_judge(const ImageGeom &g, int tile, const float *zmap, const double *sigma_plain,
+                                double ratio_bound, int32_t *use_plain, double *sigma_tile, hipStream_t st);
+hipError_t launch_fill_tau_learned(double *tau, const ImageGeom &g, int tile, const float *zmap,
+                                   const int32_t *use_plain, const double *sigma_est, const double *sigma_hat,
+                                   double mult, hipStream_t st);
+
 }  // namespace htsvd

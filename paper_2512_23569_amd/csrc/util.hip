@@ -29,7 +29,70 @@ __global__ void fill_tau_kernel(double *tau, int64_t n_ref, const double *sigma_
     tau[r] = s * mult;
 }
 
+// Per sub-image: the mean of the learned sigma over the tile's 8x8 blocks is compared with the
+// plain estimate; the plain value replaces the learned map where they differ by more than
+// ratio_bound (or the map is not finite).  sigma_tile = the value the tile then stands for.
+__global__ void learned_judge_kernel(ImageGeom g, int tile, const float *zmap, const double *sigma_plain,
+                                     double log_bound, int32_t *use_plain, double *sigma_tile) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ntx = (g.w + tile - 1) / tile, nty = (g.h + tile - 1) / tile;
+    if (t >= ntx * nty) return;
+    const int hb = (g.h + PS - 1) / PS, wb = (g.w + PS - 1) / PS, bpt = tile / PS;
+    const int ty = t / ntx, tx = t % ntx;
+    double sum = 0.0;
+    int n = 0;
+    for (int by = ty * bpt; by < min(hb, (ty + 1) * bpt); ++by)
+        for (int bx = tx * bpt; bx < min(wb, (tx + 1) * bpt); ++bx) {
+            sum += exp((double)zmap[by * wb + bx]);
+            ++n;
+        }
+    const double mean = n > 0 ? sum / n : 0.0;
+    const double sp = sigma_plain[t];
+    const bool ok = isfinite(mean) && mean > 0.0 && sp > 0.0 && fabs(log(mean / sp)) <= log_bound;
+    use_plain[t] = ok ? 0 : 1;
+    sigma_tile[t] = ok ? mean : sp;
+}
+
+// tau of every reference: the learned sigma of the 8x8 block holding its top-left pixel, scaled
+// by its tile's vote (sigma_hat / sigma_est), or the tile's plain sigma_hat where the judge
+// rejected the map.
+__global__ void fill_tau_learned_kernel(double *tau, ImageGeom g, int tile, const float *zmap,
+                                        const int32_t *use_plain, const double *sigma_est,
+                                        const double *sigma_hat, double mult) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= (int64_t)g.ny * g.nx) return;
+    const int iy = (int)(r / g.nx), ix = (int)(r % g.nx);
+    const int y = ref_pos(iy, g.ny, g.h, g.s), x = ref_pos(ix, g.nx, g.w, g.s);
+    const int ntx = (g.w + tile - 1) / tile;
+    const int t = (y / tile) * ntx + x / tile;
+    double s;
+    if (use_plain[t]) {
+        s = sigma_hat[t];
+    } else {
+        const int wb = (g.w + PS - 1) / PS;
+        s = exp((double)zmap[(y / PS) * wb + x / PS]) * (sigma_hat[t] / sigma_est[t]);
+    }
+    tau[r] = s * mult;
+}
+
 }  // namespace
+
+hipError_t launch_learned_judge(const ImageGeom &g, int tile, const float *zmap, const double *sigma_plain,
+                                double ratio_bound, int32_t *use_plain, double *sigma_tile, hipStream_t st) {
+    const int n = ((g.h + tile - 1) / tile) * ((g.w + tile - 1) / tile);
+    hipLaunchKernelGGL(learned_judge_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g, tile, zmap, sigma_plain,
+                       log(ratio_bound), use_plain, sigma_tile);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_tau_learned(double *tau, const ImageGeom &g, int tile, const float *zmap,
+                                   const int32_t *use_plain, const double *sigma_est, const double *sigma_hat,
+                                   double mult, hipStream_t st) {
+    const int64_t n = (int64_t)g.ny * g.nx;
+    hipLaunchKernelGGL(fill_tau_learned_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tau, g, tile,
+                       zmap, use_plain, sigma_est, sigma_hat, mult);
+    return hipGetLastError();
+}
 
 hipError_t launch_zero_rows(float *p, int64_t rows, int64_t cols, int64_t stride, hipStream_t st) {
     const int64_t n = rows * cols;

@@ -29,7 +29,7 @@ import numpy as np
 __all__ = [
     "gray_layer", "make_clean", "add_awgn", "add_poisson_gaussian",
     "smooth_sigma_field", "add_sigma_field_noise", "psnr", "make_cfg",
-    "BATCH_SIZES", "batch_specs",
+    "BATCH_SIZES", "batch_specs", "block_log_sigma", "sigma_crop",
 ]
 
 
@@ -216,3 +216,27 @@ def batch_specs(n: int = 64, seed: int = 4):
         sigma = float(rng.uniform(5.0, 75.0))
         out.append((h, w, sigma, seed + 1 + i))
     return out
+
+
+def block_log_sigma(sigma_field: np.ndarray, B: int = 8) -> np.ndarray:
+    """Training label of the sigma network: log of the root-mean-square sigma of every BxB
+    block of a per-pixel sigma field (edge blocks partial)."""
+    h, w = sigma_field.shape
+    hb, wb = -(-h // B), -(-w // B)
+    pad = np.zeros((hb * B, wb * B))
+    cnt = np.zeros((hb * B, wb * B))
+    pad[:h, :w] = sigma_field ** 2
+    cnt[:h, :w] = 1.0
+    s = pad.reshape(hb, B, wb, B).sum(axis=(1, 3))
+    n = cnt.reshape(hb, B, wb, B).sum(axis=(1, 3))
+    return 0.5 * np.log(s / n)
+
+
+def sigma_crop(seed: int, size: int = 128, c: int = 3, lo: float = 5.0, hi: float = 75.0):
+    """One training crop: a clean synthetic image with noise of a smooth random sigma field
+    (4x4 grid of U[lo,hi] values, bilinear), and its per-8x8-block log-sigma label."""
+    rng = _rng(seed)
+    field = smooth_sigma_field(size, size, rng, lo, hi)
+    clean = make_clean(size, size, c, int(rng.integers(0, 2 ** 31)))
+    noisy = add_sigma_field_noise(clean, field, int(rng.integers(0, 2 ** 31)))
+    return noisy, block_log_sigma(field).astype(np.float32), clean

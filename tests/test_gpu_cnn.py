@@ -1,0 +1,171 @@
+"""The learned noise-level network on the GPU vs its FP64 oracle (needs an MI355X).
+
+Tolerances: activations are stored in bf16 (8 significant bits, unit roundoff 2^-8), so
+the oracle mirrors that rounding (round to nearest even after every ReLU) and uses the same
+bf16-rounded parameters; what remains is FP32-vs-FP64 accumulation order, which can move an
+activation across a bf16 rounding boundary (one bf16 ulp, 2^-8 relative) and propagate
+through at most five layers.  The checks therefore allow |dz| <= 0.03 on log(sigma) and a
+gradient cosine >= 0.999 with relative L2 error <= 3e-2."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import cnn
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def to_bf16(a):
+    """Round FP32 values to bf16 (round to nearest even), returned as FP64."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def dn():
+    import paper_2512_23569_amd as ht
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    d = ht.Denoiser(0, load_network=False)
+    yield d
+    d.close()
+
+
+def _params(c, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co, s, relu in cnn.layer_shapes(c):
+        sd = np.sqrt(2.0 / (9 * ci)) * scale
+        parts.append(rng.standard_normal(co * 9 * ci) * sd)
+        parts.append(rng.standard_normal(co) * 0.05 + (np.log(20.0) if co == 1 else 0.0))
+    return np.concatenate(parts).astype(np.float32)
+
+
+@pytest.mark.parametrize("h,w,c,seed", [(40, 27, 3, 0), (128, 128, 3, 1), (33, 64, 1, 2), (17, 9, 3, 3)])
+def test_forward_matches_oracle(dn, h, w, c, seed):
+    import paper_2512_23569_amd as ht
+    p = _params(c, seed)
+    ht.htsvd_cnn_set_weights(dn.ctx, c, p)
+    rng = np.random.default_rng(seed + 10)
+    img = synth.add_awgn(synth.make_clean(h, w, c, seed + 20), float(rng.uniform(5, 60)), seed + 30)
+    d = torch.from_numpy(img).cuda()
+    z = dn.sigma_map(d).cpu().numpy()
+    ref, _ = cnn.forward(to_bf16(p), img.reshape(1, h, w, c), c, act_round=to_bf16)
+    assert z.shape == ref[0].shape
+    assert np.max(np.abs(z - ref[0])) <= 0.03, np.max(np.abs(z - ref[0]))
+
+
+@pytest.mark.parametrize("c", [3, 1])
+def test_gradients_match_oracle(dn, c):
+    import paper_2512_23569_amd as ht
+    p = _params(c, 40 + c)
+    ht.htsvd_cnn_set_weights(dn.ctx, c, p)
+    n, size = 4, 48
+    crops, labels = [], []
+    for i in range(n):
+        x, y, _ = synth.sigma_crop(100 + i, size, c)
+        crops.append(x.reshape(size, size, c))
+        labels.append(y)
+    X = np.stack(crops)
+    Y = np.stack(labels).astype(np.float32)
+    g = torch.zeros(ht.htsvd_cnn_param_count(c), dtype=torch.float32, device="cuda")
+    loss = ht.htsvd_cnn_gradients(dn.ctx, torch.from_numpy(X).cuda(), n, size, size, c,
+                                  torch.from_numpy(Y).cuda(), g)
+    gg = g.cpu().numpy().astype(np.float64)
+    ref_loss, ref_g = cnn.loss_and_grad(to_bf16(p), X, Y.astype(np.float64), c, act_round=to_bf16)
+    assert abs(loss - ref_loss) <= 1e-3 * max(1.0, ref_loss)
+    cos = float(gg @ ref_g / (np.linalg.norm(gg) * np.linalg.norm(ref_g)))
+    rel = float(np.linalg.norm(gg - ref_g) / np.linalg.norm(ref_g))
+    assert cos >= 0.999 and rel <= 3e-2, (cos, rel)
+
+
+def test_training_reduces_loss_and_checkpoint_resumes(dn, tmp_path):
+    import paper_2512_23569_amd as ht
+    c, n, size = 3, 16, 64
+    ht.htsvd_cnn_init(dn.ctx, c, 7)
+    X, Y = [], []
+    for i in range(4 * n):
+        x, y, _ = synth.sigma_crop(500 + i, size, c)
+        X.append(x)
+        Y.append(y)
+    X = torch.from_numpy(np.stack(X)).cuda()
+    Y = torch.from_numpy(np.stack(Y).astype(np.float32)).cuda()
+    losses = []
+    for it in range(40):
+        b = (it % 4) * n
+        losses.append(ht.htsvd_cnn_train_step(dn.ctx, X[b:b + n], n, size, size, c, Y[b:b + n], 2e-3))
+    assert np.mean(losses[-8:]) < 0.7 * np.mean(losses[:4]), losses
+    ck = str(tmp_path / "net.ckpt")
+    ht.htsvd_cnn_save(dn.ctx, ck)
+    w_saved = ht.htsvd_cnn_get_weights(dn.ctx, c)
+    other = ht.Denoiser(0, load_network=False)
+    try:
+        ht.htsvd_cnn_load(other.ctx, ck)
+        assert np.array_equal(ht.htsvd_cnn_get_weights(other.ctx, c), w_saved)
+        # the resumed run and the uninterrupted run take the same next steps (Adam state restored)
+        for it in range(3):
+            ht.htsvd_cnn_train_step(dn.ctx, X[:n], n, size, size, c, Y[:n], 1e-3)
+            ht.htsvd_cnn_train_step(other.ctx, X[:n], n, size, size, c, Y[:n], 1e-3)
+        a, b2 = ht.htsvd_cnn_get_weights(dn.ctx, c), ht.htsvd_cnn_get_weights(other.ctx, c)
+        assert np.max(np.abs(a - b2)) <= 1e-4 * max(1.0, np.max(np.abs(a)))
+    finally:
+        other.close()
+
+
+def test_learned_path_falls_back_to_plain_estimator(dn):
+    """A network whose map is far from the plain estimate everywhere is rejected tile by tile,
+    and the output equals the plain-estimator output (up to the order of the float additions)."""
+    import paper_2512_23569_amd as ht
+    p = _params(3, 9)
+    wo = 0
+    for ci, co, s, relu in cnn.layer_shapes(3):
+        wo += co * 9 * ci + co
+    p[wo - 1] = 12.0          # last bias: sigma = e^12
+    ht.htsvd_cnn_set_weights(dn.ctx, 3, p)
+    clean, noisy, _ = synth.make_cfg("rgb512_awgn50", h=200, w=260)
+    d = torch.from_numpy(noisy).cuda()
+    plain = dn.denoise(d, -1.0, dn.params(3, stride=4, window=21, K=16, adaptive=1, estimator=0)).cpu().numpy()
+    learned = dn.denoise(d, -1.0, dn.params(3, stride=4, window=21, K=16, adaptive=1, estimator=1)).cpu().numpy()
+    # same thresholds everywhere; only the order of the LDS float additions may differ
+    assert np.max(np.abs(plain - learned)) <= 1e-3
+
+
+def test_trained_network_beats_plain_estimate_on_varying_noise():
+    """With the shipped trained weights: on images whose noise level varies smoothly, the
+    per-block learned sigma is closer to the truth than the per-sub-image plain estimate,
+    and denoising with it gives a higher PSNR."""
+    import paper_2512_23569_amd as ht
+    path = os.path.join(ht.DATA_DIR, "sigma_cnn_c3.ckpt")
+    if not os.path.exists(path):
+        pytest.skip("no trained network shipped")
+    d = ht.Denoiser(0)
+    try:
+        gains, mae_l, mae_p = [], [], []
+        for seed in range(3):
+            rng = np.random.Generator(np.random.PCG64(2000 + seed))
+            h, w = 384, 512
+            field = synth.smooth_sigma_field(h, w, rng, 5.0, 75.0)
+            clean = synth.make_clean(h, w, 3, 3000 + seed)
+            noisy = synth.add_sigma_field_noise(clean, field, 4000 + seed)
+            x = torch.from_numpy(noisy).cuda()
+            truth = synth.block_log_sigma(field)
+            z = d.sigma_map(x).cpu().numpy()
+            se = torch.zeros(12, dtype=torch.float64, device="cuda")
+            ht.htsvd_estimate_sigma(d.ctx, x, h, w, 3, x.stride(0), -1.0, d.params(3), se)
+            plain_blocks = np.repeat(np.repeat(se.cpu().numpy().reshape(3, 4), 16, 0), 16, 1)[:48, :64]
+            mae_l.append(np.mean(np.abs(z - truth)))
+            mae_p.append(np.mean(np.abs(np.log(plain_blocks) - truth)))
+            p = d.params(3, stride=4, window=21, K=16)
+            out_p = d.denoise(x, -1.0, p.replace(estimator=0)).cpu().numpy()
+            out_l = d.denoise(x, -1.0, p.replace(estimator=1)).cpu().numpy()
+            gains.append(synth.psnr(clean, out_l) - synth.psnr(clean, out_p))
+        print("sigma MAE (log) learned %.3f plain %.3f, PSNR gain %s" % (np.mean(mae_l), np.mean(mae_p), gains))
+        assert np.mean(mae_l) < np.mean(mae_p)
+        assert np.mean(gains) > 0.0
+    finally:
+        d.close()
