@@ -114,6 +114,30 @@ htsvd_status htsvd_denoise_tau(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, i
                                int64_t in_stride, const double *d_tau_ref, const htsvd_params *p, float *d_out,
                                int64_t out_stride, void *stream);
 
+/* One image of a batched call. */
+typedef struct {
+    const uint8_t *d_in;  /* device, uint8 HWC */
+    int32_t h, w, c;
+    int64_t in_stride;    /* bytes per row */
+    float sigma;          /* > 0: known noise level; HTSVD_SIGMA_AUTO: estimated (p->estimator) */
+    int32_t K;            /* group size for this image (0: p->K); the autotuner picks 16 or 32 */
+    float *d_out;         /* device, float32 HWC */
+    int64_t out_stride;   /* elements per row */
+} htsvd_image;
+
+typedef struct {
+    int32_t use_graph;      /* 1: capture the launches in a hipGraph; an identical batch replays it */
+    int32_t blocks_per_cu;  /* persistent workgroups per compute unit for the work-queue kernels (0 = 1) */
+} htsvd_batch_opts;
+
+/* Denoises n images of any sizes (one channel count) with shared method parameters.  Block
+ * matching, filtering and aggregation run as persistent kernels that pull (image, tile) units
+ * from work queues, so one launch covers the whole batch; with use_graph the whole sequence is
+ * captured once in a hipGraph and replayed while the batch (pointers, shapes, sigma, K) and
+ * the parameters stay the same.  opts may be NULL (defaults: graph on, 1 block per CU). */
+htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, const htsvd_params *p,
+                                 const htsvd_batch_opts *opts, void *stream);
+
 /* Noise levels per sub-image (ceil(h/S) * ceil(w/S) tiles, S = p->subimage, row-major):
  * d_sigma_est: plain estimate before the vote (FP64), d_sigma_hat: after Eq. 23 (FP64,
  * equals d_sigma_est when p->adaptive is 0), d_votes: "adjust" votes per tile (int32).

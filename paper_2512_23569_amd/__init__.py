@@ -41,6 +41,18 @@ class htsvd_params(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class htsvd_image(ctypes.Structure):
+    _fields_ = [
+        ("d_in", ctypes.c_void_p), ("h", ctypes.c_int32), ("w", ctypes.c_int32), ("c", ctypes.c_int32),
+        ("in_stride", ctypes.c_int64), ("sigma", ctypes.c_float), ("K", ctypes.c_int32),
+        ("d_out", ctypes.c_void_p), ("out_stride", ctypes.c_int64),
+    ]
+
+
+class htsvd_batch_opts(ctypes.Structure):
+    _fields_ = [("use_graph", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+
 class HtsvdError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__("%s (%d): %s" % (_STATUS.get(status, "?"), status, msg))
@@ -61,6 +73,7 @@ _SIGS = {
     "htsvd_block_match": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _PP, _vp, _vp, _vp]),
     "htsvd_denoise": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _i64, _vp]),
     "htsvd_denoise_tau": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _vp, _PP, _vp, _i64, _vp]),
+    "htsvd_denoise_batch": (_i32, [_vp, _i32, ctypes.POINTER(htsvd_image), _PP, ctypes.POINTER(htsvd_batch_opts), _vp]),
     "htsvd_estimate_sigma": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _vp, _vp, _vp]),
     "htsvd_sync": (_i32, [_vp, _vp]),
     "htsvd_last_error": (ctypes.c_char_p, []),
@@ -186,6 +199,14 @@ def htsvd_denoise_tau(ctx, d_in, h, w, c, in_stride, d_tau_ref, params, d_out, o
     _check(lib().htsvd_denoise_tau(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, c, in_stride,
                                    _dptr(d_tau_ref, torch.float64, "d_tau_ref"), ctypes.byref(params),
                                    _dptr(d_out, torch.float32, "d_out"), out_stride, _stream(stream)))
+
+
+def htsvd_denoise_batch(ctx, images, params, use_graph=1, blocks_per_cu=1, stream=None):
+    """images: a sequence of htsvd_image (device pointers filled in by the caller)."""
+    arr = (htsvd_image * len(images))(*images)
+    opts = htsvd_batch_opts(int(use_graph), int(blocks_per_cu))
+    _check(lib().htsvd_denoise_batch(ctx, len(images), arr, ctypes.byref(params), ctypes.byref(opts),
+                                     _stream(stream)))
 
 
 def htsvd_estimate_sigma(ctx, d_in, h, w, c, in_stride, sigma, params, d_sigma_est=None, d_sigma_hat=None,
@@ -335,6 +356,23 @@ class Denoiser:
             out = torch.empty(img.shape, dtype=torch.float32, device=img.device)
         htsvd_denoise_tau(self.ctx, img, h, w, c, st, tau_ref, params, out, out.stride(0), stream)
         return out
+
+    def denoise_batch(self, imgs, sigmas, params, Ks=None, outs=None, use_graph=True, blocks_per_cu=1,
+                      stream=None):
+        """Denoises a list of uint8 device images in one batched call; sigma HTSVD_SIGMA_AUTO
+        (-1) estimates the level.  Returns the list of float32 outputs."""
+        import torch
+        if outs is None:
+            outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in imgs]
+        descs = []
+        for i, x in enumerate(imgs):
+            h, w, c, st = _img_dims(x)
+            _dptr(x, torch.uint8, "image")
+            _dptr(outs[i], torch.float32, "output")
+            descs.append(htsvd_image(x.data_ptr(), h, w, c, st, float(sigmas[i]), int(Ks[i]) if Ks else 0,
+                                     outs[i].data_ptr(), outs[i].stride(0)))
+        htsvd_denoise_batch(self.ctx, descs, params, use_graph, blocks_per_cu, stream)
+        return outs
 
     def guard_count(self):
         return htsvd_last_guard_count(self.ctx)

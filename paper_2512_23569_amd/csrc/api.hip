@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <complex>
 #include <string>
 #include <vector>
@@ -33,6 +34,16 @@ struct CnnState {
     double *d_loss = nullptr;
 };
 
+// A planned (and possibly captured) batch: device-side descriptors and the graph replaying it.
+struct BatchCache {
+    uint64_t sig = 0;
+    bool valid = false;
+    void *dev = nullptr;           // items, unit tables, sigma/mult arrays, queues
+    size_t dev_size = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct htsvd_ctx {
     int device = 0;
     BasisDev basis[2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [0]: c=1, [1]: c=3
@@ -47,6 +58,8 @@ struct htsvd_ctx {
     double stage_ms[HTSVD_N_STAGES] = {};
     int64_t stage_calls[HTSVD_N_STAGES] = {};
     CnnState cnn;
+    BatchCache batch;
+    hipStream_t cap_stream = nullptr;   // stream used only to capture batch graphs
 };
 
 namespace {
@@ -117,6 +130,7 @@ htsvd_status ensure_ws(htsvd_ctx *ctx, size_t bytes) {
         ctx->ws = nullptr;
         ctx->ws_size = 0;
     }
+    ctx->batch.valid = false;   // a captured batch graph points into the old workspace
     size_t sz = bytes + (bytes >> 3);
     e = hipMalloc(&ctx->ws, sz);
     if (e != hipSuccess) {
@@ -227,6 +241,7 @@ htsvd_status ensure_cnn_ws(htsvd_ctx *ctx, size_t bytes) {
     CnnState &cs = ctx->cnn;
     if (cs.ws_size >= bytes) return HTSVD_OK;
     hipError_t e;
+    ctx->batch.valid = false;
     if (cs.ws) {
         if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronise before workspace growth");
         (void)hipFree(cs.ws);
@@ -432,6 +447,10 @@ void htsvd_destroy(htsvd_ctx *ctx) {
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->d_guard) (void)hipFree(ctx->d_guard);
     cnn_free(ctx->cnn);
+    if (ctx->batch.exec) (void)hipGraphExecDestroy(ctx->batch.exec);
+    if (ctx->batch.graph) (void)hipGraphDestroy(ctx->batch.graph);
+    if (ctx->batch.dev) (void)hipFree(ctx->batch.dev);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
 
@@ -805,6 +824,316 @@ htsvd_status htsvd_cnn_load(htsvd_ctx *ctx, const char *path) {
         return hip_fail(e, "upload");
     cs.step = step;
     return HTSVD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
+    const unsigned char *p = (const unsigned char *)data;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 0x100000001B3ull;
+    }
+    return h;
+}
+
+struct BatchImage {
+    int src;                 // index in the caller's array
+    ImageGeom g;
+    MethodParams mp;
+    TileGeom tg;
+    int bm_tiles_x, bm_tiles;
+    int64_t n_ref, n_tiles_sigma;
+    size_t off_idx, off_tau, off_reg, off_sig;   // byte offsets in the workspace
+    float *out;
+    int64_t out_stride;
+    float sigma;
+};
+
+// Host plan of a batch: workspace layout, unit tables, per-class descriptor lists.
+struct BatchPlan {
+    std::vector<BatchImage> im;
+    std::vector<int> classes;                     // distinct K values
+    size_t ws_total = 0;
+    int max_s = 1, max_W = 3, max_h = 8, max_w = 8;
+    bool any_auto = false;
+};
+
+htsvd_status plan_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, const htsvd_params *p, BatchPlan *bp) {
+    BatchPlan &P = *bp;
+    const int T = p->subimage;
+    for (int i = 0; i < n; ++i) {
+        const htsvd_image &x = imgs[i];
+        htsvd_params pi = *p;
+        if (x.K) pi.K = x.K;
+        BatchImage b;
+        htsvd_status s = validate(ctx, x.d_in, x.h, x.w, x.c, x.in_stride, &pi, &b.g, &b.mp, true);
+        if (s != HTSVD_OK) return fail(s, std::string("image ") + std::to_string(i) + ": " + htsvd_last_error());
+        if (!x.d_out || x.out_stride < (int64_t)x.w * x.c) return fail(HTSVD_EINVAL, "bad output of image " + std::to_string(i));
+        if (!(x.sigma > 0.f) && x.sigma != HTSVD_SIGMA_AUTO) return fail(HTSVD_EINVAL, "bad sigma of image " + std::to_string(i));
+        if (i > 0 && x.c != imgs[0].c) return fail(HTSVD_ENOTSUP, "all images of a batch must have the same channel count");
+        b.src = i;
+        b.sigma = x.sigma;
+        b.out = x.d_out;
+        b.out_stride = x.out_stride;
+        b.bm_tiles_x = (b.g.nx + REF_TILE - 1) / REF_TILE;
+        b.bm_tiles = ((b.g.ny + REF_TILE - 1) / REF_TILE) * b.bm_tiles_x;
+        b.tg = plan_filter_tiles(b.g, b.mp.W, b.mp.K, filter_lds_budget());
+        b.n_ref = (int64_t)b.g.ny * b.g.nx;
+        b.n_tiles_sigma = (int64_t)((b.g.h + T - 1) / T) * ((b.g.w + T - 1) / T);
+        P.any_auto |= (x.sigma == HTSVD_SIGMA_AUTO) || p->adaptive;
+        P.im.push_back(b);
+    }
+    // largest images first: their units enter the work queues first and the tail is short
+    std::stable_sort(P.im.begin(), P.im.end(), [](const BatchImage &a, const BatchImage &b) {
+        return (int64_t)a.g.h * a.g.w > (int64_t)b.g.h * b.g.w;
+    });
+    size_t off = 0;
+    for (BatchImage &b : P.im) {
+        b.off_idx = off; off = align256(off + sizeof(int32_t) * b.n_ref * b.mp.K);
+        b.off_tau = off; off = align256(off + sizeof(double) * b.n_ref);
+        b.off_reg = off;
+        off = align256(off + (size_t)b.tg.tiles_y * b.tg.tiles_x * b.tg.RH * b.tg.RW * (b.g.c + 1) * sizeof(float));
+        b.off_sig = off;  // sig_est, sig_hat, votes, cov (c per tile), use_plain, sig_plain
+        off = align256(off + b.n_tiles_sigma * (sizeof(double) * (3 + b.g.c) + 2 * sizeof(int32_t)));
+        P.max_s = std::max(P.max_s, b.g.s);
+        P.max_W = std::max(P.max_W, b.mp.W);
+        P.max_h = std::max(P.max_h, b.g.h);
+        P.max_w = std::max(P.max_w, b.g.w);
+        if (std::find(P.classes.begin(), P.classes.end(), b.mp.K) == P.classes.end()) P.classes.push_back(b.mp.K);
+    }
+    int64_t px = 0, refs = 0, bm = 0;
+    for (const BatchImage &b : P.im) {
+        px += (int64_t)b.g.h * b.g.w;
+        refs += b.n_ref;
+        bm += b.bm_tiles;
+    }
+    if (px >= ((int64_t)1 << 31) || refs >= ((int64_t)1 << 31) || bm >= ((int64_t)1 << 31))
+        return fail(HTSVD_ENOTSUP, "batch too large (2^31 pixels at most)");
+    P.ws_total = off;
+    return HTSVD_OK;
+}
+
+// Per-image workspace view (the layout the single-image helpers expect).
+Ws image_ws(void *base, const BatchImage &b) {
+    Ws w;
+    char *c = (char *)base;
+    w.idx = (int32_t *)(c + b.off_idx);
+    w.tau = (double *)(c + b.off_tau);
+    w.regions = (float *)(c + b.off_reg);
+    double *sig = (double *)(c + b.off_sig);
+    w.sig_est = sig;
+    w.sig_hat = sig + b.n_tiles_sigma;
+    w.cov = sig + 2 * b.n_tiles_sigma;
+    w.sig_plain = sig + (2 + b.g.c) * b.n_tiles_sigma;
+    w.votes = (int32_t *)(sig + (3 + b.g.c) * b.n_tiles_sigma);
+    w.use_plain = w.votes + b.n_tiles_sigma;
+    w.total = 0;
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, const htsvd_params *p,
+                                 const htsvd_batch_opts *opts, void *stream) {
+    if (!ctx || !imgs || !p) return fail(HTSVD_EINVAL, "null argument");
+    if (n < 1) return fail(HTSVD_EINVAL, "empty batch");
+    htsvd_batch_opts o = {1, 1};
+    if (opts) o = *opts;
+    if (o.blocks_per_cu < 1) o.blocks_per_cu = 1;
+    if (o.blocks_per_cu > 8) return fail(HTSVD_EINVAL, "blocks_per_cu must be in [1, 8]");
+    hipStream_t st = (hipStream_t)stream;
+
+    uint64_t sig = fnv1a(0xcbf29ce484222325ull, imgs, sizeof(htsvd_image) * n);
+    sig = fnv1a(sig, p, sizeof(*p));
+    sig = fnv1a(sig, &o, sizeof(o));
+    sig = fnv1a(sig, &ctx->cnn.w, sizeof(ctx->cnn.w));
+    sig = fnv1a(sig, &ctx->cnn.c, sizeof(ctx->cnn.c));
+    if (o.use_graph && ctx->batch.valid && ctx->batch.sig == sig) {
+        hipError_t e = hipGraphLaunch(ctx->batch.exec, st);
+        if (e != hipSuccess) return hip_fail(e, "graph launch");
+        return HTSVD_OK;
+    }
+
+    BatchPlan P;
+    htsvd_status s = plan_batch(ctx, n, imgs, p, &P);
+    if (s != HTSVD_OK) return s;
+    const int ni = (int)P.im.size();
+    const int C = P.im[0].g.c;
+    const bool learned_any = p->estimator == 1;
+    for (const BatchImage &b : P.im)
+        if (b.sigma == HTSVD_SIGMA_AUTO && learned_any) {
+            if (!ctx->cnn.w) return fail(HTSVD_ESTATE, "learned estimator requested but no network weights are set");
+            CnnWs cw = plan_cnn_ws(nullptr, 1, P.max_h, P.max_w, C, false);
+            if ((s = ensure_cnn_ws(ctx, cw.total)) != HTSVD_OK) return s;
+            break;
+        }
+    if ((s = ensure_ws(ctx, P.ws_total)) != HTSVD_OK) return s;
+
+    // descriptor tables (host), then one upload
+    std::vector<BatchItem> items(ni);
+    std::vector<int> bm_start(ni + 1, 0), ref_start(ni + 1, 0), pix_start(ni + 1, 0);
+    std::vector<double> sigma_h(ni), mult_h(ni);
+    for (int i = 0; i < ni; ++i) {
+        const BatchImage &b = P.im[i];
+        Ws w = image_ws(ctx->ws, b);
+        BatchItem &it = items[i];
+        it.g = b.g;
+        it.mp = b.mp;
+        it.tg = b.tg;
+        it.bm_tiles_x = b.bm_tiles_x;
+        it.idx = w.idx;
+        it.tau = w.tau;
+        it.regions = w.regions;
+        it.out = b.out;
+        it.out_stride = b.out_stride;
+        bm_start[i + 1] = bm_start[i] + b.bm_tiles;
+        ref_start[i + 1] = ref_start[i] + (int)b.n_ref;
+        pix_start[i + 1] = pix_start[i] + b.g.h * b.g.w;
+        sigma_h[i] = b.sigma > 0.f ? (double)b.sigma : 0.0;
+        mult_h[i] = p->tau_mult > 0.0 ? p->tau_mult : default_mult(C, b.mp.K);
+    }
+    // per-class (K) filter tables: items of the class and their tile prefix sums
+    std::vector<std::vector<BatchItem>> cls_items(P.classes.size());
+    std::vector<std::vector<int>> cls_start(P.classes.size());
+    std::vector<int> cls_lds(P.classes.size(), 0);
+    for (size_t k = 0; k < P.classes.size(); ++k) {
+        cls_start[k].push_back(0);
+        for (int i = 0; i < ni; ++i)
+            if (items[i].mp.K == P.classes[k]) {
+                cls_items[k].push_back(items[i]);
+                const TileGeom &tg = items[i].tg;
+                cls_start[k].push_back(cls_start[k].back() + tg.tiles_y * tg.tiles_x);
+                cls_lds[k] = std::max(cls_lds[k], filter_lds_bytes_for(tg, C, P.classes[k]));
+            }
+    }
+    // device layout: items | class items... | bm_start | ref_start | pix_start | class starts... | sigma | mult | queues
+    size_t off = 0;
+    auto reserve = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    const size_t o_items = reserve(sizeof(BatchItem) * ni);
+    std::vector<size_t> o_citems(P.classes.size()), o_cstart(P.classes.size());
+    for (size_t k = 0; k < P.classes.size(); ++k) o_citems[k] = reserve(sizeof(BatchItem) * cls_items[k].size());
+    const size_t o_bm = reserve(sizeof(int) * (ni + 1)), o_ref = reserve(sizeof(int) * (ni + 1)),
+                 o_pix = reserve(sizeof(int) * (ni + 1));
+    for (size_t k = 0; k < P.classes.size(); ++k) o_cstart[k] = reserve(sizeof(int) * cls_start[k].size());
+    const size_t o_sig = reserve(sizeof(double) * ni), o_mult = reserve(sizeof(double) * ni);
+    const size_t o_q = reserve(sizeof(int) * (1 + P.classes.size()));
+    std::vector<unsigned char> host(off, 0);
+    memcpy(host.data() + o_items, items.data(), sizeof(BatchItem) * ni);
+    for (size_t k = 0; k < P.classes.size(); ++k) {
+        memcpy(host.data() + o_citems[k], cls_items[k].data(), sizeof(BatchItem) * cls_items[k].size());
+        memcpy(host.data() + o_cstart[k], cls_start[k].data(), sizeof(int) * cls_start[k].size());
+    }
+    memcpy(host.data() + o_bm, bm_start.data(), sizeof(int) * (ni + 1));
+    memcpy(host.data() + o_ref, ref_start.data(), sizeof(int) * (ni + 1));
+    memcpy(host.data() + o_pix, pix_start.data(), sizeof(int) * (ni + 1));
+    memcpy(host.data() + o_sig, sigma_h.data(), sizeof(double) * ni);
+    memcpy(host.data() + o_mult, mult_h.data(), sizeof(double) * ni);
+    hipError_t e;
+    BatchCache &bc = ctx->batch;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronise before batch planning");
+    if (bc.exec) { (void)hipGraphExecDestroy(bc.exec); bc.exec = nullptr; }
+    if (bc.graph) { (void)hipGraphDestroy(bc.graph); bc.graph = nullptr; }
+    bc.valid = false;
+    if (bc.dev_size < off) {
+        if (bc.dev) (void)hipFree(bc.dev);
+        bc.dev = nullptr;
+        bc.dev_size = 0;
+        if (hipMalloc(&bc.dev, off) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(HTSVD_ENOMEM, "batch descriptor allocation");
+        }
+        bc.dev_size = off;
+    }
+    if ((e = hipMemcpy(bc.dev, host.data(), off, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "batch descriptor upload");
+    char *D = (char *)bc.dev;
+    const BatchItem *d_items = (const BatchItem *)(D + o_items);
+    int *d_q = (int *)(D + o_q);
+    int n_cu = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (n_cu < 1) n_cu = 1;
+    const int grid = n_cu * o.blocks_per_cu;
+
+    // the launch sequence (captured when use_graph)
+    hipStream_t ls = st;
+    const bool timing = ctx->timing;
+    if (o.use_graph) {
+        if (!ctx->cap_stream && (e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "capture stream");
+        ls = ctx->cap_stream;
+        ctx->timing = false;   // no event records inside the graph
+        if ((e = hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+            ctx->timing = timing;
+            return hip_fail(e, "begin capture");
+        }
+    }
+    auto enqueue = [&]() -> htsvd_status {
+        hipError_t e2;
+        if ((e2 = launch_zero(d_q, sizeof(int) * (1 + P.classes.size()), ls)) != hipSuccess) return hip_fail(e2, "queues");
+        if ((e2 = launch_zero(ctx->d_guard, 2 * sizeof(unsigned long long), ls)) != hipSuccess) return hip_fail(e2, "counters");
+        if ((e2 = launch_fill_tau_batched(d_items, ni, (const int *)(D + o_ref), ref_start[ni], (const double *)(D + o_sig),
+                                          (const double *)(D + o_mult), ls)) != hipSuccess)
+            return hip_fail(e2, "tau");
+        if ((e2 = launch_block_match_batched(d_items, ni, (const int *)(D + o_bm), P.max_s, P.max_W, P.max_h, P.max_w,
+                                             d_q, std::min(grid, bm_start[ni]), ls)) != hipSuccess)
+            return hip_fail(e2, "batched block matching");
+        // images whose noise level is estimated or adjusted: per-image sigma stages
+        for (int i = 0; i < ni; ++i) {
+            const BatchImage &b = P.im[i];
+            if (!(b.sigma == HTSVD_SIGMA_AUTO || p->adaptive)) continue;
+            Ws w = image_ws(ctx->ws, b);
+            htsvd_params pi = *p;
+            pi.K = b.mp.K;
+            const float *zmap = nullptr;
+            const bool learned = b.sigma == HTSVD_SIGMA_AUTO && p->estimator == 1;
+            htsvd_status s2;
+            if (learned && (s2 = run_cnn_map(ctx, b.g, ls, &zmap)) != HTSVD_OK) return s2;
+            if ((s2 = run_sigma(ctx, b.g, b.mp, &pi, b.sigma, w, zmap, ls)) != HTSVD_OK) return s2;
+            if (learned)
+                e2 = launch_fill_tau_learned(w.tau, b.g, pi.subimage, zmap, w.use_plain, w.sig_est, w.sig_hat, mult_h[i], ls);
+            else
+                e2 = launch_fill_tau(w.tau, b.n_ref, w.sig_hat, 0.0, mult_h[i], b.g, pi.subimage, ls);
+            if (e2 != hipSuccess) return hip_fail(e2, "tau");
+        }
+        for (size_t k = 0; k < P.classes.size(); ++k) {
+            const int units = cls_start[k].back();
+            if ((e2 = launch_filter_batched(C, P.classes[k], (const BatchItem *)(D + o_citems[k]), (int)cls_items[k].size(),
+                                            (const int *)(D + o_cstart[k]), cls_lds[k], ctx->basis[C == 3], ctx->d_guard,
+                                            d_q + 1 + k, std::min(grid, units), ls)) != hipSuccess)
+                return hip_fail(e2, "batched filtering");
+        }
+        if ((e2 = launch_gather_batched(C, d_items, ni, (const int *)(D + o_pix), pix_start[ni], ls)) != hipSuccess)
+            return hip_fail(e2, "batched aggregation");
+        return HTSVD_OK;
+    };
+    s = enqueue();
+    if (o.use_graph) {
+        hipGraph_t g = nullptr;
+        hipError_t ee = hipStreamEndCapture(ls, &g);
+        ctx->timing = timing;
+        if (s != HTSVD_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (ee != hipSuccess) return hip_fail(ee, "end capture");
+        hipGraphExec_t ex = nullptr;
+        if ((e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0)) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "graph instantiate");
+        }
+        bc.graph = g;
+        bc.exec = ex;
+        bc.sig = sig;
+        bc.valid = true;
+        if ((e = hipGraphLaunch(ex, st)) != hipSuccess) return hip_fail(e, "graph launch");
+    }
+    return s;
 }
 
 htsvd_status htsvd_sync(htsvd_ctx *ctx, void *stream) {

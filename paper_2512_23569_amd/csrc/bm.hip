@@ -117,22 +117,11 @@ __device__ void lds_sort(uint64_t *a, int P, int lane) {
     }
 }
 
-__global__ __launch_bounds__(256) void bm_kernel(ImageGeom g, MethodParams mp, int tiles_x, int n_tiles,
-                                                 BmLds L, int32_t *__restrict__ idx_out,
-                                                 int32_t *__restrict__ dist_out) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ TileInfo ti;
+// Groups of the 16 references of tile b.
+__device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &mp, const int tiles_x, const int b,
+                                        const BmLds &L, int32_t *__restrict__ idx_out,
+                                        int32_t *__restrict__ dist_out, unsigned char *smem, TileInfo &ti) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    // XCD-aware order: consecutive workgroups are dealt round-robin over the 8 XCDs; give
-    // each XCD a contiguous run of tiles so neighbouring tiles share its L2.
-    // The grid has 8*ceil(n_tiles/8) workgroups; b -> (b%8)*per + b/8 is a bijection on it.
-    int b;
-    {
-        const int per = (n_tiles + 7) / 8;
-        b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-        if (b >= n_tiles) return;
-    }
     const int tyi = b / tiles_x, txi = b % tiles_x;
     const int R = (mp.W - 1) / 2;
 
@@ -389,6 +378,41 @@ __global__ __launch_bounds__(256) void bm_kernel(ImageGeom g, MethodParams mp, i
     }
 }
 
+__global__ __launch_bounds__(256) void bm_kernel(ImageGeom g, MethodParams mp, int tiles_x, int n_tiles,
+                                                 BmLds L, int32_t *__restrict__ idx_out,
+                                                 int32_t *__restrict__ dist_out) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ TileInfo ti;
+    // XCD-aware order: consecutive workgroups are dealt round-robin over the 8 XCDs; give
+    // each XCD a contiguous run of tiles so neighbouring tiles share its L2.
+    // The grid has 8*ceil(n_tiles/8) workgroups; b -> (b%8)*per + b/8 is a bijection on it.
+    const int per = (n_tiles + 7) / 8;
+    const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (b >= n_tiles) return;
+    bm_tile(g, mp, tiles_x, b, L, idx_out, dist_out, smem, ti);
+}
+
+// Persistent form over many images: each workgroup pulls (image, tile) units from a queue.
+__global__ __launch_bounds__(256) void bm_kernel_batched(const BatchItem *__restrict__ items, int n_items,
+                                                         const int *__restrict__ unit_start, BmLds L,
+                                                         int *__restrict__ queue) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ TileInfo ti;
+    __shared__ int s_u;
+    const int total = unit_start[n_items];
+    for (;;) {
+        if (threadIdx.x == 0) s_u = atomicAdd(queue, 1);
+        __syncthreads();
+        const int u = s_u;
+        __syncthreads();
+        if (u >= total) break;
+        const int i = find_unit(unit_start, n_items, u);
+        const BatchItem it = items[i];
+        bm_tile(it.g, it.mp, it.bm_tiles_x, u - unit_start[i], L, it.idx, nullptr, smem, ti);
+        __syncthreads();
+    }
+}
+
 BmLds bm_lds_layout(int uh_max, int uw_max) {
     BmLds L;
     L.rows = uh_max + PS - 1;
@@ -433,6 +457,20 @@ hipError_t launch_block_match(const ImageGeom &g, const MethodParams &mp, int32_
     // round the grid up to a multiple of 8 so the XCD remap is a bijection onto [0, 8*per)
     const int per = (n_tiles + 7) / 8;
     hipLaunchKernelGGL(bm_kernel, dim3(8 * per), dim3(256), L.total, st, g, mp, tiles_x, n_tiles, L, idx, dist);
+    return hipGetLastError();
+}
+
+// Batched block matching: one persistent launch over the tiles of all images; the LDS layout
+// is the largest any image of the batch needs.
+hipError_t launch_block_match_batched(const BatchItem *items, int n_items, const int *unit_start, int max_s,
+                                      int max_W, int max_h, int max_w, int *queue, int grid, hipStream_t st) {
+    const int span = (REF_TILE - 1) * max_s + max_W;
+    const int uh = span < max_h - PS + 1 ? span : max_h - PS + 1;
+    const int uw = span < max_w - PS + 1 ? span : max_w - PS + 1;
+    BmLds L = bm_lds_layout(uh, uw);
+    hipError_t e = prepare_dynamic_lds((const void *)bm_kernel_batched, L.total, (int)sizeof(TileInfo) + 16);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bm_kernel_batched, dim3(grid), dim3(256), L.total, st, items, n_items, unit_start, L, queue);
     return hipGetLastError();
 }
 

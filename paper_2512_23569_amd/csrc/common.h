@@ -38,6 +38,37 @@ struct BasisDev {
     double *T64;    // P*P doubles
 };
 
+// Reference tiles of the filter kernel and the image regions their groups reach.
+struct TileGeom {
+    int TY, TX;          // references per tile
+    int tiles_y, tiles_x;
+    int RH, RW;          // region capacity (rows, cols) per tile
+    int R;               // search radius (W-1)/2
+};
+
+// One image of a batched call, as the persistent kernels see it.
+struct BatchItem {
+    ImageGeom g;
+    MethodParams mp;
+    TileGeom tg;
+    int bm_tiles_x;
+    int32_t *idx;          // groups, n_ref * K
+    const double *tau;     // thresholds, n_ref
+    float *regions;        // per-tile regions of the filter
+    float *out;            // output image
+    int64_t out_stride;
+};
+
+// Index i of the unit range [start[i], start[i+1]) holding u (start has n+1 entries).
+__device__ inline int find_unit(const int *start, int n, int u) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Reference position along one side: 0, s, 2s, ... and the last position n-ps.
 __host__ __device__ inline int ref_pos(int i, int n_ref, int n, int s) {
     return (i == n_ref - 1) ? (n - PS) : i * s;
@@ -67,6 +98,19 @@ hipError_t launch_sigma_est(const ImageGeom &g, int tile, double *cov_work, doub
 hipError_t launch_vote(const ImageGeom &g, const MethodParams &mp, const int32_t *idx, int tile, int n_vote,
                        uint64_t seed, int gamma_rank, double beta, const double *sigma_est, double *sigma_hat,
                        int32_t *votes, hipStream_t st);
+
+// ---- batched (persistent, work-queue) forms ----
+hipError_t launch_block_match_batched(const BatchItem *items, int n_items, const int *unit_start, int max_s,
+                                      int max_W, int max_h, int max_w, int *queue, int grid, hipStream_t st);
+hipError_t launch_filter_batched(int C, int K, const BatchItem *items, int n_items, const int *unit_start, int lds,
+                                 const BasisDev &b, unsigned long long *gc, int *queue, int grid, hipStream_t st);
+hipError_t launch_gather_batched(int C, const BatchItem *items, int n_items, const int *pix_start, int total_px,
+                                 hipStream_t st);
+hipError_t launch_fill_tau_batched(const BatchItem *items, int n_items, const int *ref_start, int total_refs,
+                                   const double *sigma, const double *mult, hipStream_t st);
+TileGeom plan_filter_tiles(const ImageGeom &g, int W, int K, int lds_budget);
+int filter_lds_bytes_for(const TileGeom &tg, int C, int K);
+int filter_lds_budget();
 
 // ---- learned noise-level network ----
 void cnn_layout(int c, int *w_off, int *b_off, int *total);

@@ -93,13 +93,6 @@ __device__ inline double wave_sum_f64(double v) {
     return v;
 }
 
-// Geometry of the reference tiles and their LDS / global regions.
-struct TileGeom {
-    int TY, TX;          // references per tile
-    int tiles_y, tiles_x;
-    int RH, RW;          // region capacity (rows, cols) per tile
-    int R;               // search radius (W-1)/2
-};
 
 __device__ __host__ inline void region_rows(const ImageGeom &g, const TileGeom &tg, int ty, int *r0, int *r1) {
     const int i0 = ty * tg.TY;
@@ -142,24 +135,24 @@ __device__ inline void load_row(const uint8_t *p, const uint8_t *end, float (&ou
     }
 }
 
+struct FilterShared {
+    int near_k[NWAVE][NEAR_CAP], near_q[NWAVE][NEAR_CAP], near_n[NWAVE];
+    int r0, c0;
+};
+
+// Filters every group of one reference tile and writes the tile's region (sums, counts).
 template <int C, int K>
-__global__ __launch_bounds__(256) void filter_kernel(ImageGeom g, TileGeom tg, const float *__restrict__ B,
-                                                     const double *__restrict__ T64, const int32_t *__restrict__ idx,
-                                                     const double *__restrict__ tau_ref, float *__restrict__ regions,
-                                                     unsigned long long *__restrict__ guard_count) {
+__device__ __forceinline__ void filter_tile(const ImageGeom &g, const TileGeom &tg, const float *__restrict__ B,
+                                            const double *__restrict__ T64, const int32_t *__restrict__ idx,
+                                            const double *__restrict__ tau_ref, float *__restrict__ regions,
+                                            unsigned long long *__restrict__ guard_count, const int tile,
+                                            float *smem, FilterShared &sh) {
     constexpr int P = 64 * C;
     constexpr int CH = C + 1;                     // sums + count per pixel
-    extern __shared__ __align__(16) float smem[];
-    __shared__ int near_k[NWAVE][NEAR_CAP], near_q[NWAVE][NEAR_CAP], near_n[NWAVE];
-    __shared__ int s_r0, s_c0;
-
+    auto &near_k = sh.near_k;
+    auto &near_q = sh.near_q;
+    auto &near_n = sh.near_n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n_tiles = tg.tiles_y * tg.tiles_x;
-    // XCD-aware order: consecutive workgroup ids go round-robin over 8 XCDs; give each XCD a
-    // contiguous run of tiles (grid = 8 * ceil(n_tiles / 8), b -> (b%8)*per + b/8 is a bijection).
-    const int per = (n_tiles + 7) / 8;
-    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (tile >= n_tiles) return;
     const int ty = tile / tg.tiles_x, tx = tile % tg.tiles_x;
 
     float *region = smem;                               // [RH][RW][CH]
@@ -169,12 +162,12 @@ __global__ __launch_bounds__(256) void filter_kernel(ImageGeom g, TileGeom tg, c
         int r0, r1, c0, c1;
         region_rows(g, tg, ty, &r0, &r1);
         region_cols(g, tg, tx, &c0, &c1);
-        s_r0 = r0;
-        s_c0 = c0;
+        sh.r0 = r0;
+        sh.c0 = c0;
     }
     for (int e = tid; e < region_elems; e += 256) region[e] = 0.f;
     __syncthreads();
-    const int r0 = s_r0, c0 = s_c0;
+    const int r0 = sh.r0, c0 = sh.c0;
     const uint8_t *img_end = g.img + (int64_t)(g.h - 1) * g.stride + (int64_t)g.w * C;
 
     const float *U0 = B, *V0 = B + 64, *U1r = B + 128, *U1i = B + 192, *V1r = B + 256, *V1i = B + 320;
@@ -436,13 +429,52 @@ __global__ __launch_bounds__(256) void filter_kernel(ImageGeom g, TileGeom tg, c
     for (int e = tid; e < region_elems; e += 256) dst[e] = region[e];
 }
 
+template <int C, int K>
+__global__ __launch_bounds__(256) void filter_kernel(ImageGeom g, TileGeom tg, const float *__restrict__ B,
+                                                     const double *__restrict__ T64, const int32_t *__restrict__ idx,
+                                                     const double *__restrict__ tau_ref, float *__restrict__ regions,
+                                                     unsigned long long *__restrict__ guard_count) {
+    extern __shared__ __align__(16) float smem[];
+    __shared__ FilterShared sh;
+    const int n_tiles = tg.tiles_y * tg.tiles_x;
+    // XCD-aware order: consecutive workgroup ids go round-robin over 8 XCDs; give each XCD a
+    // contiguous run of tiles (grid = 8 * ceil(n_tiles / 8), b -> (b%8)*per + b/8 is a bijection).
+    const int per = (n_tiles + 7) / 8;
+    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= n_tiles) return;
+    filter_tile<C, K>(g, tg, B, T64, idx, tau_ref, regions, guard_count, tile, smem, sh);
+}
+
+// Persistent form over many images: each workgroup pulls (image, tile) units from a queue.
+template <int C, int K>
+__global__ __launch_bounds__(256) void filter_kernel_batched(const BatchItem *__restrict__ items, int n_items,
+                                                             const int *__restrict__ unit_start,
+                                                             const float *__restrict__ B,
+                                                             const double *__restrict__ T64,
+                                                             unsigned long long *__restrict__ guard_count,
+                                                             int *__restrict__ queue) {
+    extern __shared__ __align__(16) float smem[];
+    __shared__ FilterShared sh;
+    __shared__ int s_u;
+    const int total = unit_start[n_items];
+    for (;;) {
+        if (threadIdx.x == 0) s_u = atomicAdd(queue, 1);
+        __syncthreads();
+        const int u = s_u;
+        __syncthreads();
+        if (u >= total) break;
+        const int i = find_unit(unit_start, n_items, u);
+        const BatchItem it = items[i];
+        filter_tile<C, K>(it.g, it.tg, B, T64, it.idx, it.tau, it.regions, guard_count, u - unit_start[i], smem, sh);
+        __syncthreads();
+    }
+}
+
 // out = (sum of the regions covering the pixel) / (their count); noisy value where no patch landed.
 template <int C>
-__global__ void gather_kernel(ImageGeom g, TileGeom tg, const float *__restrict__ regions, float *__restrict__ out,
-                              int64_t out_stride) {
+__device__ __forceinline__ void gather_px(const ImageGeom &g, const TileGeom &tg, const float *__restrict__ regions,
+                                          float *__restrict__ out, int64_t out_stride, int64_t e) {
     constexpr int CH = C + 1;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)g.h * g.w) return;
     const int y = (int)(e / g.w), x = (int)(e % g.w);
     const int span_y = tg.TY * g.s, span_x = tg.TX * g.s;
     const int ty_lo = max(0, (y - tg.R - PS - span_y) / span_y - 1);
@@ -471,6 +503,25 @@ __global__ void gather_kernel(ImageGeom g, TileGeom tg, const float *__restrict_
     const uint8_t *px = g.img + (int64_t)y * g.stride + (int64_t)x * C;
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) o[ch] = acc[C] > 0.f ? acc[ch] / acc[C] : (float)px[ch];
+}
+
+template <int C>
+__global__ void gather_kernel(ImageGeom g, TileGeom tg, const float *__restrict__ regions, float *__restrict__ out,
+                              int64_t out_stride) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)g.h * g.w) return;
+    gather_px<C>(g, tg, regions, out, out_stride, e);
+}
+
+// All pixels of all images of a batch; pix_start holds the prefix sums of the pixel counts.
+template <int C>
+__global__ void gather_kernel_batched(const BatchItem *__restrict__ items, int n_items,
+                                      const int *__restrict__ pix_start) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= pix_start[n_items]) return;
+    const int i = find_unit(pix_start, n_items, e);
+    const BatchItem &it = items[i];
+    gather_px<C>(it.g, it.tg, it.regions, it.out, it.out_stride, e - pix_start[i]);
 }
 
 // Largest reference tile (<= 16 per side) whose region and group buffers fit in LDS.
@@ -507,7 +558,42 @@ hipError_t launch_filter_t(const ImageGeom &g, const TileGeom &tg, const BasisDe
     return hipGetLastError();
 }
 
+template <int C, int K>
+hipError_t launch_filter_batched_t(const BatchItem *items, int n_items, const int *unit_start, int lds,
+                                   const BasisDev &b, unsigned long long *gc, int *queue, int grid, hipStream_t st) {
+    const int static_lds = (int)sizeof(FilterShared) + 16;
+    hipError_t e = prepare_dynamic_lds((const void *)filter_kernel_batched<C, K>, lds, static_lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((filter_kernel_batched<C, K>), dim3(grid), dim3(256), lds, st, items, n_items, unit_start, b.f32,
+                       b.T64, gc, queue);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int filter_lds_bytes_for(const TileGeom &tg, int C, int K) { return (tg.RH * tg.RW * (C + 1) + NWAVE * K * 64 * C) * 4; }
+
+TileGeom plan_filter_tiles(const ImageGeom &g, int W, int K, int lds_budget) { return plan_tiles(g, W, K, lds_budget); }
+
+hipError_t launch_filter_batched(int C, int K, const BatchItem *items, int n_items, const int *unit_start, int lds,
+                                 const BasisDev &b, unsigned long long *gc, int *queue, int grid, hipStream_t st) {
+#define HFB_CASE(CC, KK) \
+    if (C == CC && K == KK) return launch_filter_batched_t<CC, KK>(items, n_items, unit_start, lds, b, gc, queue, grid, st);
+    HFB_CASE(1, 4) HFB_CASE(1, 8) HFB_CASE(1, 16) HFB_CASE(1, 32)
+    HFB_CASE(3, 4) HFB_CASE(3, 8) HFB_CASE(3, 16) HFB_CASE(3, 32)
+#undef HFB_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_gather_batched(int C, const BatchItem *items, int n_items, const int *pix_start, int total_px,
+                                 hipStream_t st) {
+    const unsigned grid = (unsigned)((total_px + 255) / 256);
+    if (C == 3)
+        hipLaunchKernelGGL(gather_kernel_batched<3>, dim3(grid), dim3(256), 0, st, items, n_items, pix_start);
+    else
+        hipLaunchKernelGGL(gather_kernel_batched<1>, dim3(grid), dim3(256), 0, st, items, n_items, pix_start);
+    return hipGetLastError();
+}
 
 int filter_lds_budget() { return 160 * 1024 - (2 * NWAVE * NEAR_CAP + NWAVE + 2) * 4 - 64; }
 

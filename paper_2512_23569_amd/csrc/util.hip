@@ -75,7 +75,23 @@ __global__ void fill_tau_learned_kernel(double *tau, ImageGeom g, int tile, cons
     tau[r] = s * mult;
 }
 
+// Known noise levels of a batch: tau of every reference of image i = sigma[i] * mult[i].
+__global__ void fill_tau_batched_kernel(const BatchItem *items, int n_items, const int *ref_start,
+                                        const double *sigma, const double *mult) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ref_start[n_items]) return;
+    const int i = find_unit(ref_start, n_items, e);
+    const_cast<double *>(items[i].tau)[e - ref_start[i]] = sigma[i] * mult[i];
+}
+
 }  // namespace
+
+hipError_t launch_fill_tau_batched(const BatchItem *items, int n_items, const int *ref_start, int total_refs,
+                                   const double *sigma, const double *mult, hipStream_t st) {
+    hipLaunchKernelGGL(fill_tau_batched_kernel, dim3((total_refs + 255) / 256), dim3(256), 0, st, items, n_items,
+                       ref_start, sigma, mult);
+    return hipGetLastError();
+}
 
 hipError_t launch_learned_judge(const ImageGeom &g, int tile, const float *zmap, const double *sigma_plain,
                                 double ratio_bound, int32_t *use_plain, double *sigma_tile, hipStream_t st) {
