@@ -120,21 +120,29 @@ typedef struct {
     int32_t h, w, c;
     int64_t in_stride;    /* bytes per row */
     float sigma;          /* > 0: known noise level; HTSVD_SIGMA_AUTO: estimated (p->estimator) */
-    int32_t K;            /* group size for this image (0: p->K); the autotuner picks 16 or 32 */
+    int32_t K;            /* group size for this image: 0 = p->K; HTSVD_K_AUTO = chosen on the device
+                             between 16 and 32 from the image's mean estimated sigma (opts->k_sigma_cutoff) */
     float *d_out;         /* device, float32 HWC */
     int64_t out_stride;   /* elements per row */
 } htsvd_image;
 
+#define HTSVD_K_AUTO (-1)
+
 typedef struct {
     int32_t use_graph;      /* 1: capture the launches in a hipGraph; an identical batch replays it */
     int32_t blocks_per_cu;  /* persistent workgroups per compute unit for the work-queue kernels (0 = 1) */
+    float k_sigma_cutoff;   /* HTSVD_K_AUTO images whose mean sigma is below this use K = 16, else 32 */
+    int32_t tile_side;      /* largest side of a filter reference tile, 0..16 (0 = 16); LDS may cap it lower */
 } htsvd_batch_opts;
 
 /* Denoises n images of any sizes (one channel count) with shared method parameters.  Block
  * matching, filtering and aggregation run as persistent kernels that pull (image, tile) units
  * from work queues, so one launch covers the whole batch; with use_graph the whole sequence is
  * captured once in a hipGraph and replayed while the batch (pointers, shapes, sigma, K) and
- * the parameters stay the same.  opts may be NULL (defaults: graph on, 1 block per CU). */
+ * the parameters stay the same.  An HTSVD_K_AUTO image is matched with 32 members; after its
+ * noise level is known a device kernel keeps 32 or the first 16 members (the 16 nearest under
+ * the same order), so the choice needs no host round trip and stays inside the graph.
+ * opts may be NULL (defaults: graph on, 1 block per CU, cutoff 0 = always 32, tile side 16). */
 htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, const htsvd_params *p,
                                  const htsvd_batch_opts *opts, void *stream);
 

@@ -18,6 +18,7 @@ DATA_DIR = os.path.join(_HERE, "data")
 
 HTSVD_OK, HTSVD_EINVAL, HTSVD_ESHAPE, HTSVD_ENOMEM, HTSVD_EDEVICE, HTSVD_ENOTSUP, HTSVD_ESTATE = 0, -1, -2, -3, -4, -5, -6
 HTSVD_SIGMA_AUTO = -1.0
+HTSVD_K_AUTO = -1
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EDEVICE", -5: "ENOTSUP", -6: "ESTATE"}
 
 
@@ -50,7 +51,8 @@ class htsvd_image(ctypes.Structure):
 
 
 class htsvd_batch_opts(ctypes.Structure):
-    _fields_ = [("use_graph", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+    _fields_ = [("use_graph", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("k_sigma_cutoff", ctypes.c_float), ("tile_side", ctypes.c_int32)]
 
 
 class HtsvdError(RuntimeError):
@@ -201,10 +203,11 @@ def htsvd_denoise_tau(ctx, d_in, h, w, c, in_stride, d_tau_ref, params, d_out, o
                                    _dptr(d_out, torch.float32, "d_out"), out_stride, _stream(stream)))
 
 
-def htsvd_denoise_batch(ctx, images, params, use_graph=1, blocks_per_cu=1, stream=None):
+def htsvd_denoise_batch(ctx, images, params, use_graph=1, blocks_per_cu=1, k_sigma_cutoff=0.0, tile_side=0,
+                        stream=None):
     """images: a sequence of htsvd_image (device pointers filled in by the caller)."""
     arr = (htsvd_image * len(images))(*images)
-    opts = htsvd_batch_opts(int(use_graph), int(blocks_per_cu))
+    opts = htsvd_batch_opts(int(use_graph), int(blocks_per_cu), float(k_sigma_cutoff), int(tile_side))
     _check(lib().htsvd_denoise_batch(ctx, len(images), arr, ctypes.byref(params), ctypes.byref(opts),
                                      _stream(stream)))
 
@@ -358,9 +361,10 @@ class Denoiser:
         return out
 
     def denoise_batch(self, imgs, sigmas, params, Ks=None, outs=None, use_graph=True, blocks_per_cu=1,
-                      stream=None):
+                      k_sigma_cutoff=0.0, tile_side=0, stream=None):
         """Denoises a list of uint8 device images in one batched call; sigma HTSVD_SIGMA_AUTO
-        (-1) estimates the level.  Returns the list of float32 outputs."""
+        (-1) estimates the level, K HTSVD_K_AUTO (-1) picks 16 or 32 on the device.  Returns the
+        list of float32 outputs."""
         import torch
         if outs is None:
             outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in imgs]
@@ -371,7 +375,7 @@ class Denoiser:
             _dptr(outs[i], torch.float32, "output")
             descs.append(htsvd_image(x.data_ptr(), h, w, c, st, float(sigmas[i]), int(Ks[i]) if Ks else 0,
                                      outs[i].data_ptr(), outs[i].stride(0)))
-        htsvd_denoise_batch(self.ctx, descs, params, use_graph, blocks_per_cu, stream)
+        htsvd_denoise_batch(self.ctx, descs, params, use_graph, blocks_per_cu, k_sigma_cutoff, tile_side, stream)
         return outs
 
     def guard_count(self):

@@ -843,7 +843,8 @@ struct BatchImage {
     int src;                 // index in the caller's array
     ImageGeom g;
     MethodParams mp;
-    TileGeom tg;
+    TileGeom tg, tg_alt;        // tiling for mp.K, and for K = 16 (auto images)
+    bool auto_k;
     int bm_tiles_x, bm_tiles;
     int64_t n_ref, n_tiles_sigma;
     size_t off_idx, off_tau, off_reg, off_sig;   // byte offsets in the workspace
@@ -861,14 +862,17 @@ struct BatchPlan {
     bool any_auto = false;
 };
 
-htsvd_status plan_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, const htsvd_params *p, BatchPlan *bp) {
+htsvd_status plan_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, const htsvd_params *p, int tile_side,
+                        BatchPlan *bp) {
     BatchPlan &P = *bp;
     const int T = p->subimage;
     for (int i = 0; i < n; ++i) {
         const htsvd_image &x = imgs[i];
         htsvd_params pi = *p;
-        if (x.K) pi.K = x.K;
         BatchImage b;
+        b.auto_k = x.K == HTSVD_K_AUTO;
+        if (b.auto_k) pi.K = 32;
+        else if (x.K) pi.K = x.K;
         htsvd_status s = validate(ctx, x.d_in, x.h, x.w, x.c, x.in_stride, &pi, &b.g, &b.mp, true);
         if (s != HTSVD_OK) return fail(s, std::string("image ") + std::to_string(i) + ": " + htsvd_last_error());
         if (!x.d_out || x.out_stride < (int64_t)x.w * x.c) return fail(HTSVD_EINVAL, "bad output of image " + std::to_string(i));
@@ -880,7 +884,8 @@ htsvd_status plan_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, cons
         b.out_stride = x.out_stride;
         b.bm_tiles_x = (b.g.nx + REF_TILE - 1) / REF_TILE;
         b.bm_tiles = ((b.g.ny + REF_TILE - 1) / REF_TILE) * b.bm_tiles_x;
-        b.tg = plan_filter_tiles(b.g, b.mp.W, b.mp.K, filter_lds_budget());
+        b.tg = plan_filter_tiles(b.g, b.mp.W, b.mp.K, tile_side);
+        b.tg_alt = plan_filter_tiles(b.g, b.mp.W, 16, tile_side);
         b.n_ref = (int64_t)b.g.ny * b.g.nx;
         b.n_tiles_sigma = (int64_t)((b.g.h + T - 1) / T) * ((b.g.w + T - 1) / T);
         P.any_auto |= (x.sigma == HTSVD_SIGMA_AUTO) || p->adaptive;
@@ -895,7 +900,11 @@ htsvd_status plan_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, cons
         b.off_idx = off; off = align256(off + sizeof(int32_t) * b.n_ref * b.mp.K);
         b.off_tau = off; off = align256(off + sizeof(double) * b.n_ref);
         b.off_reg = off;
-        off = align256(off + (size_t)b.tg.tiles_y * b.tg.tiles_x * b.tg.RH * b.tg.RW * (b.g.c + 1) * sizeof(float));
+        size_t reg = (size_t)b.tg.tiles_y * b.tg.tiles_x * b.tg.RH * b.tg.RW * (b.g.c + 1) * sizeof(float);
+        if (b.auto_k)
+            reg = std::max(reg, (size_t)b.tg_alt.tiles_y * b.tg_alt.tiles_x * b.tg_alt.RH * b.tg_alt.RW *
+                                    (b.g.c + 1) * sizeof(float));
+        off = align256(off + reg);
         b.off_sig = off;  // sig_est, sig_hat, votes, cov (c per tile), use_plain, sig_plain
         off = align256(off + b.n_tiles_sigma * (sizeof(double) * (3 + b.g.c) + 2 * sizeof(int32_t)));
         P.max_s = std::max(P.max_s, b.g.s);
@@ -903,6 +912,7 @@ htsvd_status plan_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, cons
         P.max_h = std::max(P.max_h, b.g.h);
         P.max_w = std::max(P.max_w, b.g.w);
         if (std::find(P.classes.begin(), P.classes.end(), b.mp.K) == P.classes.end()) P.classes.push_back(b.mp.K);
+        if (b.auto_k && std::find(P.classes.begin(), P.classes.end(), 16) == P.classes.end()) P.classes.push_back(16);
     }
     int64_t px = 0, refs = 0, bm = 0;
     for (const BatchImage &b : P.im) {
@@ -942,14 +952,34 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
                                  const htsvd_batch_opts *opts, void *stream) {
     if (!ctx || !imgs || !p) return fail(HTSVD_EINVAL, "null argument");
     if (n < 1) return fail(HTSVD_EINVAL, "empty batch");
-    htsvd_batch_opts o = {1, 1};
+    htsvd_batch_opts o = {1, 1, 0.f, 0};
     if (opts) o = *opts;
     if (o.blocks_per_cu < 1) o.blocks_per_cu = 1;
     if (o.blocks_per_cu > 8) return fail(HTSVD_EINVAL, "blocks_per_cu must be in [1, 8]");
+    if (!(o.k_sigma_cutoff >= 0.f)) return fail(HTSVD_EINVAL, "k_sigma_cutoff must be >= 0");
+    if (o.tile_side < 0 || o.tile_side > 16) return fail(HTSVD_EINVAL, "tile_side must be in [0, 16]");
     hipStream_t st = (hipStream_t)stream;
 
-    uint64_t sig = fnv1a(0xcbf29ce484222325ull, imgs, sizeof(htsvd_image) * n);
-    sig = fnv1a(sig, p, sizeof(*p));
+    // signature of the batch, field by field (struct padding is not hashed)
+    uint64_t sig = 0xcbf29ce484222325ull;
+    for (int i = 0; i < n; ++i) {
+        const htsvd_image &x = imgs[i];
+        sig = fnv1a(sig, &x.d_in, sizeof(x.d_in));
+        sig = fnv1a(sig, &x.h, sizeof(x.h));
+        sig = fnv1a(sig, &x.w, sizeof(x.w));
+        sig = fnv1a(sig, &x.c, sizeof(x.c));
+        sig = fnv1a(sig, &x.in_stride, sizeof(x.in_stride));
+        sig = fnv1a(sig, &x.sigma, sizeof(x.sigma));
+        sig = fnv1a(sig, &x.K, sizeof(x.K));
+        sig = fnv1a(sig, &x.d_out, sizeof(x.d_out));
+        sig = fnv1a(sig, &x.out_stride, sizeof(x.out_stride));
+    }
+    const int32_t pi32[] = {p->ps, p->stride, p->window, p->K, p->adaptive, p->gamma_rank, p->gcp_num,
+                            p->gcp_den, p->estimator, p->subimage, p->n_vote};
+    sig = fnv1a(sig, pi32, sizeof(pi32));
+    sig = fnv1a(sig, &p->tau_mult, sizeof(p->tau_mult));
+    sig = fnv1a(sig, &p->beta, sizeof(p->beta));
+    sig = fnv1a(sig, &p->vote_seed, sizeof(p->vote_seed));
     sig = fnv1a(sig, &o, sizeof(o));
     sig = fnv1a(sig, &ctx->cnn.w, sizeof(ctx->cnn.w));
     sig = fnv1a(sig, &ctx->cnn.c, sizeof(ctx->cnn.c));
@@ -960,7 +990,7 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
     }
 
     BatchPlan P;
-    htsvd_status s = plan_batch(ctx, n, imgs, p, &P);
+    htsvd_status s = plan_batch(ctx, n, imgs, p, o.tile_side, &P);
     if (s != HTSVD_OK) return s;
     const int ni = (int)P.im.size();
     const int C = P.im[0].g.c;
@@ -978,6 +1008,7 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
     std::vector<BatchItem> items(ni);
     std::vector<int> bm_start(ni + 1, 0), ref_start(ni + 1, 0), pix_start(ni + 1, 0);
     std::vector<double> sigma_h(ni), mult_h(ni);
+    std::vector<int> ksel_h(ni), auto_list;
     for (int i = 0; i < ni; ++i) {
         const BatchImage &b = P.im[i];
         Ws w = image_ws(ctx->ws, b);
@@ -991,30 +1022,47 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
         it.regions = w.regions;
         it.out = b.out;
         it.out_stride = b.out_stride;
+        it.idx_stride = b.mp.K;
+        it.tau_mul = 1.0;
+        it.ksel = nullptr;       // set to the device table below for auto images
+        it.k_alt = 16;
+        it.tg_alt = b.tg_alt;
+        ksel_h[i] = b.mp.K;
+        if (b.auto_k) auto_list.push_back(i);
         bm_start[i + 1] = bm_start[i] + b.bm_tiles;
         ref_start[i + 1] = ref_start[i] + (int)b.n_ref;
         pix_start[i + 1] = pix_start[i] + b.g.h * b.g.w;
         sigma_h[i] = b.sigma > 0.f ? (double)b.sigma : 0.0;
         mult_h[i] = p->tau_mult > 0.0 ? p->tau_mult : default_mult(C, b.mp.K);
     }
-    // per-class (K) filter tables: items of the class and their tile prefix sums
-    std::vector<std::vector<BatchItem>> cls_items(P.classes.size());
-    std::vector<std::vector<int>> cls_start(P.classes.size());
-    std::vector<int> cls_lds(P.classes.size(), 0);
-    for (size_t k = 0; k < P.classes.size(); ++k) {
-        cls_start[k].push_back(0);
-        for (int i = 0; i < ni; ++i)
-            if (items[i].mp.K == P.classes[k]) {
-                cls_items[k].push_back(items[i]);
-                const TileGeom &tg = items[i].tg;
-                cls_start[k].push_back(cls_start[k].back() + tg.tiles_y * tg.tiles_x);
-                cls_lds[k] = std::max(cls_lds[k], filter_lds_bytes_for(tg, C, P.classes[k]));
-            }
-    }
-    // device layout: items | class items... | bm_start | ref_start | pix_start | class starts... | sigma | mult | queues
+    // device layout: items | class items... | bm_start | ref_start | pix_start | class starts... | sigma | mult |
+    // ksel | auto list | queues
     size_t off = 0;
     auto reserve = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     const size_t o_items = reserve(sizeof(BatchItem) * ni);
+    const size_t o_ksel = reserve(sizeof(int) * ni), o_auto = reserve(sizeof(int) * std::max<size_t>(1, auto_list.size()));
+    // per-class (K) filter tables: items of the class and their tile prefix sums.  An auto image
+    // appears in the class 32 list and, with its K = 16 tiling and threshold factor, in class 16.
+    std::vector<std::vector<BatchItem>> cls_items(P.classes.size());
+    std::vector<std::vector<int>> cls_start(P.classes.size()), cls_src(P.classes.size());
+    std::vector<int> cls_lds(P.classes.size(), 0);
+    for (size_t k = 0; k < P.classes.size(); ++k) {
+        const int K = P.classes[k];
+        cls_start[k].push_back(0);
+        for (int i = 0; i < ni; ++i) {
+            BatchItem it = items[i];
+            if (it.mp.K != K) {
+                if (!(P.im[i].auto_k && K == 16)) continue;
+                it.mp.K = 16;
+                it.tg = P.im[i].tg_alt;
+                it.tau_mul = p->tau_mult > 0.0 ? 1.0 : default_mult(C, 16) / default_mult(C, 32);
+            }
+            cls_items[k].push_back(it);
+            cls_src[k].push_back(i);
+            cls_start[k].push_back(cls_start[k].back() + it.tg.tiles_y * it.tg.tiles_x);
+            cls_lds[k] = std::max(cls_lds[k], filter_lds_bytes_for(it.tg, C, K));
+        }
+    }
     std::vector<size_t> o_citems(P.classes.size()), o_cstart(P.classes.size());
     for (size_t k = 0; k < P.classes.size(); ++k) o_citems[k] = reserve(sizeof(BatchItem) * cls_items[k].size());
     const size_t o_bm = reserve(sizeof(int) * (ni + 1)), o_ref = reserve(sizeof(int) * (ni + 1)),
@@ -1022,17 +1070,6 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
     for (size_t k = 0; k < P.classes.size(); ++k) o_cstart[k] = reserve(sizeof(int) * cls_start[k].size());
     const size_t o_sig = reserve(sizeof(double) * ni), o_mult = reserve(sizeof(double) * ni);
     const size_t o_q = reserve(sizeof(int) * (1 + P.classes.size()));
-    std::vector<unsigned char> host(off, 0);
-    memcpy(host.data() + o_items, items.data(), sizeof(BatchItem) * ni);
-    for (size_t k = 0; k < P.classes.size(); ++k) {
-        memcpy(host.data() + o_citems[k], cls_items[k].data(), sizeof(BatchItem) * cls_items[k].size());
-        memcpy(host.data() + o_cstart[k], cls_start[k].data(), sizeof(int) * cls_start[k].size());
-    }
-    memcpy(host.data() + o_bm, bm_start.data(), sizeof(int) * (ni + 1));
-    memcpy(host.data() + o_ref, ref_start.data(), sizeof(int) * (ni + 1));
-    memcpy(host.data() + o_pix, pix_start.data(), sizeof(int) * (ni + 1));
-    memcpy(host.data() + o_sig, sigma_h.data(), sizeof(double) * ni);
-    memcpy(host.data() + o_mult, mult_h.data(), sizeof(double) * ni);
     hipError_t e;
     BatchCache &bc = ctx->batch;
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronise before batch planning");
@@ -1049,6 +1086,26 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
         }
         bc.dev_size = off;
     }
+    // device table of the chosen group sizes, referenced by the descriptors of auto images
+    const int *d_ksel = (const int *)((char *)bc.dev + o_ksel);
+    for (int i = 0; i < ni; ++i)
+        if (P.im[i].auto_k) items[i].ksel = d_ksel + i;
+    for (size_t k = 0; k < P.classes.size(); ++k)
+        for (size_t j = 0; j < cls_items[k].size(); ++j)
+            if (P.im[cls_src[k][j]].auto_k) cls_items[k][j].ksel = d_ksel + cls_src[k][j];
+    std::vector<unsigned char> host(off, 0);
+    memcpy(host.data() + o_items, items.data(), sizeof(BatchItem) * ni);
+    for (size_t k = 0; k < P.classes.size(); ++k) {
+        memcpy(host.data() + o_citems[k], cls_items[k].data(), sizeof(BatchItem) * cls_items[k].size());
+        memcpy(host.data() + o_cstart[k], cls_start[k].data(), sizeof(int) * cls_start[k].size());
+    }
+    memcpy(host.data() + o_bm, bm_start.data(), sizeof(int) * (ni + 1));
+    memcpy(host.data() + o_ref, ref_start.data(), sizeof(int) * (ni + 1));
+    memcpy(host.data() + o_pix, pix_start.data(), sizeof(int) * (ni + 1));
+    memcpy(host.data() + o_sig, sigma_h.data(), sizeof(double) * ni);
+    memcpy(host.data() + o_mult, mult_h.data(), sizeof(double) * ni);
+    memcpy(host.data() + o_ksel, ksel_h.data(), sizeof(int) * ni);
+    if (!auto_list.empty()) memcpy(host.data() + o_auto, auto_list.data(), sizeof(int) * auto_list.size());
     if ((e = hipMemcpy(bc.dev, host.data(), off, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "batch descriptor upload");
     char *D = (char *)bc.dev;
@@ -1101,6 +1158,9 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
                 e2 = launch_fill_tau(w.tau, b.n_ref, w.sig_hat, 0.0, mult_h[i], b.g, pi.subimage, ls);
             if (e2 != hipSuccess) return hip_fail(e2, "tau");
         }
+        if ((e2 = launch_select_k(d_items, (const int *)(D + o_auto), (int)auto_list.size(), (const double *)(D + o_mult),
+                                  (double)o.k_sigma_cutoff, (int *)(D + o_ksel), ls)) != hipSuccess)
+            return hip_fail(e2, "group size selection");
         for (size_t k = 0; k < P.classes.size(); ++k) {
             const int units = cls_start[k].back();
             if ((e2 = launch_filter_batched(C, P.classes[k], (const BatchItem *)(D + o_citems[k]), (int)cls_items[k].size(),

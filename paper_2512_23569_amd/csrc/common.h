@@ -52,11 +52,16 @@ struct BatchItem {
     MethodParams mp;
     TileGeom tg;
     int bm_tiles_x;
-    int32_t *idx;          // groups, n_ref * K
+    int32_t *idx;          // groups, n_ref * idx_stride (the first mp.K of each row are used)
     const double *tau;     // thresholds, n_ref
     float *regions;        // per-tile regions of the filter
     float *out;            // output image
     int64_t out_stride;
+    int idx_stride;        // members stored per reference (>= mp.K)
+    double tau_mul;        // factor applied to tau (threshold multiplier of this K over the stored one)
+    const int *ksel;       // device: this image's entry of the chosen group sizes (nullptr: fixed mp.K)
+    int k_alt;             // the other group size the image may take, and its tiling
+    TileGeom tg_alt;
 };
 
 // Index i of the unit range [start[i], start[i+1]) holding u (start has n+1 entries).
@@ -106,9 +111,13 @@ hipError_t launch_filter_batched(int C, int K, const BatchItem *items, int n_ite
                                  const BasisDev &b, unsigned long long *gc, int *queue, int grid, hipStream_t st);
 hipError_t launch_gather_batched(int C, const BatchItem *items, int n_items, const int *pix_start, int total_px,
                                  hipStream_t st);
+hipError_t launch_select_k(const BatchItem *items, const int *auto_list, int n_auto, const double *mult,
+                           double cutoff, int *ksel, hipStream_t st);
 hipError_t launch_fill_tau_batched(const BatchItem *items, int n_items, const int *ref_start, int total_refs,
                                    const double *sigma, const double *mult, hipStream_t st);
-TileGeom plan_filter_tiles(const ImageGeom &g, int W, int K, int lds_budget);
+// Reference tiling of the filter: the largest square tile (side <= max_side, 0 = 16) whose
+// region and group buffers fit in LDS.
+TileGeom plan_filter_tiles(const ImageGeom &g, int W, int K, int max_side);
 int filter_lds_bytes_for(const TileGeom &tg, int C, int K);
 int filter_lds_budget();
 

@@ -146,7 +146,8 @@ __device__ __forceinline__ void filter_tile(const ImageGeom &g, const TileGeom &
                                             const double *__restrict__ T64, const int32_t *__restrict__ idx,
                                             const double *__restrict__ tau_ref, float *__restrict__ regions,
                                             unsigned long long *__restrict__ guard_count, const int tile,
-                                            float *smem, FilterShared &sh) {
+                                            float *smem, FilterShared &sh, const int idx_stride,
+                                            const double tau_mul) {
     constexpr int P = 64 * C;
     constexpr int CH = C + 1;                     // sums + count per pixel
     auto &near_k = sh.near_k;
@@ -177,7 +178,7 @@ __device__ __forceinline__ void filter_tile(const ImageGeom &g, const TileGeom &
     const int ny_t = min(tg.TY, g.ny - iy0), nx_t = min(tg.TX, g.nx - ix0);
     for (int t = wave; t < ny_t * nx_t; t += NWAVE) {
         const int64_t r = (int64_t)(iy0 + t / nx_t) * g.nx + (ix0 + t % nx_t);
-        const double tau = tau_ref[r];
+        const double tau = tau_ref[r] * tau_mul;
         const float tauf = (float)tau;
         const bool guard_on = tau > (double)GUARD_F;
         if (lane == 0) near_n[wave] = 0;
@@ -187,7 +188,7 @@ __device__ __forceinline__ void filter_tile(const ImageGeom &g, const TileGeom &
 #pragma unroll 1
         for (int task = lane; task < 8 * K; task += 64) {
             const int m = task >> 3, a = task & 7;
-            const int32_t lin = idx[r * K + m];
+            const int32_t lin = idx[r * idx_stride + m];
             const int ym = lin / g.w, xm = lin % g.w;
             float px[8 * C];
             load_row<C>(g.img + (int64_t)(ym + a) * g.stride + (int64_t)xm * C, img_end, px);
@@ -315,7 +316,7 @@ __device__ __forceinline__ void filter_tile(const ImageGeom &g, const TileGeom &
                     for (int mm = 0; mm < K; ++mm) {
                         const double w = haar_weight(k, mm, K);
                         if (w == 0.0) continue;
-                        const int32_t l2 = idx[r * K + mm];
+                        const int32_t l2 = idx[r * idx_stride + mm];
                         const int y2 = l2 / g.w, x2 = l2 % g.w;
                         acc += w * (double)g.img[(int64_t)(y2 + i) * g.stride + (int64_t)(x2 + j) * C + ch];
                     }
@@ -392,7 +393,7 @@ __device__ __forceinline__ void filter_tile(const ImageGeom &g, const TileGeom &
             for (int task = sub; task < 8 * K; task += 8) {
                 const int m = task >> 3, a = task & 7;
                 const float *row = buf + m * P + a * 8;
-                const int32_t lin = idx[r * K + m];
+                const int32_t lin = idx[r * idx_stride + m];
                 const int ym = lin / g.w, xm = lin % g.w;
                 float *dst = region + ((ym + a - r0) * tg.RW + (xm + l8 - c0)) * CH;
                 float y0[8];
@@ -442,7 +443,7 @@ __global__ __launch_bounds__(256) void filter_kernel(ImageGeom g, TileGeom tg, c
     const int per = (n_tiles + 7) / 8;
     const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (tile >= n_tiles) return;
-    filter_tile<C, K>(g, tg, B, T64, idx, tau_ref, regions, guard_count, tile, smem, sh);
+    filter_tile<C, K>(g, tg, B, T64, idx, tau_ref, regions, guard_count, tile, smem, sh, K, 1.0);
 }
 
 // Persistent form over many images: each workgroup pulls (image, tile) units from a queue.
@@ -465,7 +466,9 @@ __global__ __launch_bounds__(256) void filter_kernel_batched(const BatchItem *__
         if (u >= total) break;
         const int i = find_unit(unit_start, n_items, u);
         const BatchItem it = items[i];
-        filter_tile<C, K>(it.g, it.tg, B, T64, it.idx, it.tau, it.regions, guard_count, u - unit_start[i], smem, sh);
+        if (it.ksel && *it.ksel != K) continue;   // the image took the other group size (uniform per block)
+        filter_tile<C, K>(it.g, it.tg, B, T64, it.idx, it.tau, it.regions, guard_count, u - unit_start[i], smem, sh,
+                          it.idx_stride, it.tau_mul);
         __syncthreads();
     }
 }
@@ -521,16 +524,17 @@ __global__ void gather_kernel_batched(const BatchItem *__restrict__ items, int n
     if (e >= pix_start[n_items]) return;
     const int i = find_unit(pix_start, n_items, e);
     const BatchItem &it = items[i];
-    gather_px<C>(it.g, it.tg, it.regions, it.out, it.out_stride, e - pix_start[i]);
+    const bool alt = it.ksel && *it.ksel == it.k_alt;
+    gather_px<C>(it.g, alt ? it.tg_alt : it.tg, it.regions, it.out, it.out_stride, e - pix_start[i]);
 }
 
 // Largest reference tile (<= 16 per side) whose region and group buffers fit in LDS.
-TileGeom plan_tiles(const ImageGeom &g, int W, int K, int lds_budget) {
+TileGeom plan_tiles(const ImageGeom &g, int W, int K, int lds_budget, int max_side = 16) {
     TileGeom tg;
     tg.R = (W - 1) / 2;
     const int CH = g.c + 1;
     const int group_bytes = NWAVE * K * 64 * g.c * 4;
-    int T = 16;
+    int T = max(1, min(16, max_side));
     for (; T > 1; --T) {
         const int RH = min((T - 1) * g.s + 2 * tg.R + PS, g.h);
         const int RW = min((T - 1) * g.s + 2 * tg.R + PS, g.w);
@@ -573,7 +577,9 @@ hipError_t launch_filter_batched_t(const BatchItem *items, int n_items, const in
 
 int filter_lds_bytes_for(const TileGeom &tg, int C, int K) { return (tg.RH * tg.RW * (C + 1) + NWAVE * K * 64 * C) * 4; }
 
-TileGeom plan_filter_tiles(const ImageGeom &g, int W, int K, int lds_budget) { return plan_tiles(g, W, K, lds_budget); }
+TileGeom plan_filter_tiles(const ImageGeom &g, int W, int K, int max_side) {
+    return plan_tiles(g, W, K, filter_lds_budget(), max_side > 0 ? max_side : 16);
+}
 
 hipError_t launch_filter_batched(int C, int K, const BatchItem *items, int n_items, const int *unit_start, int lds,
                                  const BasisDev &b, unsigned long long *gc, int *queue, int grid, hipStream_t st) {

@@ -84,7 +84,37 @@ __global__ void fill_tau_batched_kernel(const BatchItem *items, int n_items, con
     const_cast<double *>(items[i].tau)[e - ref_start[i]] = sigma[i] * mult[i];
 }
 
+// Group size of each image in auto mode: the mean threshold over its references, divided by
+// the multiplier it was filled with, is the image's mean noise level; below the cutoff the
+// image is filtered with 16-member groups (the first half of its 32-member groups), else 32.
+// One block per image; a fixed-order tree keeps the decision deterministic.
+__global__ __launch_bounds__(256) void select_k_kernel(const BatchItem *__restrict__ items,
+                                                       const int *__restrict__ auto_list,
+                                                       const double *__restrict__ mult, double cutoff,
+                                                       int *__restrict__ ksel) {
+    __shared__ double part[256];
+    const int i = auto_list[blockIdx.x];
+    const BatchItem &it = items[i];
+    const int64_t n = (int64_t)it.g.ny * it.g.nx;
+    double acc = 0.0;
+    for (int64_t e = threadIdx.x; e < n; e += 256) acc += it.tau[e];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ksel[i] = (part[0] / (double)n) / mult[i] < cutoff ? 16 : 32;
+}
+
 }  // namespace
+
+hipError_t launch_select_k(const BatchItem *items, const int *auto_list, int n_auto, const double *mult,
+                           double cutoff, int *ksel, hipStream_t st) {
+    if (n_auto <= 0) return hipSuccess;
+    hipLaunchKernelGGL(select_k_kernel, dim3(n_auto), dim3(256), 0, st, items, auto_list, mult, cutoff, ksel);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_tau_batched(const BatchItem *items, int n_items, const int *ref_start, int total_refs,
                                    const double *sigma, const double *mult, hipStream_t st) {

@@ -121,3 +121,36 @@ def test_batch_errors(dn):
     with pytest.raises(ht.HtsvdError) as e:
         dn.denoise_batch([a], [0.0], dn.params(3))
     assert e.value.status == ht.HTSVD_EINVAL
+
+
+def test_auto_group_size_follows_the_sigma_cutoff(dn):
+    """HTSVD_K_AUTO: images whose mean noise level is below the cutoff are filtered with the first
+    16 members of their 32-member groups, the others with 32; each output equals the one-image
+    call with that K (known sigma, and the plain estimate without the vote)."""
+    import paper_2512_23569_amd as ht
+    cl, nz, sig = _mixed_batch(3, 21)
+    ins = [_dev(x) for x in nz]
+    cutoff = 20.0   # 5 units from the nearest level of the batch (15 and 25)
+    for adaptive_sigma in (False, True):
+        sigmas = [-1.0] * len(ins) if adaptive_sigma else sig
+        p = dn.params(3, stride=4, window=21, adaptive=0, estimator=0)
+        outs = dn.denoise_batch(ins, sigmas, p, Ks=[ht.HTSVD_K_AUTO] * len(ins), k_sigma_cutoff=cutoff)
+        for i, x in enumerate(ins):
+            K = 16 if sig[i] < cutoff else 32
+            one = dn.denoise(x, sigmas[i], p.replace(K=K))
+            assert torch.max(torch.abs(outs[i] - one)).item() <= RUN_TOL, (adaptive_sigma, i, sig[i])
+
+
+def test_auto_group_size_in_graph_replays(dn):
+    import paper_2512_23569_amd as ht
+    cl, nz, sig = _mixed_batch(3, 31)
+    ins = [_dev(x) for x in nz]
+    p = dn.params(3, stride=3, window=15, adaptive=1, estimator=1)
+    Ks = [ht.HTSVD_K_AUTO, 32, ht.HTSVD_K_AUTO, 16, ht.HTSVD_K_AUTO, ht.HTSVD_K_AUTO]
+    eager = [o.clone() for o in dn.denoise_batch(ins, [-1.0] * 6, p, Ks=Ks, use_graph=False, k_sigma_cutoff=30.0)]
+    for rep in range(3):
+        outs = dn.denoise_batch(ins, [-1.0] * 6, p, Ks=Ks, use_graph=True, k_sigma_cutoff=30.0,
+                                tile_side=4)
+        torch.cuda.synchronize()
+        for e, o in zip(eager, outs):
+            assert torch.max(torch.abs(e - o)).item() <= RUN_TOL, rep
