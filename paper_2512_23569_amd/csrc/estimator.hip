@@ -30,12 +30,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int COV_MAX_SIDE = 128 + PS - 1;   // staged pixels per side for a 128 sub-image
 constexpr int COV_PITCH = 140;                 // bytes per staged row (>= 135 + 4, multiple of 4)
-
-struct CovLds {
-    int tile;   // sub-image side
-};
 
 __device__ inline void tile_bounds(const ImageGeom &g, int T, int t, int *y0, int *y1, int *x0, int *x1) {
     const int ntx = (g.w + T - 1) / T;
@@ -63,35 +58,42 @@ __device__ inline v4i frag16(const unsigned char *lds, int plane, int r, int col
     return f;
 }
 
+// Sum over the 64 lanes of a wavefront (every lane gets the total).
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// LDS layout of cov_eig_kernel (bytes)
+constexpr int COV_BAND = 16;                               // patch rows per staged band
+constexpr int COV_STAGE_ROWS = COV_BAND + PS - 1;          // 23 pixel rows per band
+constexpr int COV_PLANE = COV_STAGE_ROWS * COV_PITCH;      // one byte-shifted copy
+constexpr int COV_OFF_S2 = 0;                              // int32 [64][64] second moments
+constexpr int COV_OFF_S1 = COV_OFF_S2 + 64 * 64 * 4;       // int32 [64] first moments
+constexpr int COV_OFF_STAGE = COV_OFF_S1 + 64 * 4;         // 4 copies of the band
+constexpr int COV_OFF_VEC = COV_OFF_STAGE + 4 * COV_PLANE; // double [3][64] (v, w / d, e2, eigenvalues)
+constexpr int COV_LDS = COV_OFF_VEC + 3 * 64 * 8;
+
+// One workgroup per (sub-image, channel).  Phase 1 (4 waves): exact integer second moments of
+// the shifted patches on the matrix cores, the sub-image staged band by band.  Phase 2 (wave
+// 0): covariance rows in registers (lane i holds row i), Householder reduction to tridiagonal
+// form, eigenvalues by Sturm-count bisection (lane i finds the i-th smallest), tail rule.
 __global__ __launch_bounds__(256) void cov_eig_kernel(ImageGeom g, int T, double *__restrict__ sigma2) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_y0, s_y1, s_x0, s_x1;
-    __shared__ int s_stop;
+    int32_t *S2 = reinterpret_cast<int32_t *>(smem + COV_OFF_S2);
+    int32_t *S1 = reinterpret_cast<int32_t *>(smem + COV_OFF_S1);
+    unsigned char *stage = smem + COV_OFF_STAGE;
+    double *vec = reinterpret_cast<double *>(smem + COV_OFF_VEC);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int t = blockIdx.x / g.c, ch = blockIdx.x % g.c;
-    if (tid == 0) {
-        int y0, y1, x0, x1;
-        tile_bounds(g, T, t, &y0, &y1, &x0, &x1);
-        s_y0 = y0; s_y1 = y1; s_x0 = x0; s_x1 = x1;
-    }
-    __syncthreads();
-    const int y0 = s_y0, y1 = s_y1, x0 = s_x0, x1 = s_x1;
+    int y0, y1, x0, x1;
+    tile_bounds(g, T, t, &y0, &y1, &x0, &x1);
     const int ny = y1 - y0 + 1, nx = x1 - x0 + 1;   // patch positions
-    const int prow = ny + PS - 1, pcol = nx + PS - 1;
-    const int plane = COV_MAX_SIDE * COV_PITCH;
+    const int pcol = nx + PS - 1;
+    for (int e = tid; e < 64 * 64 + 64; e += 256) S2[e] = 0;   // S1 follows S2
 
-    // stage x - 128 of this channel in 4 byte-shifted copies
-    for (int e = tid; e < prow * pcol; e += 256) {
-        const int r = e / pcol, col = e % pcol;
-        const int v = (int)g.img[(int64_t)(y0 + r) * g.stride + (int64_t)(x0 + col) * g.c + ch] - 128;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (col >= k) smem[k * plane + r * COV_PITCH + col - k] = (unsigned char)(int8_t)v;
-    }
-    // zero the padding columns a fragment may read past pcol (masked anyway, keep defined)
-    __syncthreads();
-
-    // ---- second moments on the matrix cores ----
+    // ---- phase 1: second moments on the matrix cores ----
     // k-step = 64 consecutive patch positions of one row; lane (i = l%16, kq = l/16) holds
     // patch-vector entry 16*blk + i for patches 16*kq .. 16*kq+15 of the step.
     v4i acc[10];
@@ -103,32 +105,41 @@ __global__ __launch_bounds__(256) void cov_eig_kernel(ImageGeom g, int T, double
     const v4i ones = {0x01010101, 0x01010101, 0x01010101, 0x01010101};
     const int i16 = lane & 15, kq = lane >> 4;
     const int xsteps = (nx + 63) / 64;
-    for (int stp = wave; stp < ny * xsteps; stp += 4) {
-        const int py = stp / xsteps, pxs = (stp % xsteps) * 64;
-        const int k0 = pxs + 16 * kq;                 // first patch column of this lane
-        const int valid = min(16, max(0, nx - k0));
-        v4i f[4];
+    for (int b0 = 0; b0 < ny; b0 += COV_BAND) {
+        const int nb = min(COV_BAND, ny - b0);
+        const int prow = nb + PS - 1;
+        __syncthreads();   // previous band consumed
+        for (int e = tid; e < prow * pcol; e += 256) {
+            const int r = e / pcol, col = e % pcol;
+            const int v = (int)g.img[(int64_t)(y0 + b0 + r) * g.stride + (int64_t)(x0 + col) * g.c + ch] - 128;
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk) {
-            const int e = 16 * blk + i16;             // patch-vector entry (a, b) = (e/8, e%8)
-            f[blk] = frag16(smem, plane, py + e / 8, k0 + e % 8, valid);
+            for (int k = 0; k < 4; ++k)
+                if (col >= k) stage[k * COV_PLANE + r * COV_PITCH + col - k] = (unsigned char)(int8_t)v;
         }
-        int a = 0;
+        __syncthreads();
+        for (int stp = wave; stp < nb * xsteps; stp += 4) {
+            const int py = stp / xsteps, pxs = (stp % xsteps) * 64;
+            const int k0 = pxs + 16 * kq;                 // first patch column of this lane
+            const int valid = min(16, max(0, nx - k0));
+            v4i f[4];
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
-#pragma unroll
-            for (int jb = ib; jb < 4; ++jb) {
-                acc[a] = __builtin_amdgcn_mfma_i32_16x16x64_i8(f[ib], f[jb], acc[a], 0, 0, 0);
-                ++a;
+            for (int blk = 0; blk < 4; ++blk) {
+                const int e = 16 * blk + i16;             // patch-vector entry (a, b) = (e/8, e%8)
+                f[blk] = frag16(stage, COV_PLANE, py + e / 8, k0 + e % 8, valid);
             }
-            acc1[ib] = __builtin_amdgcn_mfma_i32_16x16x64_i8(f[ib], ones, acc1[ib], 0, 0, 0);
+            int a = 0;
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) {
+#pragma unroll
+                for (int jb = ib; jb < 4; ++jb) {
+                    acc[a] = __builtin_amdgcn_mfma_i32_16x16x64_i8(f[ib], f[jb], acc[a], 0, 0, 0);
+                    ++a;
+                }
+                acc1[ib] = __builtin_amdgcn_mfma_i32_16x16x64_i8(f[ib], ones, acc1[ib], 0, 0, 0);
+            }
         }
     }
-    __syncthreads();  // staging no longer needed: reuse LDS
-
-    // per-wave partials -> LDS, summed in int64
-    int32_t *part = reinterpret_cast<int32_t *>(smem);          // [4 waves][64][64]
-    int32_t *part1 = part + 4 * 64 * 64;                        // [4 waves][64]
+    // wave partials -> LDS (integer adds: exact, order free; totals < 2^28)
     {
         int a = 0;
 #pragma unroll
@@ -136,123 +147,110 @@ __global__ __launch_bounds__(256) void cov_eig_kernel(ImageGeom g, int T, double
 #pragma unroll
             for (int jb = ib; jb < 4; ++jb) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * ib + 4 * kq + r, col = 16 * jb + i16;
-                    part[(wave * 64 + row) * 64 + col] = acc[a][r];
-                }
+                for (int r = 0; r < 4; ++r) atomicAdd(&S2[(16 * ib + 4 * kq + r) * 64 + 16 * jb + i16], acc[a][r]);
                 ++a;
             }
             if (i16 == 0) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) part1[wave * 64 + 16 * ib + 4 * kq + r] = acc1[ib][r];
+                for (int r = 0; r < 4; ++r) atomicAdd(&S1[16 * ib + 4 * kq + r], acc1[ib][r]);
             }
         }
     }
     __syncthreads();
-    double *A = reinterpret_cast<double *>(smem + (4 * 64 * 64 + 4 * 64) * 4);   // 64 x 64
-    double *S1 = A + 64 * 64;
-    const double n = (double)ny * (double)nx;
-    if (tid < 64) {
-        int64_t s = 0;
-        for (int w = 0; w < 4; ++w) s += part1[w * 64 + tid];
-        S1[tid] = (double)s;
-    }
-    __syncthreads();
-    for (int e = tid; e < 64 * 64; e += 256) {
-        const int i = e / 64, j = e % 64;
-        const int ii = min(i, j), jj = max(i, j);   // only blocks ib <= jb were computed
-        int64_t s = 0;
-        if ((ii / 16) <= (jj / 16)) {
-            for (int w = 0; w < 4; ++w) s += part[(w * 64 + ii) * 64 + jj];
-        }
-        A[e] = (double)s / n - (S1[i] / n) * (S1[j] / n);
-    }
-    __syncthreads();
+    if (wave != 0) return;   // phase 2 runs on one wavefront; no block barrier follows
 
-    // ---- cyclic Jacobi, round-robin pairs ----
-    __shared__ double rc[32], rs[32];
-    __shared__ int rp[32], rq[32];
-    for (int sweep = 0; sweep < 20; ++sweep) {
-        for (int rnd = 0; rnd < 63; ++rnd) {
-            if (tid < 32) {
-                int p, q;
-                if (tid == 0) { p = rnd; q = 63; }
-                else { p = (rnd + tid) % 63; q = (rnd - tid + 63) % 63; }
-                if (p > q) { int x = p; p = q; q = x; }
-                const double apq = A[p * 64 + q];
-                double c = 1.0, s = 0.0;
-                if (apq != 0.0) {
-                    const double app = A[p * 64 + p], aqq = A[q * 64 + q];
-                    const double theta = (aqq - app) / (2.0 * apq);
-                    double tt = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
-                    if (theta < 0.0) tt = -tt;
-                    c = 1.0 / sqrt(tt * tt + 1.0);
-                    s = tt * c;
-                }
-                rc[tid] = c; rs[tid] = s; rp[tid] = p; rq[tid] = q;
-            }
-            __syncthreads();
-            // rows p, q <- J^T A
-            for (int e = tid; e < 32 * 64; e += 256) {
-                const int k = e / 64, j = e % 64;
-                const int p = rp[k], q = rq[k];
-                const double c = rc[k], s = rs[k];
-                const double ap = A[p * 64 + j], aq = A[q * 64 + j];
-                A[p * 64 + j] = c * ap - s * aq;
-                A[q * 64 + j] = s * ap + c * aq;
-            }
-            __syncthreads();
-            // columns p, q <- A J
-            for (int e = tid; e < 32 * 64; e += 256) {
-                const int k = e / 64, i = e % 64;
-                const int p = rp[k], q = rq[k];
-                const double c = rc[k], s = rs[k];
-                const double ap = A[i * 64 + p], aq = A[i * 64 + q];
-                A[i * 64 + p] = c * ap - s * aq;
-                A[i * 64 + q] = s * ap + c * aq;
-            }
-            __syncthreads();
-        }
-        // convergence: off-diagonal mass relative to the diagonal
-        if (tid < 64) {
-            double off = 0.0, dg = 0.0;
-            for (int j = 0; j < 64; ++j) {
-                const double v = A[tid * 64 + j];
-                if (j == tid) dg += v * v; else off += v * v;
-            }
-            S1[tid] = off;
-            S1[64 + tid] = dg;  // S1 has room: it is followed by unused LDS (see layout)
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double off = 0.0, dg = 0.0;
-            for (int j = 0; j < 64; ++j) { off += S1[j]; dg += S1[64 + j]; }
-            s_stop = off <= 1e-30 * dg;
-        }
-        __syncthreads();
-        if (s_stop) break;
+    // ---- phase 2: covariance row i = lane, in registers ----
+    const int i = lane;
+    const double n = (double)ny * (double)nx;
+    const double s1i = (double)S1[i] / n;
+    double row[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+        const int ii = min(i, j), jj = max(i, j);   // only blocks ib <= jb were accumulated
+        row[j] = (double)S2[ii * 64 + jj] / n - s1i * ((double)S1[j] / n);
     }
-    // ---- eigenvalues descending, tail rule ----
-    if (tid == 0) {
-        double ev[64];
-        for (int i = 0; i < 64; ++i) ev[i] = A[i * 64 + i];
-        for (int i = 1; i < 64; ++i) {          // insertion sort, descending
-            const double v = ev[i];
-            int j = i - 1;
-            while (j >= 0 && ev[j] < v) { ev[j + 1] = ev[j]; --j; }
-            ev[j + 1] = v;
-        }
-        double res = ev[63];
-        for (int i = 0; i < 64; ++i) {
-            double sum = 0.0;
-            for (int j = i; j < 64; ++j) sum += ev[j];
-            const double tau = sum / (double)(64 - i);
-            int above = 0, below = 0;
-            for (int j = i; j < 64; ++j) { above += ev[j] > tau; below += ev[j] < tau; }
-            if (above == below) { res = tau; break; }
-        }
-        sigma2[t * g.c + ch] = res;
+    double *vv = vec, *ww = vec + 64;
+    // Householder: step k annihilates column k below the subdiagonal.
+    for (int k = 0; k < 62; ++k) {
+        double xk = 0.0;
+#pragma unroll
+        for (int j = 0; j < 64; ++j) xk = (j == k) ? row[j] : xk;   // lane i: A[i][k]
+        const double tail = wave_sum_d(i > k + 1 ? xk * xk : 0.0);
+        const double x0 = __shfl(xk, k + 1);
+        if (tail == 0.0) continue;                       // column already reduced (uniform)
+        const double nrm = sqrt(x0 * x0 + tail);
+        const double alpha = x0 > 0.0 ? -nrm : nrm;
+        const double v0 = x0 - alpha;
+        const double beta = 2.0 / (v0 * v0 + tail);
+        const double vi = i == k + 1 ? v0 : (i > k + 1 ? xk : 0.0);
+        vv[i] = vi;
+        __builtin_amdgcn_wave_barrier();
+        double pi = 0.0;
+#pragma unroll
+        for (int j = 0; j < 64; ++j) pi += row[j] * vv[j];
+        pi *= beta;
+        const double Kc = 0.5 * beta * wave_sum_d(pi * vi);
+        const double wi = pi - Kc * vi;
+        ww[i] = wi;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int j = 0; j < 64; ++j) row[j] -= vi * ww[j] + wi * vv[j];
+        __builtin_amdgcn_wave_barrier();
     }
+    // tridiagonal: d_i = A[i][i], e_{i-1} = A[i][i-1]
+    double di = 0.0, sub = 0.0;
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+        di = (j == i) ? row[j] : di;
+        sub = (j == i - 1) ? row[j] : sub;
+    }
+    double *dd = vec, *e2 = vec + 64, *ev = vec + 128;
+    __builtin_amdgcn_wave_barrier();
+    dd[i] = di;
+    e2[i] = i > 0 ? sub * sub : 0.0;    // e2[i] = e_{i-1}^2
+    // Gershgorin interval
+    const double se = fabs(sub) + fabs(__shfl(sub, (i + 1) & 63) * (i < 63 ? 1.0 : 0.0));
+    double lo = di - se, hi = di + se;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o));
+        hi = fmax(hi, __shfl_xor(hi, o));
+    }
+    __builtin_amdgcn_wave_barrier();
+    // bisection for the i-th smallest eigenvalue: count(x) = #eigenvalues < x (Sturm)
+    const double span = fmax(hi - lo, 1e-300);
+    lo -= 1e-12 * span;
+    hi += 1e-12 * span;
+    for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        int cnt = 0;
+        double q = dd[0] - mid;
+        cnt += q < 0.0;
+        for (int j = 1; j < 64; ++j) {
+            if (q == 0.0) q = 1e-300;
+            q = (dd[j] - mid) - e2[j] / q;
+            cnt += q < 0.0;
+        }
+        if (cnt > i) hi = mid;
+        else lo = mid;
+    }
+    const double lam = 0.5 * (lo + hi);   // ascending: lane i holds the i-th smallest
+    ev[i] = lam;
+    __builtin_amdgcn_wave_barrier();
+    // tail rule on the descending order: tail m = the 64 - m smallest values (lane m)
+    const int m = lane, len = 64 - m;
+    double sum = 0.0;
+    for (int j = len - 1; j >= 0; --j) sum += ev[j];   // largest of the tail first
+    const double tau = sum / (double)len;
+    int above = 0, below = 0;
+    for (int j = 0; j < len; ++j) {
+        above += ev[j] > tau;
+        below += ev[j] < tau;
+    }
+    const uint64_t hit = __ballot(above == below);
+    // cross-lane read with every lane active; the smallest eigenvalue when no tail qualifies
+    const double tau_first = __shfl(tau, hit ? __ffsll((unsigned long long)hit) - 1 : 0);
+    if (lane == 0) sigma2[t * g.c + ch] = hit ? tau_first : ev[0];
 }
 
 __global__ void combine_sigma_kernel(const double *sigma2, int c, int n_tiles, double *sigma_est) {
@@ -290,32 +288,38 @@ __device__ inline void ref_range(int n_ref, int n, int s, int lo, int hi, int *f
     *last = l;
 }
 
-// One wavefront per sub-image: up to n_vote sampled groups, rank of lambda_hat, majority.
+// One workgroup (4 wavefronts) per sub-image: the sampled groups are spread over the waves;
+// per group the exact autocorrelations c_d, then lambda_k = sum_d c_d cos(2 pi k d / K) with
+// lane k computing lambda_k (same summation order for every k), the rank of lambda_hat, and
+// the majority over the groups.
 template <int K>
-__global__ __launch_bounds__(64) void vote_kernel(ImageGeom g, const int32_t *__restrict__ idx, int T, int n_vote,
-                                                  uint64_t seed, int gamma_rank, double beta,
-                                                  const double *__restrict__ sigma_est, double *__restrict__ sigma_hat,
-                                                  int32_t *__restrict__ votes) {
-    const int t = blockIdx.x, lane = threadIdx.x;
+__global__ __launch_bounds__(256) void vote_kernel(ImageGeom g, const int32_t *__restrict__ idx, int T, int n_vote,
+                                                   uint64_t seed, int gamma_rank, double beta,
+                                                   const double *__restrict__ sigma_est, double *__restrict__ sigma_hat,
+                                                   int32_t *__restrict__ votes) {
+    const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ntx = (g.w + T - 1) / T;
     const int ty = t / ntx, tx = t % ntx;
-    __shared__ int s_iy0, s_iy1, s_ix0, s_ix1;
-    if (lane == 0) {
+    __shared__ int s_iy0, s_iy1, s_ix0, s_ix1, s_yes;
+    __shared__ double cos_tab[K];
+    if (tid == 0) {
         ref_range(g.ny, g.h, g.s, ty * T, ty * T + T - 1, &s_iy0, &s_iy1);
         ref_range(g.nx, g.w, g.s, tx * T, tx * T + T - 1, &s_ix0, &s_ix1);
+        s_yes = 0;
     }
+    if (tid < K) cos_tab[tid] = cos(2.0 * M_PI * (double)tid / (double)K);
     __syncthreads();
     const int nyr = s_iy1 - s_iy0 + 1, nxr = s_ix1 - s_ix0 + 1;
     const int64_t n_t = (s_iy0 < 0 || s_ix0 < 0) ? 0 : (int64_t)nyr * nxr;
     const double se = sigma_est[t];
     if (n_t == 0) {
-        if (lane == 0) { sigma_hat[t] = se; if (votes) votes[t] = 0; }
+        if (tid == 0) { sigma_hat[t] = se; if (votes) votes[t] = 0; }
         return;
     }
     const int nv = n_t <= n_vote ? (int)n_t : n_vote;
     const int P = 64 * g.c;
     int yes = 0;
-    for (int i = 0; i < nv; ++i) {
+    for (int i = wave; i < nv; i += 4) {
         int64_t j;
         if (n_t <= n_vote) {
             j = i;
@@ -339,10 +343,10 @@ __global__ __launch_bounds__(64) void vote_kernel(ImageGeom g, const int32_t *__
             }
 #pragma unroll
             for (int d = 0; d <= K / 2; ++d) {
-                int s = 0;
+                int sacc = 0;
 #pragma unroll
-                for (int m = 0; m < K; ++m) s += v[m] * v[(m + d) % K];
-                cd[d] += s;
+                for (int m = 0; m < K; ++m) sacc += v[m] * v[(m + d) % K];
+                cd[d] += sacc;
             }
         }
 #pragma unroll
@@ -350,44 +354,39 @@ __global__ __launch_bounds__(64) void vote_kernel(ImageGeom g, const int32_t *__
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) cd[d] += __shfl_xor(cd[d], o);
         }
-        if (lane == 0) {
-            double lam[K / 2 + 1];
-            for (int k = 0; k <= K / 2; ++k) {
-                double acc = 0.0;
-                for (int d = 0; d < K; ++d) {
-                    const int dd = d <= K / 2 ? d : K - d;
-                    acc += (double)cd[dd] * cos(2.0 * M_PI * (double)((k * d) % K) / (double)K);
-                }
-                lam[k] = acc;
-            }
-            const double lhat = lam[K / 2];
-            const double tol = 1e-10 * (double)K * (double)cd[0];
-            int a = 1;
-            if (lam[0] < lhat - tol) a += 1;
-            for (int k = 1; k < K / 2; ++k)
-                if (lam[k] < lhat - tol) a += 2;
-            if (a <= gamma_rank) ++yes;
+        // lane k <= K/2: lambda_k
+        const int k = lane <= K / 2 ? lane : 0;
+        double lam = 0.0;
+#pragma unroll
+        for (int d = 0; d < K; ++d) {
+            const int dd = d <= K / 2 ? d : K - d;
+            lam += (double)cd[dd] * cos_tab[(k * d) % K];
         }
+        const double lhat = __shfl(lam, K / 2);
+        const double tol = 1e-10 * (double)K * (double)cd[0];
+        const bool below = lam < lhat - tol;
+        const uint64_t inner = __ballot(below && lane >= 1 && lane < K / 2);
+        const uint64_t first = __ballot(below && lane == 0);
+        const int a = 1 + (first ? 1 : 0) + 2 * __popcll(inner);
+        if (lane == 0 && a <= gamma_rank) ++yes;
     }
-    if (lane == 0) {
-        sigma_hat[t] = 2 * yes > nv ? se / beta : se;
-        if (votes) votes[t] = yes;
+    if (lane == 0 && yes) atomicAdd(&s_yes, yes);
+    __syncthreads();
+    if (tid == 0) {
+        sigma_hat[t] = 2 * s_yes > nv ? se / beta : se;
+        if (votes) votes[t] = s_yes;
     }
 }
 
 }  // namespace
 
-int cov_lds_bytes() {
-    const int stage = 4 * COV_MAX_SIDE * COV_PITCH;
-    const int red = (4 * 64 * 64 + 4 * 64) * 4 + (64 * 64 + 128) * 8;
-    return stage > red ? stage : red;
-}
+int cov_lds_bytes() { return COV_LDS; }
 
 hipError_t launch_sigma_est(const ImageGeom &g, int tile, double *work, double *sigma_est, hipStream_t st) {
     if (tile != 128) return hipErrorInvalidValue;
     const int n_tiles = ((g.h + tile - 1) / tile) * ((g.w + tile - 1) / tile);
     const int lds = cov_lds_bytes();
-    hipError_t e0 = prepare_dynamic_lds((const void *)cov_eig_kernel, lds, 1024);
+    hipError_t e0 = prepare_dynamic_lds((const void *)cov_eig_kernel, lds, 0);
     if (e0 != hipSuccess) return e0;
     hipLaunchKernelGGL(cov_eig_kernel, dim3(n_tiles * g.c), dim3(256), lds, st, g, tile, work);
     hipError_t e = hipGetLastError();
@@ -408,7 +407,7 @@ hipError_t launch_vote(const ImageGeom &g, const MethodParams &mp, const int32_t
     const int n_tiles = ((g.h + tile - 1) / tile) * ((g.w + tile - 1) / tile);
 #define HV_CASE(KK)                                                                                              \
     if (mp.K == KK) {                                                                                            \
-        hipLaunchKernelGGL(vote_kernel<KK>, dim3(n_tiles), dim3(64), 0, st, g, idx, tile, n_vote, seed, gamma_rank, \
+        hipLaunchKernelGGL(vote_kernel<KK>, dim3(n_tiles), dim3(256), 0, st, g, idx, tile, n_vote, seed, gamma_rank, \
                            beta, sigma_est, sigma_hat, votes);                                                   \
         return hipGetLastError();                                                                                \
     }
