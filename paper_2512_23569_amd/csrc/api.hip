@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <complex>
 #include <string>
 #include <vector>
@@ -46,7 +47,7 @@ struct BatchCache {
 
 struct htsvd_ctx {
     int device = 0;
-    BasisDev basis[2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [0]: c=1, [1]: c=3
+    BasisDev basis[2] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};  // [0]: c=1, [1]: c=3
     bool has_basis[2] = {false, false};
     void *ws = nullptr;
     size_t ws_size = 0;
@@ -443,6 +444,7 @@ void htsvd_destroy(htsvd_ctx *ctx) {
     for (int i = 0; i < 2; ++i) {
         if (ctx->basis[i].f32) (void)hipFree(ctx->basis[i].f32);
         if (ctx->basis[i].T64) (void)hipFree(ctx->basis[i].T64);
+        if (ctx->basis[i].frag) (void)hipFree(const_cast<void *>(ctx->basis[i].frag));
     }
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->d_guard) (void)hipFree(ctx->d_guard);
@@ -550,6 +552,87 @@ htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double
                 T[(size_t)(k * 64 + e) * P + p] = acc.real() / c;
             }
     }
+    // MFMA operand fragments of the block-diagonal per-slice maps (see the filter's header):
+    //   forward F = L_S^-1 T L_x^-1, inverse Finv = L_S^-1 T^T L_x^-1, with L_x the per-position
+    //   channel map (R,G,B) -> (R+G+B, 2R-G-B, B-G) and S = L_S (s0', re', im') the recombination
+    //   S0 = s0' + 2re', S1 = s0' - re' - im', S2 = s0' - re' + im'  (c = 1: identities).
+    std::vector<uint16_t> frag;
+    {
+        const int NP = c == 3 ? 40 : 8;
+        std::vector<double> Lxi((size_t)P * P, 0.0), LSi((size_t)P * P, 0.0);
+        if (c == 3) {
+            // inverses of [[1,1,1],[2,-1,-1],[0,-1,1]] and [[1,2,0],[1,-1,-1],[1,-1,1]]
+            const double lxi[3][3] = {{1.0 / 3, 1.0 / 3, 0.0}, {1.0 / 3, -1.0 / 6, -0.5}, {1.0 / 3, -1.0 / 6, 0.5}};
+            const double lsi[3][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {1.0 / 3, -1.0 / 6, -1.0 / 6}, {0.0, -0.5, 0.5}};
+            for (int e2 = 0; e2 < 64; ++e2)
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        Lxi[(size_t)(a * 64 + e2) * P + b * 64 + e2] = lxi[a][b];
+                        LSi[(size_t)(a * 64 + e2) * P + b * 64 + e2] = lsi[a][b];
+                    }
+        } else {
+            for (int e2 = 0; e2 < 64; ++e2) Lxi[(size_t)e2 * P + e2] = LSi[(size_t)e2 * P + e2] = 1.0;
+        }
+        auto mul = [&](const std::vector<double> &A, const std::vector<double> &B, bool bt) {
+            std::vector<double> Cm((size_t)P * P, 0.0);
+            for (int i = 0; i < P; ++i)
+                for (int k = 0; k < P; ++k) {
+                    const double a = A[(size_t)i * P + k];
+                    if (a == 0.0) continue;
+                    for (int j = 0; j < P; ++j) Cm[(size_t)i * P + j] += a * (bt ? B[(size_t)j * P + k] : B[(size_t)k * P + j]);
+                }
+            return Cm;
+        };
+        const std::vector<double> Ff = mul(mul(LSi, T, false), Lxi, false);
+        const std::vector<double> Fi = mul(mul(LSi, T, true), Lxi, false);
+        for (int n = 0; n < P; ++n)
+            for (int k = 0; k < P; ++k)
+                if ((n < 64) != (k < 64) && (std::fabs(Ff[(size_t)n * P + k]) > 1e-12 || std::fabs(Fi[(size_t)n * P + k]) > 1e-12))
+                    return fail(HTSVD_EINVAL, "per-slice transform is not block diagonal");
+        auto f16 = [](double x) -> uint16_t {   // round to nearest even, with subnormals
+            const float f = (float)x;
+            uint32_t u;
+            memcpy(&u, &f, 4);
+            const uint32_t sgn = (u >> 16) & 0x8000u;
+            const float af = std::fabs(f);
+            if (af >= 65520.f) return (uint16_t)(sgn | 0x7c00u);
+            if (af < 6.103515625e-05f) {   // subnormal: multiples of 2^-24
+                const float q = std::nearbyint(af * 16777216.f);
+                return (uint16_t)(sgn | (uint32_t)q);
+            }
+            uint32_t e = ((u >> 23) & 0xffu) - 127 + 15, m = u & 0x7fffffu;
+            uint32_t hm = m >> 13, rem = m & 0x1fffu;
+            if (rem > 0x1000u || (rem == 0x1000u && (hm & 1u))) {
+                if (++hm == 0x400u) { hm = 0; ++e; }
+            }
+            return (uint16_t)(sgn | (e << 10) | hm);
+        };
+        auto f16v = [](uint16_t hbits) -> double {
+            const uint32_t e = (hbits >> 10) & 31u, m = hbits & 1023u;
+            const double v = e == 0 ? std::ldexp((double)m, -24) : std::ldexp(1.0 + m / 1024.0, (int)e - 15);
+            return (hbits & 0x8000u) ? -v : v;
+        };
+        frag.assign((size_t)2 * 2 * NP * 64 * 8, 0);
+        for (int dir = 0; dir < 2; ++dir) {
+            const std::vector<double> &M = dir == 0 ? Ff : Fi;
+            int pr = 0;
+            for (int t = 0; t < 2 * c; ++t)
+                for (int st = 0; st < 4 * c; ++st) {
+                    const bool blk0 = t < 2, kin0 = st < 4;
+                    if (blk0 != kin0) continue;   // zero blocks are skipped
+                    for (int l = 0; l < 64; ++l)
+                        for (int jj = 0; jj < 8; ++jj) {
+                            const int k = 16 * st + 8 * (l / 32) + jj, n = 32 * t + (l % 32);
+                            const double v = M[(size_t)n * P + k];
+                            const uint16_t hi = f16(v), lo = f16(v - f16v(hi));
+                            frag[((size_t)((dir * 2 + 0) * NP + pr) * 64 + l) * 8 + jj] = hi;
+                            frag[((size_t)((dir * 2 + 1) * NP + pr) * 64 + l) * 8 + jj] = lo;
+                        }
+                    ++pr;
+                }
+            if (pr != NP) return fail(HTSVD_EINVAL, "internal: fragment table size");
+        }
+    }
     const int slot = c == 3;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -563,6 +646,15 @@ htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double
     if ((e = hipMemcpy(ctx->basis[slot].f32, f32.data(), sizeof(float) * 6 * 64, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "basis upload");
     if ((e = hipMemcpy(ctx->basis[slot].T64, T.data(), sizeof(double) * P * P, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "basis upload");
+    if (!ctx->basis[slot].frag) {
+        void *fp = nullptr;
+        if ((e = hipMalloc(&fp, sizeof(uint16_t) * 2 * 2 * 40 * 64 * 8)) != hipSuccess)
+            return fail(HTSVD_ENOMEM, "basis allocation");
+        ctx->basis[slot].frag = fp;
+    }
+    if ((e = hipMemcpy(const_cast<void *>(ctx->basis[slot].frag), frag.data(), sizeof(uint16_t) * frag.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "basis upload");
     ctx->has_basis[slot] = true;
     return HTSVD_OK;
@@ -900,10 +992,10 @@ htsvd_status plan_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, cons
         b.off_idx = off; off = align256(off + sizeof(int32_t) * b.n_ref * b.mp.K);
         b.off_tau = off; off = align256(off + sizeof(double) * b.n_ref);
         b.off_reg = off;
-        size_t reg = (size_t)b.tg.tiles_y * b.tg.tiles_x * b.tg.RH * b.tg.RW * (b.g.c + 1) * sizeof(float);
+        size_t reg = (size_t)b.tg.tiles_y * b.tg.tiles_x * region_elems(b.tg, b.g.c) * sizeof(float);
         if (b.auto_k)
-            reg = std::max(reg, (size_t)b.tg_alt.tiles_y * b.tg_alt.tiles_x * b.tg_alt.RH * b.tg_alt.RW *
-                                    (b.g.c + 1) * sizeof(float));
+            reg = std::max(reg, (size_t)b.tg_alt.tiles_y * b.tg_alt.tiles_x * region_elems(b.tg_alt, b.g.c) *
+                                    sizeof(float));
         off = align256(off + reg);
         b.off_sig = off;  // sig_est, sig_hat, votes, cov (c per tile), use_plain, sig_plain
         off = align256(off + b.n_tiles_sigma * (sizeof(double) * (3 + b.g.c) + 2 * sizeof(int32_t)));

@@ -34,8 +34,9 @@ struct MethodParams {
 // Plus the FP64 matrix T (P x P, P = 64c) with s = T g for one patch in slice-major
 // vector form, used to re-decide coefficients near the threshold.
 struct BasisDev {
-    float *f32;     // 6*64 floats
-    double *T64;    // P*P doubles
+    float *f32;        // 6*64 floats
+    double *T64;       // P*P doubles
+    const void *frag;  // MFMA operand fragments of the per-slice transform matrices (fp16 hi/lo)
 };
 
 // Reference tiles of the filter kernel and the image regions their groups reach.
@@ -43,8 +44,17 @@ struct TileGeom {
     int TY, TX;          // references per tile
     int tiles_y, tiles_x;
     int RH, RW;          // region capacity (rows, cols) per tile
+    int RP;              // row pitch of a region plane in floats (>= RW, RP % 16 == 8)
+    int FS;              // fixed-point shift of the LDS accumulation (sums in int32 units of 2^-FS)
     int R;               // search radius (W-1)/2
 };
+
+// A tile's region is C + 1 planes of RH x RP floats: the channel sums, then the number of
+// patches covering each pixel.  Planar, with the pitch chosen so that the 4 x 8 pixels of a
+// patch half fall on 32 distinct LDS banks.  In LDS the planes hold int32 (fixed point for the
+// sums, see FS); the global copy is float.
+__host__ __device__ inline int region_plane(const TileGeom &tg) { return tg.RH * tg.RP; }
+__host__ __device__ inline int region_elems(const TileGeom &tg, int C) { return (C + 1) * tg.RH * tg.RP; }
 
 // One image of a batched call, as the persistent kernels see it.
 struct BatchItem {
@@ -86,6 +96,22 @@ __host__ __device__ inline int ref_count(int n, int s) {
     return c;
 }
 
+// Image rows / columns reached by the groups of reference tile (ty, tx): the references'
+// window reach plus the patch extent, clipped to the image.
+__device__ __host__ inline void region_rows(const ImageGeom &g, const TileGeom &tg, int ty, int *r0, int *r1) {
+    const int i0 = ty * tg.TY;
+    const int i1 = min(i0 + tg.TY, g.ny) - 1;
+    *r0 = max(0, ref_pos(i0, g.ny, g.h, g.s) - tg.R);
+    *r1 = min(g.h - 1, ref_pos(i1, g.ny, g.h, g.s) + tg.R + PS - 1);
+}
+
+__device__ __host__ inline void region_cols(const ImageGeom &g, const TileGeom &tg, int tx, int *c0, int *c1) {
+    const int i0 = tx * tg.TX;
+    const int i1 = min(i0 + tg.TX, g.nx) - 1;
+    *c0 = max(0, ref_pos(i0, g.nx, g.w, g.s) - tg.R);
+    *c1 = min(g.w - 1, ref_pos(i1, g.nx, g.w, g.s) + tg.R + PS - 1);
+}
+
 // Makes `bytes` of dynamic LDS available to `kernel` (static LDS comes on top); fails with
 // hipErrorInvalidValue if the device cannot give a workgroup that much.
 hipError_t prepare_dynamic_lds(const void *kernel, int bytes, int static_bytes);
@@ -119,6 +145,15 @@ hipError_t launch_fill_tau_batched(const BatchItem *items, int n_items, const in
 // region and group buffers fit in LDS.
 TileGeom plan_filter_tiles(const ImageGeom &g, int W, int K, int max_side);
 int filter_lds_bytes_for(const TileGeom &tg, int C, int K);
+// matrix-core filter (filter_mfma.hip)
+int filter_mfma_lds_bytes(const TileGeom &tg, int C);
+int filter_mfma_group_bytes(int C);  // LDS besides the region
+int filter_mfma_static_bytes();
+hipError_t launch_filter_mfma(const ImageGeom &g, const TileGeom &tg, int K, const BasisDev &b, const int32_t *idx,
+                              const double *tau_ref, float *regions, unsigned long long *gc, hipStream_t st);
+hipError_t launch_filter_mfma_batched(int C, int K, const BatchItem *items, int n_items, const int *unit_start,
+                                      int lds, const BasisDev &b, unsigned long long *gc, int *queue, int grid,
+                                      hipStream_t st);
 int filter_lds_budget();
 
 // ---- learned noise-level network ----

@@ -1,0 +1,697 @@
+// Collaborative filtering (Eq. 19-21) and aggregation (Algorithm 1) on the matrix cores of gfx950.
+//
+// The per-patch transform S = U^T * G * V is linear in the patch, and with the 3-point DFT along
+// the channel mode (Eq. 4-5) it splits into a real 64 x 64 map on the channel sum and a real
+// 128 x 128 map on the (real, imaginary) pair of the first Fourier slice; the third slice is the
+// conjugate of the second.  Thirty-two patches at a time are contracted against these matrices
+// with v_mfma_f32_32x32x16_f16:
+//
+//   forward   [s0'; re'; im'] (32 patches x 192) = [a0, ar, ai] (32 x 192) . F^T
+//             a0 = R+G+B, ar = 2R-G-B, ai = B-G are integers, exact in fp16; F is split into
+//             fp16 hi + lo (two products, ~22-bit matrix); accumulation in fp32.
+//             S0 = s0' + 2 re', S1 = s0' - re' - im', S2 = s0' - re' + im'  (1/3 and sqrt3 folded into F)
+//   Haar      along the group (Eq. 7-8), in registers: the result layout of the MFMA puts 16
+//             patches of one coefficient column in one lane, the other 16 in lane + 32.
+//             Unnormalised butterflies; the threshold of a coefficient produced by l butterflies
+//             is tau * 2^(l/2), and the inverse scales kept values by 2^-l (exact).
+//   threshold keep |s| >= tau (Eq. 20); values within 0.05 of tau are re-decided in FP64 from the
+//             uint8 group and the FP64 transform.
+//   inverse   the kept coefficients, recombined as s0 = S0+S1+S2, sr = 2S0-S1-S2, d = S2-S1,
+//             are transposed through LDS into the A-operand layout and multiplied by the inverse
+//             matrix with three products (hi.hi + hi.lo + lo.hi); R, G, B follow as above.
+//   Algorithm 1: every reconstructed patch is added (sums and a count) into an LDS copy of the
+//             image region the tile's groups reach; the region goes to the tile's slot of a
+//             global buffer and the gather kernel divides.
+//
+// c = 1 uses the single 64 x 64 map and no channel DFT.
+#include "common.h"
+
+namespace htsvd {
+
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+namespace {
+
+constexpr int MW = 4;          // wavefronts per workgroup
+constexpr int MNEAR = 64;      // near-threshold list capacity per wavefront
+constexpr float MGUARD = 0.05f;
+constexpr int XS = 33;         // words per row of the per-wave transpose buffer (32 + 1 pad)
+constexpr int XWORDS = 32 * XS;
+
+struct MfmaShared {
+    int r0, c0;
+    int near_n[MW];
+    int near_a[MW][MNEAR];     // lane | tile << 6 | reg << 9 | group << 13
+    int near_b[MW][MNEAR];     // haar row k | coefficient q << 8
+    int near_kill[MW][MNEAR];
+};
+
+// Number of pairs of fragment tables: c = 3: forward/inverse x hi/lo x 40 (tile, k-step) blocks.
+template <int C>
+struct Frag {
+    static constexpr int NPAIR = C == 3 ? 40 : 8;
+};
+
+// Pair index of (output tile t, k-step s) in the block-diagonal fragment table.
+template <int C>
+__device__ __host__ constexpr int pair_of(int t, int s) {
+    return (C == 1 || t < 2) ? t * 4 + s : 8 + (t - 2) * 8 + (s - 4);
+}
+
+__device__ inline v8h ldfrag(const v8h *__restrict__ base, int dir, int term, int pair, int npair, int lane) {
+    return base[((dir * 2 + term) * npair + pair) * 64 + lane];
+}
+
+// 8*C bytes of one patch row starting at p (dword loads + byte alignment when in bounds).
+template <int C>
+__device__ inline void load_row_u8(const uint8_t *p, const uint8_t *end, uint32_t (&out)[2 * C]) {
+    constexpr int ND = 2 * C + 1;
+    const uintptr_t a = (uintptr_t)p;
+    const uint32_t *base = reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
+    const int sh = (int)(a & 3);
+    if ((const uint8_t *)(base + ND) <= end) {
+        uint32_t d[ND];
+#pragma unroll
+        for (int i = 0; i < ND; ++i) d[i] = base[i];
+#pragma unroll
+        for (int i = 0; i < 2 * C; ++i) out[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh * 1u);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 2 * C; ++i)
+            out[i] = (uint32_t)p[4 * i] | ((uint32_t)p[4 * i + 1] << 8) | ((uint32_t)p[4 * i + 2] << 16) |
+                     ((uint32_t)p[4 * i + 3] << 24);
+    }
+}
+
+__device__ inline int byte_of(const uint32_t *w, int i) { return (int)((w[i >> 2] >> (8 * (i & 3))) & 0xffu); }
+
+// Entry (k, m) of the orthonormal Haar matrix H_n of Eq. 8.
+__device__ inline double haar_w(int k, int m, int n) {
+    const double r2 = 0.70710678118654752440;
+    double w = 1.0;
+    while (n > 1) {
+        if (k < n / 2) {
+            w *= r2;
+            m >>= 1;
+            n >>= 1;
+        } else {
+            const int i = k - n / 2;
+            return m == 2 * i ? w * r2 : (m == 2 * i + 1 ? -w * r2 : 0.0);
+        }
+    }
+    return w;
+}
+
+__device__ inline void wave_lds_fence() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline double wave_sum64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Value of the same register in lane l ^ 32.
+__device__ inline float swap_half(float v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(threadIdx.x & 32 ? r[0] : r[1]);
+}
+
+// Butterfly count l of the coefficient left in register r (group size K, 16 registers per lane).
+template <int K>
+__device__ __host__ constexpr int haar_level(int r) {
+    constexpr int KL = K < 16 ? K : 16;
+    constexpr int LK = K == 32 ? 5 : (K == 16 ? 4 : (K == 8 ? 3 : 2));
+    const int i = r % KL;
+    if (i == 0) return LK;
+    int l = 1;
+    while (!((i >> (l - 1)) & 1)) ++l;
+    return l;
+}
+
+// Haar row k (Eq. 8 order) of the coefficient in register r of lane half h.
+template <int K>
+__device__ inline int haar_row(int r, int h) {
+    constexpr int KL = K < 16 ? K : 16;
+    const int i = r % KL;
+    if (i == 0) return K == 32 ? h : 0;
+    const int l = haar_level<K>(r);
+    const int mu0 = (K == 32 ? 16 * h : 0) + i - (1 << (l - 1));
+    return (K >> l) + (mu0 >> l);
+}
+
+// Contribution in fixed point (round to nearest even); |v| is clamped to 1024 (four times the
+// 8-bit range) so that no region sum can overflow (see the accumulation shift of the tiling).
+__device__ inline int to_fixed(float v, float scale) {
+    return __float2int_rn(fminf(fmaxf(v, -1024.f), 1024.f) * scale);
+}
+
+// LDS bytes of the forward fragment table (kept in LDS for the whole kernel).
+template <int C>
+__device__ __host__ constexpr int ftab_bytes() {
+    return Frag<C>::NPAIR * 2 * 64 * 16;
+}
+
+// One reference tile: every group of the tile, 32 patches (32/K groups) per wavefront step.
+//   FL: forward fragments in LDS ([term][pair][lane]); FG: global table (inverse at dir 1).
+template <int C, int K>
+__device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileGeom &tg, const v8h *FL,
+                                                 const v8h *__restrict__ FG, const double *__restrict__ T64,
+                                                 const int32_t *__restrict__ idx, const int idx_stride,
+                                                 const double *__restrict__ tau_ref, const double tau_mul,
+                                                 float *__restrict__ regions,
+                                                 unsigned long long *__restrict__ guard_count, const int tile,
+                                                 float *region, uint32_t *xbuf_all, MfmaShared &sh) {
+    constexpr int P = 64 * C;
+    constexpr int CH = C + 1;
+    constexpr int NT = 2 * C;            // 32-column tiles of the 64C coefficients
+    constexpr int NPAIR = Frag<C>::NPAIR;
+    constexpr int G = 32 / K;            // groups per step
+    constexpr int KL = K < 16 ? K : 16;  // group members per lane-half block
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c32 = lane & 31, h = lane >> 5;
+    const int ty = tile / tg.tiles_x, tx = tile % tg.tiles_x;
+    uint32_t *xbuf = xbuf_all + wave * XWORDS;
+    const int plane = region_plane(tg), relems = region_elems(tg, C);
+    // LDS accumulation in int32 (float atomics in LDS are far slower than integer ones):
+    // channel sums in units of 2^-FS, then patches by top-left pixel, which become the count.
+    int *iregion = reinterpret_cast<int *>(region);
+    int *hist = iregion + C * plane;
+    const float fscale = (float)(1 << tg.FS);
+    if (tid == 0) {
+        int r0, r1, c0, c1;
+        region_rows(g, tg, ty, &r0, &r1);
+        region_cols(g, tg, tx, &c0, &c1);
+        sh.r0 = r0;
+        sh.c0 = c0;
+    }
+    for (int e = tid; e < relems; e += MW * 64) iregion[e] = 0;
+    __syncthreads();
+    const int r0 = sh.r0, c0 = sh.c0;
+    const uint8_t *img_end = g.img + (int64_t)(g.h - 1) * g.stride + (int64_t)g.w * C;
+    const int iy0 = ty * tg.TY, ix0 = tx * tg.TX;
+    const int ny_t = min(tg.TY, g.ny - iy0), nx_t = min(tg.TX, g.nx - ix0);
+    const int nref = ny_t * nx_t;
+
+    // MFMA row rho = lane % 32 holds group member mu_in of this step's 32 patches
+    const int rho = c32;
+    const int mu_in = 16 * ((rho >> 2) & 1) + 4 * (rho >> 3) + (rho & 3);
+
+    for (int base = wave * G; base < nref; base += MW * G) {
+        const bool full = base + G <= nref;
+        auto ref_of = [&](int gi) -> int64_t {
+            const int t = min(base + gi, nref - 1);
+            return (int64_t)(iy0 + t / nx_t) * g.nx + (ix0 + t % nx_t);
+        };
+        // ---- this lane's patch: A operands of the forward products (pixel rows 2 sp + h) ----
+        v8h fa0[4], far[4], fai[4];
+        int off_in;   // region offset of the patch (for the aggregation, shared by lane shuffles)
+        {
+            const int64_t r_in = ref_of(mu_in / K);
+            const int32_t lin_in = idx[r_in * idx_stride + (mu_in % K)];
+            const int yin = lin_in / g.w, xin = lin_in % g.w;
+            off_in = (yin - r0) * tg.RP + (xin - c0);
+            if (h == 0 && (full || base + mu_in / K < nref)) atomicAdd(hist + off_in, 1);
+            const uint8_t *pin = g.img + (int64_t)yin * g.stride + (int64_t)xin * C;
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) {
+                uint32_t wv[2 * C];
+                load_row_u8<C>(pin + (int64_t)(2 * sp + h) * g.stride, img_end, wv);
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    if (C == 3) {
+                        const int R = byte_of(wv, 3 * b), Gc = byte_of(wv, 3 * b + 1), Bc = byte_of(wv, 3 * b + 2);
+                        fa0[sp][b] = (_Float16)(float)(R + Gc + Bc);
+                        far[sp][b] = (_Float16)(float)(2 * R - Gc - Bc);
+                        fai[sp][b] = (_Float16)(float)(Bc - Gc);
+                    } else {
+                        fa0[sp][b] = (_Float16)(float)byte_of(wv, b);
+                    }
+                }
+            }
+        }
+        // ---- thresholds of the groups this lane half holds ----
+        float tau_l[16 / KL];
+        bool guard_l[16 / KL];
+#pragma unroll
+        for (int gs = 0; gs < 16 / KL; ++gs) {
+            const int gi = K == 32 ? 0 : (16 * h + gs * KL) / K;
+            const bool valid = base + gi < nref;
+            const double tau = tau_ref[ref_of(gi)] * tau_mul;
+            tau_l[gs] = valid ? (float)tau : __builtin_inff();
+            guard_l[gs] = valid && tau > (double)MGUARD;
+        }
+
+        v16f out[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) out[t] = (v16f){};
+
+        // two passes over the coefficient positions 32 tp + c (tp = 0, 1)
+#pragma unroll 1
+        for (int tp = 0; tp < 2; ++tp) {
+            // inverse fragments of the first chunk, fetched early (global, L2-resident)
+            v8h bh[8], bl[8];
+#pragma unroll
+            for (int ss = 0; ss < 2; ++ss)
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int pr = pair_of<C>(t, 2 * tp + ss);
+                    bh[ss * 2 + t] = ldfrag(FG, 1, 0, pr, NPAIR, lane);
+                    bl[ss * 2 + t] = ldfrag(FG, 1, 1, pr, NPAIR, lane);
+                }
+            // ---- forward products for the tiles (slice, tp), fragments from LDS ----
+            v16f acc[C];
+#pragma unroll
+            for (int sl = 0; sl < C; ++sl) acc[sl] = (v16f){};
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) {
+                const int p0 = pair_of<C>(tp, sp);
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fa0[sp], FL[(0 * NPAIR + p0) * 64 + lane], acc[0], 0, 0, 0);
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fa0[sp], FL[(1 * NPAIR + p0) * 64 + lane], acc[0], 0, 0, 0);
+                if (C == 3) {
+#pragma unroll
+                    for (int sl = 1; sl < C; ++sl) {
+                        const int t = 2 * sl + tp;
+                        const int pr = pair_of<C>(t, 4 + sp), pi = pair_of<C>(t, 8 + sp);
+                        acc[sl] = __builtin_amdgcn_mfma_f32_32x32x16_f16(far[sp], FL[(0 * NPAIR + pr) * 64 + lane], acc[sl], 0, 0, 0);
+                        acc[sl] = __builtin_amdgcn_mfma_f32_32x32x16_f16(far[sp], FL[(1 * NPAIR + pr) * 64 + lane], acc[sl], 0, 0, 0);
+                        acc[sl] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fai[sp], FL[(0 * NPAIR + pi) * 64 + lane], acc[sl], 0, 0, 0);
+                        acc[sl] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fai[sp], FL[(1 * NPAIR + pi) * 64 + lane], acc[sl], 0, 0, 0);
+                    }
+                }
+            }
+            // ---- inverse channel DFT: (s0', re', im') -> S0, S1, S2 ----
+            if (C == 3) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float s0 = acc[0][r], re = acc[1][r], im = acc[2][r];
+                    const float t0 = s0 - re;
+                    acc[0][r] = s0 + 2.f * re;
+                    acc[1][r] = t0 - im;
+                    acc[2][r] = t0 + im;
+                }
+            }
+
+            // ---- Haar along the group; threshold; guard-band values kept for now ----
+            uint32_t nearbits[C];
+#pragma unroll
+            for (int sl = 0; sl < C; ++sl) {
+                float v[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) v[r] = acc[sl][r];
+#pragma unroll
+                for (int st = 1; st < KL; st <<= 1)
+#pragma unroll
+                    for (int i = 0; i < 16; i += 2 * st) {
+                        const float a = v[i], b = v[i + st];
+                        v[i] = a + b;
+                        v[i + st] = a - b;
+                    }
+                if (K == 32) {
+                    const float o = swap_half(v[0]);
+                    v[0] = h ? o - v[0] : v[0] + o;
+                }
+                uint32_t nb = 0;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int l = haar_level<K>(r);
+                    const float sc = l == 1 ? 1.41421356237309505f : (l == 2 ? 2.f : (l == 3 ? 2.82842712474619010f
+                                     : (l == 4 ? 4.f : 5.65685424949238019f)));
+                    const float inv = l == 1 ? 0.5f : (l == 2 ? 0.25f : (l == 3 ? 0.125f : (l == 4 ? 0.0625f : 0.03125f)));
+                    const int gs = r / KL;
+                    const float tl = tau_l[gs] * sc;
+                    const float a = fabsf(v[r]);
+                    const bool near = guard_l[gs] && fabsf(a - tl) < MGUARD * sc;
+                    nb |= (uint32_t)near << r;
+                    v[r] = (a >= tl || near) ? v[r] * inv : 0.f;
+                }
+                nearbits[sl] = nb;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[sl][r] = v[r];
+            }
+
+            // ---- FP64 re-decision of the coefficients inside the guard band (rare) ----
+            bool any_near = false;
+#pragma unroll
+            for (int sl = 0; sl < C; ++sl) any_near |= nearbits[sl] != 0;
+            if (__ballot(any_near)) {
+                if (lane == 0) sh.near_n[wave] = 0;
+                wave_lds_fence();
+                uint32_t kill[C];
+#pragma unroll
+                for (int sl = 0; sl < C; ++sl) {
+                    kill[sl] = 0;
+                    uint32_t bits = nearbits[sl];
+                    while (bits) {
+                        const int r = __builtin_ctz(bits);
+                        bits &= bits - 1;
+                        const int e = atomicAdd(&sh.near_n[wave], 1);
+                        const int gi = K == 32 ? 0 : (16 * h + r) / K;
+                        if (e < MNEAR) {
+                            sh.near_a[wave][e] = lane | (sl << 6) | (r << 9) | (gi << 13);
+                            sh.near_b[wave][e] = haar_row<K>(r, h) | ((32 * (2 * sl + tp) + c32) << 8);
+                        } else {   // list full: the FP32 value decides
+                            const int l = haar_level<K>(r);
+                            const float sc = l == 1 ? 1.41421356237309505f : (l == 2 ? 2.f : (l == 3 ? 2.82842712474619010f
+                                             : (l == 4 ? 4.f : 5.65685424949238019f)));
+                            const float inv = 1.f / (float)(1 << l);
+                            float vr = 0.f;
+#pragma unroll
+                            for (int rr = 0; rr < 16; ++rr) vr = rr == r ? acc[sl][rr] : vr;
+                            float tauv = tau_l[0];
+#pragma unroll
+                            for (int gs = 0; gs < 16 / KL; ++gs) tauv = gs == r / KL ? tau_l[gs] : tauv;
+                            if (!(fabsf(vr) >= tauv * sc * inv)) kill[sl] |= 1u << r;
+                        }
+                    }
+                }
+                wave_lds_fence();
+                const int n_all = sh.near_n[wave];
+                const int nn = min(n_all, MNEAR);
+                if (lane == 0) {
+                    atomicAdd(guard_count, (unsigned long long)nn);
+                    if (n_all > nn) atomicAdd(guard_count + 1, (unsigned long long)(n_all - nn));
+                }
+                for (int e = 0; e < nn; ++e) {
+                    const int ia = sh.near_a[wave][e], ib = sh.near_b[wave][e];
+                    const int gi = (ia >> 13) & 7, k = ib & 255, q = ib >> 8;
+                    const int64_t rr = ref_of(gi);
+                    double part = 0.0;
+                    for (int p = lane; p < P; p += 64) {
+                        const int ch = p / 64, i = (p / 8) % 8, j = p % 8;
+                        double accp = 0.0;
+                        for (int m = 0; m < K; ++m) {
+                            const double w = haar_w(k, m, K);
+                            if (w == 0.0) continue;
+                            const int32_t l2 = idx[rr * idx_stride + m];
+                            accp += w * (double)g.img[(int64_t)(l2 / g.w + i) * g.stride + (int64_t)(l2 % g.w + j) * C + ch];
+                        }
+                        part += T64[(int64_t)q * P + p] * accp;
+                    }
+                    const double sv = wave_sum64(part);
+                    const double tau = tau_ref[rr] * tau_mul;
+                    if (lane == 0) sh.near_kill[wave][e] = !(fabs(sv) >= tau);
+                }
+                wave_lds_fence();
+                for (int e = 0; e < nn; ++e) {
+                    const int ia = sh.near_a[wave][e];
+                    if ((ia & 63) == lane && sh.near_kill[wave][e]) {
+                        const int sl = (ia >> 6) & 7, r = (ia >> 9) & 15;
+#pragma unroll
+                        for (int ss = 0; ss < C; ++ss)
+                            if (ss == sl) kill[ss] |= 1u << r;
+                    }
+                }
+#pragma unroll
+                for (int sl = 0; sl < C; ++sl)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        if ((kill[sl] >> r) & 1u) acc[sl][r] = 0.f;
+            }
+
+            // ---- inverse Haar (transposed butterfly network) ----
+#pragma unroll
+            for (int sl = 0; sl < C; ++sl) {
+                float v[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) v[r] = acc[sl][r];
+                if (K == 32) {
+                    const float o = swap_half(v[0]);
+                    v[0] = h ? o - v[0] : v[0] + o;
+                }
+#pragma unroll
+                for (int st = KL / 2; st >= 1; st >>= 1)
+#pragma unroll
+                    for (int i = 0; i < 16; i += 2 * st) {
+                        const float a = v[i], b = v[i + st];
+                        v[i] = a + b;
+                        v[i + st] = a - b;
+                    }
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[sl][r] = v[r];
+            }
+            // ---- channel DFT of the kept coefficients: s0, 2 re, d ----
+            if (C == 3) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float a = acc[0][r], b = acc[1][r], cc = acc[2][r];
+                    const float u = b + cc;
+                    acc[0][r] = a + u;
+                    acc[1][r] = 2.f * a - u;
+                    acc[2][r] = cc - b;
+                }
+            }
+
+            // ---- inverse products: each 32-coefficient tile is transposed through LDS ----
+#pragma unroll
+            for (int sl = 0; sl < C; ++sl) {
+                const int j = 2 * sl + tp;   // tile of the k dimension
+                constexpr int NTMAX = C == 3 ? 4 : 2;
+                const int tlo = sl == 0 ? 0 : 2, ntile = sl == 0 ? 2 : 4;
+                // prefetch the next chunk's fragments
+                v8h nh[2 * NTMAX], nl[2 * NTMAX];
+                if (sl + 1 < C) {
+                    const int jn = 2 * (sl + 1) + tp;
+#pragma unroll
+                    for (int ss = 0; ss < 2; ++ss)
+#pragma unroll
+                        for (int tt = 0; tt < 4; ++tt) {
+                            const int pr = pair_of<C>(2 + tt, 2 * jn + ss);
+                            nh[ss * 4 + tt] = ldfrag(FG, 1, 0, pr, NPAIR, lane);
+                            nl[ss * 4 + tt] = ldfrag(FG, 1, 1, pr, NPAIR, lane);
+                        }
+                }
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float v = acc[sl][r];
+                    const _Float16 hi = (_Float16)v;
+                    const _Float16 lo = (_Float16)(v - (float)hi);
+                    xbuf[(16 * h + r) * XS + c32] =
+                        (uint32_t)__builtin_bit_cast(uint16_t, hi) | ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
+                }
+                wave_lds_fence();
+#pragma unroll
+                for (int ss = 0; ss < 2; ++ss) {
+                    v8h ahi, alo;
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) {
+                        const uint32_t wd = xbuf[mu_in * XS + 16 * ss + 8 * h + jj];
+                        ahi[jj] = __builtin_bit_cast(_Float16, (uint16_t)(wd & 0xffffu));
+                        alo[jj] = __builtin_bit_cast(_Float16, (uint16_t)(wd >> 16));
+                    }
+#pragma unroll
+                    for (int tt = 0; tt < ntile; ++tt) {
+                        const int t = tlo + tt;
+                        const int fi = ss * ntile + tt;
+                        out[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, bh[fi], out[t], 0, 0, 0);
+                        out[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, bl[fi], out[t], 0, 0, 0);
+                        out[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, bh[fi], out[t], 0, 0, 0);
+                    }
+                }
+                wave_lds_fence();
+                if (sl + 1 < C) {
+#pragma unroll
+                    for (int f = 0; f < 8; ++f) {
+                        bh[f] = nh[f];
+                        bl[f] = nl[f];
+                    }
+                }
+            }
+        }
+
+        // ---- aggregation into the LDS region ----
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int mu = 16 * h + r;
+            const int gi = mu / K;
+            // patch offset from the lane that loaded member mu (MFMA row 8(r/4) + 4h + r%4)
+            const int off = __shfl(off_in, 8 * (r >> 2) + 4 * h + (r & 3));
+            if (!full && base + gi >= nref) continue;
+#pragma unroll
+            for (int tq = 0; tq < 2; ++tq) {
+                const int p = 32 * tq + c32, a = p >> 3, b = p & 7;
+                int *dst = iregion + off + a * tg.RP + b;
+                if (C == 3) {
+                    const float p0 = out[tq][r], pr = out[2 + tq][r], pi = out[4 + tq][r];
+                    const float t0 = p0 - pr;
+                    atomicAdd(dst, to_fixed(p0 + 2.f * pr, fscale));
+                    atomicAdd(dst + plane, to_fixed(t0 - pi, fscale));
+                    atomicAdd(dst + 2 * plane, to_fixed(t0 + pi, fscale));
+                } else {
+                    atomicAdd(dst, to_fixed(out[tq][r], fscale));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // coverage count of every pixel: 8 x 8 box sum of the patch histogram (separable, in place,
+    // one row then one column per thread; prev[] holds the histogram values leaving the window)
+    for (int y = tid; y < tg.RH; y += MW * 64) {
+        int *row = hist + y * tg.RP;
+        int prev[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int run = 0;
+        for (int x0 = 0; x0 < tg.RW; x0 += 8) {
+            int cur[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) cur[i] = x0 + i < tg.RW ? row[x0 + i] : 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                run += cur[i] - prev[i];
+                if (x0 + i < tg.RW) row[x0 + i] = run;
+                prev[i] = cur[i];
+            }
+        }
+    }
+    __syncthreads();
+    for (int x = tid; x < tg.RW; x += MW * 64) {
+        int prev[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int run = 0;
+        for (int y0 = 0; y0 < tg.RH; y0 += 8) {
+            int cur[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) cur[i] = y0 + i < tg.RH ? hist[(y0 + i) * tg.RP + x] : 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                run += cur[i] - prev[i];
+                if (y0 + i < tg.RH) hist[(y0 + i) * tg.RP + x] = run;
+                prev[i] = cur[i];
+            }
+        }
+    }
+    __syncthreads();
+    float *dst = regions + (int64_t)tile * relems;
+    const float unscale = 1.f / fscale;
+    for (int e = tid; e < relems; e += MW * 64) dst[e] = (float)iregion[e] * (e < C * plane ? unscale : 1.f);
+}
+
+// Copies the forward fragment table into LDS (once per workgroup).
+template <int C>
+__device__ inline void stage_ftab(const v8h *__restrict__ FG, v8h *FL) {
+    constexpr int N = Frag<C>::NPAIR * 2 * 64;   // dir 0: [term][pair][lane]
+    for (int e = threadIdx.x; e < N; e += MW * 64) FL[e] = FG[e];
+    __syncthreads();
+}
+
+// Persistent over the tiles of one image: workgroup b takes tiles b, b + grid, ... in an
+// XCD-aware order (consecutive ids go round-robin over the 8 XCDs; with grid a multiple of 8
+// each workgroup stays in one class, whose tiles form a contiguous run).
+template <int C, int K>
+__global__ __launch_bounds__(MW * 64) void filter_mfma_kernel(ImageGeom g, TileGeom tg, const v8h *__restrict__ F,
+                                                             const double *__restrict__ T64,
+                                                             const int32_t *__restrict__ idx,
+                                                             const double *__restrict__ tau_ref,
+                                                             float *__restrict__ regions,
+                                                             unsigned long long *__restrict__ guard_count) {
+    extern __shared__ __align__(16) float smem[];
+    __shared__ MfmaShared sh;
+    v8h *FL = reinterpret_cast<v8h *>(smem);
+    float *region = smem + ftab_bytes<C>() / 4;
+    uint32_t *xb = reinterpret_cast<uint32_t *>(region + region_elems(tg, C));
+    stage_ftab<C>(F, FL);
+    const int n_tiles = tg.tiles_y * tg.tiles_x;
+    const int per = (n_tiles + 7) / 8;
+    for (int v = blockIdx.x; v < 8 * per; v += gridDim.x) {
+        const int tile = (v & 7) * per + (v >> 3);
+        if (tile >= n_tiles) continue;
+        filter_tile_mfma<C, K>(g, tg, FL, F, T64, idx, K, tau_ref, 1.0, regions, guard_count, tile, region, xb, sh);
+        __syncthreads();
+    }
+}
+
+template <int C, int K>
+__global__ __launch_bounds__(MW * 64) void filter_mfma_kernel_batched(const BatchItem *__restrict__ items,
+                                                                     int n_items, const int *__restrict__ unit_start,
+                                                                     const v8h *__restrict__ F,
+                                                                     const double *__restrict__ T64,
+                                                                     unsigned long long *__restrict__ guard_count,
+                                                                     int *__restrict__ queue) {
+    extern __shared__ __align__(16) float smem[];
+    __shared__ MfmaShared sh;
+    __shared__ int s_u;
+    v8h *FL = reinterpret_cast<v8h *>(smem);
+    float *region = smem + ftab_bytes<C>() / 4;
+    stage_ftab<C>(F, FL);
+    const int total = unit_start[n_items];
+    for (;;) {
+        if (threadIdx.x == 0) s_u = atomicAdd(queue, 1);
+        __syncthreads();
+        const int u = s_u;
+        __syncthreads();
+        if (u >= total) break;
+        const int i = find_unit(unit_start, n_items, u);
+        const BatchItem it = items[i];
+        if (it.ksel && *it.ksel != K) continue;   // the image took the other group size (uniform per block)
+        uint32_t *xb = reinterpret_cast<uint32_t *>(region + region_elems(it.tg, C));
+        filter_tile_mfma<C, K>(it.g, it.tg, FL, F, T64, it.idx, it.idx_stride, it.tau, it.tau_mul, it.regions,
+                               guard_count, u - unit_start[i], region, xb, sh);
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+int filter_mfma_lds_bytes(const TileGeom &tg, int C) {
+    return (C == 3 ? ftab_bytes<3>() : ftab_bytes<1>()) + region_elems(tg, C) * 4 + MW * XWORDS * 4;
+}
+
+int filter_mfma_group_bytes(int C) { return (C == 3 ? ftab_bytes<3>() : ftab_bytes<1>()) + MW * XWORDS * 4; }
+
+int filter_mfma_static_bytes() { return (int)sizeof(MfmaShared) + 16; }
+
+template <int C, int K>
+static hipError_t launch_mfma_t(const ImageGeom &g, const TileGeom &tg, const BasisDev &b, const int32_t *idx,
+                                const double *tau_ref, float *regions, unsigned long long *gc, hipStream_t st) {
+    const int n_tiles = tg.tiles_y * tg.tiles_x;
+    const int lds = filter_mfma_lds_bytes(tg, C);
+    hipError_t e = prepare_dynamic_lds((const void *)filter_mfma_kernel<C, K>, lds, (int)sizeof(MfmaShared));
+    if (e != hipSuccess) return e;
+    int dev = 0, n_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (n_cu < 8) n_cu = 8;
+    const int per = (n_tiles + 7) / 8;
+    const int grid = min(8 * per, (n_cu / 8) * 8);
+    hipLaunchKernelGGL((filter_mfma_kernel<C, K>), dim3(grid), dim3(MW * 64), lds, st, g, tg, (const v8h *)b.frag,
+                       b.T64, idx, tau_ref, regions, gc);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_mfma(const ImageGeom &g, const TileGeom &tg, int K, const BasisDev &b, const int32_t *idx,
+                              const double *tau_ref, float *regions, unsigned long long *gc, hipStream_t st) {
+    if (!b.frag) return hipErrorInvalidValue;
+#define HM_CASE(CC, KK) \
+    if (g.c == CC && K == KK) return launch_mfma_t<CC, KK>(g, tg, b, idx, tau_ref, regions, gc, st);
+    HM_CASE(1, 4) HM_CASE(1, 8) HM_CASE(1, 16) HM_CASE(1, 32)
+    HM_CASE(3, 4) HM_CASE(3, 8) HM_CASE(3, 16) HM_CASE(3, 32)
+#undef HM_CASE
+    return hipErrorInvalidValue;
+}
+
+template <int C, int K>
+static hipError_t launch_mfma_batched_t(const BatchItem *items, int n_items, const int *unit_start, int lds,
+                                        const BasisDev &b, unsigned long long *gc, int *queue, int grid,
+                                        hipStream_t st) {
+    hipError_t e = prepare_dynamic_lds((const void *)filter_mfma_kernel_batched<C, K>, lds,
+                                       (int)sizeof(MfmaShared) + 16);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((filter_mfma_kernel_batched<C, K>), dim3(grid), dim3(MW * 64), lds, st, items, n_items,
+                       unit_start, (const v8h *)b.frag, b.T64, gc, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_mfma_batched(int C, int K, const BatchItem *items, int n_items, const int *unit_start,
+                                      int lds, const BasisDev &b, unsigned long long *gc, int *queue, int grid,
+                                      hipStream_t st) {
+    if (!b.frag) return hipErrorInvalidValue;
+#define HMB_CASE(CC, KK) \
+    if (C == CC && K == KK) return launch_mfma_batched_t<CC, KK>(items, n_items, unit_start, lds, b, gc, queue, grid, st);
+    HMB_CASE(1, 4) HMB_CASE(1, 8) HMB_CASE(1, 16) HMB_CASE(1, 32)
+    HMB_CASE(3, 4) HMB_CASE(3, 8) HMB_CASE(3, 16) HMB_CASE(3, 32)
+#undef HMB_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace htsvd

@@ -1,9 +1,11 @@
 """The batched persistent launch (one work-queue launch per stage for a whole batch, optionally
 replayed from a hipGraph) vs the FP64 oracle and vs the one-image entry points (needs an MI355X).
 
-Filtering adds group estimates into LDS with float atomics, so two runs of the same image can
-differ in the order of those additions; comparisons between two GPU runs therefore allow 1e-3
-on the 0..255 scale, and comparisons with the oracle use the pixel parity bar."""
+Filtering accumulates the reconstructed patches in LDS as int32 fixed point (units of 2^-FS,
+FS >= 10 chosen per tiling so that no sum can overflow), so two runs
+with the same tiling give identical results, and runs with different tilings differ by at most
+the rounding of one fixed-point unit per run (2 * 2^-(FS+1) on the 0..255 scale).  Comparisons
+between GPU runs allow RUN_TOL; comparisons with the oracle use the pixel parity bar."""
 import numpy as np
 import pytest
 
@@ -14,7 +16,7 @@ from helpers import assert_pixel_parity
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-RUN_TOL = 1e-3
+RUN_TOL = 2e-3
 
 
 @pytest.fixture(scope="module")
