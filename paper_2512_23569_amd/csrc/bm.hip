@@ -6,7 +6,7 @@
 // Distances are squared Euclidean and exact.  Algorithm 1 "Grouping" keeps the K
 // smallest, ordered by (distance, row, column).
 //
-// Mapping.  One workgroup (4 waves) owns a 4x4 tile of references.  The union of their
+// Mapping.  One workgroup (16 waves, four per SIMD) owns a 4x4 tile of references.  The union of their
 // search windows (at most 64x64 candidate positions) is staged in LDS as
 //   - the shifted green (or gray) plane x-128 in int8, in 4 byte-shifted copies so any
 //     8-pixel row segment is a 4-byte-aligned pair of dwords, and
@@ -16,7 +16,7 @@
 // v_mfma_f32_16x16x32_f16 for the sum plane (all partial sums are integers < 2^24, so the
 // fp32 accumulation is exact).  Distances of each reference land in an LDS table indexed
 // by the raster position inside its clipped window, so (distance, position) orders like
-// (distance, row, column).  Each wave then selects the K smallest keys of 4 references:
+// (distance, row, column).  Each wave then selects the K smallest keys of one reference:
 // the K-th smallest of the 64 lane minima bounds the answer from above, the keys under
 // that bound are compacted and sorted with a wave bitonic network.
 #include "common.h"
@@ -30,6 +30,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int NREF = REF_TILE * REF_TILE;  // 16
+constexpr int BMW = 16;                    // wavefronts per workgroup (four per SIMD)
+constexpr int BMT = BMW * 64;
 constexpr int SEL_CAP = 512;               // >= K * ceil(MAX_CAND / 64) for K <= 32
 
 struct TileInfo {
@@ -152,9 +154,9 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
     }
     // Eq. 9 branch per reference from the raw channel norms (16 threads per reference).
     if (g.c == 3) {
-        const int i = tid >> 4, sub = tid & 15;
+        const int i = tid >> 4, sub = tid & 15;   // 16 threads per reference (the first 256 threads)
         int nr = 0, ng = 0, nb = 0;
-        if (ti.ry[i] >= 0) {
+        if (i < NREF && ti.ry[i] >= 0) {
             for (int p = sub; p < PS * PS; p += 16) {
                 const uint8_t *px = g.img + (int64_t)(ti.ry[i] + p / PS) * g.stride + (int64_t)(ti.rx[i] + p % PS) * 3;
                 nr += px[0] * px[0]; ng += px[1] * px[1]; nb += px[2] * px[2];
@@ -164,7 +166,7 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
         for (int o = 8; o > 0; o >>= 1) {
             nr += __shfl_xor(nr, o); ng += __shfl_xor(ng, o); nb += __shfl_xor(nb, o);
         }
-        if (sub == 0) {
+        if (sub == 0 && i < NREF) {
             const int64_t mx = nr > nb ? nr : nb;
             ti.green[i] = (int64_t)mp.gnum * mp.gnum * ng >= (int64_t)mp.gden * mp.gden * mx ? 1 : 0;
         }
@@ -189,7 +191,7 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
     const int plane16 = L.rows * L.pitch16;
 
     // ---- stage the shifted planes ----
-    for (int e = tid; e < prow * pcol; e += 256) {
+    for (int e = tid; e < prow * pcol; e += BMT) {
         const int r = e / pcol, col = e % pcol;
         const uint8_t *px = g.img + (int64_t)(uy0 + r) * g.stride + (int64_t)(ux0 + col) * g.c;
         int v8, vs = 0;
@@ -214,7 +216,7 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
     {
         int32_t *rs8 = reinterpret_cast<int32_t *>(tab);          // prow x uw, tab is free now
         int32_t *rs16 = rs8 + prow * uw;
-        for (int e = tid; e < prow * uw; e += 256) {
+        for (int e = tid; e < prow * uw; e += BMT) {
             const int r = e / uw, col = e % uw;
             int a = 0, s = 0;
 #pragma unroll
@@ -230,7 +232,7 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
             rs16[e] = s;
         }
         __syncthreads();
-        for (int e = tid; e < uh * uw; e += 256) {
+        for (int e = tid; e < uh * uw; e += BMT) {
             const int r = e / uw, col = e % uw;
             int a = 0, s = 0;
 #pragma unroll
@@ -286,7 +288,7 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
         }
         const int nU = uh * uw;
         const int nchunks = (nU + 15) >> 4;
-        for (int chunk = wave; chunk < nchunks; chunk += 4) {
+        for (int chunk = wave; chunk < nchunks; chunk += BMW) {
             const int j = chunk * 16 + i16;
             const int jj = j < nU ? j : 0;
             const int cr = jj / uw, cc = jj % uw;
@@ -331,7 +333,7 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
     // ---- top-K per reference ----
     uint64_t *sel = reinterpret_cast<uint64_t *>(smem + L.off_sel) + wave * SEL_CAP;
     const int K = mp.K;
-    for (int ii = wave; ii < NREF; ii += 4) {
+    for (int ii = wave; ii < NREF; ii += BMW) {
         if (ti.ry[ii] < 0) continue;
         const int n = ti.wh[ii] * ti.ww[ii];
         const uint32_t *row = tab + ii * MAX_CAND;
@@ -378,7 +380,7 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
     }
 }
 
-__global__ __launch_bounds__(256) void bm_kernel(ImageGeom g, MethodParams mp, int tiles_x, int n_tiles,
+__global__ __launch_bounds__(BMT) void bm_kernel(ImageGeom g, MethodParams mp, int tiles_x, int n_tiles,
                                                  BmLds L, int32_t *__restrict__ idx_out,
                                                  int32_t *__restrict__ dist_out) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -393,7 +395,7 @@ __global__ __launch_bounds__(256) void bm_kernel(ImageGeom g, MethodParams mp, i
 }
 
 // Persistent form over many images: each workgroup pulls (image, tile) units from a queue.
-__global__ __launch_bounds__(256) void bm_kernel_batched(const BatchItem *__restrict__ items, int n_items,
+__global__ __launch_bounds__(BMT) void bm_kernel_batched(const BatchItem *__restrict__ items, int n_items,
                                                          const int *__restrict__ unit_start, BmLds L,
                                                          int *__restrict__ queue) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -427,7 +429,7 @@ BmLds bm_lds_layout(int uh_max, int uw_max) {
     L.off_n16 = off; off += uh_max * uw_max * 4;
     off = (off + 15) & ~15;
     // the selection scratch reuses the plane/norm region once the distances are in the table
-    const int sel_bytes = 4 * SEL_CAP * 8;
+    const int sel_bytes = BMW * SEL_CAP * 8;
     int region = off;
     L.off_sel = 0;
     if (region < sel_bytes) region = sel_bytes;
@@ -456,7 +458,7 @@ hipError_t launch_block_match(const ImageGeom &g, const MethodParams &mp, int32_
     if (e != hipSuccess) return e;
     // round the grid up to a multiple of 8 so the XCD remap is a bijection onto [0, 8*per)
     const int per = (n_tiles + 7) / 8;
-    hipLaunchKernelGGL(bm_kernel, dim3(8 * per), dim3(256), L.total, st, g, mp, tiles_x, n_tiles, L, idx, dist);
+    hipLaunchKernelGGL(bm_kernel, dim3(8 * per), dim3(BMT), L.total, st, g, mp, tiles_x, n_tiles, L, idx, dist);
     return hipGetLastError();
 }
 
@@ -470,7 +472,7 @@ hipError_t launch_block_match_batched(const BatchItem *items, int n_items, const
     BmLds L = bm_lds_layout(uh, uw);
     hipError_t e = prepare_dynamic_lds((const void *)bm_kernel_batched, L.total, (int)sizeof(TileInfo) + 16);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bm_kernel_batched, dim3(grid), dim3(256), L.total, st, items, n_items, unit_start, L, queue);
+    hipLaunchKernelGGL(bm_kernel_batched, dim3(grid), dim3(BMT), L.total, st, items, n_items, unit_start, L, queue);
     return hipGetLastError();
 }
 
