@@ -145,9 +145,13 @@ __device__ inline int haar_row(int r, int h) {
 
 // Contribution in fixed point (round to nearest even); |v| is clamped to 1024 (four times the
 // 8-bit range) so that no region sum can overflow (see the accumulation shift of the tiling).
+// The scale is applied here, after the fp16 products, whose range it would exceed.
 __device__ inline int to_fixed(float v, float scale) {
     return __float2int_rn(fminf(fmaxf(v, -1024.f), 1024.f) * scale);
 }
+
+// 2^e for a small integer exponent (exact).
+__device__ inline float exp2i(int e) { return __int_as_float((e + 127) << 23); }
 
 // LDS bytes of the forward fragment table (kept in LDS for the whole kernel).
 template <int C>
@@ -196,6 +200,8 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
     const int ny_t = min(tg.TY, g.ny - iy0), nx_t = min(tg.TX, g.nx - ix0);
     const int nref = ny_t * nx_t;
 
+    // pixel of patch position 32 tq + c held by this lane in the output layout
+    const int lane_off[2] = {(c32 >> 3) * tg.RP + (c32 & 7), (4 + (c32 >> 3)) * tg.RP + (c32 & 7)};
     // MFMA row rho = lane % 32 holds group member mu_in of this step's 32 patches
     const int rho = c32;
     const int mu_in = 16 * ((rho >> 2) & 1) + 4 * (rho >> 3) + (rho & 3);
@@ -234,15 +240,29 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             }
         }
         // ---- thresholds of the groups this lane half holds ----
-        float tau_l[16 / KL];
-        bool guard_l[16 / KL];
+        // per (group slot, butterfly count l): keep-or-undecided above lo, undecided below hi
+        // (the guard band (tau - g, tau + g) scaled by 2^(l/2)); without a guard band lo is the
+        // float just below the threshold and hi = lo (empty band)
+        constexpr int NS = 16 / KL;
+        constexpr int LK = K == 32 ? 5 : (K == 16 ? 4 : (K == 8 ? 3 : 2));
+        float tau_l[NS], lo_t[NS][LK + 1], hi_t[NS][LK + 1];
 #pragma unroll
-        for (int gs = 0; gs < 16 / KL; ++gs) {
+        for (int gs = 0; gs < NS; ++gs) {
             const int gi = K == 32 ? 0 : (16 * h + gs * KL) / K;
             const bool valid = base + gi < nref;
             const double tau = tau_ref[ref_of(gi)] * tau_mul;
             tau_l[gs] = valid ? (float)tau : __builtin_inff();
-            guard_l[gs] = valid && tau > (double)MGUARD;
+            const bool guard = valid && tau > (double)MGUARD;
+#pragma unroll
+            for (int l = 1; l <= LK; ++l) {
+                const float sc = l == 1 ? 1.41421356237309505f : (l == 2 ? 2.f : (l == 3 ? 2.82842712474619010f
+                                 : (l == 4 ? 4.f : 5.65685424949238019f)));
+                const float tl = tau_l[gs] * sc;
+                // a >= tl  <=>  a > (the float just below tl); tl = 0 keeps everything
+                const float below = tl > 0.f ? __int_as_float(__float_as_int(tl) - 1) : -1.f;
+                lo_t[gs][l] = guard ? tl - MGUARD * sc : below;
+                hi_t[gs][l] = guard ? tl + MGUARD * sc : lo_t[gs][l];
+            }
         }
 
         v16f out[NT];
@@ -296,7 +316,7 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             }
 
             // ---- Haar along the group; threshold; guard-band values kept for now ----
-            uint32_t nearbits[C];
+            bool any_near = false;
 #pragma unroll
             for (int sl = 0; sl < C; ++sl) {
                 float v[16];
@@ -314,30 +334,35 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                     const float o = swap_half(v[0]);
                     v[0] = h ? o - v[0] : v[0] + o;
                 }
-                uint32_t nb = 0;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int l = haar_level<K>(r);
-                    const float sc = l == 1 ? 1.41421356237309505f : (l == 2 ? 2.f : (l == 3 ? 2.82842712474619010f
-                                     : (l == 4 ? 4.f : 5.65685424949238019f)));
-                    const float inv = l == 1 ? 0.5f : (l == 2 ? 0.25f : (l == 3 ? 0.125f : (l == 4 ? 0.0625f : 0.03125f)));
                     const int gs = r / KL;
-                    const float tl = tau_l[gs] * sc;
                     const float a = fabsf(v[r]);
-                    const bool near = guard_l[gs] && fabsf(a - tl) < MGUARD * sc;
-                    nb |= (uint32_t)near << r;
-                    v[r] = (a >= tl || near) ? v[r] * inv : 0.f;
+                    const bool keep = a > lo_t[gs][l];
+                    any_near |= keep && a < hi_t[gs][l];
+                    v[r] = keep ? v[r] * exp2i(-l) : 0.f;   // kept values scaled by 2^-l (inverse Haar)
                 }
-                nearbits[sl] = nb;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[sl][r] = v[r];
             }
 
             // ---- FP64 re-decision of the coefficients inside the guard band (rare) ----
-            bool any_near = false;
-#pragma unroll
-            for (int sl = 0; sl < C; ++sl) any_near |= nearbits[sl] != 0;
             if (__ballot(any_near)) {
+                // rebuild the band membership from the kept (scaled) values
+                uint32_t nearbits[C];
+#pragma unroll
+                for (int sl = 0; sl < C; ++sl) {
+                    uint32_t nb = 0;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int l = haar_level<K>(r);
+                        const int gs = r / KL;
+                        const float a = fabsf(acc[sl][r]) * exp2i(l);
+                        nb |= (uint32_t)(a > lo_t[gs][l] && a < hi_t[gs][l]) << r;
+                    }
+                    nearbits[sl] = nb;
+                }
                 if (lane == 0) sh.near_n[wave] = 0;
                 wave_lds_fence();
                 uint32_t kill[C];
@@ -357,14 +382,13 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                             const int l = haar_level<K>(r);
                             const float sc = l == 1 ? 1.41421356237309505f : (l == 2 ? 2.f : (l == 3 ? 2.82842712474619010f
                                              : (l == 4 ? 4.f : 5.65685424949238019f)));
-                            const float inv = 1.f / (float)(1 << l);
                             float vr = 0.f;
 #pragma unroll
                             for (int rr = 0; rr < 16; ++rr) vr = rr == r ? acc[sl][rr] : vr;
                             float tauv = tau_l[0];
 #pragma unroll
-                            for (int gs = 0; gs < 16 / KL; ++gs) tauv = gs == r / KL ? tau_l[gs] : tauv;
-                            if (!(fabsf(vr) >= tauv * sc * inv)) kill[sl] |= 1u << r;
+                            for (int gs = 0; gs < NS; ++gs) tauv = gs == r / KL ? tau_l[gs] : tauv;
+                            if (!(fabsf(vr) * exp2i(l) >= tauv * sc)) kill[sl] |= 1u << r;
                         }
                     }
                 }
@@ -512,8 +536,7 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             if (!full && base + gi >= nref) continue;
 #pragma unroll
             for (int tq = 0; tq < 2; ++tq) {
-                const int p = 32 * tq + c32, a = p >> 3, b = p & 7;
-                int *dst = iregion + off + a * tg.RP + b;
+                int *dst = iregion + off + lane_off[tq];
                 if (C == 3) {
                     const float p0 = out[tq][r], pr = out[2 + tq][r], pi = out[4 + tq][r];
                     const float t0 = p0 - pr;
