@@ -46,6 +46,8 @@ def _L():
         lib.orc_patch_inverse.argtypes = [p, p, i32, i32, p, p]
         lib.orc_gcp_green.argtypes = [p, i64, i32, i32, i32, i32, i32, i32]
         lib.orc_block_match.argtypes = [p, i32, i32, i32, i64, i32, i32, i32, i32, i32, i32, p, p, i32]
+        lib.orc_block_match_list.argtypes = [p, i32, i32, i32, i64, i32, i32, i32, i32, i32, i32, p, i64, p, p,
+                                             i32]
         lib.orc_denoise.argtypes = [p, i32, i32, i32, i64, i32, i32, i32, i32, i32, i32, p, p, p, p, dbl, p,
                                     i32, i64, i64]
         _lib = lib
@@ -171,6 +173,20 @@ def block_match(img: np.ndarray, ps: int, s: int, W: int, K: int, gnum: int = 6,
     idx = np.zeros((n_ref, K), dtype=np.int32)
     dist = np.zeros((n_ref, K), dtype=np.int64)
     _check(L.orc_block_match(_ptr(a), h, w, c, w * c, ps, s, W, K, gnum, gden, _ptr(idx), _ptr(dist), nthreads))
+    return idx, dist
+
+
+def block_match_list(img: np.ndarray, refs, ps: int, s: int, W: int, K: int, gnum: int = 6, gden: int = 5,
+                     nthreads: int = 0):
+    """Groups of the listed references (raster indices into the reference grid), same rule
+    as block_match: (idx[len(refs), K], dist[len(refs), K])."""
+    a, h, w, c = _img3(img)
+    L = _L()
+    r = np.ascontiguousarray(np.asarray(refs, dtype=np.int64))
+    idx = np.zeros((r.size, K), dtype=np.int32)
+    dist = np.zeros((r.size, K), dtype=np.int64)
+    _check(L.orc_block_match_list(_ptr(a), h, w, c, w * c, ps, s, W, K, gnum, gden, _ptr(r), r.size, _ptr(idx),
+                                  _ptr(dist), nthreads))
     return idx, dist
 
 

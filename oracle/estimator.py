@@ -80,24 +80,26 @@ def patch_covariance(plane: np.ndarray, y0: int, y1: int, x0: int, x1: int, ps: 
     return s2 / n - np.outer(s1, s1) / (n * n)
 
 
-def sigma_est_tiles(img: np.ndarray, T: int = 128, ps: int = 8) -> np.ndarray:
-    """Plain sigma_est per sub-image: sqrt(mean over channels of the Chen tail variance)."""
+def sigma_est_tiles(img: np.ndarray, T: int = 128, ps: int = 8, tiles=None) -> np.ndarray:
+    """Plain sigma_est per sub-image: sqrt(mean over channels of the Chen tail variance).
+    With `tiles` (raster tile indices) only those entries are computed (the others are 0)."""
     a = img if img.ndim == 3 else img[:, :, None]
     h, w, c = a.shape
     nty, ntx = tile_grid(h, w, T)
     out = np.zeros(nty * ntx, dtype=np.float64)
-    for ty in range(nty):
-        for tx in range(ntx):
-            y0 = min(ty * T, h - ps)
-            y1 = min(ty * T + T - 1, h - ps)
-            x0 = min(tx * T, w - ps)
-            x1 = min(tx * T + T - 1, w - ps)
-            s2 = 0.0
-            for ch in range(c):
-                C = patch_covariance(a[:, :, ch], y0, y1, x0, x1, ps)
-                ev = np.linalg.eigvalsh(C)[::-1]
-                s2 += chen_tail_sigma2(ev)
-            out[ty * ntx + tx] = np.sqrt(max(s2 / c, 0.0))
+    todo = range(nty * ntx) if tiles is None else sorted(set(int(t) for t in tiles))
+    for t in todo:
+        ty, tx = divmod(t, ntx)
+        y0 = min(ty * T, h - ps)
+        y1 = min(ty * T + T - 1, h - ps)
+        x0 = min(tx * T, w - ps)
+        x1 = min(tx * T + T - 1, w - ps)
+        s2 = 0.0
+        for ch in range(c):
+            C = patch_covariance(a[:, :, ch], y0, y1, x0, x1, ps)
+            ev = np.linalg.eigvalsh(C)[::-1]
+            s2 += chen_tail_sigma2(ev)
+        out[t] = np.sqrt(max(s2 / c, 0.0))
     return out
 
 

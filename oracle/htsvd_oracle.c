@@ -372,6 +372,53 @@ int orc_block_match(const uint8_t *img, int h, int w, int c, int64_t stride, int
     return status;
 }
 
+/* Groups of the listed references only (raster indices into the reference grid); row i of
+ * idx/dist belongs to refs[i].  Same grouping as orc_block_match. */
+int orc_block_match_list(const uint8_t *img, int h, int w, int c, int64_t stride, int ps, int s, int W, int K,
+                         int gnum, int gden, const int64_t *refs, int64_t n, int32_t *idx, int64_t *dist,
+                         int nthreads)
+{
+    int err = check_common(h, w, c, stride, ps, s, W, K);
+    if (err) return err;
+    int *ys = (int *)malloc(sizeof(int) * (h / s + 2));
+    int *xs = (int *)malloc(sizeof(int) * (w / s + 2));
+    const int ny = orc_ref_grid(h, ps, s, ys), nx = orc_ref_grid(w, ps, s, xs);
+    bm_ctx_t m = {img, h, w, c, stride, ps, W, K, gnum, gden};
+    int status = ORC_OK;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+    {
+        cand_t *cand = (cand_t *)malloc(sizeof(cand_t) * W * W);
+        int32_t *gy = (int32_t *)malloc(sizeof(int32_t) * K), *gx = (int32_t *)malloc(sizeof(int32_t) * K);
+        int64_t *gd = (int64_t *)malloc(sizeof(int64_t) * K);
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t r = refs[i];
+            if (r < 0 || r >= (int64_t)ny * nx) {
+                status = ORC_EINVAL;
+                continue;
+            }
+            int e = group_one(&m, ys[r / nx], xs[r % nx], cand, gy, gx, gd);
+            if (e) {
+                status = e;
+                continue;
+            }
+            for (int k = 0; k < K; ++k) {
+                idx[i * K + k] = gy[k] * w + gx[k];
+                if (dist) dist[i * K + k] = gd[k];
+            }
+        }
+        free(cand); free(gy); free(gx); free(gd);
+    }
+    free(ys);
+    free(xs);
+    return status;
+}
+
 /* ---- Haar-tSVD denoising, Algorithm 1 ---------------------------------- */
 
 /* Denoises the image with per-reference thresholds tau_ref[r] (r = iy*nx+ix).

@@ -1,0 +1,147 @@
+"""Parity at the full workload sizes (needs an MI355X).
+
+Workloads: the 12 MP RGB image with Poisson-Gaussian noise in the configuration the benchmark
+times (reference stride 3, window 31, K = 32, noise level estimated with the plain estimator
+and the Eq. 23 vote), and the 64-image batch through the batched launch.  The FP64 oracle
+cannot process 12 MP within a test, so it checks what it can compute exactly:
+
+  - groups of sampled references, bit-exact (indices and distances), including the last
+    reference row and column of the grid;
+  - sigma_est of sampled sub-images (relative 1e-9), including partial edge sub-images, and
+    their Eq. 23 votes (identical counts), from oracle groups of the sampled voters;
+  - denoised pixels of row bands: the oracle processes every reference whose groups can reach
+    the band (reference rows within R + ps - 1 of it), so the band's pixels are complete sums;
+    the pixel parity bar (>= 99.99% within 1e-2, |dPSNR| <= 0.01 dB) applies to each band.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import PIX_FRAC, PIX_TOL
+from oracle import estimator as est
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PS, S, W, K = 8, 3, 31, 32
+
+
+@pytest.fixture(scope="module")
+def dn():
+    import paper_2512_23569_amd as ht
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    d = ht.Denoiser(0, load_network=False)
+    yield d
+    d.close()
+
+
+@pytest.fixture(scope="module")
+def big():
+    clean, noisy, spec = synth.make_cfg("rgb12mp_pg")
+    return clean, noisy
+
+
+def _ref_rows_for_band(h, y0, y1, s=S, w=W):
+    """Reference-row range [a, b) whose groups can reach pixel rows [y0, y1)."""
+    R = (w - 1) // 2
+    ys = oracle.ref_grid(h, PS, s)
+    keep = np.nonzero((ys >= y0 - (PS - 1) - R) & (ys <= y1 - 1 + R))[0]
+    return int(keep[0]), int(keep[-1]) + 1
+
+
+def _band_parity(gpu, ref, clean, y0, y1):
+    g = gpu[y0:y1].astype(np.float64)
+    r = ref[y0:y1]
+    d = np.abs(g - r)
+    frac = float(np.mean(d <= PIX_TOL))
+    dps = abs(synth.psnr(clean[y0:y1], g) - synth.psnr(clean[y0:y1], r))
+    assert frac >= PIX_FRAC and dps <= 0.01, (y0, y1, frac, float(d.max()), dps)
+
+
+def test_12mp_groups_sampled_bitexact(dn, big):
+    clean, noisy = big
+    h, w = noisy.shape[:2]
+    p = dn.params(3, stride=S, window=W, K=K)
+    idx, dist = dn.block_match(torch.from_numpy(noisy).cuda(), p)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    ny, nx = oracle.n_refs(h, w, PS, S)
+    rng = np.random.default_rng(12)
+    refs = np.concatenate([rng.integers(0, ny * nx, 3000), np.arange((ny - 1) * nx, ny * nx, 37),
+                           np.arange(nx - 1, ny * nx, nx * 29), [0, nx - 1, ny * nx - 1]])
+    oi, od = oracle.block_match_list(noisy, refs, PS, S, W, K)
+    bad = np.nonzero(np.any(idx[refs] != oi, axis=1) | np.any(dist[refs] != od, axis=1))[0]
+    assert bad.size == 0, "reference %d: gpu %s oracle %s" % (refs[bad[0]], idx[refs[bad[0]]], oi[bad[0]])
+
+
+def test_12mp_sigma_and_votes_sampled(dn, big):
+    import paper_2512_23569_amd as ht
+    clean, noisy = big
+    h, w = noisy.shape[:2]
+    p = dn.params(3, stride=S, window=W, K=K, adaptive=1)
+    nty, ntx = est.tile_grid(h, w, 128)
+    se = torch.zeros(nty * ntx, dtype=torch.float64, device="cuda")
+    sh = torch.zeros_like(se)
+    votes = torch.zeros(nty * ntx, dtype=torch.int32, device="cuda")
+    x = torch.from_numpy(noisy).cuda()
+    ht.htsvd_estimate_sigma(dn.ctx, x, h, w, 3, x.stride(0), -1.0, p, se, sh, votes)
+    se, sh, votes = se.cpu().numpy(), sh.cpu().numpy(), votes.cpu().numpy()
+    rng = np.random.default_rng(13)
+    tiles = sorted(set(rng.integers(0, nty * ntx, 16).tolist()) | {0, ntx - 1, (nty - 1) * ntx, nty * ntx - 1})
+    ref_se = est.sigma_est_tiles(noisy, tiles=tiles)
+    assert np.allclose(se[tiles], ref_se[tiles], rtol=1e-9, atol=0), (se[tiles], ref_se[tiles])
+    # votes of the sampled tiles from oracle groups of the sampled voters
+    ys, xs = oracle.ref_grid(h, PS, S), oracle.ref_grid(w, PS, S)
+    tile_of = est.tile_of_refs(ys, xs, h, w, 128)
+    for t in tiles:
+        voters = est.vote_samples(np.nonzero(tile_of == t)[0], t, p.n_vote, p.vote_seed)
+        gi, _ = oracle.block_match_list(noisy, voters, PS, S, W, K)
+        yes = sum(est.rank_position(est.group_vectors(noisy, gi[i], PS)) <= p.gamma_rank for i in range(len(voters)))
+        assert votes[t] == yes, (t, votes[t], yes)
+        want = ref_se[t] / p.beta if 2 * yes > len(voters) else ref_se[t]
+        assert np.isclose(sh[t], want, rtol=1e-9, atol=0), (t, sh[t], want)
+
+
+def test_12mp_denoised_bands(dn, big, basis3):
+    """The benchmark's plain form (estimated sigma) against the oracle on two row bands, with the
+    oracle given the thresholds the sampled sigma parity above vouches for."""
+    import paper_2512_23569_amd as ht
+    clean, noisy = big
+    h, w = noisy.shape[:2]
+    p = dn.params(3, stride=S, window=W, K=K, adaptive=1)
+    x = torch.from_numpy(noisy).cuda()
+    out = dn.denoise(x, -1.0, p).cpu().numpy()
+    nty, ntx = est.tile_grid(h, w, 128)
+    sh = torch.zeros(nty * ntx, dtype=torch.float64, device="cuda")
+    ht.htsvd_estimate_sigma(dn.ctx, x, h, w, 3, x.stride(0), -1.0, p, None, sh, None)
+    tau = est.tau_per_ref(sh.cpu().numpy(), h, w, PS, S, 3, K)
+    U, V = basis3
+    ny, nx = oracle.n_refs(h, w, PS, S)
+    for y0, y1 in ((1504, 1552), (h - 40, h)):
+        a, b = _ref_rows_for_band(h, y0, y1)
+        ref = oracle.denoise(noisy, U, V, tau, s=S, W=W, K=K, r_begin=a * nx, r_end=b * nx)
+        _band_parity(out, ref, clean, y0, y1)
+
+
+def test_batch_of_64_sampled_bands(dn, basis3):
+    """The 64-image batch through one graph replay (known per-image sigma, K = 16 as the
+    autotuner picks for it): bands of the largest and smallest images against the oracle."""
+    specs = synth.batch_specs(64, seed=4)
+    pairs = [(synth.make_clean(hh, ww, 3, sd), hh, ww, sg, sd) for hh, ww, sg, sd in specs]
+    noisy = [synth.add_awgn(c, sg, sd + 1000) for c, hh, ww, sg, sd in pairs]
+    ins = [torch.from_numpy(n).cuda() for n in noisy]
+    sig = [sp[2] for sp in specs]
+    p = dn.params(3, stride=4, window=31, K=16)
+    outs = dn.denoise_batch(ins, sig, p, use_graph=True)
+    outs = dn.denoise_batch(ins, sig, p, outs=outs, use_graph=True)   # replay
+    torch.cuda.synchronize()
+    U, V = basis3
+    sizes = [n.shape[0] * n.shape[1] for n in noisy]
+    for i in (int(np.argmax(sizes)), int(np.argmin(sizes))):
+        h, w = noisy[i].shape[:2]
+        ny, nx = oracle.n_refs(h, w, PS, 4)
+        tau = sig[i] * oracle.tau_multiplier(3, 16)
+        y0, y1 = h // 2 - 16, h // 2 + 16
+        a, b = _ref_rows_for_band(h, y0, y1, s=4)
+        ref = oracle.denoise(noisy[i], U, V, tau, s=4, W=31, K=16, r_begin=a * nx, r_end=b * nx)
+        _band_parity(outs[i].cpu().numpy(), ref, pairs[i][0], y0, y1)
