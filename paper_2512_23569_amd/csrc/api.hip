@@ -144,6 +144,10 @@ htsvd_status ensure_ws(htsvd_ctx *ctx, size_t bytes) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Largest ratio between the learned and the plain sigma of a sub-image at which the learned map
+// is trusted there.
+constexpr double JUDGE_RATIO = 1.5;
+
 double default_mult(int c, int K) { return sqrt(2.0 * log((double)c * K * PS * PS)); }
 
 // Workspace carve-up for one denoise call.
@@ -157,6 +161,7 @@ struct Ws {
     double *cov;
     int32_t *use_plain;
     double *sig_plain;
+    int32_t *mom;      // per (sub-image, channel) moments of the plain estimator
     size_t total;
 };
 
@@ -179,6 +184,7 @@ Ws plan_ws(void *base, const ImageGeom &g, int W, int K, int tile) {
     w.cov = (double *)take(sizeof(double) * n_tiles * g.c);  // per-channel tail variances
     w.use_plain = (int32_t *)take(sizeof(int32_t) * n_tiles);
     w.sig_plain = (double *)take(sizeof(double) * n_tiles);
+    w.mom = (int32_t *)take(sizeof(int32_t) * sigma_mom_ints() * n_tiles * g.c);
     w.total = off;
     return w;
 }
@@ -339,7 +345,8 @@ htsvd_status validate_crops(htsvd_ctx *ctx, const uint8_t *d, int32_t n, int32_t
 }
 
 // Learned log-sigma map of one image into the network workspace; returns its device pointer.
-htsvd_status run_cnn_map(htsvd_ctx *ctx, const ImageGeom &g, hipStream_t st, const float **zmap) {
+htsvd_status run_cnn_map(htsvd_ctx *ctx, const ImageGeom &g, hipStream_t st, const float **zmap,
+                         float *z_out = nullptr) {
     CnnState &cs = ctx->cnn;
     if (!cs.w) return fail(HTSVD_ESTATE, "learned estimator requested but no network weights are set");
     if (cs.c != g.c) return fail(HTSVD_EINVAL, "network channel count differs from the image's");
@@ -348,9 +355,11 @@ htsvd_status run_cnn_map(htsvd_ctx *ctx, const ImageGeom &g, hipStream_t st, con
     if (s != HTSVD_OK) return s;
     CnnWs w = plan_cnn_ws(cs.ws, 1, g.h, g.w, g.c, false);
     StageScope sc(ctx, HTSVD_STAGE_SIGMA, st);
-    hipError_t e = cnn_forward(cnn_buffers(cs, w), g.img, g.stride, 0, 1, g.h, g.w, g.c, st);
+    CnnBuffers cb = cnn_buffers(cs, w);
+    if (z_out) cb.z = z_out;
+    hipError_t e = cnn_forward(cb, g.img, g.stride, 0, 1, g.h, g.w, g.c, st);
     if (e != hipSuccess) return hip_fail(e, "network forward");
-    *zmap = w.z;
+    *zmap = cb.z;
     return HTSVD_OK;
 }
 
@@ -373,11 +382,11 @@ htsvd_status run_sigma(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &m
         if ((e = launch_fill_const(w.sig_est, n_tiles, (double)sigma, st)) != hipSuccess) return hip_fail(e, "sigma");
     } else if (p->estimator == 1) {
         // learned map (already in zmap) judged per tile by the plain estimate
-        if ((e = launch_sigma_est(g, T, w.cov, w.sig_plain, st)) != hipSuccess) return hip_fail(e, "sigma estimation");
-        if ((e = launch_learned_judge(g, T, zmap, w.sig_plain, 1.5, w.use_plain, w.sig_est, st)) != hipSuccess)
+        if ((e = launch_sigma_est(g, T, w.mom, w.cov, w.sig_plain, st)) != hipSuccess) return hip_fail(e, "sigma estimation");
+        if ((e = launch_learned_judge(g, T, zmap, w.sig_plain, JUDGE_RATIO, w.use_plain, w.sig_est, st)) != hipSuccess)
             return hip_fail(e, "sigma judge");
     } else {
-        if ((e = launch_sigma_est(g, T, w.cov, w.sig_est, st)) != hipSuccess) return hip_fail(e, "sigma estimation");
+        if ((e = launch_sigma_est(g, T, w.mom, w.cov, w.sig_est, st)) != hipSuccess) return hip_fail(e, "sigma estimation");
     }
     if (p->adaptive) {
         if ((e = launch_vote(g, mp, w.idx, T, p->n_vote, p->vote_seed, p->gamma_rank, p->beta, w.sig_est,
@@ -940,6 +949,8 @@ struct BatchImage {
     int bm_tiles_x, bm_tiles;
     int64_t n_ref, n_tiles_sigma;
     size_t off_idx, off_tau, off_reg, off_sig;   // byte offsets in the workspace
+    size_t off_z;                                 // learned log-sigma map (learned images)
+    bool learned;
     float *out;
     int64_t out_stride;
     float sigma;
@@ -950,6 +961,7 @@ struct BatchPlan {
     std::vector<BatchImage> im;
     std::vector<int> classes;                     // distinct K values
     size_t ws_total = 0;
+    size_t off_mom = 0;                           // plain-estimator moments of all estimated images
     int max_s = 1, max_W = 3, max_h = 8, max_w = 8;
     bool any_auto = false;
 };
@@ -980,6 +992,8 @@ htsvd_status plan_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, cons
         b.tg_alt = plan_filter_tiles(b.g, b.mp.W, 16, tile_side);
         b.n_ref = (int64_t)b.g.ny * b.g.nx;
         b.n_tiles_sigma = (int64_t)((b.g.h + T - 1) / T) * ((b.g.w + T - 1) / T);
+        b.learned = x.sigma == HTSVD_SIGMA_AUTO && p->estimator == 1;
+        b.off_z = 0;
         P.any_auto |= (x.sigma == HTSVD_SIGMA_AUTO) || p->adaptive;
         P.im.push_back(b);
     }
@@ -999,6 +1013,10 @@ htsvd_status plan_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, cons
         off = align256(off + reg);
         b.off_sig = off;  // sig_est, sig_hat, votes, cov (c per tile), use_plain, sig_plain
         off = align256(off + b.n_tiles_sigma * (sizeof(double) * (3 + b.g.c) + 2 * sizeof(int32_t)));
+        if (b.learned) {
+            b.off_z = off;
+            off = align256(off + sizeof(float) * cnn_act_elems(6, 1, b.g.h, b.g.w, b.g.c));
+        }
         P.max_s = std::max(P.max_s, b.g.s);
         P.max_W = std::max(P.max_W, b.mp.W);
         P.max_h = std::max(P.max_h, b.g.h);
@@ -1006,6 +1024,11 @@ htsvd_status plan_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, cons
         if (std::find(P.classes.begin(), P.classes.end(), b.mp.K) == P.classes.end()) P.classes.push_back(b.mp.K);
         if (b.auto_k && std::find(P.classes.begin(), P.classes.end(), 16) == P.classes.end()) P.classes.push_back(16);
     }
+    int64_t mom_units = 0;
+    for (const BatchImage &b : P.im)
+        if (b.sigma == HTSVD_SIGMA_AUTO) mom_units += b.n_tiles_sigma * b.g.c;
+    P.off_mom = off;
+    off = align256(off + sizeof(int32_t) * sigma_mom_ints() * mom_units);
     int64_t px = 0, refs = 0, bm = 0;
     for (const BatchImage &b : P.im) {
         px += (int64_t)b.g.h * b.g.w;
@@ -1032,6 +1055,7 @@ Ws image_ws(void *base, const BatchImage &b) {
     w.sig_plain = sig + (2 + b.g.c) * b.n_tiles_sigma;
     w.votes = (int32_t *)(sig + (3 + b.g.c) * b.n_tiles_sigma);
     w.use_plain = w.votes + b.n_tiles_sigma;
+    w.mom = nullptr;   // batched estimation uses the batch's shared moments buffer
     w.total = 0;
     return w;
 }
@@ -1162,6 +1186,66 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
     for (size_t k = 0; k < P.classes.size(); ++k) o_cstart[k] = reserve(sizeof(int) * cls_start[k].size());
     const size_t o_sig = reserve(sizeof(double) * ni), o_mult = reserve(sizeof(double) * ni);
     const size_t o_q = reserve(sizeof(int) * (1 + P.classes.size()));
+    // noise-level stage tables over the images whose sigma is estimated or adjusted
+    std::vector<SigmaItem> sitems;
+    std::vector<int> cov_sel, tile_sel, ref_sel, cov_st{0}, tile_st{0}, ref_st{0};
+    constexpr int NVK = 4;
+    const int vK[NVK] = {4, 8, 16, 32};
+    std::vector<int> vote_sel[NVK], vote_st[NVK];
+    for (int v = 0; v < NVK; ++v) vote_st[v].push_back(0);
+    for (int i = 0; i < ni; ++i) {
+        const BatchImage &b = P.im[i];
+        if (!(b.sigma == HTSVD_SIGMA_AUTO || p->adaptive)) continue;
+        const Ws w = image_ws(ctx->ws, b);
+        SigmaItem si;
+        si.g = b.g;
+        si.K = b.mp.K;
+        si.mode = b.sigma > 0.f ? SIGMA_KNOWN : (b.learned ? SIGMA_LEARNED : SIGMA_PLAIN);
+        si.adaptive = p->adaptive ? 1 : 0;
+        si.n_tiles = (int)b.n_tiles_sigma;
+        si.sigma = b.sigma > 0.f ? (double)b.sigma : 0.0;
+        si.mult = mult_h[i];
+        si.idx = w.idx;
+        si.tau = w.tau;
+        si.sig_est = w.sig_est;
+        si.sig_hat = w.sig_hat;
+        si.cov = w.cov;
+        si.sig_plain = w.sig_plain;
+        si.votes = w.votes;
+        si.use_plain = w.use_plain;
+        si.zmap = b.learned ? (const float *)((char *)ctx->ws + b.off_z) : nullptr;
+        const int k = (int)sitems.size();
+        sitems.push_back(si);
+        if (si.mode != SIGMA_KNOWN) {
+            cov_sel.push_back(k);
+            cov_st.push_back(cov_st.back() + si.n_tiles * b.g.c);
+        }
+        tile_sel.push_back(k);
+        tile_st.push_back(tile_st.back() + si.n_tiles);
+        if (si.adaptive) {
+            int v = 0;
+            while (v < NVK && vK[v] != si.K) ++v;
+            if (v == NVK) return fail(HTSVD_ENOTSUP, "group size without a vote kernel");
+            vote_sel[v].push_back(k);
+            vote_st[v].push_back(vote_st[v].back() + si.n_tiles);
+        }
+        ref_sel.push_back(k);
+        ref_st.push_back(ref_st.back() + (int)b.n_ref);
+    }
+    const size_t o_sitems = reserve(sizeof(SigmaItem) * std::max<size_t>(1, sitems.size()));
+    auto reserve_ints = [&](const std::vector<int> &v) { return reserve(sizeof(int) * std::max<size_t>(1, v.size())); };
+    const size_t o_cov_sel = reserve_ints(cov_sel), o_cov_st = reserve_ints(cov_st);
+    const size_t o_tile_sel = reserve_ints(tile_sel), o_tile_st = reserve_ints(tile_st);
+    const size_t o_ref_sel = reserve_ints(ref_sel), o_ref_st = reserve_ints(ref_st);
+    size_t o_vote_sel[NVK], o_vote_st[NVK];
+    for (int v = 0; v < NVK; ++v) {
+        o_vote_sel[v] = reserve_ints(vote_sel[v]);
+        o_vote_st[v] = reserve_ints(vote_st[v]);
+    }
+    int64_t auto_refs = 1;
+    for (int i : auto_list) auto_refs = std::max(auto_refs, P.im[i].n_ref);
+    const int k_chunks = select_k_chunks(auto_refs);
+    const size_t o_kpart = reserve(sizeof(double) * k_chunks * std::max<size_t>(1, auto_list.size()));
     hipError_t e;
     BatchCache &bc = ctx->batch;
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronise before batch planning");
@@ -1198,6 +1282,20 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
     memcpy(host.data() + o_mult, mult_h.data(), sizeof(double) * ni);
     memcpy(host.data() + o_ksel, ksel_h.data(), sizeof(int) * ni);
     if (!auto_list.empty()) memcpy(host.data() + o_auto, auto_list.data(), sizeof(int) * auto_list.size());
+    if (!sitems.empty()) memcpy(host.data() + o_sitems, sitems.data(), sizeof(SigmaItem) * sitems.size());
+    auto put_ints = [&](size_t o2, const std::vector<int> &v) {
+        if (!v.empty()) memcpy(host.data() + o2, v.data(), sizeof(int) * v.size());
+    };
+    put_ints(o_cov_sel, cov_sel);
+    put_ints(o_cov_st, cov_st);
+    put_ints(o_tile_sel, tile_sel);
+    put_ints(o_tile_st, tile_st);
+    put_ints(o_ref_sel, ref_sel);
+    put_ints(o_ref_st, ref_st);
+    for (int v = 0; v < NVK; ++v) {
+        put_ints(o_vote_sel[v], vote_sel[v]);
+        put_ints(o_vote_st[v], vote_st[v]);
+    }
     if ((e = hipMemcpy(bc.dev, host.data(), off, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "batch descriptor upload");
     char *D = (char *)bc.dev;
@@ -1232,26 +1330,37 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
         if ((e2 = launch_block_match_batched(d_items, ni, (const int *)(D + o_bm), P.max_s, P.max_W, P.max_h, P.max_w,
                                              d_q, std::min(grid, bm_start[ni]), ls)) != hipSuccess)
             return hip_fail(e2, "batched block matching");
-        // images whose noise level is estimated or adjusted: per-image sigma stages
-        for (int i = 0; i < ni; ++i) {
-            const BatchImage &b = P.im[i];
-            if (!(b.sigma == HTSVD_SIGMA_AUTO || p->adaptive)) continue;
-            Ws w = image_ws(ctx->ws, b);
-            htsvd_params pi = *p;
-            pi.K = b.mp.K;
-            const float *zmap = nullptr;
-            const bool learned = b.sigma == HTSVD_SIGMA_AUTO && p->estimator == 1;
-            htsvd_status s2;
-            if (learned && (s2 = run_cnn_map(ctx, b.g, ls, &zmap)) != HTSVD_OK) return s2;
-            if ((s2 = run_sigma(ctx, b.g, b.mp, &pi, b.sigma, w, zmap, ls)) != HTSVD_OK) return s2;
-            if (learned)
-                e2 = launch_fill_tau_learned(w.tau, b.g, pi.subimage, zmap, w.use_plain, w.sig_est, w.sig_hat, mult_h[i], ls);
-            else
-                e2 = launch_fill_tau(w.tau, b.n_ref, w.sig_hat, 0.0, mult_h[i], b.g, pi.subimage, ls);
-            if (e2 != hipSuccess) return hip_fail(e2, "tau");
+        // images whose noise level is estimated or adjusted: the network per learned image, then
+        // every sub-image stage in one launch over all images
+        if (!sitems.empty()) {
+            StageScope sc(ctx, HTSVD_STAGE_SIGMA, ls);
+            const int T = p->subimage;
+            const SigmaItem *S = (const SigmaItem *)(D + o_sitems);
+            for (const SigmaItem &si : sitems) {
+                if (si.mode != SIGMA_LEARNED) continue;
+                const float *zmap = nullptr;
+                htsvd_status s2 = run_cnn_map(ctx, si.g, ls, &zmap, const_cast<float *>(si.zmap));
+                if (s2 != HTSVD_OK) return s2;
+            }
+            auto I = [&](size_t o2) { return (const int *)(D + o2); };
+            if ((e2 = launch_sigma_est_batched(S, I(o_cov_sel), I(o_cov_st), (int)cov_sel.size(), cov_st.back(), T,
+                                               (int32_t *)((char *)ctx->ws + P.off_mom), ls)) != hipSuccess)
+                return hip_fail(e2, "batched sigma estimation");
+            if ((e2 = launch_sigma_tiles_batched(S, I(o_tile_sel), I(o_tile_st), (int)tile_sel.size(), tile_st.back(),
+                                                 T, JUDGE_RATIO, ls)) != hipSuccess)
+                return hip_fail(e2, "batched sigma tiles");
+            for (int v = 0; v < NVK; ++v)
+                if ((e2 = launch_vote_batched(vK[v], S, I(o_vote_sel[v]), I(o_vote_st[v]), (int)vote_sel[v].size(),
+                                              vote_st[v].back(), T, p->n_vote, p->vote_seed, p->gamma_rank, p->beta,
+                                              ls)) != hipSuccess)
+                    return hip_fail(e2, "batched vote");
+            if ((e2 = launch_fill_tau_sigma_batched(S, I(o_ref_sel), I(o_ref_st), (int)ref_sel.size(), ref_st.back(), T,
+                                                    ls)) != hipSuccess)
+                return hip_fail(e2, "batched thresholds");
         }
-        if ((e2 = launch_select_k(d_items, (const int *)(D + o_auto), (int)auto_list.size(), (const double *)(D + o_mult),
-                                  (double)o.k_sigma_cutoff, (int *)(D + o_ksel), ls)) != hipSuccess)
+        if ((e2 = launch_select_k(d_items, (const int *)(D + o_auto), (int)auto_list.size(), k_chunks,
+                                  (double *)(D + o_kpart), (const double *)(D + o_mult), (double)o.k_sigma_cutoff,
+                                  (int *)(D + o_ksel), ls)) != hipSuccess)
             return hip_fail(e2, "group size selection");
         for (size_t k = 0; k < P.classes.size(); ++k) {
             const int units = cls_start[k].back();

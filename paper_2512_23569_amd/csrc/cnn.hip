@@ -47,34 +47,46 @@ struct ConvShape {
 };
 
 // ---- layer 1: u8 image -> 32 channels, vector ALU ----
-__global__ void l1_fwd_kernel(const uint8_t *__restrict__ img, int64_t img_stride, int64_t img_batch_stride,
-                              ConvShape cs, const float *__restrict__ wq, const float *__restrict__ bias,
-                              uint16_t *__restrict__ out) {
+// One thread per output pixel; the 9 C input taps stay in registers, the weights are uniform
+// across the wavefront (scalar loads), the 32 outputs leave as four 16-byte stores.
+template <int C>
+__global__ __launch_bounds__(256) void l1_fwd_kernel(const uint8_t *__restrict__ img, int64_t img_stride,
+                                                     int64_t img_batch_stride, ConvShape cs,
+                                                     const float *__restrict__ wq, const float *__restrict__ bias,
+                                                     uint16_t *__restrict__ out) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)cs.N * cs.Ho * cs.Wo;
     if (p >= total) return;
     const int n = (int)(p / ((int64_t)cs.Ho * cs.Wo));
     const int rem = (int)(p % ((int64_t)cs.Ho * cs.Wo));
     const int yo = rem / cs.Wo, xo = rem % cs.Wo;
-    float x[27];
-    const int C = cs.Ci;
+    float x[9 * C];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
         const int yi = cs.s * yo + t / 3 - 1, xi = cs.s * xo + t % 3 - 1;
         const bool ok = yi >= 0 && yi < cs.H && xi >= 0 && xi < cs.W;
-        for (int ci = 0; ci < C; ++ci) {
-            float v = 0.f;
-            if (ok) v = ((float)img[n * img_batch_stride + (int64_t)yi * img_stride + (int64_t)xi * C + ci] - 128.f) * 0.015625f;
-            x[t * 3 + ci] = v;
+#pragma unroll
+        for (int ci = 0; ci < C; ++ci) x[t * C + ci] = 0.f;
+        if (ok) {
+            const uint8_t *src = img + n * img_batch_stride + (int64_t)yi * img_stride + (int64_t)xi * C;
+#pragma unroll
+            for (int ci = 0; ci < C; ++ci) x[t * C + ci] = ((float)src[ci] - 128.f) * 0.015625f;
         }
     }
-    uint16_t *o = out + p * 32;
+    uint32_t packed[16];
+#pragma unroll
     for (int co = 0; co < 32; ++co) {
         float acc = bias[co];
+#pragma unroll
         for (int t = 0; t < 9; ++t)
-            for (int ci = 0; ci < C; ++ci) acc += wq[(co * 9 + t) * C + ci] * x[t * 3 + ci];
-        o[co] = f2bf(acc > 0.f ? acc : 0.f);
+#pragma unroll
+            for (int ci = 0; ci < C; ++ci) acc += wq[(co * 9 + t) * C + ci] * x[t * C + ci];
+        const uint32_t h = f2bf(acc > 0.f ? acc : 0.f);
+        packed[co >> 1] = (co & 1) ? (packed[co >> 1] | (h << 16)) : h;
     }
+    uint4 *o = reinterpret_cast<uint4 *>(out + p * 32);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2], packed[4 * q + 3]);
 }
 
 // ---- 32 -> 32 convolution on the matrix cores ----
@@ -303,8 +315,14 @@ hipError_t cnn_forward(const CnnBuffers &b, const uint8_t *img, int64_t img_stri
     cnn_layout(c, wo, bo, &tot);
     ConvShape cs = shape_of(0, N, H, W, c);
     int64_t np = (int64_t)cs.N * cs.Ho * cs.Wo;
-    hipLaunchKernelGGL(l1_fwd_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, img, img_stride, img_batch_stride,
-                       cs, b.wq + wo[0], b.wq + bo[0], b.act[1]);
+    if (c == 3)
+        hipLaunchKernelGGL(l1_fwd_kernel<3>, dim3(blocks_for(np, 256)), dim3(256), 0, st, img, img_stride,
+                           img_batch_stride, cs, b.wq + wo[0], b.wq + bo[0], b.act[1]);
+    else if (c == 1)
+        hipLaunchKernelGGL(l1_fwd_kernel<1>, dim3(blocks_for(np, 256)), dim3(256), 0, st, img, img_stride,
+                           img_batch_stride, cs, b.wq + wo[0], b.wq + bo[0], b.act[1]);
+    else
+        return hipErrorInvalidValue;
     for (int l = 1; l < 5; ++l) {
         cs = shape_of(l, N, H, W, c);
         np = (int64_t)cs.N * cs.Ho * cs.Wo;

@@ -74,6 +74,23 @@ struct BatchItem {
     TileGeom tg_alt;
 };
 
+// One image of the batched noise-level stages (sub-images of side `tile`, Sec. III-E-1).
+enum SigmaMode { SIGMA_KNOWN = 0, SIGMA_PLAIN = 1, SIGMA_LEARNED = 2 };
+struct SigmaItem {
+    ImageGeom g;
+    int K;                  // members per stored group (the vote reads the first K of each)
+    int mode;               // SigmaMode
+    int adaptive;           // Eq. 22-23 vote on
+    int n_tiles;            // sub-images
+    double sigma;           // known sigma (SIGMA_KNOWN)
+    double mult;            // threshold multiplier: tau = mult * sigma
+    const int32_t *idx;     // groups, n_ref * K
+    double *tau;            // per-reference thresholds (written)
+    double *sig_est, *sig_hat, *cov, *sig_plain;   // per sub-image (cov: c per sub-image)
+    int32_t *votes, *use_plain;
+    const float *zmap;      // learned log-sigma per 8x8 block (SIGMA_LEARNED)
+};
+
 // Index i of the unit range [start[i], start[i+1]) holding u (start has n+1 entries).
 __device__ inline int find_unit(const int *start, int n, int u) {
     int lo = 0, hi = n - 1;
@@ -124,7 +141,9 @@ hipError_t launch_fill_tau(double *tau_ref, int64_t n_ref, const double *sigma_t
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 
 // Noise estimation (plain): per sub-image covariance eigenvalues and the tail rule.
-hipError_t launch_sigma_est(const ImageGeom &g, int tile, double *cov_work, double *sigma_est,
+// mom: sigma_mom_ints() int32 per (sub-image, channel) of scratch; cov_work: c doubles per sub-image.
+int sigma_mom_ints();
+hipError_t launch_sigma_est(const ImageGeom &g, int tile, int32_t *mom, double *cov_work, double *sigma_est,
                             hipStream_t st);
 hipError_t launch_vote(const ImageGeom &g, const MethodParams &mp, const int32_t *idx, int tile, int n_vote,
                        uint64_t seed, int gamma_rank, double beta, const double *sigma_est, double *sigma_hat,
@@ -137,8 +156,9 @@ hipError_t launch_filter_batched(int C, int K, const BatchItem *items, int n_ite
                                  const BasisDev &b, unsigned long long *gc, int *queue, int grid, hipStream_t st);
 hipError_t launch_gather_batched(int C, const BatchItem *items, int n_items, const int *pix_start, int total_px,
                                  hipStream_t st);
-hipError_t launch_select_k(const BatchItem *items, const int *auto_list, int n_auto, const double *mult,
-                           double cutoff, int *ksel, hipStream_t st);
+int select_k_chunks(int64_t max_refs);
+hipError_t launch_select_k(const BatchItem *items, const int *auto_list, int n_auto, int n_chunk, double *partial,
+                           const double *mult, double cutoff, int *ksel, hipStream_t st);
 hipError_t launch_fill_tau_batched(const BatchItem *items, int n_items, const int *ref_start, int total_refs,
                                    const double *sigma, const double *mult, hipStream_t st);
 // Reference tiling of the filter: the largest square tile (side <= max_side, 0 = 16) whose
@@ -173,6 +193,18 @@ hipError_t cnn_backward(const CnnBuffers &b, const uint8_t *img, int64_t img_str
 hipError_t cnn_adam(float *w, float *m, float *v, const float *g, int n, float lr, int64_t step, float *wq,
                     uint16_t *wbf, hipStream_t st);
 hipError_t cnn_quantize(const float *w, int n, float *wq, uint16_t *wbf, hipStream_t st);
+
+// Batched noise-level stages.  Each launch walks a list of items: sel[j] is the item of list
+// entry j, start[j] .. start[j+1] its units (sub-images x channels for the covariance stage,
+// sub-images for the tile and vote stages, references for the thresholds).
+hipError_t launch_sigma_est_batched(const SigmaItem *items, const int *sel, const int *start, int n, int total,
+                                    int tile, int32_t *mom, hipStream_t st);   // mom: total units of scratch
+hipError_t launch_sigma_tiles_batched(const SigmaItem *items, const int *sel, const int *start, int n, int total,
+                                      int tile, double ratio_bound, hipStream_t st);
+hipError_t launch_vote_batched(int K, const SigmaItem *items, const int *sel, const int *start, int n, int total,
+                               int tile, int n_vote, uint64_t seed, int gamma_rank, double beta, hipStream_t st);
+hipError_t launch_fill_tau_sigma_batched(const SigmaItem *items, const int *sel, const int *start, int n,
+                                         int total, int tile, hipStream_t st);
 
 // Learned sigma map -> thresholds: per-tile judge against the plain estimate, per-reference tau.
 hipError_t launch_learned_judge(const ImageGeom &g, int tile, const float *zmap, const double *sigma_plain,

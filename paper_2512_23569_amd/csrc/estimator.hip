@@ -11,9 +11,13 @@
 //   - The patch second moments are a contraction over patches: S = X^T X with X the
 //     n x 64 matrix of shifted patches (x - 128, int8).  One workgroup per (sub-image,
 //     channel) runs it on v_mfma_i32_16x16x64_i8 with 64 patches per k-step; the row sums
-//     come from the same instruction with an all-ones operand.  int32 partials are exact.
-//   - The 64x64 FP64 covariance is diagonalised in LDS by cyclic Jacobi rotations with the
-//     round-robin pairing (32 disjoint rotations per step).
+//     come from the same instruction with an all-ones operand.  int32 partials are exact and
+//     go to a scratch buffer (mom_kernel).
+//   - The eigenvalues of the 64x64 FP64 covariance take one wavefront per (sub-image,
+//     channel) (eig_kernel): Householder reduction to tridiagonal form with lane i holding
+//     row i in registers, then Sturm-count bisection with lane i finding the i-th smallest
+//     eigenvalue.  Keeping this stage apart from the moments lets every SIMD run two such
+//     wavefronts, whose serial dependency chains would otherwise leave the CU idle.
 //
 // Eq. 22-23 vote: for a few groups per sub-image the rank a of the alternating eigenvalue
 // lambda_hat = |sum_m (-1)^m p_m|^2 among the K eigenvalues of circ(G) circ(G)^T, whose
@@ -23,6 +27,7 @@
 #include <math.h>
 
 #include "common.h"
+#include "sigma_dev.h"
 
 namespace htsvd {
 
@@ -58,6 +63,15 @@ __device__ inline v4i frag16(const unsigned char *lds, int plane, int r, int col
     return f;
 }
 
+// 1/q: the hardware estimate refined by two Newton steps (each squares the relative error).
+__device__ inline double recip(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    double e = fma(-q, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-q, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Sum over the 64 lanes of a wavefront (every lane gets the total).
 __device__ inline double wave_sum_d(double v) {
 #pragma unroll
@@ -65,33 +79,34 @@ __device__ inline double wave_sum_d(double v) {
     return v;
 }
 
-// LDS layout of cov_eig_kernel (bytes)
+// LDS layout of mom_kernel (bytes)
 constexpr int COV_BAND = 16;                               // patch rows per staged band
 constexpr int COV_STAGE_ROWS = COV_BAND + PS - 1;          // 23 pixel rows per band
 constexpr int COV_PLANE = COV_STAGE_ROWS * COV_PITCH;      // one byte-shifted copy
-constexpr int COV_OFF_S2 = 0;                              // int32 [64][64] second moments
-constexpr int COV_OFF_S1 = COV_OFF_S2 + 64 * 64 * 4;       // int32 [64] first moments
+constexpr int S2_PITCH = 65;                               // int32 row pitch of the second moments
+constexpr int COV_OFF_S2 = 0;                              // int32 [64][65] second moments
+constexpr int COV_OFF_S1 = COV_OFF_S2 + 64 * S2_PITCH * 4; // int32 [64] first moments
 constexpr int COV_OFF_STAGE = COV_OFF_S1 + 64 * 4;         // 4 copies of the band
-constexpr int COV_OFF_VEC = COV_OFF_STAGE + 4 * COV_PLANE; // double [3][64] (v, w / d, e2, eigenvalues)
-constexpr int COV_LDS = COV_OFF_VEC + 3 * 64 * 8;
+constexpr int COV_LDS = COV_OFF_STAGE + 4 * COV_PLANE;
 
-// One workgroup per (sub-image, channel).  Phase 1 (4 waves): exact integer second moments of
-// the shifted patches on the matrix cores, the sub-image staged band by band.  Phase 2 (wave
-// 0): covariance rows in registers (lane i holds row i), Householder reduction to tridiagonal
-// form, eigenvalues by Sturm-count bisection (lane i finds the i-th smallest), tail rule.
-__global__ __launch_bounds__(256) void cov_eig_kernel(ImageGeom g, int T, double *__restrict__ sigma2) {
-    extern __shared__ __align__(16) unsigned char smem[];
+// Moments of one (sub-image, channel) in global memory: the full symmetric 64 x 64 second
+// moments (row-major), then the 64 first moments, int32 (exact).
+constexpr int MOM_INTS = 64 * 64 + 64;
+
+// Moments of one (sub-image, channel), one workgroup of 4 waves: exact integer second moments
+// of the shifted patches on the matrix cores, the sub-image staged band by band; written to
+// mom (MOM_INTS int32).
+__device__ __forceinline__ void mom_tile(unsigned char *smem, const ImageGeom g, int T, int t, int ch,
+                                int32_t *__restrict__ mom) {
     int32_t *S2 = reinterpret_cast<int32_t *>(smem + COV_OFF_S2);
     int32_t *S1 = reinterpret_cast<int32_t *>(smem + COV_OFF_S1);
     unsigned char *stage = smem + COV_OFF_STAGE;
-    double *vec = reinterpret_cast<double *>(smem + COV_OFF_VEC);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int t = blockIdx.x / g.c, ch = blockIdx.x % g.c;
     int y0, y1, x0, x1;
     tile_bounds(g, T, t, &y0, &y1, &x0, &x1);
     const int ny = y1 - y0 + 1, nx = x1 - x0 + 1;   // patch positions
     const int pcol = nx + PS - 1;
-    for (int e = tid; e < 64 * 64 + 64; e += 256) S2[e] = 0;   // S1 follows S2
+    for (int e = tid; e < 64 * S2_PITCH + 64; e += 256) S2[e] = 0;   // S1 follows S2
 
     // ---- phase 1: second moments on the matrix cores ----
     // k-step = 64 consecutive patch positions of one row; lane (i = l%16, kq = l/16) holds
@@ -147,7 +162,7 @@ __global__ __launch_bounds__(256) void cov_eig_kernel(ImageGeom g, int T, double
 #pragma unroll
             for (int jb = ib; jb < 4; ++jb) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) atomicAdd(&S2[(16 * ib + 4 * kq + r) * 64 + 16 * jb + i16], acc[a][r]);
+                for (int r = 0; r < 4; ++r) atomicAdd(&S2[(16 * ib + 4 * kq + r) * S2_PITCH + 16 * jb + i16], acc[a][r]);
                 ++a;
             }
             if (i16 == 0) {
@@ -157,18 +172,27 @@ __global__ __launch_bounds__(256) void cov_eig_kernel(ImageGeom g, int T, double
         }
     }
     __syncthreads();
-    if (wave != 0) return;   // phase 2 runs on one wavefront; no block barrier follows
+    // only the blocks ib <= jb were accumulated: entry (r, c) of the full matrix is S2[min][max]
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        mom[e] = S2[min(r, c) * S2_PITCH + max(r, c)];
+    }
+    if (tid < 64) mom[64 * 64 + tid] = S1[tid];
+}
 
+// Eigenvalue stage of one (sub-image, channel), one wavefront: covariance rows in registers
+// (lane i holds row i), Householder reduction to tridiagonal form, eigenvalues by Sturm-count
+// bisection (lane i finds the i-th smallest), tail rule.  vec: 3 x 64 doubles of LDS for this
+// wave.  Writes sigma_c^2 to *out (lane 0).
+__device__ __forceinline__ void eig_tile(double *vec, const int32_t *__restrict__ mom, double n, double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
     // ---- phase 2: covariance row i = lane, in registers ----
     const int i = lane;
-    const double n = (double)ny * (double)nx;
+    const int32_t *S1 = mom + 64 * 64;
     const double s1i = (double)S1[i] / n;
     double row[64];
 #pragma unroll
-    for (int j = 0; j < 64; ++j) {
-        const int ii = min(i, j), jj = max(i, j);   // only blocks ib <= jb were accumulated
-        row[j] = (double)S2[ii * 64 + jj] / n - s1i * ((double)S1[j] / n);
-    }
+    for (int j = 0; j < 64; ++j) row[j] = (double)mom[i * 64 + j] / n - s1i * ((double)S1[j] / n);
     double *vv = vec, *ww = vec + 64;
     // Householder: step k annihilates column k below the subdiagonal.
     for (int k = 0; k < 62; ++k) {
@@ -217,22 +241,37 @@ __global__ __launch_bounds__(256) void cov_eig_kernel(ImageGeom g, int T, double
         hi = fmax(hi, __shfl_xor(hi, o));
     }
     __builtin_amdgcn_wave_barrier();
-    // bisection for the i-th smallest eigenvalue: count(x) = #eigenvalues < x (Sturm)
+    // The i-th smallest eigenvalue by quadrisection: count(x) = #eigenvalues < x (Sturm sequence
+    // of the LDL^T pivots); three interior points per step, evaluated as three interleaved
+    // chains, so 30 steps narrow the interval by 2^60 like 60 bisection steps.
     const double span = fmax(hi - lo, 1e-300);
     lo -= 1e-12 * span;
     hi += 1e-12 * span;
-    for (int it = 0; it < 60; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        int cnt = 0;
-        double q = dd[0] - mid;
-        cnt += q < 0.0;
+    for (int it = 0; it < 30; ++it) {
+        const double qw = 0.25 * (hi - lo);
+        const double x1 = lo + qw, x2 = lo + 2.0 * qw, x3 = lo + 3.0 * qw;
+        double q1 = dd[0] - x1, q2 = dd[0] - x2, q3 = dd[0] - x3;
+        int c1 = q1 < 0.0, c2 = q2 < 0.0, c3 = q3 < 0.0;
         for (int j = 1; j < 64; ++j) {
-            if (q == 0.0) q = 1e-300;
-            q = (dd[j] - mid) - e2[j] / q;
-            cnt += q < 0.0;
+            const double dj = dd[j], ej = e2[j];
+            q1 = (dj - x1) - ej * recip(q1 == 0.0 ? 1e-300 : q1);
+            q2 = (dj - x2) - ej * recip(q2 == 0.0 ? 1e-300 : q2);
+            q3 = (dj - x3) - ej * recip(q3 == 0.0 ? 1e-300 : q3);
+            c1 += q1 < 0.0;
+            c2 += q2 < 0.0;
+            c3 += q3 < 0.0;
         }
-        if (cnt > i) hi = mid;
-        else lo = mid;
+        if (c1 > i) {
+            hi = x1;
+        } else if (c2 > i) {
+            lo = x1;
+            hi = x2;
+        } else if (c3 > i) {
+            lo = x2;
+            hi = x3;
+        } else {
+            lo = x3;
+        }
     }
     const double lam = 0.5 * (lo + hi);   // ascending: lane i holds the i-th smallest
     ev[i] = lam;
@@ -250,16 +289,94 @@ __global__ __launch_bounds__(256) void cov_eig_kernel(ImageGeom g, int T, double
     const uint64_t hit = __ballot(above == below);
     // cross-lane read with every lane active; the smallest eigenvalue when no tail qualifies
     const double tau_first = __shfl(tau, hit ? __ffsll((unsigned long long)hit) - 1 : 0);
-    if (lane == 0) sigma2[t * g.c + ch] = hit ? tau_first : ev[0];
+    if (lane == 0) *out = hit ? tau_first : ev[0];
+}
+
+// Number of patch positions of sub-image t.
+__device__ inline double tile_patches(const ImageGeom &g, int T, int t) {
+    int y0, y1, x0, x1;
+    tile_bounds(g, T, t, &y0, &y1, &x0, &x1);
+    return (double)(y1 - y0 + 1) * (double)(x1 - x0 + 1);
+}
+
+// One workgroup per (sub-image, channel): block u = t * c + ch.
+__global__ __launch_bounds__(256) void mom_kernel(ImageGeom g, int T, int32_t *__restrict__ mom) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    mom_tile(smem, g, T, blockIdx.x / g.c, blockIdx.x % g.c, mom + (int64_t)blockIdx.x * MOM_INTS);
+}
+
+// One wavefront per (sub-image, channel), EIG_WAVES per workgroup.
+constexpr int EIG_WAVES = 4;
+
+__global__ __launch_bounds__(64 * EIG_WAVES, 2) void eig_kernel(ImageGeom g, int T, int n_units,
+                                                             const int32_t *__restrict__ mom,
+                                                             double *__restrict__ sigma2) {
+    __shared__ double vec[EIG_WAVES][3 * 64];
+    const int wave = threadIdx.x >> 6;
+    const int u = blockIdx.x * EIG_WAVES + wave;
+    if (u >= n_units) return;
+    eig_tile(vec[wave], mom + (int64_t)u * MOM_INTS, tile_patches(g, T, u / g.c), sigma2 + u);
+}
+
+// Batched: units (item, sub-image, channel) of the list; mom is indexed by the global unit.
+__global__ __launch_bounds__(256) void mom_kernel_batched(const SigmaItem *__restrict__ items,
+                                                          const int *__restrict__ sel, const int *__restrict__ start,
+                                                          int n, int T, int32_t *__restrict__ mom) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int j = find_unit(start, n, blockIdx.x);
+    const ImageGeom g = items[sel[j]].g;
+    const int u = blockIdx.x - start[j];
+    mom_tile(smem, g, T, u / g.c, u % g.c, mom + (int64_t)blockIdx.x * MOM_INTS);
+}
+
+__global__ __launch_bounds__(64 * EIG_WAVES, 2) void eig_kernel_batched(const SigmaItem *__restrict__ items,
+                                                                     const int *__restrict__ sel,
+                                                                     const int *__restrict__ start, int n, int total,
+                                                                     int T, const int32_t *__restrict__ mom) {
+    __shared__ double vec[EIG_WAVES][3 * 64];
+    const int wave = threadIdx.x >> 6;
+    const int gu = blockIdx.x * EIG_WAVES + wave;
+    if (gu >= total) return;
+    const int j = find_unit(start, n, gu);
+    const SigmaItem &it = items[sel[j]];
+    const ImageGeom g = it.g;
+    const int u = gu - start[j];
+    eig_tile(vec[wave], mom + (int64_t)gu * MOM_INTS, tile_patches(g, T, u / g.c), it.cov + u);
 }
 
 __global__ void combine_sigma_kernel(const double *sigma2, int c, int n_tiles, double *sigma_est) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
-    double s = 0.0;
-    for (int ch = 0; ch < c; ++ch) s += sigma2[t * c + ch];
-    s /= (double)c;
-    sigma_est[t] = s > 0.0 ? sqrt(s) : 0.0;
+    sigma_est[t] = combine_sigma_tile(sigma2, c, t);
+}
+
+// Batched per-sub-image stage: sigma_est from a known sigma, the plain estimate, or the learned
+// map judged by the plain estimate; without the vote, sigma_hat = sigma_est and no votes.
+__global__ void sigma_tiles_batched_kernel(const SigmaItem *__restrict__ items, const int *__restrict__ sel,
+                                           const int *__restrict__ start, int n, int total, int T,
+                                           double log_bound) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= total) return;
+    const int j = find_unit(start, n, u);
+    const SigmaItem &it = items[sel[j]];
+    const int t = u - start[j];
+    double se;
+    if (it.mode == SIGMA_KNOWN) {
+        se = it.sigma;
+    } else {
+        const double sp = combine_sigma_tile(it.cov, it.g.c, t);
+        if (it.mode == SIGMA_PLAIN) {
+            se = sp;
+        } else {
+            it.sig_plain[t] = sp;
+            se = judge_tile(it.g, T, t, it.zmap, sp, log_bound, it.use_plain + t);
+        }
+    }
+    it.sig_est[t] = se;
+    if (!it.adaptive) {
+        it.sig_hat[t] = se;
+        it.votes[t] = 0;
+    }
 }
 
 __global__ void fill_const_kernel(double *p, int n, double v) {
@@ -293,15 +410,21 @@ __device__ inline void ref_range(int n_ref, int n, int s, int lo, int hi, int *f
 // lane k computing lambda_k (same summation order for every k), the rank of lambda_hat, and
 // the majority over the groups.
 template <int K>
-__global__ __launch_bounds__(256) void vote_kernel(ImageGeom g, const int32_t *__restrict__ idx, int T, int n_vote,
-                                                   uint64_t seed, int gamma_rank, double beta,
-                                                   const double *__restrict__ sigma_est, double *__restrict__ sigma_hat,
-                                                   int32_t *__restrict__ votes) {
-    const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+struct VoteShared {
+    int iy0, iy1, ix0, ix1, yes;
+    double cos_tab[K];
+};
+
+template <int K>
+__device__ __forceinline__ void vote_tile(VoteShared<K> &sh, const ImageGeom g, const int32_t *__restrict__ idx, int T, int t,
+                                 int n_vote, uint64_t seed, int gamma_rank, double beta,
+                                 const double *__restrict__ sigma_est, double *__restrict__ sigma_hat,
+                                 int32_t *__restrict__ votes) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ntx = (g.w + T - 1) / T;
     const int ty = t / ntx, tx = t % ntx;
-    __shared__ int s_iy0, s_iy1, s_ix0, s_ix1, s_yes;
-    __shared__ double cos_tab[K];
+    int &s_iy0 = sh.iy0, &s_iy1 = sh.iy1, &s_ix0 = sh.ix0, &s_ix1 = sh.ix1, &s_yes = sh.yes;
+    double *cos_tab = sh.cos_tab;
     if (tid == 0) {
         ref_range(g.ny, g.h, g.s, ty * T, ty * T + T - 1, &s_iy0, &s_iy1);
         ref_range(g.nx, g.w, g.s, tx * T, tx * T + T - 1, &s_ix0, &s_ix1);
@@ -378,19 +501,45 @@ __global__ __launch_bounds__(256) void vote_kernel(ImageGeom g, const int32_t *_
     }
 }
 
+template <int K>
+__global__ __launch_bounds__(256) void vote_kernel(ImageGeom g, const int32_t *__restrict__ idx, int T, int n_vote,
+                                                   uint64_t seed, int gamma_rank, double beta,
+                                                   const double *__restrict__ sigma_est, double *__restrict__ sigma_hat,
+                                                   int32_t *__restrict__ votes) {
+    __shared__ VoteShared<K> sh;
+    vote_tile<K>(sh, g, idx, T, blockIdx.x, n_vote, seed, gamma_rank, beta, sigma_est, sigma_hat, votes);
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void vote_kernel_batched(const SigmaItem *__restrict__ items,
+                                                           const int *__restrict__ sel,
+                                                           const int *__restrict__ start, int n, int T, int n_vote,
+                                                           uint64_t seed, int gamma_rank, double beta) {
+    __shared__ VoteShared<K> sh;
+    const int j = find_unit(start, n, blockIdx.x);
+    const SigmaItem &it = items[sel[j]];
+    vote_tile<K>(sh, it.g, it.idx, T, blockIdx.x - start[j], n_vote, seed, gamma_rank, beta, it.sig_est, it.sig_hat,
+                 it.votes);
+}
+
 }  // namespace
 
 int cov_lds_bytes() { return COV_LDS; }
+int sigma_mom_ints() { return MOM_INTS; }
 
-hipError_t launch_sigma_est(const ImageGeom &g, int tile, double *work, double *sigma_est, hipStream_t st) {
+hipError_t launch_sigma_est(const ImageGeom &g, int tile, int32_t *mom, double *work, double *sigma_est,
+                            hipStream_t st) {
     if (tile != 128) return hipErrorInvalidValue;
     const int n_tiles = ((g.h + tile - 1) / tile) * ((g.w + tile - 1) / tile);
+    const int units = n_tiles * g.c;
     const int lds = cov_lds_bytes();
-    hipError_t e0 = prepare_dynamic_lds((const void *)cov_eig_kernel, lds, 0);
-    if (e0 != hipSuccess) return e0;
-    hipLaunchKernelGGL(cov_eig_kernel, dim3(n_tiles * g.c), dim3(256), lds, st, g, tile, work);
-    hipError_t e = hipGetLastError();
+    hipError_t e = prepare_dynamic_lds((const void *)mom_kernel, lds, 0);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mom_kernel, dim3(units), dim3(256), lds, st, g, tile, mom);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(eig_kernel, dim3((units + EIG_WAVES - 1) / EIG_WAVES), dim3(64 * EIG_WAVES), 0, st, g, tile,
+                       units, (const int32_t *)mom, work);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(combine_sigma_kernel, dim3((n_tiles + 255) / 256), dim3(256), 0, st, work, g.c, n_tiles,
                        sigma_est);
     return hipGetLastError();
@@ -413,6 +562,42 @@ hipError_t launch_vote(const ImageGeom &g, const MethodParams &mp, const int32_t
     }
     HV_CASE(4) HV_CASE(8) HV_CASE(16) HV_CASE(32)
 #undef HV_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sigma_est_batched(const SigmaItem *items, const int *sel, const int *start, int n, int total,
+                                    int tile, int32_t *mom, hipStream_t st) {
+    if (tile != 128) return hipErrorInvalidValue;
+    if (n <= 0 || total <= 0) return hipSuccess;
+    const int lds = cov_lds_bytes();
+    hipError_t e = prepare_dynamic_lds((const void *)mom_kernel_batched, lds, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mom_kernel_batched, dim3(total), dim3(256), lds, st, items, sel, start, n, tile, mom);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(eig_kernel_batched, dim3((total + EIG_WAVES - 1) / EIG_WAVES), dim3(64 * EIG_WAVES), 0, st,
+                       items, sel, start, n, total, tile, (const int32_t *)mom);
+    return hipGetLastError();
+}
+
+hipError_t launch_sigma_tiles_batched(const SigmaItem *items, const int *sel, const int *start, int n, int total,
+                                      int tile, double ratio_bound, hipStream_t st) {
+    if (n <= 0 || total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sigma_tiles_batched_kernel, dim3((total + 255) / 256), dim3(256), 0, st, items, sel, start, n,
+                       total, tile, log(ratio_bound));
+    return hipGetLastError();
+}
+
+hipError_t launch_vote_batched(int K, const SigmaItem *items, const int *sel, const int *start, int n, int total,
+                               int tile, int n_vote, uint64_t seed, int gamma_rank, double beta, hipStream_t st) {
+    if (n <= 0 || total <= 0) return hipSuccess;
+#define HVB_CASE(KK)                                                                                             \
+    if (K == KK) {                                                                                               \
+        hipLaunchKernelGGL(vote_kernel_batched<KK>, dim3(total), dim3(256), 0, st, items, sel, start, n, tile,      \
+                           n_vote, seed, gamma_rank, beta);                                                     \
+        return hipGetLastError();                                                                                \
+    }
+    HVB_CASE(4) HVB_CASE(8) HVB_CASE(16) HVB_CASE(32)
+#undef HVB_CASE
     return hipErrorInvalidValue;
 }
 

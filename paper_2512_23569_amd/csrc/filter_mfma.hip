@@ -639,14 +639,28 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_kernel_batched(const Batc
     stage_ftab<C>(F, FL);
     const int total = unit_start[n_items];
     for (;;) {
-        if (threadIdx.x == 0) s_u = atomicAdd(queue, 1);
+        // thread 0 claims the next unit of an image filtered with this group size; units of an
+        // image that took the other size are skipped by moving the queue past the image's end
+        // (every value below the end that the queue then skips is one of its units).  The skip
+        // loop holds no barrier, so the block's barriers below stay on uniform paths.
+        if (threadIdx.x == 0) {
+            int c;
+            for (;;) {
+                c = atomicAdd(queue, 1);
+                if (c >= total) break;
+                const int ic = find_unit(unit_start, n_items, c);
+                const int *ks = items[ic].ksel;
+                if (!ks || *ks == K) break;
+                atomicMax(queue, unit_start[ic + 1]);
+            }
+            s_u = c;
+        }
         __syncthreads();
         const int u = s_u;
         __syncthreads();
         if (u >= total) break;
         const int i = find_unit(unit_start, n_items, u);
         const BatchItem it = items[i];
-        if (it.ksel && *it.ksel != K) continue;   // the image took the other group size (uniform per block)
         uint32_t *xb = reinterpret_cast<uint32_t *>(region + region_elems(it.tg, C));
         filter_tile_mfma<C, K>(it.g, it.tg, FL, F, T64, it.idx, it.idx_stride, it.tau, it.tau_mul, it.regions,
                                guard_count, u - unit_start[i], region, xb, sh);

@@ -1,5 +1,6 @@
 // Small utility kernels: buffer clearing and per-reference thresholds.
 #include "common.h"
+#include "sigma_dev.h"
 
 namespace htsvd {
 namespace {
@@ -21,58 +22,47 @@ __global__ void fill_tau_kernel(double *tau, int64_t n_ref, const double *sigma_
     if (r >= n_ref) return;
     double s = sigma_const;
     if (sigma_tile) {
-        const int iy = (int)(r / g.nx), ix = (int)(r % g.nx);
-        const int y = ref_pos(iy, g.ny, g.h, g.s), x = ref_pos(ix, g.nx, g.w, g.s);
-        const int ntx = (g.w + tile - 1) / tile;
-        s = sigma_tile[(y / tile) * ntx + x / tile];
+        int y, x;
+        s = sigma_tile[ref_tile(g, tile, r, &y, &x)];
     }
     tau[r] = s * mult;
 }
 
-// Per sub-image: the mean of the learned sigma over the tile's 8x8 blocks is compared with the
-// plain estimate; the plain value replaces the learned map where they differ by more than
-// ratio_bound (or the map is not finite).  sigma_tile = the value the tile then stands for.
+// Per sub-image: the learned map judged by the plain estimate (see judge_tile).
 __global__ void learned_judge_kernel(ImageGeom g, int tile, const float *zmap, const double *sigma_plain,
                                      double log_bound, int32_t *use_plain, double *sigma_tile) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int ntx = (g.w + tile - 1) / tile, nty = (g.h + tile - 1) / tile;
     if (t >= ntx * nty) return;
-    const int hb = (g.h + PS - 1) / PS, wb = (g.w + PS - 1) / PS, bpt = tile / PS;
-    const int ty = t / ntx, tx = t % ntx;
-    double sum = 0.0;
-    int n = 0;
-    for (int by = ty * bpt; by < min(hb, (ty + 1) * bpt); ++by)
-        for (int bx = tx * bpt; bx < min(wb, (tx + 1) * bpt); ++bx) {
-            sum += exp((double)zmap[by * wb + bx]);
-            ++n;
-        }
-    const double mean = n > 0 ? sum / n : 0.0;
-    const double sp = sigma_plain[t];
-    const bool ok = isfinite(mean) && mean > 0.0 && sp > 0.0 && fabs(log(mean / sp)) <= log_bound;
-    use_plain[t] = ok ? 0 : 1;
-    sigma_tile[t] = ok ? mean : sp;
+    sigma_tile[t] = judge_tile(g, tile, t, zmap, sigma_plain[t], log_bound, use_plain + t);
 }
 
-// tau of every reference: the learned sigma of the 8x8 block holding its top-left pixel, scaled
-// by its tile's vote (sigma_hat / sigma_est), or the tile's plain sigma_hat where the judge
-// rejected the map.
+// tau of every reference under the learned map (see learned_ref_sigma).
 __global__ void fill_tau_learned_kernel(double *tau, ImageGeom g, int tile, const float *zmap,
                                         const int32_t *use_plain, const double *sigma_est,
                                         const double *sigma_hat, double mult) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= (int64_t)g.ny * g.nx) return;
-    const int iy = (int)(r / g.nx), ix = (int)(r % g.nx);
-    const int y = ref_pos(iy, g.ny, g.h, g.s), x = ref_pos(ix, g.nx, g.w, g.s);
-    const int ntx = (g.w + tile - 1) / tile;
-    const int t = (y / tile) * ntx + x / tile;
+    tau[r] = learned_ref_sigma(g, tile, r, zmap, use_plain, sigma_est, sigma_hat) * mult;
+}
+
+// Batched thresholds of the images whose noise level went through the sub-image stages.
+__global__ void fill_tau_sigma_batched_kernel(const SigmaItem *__restrict__ items, const int *__restrict__ sel,
+                                              const int *__restrict__ start, int n, int total, int tile) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= total) return;
+    const int j = find_unit(start, n, u);
+    const SigmaItem &it = items[sel[j]];
+    const ImageGeom g = it.g;
+    const int64_t r = u - start[j];
     double s;
-    if (use_plain[t]) {
-        s = sigma_hat[t];
+    if (it.mode == SIGMA_LEARNED) {
+        s = learned_ref_sigma(g, tile, r, it.zmap, it.use_plain, it.sig_est, it.sig_hat);
     } else {
-        const int wb = (g.w + PS - 1) / PS;
-        s = exp((double)zmap[(y / PS) * wb + x / PS]) * (sigma_hat[t] / sigma_est[t]);
+        int y, x;
+        s = it.sig_hat[ref_tile(g, tile, r, &y, &x)];
     }
-    tau[r] = s * mult;
+    it.tau[r] = s * it.mult;
 }
 
 // Known noise levels of a batch: tau of every reference of image i = sigma[i] * mult[i].
@@ -87,32 +77,64 @@ __global__ void fill_tau_batched_kernel(const BatchItem *items, int n_items, con
 // Group size of each image in auto mode: the mean threshold over its references, divided by
 // the multiplier it was filled with, is the image's mean noise level; below the cutoff the
 // image is filtered with 16-member groups (the first half of its 32-member groups), else 32.
-// One block per image; a fixed-order tree keeps the decision deterministic.
-__global__ __launch_bounds__(256) void select_k_kernel(const BatchItem *__restrict__ items,
-                                                       const int *__restrict__ auto_list,
-                                                       const double *__restrict__ mult, double cutoff,
-                                                       int *__restrict__ ksel) {
-    __shared__ double part[256];
-    const int i = auto_list[blockIdx.x];
-    const BatchItem &it = items[i];
-    const int64_t n = (int64_t)it.g.ny * it.g.nx;
-    double acc = 0.0;
-    for (int64_t e = threadIdx.x; e < n; e += 256) acc += it.tau[e];
-    part[threadIdx.x] = acc;
+// Two passes with fixed-order trees keep the decision deterministic: chunks of SK_CHUNK
+// references are summed by one block each, then one block per image adds its chunk sums.
+constexpr int SK_CHUNK = 8192;
+
+__device__ inline double block_sum_256(double v, double *part) {
+    part[threadIdx.x] = v;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) ksel[i] = (part[0] / (double)n) / mult[i] < cutoff ? 16 : 32;
+    return part[0];
+}
+
+__global__ __launch_bounds__(256) void select_k_partial_kernel(const BatchItem *__restrict__ items,
+                                                               const int *__restrict__ auto_list, int n_chunk,
+                                                               double *__restrict__ partial) {
+    __shared__ double part[256];
+    const int a = blockIdx.y, c = blockIdx.x;
+    const BatchItem &it = items[auto_list[a]];
+    const int64_t n = (int64_t)it.g.ny * it.g.nx;
+    const int64_t e0 = (int64_t)c * SK_CHUNK, e1 = min(n, e0 + SK_CHUNK);
+    double acc = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) acc += it.tau[e];
+    const double tot = block_sum_256(acc, part);
+    if (threadIdx.x == 0) partial[(int64_t)a * n_chunk + c] = tot;
+}
+
+__global__ __launch_bounds__(256) void select_k_kernel(const BatchItem *__restrict__ items,
+                                                       const int *__restrict__ auto_list, int n_chunk,
+                                                       const double *__restrict__ partial,
+                                                       const double *__restrict__ mult, double cutoff,
+                                                       int *__restrict__ ksel) {
+    __shared__ double part[256];
+    const int a = blockIdx.x, i = auto_list[a];
+    const BatchItem &it = items[i];
+    const int64_t n = (int64_t)it.g.ny * it.g.nx;
+    const int used = (int)((n + SK_CHUNK - 1) / SK_CHUNK);
+    double acc = 0.0;
+    for (int c = threadIdx.x; c < used; c += 256) acc += partial[(int64_t)a * n_chunk + c];
+    const double tot = block_sum_256(acc, part);
+    if (threadIdx.x == 0) ksel[i] = (tot / (double)n) / mult[i] < cutoff ? 16 : 32;
 }
 
 }  // namespace
 
-hipError_t launch_select_k(const BatchItem *items, const int *auto_list, int n_auto, const double *mult,
-                           double cutoff, int *ksel, hipStream_t st) {
+int select_k_chunks(int64_t max_refs) { return (int)((max_refs + SK_CHUNK - 1) / SK_CHUNK); }
+
+hipError_t launch_select_k(const BatchItem *items, const int *auto_list, int n_auto, int n_chunk, double *partial,
+                           const double *mult, double cutoff, int *ksel, hipStream_t st) {
     if (n_auto <= 0) return hipSuccess;
-    hipLaunchKernelGGL(select_k_kernel, dim3(n_auto), dim3(256), 0, st, items, auto_list, mult, cutoff, ksel);
+    if (n_chunk < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(select_k_partial_kernel, dim3(n_chunk, n_auto), dim3(256), 0, st, items, auto_list, n_chunk,
+                       partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(select_k_kernel, dim3(n_auto), dim3(256), 0, st, items, auto_list, n_chunk, partial, mult,
+                       cutoff, ksel);
     return hipGetLastError();
 }
 
@@ -137,6 +159,14 @@ hipError_t launch_fill_tau_learned(double *tau, const ImageGeom &g, int tile, co
     const int64_t n = (int64_t)g.ny * g.nx;
     hipLaunchKernelGGL(fill_tau_learned_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tau, g, tile,
                        zmap, use_plain, sigma_est, sigma_hat, mult);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_tau_sigma_batched(const SigmaItem *items, const int *sel, const int *start, int n,
+                                         int total, int tile, hipStream_t st) {
+    if (n <= 0 || total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_tau_sigma_batched_kernel, dim3((total + 255) / 256), dim3(256), 0, st, items, sel, start,
+                       n, total, tile);
     return hipGetLastError();
 }
 
