@@ -33,7 +33,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int MW = 4;          // wavefronts per workgroup
+constexpr int MW = 8;          // wavefronts per workgroup (two per SIMD)
 constexpr int MNEAR = 64;      // near-threshold list capacity per wavefront
 constexpr float MGUARD = 0.05f;
 constexpr int XS = 33;         // words per row of the per-wave transpose buffer (32 + 1 pad)
@@ -153,16 +153,11 @@ __device__ inline int to_fixed(float v, float scale) {
 // 2^e for a small integer exponent (exact).
 __device__ inline float exp2i(int e) { return __int_as_float((e + 127) << 23); }
 
-// LDS bytes of the forward fragment table (kept in LDS for the whole kernel).
-template <int C>
-__device__ __host__ constexpr int ftab_bytes() {
-    return Frag<C>::NPAIR * 2 * 64 * 16;
-}
-
 // One reference tile: every group of the tile, 32 patches (32/K groups) per wavefront step.
-//   FL: forward fragments in LDS ([term][pair][lane]); FG: global table (inverse at dir 1).
+//   FG: fragment tables (forward at dir 0, inverse at dir 1), read through the caches; the
+//   eight wavefronts of a workgroup share them and the tile's LDS region.
 template <int C, int K>
-__device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileGeom &tg, const v8h *FL,
+__device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileGeom &tg,
                                                  const v8h *__restrict__ FG, const double *__restrict__ T64,
                                                  const int32_t *__restrict__ idx, const int idx_stride,
                                                  const double *__restrict__ tau_ref, const double tau_mul,
@@ -213,7 +208,7 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             return (int64_t)(iy0 + t / nx_t) * g.nx + (ix0 + t % nx_t);
         };
         // ---- this lane's patch: A operands of the forward products (pixel rows 2 sp + h) ----
-        v8h fa0[4], far[4], fai[4];
+        uint32_t raw[4][2 * C];   // pixel rows 2 sp + h of this lane's patch (8 C bytes each)
         int off_in;   // region offset of the patch (for the aggregation, shared by lane shuffles)
         {
             const int64_t r_in = ref_of(mu_in / K);
@@ -223,21 +218,7 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             if (h == 0 && (full || base + mu_in / K < nref)) atomicAdd(hist + off_in, 1);
             const uint8_t *pin = g.img + (int64_t)yin * g.stride + (int64_t)xin * C;
 #pragma unroll
-            for (int sp = 0; sp < 4; ++sp) {
-                uint32_t wv[2 * C];
-                load_row_u8<C>(pin + (int64_t)(2 * sp + h) * g.stride, img_end, wv);
-#pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    if (C == 3) {
-                        const int R = byte_of(wv, 3 * b), Gc = byte_of(wv, 3 * b + 1), Bc = byte_of(wv, 3 * b + 2);
-                        fa0[sp][b] = (_Float16)(float)(R + Gc + Bc);
-                        far[sp][b] = (_Float16)(float)(2 * R - Gc - Bc);
-                        fai[sp][b] = (_Float16)(float)(Bc - Gc);
-                    } else {
-                        fa0[sp][b] = (_Float16)(float)byte_of(wv, b);
-                    }
-                }
-            }
+            for (int sp = 0; sp < 4; ++sp) load_row_u8<C>(pin + (int64_t)(2 * sp + h) * g.stride, img_end, raw[sp]);
         }
         // ---- thresholds of the groups this lane half holds ----
         // per (group slot, butterfly count l): keep-or-undecided above lo, undecided below hi
@@ -272,34 +253,41 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
         // two passes over the coefficient positions 32 tp + c (tp = 0, 1)
 #pragma unroll 1
         for (int tp = 0; tp < 2; ++tp) {
-            // inverse fragments of the first chunk, fetched early (global, L2-resident)
-            v8h bh[8], bl[8];
+            // the raw bytes are converted again in each pass (keeps the converted operands short-lived)
 #pragma unroll
-            for (int ss = 0; ss < 2; ++ss)
+            for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const int pr = pair_of<C>(t, 2 * tp + ss);
-                    bh[ss * 2 + t] = ldfrag(FG, 1, 0, pr, NPAIR, lane);
-                    bl[ss * 2 + t] = ldfrag(FG, 1, 1, pr, NPAIR, lane);
-                }
-            // ---- forward products for the tiles (slice, tp), fragments from LDS ----
+                for (int i = 0; i < 2 * C; ++i) asm volatile("" : "+v"(raw[sp][i]));
+            // ---- forward products for the tiles (slice, tp) ----
             v16f acc[C];
 #pragma unroll
             for (int sl = 0; sl < C; ++sl) acc[sl] = (v16f){};
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp) {
+                v8h a0, ar, ai;
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    if (C == 3) {
+                        const int R = byte_of(raw[sp], 3 * b), Gc = byte_of(raw[sp], 3 * b + 1), Bc = byte_of(raw[sp], 3 * b + 2);
+                        a0[b] = (_Float16)(float)(R + Gc + Bc);
+                        ar[b] = (_Float16)(float)(2 * R - Gc - Bc);
+                        ai[b] = (_Float16)(float)(Bc - Gc);
+                    } else {
+                        a0[b] = (_Float16)(float)byte_of(raw[sp], b);
+                    }
+                }
                 const int p0 = pair_of<C>(tp, sp);
-                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fa0[sp], FL[(0 * NPAIR + p0) * 64 + lane], acc[0], 0, 0, 0);
-                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fa0[sp], FL[(1 * NPAIR + p0) * 64 + lane], acc[0], 0, 0, 0);
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, ldfrag(FG, 0, 0, p0, NPAIR, lane), acc[0], 0, 0, 0);
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, ldfrag(FG, 0, 1, p0, NPAIR, lane), acc[0], 0, 0, 0);
                 if (C == 3) {
 #pragma unroll
                     for (int sl = 1; sl < C; ++sl) {
                         const int t = 2 * sl + tp;
                         const int pr = pair_of<C>(t, 4 + sp), pi = pair_of<C>(t, 8 + sp);
-                        acc[sl] = __builtin_amdgcn_mfma_f32_32x32x16_f16(far[sp], FL[(0 * NPAIR + pr) * 64 + lane], acc[sl], 0, 0, 0);
-                        acc[sl] = __builtin_amdgcn_mfma_f32_32x32x16_f16(far[sp], FL[(1 * NPAIR + pr) * 64 + lane], acc[sl], 0, 0, 0);
-                        acc[sl] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fai[sp], FL[(0 * NPAIR + pi) * 64 + lane], acc[sl], 0, 0, 0);
-                        acc[sl] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fai[sp], FL[(1 * NPAIR + pi) * 64 + lane], acc[sl], 0, 0, 0);
+                        acc[sl] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ar, ldfrag(FG, 0, 0, pr, NPAIR, lane), acc[sl], 0, 0, 0);
+                        acc[sl] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ar, ldfrag(FG, 0, 1, pr, NPAIR, lane), acc[sl], 0, 0, 0);
+                        acc[sl] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ai, ldfrag(FG, 0, 0, pi, NPAIR, lane), acc[sl], 0, 0, 0);
+                        acc[sl] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ai, ldfrag(FG, 0, 1, pi, NPAIR, lane), acc[sl], 0, 0, 0);
                     }
                 }
             }
@@ -475,19 +463,6 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                 const int j = 2 * sl + tp;   // tile of the k dimension
                 constexpr int NTMAX = C == 3 ? 4 : 2;
                 const int tlo = sl == 0 ? 0 : 2, ntile = sl == 0 ? 2 : 4;
-                // prefetch the next chunk's fragments
-                v8h nh[2 * NTMAX], nl[2 * NTMAX];
-                if (sl + 1 < C) {
-                    const int jn = 2 * (sl + 1) + tp;
-#pragma unroll
-                    for (int ss = 0; ss < 2; ++ss)
-#pragma unroll
-                        for (int tt = 0; tt < 4; ++tt) {
-                            const int pr = pair_of<C>(2 + tt, 2 * jn + ss);
-                            nh[ss * 4 + tt] = ldfrag(FG, 1, 0, pr, NPAIR, lane);
-                            nl[ss * 4 + tt] = ldfrag(FG, 1, 1, pr, NPAIR, lane);
-                        }
-                }
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const float v = acc[sl][r];
@@ -509,20 +484,14 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
 #pragma unroll
                     for (int tt = 0; tt < ntile; ++tt) {
                         const int t = tlo + tt;
-                        const int fi = ss * ntile + tt;
-                        out[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, bh[fi], out[t], 0, 0, 0);
-                        out[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, bl[fi], out[t], 0, 0, 0);
-                        out[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, bh[fi], out[t], 0, 0, 0);
+                        const int pr = pair_of<C>(t, 2 * j + ss);
+                        const v8h fbh = ldfrag(FG, 1, 0, pr, NPAIR, lane), fbl = ldfrag(FG, 1, 1, pr, NPAIR, lane);
+                        out[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, fbh, out[t], 0, 0, 0);
+                        out[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, fbl, out[t], 0, 0, 0);
+                        out[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, fbh, out[t], 0, 0, 0);
                     }
                 }
                 wave_lds_fence();
-                if (sl + 1 < C) {
-#pragma unroll
-                    for (int f = 0; f < 8; ++f) {
-                        bh[f] = nh[f];
-                        bl[f] = nl[f];
-                    }
-                }
             }
         }
 
@@ -590,14 +559,6 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
     for (int e = tid; e < relems; e += MW * 64) dst[e] = (float)iregion[e] * (e < C * plane ? unscale : 1.f);
 }
 
-// Copies the forward fragment table into LDS (once per workgroup).
-template <int C>
-__device__ inline void stage_ftab(const v8h *__restrict__ FG, v8h *FL) {
-    constexpr int N = Frag<C>::NPAIR * 2 * 64;   // dir 0: [term][pair][lane]
-    for (int e = threadIdx.x; e < N; e += MW * 64) FL[e] = FG[e];
-    __syncthreads();
-}
-
 // Persistent over the tiles of one image: workgroup b takes tiles b, b + grid, ... in an
 // XCD-aware order (consecutive ids go round-robin over the 8 XCDs; with grid a multiple of 8
 // each workgroup stays in one class, whose tiles form a contiguous run).
@@ -610,16 +571,14 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_kernel(ImageGeom g, TileG
                                                              unsigned long long *__restrict__ guard_count) {
     extern __shared__ __align__(16) float smem[];
     __shared__ MfmaShared sh;
-    v8h *FL = reinterpret_cast<v8h *>(smem);
-    float *region = smem + ftab_bytes<C>() / 4;
+    float *region = smem;
     uint32_t *xb = reinterpret_cast<uint32_t *>(region + region_elems(tg, C));
-    stage_ftab<C>(F, FL);
     const int n_tiles = tg.tiles_y * tg.tiles_x;
     const int per = (n_tiles + 7) / 8;
     for (int v = blockIdx.x; v < 8 * per; v += gridDim.x) {
         const int tile = (v & 7) * per + (v >> 3);
         if (tile >= n_tiles) continue;
-        filter_tile_mfma<C, K>(g, tg, FL, F, T64, idx, K, tau_ref, 1.0, regions, guard_count, tile, region, xb, sh);
+        filter_tile_mfma<C, K>(g, tg, F, T64, idx, K, tau_ref, 1.0, regions, guard_count, tile, region, xb, sh);
         __syncthreads();
     }
 }
@@ -634,9 +593,7 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_kernel_batched(const Batc
     extern __shared__ __align__(16) float smem[];
     __shared__ MfmaShared sh;
     __shared__ int s_u;
-    v8h *FL = reinterpret_cast<v8h *>(smem);
-    float *region = smem + ftab_bytes<C>() / 4;
-    stage_ftab<C>(F, FL);
+    float *region = smem;
     const int total = unit_start[n_items];
     for (;;) {
         // thread 0 claims the next unit of an image filtered with this group size; units of an
@@ -662,7 +619,7 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_kernel_batched(const Batc
         const int i = find_unit(unit_start, n_items, u);
         const BatchItem it = items[i];
         uint32_t *xb = reinterpret_cast<uint32_t *>(region + region_elems(it.tg, C));
-        filter_tile_mfma<C, K>(it.g, it.tg, FL, F, T64, it.idx, it.idx_stride, it.tau, it.tau_mul, it.regions,
+        filter_tile_mfma<C, K>(it.g, it.tg, F, T64, it.idx, it.idx_stride, it.tau, it.tau_mul, it.regions,
                                guard_count, u - unit_start[i], region, xb, sh);
         __syncthreads();
     }
@@ -671,10 +628,13 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_kernel_batched(const Batc
 }  // namespace
 
 int filter_mfma_lds_bytes(const TileGeom &tg, int C) {
-    return (C == 3 ? ftab_bytes<3>() : ftab_bytes<1>()) + region_elems(tg, C) * 4 + MW * XWORDS * 4;
+    return region_elems(tg, C) * 4 + MW * XWORDS * 4;
 }
 
-int filter_mfma_group_bytes(int C) { return (C == 3 ? ftab_bytes<3>() : ftab_bytes<1>()) + MW * XWORDS * 4; }
+int filter_mfma_group_bytes(int C) {
+    (void)C;
+    return MW * XWORDS * 4;
+}
 
 int filter_mfma_static_bytes() { return (int)sizeof(MfmaShared) + 16; }
 
