@@ -60,10 +60,33 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
-    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-    lo = __shfl_xor(lo, m);
-    hi = __shfl_xor(hi, m);
+// Value of v in lane (lane ^ j) for j = 1, 2, 4, 8, 16, 32, by register moves between lanes
+// (DPP within a row of 16 lanes, the row-swap instructions across rows), no LDS round trip.
+//   j = 1, 2: quad permutations; j = 4, 8: row shift left (lane i reads i + j) for lanes with
+//   bit j clear, row shift right (reads i - j) for the others; j = 16, 32: permlane swaps.
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int j, int lane) {
+    if (j == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);   // [1,0,3,2]
+    if (j == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);   // [2,3,0,1]
+    if (j == 4) {
+        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x104, 0xF, 0xF, true);
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x114, 0xF, 0xF, true);
+        return (lane & 4) ? dn : up;
+    }
+    if (j == 8) {
+        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x108, 0xF, 0xF, true);
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x118, 0xF, 0xF, true);
+        return (lane & 8) ? dn : up;
+    }
+    if (j == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    }
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane & 32) ? r[0] : r[1];
+}
+
+__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v, int j, int lane) {
+    const uint32_t lo = xor_lane((uint32_t)v, j, lane), hi = xor_lane((uint32_t)(v >> 32), j, lane);
     return ((uint64_t)hi << 32) | lo;
 }
 
@@ -79,7 +102,7 @@ __device__ inline uint64_t wave_sort64(uint64_t v, int lane) {
     for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            uint64_t p = shfl_xor_u64(v, j);
+            uint64_t p = xor_lane_u64(v, j, lane);
             bool up = (lane & k) == 0;
             bool lower = (lane & j) == 0;
             uint64_t mn = v < p ? v : p, mx = v < p ? p : v;
@@ -288,10 +311,19 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
         }
         const int nU = uh * uw;
         const int nchunks = (nU + 15) >> 4;
+        // candidate j = 16 chunk + i16 at (row, column) = (j / uw, j % uw), stepped by 16 BMW
+        constexpr int JSTEP = 16 * BMW;
+        const int step_r = JSTEP / uw, step_c = JSTEP % uw;
+        int jr = (16 * wave + i16) / uw, jc = (16 * wave + i16) % uw;
         for (int chunk = wave; chunk < nchunks; chunk += BMW) {
             const int j = chunk * 16 + i16;
-            const int jj = j < nU ? j : 0;
-            const int cr = jj / uw, cc = jj % uw;
+            const int cr = j < nU ? jr : 0, cc = j < nU ? jc : 0;
+            jr += step_r;
+            jc += step_c;
+            if (jc >= uw) {
+                jc -= uw;
+                ++jr;
+            }
             v4i b8;
             {
                 const int k = cc & 3;
@@ -304,13 +336,13 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
             acc8 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a8, b8, acc8, 0, 0, 0);
             v4f acc16 = {0.f, 0.f, 0.f, 0.f};
             if (any_sum) {
+                // 8 halves from the copy in which they start on a dword (pitch and offsets even)
                 const int k = cc & 1;
                 const _Float16 *base = p16 + k * plane16;
-                const _Float16 *ra = base + (cr + q) * L.pitch16 + cc - k;
-                const _Float16 *rb = base + (cr + q + 4) * L.pitch16 + cc - k;
-                v8h b16a, b16b;
-#pragma unroll
-                for (int t = 0; t < 8; ++t) { b16a[t] = ra[t]; b16b[t] = rb[t]; }
+                const uint32_t *ra = reinterpret_cast<const uint32_t *>(base + (cr + q) * L.pitch16 + cc - k);
+                const uint32_t *rb = reinterpret_cast<const uint32_t *>(base + (cr + q + 4) * L.pitch16 + cc - k);
+                const v8h b16a = __builtin_bit_cast(v8h, make_uint4(ra[0], ra[1], ra[2], ra[3]));
+                const v8h b16b = __builtin_bit_cast(v8h, make_uint4(rb[0], rb[1], rb[2], rb[3]));
                 acc16 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a16a, b16a, acc16, 0, 0, 0);
                 acc16 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a16b, b16b, acc16, 0, 0, 0);
             }
@@ -337,23 +369,32 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
         if (ti.ry[ii] < 0) continue;
         const int n = ti.wh[ii] * ti.ww[ii];
         const uint32_t *row = tab + ii * MAX_CAND;
+        // this lane's candidates p = lane + 64 i, read once; key = (distance, position)
+        constexpr int NPL = (MAX_CAND + 63) / 64;
+        uint32_t dv[NPL];
         uint64_t lmin = ~0ull;
-        for (int p = lane; p < n; p += 64) {
-            const uint64_t key = ((uint64_t)row[p] << 10) | (uint64_t)p;
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+            const int p = lane + 64 * i;
+            dv[i] = p < n ? row[p] : 0xFFFFFFFFu;
+            const uint64_t key = p < n ? (((uint64_t)dv[i] << 10) | (uint64_t)p) : ~0ull;
             lmin = key < lmin ? key : lmin;
         }
         const uint64_t sorted = wave_sort64(lmin, lane);
         const uint64_t theta = readlane_u64(sorted, K - 1);
         int cnt = 0;
-        for (int p = lane; p < n; p += 64) {
-            const uint64_t key = ((uint64_t)row[p] << 10) | (uint64_t)p;
-            cnt += key <= theta;
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+            const int p = lane + 64 * i;
+            cnt += (p < n && (((uint64_t)dv[i] << 10) | (uint64_t)p) <= theta);
         }
         int total;
         int off = wave_excl_scan(cnt, lane, &total);
-        for (int p = lane; p < n; p += 64) {
-            const uint64_t key = ((uint64_t)row[p] << 10) | (uint64_t)p;
-            if (key <= theta) sel[off++] = key;
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+            const int p = lane + 64 * i;
+            const uint64_t key = ((uint64_t)dv[i] << 10) | (uint64_t)p;
+            if (p < n && key <= theta) sel[off++] = key;
         }
         wave_lds_sync();
         uint64_t mine;
