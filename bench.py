@@ -288,7 +288,8 @@ def bench_batch(dn, args, autotune, stream):
                             "k_sigma_cutoff": cutoff},
         "speedup": round(ms_plain / ms_bl, 3),
         "dpsnr_db": round(dps, 3),
-        "equal_psnr": bool(dps >= -0.05),
+        "psnr_within_0p05_db": bool(abs(dps) <= 0.05),
+        "psnr_not_worse_than_0p05_db": bool(dps >= -0.05),
         "unit": "Mpixel/s",
         "gen_s": round(gen_s, 1), "tune_s": round(tune_s, 1), "launch_candidates": allr,
     }

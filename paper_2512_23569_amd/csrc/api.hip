@@ -345,8 +345,7 @@ htsvd_status validate_crops(htsvd_ctx *ctx, const uint8_t *d, int32_t n, int32_t
 }
 
 // Learned log-sigma map of one image into the network workspace; returns its device pointer.
-htsvd_status run_cnn_map(htsvd_ctx *ctx, const ImageGeom &g, hipStream_t st, const float **zmap,
-                         float *z_out = nullptr) {
+htsvd_status run_cnn_map(htsvd_ctx *ctx, const ImageGeom &g, hipStream_t st, const float **zmap) {
     CnnState &cs = ctx->cnn;
     if (!cs.w) return fail(HTSVD_ESTATE, "learned estimator requested but no network weights are set");
     if (cs.c != g.c) return fail(HTSVD_EINVAL, "network channel count differs from the image's");
@@ -355,11 +354,9 @@ htsvd_status run_cnn_map(htsvd_ctx *ctx, const ImageGeom &g, hipStream_t st, con
     if (s != HTSVD_OK) return s;
     CnnWs w = plan_cnn_ws(cs.ws, 1, g.h, g.w, g.c, false);
     StageScope sc(ctx, HTSVD_STAGE_SIGMA, st);
-    CnnBuffers cb = cnn_buffers(cs, w);
-    if (z_out) cb.z = z_out;
-    hipError_t e = cnn_forward(cb, g.img, g.stride, 0, 1, g.h, g.w, g.c, st);
+    hipError_t e = cnn_forward(cnn_buffers(cs, w), g.img, g.stride, 0, 1, g.h, g.w, g.c, st);
     if (e != hipSuccess) return hip_fail(e, "network forward");
-    *zmap = cb.z;
+    *zmap = w.z;
     return HTSVD_OK;
 }
 
@@ -956,12 +953,21 @@ struct BatchImage {
     float sigma;
 };
 
+// Learned images of one size: one network run over all of them, their maps contiguous.
+struct CnnClass {
+    int h, w;
+    std::vector<int> members;   // indices into BatchPlan::im
+    size_t ws_bytes;            // network workspace for the class
+};
+
 // Host plan of a batch: workspace layout, unit tables, per-class descriptor lists.
 struct BatchPlan {
     std::vector<BatchImage> im;
     std::vector<int> classes;                     // distinct K values
     size_t ws_total = 0;
     size_t off_mom = 0;                           // plain-estimator moments of all estimated images
+    std::vector<CnnClass> cnn;                    // learned images grouped by size
+    size_t cnn_ws = 0;                            // largest network workspace of a class
     int max_s = 1, max_W = 3, max_h = 8, max_w = 8;
     bool any_auto = false;
 };
@@ -1013,16 +1019,29 @@ htsvd_status plan_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, cons
         off = align256(off + reg);
         b.off_sig = off;  // sig_est, sig_hat, votes, cov (c per tile), use_plain, sig_plain
         off = align256(off + b.n_tiles_sigma * (sizeof(double) * (3 + b.g.c) + 2 * sizeof(int32_t)));
-        if (b.learned) {
-            b.off_z = off;
-            off = align256(off + sizeof(float) * cnn_act_elems(6, 1, b.g.h, b.g.w, b.g.c));
-        }
         P.max_s = std::max(P.max_s, b.g.s);
         P.max_W = std::max(P.max_W, b.mp.W);
         P.max_h = std::max(P.max_h, b.g.h);
         P.max_w = std::max(P.max_w, b.g.w);
         if (std::find(P.classes.begin(), P.classes.end(), b.mp.K) == P.classes.end()) P.classes.push_back(b.mp.K);
         if (b.auto_k && std::find(P.classes.begin(), P.classes.end(), 16) == P.classes.end()) P.classes.push_back(16);
+    }
+    // learned maps: one contiguous block per size class (the network writes a class at once)
+    for (size_t i = 0; i < P.im.size(); ++i) {
+        const BatchImage &b = P.im[i];
+        if (!b.learned) continue;
+        size_t k = 0;
+        while (k < P.cnn.size() && !(P.cnn[k].h == b.g.h && P.cnn[k].w == b.g.w)) ++k;
+        if (k == P.cnn.size()) P.cnn.push_back(CnnClass{b.g.h, b.g.w, {}, 0});
+        P.cnn[k].members.push_back((int)i);
+    }
+    for (CnnClass &cc : P.cnn) {
+        const int c = P.im[cc.members[0]].g.c;
+        const size_t zone = sizeof(float) * cnn_act_elems(6, 1, cc.h, cc.w, c);
+        for (size_t n = 0; n < cc.members.size(); ++n) P.im[cc.members[n]].off_z = off + n * zone;
+        off = align256(off + zone * cc.members.size());
+        cc.ws_bytes = plan_cnn_ws(nullptr, (int)cc.members.size(), cc.h, cc.w, c, false).total;
+        P.cnn_ws = std::max(P.cnn_ws, cc.ws_bytes);
     }
     int64_t mom_units = 0;
     for (const BatchImage &b : P.im)
@@ -1111,13 +1130,12 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
     const int ni = (int)P.im.size();
     const int C = P.im[0].g.c;
     const bool learned_any = p->estimator == 1;
-    for (const BatchImage &b : P.im)
-        if (b.sigma == HTSVD_SIGMA_AUTO && learned_any) {
-            if (!ctx->cnn.w) return fail(HTSVD_ESTATE, "learned estimator requested but no network weights are set");
-            CnnWs cw = plan_cnn_ws(nullptr, 1, P.max_h, P.max_w, C, false);
-            if ((s = ensure_cnn_ws(ctx, cw.total)) != HTSVD_OK) return s;
-            break;
-        }
+    (void)learned_any;
+    if (!P.cnn.empty()) {
+        if (!ctx->cnn.w) return fail(HTSVD_ESTATE, "learned estimator requested but no network weights are set");
+        if (ctx->cnn.c != C) return fail(HTSVD_EINVAL, "network channel count differs from the images'");
+        if ((s = ensure_cnn_ws(ctx, P.cnn_ws)) != HTSVD_OK) return s;
+    }
     if ((s = ensure_ws(ctx, P.ws_total)) != HTSVD_OK) return s;
 
     // descriptor tables (host), then one upload
@@ -1233,6 +1251,12 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
         ref_st.push_back(ref_st.back() + (int)b.n_ref);
     }
     const size_t o_sitems = reserve(sizeof(SigmaItem) * std::max<size_t>(1, sitems.size()));
+    // per size class of learned images: their input pointers and row strides
+    std::vector<size_t> o_ctab(P.cnn.size()), o_cstr(P.cnn.size());
+    for (size_t k = 0; k < P.cnn.size(); ++k) {
+        o_ctab[k] = reserve(sizeof(const uint8_t *) * P.cnn[k].members.size());
+        o_cstr[k] = reserve(sizeof(int64_t) * P.cnn[k].members.size());
+    }
     auto reserve_ints = [&](const std::vector<int> &v) { return reserve(sizeof(int) * std::max<size_t>(1, v.size())); };
     const size_t o_cov_sel = reserve_ints(cov_sel), o_cov_st = reserve_ints(cov_st);
     const size_t o_tile_sel = reserve_ints(tile_sel), o_tile_st = reserve_ints(tile_st);
@@ -1283,6 +1307,12 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
     memcpy(host.data() + o_ksel, ksel_h.data(), sizeof(int) * ni);
     if (!auto_list.empty()) memcpy(host.data() + o_auto, auto_list.data(), sizeof(int) * auto_list.size());
     if (!sitems.empty()) memcpy(host.data() + o_sitems, sitems.data(), sizeof(SigmaItem) * sitems.size());
+    for (size_t k = 0; k < P.cnn.size(); ++k)
+        for (size_t n = 0; n < P.cnn[k].members.size(); ++n) {
+            const ImageGeom &gk = P.im[P.cnn[k].members[n]].g;
+            memcpy(host.data() + o_ctab[k] + n * sizeof(const uint8_t *), &gk.img, sizeof(const uint8_t *));
+            memcpy(host.data() + o_cstr[k] + n * sizeof(int64_t), &gk.stride, sizeof(int64_t));
+        }
     auto put_ints = [&](size_t o2, const std::vector<int> &v) {
         if (!v.empty()) memcpy(host.data() + o2, v.data(), sizeof(int) * v.size());
     };
@@ -1336,11 +1366,15 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
             StageScope sc(ctx, HTSVD_STAGE_SIGMA, ls);
             const int T = p->subimage;
             const SigmaItem *S = (const SigmaItem *)(D + o_sitems);
-            for (const SigmaItem &si : sitems) {
-                if (si.mode != SIGMA_LEARNED) continue;
-                const float *zmap = nullptr;
-                htsvd_status s2 = run_cnn_map(ctx, si.g, ls, &zmap, const_cast<float *>(si.zmap));
-                if (s2 != HTSVD_OK) return s2;
+            // the network once per size class, writing the class's contiguous maps
+            for (size_t k = 0; k < P.cnn.size(); ++k) {
+                const CnnClass &cc = P.cnn[k];
+                const int m = (int)cc.members.size();
+                CnnBuffers cb = cnn_buffers(ctx->cnn, plan_cnn_ws(ctx->cnn.ws, m, cc.h, cc.w, C, false));
+                cb.z = (float *)((char *)ctx->ws + P.im[cc.members[0]].off_z);
+                if ((e2 = cnn_forward_tab(cb, (const uint8_t *const *)(D + o_ctab[k]), (const int64_t *)(D + o_cstr[k]),
+                                          m, cc.h, cc.w, C, ls)) != hipSuccess)
+                    return hip_fail(e2, "network forward");
             }
             auto I = [&](size_t o2) { return (const int *)(D + o2); };
             if ((e2 = launch_sigma_est_batched(S, I(o_cov_sel), I(o_cov_st), (int)cov_sel.size(), cov_st.back(), T,

@@ -60,31 +60,6 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Value of v in lane (lane ^ j) for j = 1, 2, 4, 8, 16, 32, by register moves between lanes
-// (DPP within a row of 16 lanes, the row-swap instructions across rows), no LDS round trip.
-//   j = 1, 2: quad permutations; j = 4, 8: row shift left (lane i reads i + j) for lanes with
-//   bit j clear, row shift right (reads i - j) for the others; j = 16, 32: permlane swaps.
-__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int j, int lane) {
-    if (j == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);   // [1,0,3,2]
-    if (j == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);   // [2,3,0,1]
-    if (j == 4) {
-        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x104, 0xF, 0xF, true);
-        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x114, 0xF, 0xF, true);
-        return (lane & 4) ? dn : up;
-    }
-    if (j == 8) {
-        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x108, 0xF, 0xF, true);
-        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x118, 0xF, 0xF, true);
-        return (lane & 8) ? dn : up;
-    }
-    if (j == 16) {
-        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-        return (lane & 16) ? r[0] : r[1];
-    }
-    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-    return (lane & 32) ? r[0] : r[1];
-}
-
 __device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v, int j, int lane) {
     const uint32_t lo = xor_lane((uint32_t)v, j, lane), hi = xor_lane((uint32_t)(v >> 32), j, lane);
     return ((uint64_t)hi << 32) | lo;

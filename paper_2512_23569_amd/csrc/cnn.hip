@@ -48,10 +48,14 @@ struct ConvShape {
 
 // ---- layer 1: u8 image -> 32 channels, vector ALU ----
 // One thread per output pixel; the 9 C input taps stay in registers, the weights are uniform
-// across the wavefront (scalar loads), the 32 outputs leave as four 16-byte stores.
+// across the wavefront (scalar loads), the 32 outputs leave as four 16-byte stores.  Image n
+// starts at img + n img_batch_stride with row stride img_stride, or, with a table, at
+// img_tab[n] with row stride stride_tab[n] (images of one size in separate buffers).
 template <int C>
 __global__ __launch_bounds__(256) void l1_fwd_kernel(const uint8_t *__restrict__ img, int64_t img_stride,
-                                                     int64_t img_batch_stride, ConvShape cs,
+                                                     int64_t img_batch_stride,
+                                                     const uint8_t *const *__restrict__ img_tab,
+                                                     const int64_t *__restrict__ stride_tab, ConvShape cs,
                                                      const float *__restrict__ wq, const float *__restrict__ bias,
                                                      uint16_t *__restrict__ out) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -60,6 +64,8 @@ __global__ __launch_bounds__(256) void l1_fwd_kernel(const uint8_t *__restrict__
     const int n = (int)(p / ((int64_t)cs.Ho * cs.Wo));
     const int rem = (int)(p % ((int64_t)cs.Ho * cs.Wo));
     const int yo = rem / cs.Wo, xo = rem % cs.Wo;
+    const uint8_t *ibase = img_tab ? img_tab[n] : img + n * img_batch_stride;
+    const int64_t rs = img_tab ? stride_tab[n] : img_stride;
     float x[9 * C];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
@@ -68,7 +74,7 @@ __global__ __launch_bounds__(256) void l1_fwd_kernel(const uint8_t *__restrict__
 #pragma unroll
         for (int ci = 0; ci < C; ++ci) x[t * C + ci] = 0.f;
         if (ok) {
-            const uint8_t *src = img + n * img_batch_stride + (int64_t)yi * img_stride + (int64_t)xi * C;
+            const uint8_t *src = ibase + (int64_t)yi * rs + (int64_t)xi * C;
 #pragma unroll
             for (int ci = 0; ci < C; ++ci) x[t * C + ci] = ((float)src[ci] - 128.f) * 0.015625f;
         }
@@ -309,18 +315,19 @@ size_t cnn_act_elems(int l, int N, int H, int W, int c) {
     return (size_t)cs.N * cs.Ho * cs.Wo * cs.Co;
 }
 
-hipError_t cnn_forward(const CnnBuffers &b, const uint8_t *img, int64_t img_stride, int64_t img_batch_stride,
-                       int N, int H, int W, int c, hipStream_t st) {
+static hipError_t forward_impl(const CnnBuffers &b, const uint8_t *img, int64_t img_stride,
+                               int64_t img_batch_stride, const uint8_t *const *img_tab, const int64_t *stride_tab,
+                               int N, int H, int W, int c, hipStream_t st) {
     int wo[6], bo[6], tot;
     cnn_layout(c, wo, bo, &tot);
     ConvShape cs = shape_of(0, N, H, W, c);
     int64_t np = (int64_t)cs.N * cs.Ho * cs.Wo;
     if (c == 3)
         hipLaunchKernelGGL(l1_fwd_kernel<3>, dim3(blocks_for(np, 256)), dim3(256), 0, st, img, img_stride,
-                           img_batch_stride, cs, b.wq + wo[0], b.wq + bo[0], b.act[1]);
+                           img_batch_stride, img_tab, stride_tab, cs, b.wq + wo[0], b.wq + bo[0], b.act[1]);
     else if (c == 1)
         hipLaunchKernelGGL(l1_fwd_kernel<1>, dim3(blocks_for(np, 256)), dim3(256), 0, st, img, img_stride,
-                           img_batch_stride, cs, b.wq + wo[0], b.wq + bo[0], b.act[1]);
+                           img_batch_stride, img_tab, stride_tab, cs, b.wq + wo[0], b.wq + bo[0], b.act[1]);
     else
         return hipErrorInvalidValue;
     for (int l = 1; l < 5; ++l) {
@@ -337,6 +344,17 @@ hipError_t cnn_forward(const CnnBuffers &b, const uint8_t *img, int64_t img_stri
     hipLaunchKernelGGL(l6_fwd_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, b.act[5], cs, b.wq + wo[5],
                        b.wq + bo[5], b.z);
     return hipGetLastError();
+}
+
+hipError_t cnn_forward(const CnnBuffers &b, const uint8_t *img, int64_t img_stride, int64_t img_batch_stride,
+                       int N, int H, int W, int c, hipStream_t st) {
+    return forward_impl(b, img, img_stride, img_batch_stride, nullptr, nullptr, N, H, W, c, st);
+}
+
+hipError_t cnn_forward_tab(const CnnBuffers &b, const uint8_t *const *img_tab, const int64_t *stride_tab, int N,
+                           int H, int W, int c, hipStream_t st) {
+    if (!img_tab || !stride_tab) return hipErrorInvalidValue;
+    return forward_impl(b, nullptr, 0, 0, img_tab, stride_tab, N, H, W, c, st);
 }
 
 // Backward pass: grads (FP32, zeroed here) of mean |z - target|; d0/d1 are FP32 scratch

@@ -101,6 +101,38 @@ __device__ inline int find_unit(const int *start, int n, int u) {
     return lo;
 }
 
+// Value of v in lane (lane ^ j) for j = 1, 2, 4, 8, 16, 32, by register moves between lanes
+// (DPP within a row of 16 lanes, the row-swap instructions across rows), no LDS round trip.
+//   j = 1, 2: quad permutations; j = 4, 8: row shift left (lane i reads i + j) for lanes with
+//   bit j clear, row shift right (reads i - j) for the others; j = 16, 32: permlane swaps.
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int j, int lane) {
+    if (j == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);   // [1,0,3,2]
+    if (j == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);   // [2,3,0,1]
+    if (j == 4) {
+        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x104, 0xF, 0xF, true);
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x114, 0xF, 0xF, true);
+        return (lane & 4) ? dn : up;
+    }
+    if (j == 8) {
+        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x108, 0xF, 0xF, true);
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x118, 0xF, 0xF, true);
+        return (lane & 8) ? dn : up;
+    }
+    if (j == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    }
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane & 32) ? r[0] : r[1];
+}
+
+// Value of v in lane l (l uniform over the wavefront), as a scalar.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, l), hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Reference position along one side: 0, s, 2s, ... and the last position n-ps.
 __host__ __device__ inline int ref_pos(int i, int n_ref, int n, int s) {
     return (i == n_ref - 1) ? (n - PS) : i * s;
@@ -187,6 +219,10 @@ struct CnnBuffers {
 };
 hipError_t cnn_forward(const CnnBuffers &b, const uint8_t *img, int64_t img_stride, int64_t img_batch_stride,
                        int N, int H, int W, int c, hipStream_t st);
+// The same for N images of one size in separate buffers: image n at img_tab[n] (device table),
+// row stride stride_tab[n]; the outputs of image n follow those of image n - 1 in b.z.
+hipError_t cnn_forward_tab(const CnnBuffers &b, const uint8_t *const *img_tab, const int64_t *stride_tab, int N,
+                           int H, int W, int c, hipStream_t st);
 hipError_t cnn_backward(const CnnBuffers &b, const uint8_t *img, int64_t img_stride, int64_t img_batch_stride,
                         int N, int H, int W, int c, const float *target, float *grads, float *d0, float *d1,
                         double *loss_sum, hipStream_t st);

@@ -72,10 +72,16 @@ __device__ inline double recip(double q) {
     return fma(r, e, r);
 }
 
-// Sum over the 64 lanes of a wavefront (every lane gets the total).
-__device__ inline double wave_sum_d(double v) {
+// Sum over the 64 lanes of a wavefront (every lane gets the total; partners exchange by DPP
+// and row swaps, offsets 32, 16, ..., 1).
+__device__ __forceinline__ double wave_sum_d(double v) {
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = xor_lane((uint32_t)b, o, lane), hi = xor_lane((uint32_t)(b >> 32), o, lane);
+        v += __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    }
     return v;
 }
 
@@ -193,33 +199,28 @@ __device__ __forceinline__ void eig_tile(double *vec, const int32_t *__restrict_
     double row[64];
 #pragma unroll
     for (int j = 0; j < 64; ++j) row[j] = (double)mom[i * 64 + j] / n - s1i * ((double)S1[j] / n);
-    double *vv = vec, *ww = vec + 64;
     // Householder: step k annihilates column k below the subdiagonal.
     for (int k = 0; k < 62; ++k) {
         double xk = 0.0;
 #pragma unroll
         for (int j = 0; j < 64; ++j) xk = (j == k) ? row[j] : xk;   // lane i: A[i][k]
         const double tail = wave_sum_d(i > k + 1 ? xk * xk : 0.0);
-        const double x0 = __shfl(xk, k + 1);
+        const double x0 = readlane_f64(xk, k + 1);
         if (tail == 0.0) continue;                       // column already reduced (uniform)
         const double nrm = sqrt(x0 * x0 + tail);
         const double alpha = x0 > 0.0 ? -nrm : nrm;
         const double v0 = x0 - alpha;
         const double beta = 2.0 / (v0 * v0 + tail);
         const double vi = i == k + 1 ? v0 : (i > k + 1 ? xk : 0.0);
-        vv[i] = vi;
-        __builtin_amdgcn_wave_barrier();
+        // v and w are broadcast lane by lane as scalar operands (no LDS round trip)
         double pi = 0.0;
 #pragma unroll
-        for (int j = 0; j < 64; ++j) pi += row[j] * vv[j];
+        for (int j = 0; j < 64; ++j) pi += row[j] * readlane_f64(vi, j);
         pi *= beta;
         const double Kc = 0.5 * beta * wave_sum_d(pi * vi);
         const double wi = pi - Kc * vi;
-        ww[i] = wi;
-        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int j = 0; j < 64; ++j) row[j] -= vi * ww[j] + wi * vv[j];
-        __builtin_amdgcn_wave_barrier();
+        for (int j = 0; j < 64; ++j) row[j] -= vi * readlane_f64(wi, j) + wi * readlane_f64(vi, j);
     }
     // tridiagonal: d_i = A[i][i], e_{i-1} = A[i][i-1]
     double di = 0.0, sub = 0.0;
@@ -391,15 +392,22 @@ __device__ inline uint64_t splitmix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-// First and last reference index along one side whose position lies in [lo, hi].
+// First and last reference index along one side whose position lies in [lo, hi] (lo >= 0),
+// or first > last.  Positions increase strictly: i s for i < n_ref - 1, then n - PS.
 __device__ inline void ref_range(int n_ref, int n, int s, int lo, int hi, int *first, int *last) {
-    int f = -1, l = -2;
-    for (int i = 0; i < n_ref; ++i) {
-        const int p = ref_pos(i, n_ref, n, s);
-        if (p >= lo && p <= hi) {
-            if (f < 0) f = i;
-            l = i;
-        }
+    const int reg = n_ref - 1;          // references on the regular grid: 0 .. reg - 1
+    const int pl = n - PS;              // position of the last reference
+    int f = (lo + s - 1) / s;           // smallest regular i with i s >= lo
+    if (f >= reg) f = pl >= lo ? reg : n_ref;
+    int l;
+    if (pl <= hi) {
+        l = reg;
+    } else {
+        l = min(hi / s, reg - 1);       // largest regular i with i s <= hi
+    }
+    if (f > l) {
+        f = -1;
+        l = -2;
     }
     *first = f;
     *last = l;

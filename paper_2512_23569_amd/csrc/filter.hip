@@ -104,15 +104,18 @@ int filter_lds_bytes_for(const TileGeom &tg, int C, int K) {
 
 // Fixed-point shift of the region sums: a pixel of a tile's region receives at most T^2 K
 // contributions (every member of every group of the tile), each clamped to |v| <= 1024, so
-// T^2 K 1024 2^FS must stay below 2^31.  Tiles are capped so that FS >= 10 (rounding error
-// of a contribution <= 2^-11).
+// T^2 K 1024 2^FS must stay below 2^31.  Tiles are capped so that FS >= 9: a contribution
+// is rounded by at most 2^-10, and so is the average of a pixel's contributions.  FS <= 12
+// keeps every scaled contribution below 2^22, the range of the filter's rounding by
+// addition of 1.5 * 2^23.
 constexpr double FX_CLAMP = 1024.0;
-constexpr int FX_MIN_SHIFT = 10;
+constexpr int FX_MIN_SHIFT = 9;
+constexpr int FX_MAX_SHIFT = 12;
 
 int accumulation_shift(int T, int K) {
     const double worst = (double)T * T * K * FX_CLAMP;
     int fs = 0;
-    while (fs < 16 && worst * (double)(1 << (fs + 1)) < 2147483647.0) ++fs;
+    while (fs < FX_MAX_SHIFT && worst * (double)(1 << (fs + 1)) < 2147483647.0) ++fs;
     return fs;
 }
 

@@ -145,9 +145,13 @@ __device__ inline int haar_row(int r, int h) {
 
 // Contribution in fixed point (round to nearest even); |v| is clamped to 1024 (four times the
 // 8-bit range) so that no region sum can overflow (see the accumulation shift of the tiling).
-// The scale is applied here, after the fp16 products, whose range it would exceed.
+// The scale 2^FS (FS <= 12) is applied here, after the fp16 products, whose range it would
+// exceed.  |v| scale <= 2^22, so v scale + 1.5 * 2^23 lies in [2^23, 2^24], where floats are
+// the integers: one fused multiply-add rounds to nearest even and the bits give the integer.
 __device__ inline int to_fixed(float v, float scale) {
-    return __float2int_rn(fminf(fmaxf(v, -1024.f), 1024.f) * scale);
+    constexpr float MAGIC = 12582912.0f;   // 1.5 * 2^23
+    const float t = fmaf(fminf(fmaxf(v, -1024.f), 1024.f), scale, MAGIC);
+    return __float_as_int(t) - __float_as_int(MAGIC);
 }
 
 // 2^e for a small integer exponent (exact).

@@ -2,9 +2,9 @@
 replayed from a hipGraph) vs the FP64 oracle and vs the one-image entry points (needs an MI355X).
 
 Filtering accumulates the reconstructed patches in LDS as int32 fixed point (units of 2^-FS,
-FS >= 10 chosen per tiling so that no sum can overflow), so two runs
+9 <= FS <= 12 chosen per tiling so that no sum can overflow), so two runs
 with the same tiling give identical results, and runs with different tilings differ by at most
-the rounding of one fixed-point unit per run (2 * 2^-(FS+1) on the 0..255 scale).  Comparisons
+the rounding of one fixed-point unit per run (2 * 2^-(FS+1) <= 2^-9 on the 0..255 scale).  Comparisons
 between GPU runs allow RUN_TOL; comparisons with the oracle use the pixel parity bar."""
 import numpy as np
 import pytest
