@@ -157,11 +157,21 @@ __device__ inline int to_fixed(float v, float scale) {
 // 2^e for a small integer exponent (exact).
 __device__ inline float exp2i(int e) { return __int_as_float((e + 127) << 23); }
 
+// Fragments of the slice-0 pairs (pair < 8: the 64 x 64 map) of both directions and terms,
+// kept in LDS: [dir][term][pair][lane].
+constexpr int F0_PAIRS = 8;
+constexpr int F0_BYTES = 2 * 2 * F0_PAIRS * 64 * 16;
+
+__device__ inline v8h ldfrag0(const v8h *FL0, int dir, int term, int pair, int lane) {
+    return FL0[((dir * 2 + term) * F0_PAIRS + pair) * 64 + lane];
+}
+
 // One reference tile: every group of the tile, 32 patches (32/K groups) per wavefront step.
-//   FG: fragment tables (forward at dir 0, inverse at dir 1), read through the caches; the
-//   eight wavefronts of a workgroup share them and the tile's LDS region.
+//   FL0: LDS copy of the slice-0 fragments (the 64 x 64 map, both directions); FG: the whole
+//   tables (forward at dir 0, inverse at dir 1), read through the caches for the other slices.
+//   The eight wavefronts of a workgroup share both and the tile's LDS region.
 template <int C, int K>
-__device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileGeom &tg,
+__device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileGeom &tg, const v8h *FL0,
                                                  const v8h *__restrict__ FG, const double *__restrict__ T64,
                                                  const int32_t *__restrict__ idx, const int idx_stride,
                                                  const double *__restrict__ tau_ref, const double tau_mul,
@@ -281,8 +291,8 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                     }
                 }
                 const int p0 = pair_of<C>(tp, sp);
-                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, ldfrag(FG, 0, 0, p0, NPAIR, lane), acc[0], 0, 0, 0);
-                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, ldfrag(FG, 0, 1, p0, NPAIR, lane), acc[0], 0, 0, 0);
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, ldfrag0(FL0, 0, 0, p0, lane), acc[0], 0, 0, 0);
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, ldfrag0(FL0, 0, 1, p0, lane), acc[0], 0, 0, 0);
                 if (C == 3) {
 #pragma unroll
                     for (int sl = 1; sl < C; ++sl) {
@@ -489,7 +499,8 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                     for (int tt = 0; tt < ntile; ++tt) {
                         const int t = tlo + tt;
                         const int pr = pair_of<C>(t, 2 * j + ss);
-                        const v8h fbh = ldfrag(FG, 1, 0, pr, NPAIR, lane), fbl = ldfrag(FG, 1, 1, pr, NPAIR, lane);
+                        const v8h fbh = sl == 0 ? ldfrag0(FL0, 1, 0, pr, lane) : ldfrag(FG, 1, 0, pr, NPAIR, lane);
+                        const v8h fbl = sl == 0 ? ldfrag0(FL0, 1, 1, pr, lane) : ldfrag(FG, 1, 1, pr, NPAIR, lane);
                         out[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, fbh, out[t], 0, 0, 0);
                         out[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, fbl, out[t], 0, 0, 0);
                         out[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, fbh, out[t], 0, 0, 0);
@@ -575,14 +586,20 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_kernel(ImageGeom g, TileG
                                                              unsigned long long *__restrict__ guard_count) {
     extern __shared__ __align__(16) float smem[];
     __shared__ MfmaShared sh;
-    float *region = smem;
+    v8h *FL0 = reinterpret_cast<v8h *>(smem);
+    for (int e = threadIdx.x; e < F0_BYTES / 16; e += MW * 64) {
+        const int dt = e / (F0_PAIRS * 64), pl = e % (F0_PAIRS * 64);
+        FL0[e] = F[(dt * Frag<C>::NPAIR) * 64 + pl];
+    }
+    __syncthreads();
+    float *region = smem + F0_BYTES / 4;
     uint32_t *xb = reinterpret_cast<uint32_t *>(region + region_elems(tg, C));
     const int n_tiles = tg.tiles_y * tg.tiles_x;
     const int per = (n_tiles + 7) / 8;
     for (int v = blockIdx.x; v < 8 * per; v += gridDim.x) {
         const int tile = (v & 7) * per + (v >> 3);
         if (tile >= n_tiles) continue;
-        filter_tile_mfma<C, K>(g, tg, F, T64, idx, K, tau_ref, 1.0, regions, guard_count, tile, region, xb, sh);
+        filter_tile_mfma<C, K>(g, tg, FL0, F, T64, idx, K, tau_ref, 1.0, regions, guard_count, tile, region, xb, sh);
         __syncthreads();
     }
 }
@@ -597,7 +614,13 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_kernel_batched(const Batc
     extern __shared__ __align__(16) float smem[];
     __shared__ MfmaShared sh;
     __shared__ int s_u;
-    float *region = smem;
+    v8h *FL0 = reinterpret_cast<v8h *>(smem);
+    for (int e = threadIdx.x; e < F0_BYTES / 16; e += MW * 64) {
+        const int dt = e / (F0_PAIRS * 64), pl = e % (F0_PAIRS * 64);
+        FL0[e] = F[(dt * Frag<C>::NPAIR) * 64 + pl];
+    }
+    __syncthreads();
+    float *region = smem + F0_BYTES / 4;
     const int total = unit_start[n_items];
     for (;;) {
         // thread 0 claims the next unit of an image filtered with this group size; units of an
@@ -623,7 +646,7 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_kernel_batched(const Batc
         const int i = find_unit(unit_start, n_items, u);
         const BatchItem it = items[i];
         uint32_t *xb = reinterpret_cast<uint32_t *>(region + region_elems(it.tg, C));
-        filter_tile_mfma<C, K>(it.g, it.tg, F, T64, it.idx, it.idx_stride, it.tau, it.tau_mul, it.regions,
+        filter_tile_mfma<C, K>(it.g, it.tg, FL0, F, T64, it.idx, it.idx_stride, it.tau, it.tau_mul, it.regions,
                                guard_count, u - unit_start[i], region, xb, sh);
         __syncthreads();
     }
@@ -632,12 +655,12 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_kernel_batched(const Batc
 }  // namespace
 
 int filter_mfma_lds_bytes(const TileGeom &tg, int C) {
-    return region_elems(tg, C) * 4 + MW * XWORDS * 4;
+    return F0_BYTES + region_elems(tg, C) * 4 + MW * XWORDS * 4;
 }
 
 int filter_mfma_group_bytes(int C) {
     (void)C;
-    return MW * XWORDS * 4;
+    return F0_BYTES + MW * XWORDS * 4;
 }
 
 int filter_mfma_static_bytes() { return (int)sizeof(MfmaShared) + 16; }
