@@ -39,7 +39,6 @@ struct TileInfo {
     int wy0[NREF], wx0[NREF];      // clipped window origin (candidate positions)
     int wh[NREF], ww[NREF];        // clipped window size
     int green[NREF];               // Eq. 9 branch: 1 green/gray distance, 0 channel-sum distance
-    int uy0, ux0, uh, uw;          // union of the windows
     int any_sum;                   // some reference uses the channel-sum distance
 };
 
@@ -126,6 +125,14 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
     const int R = (mp.W - 1) / 2;
 
     // ---- tile geometry ----
+    // The union of the 16 windows in closed form (positions increase along each side), so every
+    // thread has it at once and the staging loads need not wait for the per-reference table.
+    const int iya = tyi * REF_TILE, iyb = min(iya + REF_TILE, g.ny) - 1;
+    const int ixa = txi * REF_TILE, ixb = min(ixa + REF_TILE, g.nx) - 1;
+    const int uy0 = max(0, ref_pos(iya, g.ny, g.h, g.s) - R);
+    const int ux0 = max(0, ref_pos(ixa, g.nx, g.w, g.s) - R);
+    const int uh = min(g.h - PS, ref_pos(iyb, g.ny, g.h, g.s) + R) - uy0 + 1;
+    const int uw = min(g.w - PS, ref_pos(ixb, g.nx, g.w, g.s) + R) - ux0 + 1;
     if (tid < NREF) {
         const int iy = tyi * REF_TILE + tid / REF_TILE, ix = txi * REF_TILE + tid % REF_TILE;
         if (iy < g.ny && ix < g.nx) {
@@ -140,23 +147,16 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
             ti.wy0[tid] = 0; ti.wx0[tid] = 0; ti.wh[tid] = 0; ti.ww[tid] = 0;
         }
     }
-    __syncthreads();
-    if (tid == 0) {
-        int uy0 = 1 << 30, ux0 = 1 << 30, uy1 = -1, ux1 = -1;
-        for (int i = 0; i < NREF; ++i) {
-            if (ti.ry[i] < 0) continue;
-            uy0 = min(uy0, ti.wy0[i]); ux0 = min(ux0, ti.wx0[i]);
-            uy1 = max(uy1, ti.wy0[i] + ti.wh[i] - 1); ux1 = max(ux1, ti.wx0[i] + ti.ww[i] - 1);
-        }
-        ti.uy0 = uy0; ti.ux0 = ux0; ti.uh = uy1 - uy0 + 1; ti.uw = ux1 - ux0 + 1;
-    }
-    // Eq. 9 branch per reference from the raw channel norms (16 threads per reference).
+    // Eq. 9 branch per reference from the raw channel norms (16 threads per reference; the
+    // reference position is recomputed here, so these loads overlap with the staging below).
     if (g.c == 3) {
         const int i = tid >> 4, sub = tid & 15;   // 16 threads per reference (the first 256 threads)
         int nr = 0, ng = 0, nb = 0;
-        if (i < NREF && ti.ry[i] >= 0) {
+        const int iy = iya + i / REF_TILE, ix = ixa + i % REF_TILE;
+        if (i < NREF && iy < g.ny && ix < g.nx) {
+            const int ry = ref_pos(iy, g.ny, g.h, g.s), rx = ref_pos(ix, g.nx, g.w, g.s);
             for (int p = sub; p < PS * PS; p += 16) {
-                const uint8_t *px = g.img + (int64_t)(ti.ry[i] + p / PS) * g.stride + (int64_t)(ti.rx[i] + p % PS) * 3;
+                const uint8_t *px = g.img + (int64_t)(ry + p / PS) * g.stride + (int64_t)(rx + p % PS) * 3;
                 nr += px[0] * px[0]; ng += px[1] * px[1]; nb += px[2] * px[2];
             }
         }
@@ -171,13 +171,6 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
     } else if (tid < NREF) {
         ti.green[tid] = 1;
     }
-    __syncthreads();
-    if (tid == 0) {
-        int any = 0;
-        for (int i = 0; i < NREF; ++i) any |= (ti.ry[i] >= 0 && !ti.green[i]);
-        ti.any_sum = any;
-    }
-    const int uy0 = ti.uy0, ux0 = ti.ux0, uh = ti.uh, uw = ti.uw;
     const int prow = uh + PS - 1, pcol = uw + PS - 1;
 
     unsigned char *p8 = smem + L.off_p8;
@@ -209,6 +202,11 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
         }
     }
     __syncthreads();
+    if (tid == 0) {   // read after the norm phase's barriers
+        int any = 0;
+        for (int i = 0; i < NREF; ++i) any |= (ti.ry[i] >= 0 && !ti.green[i]);
+        ti.any_sum = any;
+    }
 
     // ---- squared norms at every candidate position (horizontal then vertical 8-sums) ----
     {
