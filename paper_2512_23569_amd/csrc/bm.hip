@@ -181,24 +181,63 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
     const int plane8 = L.rows * L.pitch8;
     const int plane16 = L.rows * L.pitch16;
 
-    // ---- stage the shifted planes ----
-    for (int e = tid; e < prow * pcol; e += BMT) {
-        const int r = e / pcol, col = e % pcol;
-        const uint8_t *px = g.img + (int64_t)(uy0 + r) * g.stride + (int64_t)(ux0 + col) * g.c;
-        int v8, vs = 0;
-        if (g.c == 3) {
-            v8 = (int)px[1] - 128;
-            vs = (int)px[0] + (int)px[1] + (int)px[2] - 384;
-        } else {
-            v8 = (int)px[0] - 128;
-        }
+    // ---- stage the shifted planes: one thread per (row, group of 4 columns) ----
+    // Dword w of int8 copy k holds the row's pixels 4w + k .. 4w + k + 3, and halves 4w .. 4w + 3
+    // of fp16 copy k hold the pixels 4w + k .. 4w + k + 3, so a thread needs pixels 4w .. 4w + 6.
+    // Bytes at or beyond the staged width pcol are never read (candidates end at pcol - 1).
+    {
+        const int nw = (pcol + 3) >> 2;
+        const uint8_t *img_end = g.img + (int64_t)(g.h - 1) * g.stride + (int64_t)g.w * g.c;
+        uint32_t *p8w = reinterpret_cast<uint32_t *>(p8);
+        uint32_t *p16w = reinterpret_cast<uint32_t *>(p16);
+        for (int e = tid; e < prow * nw; e += BMT) {
+            const int r = e / nw, w4 = 4 * (e - r * nw);
+            const int npx = min(7, pcol - w4);
+            const uint8_t *a = g.img + (int64_t)(uy0 + r) * g.stride + (int64_t)(ux0 + w4) * g.c;
+            uint32_t raw[6];   // bytes 0 .. 23 from a
+            const uintptr_t ai = (uintptr_t)a;
+            const uint32_t *ab = reinterpret_cast<const uint32_t *>(ai & ~(uintptr_t)3);
+            if (npx == 7 && (const uint8_t *)(ab + 7) <= img_end) {
+                const uint32_t sh = (uint32_t)(ai & 3);
+                uint32_t d[7];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (col >= k) p8[k * plane8 + r * L.pitch8 + col - k] = (unsigned char)(int8_t)v8;
-        if (g.c == 3) {
+                for (int i = 0; i < 7; ++i) d[i] = ab[i];
 #pragma unroll
-            for (int k = 0; k < 2; ++k)
-                if (col >= k) p16[k * plane16 + r * L.pitch16 + col - k] = (_Float16)vs;
+                for (int i = 0; i < 6; ++i) raw[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
+            } else {   // row end: only the pixels that exist, byte by byte
+#pragma unroll
+                for (int i = 0; i < 6; ++i) raw[i] = 0u;
+                const int nb = npx * g.c;
+                for (int b = 0; b < nb; ++b) raw[b >> 2] |= (uint32_t)a[b] << (8 * (b & 3));
+            }
+            auto byte_at = [&](int i) { return (int)((raw[i >> 2] >> (8 * (i & 3))) & 0xffu); };
+            int v8[7], vs[7];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                if (g.c == 3) {
+                    const int R = byte_at(3 * q), G = byte_at(3 * q + 1), B = byte_at(3 * q + 2);
+                    v8[q] = G - 128;
+                    vs[q] = R + G + B - 384;
+                } else {
+                    v8[q] = byte_at(q) - 128;
+                    vs[q] = 0;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                p8w[(k * plane8 + r * L.pitch8 + w4) >> 2] =
+                    (uint32_t)(uint8_t)v8[k] | ((uint32_t)(uint8_t)v8[k + 1] << 8) |
+                    ((uint32_t)(uint8_t)v8[k + 2] << 16) | ((uint32_t)(uint8_t)v8[k + 3] << 24);
+            if (g.c == 3) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int hh = 0; hh < 2; ++hh) {
+                        const uint32_t lo = __builtin_bit_cast(uint16_t, (_Float16)vs[2 * hh + k]);
+                        const uint32_t hi = __builtin_bit_cast(uint16_t, (_Float16)vs[2 * hh + k + 1]);
+                        p16w[(k * plane16 + r * L.pitch16 + w4 + 2 * hh) >> 1] = lo | (hi << 16);
+                    }
+            }
         }
     }
     __syncthreads();
@@ -209,35 +248,84 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
     }
 
     // ---- squared norms at every candidate position (horizontal then vertical 8-sums) ----
+    // Four consecutive outputs per thread from one window of 11 values, sliding (exact integers).
+    // Reads past the last valid output stay inside the staged planes and the table; the
+    // outputs they feed are not stored.
     {
         int32_t *rs8 = reinterpret_cast<int32_t *>(tab);          // prow x uw, tab is free now
         int32_t *rs16 = rs8 + prow * uw;
-        for (int e = tid; e < prow * uw; e += BMT) {
-            const int r = e / uw, col = e % uw;
-            int a = 0, s = 0;
+        const int ng = (uw + 3) >> 2;
+        for (int e = tid; e < prow * ng; e += BMT) {
+            const int r = e / ng, c0 = 4 * (e - r * ng);
+            int q8[11], q16[11];
+            {
+                const uint32_t *w8 = reinterpret_cast<const uint32_t *>(p8 + r * L.pitch8 + c0);
+                const uint32_t b[3] = {w8[0], w8[1], w8[2]};
 #pragma unroll
-            for (int j = 0; j < PS; ++j) {
-                const int v = (int8_t)p8[r * L.pitch8 + col + j];
-                a += v * v;
-                if (g.c == 3) {
-                    const int t = (int)p16[r * L.pitch16 + col + j];
-                    s += t * t;
+                for (int j = 0; j < 11; ++j) {
+                    const int v = (int)(int8_t)(b[j >> 2] >> (8 * (j & 3)));
+                    q8[j] = v * v;
                 }
             }
-            rs8[e] = a;
-            rs16[e] = s;
+            if (g.c == 3) {
+                const uint32_t *w16 = reinterpret_cast<const uint32_t *>(p16 + r * L.pitch16 + c0);
+                uint32_t b[6];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) b[i] = w16[i];
+#pragma unroll
+                for (int j = 0; j < 11; ++j) {
+                    const int t = (int)__builtin_bit_cast(_Float16, (uint16_t)(b[j >> 1] >> (16 * (j & 1))));
+                    q16[j] = t * t;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 11; ++j) q16[j] = 0;
+            }
+            int a = 0, t = 0;
+#pragma unroll
+            for (int j = 0; j < PS; ++j) {
+                a += q8[j];
+                t += q16[j];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (c0 + k < uw) {
+                    rs8[r * uw + c0 + k] = a;
+                    rs16[r * uw + c0 + k] = t;
+                }
+                if (k < 3) {
+                    a += q8[k + PS] - q8[k];
+                    t += q16[k + PS] - q16[k];
+                }
+            }
         }
         __syncthreads();
-        for (int e = tid; e < uh * uw; e += BMT) {
-            const int r = e / uw, col = e % uw;
-            int a = 0, s = 0;
+        const int nr4 = (uh + 3) >> 2;
+        for (int e = tid; e < nr4 * uw; e += BMT) {
+            const int r4 = 4 * (e / uw), col = e - (r4 >> 2) * uw;
+            int c8[11], c16[11];
+#pragma unroll
+            for (int i = 0; i < 11; ++i) {
+                c8[i] = rs8[(r4 + i) * uw + col];
+                c16[i] = rs16[(r4 + i) * uw + col];
+            }
+            int a = 0, t = 0;
 #pragma unroll
             for (int i = 0; i < PS; ++i) {
-                a += rs8[(r + i) * uw + col];
-                s += rs16[(r + i) * uw + col];
+                a += c8[i];
+                t += c16[i];
             }
-            n8[e] = a;
-            n16[e] = s;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (r4 + k < uh) {
+                    n8[(r4 + k) * uw + col] = a;
+                    n16[(r4 + k) * uw + col] = t;
+                }
+                if (k < 3) {
+                    a += c8[k + PS] - c8[k];
+                    t += c16[k + PS] - c16[k];
+                }
+            }
         }
         __syncthreads();
     }
