@@ -86,6 +86,14 @@ __device__ inline void load_row_u8(const uint8_t *p, const uint8_t *end, uint32_
 
 __device__ inline int byte_of(const uint32_t *w, int i) { return (int)((w[i >> 2] >> (8 * (i & 3))) & 0xffu); }
 
+// Byte i of the words as a float (one byte-to-float conversion).
+__device__ inline float byte_f(const uint32_t *w, int i) { return (float)((w[i >> 2] >> (8 * (i & 3))) & 0xffu); }
+
+// Two floats as a packed pair of fp16 (round toward zero), low half first.
+__device__ inline uint32_t pack_rtz(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(lo, hi));
+}
+
 // Entry (k, m) of the orthonormal Haar matrix H_n of Eq. 8.
 __device__ inline double haar_w(int k, int m, int n) {
     const double r2 = 0.70710678118654752440;
@@ -278,18 +286,25 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             for (int sl = 0; sl < C; ++sl) acc[sl] = (v16f){};
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp) {
-                v8h a0, ar, ai;
+                // bytes straight to float, the channel DFT in float, pairs packed to fp16 with
+                // round-toward-zero (all values are integers below 2^11, exact either way)
+                uint32_t w0[4], wr[4], wi[4];
 #pragma unroll
-                for (int b = 0; b < 8; ++b) {
+                for (int b = 0; b < 8; b += 2) {
                     if (C == 3) {
-                        const int R = byte_of(raw[sp], 3 * b), Gc = byte_of(raw[sp], 3 * b + 1), Bc = byte_of(raw[sp], 3 * b + 2);
-                        a0[b] = (_Float16)(float)(R + Gc + Bc);
-                        ar[b] = (_Float16)(float)(2 * R - Gc - Bc);
-                        ai[b] = (_Float16)(float)(Bc - Gc);
+                        const float R0 = byte_f(raw[sp], 3 * b), G0 = byte_f(raw[sp], 3 * b + 1), B0 = byte_f(raw[sp], 3 * b + 2);
+                        const float R1 = byte_f(raw[sp], 3 * b + 3), G1 = byte_f(raw[sp], 3 * b + 4), B1 = byte_f(raw[sp], 3 * b + 5);
+                        const float t0 = G0 + B0, t1 = G1 + B1;
+                        w0[b / 2] = pack_rtz(R0 + t0, R1 + t1);
+                        wr[b / 2] = pack_rtz(fmaf(2.f, R0, -t0), fmaf(2.f, R1, -t1));
+                        wi[b / 2] = pack_rtz(B0 - G0, B1 - G1);
                     } else {
-                        a0[b] = (_Float16)(float)byte_of(raw[sp], b);
+                        w0[b / 2] = pack_rtz(byte_f(raw[sp], b), byte_f(raw[sp], b + 1));
                     }
                 }
+                const v8h a0 = __builtin_bit_cast(v8h, make_uint4(w0[0], w0[1], w0[2], w0[3]));
+                const v8h ar = C == 3 ? __builtin_bit_cast(v8h, make_uint4(wr[0], wr[1], wr[2], wr[3])) : a0;
+                const v8h ai = C == 3 ? __builtin_bit_cast(v8h, make_uint4(wi[0], wi[1], wi[2], wi[3])) : a0;
                 const int p0 = pair_of<C>(tp, sp);
                 acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, ldfrag0(FL0, 0, 0, p0, lane), acc[0], 0, 0, 0);
                 acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, ldfrag0(FL0, 0, 1, p0, lane), acc[0], 0, 0, 0);
