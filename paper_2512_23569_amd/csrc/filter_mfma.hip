@@ -494,11 +494,10 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                 const int tlo = sl == 0 ? 0 : 2, ntile = sl == 0 ? 2 : 4;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
+                    // hi = v rounded to fp16 (nearest), lo = the rest (toward zero), one word
                     const float v = acc[sl][r];
-                    const _Float16 hi = (_Float16)v;
-                    const _Float16 lo = (_Float16)(v - (float)hi);
-                    xbuf[(16 * h + r) * XS + c32] =
-                        (uint32_t)__builtin_bit_cast(uint16_t, hi) | ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
+                    const float hf = (float)(_Float16)v;
+                    xbuf[(16 * h + r) * XS + c32] = pack_rtz(hf, v - hf);
                 }
                 wave_lds_fence();
 #pragma unroll
