@@ -156,3 +156,26 @@ def test_auto_group_size_in_graph_replays(dn):
         torch.cuda.synchronize()
         for e, o in zip(eager, outs):
             assert torch.max(torch.abs(e - o)).item() <= RUN_TOL, rep
+
+
+def test_learned_images_of_one_size_share_a_network_run(dn):
+    """Learned images are grouped by size and the network runs once per size class (input
+    layer through a pointer table, maps contiguous per class): three images of one size, each in
+    its own buffer with its own row padding, and one of another size give the one-image results."""
+    shapes = [(96, 80), (96, 80), (70, 130), (96, 80)]
+    sig = [12.0, 35.0, 20.0, 60.0]
+    ins, outs = [], []
+    for i, (h, w) in enumerate(shapes):
+        clean = synth.make_clean(h, w, 3, 500 + i)
+        noisy = synth.add_awgn(clean, sig[i], 600 + i)
+        pad = 3 * i   # different row strides within the class
+        buf = torch.zeros((h, w * 3 + pad), dtype=torch.uint8, device="cuda")
+        buf[:, : w * 3] = _dev(noisy).reshape(h, w * 3)
+        ins.append(buf[:, : w * 3].reshape(h, w, 3) if pad == 0 else buf.as_strided((h, w, 3), (w * 3 + pad, 3, 1)))
+    for est in (1, 0):
+        p = dn.params(3, stride=3, window=15, K=16, adaptive=1, estimator=est)
+        outs = dn.denoise_batch(ins, [-1.0] * len(ins), p, use_graph=True)
+        torch.cuda.synchronize()
+        for i, x in enumerate(ins):
+            one = dn.denoise(x, -1.0, p)
+            assert torch.max(torch.abs(outs[i] - one)).item() <= RUN_TOL, (est, i)
