@@ -433,14 +433,18 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
         // this lane's candidates p = lane + 64 i, read once; key = (distance, position)
         constexpr int NPL = (MAX_CAND + 63) / 64;
         uint32_t dv[NPL];
-        uint64_t lmin = ~0ull;
+        uint32_t dmin = 0xFFFFFFFFu;   // valid distances are below 2^26
 #pragma unroll
         for (int i = 0; i < NPL; ++i) {
             const int p = lane + 64 * i;
             dv[i] = p < n ? row[p] : 0xFFFFFFFFu;
-            const uint64_t key = p < n ? (((uint64_t)dv[i] << 10) | (uint64_t)p) : ~0ull;
-            lmin = key < lmin ? key : lmin;
+            dmin = min(dmin, dv[i]);
         }
+        // the lane's smallest key: its smallest distance at the first (smallest) position
+        int pmin = 0;
+#pragma unroll
+        for (int i = NPL - 1; i >= 0; --i) pmin = dv[i] == dmin ? lane + 64 * i : pmin;
+        const uint64_t lmin = dmin == 0xFFFFFFFFu ? ~0ull : (((uint64_t)dmin << 10) | (uint64_t)pmin);
         const uint64_t sorted = wave_sort64(lmin, lane);
         const uint64_t theta = readlane_u64(sorted, K - 1);
         int cnt = 0;
