@@ -186,6 +186,38 @@ __device__ __forceinline__ void mom_tile(unsigned char *smem, const ImageGeom g,
     if (tid < 64) mom[64 * 64 + tid] = S1[tid];
 }
 
+// Householder steps k = 8B .. min(8B + 8, 62) - 1 on the rows held one per lane (lane i: row i).
+// The reflector vector v is zero at indices <= k, so for a step of this block the products and
+// updates of the columns below 8B are exact zeros for every entry read later (the tridiagonal
+// entries of the reduced rows, and v, w, p): those columns are left out.
+template <int B>
+__device__ __forceinline__ void hh_block(double (&row)[64], int i) {
+    constexpr int J0 = 8 * B;
+    constexpr int KEND = J0 + 8 < 62 ? J0 + 8 : 62;
+    for (int k = J0; k < KEND; ++k) {
+        double xk = 0.0;
+#pragma unroll
+        for (int j = J0; j < J0 + 8; ++j) xk = (j == k) ? row[j] : xk;   // lane i: A[i][k]
+        const double tail = wave_sum_d(i > k + 1 ? xk * xk : 0.0);
+        const double x0 = readlane_f64(xk, k + 1);
+        if (tail == 0.0) continue;                       // column already reduced (uniform)
+        const double nrm = sqrt(x0 * x0 + tail);
+        const double alpha = x0 > 0.0 ? -nrm : nrm;
+        const double v0 = x0 - alpha;
+        const double beta = 2.0 / (v0 * v0 + tail);
+        const double vi = i == k + 1 ? v0 : (i > k + 1 ? xk : 0.0);
+        // v and w are broadcast lane by lane as scalar operands (no LDS round trip)
+        double pi = 0.0;
+#pragma unroll
+        for (int j = J0 + 1; j < 64; ++j) pi += row[j] * readlane_f64(vi, j);
+        pi *= beta;
+        const double Kc = 0.5 * beta * wave_sum_d(pi * vi);
+        const double wi = pi - Kc * vi;
+#pragma unroll
+        for (int j = J0; j < 64; ++j) row[j] -= vi * readlane_f64(wi, j) + wi * readlane_f64(vi, j);
+    }
+}
+
 // Eigenvalue stage of one (sub-image, channel), one wavefront: covariance rows in registers
 // (lane i holds row i), Householder reduction to tridiagonal form, eigenvalues by Sturm-count
 // bisection (lane i finds the i-th smallest), tail rule.  vec: 3 x 64 doubles of LDS for this
@@ -199,29 +231,15 @@ __device__ __forceinline__ void eig_tile(double *vec, const int32_t *__restrict_
     double row[64];
 #pragma unroll
     for (int j = 0; j < 64; ++j) row[j] = (double)mom[i * 64 + j] / n - s1i * ((double)S1[j] / n);
-    // Householder: step k annihilates column k below the subdiagonal.
-    for (int k = 0; k < 62; ++k) {
-        double xk = 0.0;
-#pragma unroll
-        for (int j = 0; j < 64; ++j) xk = (j == k) ? row[j] : xk;   // lane i: A[i][k]
-        const double tail = wave_sum_d(i > k + 1 ? xk * xk : 0.0);
-        const double x0 = readlane_f64(xk, k + 1);
-        if (tail == 0.0) continue;                       // column already reduced (uniform)
-        const double nrm = sqrt(x0 * x0 + tail);
-        const double alpha = x0 > 0.0 ? -nrm : nrm;
-        const double v0 = x0 - alpha;
-        const double beta = 2.0 / (v0 * v0 + tail);
-        const double vi = i == k + 1 ? v0 : (i > k + 1 ? xk : 0.0);
-        // v and w are broadcast lane by lane as scalar operands (no LDS round trip)
-        double pi = 0.0;
-#pragma unroll
-        for (int j = 0; j < 64; ++j) pi += row[j] * readlane_f64(vi, j);
-        pi *= beta;
-        const double Kc = 0.5 * beta * wave_sum_d(pi * vi);
-        const double wi = pi - Kc * vi;
-#pragma unroll
-        for (int j = 0; j < 64; ++j) row[j] -= vi * readlane_f64(wi, j) + wi * readlane_f64(vi, j);
-    }
+    // Householder: step k annihilates column k below the subdiagonal; steps run in blocks of 8.
+    hh_block<0>(row, i);
+    hh_block<1>(row, i);
+    hh_block<2>(row, i);
+    hh_block<3>(row, i);
+    hh_block<4>(row, i);
+    hh_block<5>(row, i);
+    hh_block<6>(row, i);
+    hh_block<7>(row, i);
     // tridiagonal: d_i = A[i][i], e_{i-1} = A[i][i-1]
     double di = 0.0, sub = 0.0;
 #pragma unroll
