@@ -525,12 +525,25 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
         }
 
         // ---- aggregation into the LDS region ----
+        // patch offsets of the MFMA rows 8(r/4) + 4h + r%4 through the (now free) transpose
+        // buffer: one store per lane, four 16-byte reads
+        xbuf[lane] = (uint32_t)off_in;
+        wave_lds_fence();
+        int offs[16];
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+            const uint4 o4 = *reinterpret_cast<const uint4 *>(xbuf + 8 * q4 + 4 * h);
+            offs[4 * q4] = (int)o4.x;
+            offs[4 * q4 + 1] = (int)o4.y;
+            offs[4 * q4 + 2] = (int)o4.z;
+            offs[4 * q4 + 3] = (int)o4.w;
+        }
+        wave_lds_fence();
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int mu = 16 * h + r;
             const int gi = mu / K;
-            // patch offset from the lane that loaded member mu (MFMA row 8(r/4) + 4h + r%4)
-            const int off = __shfl(off_in, 8 * (r >> 2) + 4 * h + (r & 3));
+            const int off = offs[r];
             if (!full && base + gi >= nref) continue;
 #pragma unroll
             for (int tq = 0; tq < 2; ++tq) {
