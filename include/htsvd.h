@@ -89,6 +89,32 @@ htsvd_status htsvd_default_params(int32_t c, htsvd_params *out);
  * threshold guard band).  Returns HTSVD_EINVAL if they are not orthogonal to 1e-9. */
 htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double *h_U, const double *h_V);
 
+/* Channel Gram sums of all reference patches of one image (the sums behind the learned basis
+ * of Sec. III-B, Eq. 10-11).  Over the reference grid of step `stride` (Algorithm 1) and patches
+ * P of ps = 8, into the DEVICE int64 array d_gram of 2*c*c*64 entries:
+ *   d_gram[((0*c + a)*c + b)*64 + i*8 + k] = sum_P sum_j P(i, j, a) P(k, j, b)   (patch rows)
+ *   d_gram[((1*c + a)*c + b)*64 + i*8 + k] = sum_P sum_j P(j, i, a) P(j, k, b)   (patch columns)
+ * Exact integers.  Asynchronous on `stream` (clears d_gram first); the caller owns d_gram.
+ * Errors: HTSVD_EINVAL (null pointers, c not 1/3, stride < 1, in_stride < w*c), HTSVD_ENOTSUP
+ * (ps != 8, more than 2^30 pixels), HTSVD_ESHAPE (image smaller than one patch). */
+htsvd_status htsvd_basis_gram(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                              int64_t in_stride, int32_t ps, int32_t stride, int64_t *d_gram, void *stream);
+
+/* Learns the t-SVD basis pair (U, V) from one image (Sec. III-B, Eq. 10-11) and installs it as
+ * the context's basis for c channels, exactly as htsvd_set_basis would.  Per slice f of the
+ * channel DFT (Eq. 5), U_hat^(f) holds the eigenvectors of C_row = sum_P P_hat P_hat^H and
+ * V_hat^(f) those of C_col = sum_P P_hat^H P_hat over all reference patches of the grid of
+ * step `stride`, by descending eigenvalue, each with the phase that makes its entry of largest
+ * modulus (the first among equals) real and positive; slices f and c-f are conjugate, so U and
+ * V are real.  The sums run on the device (see htsvd_basis_gram); the 8x8 eigendecompositions
+ * run on the host.  h_U, h_V (host, ps*ps*c FP64 each, slice-major as in htsvd_set_basis) receive
+ * the pair when not NULL.  Synchronises `stream`; like htsvd_set_basis, it must not overlap a
+ * running call that uses the basis for c channels.  Errors as htsvd_basis_gram, plus those of
+ * htsvd_set_basis and HTSVD_EDEVICE / HTSVD_ENOMEM from the device. */
+htsvd_status htsvd_learn_basis(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                               int64_t in_stride, int32_t ps, int32_t stride, double *h_U, double *h_V,
+                               void *stream);
+
 /* Number of reference positions along a side of length n (grid 0, s, 2s, ..., n-ps). */
 int32_t htsvd_ref_count(int32_t n, int32_t ps, int32_t stride);
 

@@ -38,14 +38,46 @@ def _fix_phase(Q: np.ndarray) -> np.ndarray:
     return Q
 
 
+def _patches(img: np.ndarray, ps: int, stride: int) -> np.ndarray:
+    """All reference patches of the grid of Algorithm 1, (n, ps, ps, c) FP64."""
+    a = img if img.ndim == 3 else img[:, :, None]
+    h, w, c = a.shape
+    from oracle import ref_grid
+    ys, xs = ref_grid(h, ps, stride), ref_grid(w, ps, stride)
+    return np.stack([a[y:y + ps, x:x + ps, :] for y in ys for x in xs]).astype(np.float64)
+
+
+def slice_covariances(img: np.ndarray, ps: int = 8, stride: int = 4):
+    """Per Fourier slice f (Eq. 5 along the channel mode) of all reference patches P:
+    C_row^(f) = sum P_hat P_hat^H and C_col^(f) = sum P_hat^H P_hat, as (c, ps, ps) complex."""
+    ph = np.fft.fft(_patches(img, ps, stride), axis=3)
+    c = ph.shape[3]
+    Crow = np.zeros((c, ps, ps), dtype=np.complex128)
+    Ccol = np.zeros((c, ps, ps), dtype=np.complex128)
+    for f in range(c):
+        P = ph[:, :, :, f]
+        Crow[f] = np.einsum("nij,nkj->ik", P, np.conj(P))
+        Ccol[f] = np.einsum("nji,njk->ik", np.conj(P), P)
+    return Crow, Ccol
+
+
+def channel_gram(img: np.ndarray, ps: int = 8, stride: int = 4) -> np.ndarray:
+    """Exact integer sums over all reference patches P, (2, c, c, ps, ps) int64:
+    [0][a][b][i][k] = sum_P sum_j P(i, j, a) P(k, j, b) (rows), [1][a][b][i][k] = sum_P sum_j
+    P(j, i, a) P(j, k, b) (columns).  The slice covariances above are their combinations
+    sum_ab w^(f(a-b)) [0][a][b] and sum_ab w^(f(b-a)) [1][a][b], w = exp(-2 pi i / c)."""
+    P = _patches(img, ps, stride).astype(np.int64)
+    row = np.einsum("nija,nkjb->abik", P, P)
+    col = np.einsum("njia,njkb->abik", P, P)
+    return np.stack([row, col])
+
+
 def learn(img: np.ndarray, ps: int = 8, stride: int = 4):
     """Returns (U, V) as real (ps, ps, c) tensors learned from the reference patches of img."""
     a = img if img.ndim == 3 else img[:, :, None]
-    h, w, c = a.shape
-    from oracle import ref_grid, from_slices
-    ys, xs = ref_grid(h, ps, stride), ref_grid(w, ps, stride)
-    pats = np.stack([a[y:y + ps, x:x + ps, :] for y in ys for x in xs]).astype(np.float64)  # n,ps,ps,c
-    ph = np.fft.fft(pats, axis=3)  # Eq. 5 along the channel mode
+    c = a.shape[2]
+    from oracle import from_slices
+    Crow_all, Ccol_all = slice_covariances(img, ps, stride)
     Uh = np.zeros((c, ps, ps), dtype=np.complex128)
     Vh = np.zeros((c, ps, ps), dtype=np.complex128)
     for f in range(c):
@@ -53,10 +85,7 @@ def learn(img: np.ndarray, ps: int = 8, stride: int = 4):
             Uh[f] = np.conj(Uh[c - f])
             Vh[f] = np.conj(Vh[c - f])
             continue
-        P = ph[:, :, :, f]
-        Crow = np.einsum("nij,nkj->ik", P, np.conj(P))
-        Ccol = np.einsum("nji,njk->ik", np.conj(P), P)
-        for C, dst in ((Crow, Uh), (Ccol, Vh)):
+        for C, dst in ((Crow_all[f], Uh), (Ccol_all[f], Vh)):
             C = 0.5 * (C + C.conj().T)
             ev, Q = np.linalg.eigh(C)
             Q = Q[:, ::-1]

@@ -72,6 +72,8 @@ _SIGS = {
     "htsvd_default_params": (_i32, [_i32, _PP]),
     "htsvd_set_basis": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "htsvd_ref_count": (_i32, [_i32, _i32, _i32]),
+    "htsvd_basis_gram": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _i32, _i32, _vp, _vp]),
+    "htsvd_learn_basis": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _i32, _i32, _vp, _vp, _vp]),
     "htsvd_block_match": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _PP, _vp, _vp, _vp]),
     "htsvd_denoise": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _i64, _vp]),
     "htsvd_denoise_tau": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _vp, _PP, _vp, _i64, _vp]),
@@ -180,6 +182,22 @@ def htsvd_set_basis(ctx, ps: int, c: int, U_slices: np.ndarray, V_slices: np.nda
 
 def htsvd_ref_count(n: int, ps: int, stride: int) -> int:
     return int(lib().htsvd_ref_count(n, ps, stride))
+
+
+def htsvd_basis_gram(ctx, d_in, h, w, c, in_stride, ps, stride, d_gram, stream=None):
+    import torch
+    _check(lib().htsvd_basis_gram(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, c, in_stride, ps, stride,
+                                  _dptr(d_gram, torch.int64, "d_gram"), _stream(stream)))
+
+
+def htsvd_learn_basis(ctx, d_in, h, w, c, in_stride, ps, stride, stream=None):
+    """Returns the learned pair as slice-major (c, ps, ps) FP64 arrays (also installed in ctx)."""
+    import torch
+    U = np.zeros((c, ps, ps), dtype=np.float64)
+    V = np.zeros((c, ps, ps), dtype=np.float64)
+    _check(lib().htsvd_learn_basis(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, c, in_stride, ps, stride,
+                                   U.ctypes.data_as(_vp), V.ctypes.data_as(_vp), _stream(stream)))
+    return U, V
 
 
 def htsvd_block_match(ctx, d_in, h, w, c, in_stride, params, d_idx, d_dist=None, stream=None):
@@ -343,6 +361,20 @@ class Denoiser:
         dist = torch.empty((n_ref, params.K), dtype=torch.int32, device=img.device) if with_dist else None
         htsvd_block_match(self.ctx, img, h, w, c, st, params, idx, dist, stream)
         return idx, dist
+
+    def basis_gram(self, img, stride=4, stream=None):
+        """Channel Gram sums (2, c, c, 8, 8) int64 of the image's reference patches."""
+        import torch
+        h, w, c, st = _img_dims(img)
+        out = torch.empty((2, c, c, 8, 8), dtype=torch.int64, device=img.device)
+        htsvd_basis_gram(self.ctx, img, h, w, c, st, 8, stride, out, stream)
+        return out
+
+    def learn_basis(self, img, stride=4, stream=None):
+        """Learns the basis pair from this image and makes it the one used for its channel
+        count; returns (U, V) slice-major (c, 8, 8) FP64."""
+        h, w, c, st = _img_dims(img)
+        return htsvd_learn_basis(self.ctx, img, h, w, c, st, 8, stride, stream)
 
     def denoise(self, img, sigma, params, out=None, stream=None):
         import torch

@@ -12,6 +12,7 @@
 
 #include "../../include/htsvd.h"
 #include "common.h"
+#include "hevd.h"
 
 namespace htsvd {
 hipError_t launch_filter(const ImageGeom &g, int W, int K, const BasisDev &b, const int32_t *idx,
@@ -52,6 +53,7 @@ struct htsvd_ctx {
     void *ws = nullptr;
     size_t ws_size = 0;
     unsigned long long *d_guard = nullptr;  // [0] re-decided in FP64, [1] past the per-group list
+    int64_t *d_gram = nullptr;              // channel Gram sums of the basis learning pass
     // Optional per-stage timing with HIP events recorded on the call's stream.
     bool timing = false;
     hipEvent_t ev[2 * HTSVD_N_STAGES] = {};
@@ -454,6 +456,7 @@ void htsvd_destroy(htsvd_ctx *ctx) {
     }
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->d_guard) (void)hipFree(ctx->d_guard);
+    if (ctx->d_gram) (void)hipFree(ctx->d_gram);
     cnn_free(ctx->cnn);
     if (ctx->batch.exec) (void)hipGraphExecDestroy(ctx->batch.exec);
     if (ctx->batch.graph) (void)hipGraphDestroy(ctx->batch.graph);
@@ -663,6 +666,60 @@ htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double
                        hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "basis upload");
     ctx->has_basis[slot] = true;
+    return HTSVD_OK;
+}
+
+namespace {
+
+htsvd_status check_gram_args(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                             int64_t in_stride, int32_t ps, int32_t stride) {
+    if (!ctx) return fail(HTSVD_EINVAL, "null context");
+    if (!d_in) return fail(HTSVD_EINVAL, "null input image");
+    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    if (ps != PS) return fail(HTSVD_ENOTSUP, "only ps = 8 is supported");
+    if (stride < 1) return fail(HTSVD_EINVAL, "stride must be >= 1");
+    if (h < PS || w < PS) return fail(HTSVD_ESHAPE, "image smaller than one patch");
+    if (in_stride < (int64_t)w * c) return fail(HTSVD_EINVAL, "in_stride < w*c");
+    if ((int64_t)h * w > (int64_t)1 << 30) return fail(HTSVD_ENOTSUP, "image larger than 2^30 pixels");
+    return HTSVD_OK;
+}
+
+}  // namespace
+
+htsvd_status htsvd_basis_gram(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                              int64_t in_stride, int32_t ps, int32_t stride, int64_t *d_gram, void *stream) {
+    htsvd_status s = check_gram_args(ctx, d_in, h, w, c, in_stride, ps, stride);
+    if (s != HTSVD_OK) return s;
+    if (!d_gram) return fail(HTSVD_EINVAL, "null output");
+    hipError_t e = launch_gram(d_in, in_stride, h, w, c, stride, d_gram, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "Gram sums");
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_learn_basis(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                               int64_t in_stride, int32_t ps, int32_t stride, double *h_U, double *h_V,
+                               void *stream) {
+    htsvd_status s = check_gram_args(ctx, d_in, h, w, c, in_stride, ps, stride);
+    if (s != HTSVD_OK) return s;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (!ctx->d_gram && (e = hipMalloc(&ctx->d_gram, sizeof(int64_t) * 2 * 9 * 64)) != hipSuccess) {
+        ctx->d_gram = nullptr;
+        return fail(HTSVD_ENOMEM, "Gram buffer allocation");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if ((e = launch_gram(d_in, in_stride, h, w, c, stride, ctx->d_gram, st)) != hipSuccess)
+        return hip_fail(e, "Gram sums");
+    std::vector<int64_t> gram((size_t)2 * c * c * 64);
+    if ((e = hipMemcpyAsync(gram.data(), ctx->d_gram, sizeof(int64_t) * gram.size(), hipMemcpyDeviceToHost, st)) !=
+        hipSuccess)
+        return hip_fail(e, "Gram download");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "Gram download");
+    std::vector<double> U((size_t)64 * c), V((size_t)64 * c);
+    basis_from_gram(c, gram.data(), U.data(), V.data(), nullptr, nullptr);
+    if ((s = htsvd_set_basis(ctx, ps, c, U.data(), V.data())) != HTSVD_OK) return s;
+    if (h_U) memcpy(h_U, U.data(), sizeof(double) * U.size());
+    if (h_V) memcpy(h_V, V.data(), sizeof(double) * V.size());
     return HTSVD_OK;
 }
 

@@ -1,0 +1,151 @@
+// Channel Gram sums of all reference patches of one image: the device half of learning the
+// t-SVD basis pair from the image itself (Sec. III-B, Eq. 10-11).
+//
+// Over the reference grid (rows ys, columns xs, Algorithm 1) the row sums
+//   G_row[a][b][i][k] = sum_{y in ys, x in xs} sum_j X(y+i, x+j, a) X(y+k, x+j, b)
+// regroup by image column: for a fixed y the pair (x, j) only enters through col = x + j, so
+//   G_row = sum_{y in ys} sum_col m(col) v v^T,   v = X(y..y+7, col, :),
+// with m(col) the number of reference columns whose patch covers col.  The column sums are the
+// same with the roles of rows and columns swapped (horizontal 8-vectors at the reference
+// columns, weighted by the number of reference rows covering the pixel row).  Every entry is an
+// exact integer (below 2^50 for any image the library accepts), accumulated in 32-bit per staged
+// chunk and in 64-bit across chunks.
+#include "common.h"
+
+namespace htsvd {
+
+namespace {
+
+constexpr int GR_THREADS = 256;
+constexpr int GR_CHUNK = 256;    // vectors staged per step, one per thread
+constexpr int GR_MAX_BLOCKS = 1024;
+
+// Reference positions along a side of n pixels (n_ref of them) whose patch covers pixel pos:
+// regular positions i*s for i <= n_ref - 2, plus the last one at n - 8.
+__device__ inline int cover_count(int pos, int n, int n_ref, int s) {
+    int cnt = 0;
+    if (n_ref >= 2) {
+        const int lo = pos >= PS - 1 ? (pos - (PS - 1) + s - 1) / s : 0;
+        const int hi = min(n_ref - 2, pos / s);
+        cnt = max(0, hi - lo + 1);
+    }
+    return cnt + (pos >= n - PS ? 1 : 0);
+}
+
+// Thread tasks: an entry row r = ch*8 + i (A = 8c of them) times a block of 4 entry columns
+// starting at 4*bb, for bb >= r/4 (the other blocks follow by symmetry).  T = 4c(2c+1) tasks.
+template <int C>
+__global__ __launch_bounds__(GR_THREADS) void gram_kernel(const uint8_t *__restrict__ img, int64_t stride, int h,
+                                                          int w, int s, int ny, int nx,
+                                                          unsigned long long *__restrict__ out) {
+    constexpr int A = 8 * C, NBB = 2 * C, T = 4 * C * (2 * C + 1), GRP = GR_THREADS / T;
+    __shared__ __align__(16) uint32_t sv[GR_CHUNK * A];    // the staged vectors
+    __shared__ __align__(16) uint32_t smv[GR_CHUNK * A];   // the same, times their weight
+    __shared__ unsigned long long sred[GRP * T * 4];
+    const int g = blockIdx.y;   // 0: row sums, 1: column sums
+    const int64_t n_vec = g == 0 ? (int64_t)ny * w : (int64_t)nx * h;
+    const int64_t n_chunks = (n_vec + GR_CHUNK - 1) / GR_CHUNK;
+    const int tid = threadIdx.x;
+    const int grp = tid / T, task = tid % T;
+    const bool active = grp < GRP;
+    int r = 0, bb = 0;
+    {
+        int rem = task;
+        while (rem >= NBB - r / 4) {
+            rem -= NBB - r / 4;
+            ++r;
+        }
+        bb = r / 4 + rem;
+    }
+    unsigned long long tot0 = 0, tot1 = 0, tot2 = 0, tot3 = 0;
+    for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+        const int64_t q0 = ch * GR_CHUNK;
+        const int nv = (int)min<int64_t>(GR_CHUNK, n_vec - q0);
+        if (tid < nv) {
+            const int64_t q = q0 + tid;
+            const uint8_t *p;
+            int64_t step;
+            uint32_t m;
+            if (g == 0) {
+                const int iy = (int)(q / w), col = (int)(q % w);
+                p = img + (int64_t)ref_pos(iy, ny, h, s) * stride + (int64_t)col * C;
+                step = stride;
+                m = cover_count(col, w, nx, s);
+            } else {
+                const int row = (int)(q / nx), ix = (int)(q % nx);
+                p = img + (int64_t)row * stride + (int64_t)ref_pos(ix, nx, w, s) * C;
+                step = C;
+                m = cover_count(row, h, ny, s);
+            }
+#pragma unroll
+            for (int i = 0; i < PS; ++i)
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const uint32_t v = p[i * step + c];
+                    sv[tid * A + c * PS + i] = v;
+                    smv[tid * A + c * PS + i] = m * v;
+                }
+        }
+        __syncthreads();
+        if (active) {
+            // At most 256/GRP vectors of weight <= 9 per chunk: every partial sum stays below 2^32.
+            uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            for (int v = grp; v < nv; v += GRP) {
+                const uint32_t x = smv[v * A + r];
+                const uint4 y = *reinterpret_cast<const uint4 *>(&sv[v * A + 4 * bb]);
+                a0 += x * y.x;
+                a1 += x * y.y;
+                a2 += x * y.z;
+                a3 += x * y.w;
+            }
+            tot0 += a0;
+            tot1 += a1;
+            tot2 += a2;
+            tot3 += a3;
+        }
+        __syncthreads();
+    }
+    if (active) {
+        unsigned long long *d = sred + (grp * T + task) * 4;
+        d[0] = tot0;
+        d[1] = tot1;
+        d[2] = tot2;
+        d[3] = tot3;
+    }
+    __syncthreads();
+    // One atomic per entry and block; the mirrored entry (b, r) is added too where no task of
+    // its own covers it (column block below its row's block).
+    for (int e = tid; e < T * 4; e += GR_THREADS) {
+        unsigned long long sum = 0;
+        for (int k = 0; k < GRP; ++k) sum += sred[k * T * 4 + e];
+        if (sum == 0) continue;
+        int rr = 0, rem = e / 4;
+        while (rem >= NBB - rr / 4) {
+            rem -= NBB - rr / 4;
+            ++rr;
+        }
+        const int b = 4 * (rr / 4 + rem) + (e & 3);
+        // entry (rr, b) = (ch1*8 + i, ch2*8 + k) -> out[g][ch1][ch2][i][k]
+        unsigned long long *og = out + (size_t)g * C * C * 64;
+        atomicAdd(og + ((rr / PS) * C + b / PS) * 64 + (rr % PS) * PS + b % PS, sum);
+        if (b / 4 != rr / 4) atomicAdd(og + ((b / PS) * C + rr / PS) * 64 + (b % PS) * PS + rr % PS, sum);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gram(const uint8_t *img, int64_t stride, int h, int w, int c, int s, int64_t *out, hipStream_t st) {
+    hipError_t e = launch_zero(out, sizeof(int64_t) * 2 * c * c * 64, st);
+    if (e != hipSuccess) return e;
+    const int ny = ref_count(h, s), nx = ref_count(w, s);
+    const int64_t n_vec = std::max<int64_t>((int64_t)ny * w, (int64_t)nx * h);
+    const int nb = (int)std::min<int64_t>(GR_MAX_BLOCKS, (n_vec + GR_CHUNK - 1) / GR_CHUNK);
+    unsigned long long *o = reinterpret_cast<unsigned long long *>(out);
+    if (c == 3)
+        hipLaunchKernelGGL(gram_kernel<3>, dim3(nb, 2), dim3(GR_THREADS), 0, st, img, stride, h, w, s, ny, nx, o);
+    else
+        hipLaunchKernelGGL(gram_kernel<1>, dim3(nb, 2), dim3(GR_THREADS), 0, st, img, stride, h, w, s, ny, nx, o);
+    return hipGetLastError();
+}
+
+}  // namespace htsvd

@@ -249,4 +249,7 @@ hipError_t launch_fill_tau_learned(double *tau, const ImageGeom &g, int tile, co
                                    const int32_t *use_plain, const double *sigma_est, const double *sigma_hat,
                                    double mult, hipStream_t st);
 
+// Channel Gram sums of the reference patches (rows, then columns) into out[2][c][c][8][8].
+hipError_t launch_gram(const uint8_t *img, int64_t stride, int h, int w, int c, int s, int64_t *out, hipStream_t st);
+
 }  // namespace htsvd

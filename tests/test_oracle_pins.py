@@ -130,6 +130,89 @@ def test_learned_basis_is_orthogonal_and_real(basis3, basis1):
             assert np.allclose(oracle.tprod_fft(oracle.ttranspose(T), T), Id, atol=1e-12)
 
 
+# ---- learned basis: Sec. III-B, Eq. 10-11 --------------------------------------
+
+def _py_grid(n, ps, s):
+    g = list(range(0, n - ps + 1, s))
+    if g[-1] != n - ps:
+        g.append(n - ps)
+    return g
+
+
+def test_channel_gram_by_brute_force():
+    """The Gram sums over all reference patches, with Python integers and loops."""
+    from oracle import learn_basis as lb
+    rng = np.random.default_rng(21)
+    for h, w, c, s in ((13, 11, 3, 3), (8, 17, 1, 5), (10, 8, 3, 1)):
+        img = rng.integers(0, 256, (h, w, c) if c == 3 else (h, w)).astype(np.uint8)
+        a = img.astype(np.int64).reshape(h, w, c)
+        G = lb.channel_gram(img, 8, s)
+        want = np.zeros((2, c, c, 8, 8), dtype=object)
+        for y in _py_grid(h, 8, s):
+            for x in _py_grid(w, 8, s):
+                for ca in range(c):
+                    for cb in range(c):
+                        for i in range(8):
+                            for k in range(8):
+                                want[0, ca, cb, i, k] += sum(int(a[y + i, x + j, ca]) * int(a[y + k, x + j, cb])
+                                                             for j in range(8))
+                                want[1, ca, cb, i, k] += sum(int(a[y + j, x + i, ca]) * int(a[y + j, x + k, cb])
+                                                             for j in range(8))
+        assert G.dtype == np.int64 and np.array_equal(G, want.astype(np.int64))
+
+
+def test_slice_covariances_are_the_channel_combinations_of_the_gram():
+    """Eq. 5 and 10: the DFT of the patches along the channels, then P_hat P_hat^H, equals the
+    combination of the real Gram sums with the DFT weights (two routes to the same matrices)."""
+    from oracle import learn_basis as lb
+    img = synth.make_clean(40, 36, 3, seed=4)
+    Crow, Ccol = lb.slice_covariances(img, 8, 3)
+    G = lb.channel_gram(img, 8, 3).astype(np.float64)
+    wv = np.exp(-2j * np.pi / 3)
+    for f in range(3):
+        R = sum(wv ** (f * (a - b)) * G[0, a, b] for a in range(3) for b in range(3))
+        C = sum(wv ** (f * (b - a)) * G[1, a, b] for a in range(3) for b in range(3))
+        assert np.allclose(Crow[f], R, rtol=0, atol=1e-9 * np.abs(R).max())
+        assert np.allclose(Ccol[f], C, rtol=0, atol=1e-9 * np.abs(C).max())
+
+
+def test_learned_basis_diagonalises_the_slice_covariances():
+    """Sec. III-B: the slices of U and V are eigenvector bases of C_row and C_col, ordered by
+    descending eigenvalue, each column's largest-modulus entry real and positive."""
+    from oracle import learn_basis as lb
+    for img in (synth.make_clean(64, 48, 3, seed=8), synth.make_clean(48, 64, 1, seed=9)):
+        U, V = lb.learn(img, 8, 4)
+        Crow, Ccol = lb.slice_covariances(img, 8, 4)
+        for T, Cs in ((U, Crow), (V, Ccol)):
+            Th = oracle.fft3(T)
+            for f in range(T.shape[2]):
+                Q = Th[:, :, f]
+                D = Q.conj().T @ Cs[f] @ Q
+                lam = np.real(np.diag(D))
+                assert np.allclose(D, np.diag(lam), rtol=0, atol=1e-9 * np.abs(lam).max())
+                assert np.all(np.diff(lam) <= 1e-9 * lam[0])
+                for j in range(8):
+                    k = int(np.argmax(np.abs(Q[:, j])))
+                    assert abs(Q[k, j].imag) < 1e-12 and Q[k, j].real > 0
+
+
+def test_learned_basis_closed_form_for_row_constant_patches():
+    """Every patch row constant (image constant along x): C_col^(f) is a multiple of the
+    all-ones matrix, so the top column vector of every slice is 1/sqrt(8) in each entry; the
+    real tensor then has V(:, 0, 0) = 1/sqrt(8) and V(:, 0, k) = 0 for k > 0.  The same with
+    rows and columns exchanged for U."""
+    from oracle import learn_basis as lb
+    rng = np.random.default_rng(2)
+    prof = rng.integers(0, 256, (40, 1, 3)).astype(np.uint8)
+    img = np.ascontiguousarray(np.broadcast_to(prof, (40, 32, 3)))
+    U, V = lb.learn(img, 8, 4)
+    assert np.allclose(V[:, 0, 0], 1 / np.sqrt(8), atol=1e-12)
+    assert np.allclose(V[:, 0, 1:], 0.0, atol=1e-12)
+    U2, V2 = lb.learn(np.ascontiguousarray(img.transpose(1, 0, 2)), 8, 4)
+    assert np.allclose(U2[:, 0, 0], 1 / np.sqrt(8), atol=1e-12)
+    assert np.allclose(U2[:, 0, 1:], 0.0, atol=1e-12)
+
+
 # ---- grouping: Sec. III-A, Eq. 9 ---------------------------------------------
 
 def _brute_groups(img, ps, s, W, K, gnum=6, gden=5):
