@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--size", type=str, default="3000x4000", help="HxW of the single image (default 12 MP)")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
+    ap.add_argument("--learn-basis", action="store_true",
+                    help="time the per-image learned basis instead: learn (U, V) from the noisy 12 MP image, "
+                         "then denoise with it")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -155,6 +158,11 @@ def main():
     dn = ht.Denoiser(0)
     p_plain = dn.params(3, stride=s, window=W, K=32, adaptive=1, estimator=0)
     p_learn = p_plain.replace(estimator=1)
+
+    if args.learn_basis:
+        bench_learn_basis(dn, args, clean, noisy, d_in, d_out, p_plain, stream, s, sigma, gen_s)
+        dn.close()
+        return
 
     # ---- 12 MP, plain form (value), with stage timing for the roofline ----
     plain_fn = lambda: dn.denoise(d_in, AUTO, p_plain, out=d_out)  # noqa: E731
@@ -293,6 +301,102 @@ def bench_batch(dn, args, autotune, stream):
         "unit": "Mpixel/s",
         "gen_s": round(gen_s, 1), "tune_s": round(tune_s, 1), "launch_candidates": allr,
     }
+
+
+PEAK_INT32_VALU_TOPS = 78.6   # 256 CUs x 64 lanes x 2.4 GHz x 2 (a 32-bit multiply-add counts as two ops)
+
+
+def gram_ops(h, w, c, s):
+    """Algorithmic integer ops of the Gram sums: every 8c-vector of the two regroupings (one per
+    reference row and image column, one per reference column and image row) contributes its
+    8c(8c+1)/2 distinct products, a multiply and an add each."""
+    import paper_2512_23569_amd as ht
+    ny, nx = ht.htsvd_ref_count(h, 8, s), ht.htsvd_ref_count(w, 8, s)
+    n_vec = ny * w + nx * h
+    a = 8 * c
+    return n_vec, n_vec * a * (a + 1)
+
+
+def bench_learn_basis(dn, args, clean, noisy, d_in, d_out, p_plain, stream, s, sigma, gen_s):
+    """Per-image learned basis (Sec. III-B): a step learns (U, V) from the noisy input itself
+    (Gram sums on the device, 8x8 eigendecompositions on the host, install) and denoises with it
+    (plain form, sigma estimated).  The roofline figure is the Gram kernel's."""
+    import numpy as np
+    import torch
+
+    import paper_2512_23569_amd as ht
+    import synth
+    AUTO = ht.HTSVD_SIGMA_AUTO
+    h, w, c = noisy.shape
+    shipped = [ht.load_basis_slices(3)]
+
+    def step():
+        dn.learn_basis(d_in, stride=s)
+        dn.denoise(d_in, AUTO, p_plain, out=d_out)
+
+    ms_step = time_steps(step, args.steps, args.warmup, stream)
+    psnr_learned = synth.psnr(clean, d_out.cpu().numpy())
+    # the learning call alone (host-inclusive wall time; it synchronises the stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dn.learn_basis(d_in, stride=s)
+    learn_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # the Gram kernel alone (and its output clear), HIP events on the launch stream
+    g = dn.basis_gram(d_in, stride=s)
+    ms_gram = time_steps(lambda: ht.htsvd_basis_gram(dn.ctx, d_in, h, w, c, w * c, 8, s, g), args.steps * 5,
+                         args.warmup, stream)
+    # the same image denoised with the shipped basis, for the quality comparison
+    ht.htsvd_set_basis(dn.ctx, 8, 3, *shipped[0])
+    dn.denoise(d_in, AUTO, p_plain, out=d_out)
+    psnr_shipped = synth.psnr(clean, d_out.cpu().numpy())
+    n_vec, ops = gram_ops(h, w, c, s)
+    tops = ops / (ms_gram * 1e-3) / 1e12
+    log("learned basis: step %.2f ms, learn %.2f ms, Gram kernel %.3f ms, PSNR %.3f (shipped basis %.3f)"
+        % (ms_step, learn_ms, ms_gram, psnr_learned, psnr_shipped))
+    result = {
+        "metric": "Mpixel/s denoised with a basis learned from the image itself, 12MP RGB sigma=50",
+        "value": round(h * w / (ms_step * 1e-3) / 1e6, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32+f32",
+        "data": "synthetic",
+        "config": {"workload": "12MP RGB %dx%d, AWGN sigma=%g estimated (plain estimator + vote), basis learned "
+                               "from the noisy image (reference stride %d), ps 8, window %d, K 32"
+                               % (w, h, sigma, s, p_plain.window), "form": "plain + learned basis"},
+        "learn_ms": round(learn_ms, 3),
+        "roofline": {"bound": "alu", "kernel": "gram_kernel<3>", "achieved": round(tops, 3),
+                     "peak": PEAK_INT32_VALU_TOPS, "unit": "TOP/s", "frac": round(tops / PEAK_INT32_VALU_TOPS, 4),
+                     "traffic": None, "kernel_ms": round(ms_gram, 4), "ops_per_launch": ops, "vectors": n_vec},
+        "psnr": {"learned_basis": round(psnr_learned, 3), "shipped_basis": round(psnr_shipped, 3)},
+        "input_gen_s": round(gen_s, 1),
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline_learn(noisy, s, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline_learn(noisy, s, target_s):
+    """The oracle's learning (FFT of the patches, covariances, eigh) on a top band of the image,
+    scaled to pixels of the band."""
+    from oracle import learn_basis as lb
+    t0 = time.time()
+    band = noisy[:64]
+    lb.learn(band, 8, s)
+    t1 = time.time() - t0
+    rows = int(min(noisy.shape[0], max(64, 64 * target_s / max(t1, 1e-3))))
+    band = noisy[:rows]
+    t0 = time.time()
+    lb.learn(band, 8, s)
+    dt = time.time() - t0
+    return {"value": round(band.shape[0] * band.shape[1] / dt / 1e6, 5), "unit": "Mpixel/s", "cores": 1,
+            "kind": "oracle", "sample": "the top %d rows of the same image (%.1f s), oracle learning only" % (rows, dt)}
 
 
 def cpu_baseline(noisy, s, W, K, sigma, target_s):

@@ -498,12 +498,17 @@ htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double
     if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
     // Fourier-domain slices (DFT along the channel mode, Eq. 5): X_hat^(f) = sum_k X^(k) w^(f k).
     const cd wv = std::polar(1.0, -2.0 * M_PI / c);
+    cd twp[3], twm[3];   // w^m and w^-m
+    for (int m = 0; m < c; ++m) {
+        twp[m] = std::pow(wv, (double)m);
+        twm[m] = std::pow(wv, -(double)m);
+    }
     cd Uh[3][64], Vh[3][64];
     for (int f = 0; f < c; ++f)
         for (int e = 0; e < 64; ++e) {
             cd u = 0, v = 0;
             for (int k = 0; k < c; ++k) {
-                const cd tw = std::pow(wv, (double)((f * k) % c));
+                const cd tw = twp[(f * k) % c];
                 u += h_U[k * 64 + e] * tw;
                 v += h_V[k * 64 + e] * tw;
             }
@@ -539,25 +544,19 @@ htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double
     const int P = 64 * c;
     std::vector<double> T((size_t)P * P);
     for (int p = 0; p < P; ++p) {
-        cd Gh[3][64];
-        for (int f = 0; f < c; ++f)
-            for (int e = 0; e < 64; ++e) Gh[f][e] = 0;
-        const int kin = p / 64, ein = p % 64;
-        for (int f = 0; f < c; ++f) Gh[f][ein] = std::pow(wv, (double)((f * kin) % c));
+        // The unit patch p has a single nonzero per Fourier slice, w^(f kin) at (a0, b0), so
+        // S_hat^(f)(i, j) = conj(U_hat^(f)(a0, i)) w^(f kin) V_hat^(f)(b0, j).
+        const int kin = p / 64, a0 = (p % 64) / 8, b0 = p % 8;
         cd Sh[3][64];
-        for (int f = 0; f < c; ++f)
+        for (int f = 0; f < c; ++f) {
+            const cd g = twp[(f * kin) % c];
             for (int i = 0; i < 8; ++i)
-                for (int j = 0; j < 8; ++j) {
-                    cd acc = 0;
-                    for (int a = 0; a < 8; ++a)
-                        for (int b = 0; b < 8; ++b)
-                            acc += std::conj(Uh[f][a * 8 + i]) * Gh[f][a * 8 + b] * Vh[f][b * 8 + j];
-                    Sh[f][i * 8 + j] = acc;
-                }
+                for (int j = 0; j < 8; ++j) Sh[f][i * 8 + j] = std::conj(Uh[f][a0 * 8 + i]) * g * Vh[f][b0 * 8 + j];
+        }
         for (int k = 0; k < c; ++k)
             for (int e = 0; e < 64; ++e) {
                 cd acc = 0;
-                for (int f = 0; f < c; ++f) acc += Sh[f][e] * std::pow(wv, -(double)((f * k) % c));
+                for (int f = 0; f < c; ++f) acc += Sh[f][e] * twm[(f * k) % c];
                 T[(size_t)(k * 64 + e) * P + p] = acc.real() / c;
             }
     }
@@ -582,13 +581,20 @@ htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double
         } else {
             for (int e2 = 0; e2 < 64; ++e2) Lxi[(size_t)e2 * P + e2] = LSi[(size_t)e2 * P + e2] = 1.0;
         }
+        // A B (or A B^T) over the nonzeros of both factors (the channel maps are sparse).
         auto mul = [&](const std::vector<double> &A, const std::vector<double> &B, bool bt) {
+            std::vector<std::vector<std::pair<int, double>>> nz(P);
+            for (int k = 0; k < P; ++k)
+                for (int j = 0; j < P; ++j) {
+                    const double b = bt ? B[(size_t)j * P + k] : B[(size_t)k * P + j];
+                    if (b != 0.0) nz[k].emplace_back(j, b);
+                }
             std::vector<double> Cm((size_t)P * P, 0.0);
             for (int i = 0; i < P; ++i)
                 for (int k = 0; k < P; ++k) {
                     const double a = A[(size_t)i * P + k];
                     if (a == 0.0) continue;
-                    for (int j = 0; j < P; ++j) Cm[(size_t)i * P + j] += a * (bt ? B[(size_t)j * P + k] : B[(size_t)k * P + j]);
+                    for (const auto &jb : nz[k]) Cm[(size_t)i * P + jb.first] += a * jb.second;
                 }
             return Cm;
         };

@@ -83,20 +83,38 @@ __global__ __launch_bounds__(GR_THREADS) void gram_kernel(const uint8_t *__restr
                 for (int c = 0; c < C; ++c) {
                     const uint32_t v = p[i * step + c];
                     sv[tid * A + c * PS + i] = v;
-                    smv[tid * A + c * PS + i] = m * v;
+                    smv[tid * A + c * PS + i] = __umul24(m, v);
                 }
         }
         __syncthreads();
         if (active) {
             // At most 256/GRP vectors of weight <= 9 per chunk: every partial sum stays below 2^32.
+            // Factors below 2^24 (weighted value <= 9 * 255, value <= 255): 24-bit multiply-adds.
             uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-            for (int v = grp; v < nv; v += GRP) {
+            int v = grp;
+            for (; v + 3 * GRP < nv; v += 4 * GRP) {
+                uint32_t x[4];
+                uint4 y[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    x[u] = smv[(v + u * GRP) * A + r];
+                    y[u] = *reinterpret_cast<const uint4 *>(&sv[(v + u * GRP) * A + 4 * bb]);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a0 = __umul24(x[u], y[u].x) + a0;
+                    a1 = __umul24(x[u], y[u].y) + a1;
+                    a2 = __umul24(x[u], y[u].z) + a2;
+                    a3 = __umul24(x[u], y[u].w) + a3;
+                }
+            }
+            for (; v < nv; v += GRP) {
                 const uint32_t x = smv[v * A + r];
                 const uint4 y = *reinterpret_cast<const uint4 *>(&sv[v * A + 4 * bb]);
-                a0 += x * y.x;
-                a1 += x * y.y;
-                a2 += x * y.z;
-                a3 += x * y.w;
+                a0 = __umul24(x, y.x) + a0;
+                a1 = __umul24(x, y.y) + a1;
+                a2 = __umul24(x, y.z) + a2;
+                a3 = __umul24(x, y.w) + a3;
             }
             tot0 += a0;
             tot1 += a1;
