@@ -42,6 +42,8 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_mfma_12mp_traffic.json")
 FILTER_SRC = os.path.join(ROOT, "paper_2512_23569_amd", "csrc", "filter_mfma.hip")
 PEAK_F16_MFMA_TFLOPS = 2500.0    # MI355X dense fp16 matrix peak
+GRAM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_kernel_12mp_traffic.json")
+GRAM_SRC = os.path.join(ROOT, "paper_2512_23569_amd", "csrc", "basis_learn.hip")
 
 
 def log(msg):
@@ -63,20 +65,26 @@ def filter_mfma_flops_per_group(K: int, c: int) -> float:
     return (2 + 3) * blocks * 32768.0 * (K / 32.0)
 
 
-def filter_source_hash() -> str:
-    with open(FILTER_SRC, "rb") as f:
+def source_hash(path: str) -> str:
+    with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel_launch_refs: int):
-    """HBM bytes per launch of the filter kernel from the committed counter summary, scaled
-    to this launch; None when the summary is missing or the kernel source changed since."""
+def filter_source_hash() -> str:
+    return source_hash(FILTER_SRC)
+
+
+def measured_traffic(kernel_launch_refs: int, traffic_file: str = TRAFFIC_FILE, src: str = FILTER_SRC,
+                     hash_key: str = "filter_src_sha256_16", size_key: str = "n_ref"):
+    """HBM bytes per launch of a kernel from its committed counter summary, for the launch
+    size it was measured at; None when the summary is missing, the size differs or the kernel
+    source changed since."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("filter_src_sha256_16") != filter_source_hash() or t.get("n_ref") != kernel_launch_refs:
+    if t.get(hash_key) != source_hash(src) or t.get(size_key) != kernel_launch_refs:
         return None
     return t.get("bytes_per_launch")
 
@@ -117,6 +125,9 @@ def main():
     ap.add_argument("--learn-basis", action="store_true",
                     help="time the per-image learned basis instead: learn (U, V) from the noisy 12 MP image, "
                          "then denoise with it")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time a parameter sweep instead: sigma in {30..70} x K in {16, 32} with one grouping pass, "
+                         "against one call per setting")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -158,6 +169,11 @@ def main():
     dn = ht.Denoiser(0)
     p_plain = dn.params(3, stride=s, window=W, K=32, adaptive=1, estimator=0)
     p_learn = p_plain.replace(estimator=1)
+
+    if args.sweep:
+        bench_sweep(dn, args, clean, d_in, stream, s, W, sigma, gen_s)
+        dn.close()
+        return
 
     if args.learn_basis:
         bench_learn_basis(dn, args, clean, noisy, d_in, d_out, p_plain, stream, s, sigma, gen_s)
@@ -303,6 +319,62 @@ def bench_batch(dn, args, autotune, stream):
     }
 
 
+def bench_sweep(dn, args, clean, d_in, stream, s, W, sigma, gen_s):
+    """Parameter selection (Sec. III-D-3): the same image denoised under 10 (sigma, K) settings,
+    once with one grouping pass for all (htsvd_denoise_sweep, groups of 32 whose first 16
+    members are the 16-member groups), once as 10 separate htsvd_denoise calls.  Reports the
+    sweep's throughput in output pixels per second, the speedup, and the setting with the best
+    PSNR (the selection the sweep serves)."""
+    import torch
+
+    import paper_2512_23569_amd as ht
+    import synth
+    h, w, c = d_in.shape
+    settings = [(sg, K) for K in (16, 32) for sg in (30.0, 40.0, 50.0, 60.0, 70.0)]
+    p = dn.params(3, stride=s, window=W, K=32)
+    outs = [torch.empty((h, w, c), dtype=torch.float32, device=d_in.device) for _ in settings]
+    sweep_fn = lambda: dn.denoise_sweep(d_in, settings, p, outs=outs)  # noqa: E731
+
+    def singles():
+        for (sg, K), o in zip(settings, outs):
+            dn.denoise(d_in, sg, p.replace(K=K), out=o)
+
+    ht.htsvd_set_timing(dn.ctx, True)
+    ms_sweep = time_steps(sweep_fn, args.steps, args.warmup, stream)
+    stages = ht.htsvd_stage_times(dn.ctx)
+    ht.htsvd_set_timing(dn.ctx, False)
+    psnrs = {"sigma%g_K%d" % st: round(synth.psnr(clean, o.cpu().numpy()), 3) for st, o in zip(settings, outs)}
+    ms_single = time_steps(singles, args.steps, args.warmup, stream)
+    best = max(psnrs, key=psnrs.get)
+    n_out = len(settings) * h * w
+    log("sweep of %d settings: %.2f ms (one call each: %.2f ms), best %s %.3f dB"
+        % (len(settings), ms_sweep, ms_single, best, psnrs[best]))
+    result = {
+        "metric": "output Mpixel/s of a 10-setting parameter sweep with one grouping pass, 12MP RGB",
+        "value": round(n_out / (ms_sweep * 1e-3) / 1e6, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_sweep, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "12MP RGB %dx%d, AWGN sigma=%g, known-sigma settings sigma in {30,40,50,60,70} x K in "
+                               "{16,32}, ps 8, stride %d, window %d, grouping at K 32" % (w, h, sigma, s, W),
+                   "form": "sweep"},
+        "single_calls_ms": round(ms_single, 3),
+        "speedup_vs_single_calls": round(ms_single / ms_sweep, 3),
+        "stages_ms_per_launch": {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]},
+        "psnr": psnrs,
+        "best_setting": best,
+        "input_gen_s": round(gen_s, 1),
+    }
+    print(json.dumps(result), flush=True)
+
+
 PEAK_INT32_VALU_TOPS = 78.6   # 256 CUs x 64 lanes x 2.4 GHz x 2 (a 32-bit multiply-add counts as two ops)
 
 
@@ -373,7 +445,8 @@ def bench_learn_basis(dn, args, clean, noisy, d_in, d_out, p_plain, stream, s, s
         "learn_ms": round(learn_ms, 3),
         "roofline": {"bound": "alu", "kernel": "gram_kernel<3>", "achieved": round(tops, 3),
                      "peak": PEAK_INT32_VALU_TOPS, "unit": "TOP/s", "frac": round(tops / PEAK_INT32_VALU_TOPS, 4),
-                     "traffic": None, "kernel_ms": round(ms_gram, 4), "ops_per_launch": ops, "vectors": n_vec},
+                     "traffic": measured_traffic(n_vec, GRAM_TRAFFIC_FILE, GRAM_SRC, "src_sha256_16", "vectors"),
+                     "kernel_ms": round(ms_gram, 4), "ops_per_launch": ops, "vectors": n_vec},
         "psnr": {"learned_basis": round(psnr_learned, 3), "shipped_basis": round(psnr_shipped, 3)},
         "input_gen_s": round(gen_s, 1),
     }

@@ -140,6 +140,26 @@ htsvd_status htsvd_denoise_tau(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, i
                                int64_t in_stride, const double *d_tau_ref, const htsvd_params *p, float *d_out,
                                int64_t out_stride, void *stream);
 
+/* One setting of a parameter sweep. */
+typedef struct {
+    float sigma;          /* known noise level (> 0); tau = sigma * (p->tau_mult, or sqrt(2 ln(c K ps^2))) */
+    int32_t K;            /* group size of this setting: 4, 8, 16 or 32, at most p->K */
+    float *d_out;         /* device, float32 HWC */
+    int64_t out_stride;   /* elements per row */
+} htsvd_sweep_item;
+
+/* Denoises one image under n parameter settings (sigma, K) with a single grouping pass (the
+ * cached patch indices of the paper's fast implementation, Sec. III-D-3): groups are matched
+ * once with p->K members; a setting with K < p->K uses the first K members of each group, which
+ * are exactly its K-member groups (members are ordered by distance, then position).  Each
+ * output equals the one htsvd_denoise gives for that sigma with that K (p->adaptive must be 0:
+ * the vote of Eq. 23 depends on the group size).  Asynchronous on `stream`.  Errors:
+ * HTSVD_EINVAL (n < 1, null items or outputs, sigma <= 0, K > p->K or not a power of two in
+ * 4..32, out_stride < w*c), HTSVD_ENOTSUP (p->adaptive), and those of htsvd_denoise. */
+htsvd_status htsvd_denoise_sweep(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                                 int64_t in_stride, int32_t n, const htsvd_sweep_item *items,
+                                 const htsvd_params *p, void *stream);
+
 /* One image of a batched call. */
 typedef struct {
     const uint8_t *d_in;  /* device, uint8 HWC */

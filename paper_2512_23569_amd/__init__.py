@@ -50,6 +50,11 @@ class htsvd_image(ctypes.Structure):
     ]
 
 
+class htsvd_sweep_item(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_float), ("K", ctypes.c_int32), ("d_out", ctypes.c_void_p),
+                ("out_stride", ctypes.c_int64)]
+
+
 class htsvd_batch_opts(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("k_sigma_cutoff", ctypes.c_float), ("tile_side", ctypes.c_int32)]
@@ -77,6 +82,8 @@ _SIGS = {
     "htsvd_block_match": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _PP, _vp, _vp, _vp]),
     "htsvd_denoise": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _i64, _vp]),
     "htsvd_denoise_tau": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _vp, _PP, _vp, _i64, _vp]),
+    "htsvd_denoise_sweep": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _i32, ctypes.POINTER(htsvd_sweep_item), _PP,
+                                   _vp]),
     "htsvd_denoise_batch": (_i32, [_vp, _i32, ctypes.POINTER(htsvd_image), _PP, ctypes.POINTER(htsvd_batch_opts), _vp]),
     "htsvd_estimate_sigma": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _vp, _vp, _vp]),
     "htsvd_sync": (_i32, [_vp, _vp]),
@@ -228,6 +235,14 @@ def htsvd_denoise_batch(ctx, images, params, use_graph=1, blocks_per_cu=1, k_sig
     opts = htsvd_batch_opts(int(use_graph), int(blocks_per_cu), float(k_sigma_cutoff), int(tile_side))
     _check(lib().htsvd_denoise_batch(ctx, len(images), arr, ctypes.byref(params), ctypes.byref(opts),
                                      _stream(stream)))
+
+
+def htsvd_denoise_sweep(ctx, d_in, h, w, c, in_stride, items, params, stream=None):
+    """items: a sequence of htsvd_sweep_item (device output pointers filled in by the caller)."""
+    import torch
+    arr = (htsvd_sweep_item * len(items))(*items)
+    _check(lib().htsvd_denoise_sweep(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, c, in_stride, len(items), arr,
+                                     ctypes.byref(params), _stream(stream)))
 
 
 def htsvd_estimate_sigma(ctx, d_in, h, w, c, in_stride, sigma, params, d_sigma_est=None, d_sigma_hat=None,
@@ -408,6 +423,20 @@ class Denoiser:
             descs.append(htsvd_image(x.data_ptr(), h, w, c, st, float(sigmas[i]), int(Ks[i]) if Ks else 0,
                                      outs[i].data_ptr(), outs[i].stride(0)))
         htsvd_denoise_batch(self.ctx, descs, params, use_graph, blocks_per_cu, k_sigma_cutoff, tile_side, stream)
+        return outs
+
+    def denoise_sweep(self, img, settings, params, outs=None, stream=None):
+        """Denoises one device image under several (sigma, K) settings with one grouping pass
+        (params.K members, the largest K of the settings or more).  Returns the outputs."""
+        import torch
+        h, w, c, st = _img_dims(img)
+        if outs is None:
+            outs = [torch.empty(img.shape, dtype=torch.float32, device=img.device) for _ in settings]
+        items = []
+        for (sigma, K), o in zip(settings, outs):
+            _dptr(o, torch.float32, "output")
+            items.append(htsvd_sweep_item(float(sigma), int(K), o.data_ptr(), o.stride(0)))
+        htsvd_denoise_sweep(self.ctx, img, h, w, c, st, items, params, stream)
         return outs
 
     def guard_count(self):

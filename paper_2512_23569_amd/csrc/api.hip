@@ -795,6 +795,64 @@ htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32
     return run_filter(ctx, g, mp, wk, wk.tau, d_out, out_stride, st);
 }
 
+htsvd_status htsvd_denoise_sweep(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                                 int64_t in_stride, int32_t n, const htsvd_sweep_item *items,
+                                 const htsvd_params *p, void *stream) {
+    ImageGeom g;
+    MethodParams mp;
+    htsvd_status s = validate(ctx, d_in, h, w, c, in_stride, p, &g, &mp, true);
+    if (s != HTSVD_OK) return s;
+    if (n < 1 || !items) return fail(HTSVD_EINVAL, "a sweep needs at least one setting");
+    if (p->adaptive) return fail(HTSVD_ENOTSUP, "sweeps take known sigma without the vote (adaptive = 0)");
+    bool need_prefix = false;
+    size_t region_max = 0;
+    for (int i = 0; i < n; ++i) {
+        const htsvd_sweep_item &it = items[i];
+        if (!(it.sigma > 0.f) || !std::isfinite(it.sigma)) return fail(HTSVD_EINVAL, "sweep sigma must be > 0");
+        if (!(it.K == 4 || it.K == 8 || it.K == 16 || it.K == 32) || it.K > mp.K)
+            return fail(HTSVD_EINVAL, "sweep K must be 4, 8, 16 or 32 and at most params K");
+        if (!it.d_out) return fail(HTSVD_EINVAL, "null sweep output");
+        if (it.out_stride < (int64_t)w * c) return fail(HTSVD_EINVAL, "out_stride < w*c");
+        need_prefix |= it.K < mp.K;
+        region_max = std::max(region_max, filter_region_bytes(g, mp.W, it.K));
+    }
+    const int tile = p->subimage;
+    const int64_t n_ref = (int64_t)g.ny * g.nx;
+    // Workspace: the single-call layout for p->K, then the prefix groups and a region buffer
+    // sized for the largest tiling among the settings.
+    const Ws w0 = plan_ws(nullptr, g, mp.W, mp.K, tile);
+    const size_t off_pre = align256(w0.total);
+    const size_t off_reg = off_pre + align256(need_prefix ? sizeof(int32_t) * n_ref * (mp.K / 2) : 0);
+    if ((s = ensure_ws(ctx, off_reg + region_max)) != HTSVD_OK) return s;
+    const Ws wk = plan_ws(ctx->ws, g, mp.W, mp.K, tile);
+    int32_t *idx_pre = (int32_t *)((char *)ctx->ws + off_pre);
+    float *regions = (float *)((char *)ctx->ws + off_reg);
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = run_bm(ctx, g, mp, wk, st)) != HTSVD_OK) return s;
+    int pre_k = 0;   // group size currently held in idx_pre
+    hipError_t e;
+    for (int i = 0; i < n; ++i) {
+        const htsvd_sweep_item &it = items[i];
+        MethodParams mpi = mp;
+        mpi.K = it.K;
+        Ws wi = wk;
+        wi.regions = regions;
+        if (it.K < mp.K) {
+            if (pre_k != it.K) {
+                if ((e = launch_idx_prefix(wk.idx, mp.K, idx_pre, it.K, n_ref, st)) != hipSuccess)
+                    return hip_fail(e, "group prefix");
+                pre_k = it.K;
+            }
+            wi.idx = idx_pre;
+        }
+        const double mult = p->tau_mult > 0.0 ? p->tau_mult : default_mult(c, it.K);
+        if ((e = launch_fill_tau(wk.tau, n_ref, nullptr, (double)it.sigma, mult, g, tile, st)) != hipSuccess)
+            return hip_fail(e, "tau");
+        if ((s = run_filter(ctx, g, mpi, wi, wk.tau, it.d_out, it.out_stride, st)) != HTSVD_OK) return s;
+    }
+    return HTSVD_OK;
+}
+
 htsvd_status htsvd_estimate_sigma(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
                                   int64_t in_stride, float sigma, const htsvd_params *p, double *d_sigma_est,
                                   double *d_sigma_hat, int32_t *d_votes, void *stream) {

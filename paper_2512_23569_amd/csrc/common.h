@@ -171,6 +171,8 @@ hipError_t launch_block_match(const ImageGeom &g, const MethodParams &mp, int32_
 hipError_t launch_fill_tau(double *tau_ref, int64_t n_ref, const double *sigma_tile, double sigma_const,
                            double mult, const ImageGeom &g, int tile, hipStream_t st);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+// out[r*kout + k] = in[r*kin + k] for k < kout <= kin.
+hipError_t launch_idx_prefix(const int32_t *in, int kin, int32_t *out, int kout, int64_t n_ref, hipStream_t st);
 
 // Noise estimation (plain): per sub-image covariance eigenvalues and the tail rule.
 // mom: sigma_mom_ints() int32 per (sub-image, channel) of scratch; cov_work: c doubles per sub-image.

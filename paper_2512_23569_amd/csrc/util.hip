@@ -176,6 +176,23 @@ hipError_t launch_zero_rows(float *p, int64_t rows, int64_t cols, int64_t stride
     return hipGetLastError();
 }
 
+// The first kout members of every group stored with kin members per reference.
+__global__ void idx_prefix_kernel(const int32_t *__restrict__ in, int kin, int32_t *__restrict__ out, int kout,
+                                  int64_t n) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n * kout) return;
+    const int64_t r = e / kout;
+    out[e] = in[r * kin + (int)(e - r * kout)];
+}
+
+hipError_t launch_idx_prefix(const int32_t *in, int kin, int32_t *out, int kout, int64_t n_ref, hipStream_t st) {
+    const int64_t n = n_ref * kout;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(idx_prefix_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, kin, out, kout,
+                       n_ref);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
     const int64_t n = (int64_t)(bytes / 4);
     if (n == 0) return hipSuccess;

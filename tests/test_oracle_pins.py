@@ -262,6 +262,21 @@ def test_block_match_brute_force_with_planted_ties(h, w, c, K, W, s, seed):
     assert np.array_equal(dist, bd)
 
 
+@pytest.mark.parametrize("c,seed", [(1, 5), (3, 6)])
+def test_smaller_groups_are_prefixes_of_larger_ones(c, seed):
+    """Groups are the K smallest keys (distance, row, column) in ascending order, so the K-member
+    group is the first K members of the 2K-member one (the basis of reusing one grouping pass
+    across group sizes, Sec. III-D-3).  Checked on a tie-heavy image, with brute force at K = 4."""
+    rng = np.random.default_rng(seed)
+    img = rng.integers(0, 3, (26, 30, c) if c == 3 else (26, 30)).astype(np.uint8) * 100
+    i32, d32 = oracle.block_match(img, 8, 3, 13, 32)
+    for K in (4, 8, 16):
+        iK, dK = oracle.block_match(img, 8, 3, 13, K)
+        assert np.array_equal(iK, i32[:, :K]) and np.array_equal(dK, d32[:, :K])
+    bi, bd = _brute_groups(img, 8, 3, 13, 4)
+    assert np.array_equal(bi, i32[:, :4]) and np.array_equal(bd, d32[:, :4])
+
+
 def test_flat_image_groups_are_raster_order():
     img = np.full((20, 20), 77, np.uint8)
     idx, dist = oracle.block_match(img, 8, 4, 5, 8)
