@@ -49,7 +49,7 @@ def _L():
         lib.orc_block_match_list.argtypes = [p, i32, i32, i32, i64, i32, i32, i32, i32, i32, i32, p, i64, p, p,
                                              i32]
         lib.orc_denoise.argtypes = [p, i32, i32, i32, i64, i32, i32, i32, i32, i32, i32, p, p, p, p, dbl, p,
-                                    i32, i64, i64]
+                                    i32, i64, i64, p, p]
         _lib = lib
     return _lib
 
@@ -194,9 +194,11 @@ def block_match_list(img: np.ndarray, refs, ps: int, s: int, W: int, K: int, gnu
 
 def denoise(img: np.ndarray, U: np.ndarray, V: np.ndarray, tau, ps: int = 8, s: int = 4, W: int = 21,
             K: int = 16, gnum: int = 6, gden: int = 5, guard: float = 0.0, nthreads: int = 0,
-            r_begin: int = 0, r_end: int = -1, return_near: bool = False):
+            r_begin: int = 0, r_end: int = -1, return_near: bool = False, pest=None, ra_on=None):
     """Haar-tSVD with per-reference thresholds (scalar tau = same for all).
-    U, V: basis tensors (ps, ps, c).  Returns FP64 (h, w[, c])."""
+    U, V: basis tensors (ps, ps, c).  Returns FP64 (h, w[, c]).
+    pest (n_ref, c, ps, ps) FP64 and ra_on (n_ref,) bool: RA-Haar-tSVD (Eq. 24-25), the first
+    Haar row of each flagged group replaced by sqrt(K) U^T * pest * V and not thresholded."""
     a, h, w, c = _img3(img)
     L = _L()
     n_ref = L.orc_ref_count(h, ps, s) * L.orc_ref_count(w, ps, s)
@@ -204,8 +206,14 @@ def denoise(img: np.ndarray, U: np.ndarray, V: np.ndarray, tau, ps: int = 8, s: 
     u, v = to_slices(U), to_slices(V)
     out = np.zeros((h, w, c), dtype=np.float64)
     near = ctypes.c_int64(0)
+    pe = ro = None
+    if pest is not None:
+        pe = np.ascontiguousarray(np.asarray(pest, dtype=np.float64).reshape(n_ref, c * ps * ps))
+        ro = np.ascontiguousarray(np.broadcast_to(np.asarray(True if ra_on is None else ra_on, dtype=np.uint8),
+                                                  (n_ref,)))
     _check(L.orc_denoise(_ptr(a), h, w, c, w * c, ps, s, W, K, gnum, gden, _ptr(tau_ref), _ptr(u), _ptr(v),
-                         _ptr(out), float(guard), ctypes.byref(near), nthreads, r_begin, r_end))
+                         _ptr(out), float(guard), ctypes.byref(near), nthreads, r_begin, r_end,
+                         None if pe is None else _ptr(pe), None if ro is None else _ptr(ro)))
     res = out[:, :, 0] if img.ndim == 2 else out
     return (res, int(near.value)) if return_near else res
 

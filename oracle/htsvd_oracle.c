@@ -425,10 +425,13 @@ int orc_block_match_list(const uint8_t *img, int h, int w, int c, int64_t stride
  * U, V: basis tensors (ps x ps x c, slice-major).  out: h*w*c FP64.
  * guard > 0 and n_near != NULL: counts coefficients with ||s| - tau| < guard.
  * Only references with r in [r_begin, r_end) are processed (r_end < 0 means
- * all); the output then averages only their contributions. */
+ * all); the output then averages only their contributions.
+ * pest (n_ref x P, patch layout as the group, may be NULL) and ra_on (n_ref flags): refined
+ * group means of RA-Haar-tSVD for the references whose flag is set. */
 int orc_denoise(const uint8_t *img, int h, int w, int c, int64_t stride, int ps, int s, int W, int K,
                 int gnum, int gden, const double *tau_ref, const double *U, const double *V, double *out,
-                double guard, int64_t *n_near, int nthreads, int64_t r_begin, int64_t r_end)
+                double guard, int64_t *n_near, int nthreads, int64_t r_begin, int64_t r_end,
+                const double *pest, const uint8_t *ra_on)
 {
     int err = check_common(h, w, c, stride, ps, s, W, K);
     if (err) return err;
@@ -507,9 +510,18 @@ int orc_denoise(const uint8_t *img, int h, int w, int c, int64_t stride, int ps,
                         for (int k = 0; k < K; ++k) acc += H[a * K + k] * S[(size_t)k * P + q];
                         Sh[(size_t)a * P + q] = acc;
                     }
+                /* RA-Haar-tSVD (Eq. 24-25): the first Haar row is sqrt(K) times the transformed
+                 * group mean; with a refined mean p_est it becomes sqrt(K) U^T * p_est * V and is
+                 * kept as it is (no threshold); the other rows are thresholded as usual. */
+                int64_t q_first = 0;
+                if (pest && ra_on && ra_on[r]) {
+                    patch_forward(&basis, pest + (size_t)r * P, S, work);
+                    for (int q = 0; q < P; ++q) Sh[q] = sqrt((double)K) * S[q];
+                    q_first = P;
+                }
                 /* Eq. 20: hard threshold */
                 const double tau = tau_ref[r];
-                for (int64_t q = 0; q < (int64_t)K * P; ++q) {
+                for (int64_t q = q_first; q < (int64_t)K * P; ++q) {
                     double v = fabs(Sh[q]);
                     if (guard > 0 && fabs(v - tau) < guard) near_total += 1;
                     if (!(v >= tau)) Sh[q] = 0.0;

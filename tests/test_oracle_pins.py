@@ -213,6 +213,90 @@ def test_learned_basis_closed_form_for_row_constant_patches():
     assert np.allclose(U2[:, 0, 1:], 0.0, atol=1e-12)
 
 
+# ---- RA-Haar-tSVD: Sec. III-E-2, Eq. 24-25 --------------------------------------
+
+def test_fcn_forward_by_loops():
+    """The refinement network's forward pass against per-sample Python loops."""
+    from oracle import fcn
+    c = 1
+    rng = np.random.default_rng(41)
+    params = fcn.init_params(c, 3) + rng.normal(0, 0.01, fcn.param_count(c))
+    means = rng.uniform(0, 255, (3, 64))
+    W1, b1, W2, b2, W3, b3 = fcn.unflatten(params, c)
+    got = fcn.forward(params, means, c)
+    for n in range(3):
+        x = [(float(v) - 128.0) / 128.0 for v in means[n]]
+        h1 = [max(0.0, sum(W1[a, b] * x[b] for b in range(64)) + b1[a]) for a in range(128)]
+        h2 = [max(0.0, sum(W2[a, b] * h1[b] for b in range(128)) + b2[a]) for a in range(128)]
+        r = [sum(W3[a, b] * h2[b] for b in range(128)) + b3[a] for a in range(64)]
+        assert np.allclose(got[n], r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(fcn.refine(params, means, c), means - 128.0 * got, rtol=0, atol=1e-12)
+
+
+def test_fcn_gradient_matches_central_differences():
+    from oracle import fcn
+    c = 1
+    rng = np.random.default_rng(42)
+    params = fcn.init_params(c, 4) * 0.5
+    noisy = rng.uniform(0, 255, (5, 64))
+    clean = noisy + rng.normal(0, 10, noisy.shape)
+    _, g = fcn.loss_and_grad(params, noisy, clean, c)
+    for j in rng.choice(params.size, 40, replace=False):
+        e = np.zeros_like(params)
+        e[j] = 1e-6
+        lp, _ = fcn.loss_and_grad(params + e, noisy, clean, c)
+        lm, _ = fcn.loss_and_grad(params - e, noisy, clean, c)
+        num = (lp - lm) / 2e-6
+        assert abs(num - g[j]) <= 1e-6 * max(1.0, abs(g[j])) + 1e-9, (j, num, g[j])
+
+
+def _ra_setup(c):
+    img = synth.add_awgn(synth.make_clean(40, 44, c, 43), 30.0, 44)
+    U, V = oracle.load_basis(os.path.join(os.path.dirname(GOLD), "..", "paper_2512_23569_amd", "data",
+                                          "basis_ps8_c%d.f64" % c), 8, c)
+    idx, _ = oracle.block_match(img, 8, 4, 15, 8)
+    from oracle import fcn
+    return img, U, V, idx, fcn.group_means(img, idx)
+
+
+@pytest.mark.parametrize("c", [1, 3])
+def test_ra_off_equals_plain(c):
+    img, U, V, idx, means = _ra_setup(c)
+    plain = oracle.denoise(img, U, V, 70.0, s=4, W=15, K=8)
+    off = oracle.denoise(img, U, V, 70.0, s=4, W=15, K=8, pest=means + 5.0, ra_on=np.zeros(len(idx), bool))
+    assert np.array_equal(plain, off)
+
+
+@pytest.mark.parametrize("c", [1, 3])
+def test_ra_with_exact_means_and_zero_threshold_reconstructs(c):
+    """Eq. 24: the first Haar row already is sqrt(K) times the transformed mean, so refining it
+    with the exact mean and keeping every other coefficient reproduces the image."""
+    img, U, V, idx, means = _ra_setup(c)
+    out = oracle.denoise(img, U, V, 0.0, s=4, W=15, K=8, pest=means)
+    assert np.allclose(out, img.astype(np.float64), rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("c", [1, 3])
+def test_ra_with_infinite_threshold_aggregates_the_refined_means(c):
+    """All other Haar rows killed: every member of a group reconstructs to the refined mean,
+    and the output is the uniform aggregate of those means over the members' positions."""
+    img, U, V, idx, means = _ra_setup(c)
+    rng = np.random.default_rng(45)
+    pest = means + rng.normal(0, 3.0, means.shape)
+    out = oracle.denoise(img, U, V, 1e30, s=4, W=15, K=8, pest=pest)
+    a = img if img.ndim == 3 else img[:, :, None]
+    h, w, _ = a.shape
+    num = np.zeros((h, w, c))
+    cnt = np.zeros((h, w))
+    for r in range(len(idx)):
+        for k in range(idx.shape[1]):
+            y, x = divmod(int(idx[r, k]), w)
+            num[y:y + 8, x:x + 8] += np.moveaxis(pest[r], 0, 2)
+            cnt[y:y + 8, x:x + 8] += 1
+    want = np.where(cnt[:, :, None] > 0, num / np.maximum(cnt, 1)[:, :, None], a.astype(np.float64))
+    assert np.allclose(out.reshape(h, w, c), want, rtol=0, atol=1e-9)
+
+
 # ---- grouping: Sec. III-A, Eq. 9 ---------------------------------------------
 
 def _brute_groups(img, ps, s, W, K, gnum=6, gden=5):
