@@ -69,6 +69,10 @@ typedef struct {
     int32_t subimage;    /* sub-image side for sigma estimation and votes, 128 */
     int32_t n_vote;      /* sampled groups per sub-image for the vote, 15 */
     uint64_t vote_seed;  /* seed of the counter-based SplitMix64 sampler of the vote */
+    int32_t ra;          /* 1: RA-Haar-tSVD (Sec. III-E-2, Eq. 24-25): the refinement network of
+                            htsvd_ra_set_weights replaces the first Haar row of every group whose
+                            noise level tau / tau-multiplier exceeds ra_sigma (single-image calls) */
+    double ra_sigma;     /* 30 (Sec. IV-B applies the enhancement where sigma > 30) */
 } htsvd_params;
 
 typedef struct htsvd_ctx htsvd_ctx;
@@ -79,7 +83,7 @@ htsvd_status htsvd_create(htsvd_ctx **out, int device);
 void htsvd_destroy(htsvd_ctx *ctx);
 /* Fills `out` with the defaults for c channels: ps 8, stride 4, window 31 (c=3) or 21 (c=1),
  * K 32 (c=3) or 16 (c=1), tau_mult 0, adaptive 0, beta 1.2, gamma_rank 13, gcp 6/5,
- * estimator 0, subimage 128, n_vote 15, vote_seed 0. */
+ * estimator 0, subimage 128, n_vote 15, vote_seed 0, ra 0, ra_sigma 30. */
 htsvd_status htsvd_default_params(int32_t c, htsvd_params *out);
 
 /* Sets the shared t-SVD basis pair (U, V) for c channels (Sec. III-B, "globally reused"
@@ -139,6 +143,36 @@ htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32
 htsvd_status htsvd_denoise_tau(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
                                int64_t in_stride, const double *d_tau_ref, const htsvd_params *p, float *d_out,
                                int64_t out_stride, void *stream);
+
+/* ---- RA-Haar-tSVD refinement network (Sec. III-E-2, Eq. 24-25) ----
+ * The first Haar row of a group is sqrt(K) times its mean patch p (Eq. 24); a fully connected
+ * network refines p (Eq. 25), trained by residual learning on mean patches of noisy/clean
+ * groups.  With P = 64c values per patch (slice-major: p[(k*8 + i)*8 + j] = p(i, j, k)) and
+ * H = 256 (c = 3) or 128 (c = 1) hidden units:
+ *   x = (p - 128)/128, h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), r = W3 h2 + b3,
+ *   p_est = p - 128 r.
+ * Parameters: FP32, flattened W1 (H x P), b1, W2 (H x H), b2, W3 (P x H), b3, row-major.
+ * Inference runs on the matrix cores (fp16 hi/lo products, FP32 accumulation); training in FP32. */
+int32_t htsvd_ra_param_count(int32_t c);
+/* Copies n = htsvd_ra_param_count(c) host parameters into the context (resets Adam). */
+htsvd_status htsvd_ra_set_weights(htsvd_ctx *ctx, int32_t c, const float *h_params, int64_t n);
+/* Copies the current parameters (after training steps too) to the host. */
+htsvd_status htsvd_ra_get_weights(htsvd_ctx *ctx, int32_t c, float *h_params, int64_t n);
+/* Mean patches of n_ref groups over the image d_in: d_idx[r*K + k] = y*w + x of member k (as
+ * htsvd_block_match gives them; the image may be another one than the groups were matched on,
+ * e.g. the clean image of a training pair).  d_means: n_ref * P FP32, slice-major per group. */
+htsvd_status htsvd_ra_means(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                            int64_t in_stride, const int32_t *d_idx, int32_t K, int64_t n_ref, float *d_means,
+                            void *stream);
+/* Network output r (n * P FP32) for n mean patches (n * P FP32), on the device. */
+htsvd_status htsvd_ra_forward(htsvd_ctx *ctx, int32_t c, const float *d_means, int64_t n, float *d_r, void *stream);
+/* Loss (mean of (r - (noisy - clean)/128)^2) and its gradient (d_grad: param_count FP32) for a
+ * batch of n pairs of mean patches.  Synchronises `stream` for the loss (h_loss may be NULL). */
+htsvd_status htsvd_ra_gradients(htsvd_ctx *ctx, int32_t c, const float *d_noisy, const float *d_clean, int32_t n,
+                                float *d_grad, double *h_loss, void *stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on a batch; h_loss as above. */
+htsvd_status htsvd_ra_train_step(htsvd_ctx *ctx, int32_t c, const float *d_noisy, const float *d_clean, int32_t n,
+                                 float lr, double *h_loss, void *stream);
 
 /* One setting of a parameter sweep. */
 typedef struct {

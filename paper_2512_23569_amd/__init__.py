@@ -28,7 +28,7 @@ class htsvd_params(ctypes.Structure):
         ("tau_mult", ctypes.c_double), ("adaptive", ctypes.c_int32), ("beta", ctypes.c_double),
         ("gamma_rank", ctypes.c_int32), ("gcp_num", ctypes.c_int32), ("gcp_den", ctypes.c_int32),
         ("estimator", ctypes.c_int32), ("subimage", ctypes.c_int32), ("n_vote", ctypes.c_int32),
-        ("vote_seed", ctypes.c_uint64),
+        ("vote_seed", ctypes.c_uint64), ("ra", ctypes.c_int32), ("ra_sigma", ctypes.c_double),
     ]
 
     def replace(self, **kw) -> "htsvd_params":
@@ -98,6 +98,13 @@ _SIGS = {
     "htsvd_cnn_train_step": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _vp, _f32, _vp, _vp]),
     "htsvd_cnn_save": (_i32, [_vp, ctypes.c_char_p]),
     "htsvd_cnn_load": (_i32, [_vp, ctypes.c_char_p]),
+    "htsvd_ra_param_count": (_i32, [_i32]),
+    "htsvd_ra_set_weights": (_i32, [_vp, _i32, _vp, _i64]),
+    "htsvd_ra_get_weights": (_i32, [_vp, _i32, _vp, _i64]),
+    "htsvd_ra_means": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _vp, _i32, _i64, _vp, _vp]),
+    "htsvd_ra_forward": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp]),
+    "htsvd_ra_gradients": (_i32, [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp]),
+    "htsvd_ra_train_step": (_i32, [_vp, _i32, _vp, _vp, _i32, _f32, _vp, _vp]),
     "htsvd_set_timing": (_i32, [_vp, _i32]),
     "htsvd_stage_times": (_i32, [_vp, _vp, _vp]),
 }
@@ -331,6 +338,52 @@ def htsvd_cnn_load(ctx, path: str):
     _check(lib().htsvd_cnn_load(ctx, path.encode()))
 
 
+def htsvd_ra_param_count(c: int) -> int:
+    return int(lib().htsvd_ra_param_count(c))
+
+
+def htsvd_ra_set_weights(ctx, c: int, params: np.ndarray):
+    a = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+    _check(lib().htsvd_ra_set_weights(ctx, c, a.ctypes.data_as(_vp), a.size))
+
+
+def htsvd_ra_get_weights(ctx, c: int) -> np.ndarray:
+    a = np.zeros(htsvd_ra_param_count(c), dtype=np.float32)
+    _check(lib().htsvd_ra_get_weights(ctx, c, a.ctypes.data_as(_vp), a.size))
+    return a
+
+
+def htsvd_ra_means(ctx, d_in, h, w, c, in_stride, d_idx, K, n_ref, d_means, stream=None):
+    import torch
+    _check(lib().htsvd_ra_means(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, c, in_stride,
+                                _dptr(d_idx, torch.int32, "d_idx"), K, n_ref, _dptr(d_means, torch.float32, "d_means"),
+                                _stream(stream)))
+
+
+def htsvd_ra_forward(ctx, c, d_means, n, d_r, stream=None):
+    import torch
+    _check(lib().htsvd_ra_forward(ctx, c, _dptr(d_means, torch.float32, "d_means"), n,
+                                  _dptr(d_r, torch.float32, "d_r"), _stream(stream)))
+
+
+def htsvd_ra_gradients(ctx, c, d_noisy, d_clean, n, d_grad, stream=None) -> float:
+    import torch
+    loss = ctypes.c_double(0.0)
+    _check(lib().htsvd_ra_gradients(ctx, c, _dptr(d_noisy, torch.float32, "d_noisy"),
+                                    _dptr(d_clean, torch.float32, "d_clean"), n, _dptr(d_grad, torch.float32, "d_grad"),
+                                    ctypes.byref(loss), _stream(stream)))
+    return loss.value
+
+
+def htsvd_ra_train_step(ctx, c, d_noisy, d_clean, n, lr, want_loss=True, stream=None):
+    import torch
+    loss = ctypes.c_double(0.0)
+    _check(lib().htsvd_ra_train_step(ctx, c, _dptr(d_noisy, torch.float32, "d_noisy"),
+                                     _dptr(d_clean, torch.float32, "d_clean"), n, float(lr),
+                                     ctypes.byref(loss) if want_loss else None, _stream(stream)))
+    return loss.value if want_loss else None
+
+
 # ---- convenience layer ------------------------------------------------------------
 
 def load_basis_slices(c: int, ps: int = 8):
@@ -352,6 +405,10 @@ class Denoiser:
         net = os.path.join(DATA_DIR, "sigma_cnn_c3.ckpt")
         if load_network and os.path.exists(net):
             htsvd_cnn_load(self.ctx, net)
+        for c in (1, 3):
+            ra = os.path.join(DATA_DIR, "ra_fcn_c%d.f32" % c)
+            if load_network and os.path.exists(ra):
+                htsvd_ra_set_weights(self.ctx, c, np.fromfile(ra, dtype="<f4"))
 
     def close(self):
         if self.ctx is not None:
@@ -438,6 +495,22 @@ class Denoiser:
             items.append(htsvd_sweep_item(float(sigma), int(K), o.data_ptr(), o.stride(0)))
         htsvd_denoise_sweep(self.ctx, img, h, w, c, st, items, params, stream)
         return outs
+
+    def ra_means(self, img, idx, K, stream=None):
+        """Mean patches (n_ref, 64c) FP32 of the groups idx (n_ref, K) over the device image."""
+        import torch
+        h, w, c, st = _img_dims(img)
+        n_ref = idx.shape[0]
+        out = torch.empty((n_ref, 64 * c), dtype=torch.float32, device=img.device)
+        htsvd_ra_means(self.ctx, img, h, w, c, st, idx.contiguous(), K, n_ref, out, stream)
+        return out
+
+    def ra_forward(self, means, c, stream=None):
+        """Network output r (n, 64c) for mean patches (n, 64c)."""
+        import torch
+        out = torch.empty_like(means)
+        htsvd_ra_forward(self.ctx, c, means.contiguous(), means.shape[0], out, stream)
+        return out
 
     def guard_count(self):
         return htsvd_last_guard_count(self.ctx)

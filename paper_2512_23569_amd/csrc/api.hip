@@ -17,13 +17,29 @@
 namespace htsvd {
 hipError_t launch_filter(const ImageGeom &g, int W, int K, const BasisDev &b, const int32_t *idx,
                          const double *tau_ref, float *regions, unsigned long long *gc, float *out, int64_t out_stride,
-                         hipStream_t st, bool gather);
+                         hipStream_t st, bool gather, const float *ra_d = nullptr, const uint8_t *ra_flag = nullptr);
 size_t filter_region_bytes(const ImageGeom &g, int W, int K);
 hipError_t launch_fill_const(double *p, int n, double v, hipStream_t st);
 int bm_lds_bytes(int s, int W, int h, int w);
 }  // namespace htsvd
 
 using namespace htsvd;
+
+// RA-Haar-tSVD refinement network: FP32 master weights with Adam state, and the fp16 hi/lo
+// operand tables the inference kernel reads (plain, and with the last layer folded with the
+// patch transform), rebuilt on the host when the weights or the basis change.
+struct RaState {
+    int n = 0;   // parameters (0: no network)
+    float *w = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    uint16_t *frag = nullptr, *frag3t = nullptr;
+    float *bias = nullptr, *bias3t = nullptr;
+    int64_t step = 0;
+    uint64_t wgen = 1, frag_wgen = 0, fold_wgen = 0, fold_bgen = 0;
+    float *train_ws = nullptr;
+    size_t train_ws_floats = 0;
+    double *partial = nullptr;
+    int partial_cap = 0;
+};
 
 // Learned noise-level network state (device buffers) and its activation workspace.
 struct CnnState {
@@ -54,6 +70,9 @@ struct htsvd_ctx {
     size_t ws_size = 0;
     unsigned long long *d_guard = nullptr;  // [0] re-decided in FP64, [1] past the per-group list
     int64_t *d_gram = nullptr;              // channel Gram sums of the basis learning pass
+    std::vector<double> T64h[2];            // host copies of the FP64 patch transforms
+    uint64_t basis_gen[2] = {0, 0};         // bumped by every basis install
+    RaState ra[2];                          // RA-Haar-tSVD networks, [0]: c=1, [1]: c=3
     // Optional per-stage timing with HIP events recorded on the call's stream.
     bool timing = false;
     hipEvent_t ev[2 * HTSVD_N_STAGES] = {};
@@ -103,6 +122,9 @@ htsvd_status validate(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w,
     if (mh * mw < p->K) return fail(HTSVD_ESHAPE, "a clipped search window holds fewer than K candidates");
     if (need_basis && !ctx->has_basis[c == 3]) return fail(HTSVD_ESTATE, "no basis set for this channel count");
     if (p->subimage != 128) return fail(HTSVD_ENOTSUP, "subimage must be 128");
+    if (p->ra != 0 && p->ra != 1) return fail(HTSVD_EINVAL, "ra must be 0 or 1");
+    if (p->ra && !(p->ra_sigma >= 0.0)) return fail(HTSVD_EINVAL, "ra_sigma must be >= 0");
+
     if (p->adaptive) {
         if (p->n_vote < 1 || p->n_vote > 1024) return fail(HTSVD_EINVAL, "n_vote must be in [1, 1024]");
         if (!(p->beta > 0.0)) return fail(HTSVD_EINVAL, "beta must be > 0");
@@ -145,6 +167,35 @@ htsvd_status ensure_ws(htsvd_ctx *ctx, size_t bytes) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// fp16 bits of x (through FP32), rounded to nearest even, with subnormals.
+uint16_t host_f16(double x) {
+    const float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    const uint32_t sgn = (u >> 16) & 0x8000u;
+    const float af = std::fabs(f);
+    if (af >= 65520.f) return (uint16_t)(sgn | 0x7c00u);
+    if (af < 6.103515625e-05f) {   // subnormal: multiples of 2^-24
+        const float q = std::nearbyint(af * 16777216.f);
+        return (uint16_t)(sgn | (uint32_t)q);
+    }
+    uint32_t e = ((u >> 23) & 0xffu) - 127 + 15, m = u & 0x7fffffu;
+    uint32_t hm = m >> 13, rem = m & 0x1fffu;
+    if (rem > 0x1000u || (rem == 0x1000u && (hm & 1u))) {
+        if (++hm == 0x400u) {
+            hm = 0;
+            ++e;
+        }
+    }
+    return (uint16_t)(sgn | (e << 10) | hm);
+}
+
+double host_f16_value(uint16_t hbits) {
+    const uint32_t e = (hbits >> 10) & 31u, m = hbits & 1023u;
+    const double v = e == 0 ? std::ldexp((double)m, -24) : std::ldexp(1.0 + m / 1024.0, (int)e - 15);
+    return (hbits & 0x8000u) ? -v : v;
+}
 
 // Largest ratio between the learned and the plain sigma of a sub-image at which the learned map
 // is trusted there.
@@ -401,7 +452,8 @@ htsvd_status run_sigma(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &m
 }
 
 htsvd_status run_filter(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &mp, const Ws &w,
-                        const double *tau, float *d_out, int64_t out_stride, hipStream_t st) {
+                        const double *tau, float *d_out, int64_t out_stride, hipStream_t st,
+                        const float *ra_d = nullptr, const uint8_t *ra_flag = nullptr) {
     hipError_t e;
     {
         StageScope sc(ctx, HTSVD_STAGE_CLEAR, st);
@@ -411,7 +463,7 @@ htsvd_status run_filter(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &
     {
         StageScope sc(ctx, HTSVD_STAGE_FILTER, st);
         if ((e = launch_filter(g, mp.W, mp.K, ctx->basis[g.c == 3], w.idx, tau, w.regions, ctx->d_guard, d_out,
-                               out_stride, st, false)) != hipSuccess)
+                               out_stride, st, false, ra_d, ra_flag)) != hipSuccess)
             return hip_fail(e, "filtering");
     }
     {
@@ -419,6 +471,153 @@ htsvd_status run_filter(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &
         if ((e = launch_filter(g, mp.W, mp.K, ctx->basis[g.c == 3], w.idx, tau, w.regions, ctx->d_guard, d_out,
                                out_stride, st, true)) != hipSuccess)
             return hip_fail(e, "aggregation");
+    }
+    return HTSVD_OK;
+}
+
+// Rebuilds the network's operand tables from the master weights when they changed (and the
+// folded last layer when the weights or the basis changed).  Host work; synchronises the device.
+htsvd_status ra_prepare(htsvd_ctx *ctx, int c, bool folded) {
+    RaState &r = ctx->ra[c == 3];
+    const int slot = c == 3;
+    if (r.n == 0) return fail(HTSVD_ESTATE, "no RA network set for this channel count");
+    const bool need_plain = r.frag_wgen != r.wgen;
+    const bool need_fold = folded && (r.fold_wgen != r.wgen || r.fold_bgen != ctx->basis_gen[slot]);
+    if (!need_plain && !need_fold) return HTSVD_OK;
+    if (folded && !ctx->has_basis[slot]) return fail(HTSVD_ESTATE, "no basis set for this channel count");
+    const int P = 64 * c, H = ra_hidden(c);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "synchronise before network upload");
+    std::vector<float> w(r.n);
+    if ((e = hipMemcpy(w.data(), r.w, sizeof(float) * r.n, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "network download");
+    const float *W1 = w.data(), *b1 = W1 + H * P, *W2 = b1 + H, *b2 = W2 + H * H, *W3 = b2 + H, *b3 = W3 + P * H;
+    // operand fragments of a NOUT x KIN row-major matrix: W(nt*32 + l%32, ks*16 + 8*(l/32) + e)
+    auto build = [](const double *M, int NOUT, int KIN, uint16_t *dst) {
+        const int KS = KIN / 16, NT = NOUT / 32;
+        for (int nt = 0; nt < NT; ++nt)
+            for (int ks = 0; ks < KS; ++ks)
+                for (int l = 0; l < 64; ++l)
+                    for (int el = 0; el < 8; ++el) {
+                        const double v = M[(size_t)(nt * 32 + l % 32) * KIN + ks * 16 + 8 * (l / 32) + el];
+                        const uint16_t hi = host_f16(v), lo = host_f16(v - host_f16_value(hi));
+                        dst[((size_t)((nt * KS + ks) * 2 + 0) * 64 + l) * 8 + el] = hi;
+                        dst[((size_t)((nt * KS + ks) * 2 + 1) * 64 + l) * 8 + el] = lo;
+                    }
+    };
+    if (need_plain) {
+        std::vector<uint16_t> fr(ra_frag_halves(c));
+        const std::vector<double> d1(W1, W1 + H * P), d2(W2, W2 + H * H), d3(W3, W3 + P * H);
+        build(d1.data(), H, P, fr.data());
+        build(d2.data(), H, H, fr.data() + (size_t)2 * H * P);
+        build(d3.data(), P, H, fr.data() + (size_t)2 * H * P + (size_t)2 * H * H);
+        std::vector<float> bias(2 * H + P);
+        std::copy(b1, b1 + H, bias.begin());
+        std::copy(b2, b2 + H, bias.begin() + H);
+        std::copy(b3, b3 + P, bias.begin() + 2 * H);
+        if ((e = hipMemcpy(r.frag, fr.data(), sizeof(uint16_t) * fr.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(r.bias, bias.data(), sizeof(float) * bias.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "network upload");
+        r.frag_wgen = r.wgen;
+    }
+    if (need_fold) {
+        // 128 T W3 and 128 T b3: the network's change of the first Haar row, per coefficient
+        const std::vector<double> &T = ctx->T64h[slot];
+        std::vector<double> W3t((size_t)P * H, 0.0);
+        std::vector<float> b3t(P);
+        for (int q = 0; q < P; ++q) {
+            double bq = 0.0;
+            for (int pp = 0; pp < P; ++pp) {
+                const double t = T[(size_t)q * P + pp];
+                if (t == 0.0) continue;
+                for (int u = 0; u < H; ++u) W3t[(size_t)q * H + u] += t * W3[(size_t)pp * H + u];
+                bq += t * b3[pp];
+            }
+            b3t[q] = (float)(128.0 * bq);
+        }
+        for (double &x : W3t) x *= 128.0;
+        std::vector<uint16_t> fr((size_t)2 * P * H);
+        build(W3t.data(), P, H, fr.data());
+        if ((e = hipMemcpy(r.frag3t, fr.data(), sizeof(uint16_t) * fr.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(r.bias3t, b3t.data(), sizeof(float) * P, hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "network upload");
+        r.fold_wgen = r.wgen;
+        r.fold_bgen = ctx->basis_gen[slot];
+    }
+    return HTSVD_OK;
+}
+
+RaWeightsDev ra_dev(const RaState &r) {
+    RaWeightsDev d;
+    d.frag = r.frag;
+    d.frag3t = r.frag3t;
+    d.bias = r.bias;
+    d.bias3t = r.bias3t;
+    return d;
+}
+
+// Workspace of the RA step: the first-Haar-row corrections (n_ref x P floats), then the flags.
+size_t ra_ws_bytes(const ImageGeom &g) {
+    const int64_t n_ref = (int64_t)g.ny * g.nx;
+    return align256(sizeof(float) * n_ref * 64 * g.c) + align256((size_t)n_ref);
+}
+
+// Mean patches of the groups and the network's corrections of their first Haar rows, with the
+// flags of the groups it applies to (tau / mult > sigma_min).
+htsvd_status run_ra(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &mp, const Ws &w, const double *tau,
+                    void *base, double mult, double sigma_min, hipStream_t st, const float **d_out,
+                    const uint8_t **f_out) {
+    htsvd_status s = ra_prepare(ctx, g.c, true);
+    if (s != HTSVD_OK) return s;
+    const int64_t n_ref = (int64_t)g.ny * g.nx;
+    float *D = (float *)base;
+    uint8_t *F = (uint8_t *)base + align256(sizeof(float) * n_ref * 64 * g.c);
+    hipError_t e = launch_ra_forward(g.c, ra_dev(ctx->ra[g.c == 3]), true, nullptr, g.img, g.stride, g.h, g.w, w.idx,
+                                     mp.K, mp.K, n_ref, tau, mult, sigma_min, F, D, st);
+    if (e != hipSuccess) return hip_fail(e, "refinement network");
+    *d_out = D;
+    *f_out = F;
+    return HTSVD_OK;
+}
+
+htsvd_status ra_grad_impl(htsvd_ctx *ctx, int c, const float *d_noisy, const float *d_clean, int n, float *d_grad,
+                          double *h_loss, hipStream_t st) {
+    if (!ctx || !d_noisy || !d_clean || !d_grad) return fail(HTSVD_EINVAL, "null argument");
+    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    if (n < 1 || n > (1 << 20)) return fail(HTSVD_EINVAL, "batch must hold 1 .. 2^20 pairs");
+    RaState &r = ctx->ra[c == 3];
+    if (r.n == 0) return fail(HTSVD_ESTATE, "no RA network set for this channel count");
+    hipError_t e;
+    const size_t need = ra_train_ws_floats(c, n);
+    const int np = (int)(((int64_t)n * 64 * c + 255) / 256);
+    if (r.train_ws_floats < need || r.partial_cap < np) {
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronise before workspace growth");
+        if (r.train_ws) (void)hipFree(r.train_ws);
+        if (r.partial) (void)hipFree(r.partial);
+        r.train_ws = nullptr;
+        r.partial = nullptr;
+        r.train_ws_floats = 0;
+        r.partial_cap = 0;
+        if (hipMalloc(&r.train_ws, sizeof(float) * need) != hipSuccess ||
+            hipMalloc(&r.partial, sizeof(double) * np) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(HTSVD_ENOMEM, "training workspace");
+        }
+        r.train_ws_floats = need;
+        r.partial_cap = np;
+    }
+    int n_partial = 0;
+    if ((e = ra_gradients(c, r.w, d_noisy, d_clean, n, d_grad, r.train_ws, r.partial, &n_partial, st)) != hipSuccess)
+        return hip_fail(e, "network gradients");
+    if (h_loss) {
+        std::vector<double> part(n_partial);
+        if ((e = hipMemcpyAsync(part.data(), r.partial, sizeof(double) * n_partial, hipMemcpyDeviceToHost, st)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(e, "loss download");
+        double sum = 0.0;
+        for (double v : part) sum += v;
+        *h_loss = sum / ((double)n * 64 * c);
     }
     return HTSVD_OK;
 }
@@ -457,6 +656,12 @@ void htsvd_destroy(htsvd_ctx *ctx) {
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->d_guard) (void)hipFree(ctx->d_guard);
     if (ctx->d_gram) (void)hipFree(ctx->d_gram);
+    for (int i = 0; i < 2; ++i) {
+        RaState &r = ctx->ra[i];
+        for (void *q : {(void *)r.w, (void *)r.m, (void *)r.v, (void *)r.grad, (void *)r.frag, (void *)r.frag3t,
+                        (void *)r.bias, (void *)r.bias3t, (void *)r.train_ws, (void *)r.partial})
+            if (q) (void)hipFree(q);
+    }
     cnn_free(ctx->cnn);
     if (ctx->batch.exec) (void)hipGraphExecDestroy(ctx->batch.exec);
     if (ctx->batch.graph) (void)hipGraphDestroy(ctx->batch.graph);
@@ -483,6 +688,8 @@ htsvd_status htsvd_default_params(int32_t c, htsvd_params *out) {
     out->subimage = 128;
     out->n_vote = 15;
     out->vote_seed = 0;
+    out->ra = 0;
+    out->ra_sigma = 30.0;
     return HTSVD_OK;
 }
 
@@ -604,29 +811,8 @@ htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double
             for (int k = 0; k < P; ++k)
                 if ((n < 64) != (k < 64) && (std::fabs(Ff[(size_t)n * P + k]) > 1e-12 || std::fabs(Fi[(size_t)n * P + k]) > 1e-12))
                     return fail(HTSVD_EINVAL, "per-slice transform is not block diagonal");
-        auto f16 = [](double x) -> uint16_t {   // round to nearest even, with subnormals
-            const float f = (float)x;
-            uint32_t u;
-            memcpy(&u, &f, 4);
-            const uint32_t sgn = (u >> 16) & 0x8000u;
-            const float af = std::fabs(f);
-            if (af >= 65520.f) return (uint16_t)(sgn | 0x7c00u);
-            if (af < 6.103515625e-05f) {   // subnormal: multiples of 2^-24
-                const float q = std::nearbyint(af * 16777216.f);
-                return (uint16_t)(sgn | (uint32_t)q);
-            }
-            uint32_t e = ((u >> 23) & 0xffu) - 127 + 15, m = u & 0x7fffffu;
-            uint32_t hm = m >> 13, rem = m & 0x1fffu;
-            if (rem > 0x1000u || (rem == 0x1000u && (hm & 1u))) {
-                if (++hm == 0x400u) { hm = 0; ++e; }
-            }
-            return (uint16_t)(sgn | (e << 10) | hm);
-        };
-        auto f16v = [](uint16_t hbits) -> double {
-            const uint32_t e = (hbits >> 10) & 31u, m = hbits & 1023u;
-            const double v = e == 0 ? std::ldexp((double)m, -24) : std::ldexp(1.0 + m / 1024.0, (int)e - 15);
-            return (hbits & 0x8000u) ? -v : v;
-        };
+        auto f16 = host_f16;
+        auto f16v = host_f16_value;
         frag.assign((size_t)2 * 2 * NP * 64 * 8, 0);
         for (int dir = 0; dir < 2; ++dir) {
             const std::vector<double> &M = dir == 0 ? Ff : Fi;
@@ -672,6 +858,8 @@ htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double
                        hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "basis upload");
     ctx->has_basis[slot] = true;
+    ctx->T64h[slot] = T;
+    ++ctx->basis_gen[slot];
     return HTSVD_OK;
 }
 
@@ -753,11 +941,20 @@ htsvd_status htsvd_denoise_tau(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, i
     if (out_stride < (int64_t)w * c) return fail(HTSVD_EINVAL, "out_stride < w*c");
     const int tile = p->subimage > 0 ? p->subimage : 128;
     Ws w0 = plan_ws(nullptr, g, mp.W, mp.K, tile);
-    if ((s = ensure_ws(ctx, w0.total)) != HTSVD_OK) return s;
+    const size_t off_ra = align256(w0.total);
+    if ((s = ensure_ws(ctx, off_ra + (p->ra ? ra_ws_bytes(g) : 0))) != HTSVD_OK) return s;
     Ws wk = plan_ws(ctx->ws, g, mp.W, mp.K, tile);
     hipStream_t st = (hipStream_t)stream;
     if ((s = run_bm(ctx, g, mp, wk, st)) != HTSVD_OK) return s;
-    return run_filter(ctx, g, mp, wk, d_tau_ref, d_out, out_stride, st);
+    const float *ra_d = nullptr;
+    const uint8_t *ra_f = nullptr;
+    if (p->ra) {
+        const double mult = p->tau_mult > 0.0 ? p->tau_mult : default_mult(c, mp.K);
+        if ((s = run_ra(ctx, g, mp, wk, d_tau_ref, (char *)ctx->ws + off_ra, mult, p->ra_sigma, st, &ra_d, &ra_f)) !=
+            HTSVD_OK)
+            return s;
+    }
+    return run_filter(ctx, g, mp, wk, d_tau_ref, d_out, out_stride, st, ra_d, ra_f);
 }
 
 htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
@@ -774,7 +971,8 @@ htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32
     const bool learned = sigma == HTSVD_SIGMA_AUTO && p->estimator == 1;
     const int tile = p->subimage;
     Ws w0 = plan_ws(nullptr, g, mp.W, mp.K, tile);
-    if ((s = ensure_ws(ctx, w0.total)) != HTSVD_OK) return s;
+    const size_t off_ra = align256(w0.total);
+    if ((s = ensure_ws(ctx, off_ra + (p->ra ? ra_ws_bytes(g) : 0))) != HTSVD_OK) return s;
     Ws wk = plan_ws(ctx->ws, g, mp.W, mp.K, tile);
     const double mult = p->tau_mult > 0.0 ? p->tau_mult : default_mult(c, mp.K);
     hipStream_t st = (hipStream_t)stream;
@@ -792,7 +990,12 @@ htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32
             e = launch_fill_tau(wk.tau, (int64_t)g.ny * g.nx, wk.sig_hat, 0.0, mult, g, tile, st);
     }
     if (e != hipSuccess) return hip_fail(e, "tau");
-    return run_filter(ctx, g, mp, wk, wk.tau, d_out, out_stride, st);
+    const float *ra_d = nullptr;
+    const uint8_t *ra_f = nullptr;
+    if (p->ra && (s = run_ra(ctx, g, mp, wk, wk.tau, (char *)ctx->ws + off_ra, mult, p->ra_sigma, st, &ra_d, &ra_f)) !=
+                     HTSVD_OK)
+        return s;
+    return run_filter(ctx, g, mp, wk, wk.tau, d_out, out_stride, st, ra_d, ra_f);
 }
 
 htsvd_status htsvd_denoise_sweep(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
@@ -804,6 +1007,7 @@ htsvd_status htsvd_denoise_sweep(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h,
     if (s != HTSVD_OK) return s;
     if (n < 1 || !items) return fail(HTSVD_EINVAL, "a sweep needs at least one setting");
     if (p->adaptive) return fail(HTSVD_ENOTSUP, "sweeps take known sigma without the vote (adaptive = 0)");
+    if (p->ra) return fail(HTSVD_ENOTSUP, "RA-Haar-tSVD runs in htsvd_denoise and htsvd_denoise_tau");
     bool need_prefix = false;
     size_t region_max = 0;
     for (int i = 0; i < n; ++i) {
@@ -1208,6 +1412,7 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
                                  const htsvd_batch_opts *opts, void *stream) {
     if (!ctx || !imgs || !p) return fail(HTSVD_EINVAL, "null argument");
     if (n < 1) return fail(HTSVD_EINVAL, "empty batch");
+    if (p->ra) return fail(HTSVD_ENOTSUP, "RA-Haar-tSVD runs in htsvd_denoise and htsvd_denoise_tau");
     htsvd_batch_opts o = {1, 1, 0.f, 0};
     if (opts) o = *opts;
     if (o.blocks_per_cu < 1) o.blocks_per_cu = 1;
@@ -1550,6 +1755,107 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
         if ((e = hipGraphLaunch(ex, st)) != hipSuccess) return hip_fail(e, "graph launch");
     }
     return s;
+}
+
+int32_t htsvd_ra_param_count(int32_t c) { return (c == 1 || c == 3) ? ra_param_count(c) : 0; }
+
+htsvd_status htsvd_ra_set_weights(htsvd_ctx *ctx, int32_t c, const float *h_params, int64_t n) {
+    if (!ctx || !h_params) return fail(HTSVD_EINVAL, "null argument");
+    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    const int N = ra_param_count(c), P = 64 * c, H = ra_hidden(c);
+    if (n != N) return fail(HTSVD_EINVAL, "wrong parameter count");
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(h_params[i])) return fail(HTSVD_EINVAL, "parameters must be finite");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    RaState &r = ctx->ra[c == 3];
+    if (!r.w) {
+        void *q[8] = {};
+        const size_t bytes[8] = {sizeof(float) * N, sizeof(float) * N, sizeof(float) * N, sizeof(float) * N,
+                                 sizeof(uint16_t) * ra_frag_halves(c), sizeof(uint16_t) * 2 * P * H,
+                                 sizeof(float) * (2 * H + P), sizeof(float) * P};
+        for (int i = 0; i < 8; ++i)
+            if (hipMalloc(&q[i], bytes[i]) != hipSuccess) {
+                for (int j = 0; j < i; ++j) (void)hipFree(q[j]);
+                (void)hipGetLastError();
+                return fail(HTSVD_ENOMEM, "network allocation");
+            }
+        r.w = (float *)q[0];
+        r.m = (float *)q[1];
+        r.v = (float *)q[2];
+        r.grad = (float *)q[3];
+        r.frag = (uint16_t *)q[4];
+        r.frag3t = (uint16_t *)q[5];
+        r.bias = (float *)q[6];
+        r.bias3t = (float *)q[7];
+    }
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronise before network upload");
+    if ((e = hipMemcpy(r.w, h_params, sizeof(float) * N, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(r.m, 0, sizeof(float) * N)) != hipSuccess || (e = hipMemset(r.v, 0, sizeof(float) * N)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess)
+        return hip_fail(e, "network upload");
+    r.n = N;
+    r.step = 0;
+    ++r.wgen;
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_ra_get_weights(htsvd_ctx *ctx, int32_t c, float *h_params, int64_t n) {
+    if (!ctx || !h_params) return fail(HTSVD_EINVAL, "null argument");
+    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    RaState &r = ctx->ra[c == 3];
+    if (r.n == 0) return fail(HTSVD_ESTATE, "no RA network set for this channel count");
+    if (n != r.n) return fail(HTSVD_EINVAL, "wrong parameter count");
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(h_params, r.w, sizeof(float) * n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "network download");
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_ra_means(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                            int64_t in_stride, const int32_t *d_idx, int32_t K, int64_t n_ref, float *d_means,
+                            void *stream) {
+    if (!ctx || !d_in || !d_idx || !d_means) return fail(HTSVD_EINVAL, "null argument");
+    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    if (h < PS || w < PS) return fail(HTSVD_ESHAPE, "image smaller than one patch");
+    if (in_stride < (int64_t)w * c) return fail(HTSVD_EINVAL, "in_stride < w*c");
+    if (K < 1 || K > 64) return fail(HTSVD_EINVAL, "K must be in [1, 64]");
+    if (n_ref < 0) return fail(HTSVD_EINVAL, "n_ref must be >= 0");
+    hipError_t e = launch_ra_means(d_in, in_stride, h, w, c, d_idx, K, K, n_ref, d_means, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mean patches");
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_ra_forward(htsvd_ctx *ctx, int32_t c, const float *d_means, int64_t n, float *d_r, void *stream) {
+    if (!ctx || !d_means || !d_r) return fail(HTSVD_EINVAL, "null argument");
+    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    if (n < 0) return fail(HTSVD_EINVAL, "n must be >= 0");
+    htsvd_status s = ra_prepare(ctx, c, false);
+    if (s != HTSVD_OK) return s;
+    hipError_t e = launch_ra_forward(c, ra_dev(ctx->ra[c == 3]), false, d_means, nullptr, 0, 0, 0, nullptr, 0, 1, n,
+                                     nullptr, 0.0, 0.0, nullptr, d_r, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "refinement network");
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_ra_gradients(htsvd_ctx *ctx, int32_t c, const float *d_noisy, const float *d_clean, int32_t n,
+                                float *d_grad, double *h_loss, void *stream) {
+    return ra_grad_impl(ctx, c, d_noisy, d_clean, n, d_grad, h_loss, (hipStream_t)stream);
+}
+
+htsvd_status htsvd_ra_train_step(htsvd_ctx *ctx, int32_t c, const float *d_noisy, const float *d_clean, int32_t n,
+                                 float lr, double *h_loss, void *stream) {
+    if (!ctx) return fail(HTSVD_EINVAL, "null argument");
+    if (!(lr > 0.f)) return fail(HTSVD_EINVAL, "lr must be > 0");
+    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    RaState &r = ctx->ra[c == 3];
+    hipStream_t st = (hipStream_t)stream;
+    htsvd_status s = ra_grad_impl(ctx, c, d_noisy, d_clean, n, r.grad, h_loss, st);
+    if (s != HTSVD_OK) return s;
+    hipError_t e = ra_adam(r.w, r.m, r.v, r.grad, r.n, lr, ++r.step, st);
+    if (e != hipSuccess) return hip_fail(e, "adam");
+    ++r.wgen;
+    return HTSVD_OK;
 }
 
 htsvd_status htsvd_sync(htsvd_ctx *ctx, void *stream) {

@@ -39,6 +39,14 @@ struct BasisDev {
     const void *frag;  // MFMA operand fragments of the per-slice transform matrices (fp16 hi/lo)
 };
 
+// Device copy of the RA-Haar-tSVD refinement network for inference (ra.hip).
+struct RaWeightsDev {
+    const void *frag = nullptr;     // fp16 hi/lo operand fragments of W1, W2, W3
+    const void *frag3t = nullptr;   // of 128 T W3 (the last layer folded with the patch transform)
+    const float *bias = nullptr;    // b1, b2, b3
+    const float *bias3t = nullptr;  // 128 T b3
+};
+
 // Reference tiles of the filter kernel and the image regions their groups reach.
 struct TileGeom {
     int TY, TX;          // references per tile
@@ -203,8 +211,11 @@ int filter_lds_bytes_for(const TileGeom &tg, int C, int K);
 int filter_mfma_lds_bytes(const TileGeom &tg, int C);
 int filter_mfma_group_bytes(int C);  // LDS besides the region
 int filter_mfma_static_bytes();
+// ra_d (n_ref x 64C, may be NULL) and ra_flag (n_ref): RA-Haar-tSVD corrections of the first Haar
+// row, applied to the groups whose flag is set.
 hipError_t launch_filter_mfma(const ImageGeom &g, const TileGeom &tg, int K, const BasisDev &b, const int32_t *idx,
-                              const double *tau_ref, float *regions, unsigned long long *gc, hipStream_t st);
+                              const double *tau_ref, float *regions, unsigned long long *gc, hipStream_t st,
+                              const float *ra_d = nullptr, const uint8_t *ra_flag = nullptr);
 hipError_t launch_filter_mfma_batched(int C, int K, const BatchItem *items, int n_items, const int *unit_start,
                                       int lds, const BasisDev &b, unsigned long long *gc, int *queue, int grid,
                                       hipStream_t st);
@@ -250,6 +261,24 @@ hipError_t launch_learned_judge(const ImageGeom &g, int tile, const float *zmap,
 hipError_t launch_fill_tau_learned(double *tau, const ImageGeom &g, int tile, const float *zmap,
                                    const int32_t *use_plain, const double *sigma_est, const double *sigma_hat,
                                    double mult, hipStream_t st);
+
+// RA-Haar-tSVD refinement network (ra.hip).
+int ra_hidden(int c);
+int ra_param_count(int c);
+size_t ra_frag_halves(int c);    // fp16 values of the W1, W2, W3 fragment tables (hi and lo)
+hipError_t launch_ra_means(const uint8_t *img, int64_t stride, int h, int w, int c, const int32_t *idx,
+                           int idx_stride, int K, int64_t n_ref, float *out, hipStream_t st);
+// Network output for n inputs: from mean patches (means) or from groups (img, idx, K; then
+// flags[r] = tau[r] / mult > sigma_min when flags is not NULL).  folded: the last layer gives
+// 128 T r (the first-Haar-row correction), else r.
+hipError_t launch_ra_forward(int c, const RaWeightsDev &wd, bool folded, const float *means, const uint8_t *img,
+                             int64_t stride, int h, int w, const int32_t *idx, int idx_stride, int K, int64_t n,
+                             const double *tau, double mult, double sigma_min, uint8_t *flags, float *out,
+                             hipStream_t st);
+size_t ra_train_ws_floats(int c, int n);
+hipError_t ra_gradients(int c, const float *w, const float *noisy, const float *clean, int n, float *grad,
+                        float *ws, double *partial, int *n_partial, hipStream_t st);
+hipError_t ra_adam(float *w, float *m, float *v, const float *g, int n, float lr, int64_t step, hipStream_t st);
 
 // Channel Gram sums of the reference patches (rows, then columns) into out[2][c][c][8][8].
 hipError_t launch_gram(const uint8_t *img, int64_t stride, int h, int w, int c, int s, int64_t *out, hipStream_t st);

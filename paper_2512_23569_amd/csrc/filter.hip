@@ -149,9 +149,9 @@ hipError_t launch_gather_batched(int C, const BatchItem *items, int n_items, con
 
 hipError_t launch_filter(const ImageGeom &g, int W, int K, const BasisDev &b, const int32_t *idx,
                          const double *tau_ref, float *regions, unsigned long long *gc, float *out, int64_t out_stride,
-                         hipStream_t st, bool gather) {
+                         hipStream_t st, bool gather, const float *ra_d, const uint8_t *ra_flag) {
     const TileGeom tg = plan_filter_tiles(g, W, K, 0);
-    if (!gather) return launch_filter_mfma(g, tg, K, b, idx, tau_ref, regions, gc, st);
+    if (!gather) return launch_filter_mfma(g, tg, K, b, idx, tau_ref, regions, gc, st, ra_d, ra_flag);
     const int64_t n = (int64_t)g.h * g.w;
     if (g.c == 3)
         hipLaunchKernelGGL(gather_kernel<3>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, tg, regions, out,

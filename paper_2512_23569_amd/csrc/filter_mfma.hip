@@ -178,14 +178,16 @@ __device__ inline v8h ldfrag0(const v8h *FL0, int dir, int term, int pair, int l
 //   FL0: LDS copy of the slice-0 fragments (the 64 x 64 map, both directions); FG: the whole
 //   tables (forward at dir 0, inverse at dir 1), read through the caches for the other slices.
 //   The eight wavefronts of a workgroup share both and the tile's LDS region.
-template <int C, int K>
+template <int C, int K, bool RA = false>
 __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileGeom &tg, const v8h *FL0,
                                                  const v8h *__restrict__ FG, const double *__restrict__ T64,
                                                  const int32_t *__restrict__ idx, const int idx_stride,
                                                  const double *__restrict__ tau_ref, const double tau_mul,
                                                  float *__restrict__ regions,
                                                  unsigned long long *__restrict__ guard_count, const int tile,
-                                                 float *region, uint32_t *xbuf_all, MfmaShared &sh) {
+                                                 float *region, uint32_t *xbuf_all, MfmaShared &sh,
+                                                 const float *__restrict__ ra_d = nullptr,
+                                                 const uint8_t *__restrict__ ra_flag = nullptr) {
     constexpr int P = 64 * C;
     constexpr int CH = C + 1;
     constexpr int NT = 2 * C;            // 32-column tiles of the 64C coefficients
@@ -267,6 +269,19 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                 hi_t[gs][l] = guard ? tl + MGUARD * sc : lo_t[gs][l];
             }
         }
+        // RA-Haar-tSVD: registers holding the first Haar row (the group sum) of groups whose
+        // mean the network refines; their value becomes K (T p_est)(q) = sum - K ra_d(q), kept
+        // without threshold.
+        uint32_t ramask = 0;
+        int64_t ra_row[NS];
+        if constexpr (RA) {
+#pragma unroll
+            for (int gs = 0; gs < NS; ++gs) {
+                const int gi = K == 32 ? 0 : (16 * h + gs * KL) / K;
+                ra_row[gs] = ref_of(gi) * P;
+                if (base + gi < nref && (K < 32 || h == 0) && ra_flag[ref_of(gi)]) ramask |= 1u << (gs * KL);
+            }
+        }
 
         v16f out[NT];
 #pragma unroll
@@ -280,6 +295,14 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
                 for (int i = 0; i < 2 * C; ++i) asm volatile("" : "+v"(raw[sp][i]));
+            float dval[C][NS];
+            if constexpr (RA) {
+#pragma unroll
+                for (int sl = 0; sl < C; ++sl)
+#pragma unroll
+                    for (int gs = 0; gs < NS; ++gs)
+                        dval[sl][gs] = (ramask >> (gs * KL)) & 1u ? ra_d[ra_row[gs] + 64 * sl + 32 * tp + c32] : 0.f;
+            }
             // ---- forward products for the tiles (slice, tp) ----
             v16f acc[C];
 #pragma unroll
@@ -356,9 +379,18 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                     const int l = haar_level<K>(r);
                     const int gs = r / KL;
                     const float a = fabsf(v[r]);
-                    const bool keep = a > lo_t[gs][l];
-                    any_near |= keep && a < hi_t[gs][l];
-                    v[r] = keep ? v[r] * exp2i(-l) : 0.f;   // kept values scaled by 2^-l (inverse Haar)
+                    bool keep = a > lo_t[gs][l];
+                    bool near = keep && a < hi_t[gs][l];
+                    float vv = v[r];
+                    if constexpr (RA) {
+                        if (r % KL == 0 && ((ramask >> r) & 1u)) {
+                            keep = true;
+                            near = false;
+                            vv = v[r] - (float)K * dval[sl][gs];
+                        }
+                    }
+                    any_near |= near;
+                    v[r] = keep ? vv * exp2i(-l) : 0.f;   // kept values scaled by 2^-l (inverse Haar)
                 }
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[sl][r] = v[r];
@@ -378,7 +410,7 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                         const float a = fabsf(acc[sl][r]) * exp2i(l);
                         nb |= (uint32_t)(a > lo_t[gs][l] && a < hi_t[gs][l]) << r;
                     }
-                    nearbits[sl] = nb;
+                    nearbits[sl] = RA ? nb & ~ramask : nb;
                 }
                 if (lane == 0) sh.near_n[wave] = 0;
                 wave_lds_fence();
@@ -604,13 +636,15 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
 // Persistent over the tiles of one image: workgroup b takes tiles b, b + grid, ... in an
 // XCD-aware order (consecutive ids go round-robin over the 8 XCDs; with grid a multiple of 8
 // each workgroup stays in one class, whose tiles form a contiguous run).
-template <int C, int K>
+template <int C, int K, bool RA>
 __global__ __launch_bounds__(MW * 64) void filter_mfma_kernel(ImageGeom g, TileGeom tg, const v8h *__restrict__ F,
                                                              const double *__restrict__ T64,
                                                              const int32_t *__restrict__ idx,
                                                              const double *__restrict__ tau_ref,
                                                              float *__restrict__ regions,
-                                                             unsigned long long *__restrict__ guard_count) {
+                                                             unsigned long long *__restrict__ guard_count,
+                                                             const float *__restrict__ ra_d,
+                                                             const uint8_t *__restrict__ ra_flag) {
     extern __shared__ __align__(16) float smem[];
     __shared__ MfmaShared sh;
     v8h *FL0 = reinterpret_cast<v8h *>(smem);
@@ -626,7 +660,8 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_kernel(ImageGeom g, TileG
     for (int v = blockIdx.x; v < 8 * per; v += gridDim.x) {
         const int tile = (v & 7) * per + (v >> 3);
         if (tile >= n_tiles) continue;
-        filter_tile_mfma<C, K>(g, tg, FL0, F, T64, idx, K, tau_ref, 1.0, regions, guard_count, tile, region, xb, sh);
+        filter_tile_mfma<C, K, RA>(g, tg, FL0, F, T64, idx, K, tau_ref, 1.0, regions, guard_count, tile, region, xb,
+                                   sh, ra_d, ra_flag);
         __syncthreads();
     }
 }
@@ -692,12 +727,13 @@ int filter_mfma_group_bytes(int C) {
 
 int filter_mfma_static_bytes() { return (int)sizeof(MfmaShared) + 16; }
 
-template <int C, int K>
+template <int C, int K, bool RA>
 static hipError_t launch_mfma_t(const ImageGeom &g, const TileGeom &tg, const BasisDev &b, const int32_t *idx,
-                                const double *tau_ref, float *regions, unsigned long long *gc, hipStream_t st) {
+                                const double *tau_ref, float *regions, unsigned long long *gc, const float *ra_d,
+                                const uint8_t *ra_flag, hipStream_t st) {
     const int n_tiles = tg.tiles_y * tg.tiles_x;
     const int lds = filter_mfma_lds_bytes(tg, C);
-    hipError_t e = prepare_dynamic_lds((const void *)filter_mfma_kernel<C, K>, lds, (int)sizeof(MfmaShared));
+    hipError_t e = prepare_dynamic_lds((const void *)filter_mfma_kernel<C, K, RA>, lds, (int)sizeof(MfmaShared));
     if (e != hipSuccess) return e;
     int dev = 0, n_cu = 0;
     (void)hipGetDevice(&dev);
@@ -705,16 +741,19 @@ static hipError_t launch_mfma_t(const ImageGeom &g, const TileGeom &tg, const Ba
     if (n_cu < 8) n_cu = 8;
     const int per = (n_tiles + 7) / 8;
     const int grid = min(8 * per, (n_cu / 8) * 8);
-    hipLaunchKernelGGL((filter_mfma_kernel<C, K>), dim3(grid), dim3(MW * 64), lds, st, g, tg, (const v8h *)b.frag,
-                       b.T64, idx, tau_ref, regions, gc);
+    hipLaunchKernelGGL((filter_mfma_kernel<C, K, RA>), dim3(grid), dim3(MW * 64), lds, st, g, tg, (const v8h *)b.frag,
+                       b.T64, idx, tau_ref, regions, gc, ra_d, ra_flag);
     return hipGetLastError();
 }
 
 hipError_t launch_filter_mfma(const ImageGeom &g, const TileGeom &tg, int K, const BasisDev &b, const int32_t *idx,
-                              const double *tau_ref, float *regions, unsigned long long *gc, hipStream_t st) {
+                              const double *tau_ref, float *regions, unsigned long long *gc, hipStream_t st,
+                              const float *ra_d, const uint8_t *ra_flag) {
     if (!b.frag) return hipErrorInvalidValue;
-#define HM_CASE(CC, KK) \
-    if (g.c == CC && K == KK) return launch_mfma_t<CC, KK>(g, tg, b, idx, tau_ref, regions, gc, st);
+#define HM_CASE(CC, KK)                                                                                          \
+    if (g.c == CC && K == KK)                                                                                    \
+        return ra_d ? launch_mfma_t<CC, KK, true>(g, tg, b, idx, tau_ref, regions, gc, ra_d, ra_flag, st)         \
+                    : launch_mfma_t<CC, KK, false>(g, tg, b, idx, tau_ref, regions, gc, nullptr, nullptr, st);
     HM_CASE(1, 4) HM_CASE(1, 8) HM_CASE(1, 16) HM_CASE(1, 32)
     HM_CASE(3, 4) HM_CASE(3, 8) HM_CASE(3, 16) HM_CASE(3, 32)
 #undef HM_CASE

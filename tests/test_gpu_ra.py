@@ -1,0 +1,159 @@
+"""RA-Haar-tSVD (Sec. III-E-2, Eq. 24-25) on the GPU vs the FP64 oracle (needs an MI355X): mean
+patches bit-exact, the refinement network within the split-fp16 product error, its gradients,
+and the refined denoiser to the pixel parity bar."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import assert_pixel_parity
+from oracle import fcn
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dn():
+    import paper_2512_23569_amd as ht
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    d = ht.Denoiser(0, load_network=False)
+    yield d
+    d.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _weights(c, seed, scale=1.0):
+    p = fcn.init_params(c, seed)
+    rng = np.random.default_rng(seed + 100)
+    p = p * scale + rng.normal(0, 0.01, p.size) * (p != 0)   # small nonzero noise on the weights
+    # nonzero biases too
+    o = 0
+    for s in fcn.shapes(c):
+        n = int(np.prod(s))
+        if len(s) == 1:
+            p[o:o + n] = rng.normal(0, 0.05, n)
+        o += n
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("c,K", [(3, 32), (3, 8), (1, 16)])
+def test_mean_patches_exact(dn, c, K):
+    clean = synth.make_clean(72, 90, c, 51)
+    noisy = synth.add_awgn(clean, 40.0, 52)
+    idx, _ = dn.block_match(_dev(noisy), dn.params(c, stride=4, window=21, K=K))
+    torch.cuda.synchronize()
+    idx_h = idx.cpu().numpy()
+    for img in (noisy, clean):   # the clean image with the noisy image's groups (training pairs)
+        got = dn.ra_means(_dev(img), idx, K).cpu().numpy().astype(np.float64)
+        want = fcn.group_means(img, idx_h).reshape(len(idx_h), -1)
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("c", [3, 1])
+def test_network_forward_against_oracle(dn, c):
+    import paper_2512_23569_amd as ht
+    w = _weights(c, 7)
+    ht.htsvd_ra_set_weights(dn.ctx, c, w)
+    rng = np.random.default_rng(53)
+    means = rng.uniform(0, 255, (300, 64 * c)).astype(np.float32)   # 300: ten tiles and a ragged one
+    got = dn.ra_forward(_dev(means), c).cpu().numpy().astype(np.float64)
+    want = fcn.forward(w.astype(np.float64), means.astype(np.float64), c)
+    err = np.abs(got - want).max()
+    print("network max |dr| %.3g (max |r| %.3g)" % (err, np.abs(want).max()))
+    assert err <= 2e-5 * max(1.0, np.abs(want).max())
+    assert np.array_equal(ht.htsvd_ra_get_weights(dn.ctx, c), w)
+
+
+@pytest.mark.parametrize("c", [3, 1])
+def test_gradients_against_oracle(dn, c):
+    import paper_2512_23569_amd as ht
+    w = _weights(c, 8, scale=0.5)
+    ht.htsvd_ra_set_weights(dn.ctx, c, w)
+    rng = np.random.default_rng(54)
+    clean = rng.uniform(20, 235, (777, 64 * c))
+    noisy = (clean + rng.normal(0, 8, clean.shape)).astype(np.float32)
+    clean = clean.astype(np.float32)
+    g = torch.empty(fcn.param_count(c), dtype=torch.float32, device="cuda")
+    loss = ht.htsvd_ra_gradients(dn.ctx, c, _dev(noisy), _dev(clean), len(noisy), g)
+    lo, go = fcn.loss_and_grad(w.astype(np.float64), noisy.astype(np.float64), clean.astype(np.float64), c)
+    gg = g.cpu().numpy().astype(np.float64)
+    cos = gg @ go / (np.linalg.norm(gg) * np.linalg.norm(go))
+    rel = np.linalg.norm(gg - go) / np.linalg.norm(go)
+    print("loss %.6g vs %.6g, gradient cosine %.8f, relative error %.3g" % (loss, lo, cos, rel))
+    assert abs(loss - lo) <= 1e-5 * lo
+    assert cos >= 0.99999 and rel <= 1e-4
+
+
+def test_training_reduces_the_loss(dn):
+    import paper_2512_23569_amd as ht
+    c = 3
+    ht.htsvd_ra_set_weights(dn.ctx, c, fcn.init_params(c, 9).astype(np.float32))
+    rng = np.random.default_rng(55)
+    clean = rng.uniform(20, 235, (2048, 64 * c))
+    noisy = _dev((clean + rng.normal(0, 8, clean.shape)).astype(np.float32))
+    clean = _dev(clean.astype(np.float32))
+    first = ht.htsvd_ra_train_step(dn.ctx, c, noisy, clean, 2048, 1e-3)
+    for _ in range(60):
+        last = ht.htsvd_ra_train_step(dn.ctx, c, noisy, clean, 2048, 1e-3)
+    print("loss %.5f -> %.5f" % (first, last))
+    assert last < 0.5 * first
+
+
+@pytest.mark.parametrize("c,K,sigma", [(3, 16, 50.0), (1, 16, 45.0), (3, 32, 60.0)])
+def test_ra_denoise_parity(dn, c, K, sigma):
+    """GPU RA-Haar-tSVD against the oracle: oracle groups, oracle mean patches, the FP64
+    network and the FP64 filter with the refined first Haar row."""
+    import paper_2512_23569_amd as ht
+    w = _weights(c, 10 + K, scale=0.3)
+    ht.htsvd_ra_set_weights(dn.ctx, c, w)
+    h, wd = 96, 112
+    clean = synth.make_clean(h, wd, c, 56 + K)
+    noisy = synth.add_awgn(clean, sigma, 57 + K)
+    U, V = oracle.load_basis(os.path.join(ROOT, "paper_2512_23569_amd", "data", "basis_ps8_c%d.f64" % c), 8, c)
+    idx, _ = oracle.block_match(noisy, 8, 4, 21, K)
+    pest = fcn.refine(w.astype(np.float64), fcn.group_means(noisy, idx).reshape(len(idx), -1), c)
+    tau = sigma * oracle.tau_multiplier(c, K)
+    ref = oracle.denoise(noisy, U, V, tau, s=4, W=21, K=K, pest=pest)
+    p = dn.params(c, stride=4, window=21, K=K, ra=1)
+    gpu = dn.denoise(_dev(noisy), sigma, p).cpu().numpy()
+    m = assert_pixel_parity(gpu, ref, clean)
+    plain = oracle.denoise(noisy, U, V, tau, s=4, W=21, K=K)
+    print("RA c=%d K=%d sigma=%g" % (c, K, sigma), m, "mean |RA - plain| %.3f" % np.abs(ref - plain).mean())
+    assert np.abs(ref - plain).mean() > 0.1   # the refinement changes the result
+
+
+def test_ra_below_its_sigma_is_the_plain_filter(dn):
+    import paper_2512_23569_amd as ht
+    c = 3
+    ht.htsvd_ra_set_weights(dn.ctx, c, _weights(c, 11, scale=0.3))
+    noisy = synth.add_awgn(synth.make_clean(80, 64, c, 58), 20.0, 59)
+    d = _dev(noisy)
+    p = dn.params(c, stride=4, window=21, K=16)
+    a = dn.denoise(d, 20.0, p)
+    b = dn.denoise(d, 20.0, p.replace(ra=1, ra_sigma=30.0))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_ra_errors(dn):
+    import paper_2512_23569_amd as ht
+    d2 = ht.Denoiser(0, load_network=False)
+    try:
+        img = _dev(synth.make_clean(48, 48, 3, 60))
+        with pytest.raises(ht.HtsvdError):   # no network set
+            d2.denoise(img, 50.0, d2.params(3, stride=4, window=21, K=16, ra=1))
+        ht.htsvd_ra_set_weights(d2.ctx, 3, _weights(3, 12))
+        with pytest.raises(ht.HtsvdError):   # batched calls do not take it
+            d2.denoise_batch([img], [50.0], d2.params(3, stride=4, window=21, K=16, ra=1))
+        with pytest.raises(ht.HtsvdError):   # wrong parameter count
+            ht.htsvd_ra_set_weights(d2.ctx, 3, np.zeros(10, np.float32))
+    finally:
+        d2.close()
