@@ -128,6 +128,9 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="time a parameter sweep instead: sigma in {30..70} x K in {16, 32} with one grouping pass, "
                          "against one call per setting")
+    ap.add_argument("--ra", action="store_true",
+                    help="time RA-Haar-tSVD instead: the plain form with the refinement network of the first "
+                         "Haar row, against the plain form")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -169,6 +172,11 @@ def main():
     dn = ht.Denoiser(0)
     p_plain = dn.params(3, stride=s, window=W, K=32, adaptive=1, estimator=0)
     p_learn = p_plain.replace(estimator=1)
+
+    if args.ra:
+        bench_ra(dn, args, clean, noisy, d_in, d_out, p_plain, stream, s, W, sigma, gen_s)
+        dn.close()
+        return
 
     if args.sweep:
         bench_sweep(dn, args, clean, d_in, stream, s, W, sigma, gen_s)
@@ -317,6 +325,60 @@ def bench_batch(dn, args, autotune, stream):
         "unit": "Mpixel/s",
         "gen_s": round(gen_s, 1), "tune_s": round(tune_s, 1), "launch_candidates": allr,
     }
+
+
+def bench_ra(dn, args, clean, noisy, d_in, d_out, p_plain, stream, s, W, sigma, gen_s):
+    """RA-Haar-tSVD (Sec. III-E-2): the plain form (sigma estimated, vote) with the refinement
+    network applied to every group whose noise level exceeds 30, against the plain form.  The
+    roofline figure is the network kernel's, timed on the same number of mean patches through
+    htsvd_ra_forward (the in-denoiser launch also averages the groups)."""
+    import torch
+
+    import paper_2512_23569_amd as ht
+    import synth
+    h, w, c = d_in.shape
+    AUTO = ht.HTSVD_SIGMA_AUTO
+    p_ra = p_plain.replace(ra=1)
+    ms_plain = time_steps(lambda: dn.denoise(d_in, AUTO, p_plain, out=d_out), args.steps, args.warmup, stream)
+    psnr_plain = synth.psnr(clean, d_out.cpu().numpy())
+    ms_ra = time_steps(lambda: dn.denoise(d_in, AUTO, p_ra, out=d_out), args.steps, args.warmup, stream)
+    psnr_ra = synth.psnr(clean, d_out.cpu().numpy())
+    ny, nx = ht.htsvd_ref_count(h, 8, s), ht.htsvd_ref_count(w, 8, s)
+    n_ref = ny * nx
+    P, H = 64 * c, (256 if c == 3 else 128)
+    means = torch.rand((n_ref, P), device=d_in.device) * 255.0
+    r = torch.empty_like(means)
+    ms_net = time_steps(lambda: ht.htsvd_ra_forward(dn.ctx, c, means, n_ref, r), args.steps, args.warmup, stream)
+    macs = n_ref * (P * H + H * H + H * P)
+    alg_tf = 2 * macs / (ms_net * 1e-3) / 1e12
+    exe_tf = 3 * alg_tf   # three fp16 products per FP32 product (hi.hi, hi.lo, lo.hi)
+    log("RA: %.2f ms (plain %.2f ms), PSNR %.3f (plain %.3f), network %.3f ms for %d groups"
+        % (ms_ra, ms_plain, psnr_ra, psnr_plain, ms_net, n_ref))
+    result = {
+        "metric": "Mpixel/s denoised with RA-Haar-tSVD (refined first Haar row), 12MP RGB sigma=50",
+        "value": round(h * w / (ms_ra * 1e-3) / 1e6, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_ra, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "12MP RGB %dx%d, AWGN sigma=%g estimated (plain estimator + vote), RA network on groups "
+                               "with sigma > 30, ps 8, stride %d, window %d, K 32" % (w, h, sigma, s, W),
+                   "form": "plain + RA", "n_ref": n_ref},
+        "plain_ms": round(ms_plain, 3),
+        "roofline": {"bound": "mfma", "kernel": "fcn_fwd_kernel<3>", "achieved": round(exe_tf, 3),
+                     "peak": PEAK_F16_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": round(exe_tf / PEAK_F16_MFMA_TFLOPS, 4),
+                     "traffic": None, "kernel_ms": round(ms_net, 4), "algorithmic_fp32_tflops": round(alg_tf, 3),
+                     "macs_per_launch": macs},
+        "psnr": {"noisy": round(synth.psnr(clean, noisy), 3), "plain": round(psnr_plain, 3), "ra": round(psnr_ra, 3)},
+        "input_gen_s": round(gen_s, 1),
+    }
+    print(json.dumps(result), flush=True)
 
 
 def bench_sweep(dn, args, clean, d_in, stream, s, W, sigma, gen_s):
