@@ -2,14 +2,16 @@
 library's own kernels.
 
 Data: mean patches of noisy/clean groups (the pairs Sec. III-E-2 says overlapping groups supply
-in abundance).  Seeded clean synthetic images (half of them with the 1/f texture) get Gaussian
-noise of sigma U[30, 75] (the range where the enhancement applies, Sec. IV-B); the groups are
+in abundance).  Seeded clean synthetic images (half of them with the 1/f texture) and 512 x 512
+crops of large textured ones (1536 x 2048, whose shapes are as large as those of multi-megapixel
+images) get Gaussian noise of sigma U[30, 75] (the range where the enhancement applies, Sec.
+IV-B); the groups are
 matched on the noisy image (htsvd_block_match, K 16 and 32), and htsvd_ra_means averages them
 over the noisy and over the clean image.  Training minimises the mean of
 (r - (noisy - clean)/128)^2 with htsvd_ra_train_step (forward, backward and Adam in HIP);
 PyTorch only holds the device buffers.
 
-    python -m paper_2512_23569_amd.train_ra --c 3 --images 240 --epochs 8
+    python -m paper_2512_23569_amd.train_ra --c 3 --images 600 --big 120 --epochs 16
 """
 from __future__ import annotations
 
@@ -53,10 +55,23 @@ def _pair(args):
     return clean, noisy, sigma
 
 
-def make_images(first_seed, n, size, c, workers=8):
+def _pair_big(args):
+    seed, size, c = args
+    rng = np.random.default_rng(seed)
+    sigma = float(rng.uniform(30.0, 75.0))
+    full = synth.make_clean(1536, 2048, c, seed, texture=True)
+    y, x = int(rng.integers(0, 1536 - size + 1)), int(rng.integers(0, 2048 - size + 1))
+    clean = np.ascontiguousarray(full[y:y + size, x:x + size])
+    noisy = synth.add_awgn(clean, sigma, seed + 7)
+    return clean, noisy, sigma
+
+
+def make_images(first_seed, n, size, c, workers=8, big=False):
+    if n <= 0:
+        return []
     jobs = [(first_seed + i, size, c) for i in range(n)]
     with Pool(workers) as pool:
-        return pool.map(_pair, jobs, chunksize=4)
+        return pool.map(_pair_big if big else _pair, jobs, chunksize=1 if big else 4)
 
 
 def mean_pairs(ht, dn, images, c, Ks=(16, 32)):
@@ -101,6 +116,7 @@ def main(argv=None):
     ap.add_argument("--c", type=int, default=3)
     ap.add_argument("--images", type=int, default=240)
     ap.add_argument("--holdout", type=int, default=16)
+    ap.add_argument("--big", type=int, default=0, help="512 x 512 crops of large textured images added")
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--batch", type=int, default=4096)
@@ -115,7 +131,9 @@ def main(argv=None):
     out = args.out or os.path.join(ht.DATA_DIR, "ra_fcn_c%d.f32" % c)
     t0 = time.time()
     train_imgs = make_images(TRAIN_SEED0, args.images, args.size, c)
+    train_imgs += make_images(TRAIN_SEED0 + 5000, args.big, 512, c, big=True)
     hold_imgs = make_images(HOLDOUT_SEED0, args.holdout, args.size, c)
+    hold_big = make_images(HOLDOUT_SEED0 + 5000, 6, 512, c, big=True)
     print("images in %.1f s" % (time.time() - t0), flush=True)
     dn = ht.Denoiser(0, load_network=False)
     ht.htsvd_ra_set_weights(dn.ctx, c, init_params(c, args.seed))
@@ -145,9 +163,12 @@ def main(argv=None):
     w = ht.htsvd_ra_get_weights(dn.ctx, c)
     w.astype("<f4").tofile(out)
     gain = psnr_gain(ht, dn, hold_imgs, c)
-    log.update({"steps": steps, "holdout_psnr_ra": gain[0], "holdout_psnr_plain": gain[1],
+    gain_big = psnr_gain(ht, dn, hold_big, c)
+    log.update({"big": args.big, "steps": steps, "holdout_psnr_ra": gain[0], "holdout_psnr_plain": gain[1],
+                "holdout_big_psnr_ra": gain_big[0], "holdout_big_psnr_plain": gain_big[1],
                 "seconds": round(time.time() - t0, 1)})
     print("held-out PSNR with the refinement %.3f dB, without %.3f dB" % gain, flush=True)
+    print("held-out large-image crops: with the refinement %.3f dB, without %.3f dB" % gain_big, flush=True)
     with open(out + ".json", "w") as f:
         json.dump(log, f, indent=1)
     dn.close()
