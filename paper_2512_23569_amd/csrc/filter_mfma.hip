@@ -269,17 +269,22 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                 hi_t[gs][l] = guard ? tl + MGUARD * sc : lo_t[gs][l];
             }
         }
-        // RA-Haar-tSVD: registers holding the first Haar row (the group sum) of groups whose
-        // mean the network refines; their value becomes K (T p_est)(q) = sum - K ra_d(q), kept
-        // without threshold.
-        uint32_t ramask = 0;
+        // RA-Haar-tSVD: the forward products of every member of a refined group start from
+        // -ra_d(q) (in the accumulators' (s0', re', im') form) instead of 0.  The Haar rows past
+        // the first sum to zero over the group, so only the first row changes, to
+        // sum - K ra_d(q) = K (T p_est)(q); ramask marks the registers that hold it, which are
+        // kept without threshold.
+        uint32_t ramask = 0, raflag = 0;
         int64_t ra_row[NS];
         if constexpr (RA) {
 #pragma unroll
             for (int gs = 0; gs < NS; ++gs) {
                 const int gi = K == 32 ? 0 : (16 * h + gs * KL) / K;
                 ra_row[gs] = ref_of(gi) * P;
-                if (base + gi < nref && (K < 32 || h == 0) && ra_flag[ref_of(gi)]) ramask |= 1u << (gs * KL);
+                if (base + gi < nref && ra_flag[ref_of(gi)]) {
+                    raflag |= 1u << gs;
+                    if (K < 32 || h == 0) ramask |= 1u << (gs * KL);
+                }
             }
         }
 
@@ -295,18 +300,30 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
                 for (int i = 0; i < 2 * C; ++i) asm volatile("" : "+v"(raw[sp][i]));
-            float dval[C][NS];
-            if constexpr (RA) {
-#pragma unroll
-                for (int sl = 0; sl < C; ++sl)
-#pragma unroll
-                    for (int gs = 0; gs < NS; ++gs)
-                        dval[sl][gs] = (ramask >> (gs * KL)) & 1u ? ra_d[ra_row[gs] + 64 * sl + 32 * tp + c32] : 0.f;
-            }
             // ---- forward products for the tiles (slice, tp) ----
             v16f acc[C];
 #pragma unroll
             for (int sl = 0; sl < C; ++sl) acc[sl] = (v16f){};
+            if constexpr (RA) {
+#pragma unroll
+                for (int gs = 0; gs < NS; ++gs)
+                    if ((raflag >> gs) & 1u) {
+                        float d[C], a[C];
+#pragma unroll
+                        for (int sl = 0; sl < C; ++sl) d[sl] = ra_d[ra_row[gs] + 64 * sl + 32 * tp + c32];
+                        if (C == 3) {   // inverse of S0 = s0' + 2re', S1 = s0' - re' - im', S2 = s0' - re' + im'
+                            a[0] = -(d[0] + d[1] + d[2]) * (1.f / 3.f);
+                            a[1] = -(2.f * d[0] - d[1] - d[2]) * (1.f / 6.f);
+                            a[2] = -(d[2] - d[1]) * 0.5f;
+                        } else {
+                            a[0] = -d[0];
+                        }
+#pragma unroll
+                        for (int sl = 0; sl < C; ++sl)
+#pragma unroll
+                            for (int r = gs * KL; r < gs * KL + KL; ++r) acc[sl][r] = a[sl];
+                    }
+            }
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp) {
                 // bytes straight to float, the channel DFT in float, pairs packed to fp16 with
@@ -381,16 +398,14 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                     const float a = fabsf(v[r]);
                     bool keep = a > lo_t[gs][l];
                     bool near = keep && a < hi_t[gs][l];
-                    float vv = v[r];
                     if constexpr (RA) {
                         if (r % KL == 0 && ((ramask >> r) & 1u)) {
                             keep = true;
                             near = false;
-                            vv = v[r] - (float)K * dval[sl][gs];
                         }
                     }
                     any_near |= near;
-                    v[r] = keep ? vv * exp2i(-l) : 0.f;   // kept values scaled by 2^-l (inverse Haar)
+                    v[r] = keep ? v[r] * exp2i(-l) : 0.f;   // kept values scaled by 2^-l (inverse Haar)
                 }
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[sl][r] = v[r];
