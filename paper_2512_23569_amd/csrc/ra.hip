@@ -4,10 +4,13 @@
 // Network (residual learning on mean patches; P = 64c inputs and outputs, H hidden units):
 //   x = (p - 128) / 128,  h1 = relu(W1 x + b1),  h2 = relu(W2 h1 + b2),  r = W3 h2 + b3,
 //   p_est = p - 128 r.
-// Inference runs 32 groups per workgroup on the matrix cores: every layer is a 32 x (outputs)
-// product over the inputs in steps of v_mfma_f32_32x32x16_f16, with activations and weights
+// Inference runs 64 groups per workgroup on the matrix cores: every layer is a 64 x (outputs)
+// product over the inputs in steps of v_mfma_f32_32x32x16_f16 (each wave takes one 32-column
+// tile for both 32-row tiles, so a weight fragment read from L2 serves 64 rows, and the next
+// step's fragments are loaded while the current products run), with activations and weights
 // split into fp16 hi + lo and three products (hi.hi + hi.lo + lo.hi, about 22 bits), FP32
-// accumulation, bias and ReLU in FP32, activations kept in LDS between layers.  Inside the
+// accumulation, bias and ReLU in FP32.  Activations stay in LDS between layers, already split:
+// each layer's epilogue writes the hi and lo halves, so operands are read, not re-split.  Inside the
 // denoiser the last layer's weights are folded with the forward patch transform T (times 128),
 // so the kernel writes the change of the group's first Haar row directly:
 //   sqrt(K) T p_est = sqrt(K) T p - sqrt(K) * (128 T r).
@@ -21,78 +24,108 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int FR = 32;            // groups per workgroup
-constexpr int FWAVES = 4;
-constexpr int APITCH = 256 + 4;   // floats per activation row in LDS
+constexpr int FR = 64;            // groups per workgroup
+constexpr int FMT = FR / 32;      // 32-row tiles
+constexpr int FWAVES = 8;
+constexpr int FTHREADS = FWAVES * 64;
+constexpr int APITCH = 256 + 8;   // halves per activation row in LDS (16 bytes of padding)
+constexpr int ABUF = FR * APITCH;  // halves of one split activation array (hi, then lo)
 
-__device__ inline void split8(const float *v, v8h *hi, v8h *lo) {
-    v8h a, b;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const _Float16 hv = (_Float16)v[e];
-        a[e] = hv;
-        b[e] = (_Float16)(v[e] - (float)hv);
-    }
-    *hi = a;
-    *lo = b;
+// Stores v as fp16 hi + lo at row m, column n of a split activation buffer.
+__device__ inline void put_split(_Float16 *buf, int m, int n, float v) {
+    const _Float16 hv = (_Float16)v;
+    buf[m * APITCH + n] = hv;
+    buf[ABUF + m * APITCH + n] = (_Float16)(v - (float)hv);
 }
 
-// One layer for the 32 rows held in LDS: out(m, n) = act(sum_k in(m, k) W(n, k) + b(n)).
+// One layer for the FR rows held in LDS: out(m, n) = act(sum_k in(m, k) W(n, k) + b(n)).
 // Fragments: frag[((nt * KS + ks) * 2 + part) * 64 + lane], part 0 = hi, 1 = lo, holding
 // W(nt*32 + lane%32, ks*16 + 8*(lane/32) + e), e = 0..7.
 template <int KIN, int NOUT, bool RELU, bool TO_GLOBAL>
-__device__ inline void fcn_layer(const float *in, float *out_lds, float *out_g, int64_t out_row0, int nrows,
+__device__ inline void fcn_layer(const _Float16 *in, _Float16 *out_lds, float *out_g, int64_t out_row0, int nrows,
                                  const v8h *__restrict__ frag, const float *__restrict__ bias) {
     constexpr int KS = KIN / 16, NT = NOUT / 32;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 31, kh = 8 * (lane >> 5);
     for (int nt = wave; nt < NT; nt += FWAVES) {
-        v16f acc = (v16f){};
+        v16f acc[FMT];
+#pragma unroll
+        for (int mt = 0; mt < FMT; ++mt) acc[mt] = (v16f){};
+        const v8h *f = frag + (size_t)(nt * KS * 2) * 64;
+        v8h bhi = f[lane], blo = f[64 + lane];
         for (int ks = 0; ks < KS; ++ks) {
-            float a[8];
-            const float4 a0 = *reinterpret_cast<const float4 *>(in + m * APITCH + ks * 16 + kh);
-            const float4 a1 = *reinterpret_cast<const float4 *>(in + m * APITCH + ks * 16 + kh + 4);
-            a[0] = a0.x; a[1] = a0.y; a[2] = a0.z; a[3] = a0.w;
-            a[4] = a1.x; a[5] = a1.y; a[6] = a1.z; a[7] = a1.w;
-            v8h ahi, alo;
-            split8(a, &ahi, &alo);
-            const v8h *f = frag + (size_t)((nt * KS + ks) * 2) * 64;
-            const v8h bhi = f[lane], blo = f[64 + lane];
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, bhi, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, blo, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, bhi, acc, 0, 0, 0);
+            v8h nhi = bhi, nlo = blo;
+            if (ks + 1 < KS) {
+                nhi = f[(size_t)(ks + 1) * 128 + lane];
+                nlo = f[(size_t)(ks + 1) * 128 + 64 + lane];
+            }
+#pragma unroll
+            for (int mt = 0; mt < FMT; ++mt) {
+                const _Float16 *row = in + (mt * 32 + m) * APITCH + ks * 16 + kh;
+                const v8h ahi = *reinterpret_cast<const v8h *>(row);
+                const v8h alo = *reinterpret_cast<const v8h *>(row + ABUF);
+                acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, bhi, acc[mt], 0, 0, 0);
+                acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, blo, acc[mt], 0, 0, 0);
+                acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, bhi, acc[mt], 0, 0, 0);
+            }
+            bhi = nhi;
+            blo = nlo;
         }
         const int n = nt * 32 + m;
         const float bn = bias[n];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            float v = acc[r] + bn;
-            if (RELU) v = fmaxf(v, 0.f);
-            if (TO_GLOBAL) {
-                if (row < nrows) out_g[(out_row0 + row) * NOUT + n] = v;
-            } else {
-                out_lds[row * APITCH + n] = v;
+        for (int mt = 0; mt < FMT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = mt * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                float v = acc[mt][r] + bn;
+                if (RELU) v = fmaxf(v, 0.f);
+                if (TO_GLOBAL) {
+                    if (row < nrows) out_g[(out_row0 + row) * NOUT + n] = v;
+                } else {
+                    put_split(out_lds, row, n, v);
+                }
             }
-        }
     }
 }
 
 // Sums of the K members of group r, pixel row i of the patch, into s[c*8 + j] (integers).
 // Positions are clamped into the image (they come from the caller for the means entry point).
+// A member's row (8C bytes) is read as the 2C + 1 aligned dwords around it and realigned with
+// alignbyte; where those dwords would pass the end of the image it is read byte by byte.
 template <int C>
 __device__ inline void member_row_sums(const uint8_t *img, int64_t stride, int h, int w, const int32_t *grp, int K,
                                        int i, int *s) {
+    constexpr int NW = 2 * C;   // dwords of one row of a patch
 #pragma unroll
     for (int e = 0; e < 8 * C; ++e) s[e] = 0;
+    const uint8_t *img_end = img + (int64_t)(h - 1) * stride + (int64_t)w * C;
     for (int k = 0; k < K; ++k) {
         const int32_t lin = max(grp[k], 0);
         const int y = min(lin / w, h - 8), x = min(lin % w, w - 8);
         const uint8_t *p = img + (int64_t)(y + i) * stride + (int64_t)x * C;
+        const uintptr_t pa = reinterpret_cast<uintptr_t>(p);
+        const uint32_t *q = reinterpret_cast<const uint32_t *>(pa & ~(uintptr_t)3);
+        if (reinterpret_cast<const uint8_t *>(q + NW + 1) <= img_end) {
+            const uint32_t off = (uint32_t)(pa & 3);
+            uint32_t wv[NW + 1];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
+            for (int t = 0; t <= NW; ++t) wv[t] = q[t];
 #pragma unroll
-            for (int ch = 0; ch < C; ++ch) s[ch * 8 + j] += p[j * C + ch];
+            for (int t = 0; t < NW; ++t) {
+                const uint32_t d = __builtin_amdgcn_alignbyte(wv[t + 1], wv[t], off);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int e = 4 * t + b;   // byte e of the row: pixel e / C, channel e % C
+                    s[(e % C) * 8 + e / C] += (d >> (8 * b)) & 0xffu;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch) s[ch * 8 + j] += p[j * C + ch];
+        }
     }
 }
 
@@ -133,18 +166,18 @@ struct FcnArgs {
 };
 
 template <int C>
-__global__ __launch_bounds__(256) void fcn_fwd_kernel(FcnArgs a) {
+__global__ __launch_bounds__(FTHREADS) void fcn_fwd_kernel(FcnArgs a) {
     constexpr int P = 64 * C, H = C == 3 ? 256 : 128;
-    extern __shared__ __align__(16) float fcn_smem[];   // two activation buffers of FR x APITCH
-    float *bufA = fcn_smem, *bufB = fcn_smem + FR * APITCH;
+    extern __shared__ __align__(16) _Float16 fcn_smem[];   // two split activation buffers
+    _Float16 *bufA = fcn_smem, *bufB = fcn_smem + 2 * ABUF;
     const int64_t r0 = (int64_t)blockIdx.x * FR;
     const int nr = (int)min<int64_t>(FR, a.n - r0);
     const int tid = threadIdx.x;
     // ---- inputs x = (p - 128) / 128 into bufA (rows past the end are zero) ----
     if (a.means) {
-        for (int e = tid; e < FR * P; e += 256) {
+        for (int e = tid; e < FR * P; e += FTHREADS) {
             const int m = e / P, q = e % P;
-            bufA[m * APITCH + q] = m < nr ? (a.means[(r0 + m) * P + q] - 128.f) * (1.f / 128.f) : 0.f;
+            put_split(bufA, m, q, m < nr ? (a.means[(r0 + m) * P + q] - 128.f) * (1.f / 128.f) : 0.f);
         }
     } else {
         const int m = tid >> 3, i = tid & 7;
@@ -160,7 +193,8 @@ __global__ __launch_bounds__(256) void fcn_fwd_kernel(FcnArgs a) {
         for (int ch = 0; ch < C; ++ch)
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-                bufA[m * APITCH + ch * 64 + i * 8 + j] = m < nr ? ((float)s[ch * 8 + j] * inv - 128.f) * (1.f / 128.f) : 0.f;
+                put_split(bufA, m, ch * 64 + i * 8 + j,
+                          m < nr ? ((float)s[ch * 8 + j] * inv - 128.f) * (1.f / 128.f) : 0.f);
         if (a.flags && tid < nr) a.flags[r0 + tid] = a.tau[r0 + tid] * a.inv_mult > a.sigma_min ? 1 : 0;
     }
     __syncthreads();
@@ -342,14 +376,14 @@ hipError_t launch_ra_forward(int c, const RaWeightsDev &wd, bool folded, const f
     a.sigma_min = sigma_min;
     a.flags = flags;
     const unsigned g = nblocks(n, FR);
-    const int lds = (int)(sizeof(float) * 2 * FR * APITCH);
+    const int lds = (int)(sizeof(_Float16) * 4 * ABUF);
     const void *kfn = c == 3 ? (const void *)fcn_fwd_kernel<3> : (const void *)fcn_fwd_kernel<1>;
     hipError_t e = prepare_dynamic_lds(kfn, lds, 0);
     if (e != hipSuccess) return e;
     if (c == 3)
-        hipLaunchKernelGGL(fcn_fwd_kernel<3>, dim3(g), dim3(256), lds, st, a);
+        hipLaunchKernelGGL(fcn_fwd_kernel<3>, dim3(g), dim3(FTHREADS), lds, st, a);
     else
-        hipLaunchKernelGGL(fcn_fwd_kernel<1>, dim3(g), dim3(256), lds, st, a);
+        hipLaunchKernelGGL(fcn_fwd_kernel<1>, dim3(g), dim3(FTHREADS), lds, st, a);
     return hipGetLastError();
 }
 
