@@ -90,7 +90,9 @@ htsvd_status htsvd_default_params(int32_t c, htsvd_params *out);
  * bases, Eq. 11): host FP64 arrays of ps*ps*c values each, slice-major:
  * U[(k*ps + i)*ps + j] = U(i, j, k).  Both tensors must be orthogonal (U^T * U = I);
  * the library copies them (FP32 Fourier-domain slices for the transform, FP64 for the
- * threshold guard band).  Returns HTSVD_EINVAL if they are not orthogonal to 1e-9. */
+ * threshold guard band).  Returns HTSVD_EINVAL if they are not orthogonal to 1e-9.
+ * c = 2 or 4 .. 64 sets the basis of the hyperspectral path (htsvd_denoise_bands; one band
+ * count at a time). */
 htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double *h_U, const double *h_V);
 
 /* Channel Gram sums of all reference patches of one image (the sums behind the learned basis
@@ -143,6 +145,23 @@ htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32
 htsvd_status htsvd_denoise_tau(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
                                int64_t in_stride, const double *d_tau_ref, const htsvd_params *p, float *d_out,
                                int64_t out_stride, void *stream);
+
+/* ---- Hyperspectral tube patches (Sec. IV-D) ----
+ * A cube of `bands` uint8 bands per pixel (HWC, in_stride bytes per row) is grouped on a gray
+ * guide, the band mean rounded half up ((sum + bands/2) / bands), with the block matcher of the
+ * other paths (window, stride, K of p), and its 8 x 8 x bands tube patches are filtered with the
+ * t-product along the band axis (Eq. 19-21; basis from htsvd_set_basis or htsvd_learn_basis
+ * with c = bands) and tau = sigma * (p->tau_mult, or sqrt(2 ln(bands K ps^2))), then
+ * aggregated uniformly (Algorithm 1). */
+/* The guide image: d_guide[y*w + x] (uint8, h*w, device). */
+htsvd_status htsvd_band_guide(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t bands,
+                              int64_t in_stride, uint8_t *d_guide, void *stream);
+/* Denoises the cube with a known sigma into d_out (float32 HWC, out_stride elements per row).
+ * Errors: HTSVD_ESTATE (no basis for this band count), HTSVD_ENOTSUP (adaptive or ra set),
+ * HTSVD_EINVAL / HTSVD_ESHAPE as for htsvd_denoise. */
+htsvd_status htsvd_denoise_bands(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t bands,
+                                 int64_t in_stride, float sigma, const htsvd_params *p, float *d_out,
+                                 int64_t out_stride, void *stream);
 
 /* ---- RA-Haar-tSVD refinement network (Sec. III-E-2, Eq. 24-25) ----
  * The first Haar row of a group is sqrt(K) times its mean patch p (Eq. 24); a fully connected

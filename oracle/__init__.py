@@ -50,6 +50,7 @@ def _L():
                                              i32]
         lib.orc_denoise.argtypes = [p, i32, i32, i32, i64, i32, i32, i32, i32, i32, i32, p, p, p, p, dbl, p,
                                     i32, i64, i64, p, p]
+        lib.orc_filter_groups.argtypes = [p, i32, i32, i32, i64, i32, i32, i64, p, p, p, p, p, i32]
         _lib = lib
     return _lib
 
@@ -216,6 +217,30 @@ def denoise(img: np.ndarray, U: np.ndarray, V: np.ndarray, tau, ps: int = 8, s: 
                          None if pe is None else _ptr(pe), None if ro is None else _ptr(ro)))
     res = out[:, :, 0] if img.ndim == 2 else out
     return (res, int(near.value)) if return_near else res
+
+
+def filter_groups(img: np.ndarray, idx: np.ndarray, U: np.ndarray, V: np.ndarray, tau, ps: int = 8,
+                  nthreads: int = 0) -> np.ndarray:
+    """Eq. 19-21 and uniform aggregation of the given groups idx (n_ref, K) of y*w + x, any channel
+    count (hyperspectral tube patches, Sec. IV-D).  U, V: (ps, ps, c).  Returns FP64 (h, w, c)."""
+    a = img if img.ndim == 3 else img[:, :, None]
+    a = np.ascontiguousarray(a)
+    h, w, c = a.shape
+    ix = np.ascontiguousarray(idx, dtype=np.int32)
+    n_ref, K = ix.shape
+    tau_ref = np.ascontiguousarray(np.broadcast_to(np.asarray(tau, dtype=np.float64), (n_ref,)))
+    u, v = to_slices(U), to_slices(V)
+    out = np.zeros((h, w, c), dtype=np.float64)
+    _check(_L().orc_filter_groups(_ptr(a), h, w, c, w * c, ps, K, n_ref, _ptr(ix), _ptr(tau_ref), _ptr(u), _ptr(v),
+                                  _ptr(out), nthreads))
+    return out
+
+
+def band_guide(cube: np.ndarray) -> np.ndarray:
+    """Grouping image of a hyperspectral cube (h, w, bands): the band mean rounded half up,
+    (sum + bands // 2) // bands, exact in integers."""
+    b = cube.shape[2]
+    return ((cube.astype(np.int64).sum(axis=2) + b // 2) // b).astype(np.uint8)
 
 
 def n_refs(h: int, w: int, ps: int, s: int):

@@ -572,6 +572,105 @@ int orc_denoise(const uint8_t *img, int h, int w, int c, int64_t stride, int ps,
     return status;
 }
 
+/* Collaborative filtering (Eq. 19-21) and uniform aggregation (Algorithm 1) of given groups,
+ * for any channel count c (hyperspectral tube patches: c = bands, Sec. IV-D): group r has
+ * the K members idx[r*K + k] = y*w + x.  The transform is the bcirc t-product above; the
+ * threshold of group r is tau_ref[r].  out: h*w*c FP64 (pixels no patch covers keep their
+ * input value). */
+int orc_filter_groups(const uint8_t *img, int h, int w, int c, int64_t stride, int ps, int K, int64_t n_ref,
+                      const int32_t *idx, const double *tau_ref, const double *U, const double *V, double *out,
+                      int nthreads)
+{
+    if (c < 1 || ps < 1 || K < 1 || (K & (K - 1)) || h < ps || w < ps || stride < (int64_t)w * c) return ORC_EINVAL;
+    for (int64_t q = 0; q < n_ref * K; ++q) {
+        const int y = idx[q] / w, x = idx[q] % w;
+        if (idx[q] < 0 || y > h - ps || x > w - ps) return ORC_EINVAL;
+    }
+    const int P = ps * ps * c;
+    double *H = (double *)malloc(sizeof(double) * K * K);
+    orc_haar(K, H);
+    basis_t basis;
+    if (basis_init(&basis, U, V, ps, c)) return ORC_ENOMEM;
+    double *num = (double *)calloc((size_t)h * w * c, sizeof(double));
+    int64_t *cnt = (int64_t *)calloc((size_t)h * w, sizeof(int64_t));
+    int nt = 1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    nt = omp_get_max_threads();
+#endif
+    /* Each thread filters a contiguous run of groups into private sums, added in thread order. */
+    double **tnum = (double **)calloc(nt, sizeof(double *));
+    int64_t **tcnt = (int64_t **)calloc(nt, sizeof(int64_t *));
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        const int64_t rb = n_ref * tid / nt, re = n_ref * (tid + 1) / nt;
+        double *ln = (double *)calloc((size_t)h * w * c, sizeof(double));
+        int64_t *lc = (int64_t *)calloc((size_t)h * w, sizeof(int64_t));
+        tnum[tid] = ln;
+        tcnt[tid] = lc;
+        double *G = (double *)malloc(sizeof(double) * K * P);
+        double *S = (double *)malloc(sizeof(double) * K * P);
+        double *Sh = (double *)malloc(sizeof(double) * K * P);
+        double *work = (double *)malloc(sizeof(double) * (basis.N * basis.N + 2 * basis.N * ps));
+        for (int64_t r = rb; r < re; ++r) {
+            const int32_t *g = idx + r * K;
+            for (int k = 0; k < K; ++k)
+                for (int ch = 0; ch < c; ++ch)
+                    for (int i = 0; i < ps; ++i)
+                        for (int j = 0; j < ps; ++j)
+                            G[(size_t)k * P + (ch * ps + i) * ps + j] =
+                                img[(int64_t)(g[k] / w + i) * stride + (int64_t)(g[k] % w + j) * c + ch];
+            for (int k = 0; k < K; ++k) patch_forward(&basis, G + (size_t)k * P, S + (size_t)k * P, work);
+            for (int a = 0; a < K; ++a)
+                for (int q = 0; q < P; ++q) {
+                    double acc = 0.0;
+                    for (int k = 0; k < K; ++k) acc += H[a * K + k] * S[(size_t)k * P + q];
+                    Sh[(size_t)a * P + q] = acc;
+                }
+            for (int64_t q = 0; q < (int64_t)K * P; ++q)
+                if (!(fabs(Sh[q]) >= tau_ref[r])) Sh[q] = 0.0;
+            for (int k = 0; k < K; ++k)
+                for (int q = 0; q < P; ++q) {
+                    double acc = 0.0;
+                    for (int a = 0; a < K; ++a) acc += H[a * K + k] * Sh[(size_t)a * P + q];
+                    S[(size_t)k * P + q] = acc;
+                }
+            for (int k = 0; k < K; ++k) patch_inverse(&basis, S + (size_t)k * P, G + (size_t)k * P, work);
+            for (int k = 0; k < K; ++k)
+                for (int i = 0; i < ps; ++i)
+                    for (int j = 0; j < ps; ++j) {
+                        const int64_t pix = (int64_t)(g[k] / w + i) * w + (g[k] % w + j);
+                        for (int ch = 0; ch < c; ++ch) ln[pix * c + ch] += G[(size_t)k * P + (ch * ps + i) * ps + j];
+                        lc[pix] += 1;
+                    }
+        }
+        free(G); free(S); free(Sh); free(work);
+    }
+    for (int t = 0; t < nt; ++t) {
+        for (int64_t q = 0; q < (int64_t)h * w; ++q) {
+            cnt[q] += tcnt[t][q];
+            for (int ch = 0; ch < c; ++ch) num[q * c + ch] += tnum[t][q * c + ch];
+        }
+        free(tnum[t]);
+        free(tcnt[t]);
+    }
+    for (int64_t y = 0; y < h; ++y)
+        for (int64_t x = 0; x < w; ++x) {
+            const int64_t q = y * w + x;
+            for (int ch = 0; ch < c; ++ch)
+                out[q * c + ch] = cnt[q] > 0 ? num[q * c + ch] / (double)cnt[q] : (double)img[y * stride + x * c + ch];
+        }
+    free(tnum); free(tcnt); free(num); free(cnt); free(H);
+    basis_free(&basis);
+    return ORC_OK;
+}
+
 /* Number of reference positions along a side (for sizing outputs). */
 int orc_ref_count(int n, int ps, int s)
 {

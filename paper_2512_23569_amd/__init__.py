@@ -98,6 +98,8 @@ _SIGS = {
     "htsvd_cnn_train_step": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _vp, _f32, _vp, _vp]),
     "htsvd_cnn_save": (_i32, [_vp, ctypes.c_char_p]),
     "htsvd_cnn_load": (_i32, [_vp, ctypes.c_char_p]),
+    "htsvd_band_guide": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _vp, _vp]),
+    "htsvd_denoise_bands": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _i64, _vp]),
     "htsvd_ra_param_count": (_i32, [_i32]),
     "htsvd_ra_set_weights": (_i32, [_vp, _i32, _vp, _i64]),
     "htsvd_ra_get_weights": (_i32, [_vp, _i32, _vp, _i64]),
@@ -338,6 +340,19 @@ def htsvd_cnn_load(ctx, path: str):
     _check(lib().htsvd_cnn_load(ctx, path.encode()))
 
 
+def htsvd_band_guide(ctx, d_in, h, w, bands, in_stride, d_guide, stream=None):
+    import torch
+    _check(lib().htsvd_band_guide(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, bands, in_stride,
+                                  _dptr(d_guide, torch.uint8, "d_guide"), _stream(stream)))
+
+
+def htsvd_denoise_bands(ctx, d_in, h, w, bands, in_stride, sigma, params, d_out, out_stride, stream=None):
+    import torch
+    _check(lib().htsvd_denoise_bands(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, bands, in_stride, float(sigma),
+                                     ctypes.byref(params), _dptr(d_out, torch.float32, "d_out"), out_stride,
+                                     _stream(stream)))
+
+
 def htsvd_ra_param_count(c: int) -> int:
     return int(lib().htsvd_ra_param_count(c))
 
@@ -510,6 +525,26 @@ class Denoiser:
         import torch
         out = torch.empty_like(means)
         htsvd_ra_forward(self.ctx, c, means.contiguous(), means.shape[0], out, stream)
+        return out
+
+    def band_guide(self, cube, stream=None):
+        """Gray grouping guide (h, w) uint8 of a device cube (h, w, bands)."""
+        import torch
+        h, w, b = cube.shape
+        out = torch.empty((h, w), dtype=torch.uint8, device=cube.device)
+        htsvd_band_guide(self.ctx, cube, h, w, b, cube.stride(0), out, stream)
+        return out
+
+    def denoise_bands(self, cube, sigma, params, out=None, stream=None):
+        """Hyperspectral denoising of a device cube (h, w, bands) uint8 with a known sigma; the
+        basis for this band count comes from htsvd_set_basis or learn_basis."""
+        import torch
+        h, w, b = cube.shape
+        if cube.stride(2) != 1 or cube.stride(1) != b:
+            raise ValueError("bands of a pixel must be contiguous")
+        if out is None:
+            out = torch.empty(cube.shape, dtype=torch.float32, device=cube.device)
+        htsvd_denoise_bands(self.ctx, cube, h, w, b, cube.stride(0), sigma, params, out, out.stride(0), stream)
         return out
 
     def guard_count(self):

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhtsvd.so")
-SOURCES = ["api.hip", "bm.hip", "filter.hip", "filter_mfma.hip", "util.hip", "estimator.hip", "cnn.hip", "batch.hip", "basis_learn.hip", "ra.hip"]
+SOURCES = ["api.hip", "bm.hip", "filter.hip", "filter_mfma.hip", "util.hip", "estimator.hip", "cnn.hip", "batch.hip", "basis_learn.hip", "ra.hip", "bands.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

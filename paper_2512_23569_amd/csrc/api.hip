@@ -73,6 +73,8 @@ struct htsvd_ctx {
     std::vector<double> T64h[2];            // host copies of the FP64 patch transforms
     uint64_t basis_gen[2] = {0, 0};         // bumped by every basis install
     RaState ra[2];                          // RA-Haar-tSVD networks, [0]: c=1, [1]: c=3
+    int bands = 0;                          // band count of the hyperspectral basis (0: none)
+    double *d_band_maps = nullptr;          // its D, Dinv and slice maps (FP64)
     // Optional per-stage timing with HIP events recorded on the call's stream.
     bool timing = false;
     hipEvent_t ev[2 * HTSVD_N_STAGES] = {};
@@ -475,6 +477,80 @@ htsvd_status run_filter(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &
     return HTSVD_OK;
 }
 
+// Basis of the hyperspectral path (B bands): the band DFT, its inverse and the per-frequency
+// maps of the t-product (Eq. 4-5), checked for orthogonality slice by slice.
+htsvd_status set_basis_bands(htsvd_ctx *ctx, int B, const double *h_U, const double *h_V) {
+    typedef std::complex<double> cd;
+    const int NF = B / 2 + 1;
+    std::vector<cd> Uh((size_t)NF * 64), Vh((size_t)NF * 64);
+    for (int f = 0; f < NF; ++f)
+        for (int e = 0; e < 64; ++e) {
+            cd u = 0, v = 0;
+            for (int k = 0; k < B; ++k) {
+                const cd tw = std::polar(1.0, -2.0 * M_PI * (double)((f * k) % B) / B);
+                u += h_U[k * 64 + e] * tw;
+                v += h_V[k * 64 + e] * tw;
+            }
+            Uh[(size_t)f * 64 + e] = u;
+            Vh[(size_t)f * 64 + e] = v;
+        }
+    for (int f = 0; f < NF; ++f)
+        for (int i = 0; i < 8; ++i)
+            for (int j = 0; j < 8; ++j) {
+                cd su = 0, sv = 0;
+                for (int a = 0; a < 8; ++a) {
+                    su += std::conj(Uh[(size_t)f * 64 + a * 8 + i]) * Uh[(size_t)f * 64 + a * 8 + j];
+                    sv += std::conj(Vh[(size_t)f * 64 + a * 8 + i]) * Vh[(size_t)f * 64 + a * 8 + j];
+                }
+                const double t = i == j ? 1.0 : 0.0;
+                if (std::abs(su - t) > 1e-9 || std::abs(sv - t) > 1e-9)
+                    return fail(HTSVD_EINVAL, "basis tensors are not orthogonal");
+            }
+    std::vector<double> maps((size_t)2 * B * B + (size_t)NF * 2 * 4096, 0.0);
+    double *D = maps.data(), *Dinv = D + B * B, *M = Dinv + B * B;
+    for (int b = 0; b < B; ++b) {
+        D[0 * B + b] = 1.0;
+        Dinv[b * B + 0] = 1.0 / B;
+        for (int f = 1; f < NF; ++f) {
+            const double a = 2.0 * M_PI * (double)((f * b) % B) / B;
+            if (2 * f == B) {   // the real slice of an even band count
+                D[(B - 1) * B + b] = std::cos(a);
+                Dinv[b * B + B - 1] = std::cos(a) / B;
+            } else {
+                D[(2 * f - 1) * B + b] = std::cos(a);
+                D[(2 * f) * B + b] = -std::sin(a);
+                Dinv[b * B + 2 * f - 1] = 2.0 * std::cos(a) / B;
+                Dinv[b * B + 2 * f] = -2.0 * std::sin(a) / B;
+            }
+        }
+    }
+    for (int f = 0; f < NF; ++f)
+        for (int ip = 0; ip < 8; ++ip)
+            for (int jp = 0; jp < 8; ++jp)
+                for (int i = 0; i < 8; ++i)
+                    for (int j = 0; j < 8; ++j) {
+                        const cd m = std::conj(Uh[(size_t)f * 64 + i * 8 + ip]) * Vh[(size_t)f * 64 + j * 8 + jp];
+                        const size_t o = (size_t)f * 2 * 4096 + (size_t)(ip * 8 + jp) * 64 + (i * 8 + j);
+                        M[o] = m.real();
+                        M[o + 4096] = m.imag();
+                    }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronise before basis upload");
+    if (ctx->d_band_maps) (void)hipFree(ctx->d_band_maps);
+    ctx->d_band_maps = nullptr;
+    ctx->bands = 0;
+    if (hipMalloc(&ctx->d_band_maps, sizeof(double) * maps.size()) != hipSuccess) {
+        ctx->d_band_maps = nullptr;
+        (void)hipGetLastError();
+        return fail(HTSVD_ENOMEM, "basis allocation");
+    }
+    if ((e = hipMemcpy(ctx->d_band_maps, maps.data(), sizeof(double) * maps.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "basis upload");
+    ctx->bands = B;
+    return HTSVD_OK;
+}
+
 // Rebuilds the network's operand tables from the master weights when they changed (and the
 // folded last layer when the weights or the basis changed).  Host work; synchronises the device.
 htsvd_status ra_prepare(htsvd_ctx *ctx, int c, bool folded) {
@@ -656,6 +732,7 @@ void htsvd_destroy(htsvd_ctx *ctx) {
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->d_guard) (void)hipFree(ctx->d_guard);
     if (ctx->d_gram) (void)hipFree(ctx->d_gram);
+    if (ctx->d_band_maps) (void)hipFree(ctx->d_band_maps);
     for (int i = 0; i < 2; ++i) {
         RaState &r = ctx->ra[i];
         for (void *q : {(void *)r.w, (void *)r.m, (void *)r.v, (void *)r.grad, (void *)r.frag, (void *)r.frag3t,
@@ -702,7 +779,8 @@ htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double
     typedef std::complex<double> cd;
     if (!ctx || !h_U || !h_V) return fail(HTSVD_EINVAL, "null argument");
     if (ps != PS) return fail(HTSVD_ENOTSUP, "only ps = 8 is supported");
-    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    if (c == 2 || (c > 3 && c <= MAX_BANDS)) return set_basis_bands(ctx, c, h_U, h_V);
+    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3, or 2 .. 64 bands");
     // Fourier-domain slices (DFT along the channel mode, Eq. 5): X_hat^(f) = sum_k X^(k) w^(f k).
     const cd wv = std::polar(1.0, -2.0 * M_PI / c);
     cd twp[3], twm[3];   // w^m and w^-m
@@ -1855,6 +1933,60 @@ htsvd_status htsvd_ra_train_step(htsvd_ctx *ctx, int32_t c, const float *d_noisy
     hipError_t e = ra_adam(r.w, r.m, r.v, r.grad, r.n, lr, ++r.step, st);
     if (e != hipSuccess) return hip_fail(e, "adam");
     ++r.wgen;
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_band_guide(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t bands,
+                              int64_t in_stride, uint8_t *d_guide, void *stream) {
+    if (!ctx || !d_in || !d_guide) return fail(HTSVD_EINVAL, "null argument");
+    if (bands < 1 || bands > MAX_BANDS) return fail(HTSVD_EINVAL, "bands must be in [1, 64]");
+    if (h < 1 || w < 1) return fail(HTSVD_ESHAPE, "empty image");
+    if (in_stride < (int64_t)w * bands) return fail(HTSVD_EINVAL, "in_stride < w*bands");
+    hipError_t e = launch_band_guide(d_in, in_stride, h, w, bands, d_guide, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "band guide");
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_denoise_bands(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t bands,
+                                 int64_t in_stride, float sigma, const htsvd_params *p, float *d_out,
+                                 int64_t out_stride, void *stream) {
+    if (!ctx || !d_in || !d_out || !p) return fail(HTSVD_EINVAL, "null argument");
+    if (bands < 2 || bands > MAX_BANDS || bands == 3) return fail(HTSVD_EINVAL, "bands must be 2 or 4 .. 64");
+    if (ctx->bands != bands) return fail(HTSVD_ESTATE, "no basis set for this band count");
+    if (in_stride < (int64_t)w * bands) return fail(HTSVD_EINVAL, "in_stride < w*bands");
+    if (out_stride < (int64_t)w * bands) return fail(HTSVD_EINVAL, "out_stride < w*bands");
+    if (!(sigma > 0.f) || !std::isfinite(sigma)) return fail(HTSVD_EINVAL, "sigma must be > 0");
+    if (p->adaptive || p->ra) return fail(HTSVD_ENOTSUP, "the band path takes a known sigma, no vote or refinement");
+    // the grouping checks run on the guide's geometry (one channel)
+    ImageGeom g;
+    MethodParams mp;
+    htsvd_status s = validate(ctx, d_in, h, w, 1, w, p, &g, &mp, false);
+    if (s != HTSVD_OK) return s;
+    const int64_t n_ref = (int64_t)g.ny * g.nx;
+    const size_t off_idx = align256((size_t)h * w);
+    const size_t off_ws = off_idx + align256(sizeof(int32_t) * n_ref * mp.K);
+    if ((s = ensure_ws(ctx, off_ws + band_ws_bytes(h, w, bands, n_ref * mp.K))) != HTSVD_OK) return s;
+    uint8_t *guide = (uint8_t *)ctx->ws;
+    int32_t *idx = (int32_t *)((char *)ctx->ws + off_idx);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_band_guide(d_in, in_stride, h, w, bands, guide, st);
+    if (e != hipSuccess) return hip_fail(e, "band guide");
+    g.img = guide;
+    {
+        StageScope sc(ctx, HTSVD_STAGE_BM, st);
+        if ((e = launch_block_match(g, mp, idx, nullptr, st)) != hipSuccess) return hip_fail(e, "block matching");
+    }
+    const double mult = p->tau_mult > 0.0 ? p->tau_mult : std::sqrt(2.0 * std::log((double)bands * mp.K * PS * PS));
+    BandMaps bm;
+    bm.D = ctx->d_band_maps;
+    bm.Dinv = bm.D + bands * bands;
+    bm.M = bm.Dinv + bands * bands;
+    {
+        StageScope sc(ctx, HTSVD_STAGE_FILTER, st);
+        if ((e = launch_band_filter(bm, d_in, in_stride, h, w, bands, idx, n_ref, mp.K, (double)sigma * mult,
+                                    (char *)ctx->ws + off_ws, d_out, out_stride, st)) != hipSuccess)
+            return hip_fail(e, "band filter");
+    }
     return HTSVD_OK;
 }
 

@@ -9,6 +9,7 @@ namespace htsvd {
 
 constexpr int PS = 8;             // patch side (Sec. IV-A); the kernels are written for 8
 constexpr int MAX_WINDOW = 31;    // largest supported odd search-window side
+constexpr int MAX_BANDS = 64;     // largest band count of the hyperspectral path
 constexpr int MAX_CAND = MAX_WINDOW * MAX_WINDOW;
 constexpr int REF_TILE = 4;       // references per tile side in block matching (4 x 4 = 16 = MFMA M)
 constexpr int MAX_UNION = 64;     // largest union of search windows per tile side (candidates)
@@ -37,6 +38,13 @@ struct BasisDev {
     float *f32;        // 6*64 floats
     double *T64;       // P*P doubles
     const void *frag;  // MFMA operand fragments of the per-slice transform matrices (fp16 hi/lo)
+};
+
+// Maps of the t-product along B bands (bands.hip): the real band DFT D (B x B, rows Re0, Re1,
+// Im1, ..., and Re(B/2) last for even B), its inverse Dinv (B x B), and per frequency f <= B/2
+// the real and imaginary 64 x 64 parts of M_f((i',j'),(i,j)) = conj(U_hat_f(i,i')) V_hat_f(j,j').
+struct BandMaps {
+    const double *D = nullptr, *Dinv = nullptr, *M = nullptr;
 };
 
 // Device copy of the RA-Haar-tSVD refinement network for inference (ra.hip).
@@ -261,6 +269,13 @@ hipError_t launch_learned_judge(const ImageGeom &g, int tile, const float *zmap,
 hipError_t launch_fill_tau_learned(double *tau, const ImageGeom &g, int tile, const float *zmap,
                                    const int32_t *use_plain, const double *sigma_est, const double *sigma_hat,
                                    double mult, hipStream_t st);
+
+// Hyperspectral tube patches (bands.hip).
+hipError_t launch_band_guide(const uint8_t *cube, int64_t stride, int h, int w, int B, uint8_t *guide, hipStream_t st);
+size_t band_ws_bytes(int h, int w, int B, int64_t n_patch);
+hipError_t launch_band_filter(const BandMaps &bm, const uint8_t *cube, int64_t stride, int h, int w, int B,
+                              const int32_t *idx, int64_t n_group, int K, double tau, void *ws, float *out,
+                              int64_t out_stride, hipStream_t st);
 
 // RA-Haar-tSVD refinement network (ra.hip).
 int ra_hidden(int c);

@@ -20,14 +20,15 @@ Clean gray layer, painted in this order (float64, 0..255 scale):
   4. optionally a 1/f-spectrum Gaussian texture normalised to std 10.
 RGB images mix three independent gray layers with a random 3x3 matrix whose
 rows are 0.5*e_i + 0.5*Dirichlet(1,1,1) (each row sums to 1), then clip to
-[0,255] and round half-to-even.
+[0,255] and round half-to-even.  Hyperspectral cubes (make_hsi) use gray layers
+as abundances of a few smooth endmember spectra.
 """
 from __future__ import annotations
 
 import numpy as np
 
 __all__ = [
-    "gray_layer", "make_clean", "add_awgn", "add_poisson_gaussian",
+    "gray_layer", "make_clean", "make_hsi", "add_awgn", "add_poisson_gaussian",
     "smooth_sigma_field", "add_sigma_field_noise", "psnr", "make_cfg",
     "BATCH_SIZES", "batch_specs", "block_log_sigma", "sigma_crop",
 ]
@@ -118,6 +119,21 @@ def make_clean(h: int, w: int, c: int, seed: int, texture: bool = False) -> np.n
     mix = 0.5 * np.eye(3) + 0.5 * rng.dirichlet(np.ones(3), size=3)
     rgb = np.einsum("ij,jhw->hwi", mix, layers)
     return _quantise(rgb)
+
+
+def make_hsi(h: int, w: int, bands: int, seed: int, n_end: int = 4) -> np.ndarray:
+    """Clean uint8 hyperspectral cube (h, w, bands): n_end gray layers (as for make_clean) used
+    as abundances, normalised to sum to 1 per pixel, times n_end smooth endmember spectra
+    s_e(b) = 0.5 + 0.35 sin(2 pi (f_e b / bands + phi_e)) + 0.15 b / bands, f_e U[0.3, 1.5],
+    phi_e U[0, 1), scaled by 255, rounded half-to-even and clipped."""
+    rng = _rng(seed)
+    ab = np.stack([gray_layer(h, w, rng, texture=bool(e % 2)) for e in range(n_end)], axis=2)
+    ab = np.maximum(ab, 1.0)
+    ab /= ab.sum(axis=2, keepdims=True)
+    bb = np.arange(bands, dtype=np.float64) / bands
+    spec = np.stack([0.5 + 0.35 * np.sin(2 * np.pi * (rng.uniform(0.3, 1.5) * bb + rng.uniform())) + 0.15 * bb
+                     for _ in range(n_end)])
+    return _quantise(255.0 * np.einsum("hwe,eb->hwb", ab, spec))
 
 
 def add_awgn(clean: np.ndarray, sigma: float, seed: int) -> np.ndarray:

@@ -1,0 +1,75 @@
+"""Hyperspectral tube patches (Sec. IV-D) on the GPU vs the FP64 oracle (needs an MI355X): the
+grouping guide and the groups bit-exact, the band t-product filter to the pixel parity bar."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import assert_pixel_parity
+from oracle import learn_basis as lb
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dn():
+    import paper_2512_23569_amd as ht
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    d = ht.Denoiser(0, load_network=False)
+    yield d
+    d.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("bands", [2, 7, 31, 64])
+def test_guide_and_groups_exact(dn, bands):
+    cube = synth.add_awgn(synth.make_hsi(61, 70, bands, 80 + bands), 15.0, 81)
+    g = dn.band_guide(_dev(cube))
+    torch.cuda.synchronize()
+    want = oracle.band_guide(cube)
+    assert np.array_equal(g.cpu().numpy(), want)
+    idx, dist = dn.block_match(g, dn.params(1, stride=4, window=15, K=16))
+    oi, od = oracle.block_match(want, 8, 4, 15, 16)
+    assert np.array_equal(idx.cpu().numpy(), oi) and np.array_equal(dist.cpu().numpy(), od)
+
+
+@pytest.mark.parametrize("bands,K,sigma,s", [(31, 16, 20.0, 4), (8, 8, 30.0, 3), (5, 32, 15.0, 4), (2, 4, 25.0, 2)])
+def test_band_denoise_parity(dn, bands, K, sigma, s):
+    import paper_2512_23569_amd as ht
+    h, w = 56, 64
+    clean = synth.make_hsi(h, w, bands, 90 + bands)
+    noisy = synth.add_awgn(clean, sigma, 91 + bands)
+    U, V = lb.learn(noisy, 8, 4)
+    ht.htsvd_set_basis(dn.ctx, 8, bands, oracle.to_slices(U), oracle.to_slices(V))
+    W = 15
+    idx, _ = oracle.block_match(oracle.band_guide(noisy), 8, s, W, K)
+    tau = sigma * np.sqrt(2.0 * np.log(bands * K * 64))
+    ref = oracle.filter_groups(noisy, idx, U, V, tau)
+    p = dn.params(1, stride=s, window=W, K=K)
+    gpu = dn.denoise_bands(_dev(noisy), sigma, p).cpu().numpy()
+    m = assert_pixel_parity(gpu, ref, clean)
+    print("bands=%d K=%d sigma=%g" % (bands, K, sigma), m)
+    assert m["psnr_gpu"] > synth.psnr(clean, noisy) + 3.0
+
+
+def test_band_errors(dn):
+    import paper_2512_23569_amd as ht
+    d2 = ht.Denoiser(0, load_network=False)
+    try:
+        cube = _dev(synth.make_hsi(32, 32, 6, 95))
+        with pytest.raises(ht.HtsvdError):   # no basis for 6 bands
+            d2.denoise_bands(cube, 20.0, d2.params(1, stride=4, window=15, K=8))
+        U, V = lb.learn(synth.make_hsi(32, 32, 6, 96), 8, 4)
+        ht.htsvd_set_basis(d2.ctx, 8, 6, oracle.to_slices(U), oracle.to_slices(V))
+        with pytest.raises(ht.HtsvdError):   # sigma must be known
+            d2.denoise_bands(cube, -1.0, d2.params(1, stride=4, window=15, K=8))
+        bad = oracle.to_slices(U).copy()
+        bad[0, 0, 0] += 0.1
+        with pytest.raises(ht.HtsvdError):   # not orthogonal
+            ht.htsvd_set_basis(d2.ctx, 8, 6, bad, oracle.to_slices(V))
+    finally:
+        d2.close()

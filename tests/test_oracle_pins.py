@@ -297,6 +297,46 @@ def test_ra_with_infinite_threshold_aggregates_the_refined_means(c):
     assert np.allclose(out.reshape(h, w, c), want, rtol=0, atol=1e-9)
 
 
+# ---- hyperspectral tube patches: Sec. IV-D ---------------------------------------
+
+@pytest.mark.parametrize("c", [2, 7, 8])
+def test_tproduct_bcirc_equals_fft_route_for_band_counts(c):
+    """Eq. 2-5 for tube patches of c bands: the bcirc products equal the slice products of the
+    DFT along the bands."""
+    rng = np.random.default_rng(30 + c)
+    U = rng.normal(size=(8, 8, c))
+    V = rng.normal(size=(8, 8, c))
+    P = rng.normal(size=(8, 8, c))
+    S = oracle.patch_forward(U, V, P)
+    want = oracle.tprod_fft(oracle.tprod_fft(oracle.ttranspose(U), P), V)
+    assert np.allclose(S, want, atol=1e-10)
+
+
+def test_filter_groups_matches_denoise_and_reconstructs():
+    """With the groups of the denoiser, the groups filter is the denoiser (c = 3); with tau = 0
+    it reproduces a 7-band cube (the learned basis is orthogonal)."""
+    img = synth.add_awgn(synth.make_clean(40, 44, 3, 3), 30.0, 4)
+    U, V = oracle.load_basis(os.path.join(os.path.dirname(GOLD), "..", "paper_2512_23569_amd", "data",
+                                          "basis_ps8_c3.f64"), 8, 3)
+    idx, _ = oracle.block_match(img, 8, 4, 15, 8)
+    assert np.array_equal(oracle.denoise(img, U, V, 70.0, s=4, W=15, K=8), oracle.filter_groups(img, idx, U, V, 70.0))
+    from oracle import learn_basis as lb
+    cube = synth.make_hsi(40, 36, 7, 5)
+    U7, V7 = lb.learn(cube, 8, 4)
+    idx7, _ = oracle.block_match(oracle.band_guide(cube), 8, 4, 15, 8)
+    assert np.allclose(oracle.filter_groups(cube, idx7, U7, V7, 0.0), cube.astype(np.float64), atol=1e-9)
+
+
+def test_band_guide_rounds_half_up():
+    rng = np.random.default_rng(31)
+    cube = rng.integers(0, 256, (5, 6, 9)).astype(np.uint8)
+    g = oracle.band_guide(cube)
+    for y in range(5):
+        for x in range(6):
+            s = sum(int(v) for v in cube[y, x])
+            assert g[y, x] == int(np.floor(s / 9 + 0.5))
+
+
 # ---- grouping: Sec. III-A, Eq. 9 ---------------------------------------------
 
 def _brute_groups(img, ps, s, W, K, gnum=6, gden=5):
