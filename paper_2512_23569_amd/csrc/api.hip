@@ -70,6 +70,7 @@ struct htsvd_ctx {
     size_t ws_size = 0;
     unsigned long long *d_guard = nullptr;  // [0] re-decided in FP64, [1] past the per-group list
     int64_t *d_gram = nullptr;              // channel Gram sums of the basis learning pass
+    size_t d_gram_n = 0;                    // its capacity (int64 values)
     std::vector<double> T64h[2];            // host copies of the FP64 patch transforms
     uint64_t basis_gen[2] = {0, 0};         // bumped by every basis install
     RaState ra[2];                          // RA-Haar-tSVD networks, [0]: c=1, [1]: c=3
@@ -947,7 +948,7 @@ htsvd_status check_gram_args(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int
                              int64_t in_stride, int32_t ps, int32_t stride) {
     if (!ctx) return fail(HTSVD_EINVAL, "null context");
     if (!d_in) return fail(HTSVD_EINVAL, "null input image");
-    if (c != 1 && c != 3) return fail(HTSVD_EINVAL, "c must be 1 or 3");
+    if (c < 1 || c > MAX_BANDS) return fail(HTSVD_EINVAL, "c must be 1 .. 64");
     if (ps != PS) return fail(HTSVD_ENOTSUP, "only ps = 8 is supported");
     if (stride < 1) return fail(HTSVD_EINVAL, "stride must be >= 1");
     if (h < PS || w < PS) return fail(HTSVD_ESHAPE, "image smaller than one patch");
@@ -975,9 +976,20 @@ htsvd_status htsvd_learn_basis(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, i
     if (s != HTSVD_OK) return s;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    if (!ctx->d_gram && (e = hipMalloc(&ctx->d_gram, sizeof(int64_t) * 2 * 9 * 64)) != hipSuccess) {
+    const size_t gram_n = (size_t)2 * c * c * 64;
+    if (ctx->d_gram_n < gram_n) {
+        if (ctx->d_gram) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(ctx->d_gram);
+        }
         ctx->d_gram = nullptr;
-        return fail(HTSVD_ENOMEM, "Gram buffer allocation");
+        ctx->d_gram_n = 0;
+        if ((e = hipMalloc(&ctx->d_gram, sizeof(int64_t) * std::max<size_t>(gram_n, 2 * 9 * 64))) != hipSuccess) {
+            ctx->d_gram = nullptr;
+            (void)hipGetLastError();
+            return fail(HTSVD_ENOMEM, "Gram buffer allocation");
+        }
+        ctx->d_gram_n = std::max<size_t>(gram_n, 2 * 9 * 64);
     }
     hipStream_t st = (hipStream_t)stream;
     if ((e = launch_gram(d_in, in_stride, h, w, c, stride, ctx->d_gram, st)) != hipSuccess)

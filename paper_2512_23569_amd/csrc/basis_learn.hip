@@ -150,12 +150,83 @@ __global__ __launch_bounds__(GR_THREADS) void gram_kernel(const uint8_t *__restr
     }
 }
 
+// The same sums for a runtime channel count C (hyperspectral bands, up to 64): every thread owns
+// one entry pair (a <= b) of the A x A matrix, A = 8C, and runs over all vectors, which the
+// block stages 64 at a time in LDS as bytes with their weights.
+constexpr int GB_CHUNK = 64;
+
+__global__ __launch_bounds__(256) void gram_bands_kernel(const uint8_t *__restrict__ img, int64_t stride, int h,
+                                                         int w, int C, int s, int ny, int nx,
+                                                         unsigned long long *__restrict__ out) {
+    extern __shared__ uint8_t gb_smem[];
+    const int A = 8 * C;
+    uint8_t *sv = gb_smem;                                        // GB_CHUNK x A bytes
+    int *sm = reinterpret_cast<int *>(gb_smem + GB_CHUNK * A);    // GB_CHUNK weights
+    const int g = blockIdx.y;
+    const int64_t n_vec = g == 0 ? (int64_t)ny * w : (int64_t)nx * h;
+    const int64_t n_pairs = (int64_t)A * (A + 1) / 2;
+    const int64_t pair = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // pair -> (a, b), a <= b, row-major over the upper triangle
+    int a = 0, b = 0;
+    if (pair < n_pairs) {
+        int64_t rem = pair;
+        while (rem >= A - a) {
+            rem -= A - a;
+            ++a;
+        }
+        b = a + (int)rem;
+    }
+    unsigned long long tot = 0;
+    for (int64_t q0 = 0; q0 < n_vec; q0 += GB_CHUNK) {
+        const int nv = (int)min<int64_t>(GB_CHUNK, n_vec - q0);
+        for (int e = threadIdx.x; e < nv * A; e += 256) {
+            const int v = e / A, ai = e % A, ch = ai / 8, i = ai % 8;
+            const int64_t q = q0 + v;
+            uint8_t val;
+            if (g == 0) {
+                const int iy = (int)(q / w), col = (int)(q % w);
+                val = img[(int64_t)(ref_pos(iy, ny, h, s) + i) * stride + (int64_t)col * C + ch];
+            } else {
+                const int row = (int)(q / nx), ix = (int)(q % nx);
+                val = img[(int64_t)row * stride + (int64_t)(ref_pos(ix, nx, w, s) + i) * C + ch];
+            }
+            sv[v * A + ai] = val;
+        }
+        for (int v = threadIdx.x; v < nv; v += 256) {
+            const int64_t q = q0 + v;
+            sm[v] = g == 0 ? cover_count((int)(q % w), w, nx, s) : cover_count((int)(q / nx), h, ny, s);
+        }
+        __syncthreads();
+        if (pair < n_pairs) {
+            uint32_t acc = 0;   // <= 64 vectors of weight <= 9: below 2^32
+            for (int v = 0; v < nv; ++v) acc += (uint32_t)sm[v] * sv[v * A + a] * sv[v * A + b];
+            tot += acc;
+        }
+        __syncthreads();
+    }
+    if (pair < n_pairs) {
+        unsigned long long *og = out + (size_t)g * C * C * 64;
+        og[((a / 8) * C + b / 8) * 64 + (a % 8) * 8 + b % 8] = tot;
+        og[((b / 8) * C + a / 8) * 64 + (b % 8) * 8 + a % 8] = tot;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_gram(const uint8_t *img, int64_t stride, int h, int w, int c, int s, int64_t *out, hipStream_t st) {
+    const int ny = ref_count(h, s), nx = ref_count(w, s);
+    if (c != 1 && c != 3) {
+        const int A = 8 * c;
+        const int64_t n_pairs = (int64_t)A * (A + 1) / 2;
+        const int lds = GB_CHUNK * A + GB_CHUNK * 4;
+        hipError_t e = prepare_dynamic_lds((const void *)gram_bands_kernel, lds, 0);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(gram_bands_kernel, dim3((unsigned)((n_pairs + 255) / 256), 2), dim3(256), lds, st, img,
+                           stride, h, w, c, s, ny, nx, reinterpret_cast<unsigned long long *>(out));
+        return hipGetLastError();
+    }
     hipError_t e = launch_zero(out, sizeof(int64_t) * 2 * c * c * 64, st);
     if (e != hipSuccess) return e;
-    const int ny = ref_count(h, s), nx = ref_count(w, s);
     const int64_t n_vec = std::max<int64_t>((int64_t)ny * w, (int64_t)nx * h);
     const int nb = (int)std::min<int64_t>(GR_MAX_BLOCKS, (n_vec + GR_CHUNK - 1) / GR_CHUNK);
     unsigned long long *o = reinterpret_cast<unsigned long long *>(out);

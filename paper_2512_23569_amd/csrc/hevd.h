@@ -5,9 +5,11 @@
 #pragma once
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdint>
+#include <vector>
 
 namespace htsvd {
 
@@ -94,7 +96,8 @@ inline void hermitian_evd(int n, const cplx *A_in, double *ev, cplx *Q) {
 // Basis pair (U, V) of one image from its channel Gram sums over all reference patches P:
 //   gram[0][a][b][i][k] = sum_P sum_j P(i, j, a) P(k, j, b)   (rows of the patches)
 //   gram[1][a][b][i][k] = sum_P sum_j P(j, i, a) P(j, k, b)   (columns of the patches)
-// for channels a, b < c, ps = 8.  Slice f of the channel DFT (Eq. 5, w = exp(-2 pi i / c)) has
+// for channels a, b < c (any count: colour channels or hyperspectral bands), ps = 8.  Slice f of
+// the channel DFT (Eq. 5, w = exp(-2 pi i / c)) has
 // C_row^(f) = sum_P P_hat P_hat^H = sum_ab w^(f(a-b)) gram[0][a][b] and
 // C_col^(f) = sum_P P_hat^H P_hat = sum_ab w^(f(b-a)) gram[1][a][b]; U_hat^(f) and V_hat^(f)
 // hold their eigenvectors by descending eigenvalue.  Slice c-f is the conjugate of slice f, so
@@ -102,7 +105,7 @@ inline void hermitian_evd(int n, const cplx *A_in, double *ev, cplx *Q) {
 inline void basis_from_gram(int c, const int64_t *gram, double *U, double *V, double *ev_row, double *ev_col) {
     const int n = 8;
     const double two_pi = 2.0 * M_PI;
-    cplx Uh[3][64], Vh[3][64];
+    std::vector<std::array<cplx, 64>> Uh(c), Vh(c);
     for (int f = 0; f <= c / 2; ++f) {
         for (int g = 0; g < 2; ++g) {
             cplx C[64];
@@ -118,7 +121,7 @@ inline void basis_from_gram(int c, const int64_t *gram, double *U, double *V, do
             cplx Q[64];
             double ev[8];
             hermitian_evd(n, C, ev, Q);
-            cplx *dst = g == 0 ? Uh[f] : Vh[f];
+            cplx *dst = g == 0 ? Uh[f].data() : Vh[f].data();
             for (int e = 0; e < 64; ++e) dst[e] = Q[e];
             double *evo = g == 0 ? ev_row : ev_col;
             if (evo)

@@ -73,3 +73,30 @@ def test_band_errors(dn):
             ht.htsvd_set_basis(d2.ctx, 8, 6, bad, oracle.to_slices(V))
     finally:
         d2.close()
+
+
+@pytest.mark.parametrize("bands,s", [(7, 4), (31, 3), (2, 5)])
+def test_band_gram_sums_exact(dn, bands, s):
+    cube = synth.add_awgn(synth.make_hsi(45, 52, bands, 100 + bands), 20.0, 101)
+    G = dn.basis_gram(_dev(cube), stride=s)
+    torch.cuda.synchronize()
+    assert np.array_equal(G.cpu().numpy(), lb.channel_gram(cube, 8, s))
+
+
+@pytest.mark.parametrize("bands", [5, 8, 31])
+def test_band_learned_basis_and_denoise(dn, bands):
+    """The basis learned on the GPU from the noisy cube (Sec. III-B with c = bands) matches the
+    oracle's, and denoising with it matches oracle learning plus the oracle filter."""
+    clean = synth.make_hsi(64, 56, bands, 110 + bands)
+    noisy = synth.add_awgn(clean, 25.0, 111 + bands)
+    d = _dev(noisy)
+    Ug, Vg = dn.learn_basis(d, stride=4)
+    Uo, Vo = lb.learn(noisy, 8, 4)
+    du = np.abs(Ug - oracle.to_slices(Uo)).max()
+    dv = np.abs(Vg - oracle.to_slices(Vo)).max()
+    print("bands=%d max |dU| %.3g |dV| %.3g" % (bands, du, dv))
+    assert du <= 1e-8 and dv <= 1e-8
+    idx, _ = oracle.block_match(oracle.band_guide(noisy), 8, 4, 15, 16)
+    ref = oracle.filter_groups(noisy, idx, Uo, Vo, 25.0 * np.sqrt(2.0 * np.log(bands * 16 * 64)))
+    gpu = dn.denoise_bands(d, 25.0, dn.params(1, stride=4, window=15, K=16)).cpu().numpy()
+    assert_pixel_parity(gpu, ref, clean)
