@@ -6,7 +6,8 @@
 // device, so that keep/kill decisions agree with an FP64 reference without a guard band), and
 // the t-product S = U^T * P * V
 // (Eq. 19) is taken along the band axis through its DFT (Eq. 4-5), as three dense products:
-//   band DFT      Xd = X D^T                 (rows n*64 + e, B Fourier reals: Re0, Re1, Im1, ...)
+//   band DFT      Xd = X D^T                 (B Fourier reals Re0, Re1, Im1, ..., each stored as
+//                                             one contiguous block over the rows n*64 + e)
 //   slice maps    per frequency f, vec(S_hat_f) = M_f vec(P_hat_f), M_f((i',j'),(i,j)) =
 //                 conj(U_hat_f(i,i')) V_hat_f(j,j') (64 x 64, real for f = 0 and f = B/2)
 //   inverse DFT   S = Sd Dinv^T              (the real slices S^(k), where the threshold acts)
@@ -175,12 +176,14 @@ hipError_t gemm(const double *A, int64_t sam, int64_t sak, const double *Bm, int
 
 // One direction of the t-product on the patch matrix (rows n*64 + e, B columns):
 //   X -> Xd = X D^T -> per frequency the slice maps into Sd -> Y = Sd Dinv^T.
-// Forward uses M_f, inverse M_f^H (M is stored as real and imaginary 64 x 64 parts per slice).
+// Xd and Sd hold one contiguous block of rows per Fourier component, so the slice maps read and
+// write whole rows.  Forward uses M_f, inverse M_f^H (M stored as real and imaginary 64 x 64
+// parts per slice).
 hipError_t tproduct(const BandMaps &bm, int B, int64_t n_patch, const double *X, double *Xd, double *Sd, double *Y,
                     bool inverse, hipStream_t st) {
     const int64_t rows = n_patch * 64;
     hipError_t e;
-    if ((e = gemm(X, B, 1, bm.D, 1, B, Xd, B, 1, rows, B, B, 1.0, false, st)) != hipSuccess) return e;
+    if ((e = gemm(X, B, 1, bm.D, 1, B, Xd, 1, rows, rows, B, B, 1.0, false, st)) != hipSuccess) return e;
     const int NF = B / 2 + 1;
     for (int f = 0; f < NF; ++f) {
         const double *Mr = bm.M + (size_t)f * 2 * 4096, *Mi = Mr + 4096;
@@ -188,27 +191,21 @@ hipError_t tproduct(const BandMaps &bm, int B, int64_t n_patch, const double *X,
         const int cr = f == 0 ? 0 : 2 * f - 1, ci = 2 * f;   // columns of Re, Im of frequency f
         // C(n, e') = sum_e A(n, e) M(e', e)  [forward]   or   M(e, e')  [inverse, M^T; M^H flips Mi's sign]
         const int64_t sbk = inverse ? 64 : 1, sbn = inverse ? 1 : 64;
-        const double *ar = Xd + cr, *ai = Xd + ci;
-        double *cre = Sd + cr, *cim = Sd + ci;
+        const double *ar = Xd + cr * rows, *ai = Xd + ci * rows;
+        double *cre = Sd + cr * rows, *cim = Sd + ci * rows;
         if (real) {
-            if ((e = gemm(ar, (int64_t)64 * B, B, Mr, sbk, sbn, cre, (int64_t)64 * B, B, n_patch, 64, 64, 1.0, false,
-                          st)) != hipSuccess)
-                return e;
+            if ((e = gemm(ar, 64, 1, Mr, sbk, sbn, cre, 64, 1, n_patch, 64, 64, 1.0, false, st)) != hipSuccess) return e;
             continue;
         }
         const double si = inverse ? -1.0 : 1.0;   // Im of M or of M^H
         // Re out = Mr Re - (si Mi) Im;  Im out = (si Mi) Re + Mr Im
-        if ((e = gemm(ar, (int64_t)64 * B, B, Mr, sbk, sbn, cre, (int64_t)64 * B, B, n_patch, 64, 64, 1.0, false, st)) !=
-                hipSuccess ||
-            (e = gemm(ai, (int64_t)64 * B, B, Mi, sbk, sbn, cre, (int64_t)64 * B, B, n_patch, 64, 64, -si, true, st)) !=
-                hipSuccess ||
-            (e = gemm(ar, (int64_t)64 * B, B, Mi, sbk, sbn, cim, (int64_t)64 * B, B, n_patch, 64, 64, si, false, st)) !=
-                hipSuccess ||
-            (e = gemm(ai, (int64_t)64 * B, B, Mr, sbk, sbn, cim, (int64_t)64 * B, B, n_patch, 64, 64, 1.0, true, st)) !=
-                hipSuccess)
+        if ((e = gemm(ar, 64, 1, Mr, sbk, sbn, cre, 64, 1, n_patch, 64, 64, 1.0, false, st)) != hipSuccess ||
+            (e = gemm(ai, 64, 1, Mi, sbk, sbn, cre, 64, 1, n_patch, 64, 64, -si, true, st)) != hipSuccess ||
+            (e = gemm(ar, 64, 1, Mi, sbk, sbn, cim, 64, 1, n_patch, 64, 64, si, false, st)) != hipSuccess ||
+            (e = gemm(ai, 64, 1, Mr, sbk, sbn, cim, 64, 1, n_patch, 64, 64, 1.0, true, st)) != hipSuccess)
             return e;
     }
-    return gemm(Sd, B, 1, bm.Dinv, 1, B, Y, B, 1, rows, B, B, 1.0, false, st);
+    return gemm(Sd, 1, rows, bm.Dinv, 1, B, Y, B, 1, rows, B, B, 1.0, false, st);
 }
 
 }  // namespace

@@ -151,8 +151,9 @@ __global__ __launch_bounds__(GR_THREADS) void gram_kernel(const uint8_t *__restr
 }
 
 // The same sums for a runtime channel count C (hyperspectral bands, up to 64): every thread owns
-// one entry pair (a <= b) of the A x A matrix, A = 8C, and runs over all vectors, which the
-// block stages 64 at a time in LDS as bytes with their weights.
+// one entry pair (a <= b) of the A x A matrix, A = 8C, over one of gridDim.z slices of the
+// vectors, which the block stages 64 at a time in LDS as bytes with their weights; the slices
+// are added with 64-bit integer atomics (exact, so in any order).
 constexpr int GB_CHUNK = 64;
 
 __global__ __launch_bounds__(256) void gram_bands_kernel(const uint8_t *__restrict__ img, int64_t stride, int h,
@@ -177,7 +178,9 @@ __global__ __launch_bounds__(256) void gram_bands_kernel(const uint8_t *__restri
         b = a + (int)rem;
     }
     unsigned long long tot = 0;
-    for (int64_t q0 = 0; q0 < n_vec; q0 += GB_CHUNK) {
+    const int64_t n_chunks = (n_vec + GB_CHUNK - 1) / GB_CHUNK;
+    const int64_t c_begin = n_chunks * blockIdx.z / gridDim.z, c_end = n_chunks * (blockIdx.z + 1) / gridDim.z;
+    for (int64_t q0 = c_begin * GB_CHUNK; q0 < c_end * GB_CHUNK; q0 += GB_CHUNK) {
         const int nv = (int)min<int64_t>(GB_CHUNK, n_vec - q0);
         for (int e = threadIdx.x; e < nv * A; e += 256) {
             const int v = e / A, ai = e % A, ch = ai / 8, i = ai % 8;
@@ -204,10 +207,10 @@ __global__ __launch_bounds__(256) void gram_bands_kernel(const uint8_t *__restri
         }
         __syncthreads();
     }
-    if (pair < n_pairs) {
+    if (pair < n_pairs && tot) {
         unsigned long long *og = out + (size_t)g * C * C * 64;
-        og[((a / 8) * C + b / 8) * 64 + (a % 8) * 8 + b % 8] = tot;
-        og[((b / 8) * C + a / 8) * 64 + (b % 8) * 8 + a % 8] = tot;
+        atomicAdd(og + ((a / 8) * C + b / 8) * 64 + (a % 8) * 8 + b % 8, tot);
+        if (a != b) atomicAdd(og + ((b / 8) * C + a / 8) * 64 + (b % 8) * 8 + a % 8, tot);
     }
 }
 
@@ -215,18 +218,22 @@ __global__ __launch_bounds__(256) void gram_bands_kernel(const uint8_t *__restri
 
 hipError_t launch_gram(const uint8_t *img, int64_t stride, int h, int w, int c, int s, int64_t *out, hipStream_t st) {
     const int ny = ref_count(h, s), nx = ref_count(w, s);
+    hipError_t e = launch_zero(out, sizeof(int64_t) * 2 * c * c * 64, st);
+    if (e != hipSuccess) return e;
     if (c != 1 && c != 3) {
         const int A = 8 * c;
         const int64_t n_pairs = (int64_t)A * (A + 1) / 2;
         const int lds = GB_CHUNK * A + GB_CHUNK * 4;
-        hipError_t e = prepare_dynamic_lds((const void *)gram_bands_kernel, lds, 0);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(gram_bands_kernel, dim3((unsigned)((n_pairs + 255) / 256), 2), dim3(256), lds, st, img,
+        if ((e = prepare_dynamic_lds((const void *)gram_bands_kernel, lds, 0)) != hipSuccess) return e;
+        // enough vector slices for about 2048 workgroups, each with at least 16 chunks
+        const int64_t n_vec = std::max<int64_t>((int64_t)ny * w, (int64_t)nx * h);
+        const int64_t pair_blocks = (n_pairs + 255) / 256;
+        const int64_t zs = std::max<int64_t>(1, std::min<int64_t>((2048 + 2 * pair_blocks - 1) / (2 * pair_blocks),
+                                                                   (n_vec + 16 * GB_CHUNK - 1) / (16 * GB_CHUNK)));
+        hipLaunchKernelGGL(gram_bands_kernel, dim3((unsigned)pair_blocks, 2, (unsigned)zs), dim3(256), lds, st, img,
                            stride, h, w, c, s, ny, nx, reinterpret_cast<unsigned long long *>(out));
         return hipGetLastError();
     }
-    hipError_t e = launch_zero(out, sizeof(int64_t) * 2 * c * c * 64, st);
-    if (e != hipSuccess) return e;
     const int64_t n_vec = std::max<int64_t>((int64_t)ny * w, (int64_t)nx * h);
     const int nb = (int)std::min<int64_t>(GR_MAX_BLOCKS, (n_vec + GR_CHUNK - 1) / GR_CHUNK);
     unsigned long long *o = reinterpret_cast<unsigned long long *>(out);
