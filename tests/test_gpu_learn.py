@@ -143,4 +143,4 @@ def test_learning_errors_are_reported(dn):
     with pytest.raises(ht.HtsvdError):
         ht.htsvd_learn_basis(dn.ctx, img, 7, 32, 3, 96, 8, 4)            # smaller than a patch
     with pytest.raises(ht.HtsvdError):
-        ht.htsvd_learn_basis(dn.ctx, img, 32, 32, 2, 96, 8, 4)           # c = 2
+        ht.htsvd_learn_basis(dn.ctx, img, 32, 32, 65, 96, 8, 4)          # 65 channels (2 .. 64 are bands)
