@@ -148,8 +148,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(whole images or row strips would shard across GPUs; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(whole images or row strips would shard across GPUs).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

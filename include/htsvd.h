@@ -44,7 +44,7 @@ typedef enum {
     HTSVD_ESHAPE = -2,  /* image too small, too few candidates for K, stride too small */
     HTSVD_ENOMEM = -3,  /* device allocation failed */
     HTSVD_EDEVICE = -4, /* HIP runtime error (including deferred kernel faults) */
-    HTSVD_ENOTSUP = -5, /* parameter combination this build does not support */
+    HTSVD_ENOTSUP = -5, /* parameter combination the library does not support */
     HTSVD_ESTATE = -6   /* missing basis or network weights */
 } htsvd_status;
 
