@@ -156,6 +156,10 @@ htsvd_status htsvd_denoise_tau(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, i
 /* The guide image: d_guide[y*w + x] (uint8, h*w, device). */
 htsvd_status htsvd_band_guide(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t bands,
                               int64_t in_stride, uint8_t *d_guide, void *stream);
+/* Memory of htsvd_denoise_bands: its groups are filtered in passes whose three FP64 patch
+ * matrices (K*64*bands doubles per group each) stay below `bytes` each (default 4 GiB, at least
+ * 1 MiB, at least one group per pass).  The output does not depend on it. */
+htsvd_status htsvd_set_band_memory(htsvd_ctx *ctx, int64_t bytes);
 /* Denoises the cube with a known sigma into d_out (float32 HWC, out_stride elements per row).
  * Errors: HTSVD_ESTATE (no basis for this band count), HTSVD_ENOTSUP (adaptive or ra set),
  * HTSVD_EINVAL / HTSVD_ESHAPE as for htsvd_denoise. */

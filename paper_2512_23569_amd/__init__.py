@@ -100,6 +100,7 @@ _SIGS = {
     "htsvd_cnn_load": (_i32, [_vp, ctypes.c_char_p]),
     "htsvd_band_guide": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _vp, _vp]),
     "htsvd_denoise_bands": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _i64, _vp]),
+    "htsvd_set_band_memory": (_i32, [_vp, _i64]),
     "htsvd_ra_param_count": (_i32, [_i32]),
     "htsvd_ra_set_weights": (_i32, [_vp, _i32, _vp, _i64]),
     "htsvd_ra_get_weights": (_i32, [_vp, _i32, _vp, _i64]),
@@ -344,6 +345,10 @@ def htsvd_band_guide(ctx, d_in, h, w, bands, in_stride, d_guide, stream=None):
     import torch
     _check(lib().htsvd_band_guide(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, bands, in_stride,
                                   _dptr(d_guide, torch.uint8, "d_guide"), _stream(stream)))
+
+
+def htsvd_set_band_memory(ctx, nbytes: int):
+    _check(lib().htsvd_set_band_memory(ctx, int(nbytes)))
 
 
 def htsvd_denoise_bands(ctx, d_in, h, w, bands, in_stride, sigma, params, d_out, out_stride, stream=None):

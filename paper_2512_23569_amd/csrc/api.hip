@@ -76,6 +76,7 @@ struct htsvd_ctx {
     RaState ra[2];                          // RA-Haar-tSVD networks, [0]: c=1, [1]: c=3
     int bands = 0;                          // band count of the hyperspectral basis (0: none)
     double *d_band_maps = nullptr;          // its D, Dinv and slice maps (FP64)
+    int64_t band_cap = (int64_t)4 << 30;    // bytes per patch matrix of one pass of the band filter
     // Optional per-stage timing with HIP events recorded on the call's stream.
     bool timing = false;
     hipEvent_t ev[2 * HTSVD_N_STAGES] = {};
@@ -1959,6 +1960,13 @@ htsvd_status htsvd_band_guide(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, in
     return HTSVD_OK;
 }
 
+htsvd_status htsvd_set_band_memory(htsvd_ctx *ctx, int64_t bytes) {
+    if (!ctx) return fail(HTSVD_EINVAL, "null context");
+    if (bytes < ((int64_t)1 << 20)) return fail(HTSVD_EINVAL, "the band memory cap must be at least 1 MiB");
+    ctx->band_cap = bytes;
+    return HTSVD_OK;
+}
+
 htsvd_status htsvd_denoise_bands(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t bands,
                                  int64_t in_stride, float sigma, const htsvd_params *p, float *d_out,
                                  int64_t out_stride, void *stream) {
@@ -1977,7 +1985,7 @@ htsvd_status htsvd_denoise_bands(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h,
     const int64_t n_ref = (int64_t)g.ny * g.nx;
     const size_t off_idx = align256((size_t)h * w);
     const size_t off_ws = off_idx + align256(sizeof(int32_t) * n_ref * mp.K);
-    if ((s = ensure_ws(ctx, off_ws + band_ws_bytes(h, w, bands, n_ref * mp.K))) != HTSVD_OK) return s;
+    if ((s = ensure_ws(ctx, off_ws + band_ws_bytes(h, w, bands, mp.K, n_ref, ctx->band_cap))) != HTSVD_OK) return s;
     uint8_t *guide = (uint8_t *)ctx->ws;
     int32_t *idx = (int32_t *)((char *)ctx->ws + off_idx);
     hipStream_t st = (hipStream_t)stream;
@@ -1996,7 +2004,7 @@ htsvd_status htsvd_denoise_bands(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h,
     {
         StageScope sc(ctx, HTSVD_STAGE_FILTER, st);
         if ((e = launch_band_filter(bm, d_in, in_stride, h, w, bands, idx, n_ref, mp.K, (double)sigma * mult,
-                                    (char *)ctx->ws + off_ws, d_out, out_stride, st)) != hipSuccess)
+                                    ctx->band_cap, (char *)ctx->ws + off_ws, d_out, out_stride, st)) != hipSuccess)
             return hip_fail(e, "band filter");
     }
     return HTSVD_OK;

@@ -216,36 +216,48 @@ hipError_t launch_band_guide(const uint8_t *cube, int64_t stride, int h, int w, 
     return hipGetLastError();
 }
 
-size_t band_ws_bytes(int h, int w, int B, int64_t n_patch) {
+// Groups per pass of the filter: each of the three FP64 patch matrices stays below cap bytes.
+int64_t band_chunk_groups(int B, int K, int64_t n_group, int64_t cap) {
+    const int64_t per = (int64_t)K * 64 * B * (int64_t)sizeof(double);
+    return std::max<int64_t>(1, std::min<int64_t>(n_group, cap / per));
+}
+
+size_t band_ws_bytes(int h, int w, int B, int K, int64_t n_group, int64_t cap) {
+    const int64_t n_patch = band_chunk_groups(B, K, n_group, cap) * K;
     const size_t mat = sizeof(double) * (size_t)n_patch * 64 * B;
     return 3 * ((mat + 255) & ~(size_t)255) + (((size_t)h * w * B * 8 + 255) & ~(size_t)255) +
            (((size_t)h * w * 4 + 255) & ~(size_t)255);
 }
 
 hipError_t launch_band_filter(const BandMaps &bm, const uint8_t *cube, int64_t stride, int h, int w, int B,
-                              const int32_t *idx, int64_t n_group, int K, double tau, void *ws, float *out,
-                              int64_t out_stride, hipStream_t st) {
-    const int64_t n_patch = n_group * K;
-    const size_t mat = ((sizeof(double) * (size_t)n_patch * 64 * B) + 255) & ~(size_t)255;
+                              const int32_t *idx, int64_t n_group, int K, double tau, int64_t cap, void *ws,
+                              float *out, int64_t out_stride, hipStream_t st) {
+    const int64_t chunk = band_chunk_groups(B, K, n_group, cap);
+    const size_t mat = ((sizeof(double) * (size_t)(chunk * K) * 64 * B) + 255) & ~(size_t)255;
     double *X = (double *)ws, *Xd = (double *)((char *)ws + mat), *Sd = (double *)((char *)ws + 2 * mat);
     unsigned long long *acc = (unsigned long long *)((char *)ws + 3 * mat);
     int *cnt = (int *)((char *)acc + (((size_t)h * w * B * 8 + 255) & ~(size_t)255));
-    const int64_t nel = n_patch * 64 * B;
     hipError_t e;
-    hipLaunchKernelGGL(gather_kernel, dim3(nb(nel, 256)), dim3(256), 0, st, cube, stride, w, B, idx, n_patch, X);
-    if ((e = tproduct(bm, B, n_patch, X, Xd, Sd, X, false, st)) != hipSuccess) return e;   // S into X
-    const int64_t nt = n_group * 64 * B;
-    switch (K) {
-        case 4: hipLaunchKernelGGL(haar_threshold_kernel<4>, dim3(nb(nt, 256)), dim3(256), 0, st, X, n_group, B, tau); break;
-        case 8: hipLaunchKernelGGL(haar_threshold_kernel<8>, dim3(nb(nt, 256)), dim3(256), 0, st, X, n_group, B, tau); break;
-        case 16: hipLaunchKernelGGL(haar_threshold_kernel<16>, dim3(nb(nt, 256)), dim3(256), 0, st, X, n_group, B, tau); break;
-        case 32: hipLaunchKernelGGL(haar_threshold_kernel<32>, dim3(nb(nt, 256)), dim3(256), 0, st, X, n_group, B, tau); break;
-        default: return hipErrorInvalidValue;
-    }
-    if ((e = tproduct(bm, B, n_patch, X, Xd, Sd, X, true, st)) != hipSuccess) return e;    // estimates into X
     if ((e = launch_zero(acc, (size_t)h * w * B * 8, st)) != hipSuccess) return e;
     if ((e = launch_zero(cnt, (size_t)h * w * 4, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(aggregate_kernel, dim3(nb(nel, 256)), dim3(256), 0, st, X, idx, n_patch, w, B, acc, cnt);
+    for (int64_t g0 = 0; g0 < n_group; g0 += chunk) {
+        const int64_t ng = std::min<int64_t>(chunk, n_group - g0), n_patch = ng * K;
+        const int32_t *ix = idx + g0 * K;
+        const int64_t nel = n_patch * 64 * B;
+        hipLaunchKernelGGL(gather_kernel, dim3(nb(nel, 256)), dim3(256), 0, st, cube, stride, w, B, ix, n_patch, X);
+        if ((e = tproduct(bm, B, n_patch, X, Xd, Sd, X, false, st)) != hipSuccess) return e;   // S into X
+        const int64_t nt = ng * 64 * B;
+        switch (K) {
+            case 4: hipLaunchKernelGGL(haar_threshold_kernel<4>, dim3(nb(nt, 256)), dim3(256), 0, st, X, ng, B, tau); break;
+            case 8: hipLaunchKernelGGL(haar_threshold_kernel<8>, dim3(nb(nt, 256)), dim3(256), 0, st, X, ng, B, tau); break;
+            case 16: hipLaunchKernelGGL(haar_threshold_kernel<16>, dim3(nb(nt, 256)), dim3(256), 0, st, X, ng, B, tau); break;
+            case 32: hipLaunchKernelGGL(haar_threshold_kernel<32>, dim3(nb(nt, 256)), dim3(256), 0, st, X, ng, B, tau); break;
+            default: return hipErrorInvalidValue;
+        }
+        if ((e = tproduct(bm, B, n_patch, X, Xd, Sd, X, true, st)) != hipSuccess) return e;    // estimates into X
+        hipLaunchKernelGGL(aggregate_kernel, dim3(nb(nel, 256)), dim3(256), 0, st, X, ix, n_patch, w, B, acc, cnt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(normalize_kernel, dim3(nb((int64_t)h * w * B, 256)), dim3(256), 0, st, acc, cnt, cube, stride, h,
                        w, B, out, out_stride);
     return hipGetLastError();

@@ -272,10 +272,11 @@ hipError_t launch_fill_tau_learned(double *tau, const ImageGeom &g, int tile, co
 
 // Hyperspectral tube patches (bands.hip).
 hipError_t launch_band_guide(const uint8_t *cube, int64_t stride, int h, int w, int B, uint8_t *guide, hipStream_t st);
-size_t band_ws_bytes(int h, int w, int B, int64_t n_patch);
+// The filter works in chunks of groups whose FP64 patch matrices stay below cap bytes each.
+size_t band_ws_bytes(int h, int w, int B, int K, int64_t n_group, int64_t cap);
 hipError_t launch_band_filter(const BandMaps &bm, const uint8_t *cube, int64_t stride, int h, int w, int B,
-                              const int32_t *idx, int64_t n_group, int K, double tau, void *ws, float *out,
-                              int64_t out_stride, hipStream_t st);
+                              const int32_t *idx, int64_t n_group, int K, double tau, int64_t cap, void *ws,
+                              float *out, int64_t out_stride, hipStream_t st);
 
 // RA-Haar-tSVD refinement network (ra.hip).
 int ra_hidden(int c);

@@ -100,3 +100,22 @@ def test_band_learned_basis_and_denoise(dn, bands):
     ref = oracle.filter_groups(noisy, idx, Uo, Vo, 25.0 * np.sqrt(2.0 * np.log(bands * 16 * 64)))
     gpu = dn.denoise_bands(d, 25.0, dn.params(1, stride=4, window=15, K=16)).cpu().numpy()
     assert_pixel_parity(gpu, ref, clean)
+
+
+def test_band_filter_in_passes_is_identical(dn):
+    """A small memory cap splits the groups into several passes; the fixed-point aggregation
+    makes the output identical to the single pass."""
+    import paper_2512_23569_amd as ht
+    bands = 9
+    noisy = synth.add_awgn(synth.make_hsi(72, 80, bands, 120), 20.0, 121)
+    d = _dev(noisy)
+    dn.learn_basis(d, stride=4)
+    p = dn.params(1, stride=4, window=15, K=16)
+    one = dn.denoise_bands(d, 20.0, p)
+    ht.htsvd_set_band_memory(dn.ctx, 1 << 20)   # 1 MiB: 13 groups per pass, 18 passes
+    try:
+        many = dn.denoise_bands(d, 20.0, p)
+    finally:
+        ht.htsvd_set_band_memory(dn.ctx, 4 << 30)
+    torch.cuda.synchronize()
+    assert torch.equal(one, many)
