@@ -107,7 +107,8 @@ def test_training_reduces_the_loss(dn):
     assert last < 0.5 * first
 
 
-@pytest.mark.parametrize("c,K,sigma", [(3, 16, 50.0), (1, 16, 45.0), (3, 32, 60.0)])
+@pytest.mark.parametrize("c,K,sigma", [(3, 16, 50.0), (1, 16, 45.0), (3, 32, 60.0), (3, 8, 55.0), (3, 4, 40.0),
+                                       (1, 8, 50.0), (1, 4, 35.0)])
 def test_ra_denoise_parity(dn, c, K, sigma):
     """GPU RA-Haar-tSVD against the oracle: oracle groups, oracle mean patches, the FP64
     network and the FP64 filter with the refined first Haar row."""
