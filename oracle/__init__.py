@@ -51,6 +51,8 @@ def _L():
         lib.orc_denoise.argtypes = [p, i32, i32, i32, i64, i32, i32, i32, i32, i32, i32, p, p, p, p, dbl, p,
                                     i32, i64, i64, p, p]
         lib.orc_filter_groups.argtypes = [p, i32, i32, i32, i64, i32, i32, i64, p, p, p, p, p, i32]
+        lib.orc_block_match_video.argtypes = [p, i32, i32, i32, i32, i64, i32, i32, i32, i32, i32, i32, i32, p, p,
+                                              i32]
         _lib = lib
     return _lib
 
@@ -234,6 +236,21 @@ def filter_groups(img: np.ndarray, idx: np.ndarray, U: np.ndarray, V: np.ndarray
     _check(_L().orc_filter_groups(_ptr(a), h, w, c, w * c, ps, K, n_ref, _ptr(ix), _ptr(tau_ref), _ptr(u), _ptr(v),
                                   _ptr(out), nthreads))
     return out
+
+
+def block_match_video(frames: np.ndarray, ps: int, s: int, W: int, K: int, radius: int, gnum: int = 6,
+                      gden: int = 5, nthreads: int = 0):
+    """Spatio-temporal groups of a video (T, h, w[, c]) (Sec. IV-C): (idx[T*ny*nx, K] int32 of
+    (f*h + y)*w + x in the frames stacked vertically, dist int64)."""
+    v = np.ascontiguousarray(frames if frames.ndim == 4 else frames[..., None])
+    T, h, w, c = v.shape
+    L = _L()
+    n_ref = T * L.orc_ref_count(h, ps, s) * L.orc_ref_count(w, ps, s)
+    idx = np.zeros((n_ref, K), dtype=np.int32)
+    dist = np.zeros((n_ref, K), dtype=np.int64)
+    _check(L.orc_block_match_video(_ptr(v), T, h, w, c, w * c, ps, s, W, K, radius, gnum, gden, _ptr(idx), _ptr(dist),
+                                   nthreads))
+    return idx, dist
 
 
 def band_guide(cube: np.ndarray) -> np.ndarray:

@@ -17,6 +17,8 @@
  *     bcirc(A^T) = bcirc(A)^T.
  *   - The Haar matrix by the recursion of Sec. II-D (Eq. 7-8), built as an
  *     explicit K x K matrix and applied as a dense matrix product.
+ *   - Spatio-temporal grouping of a video (Sec. IV-C): the same distance
+ *     over the reference's window in the frames within a temporal radius.
  *
  * Readings where the paper is silent (also listed in the design notes):
  *   - reference grid: {0, s, 2s, ...} <= n-ps, plus n-ps when missing;
@@ -27,7 +29,9 @@
  *     gnum/gden (6/5), so the branch test is exact in integers; the
  *     "average" channel is replaced by the channel sum (same order, same
  *     ties); distances are squared Euclidean (same order);
- *   - ties between equal distances go to the smaller (row, column);
+ *   - ties between equal distances go to the smaller (row, column); in a
+ *     video to the smaller (frame, row, column), and a reference's window is
+ *     clipped inside its frame and searched at the same place in the others;
  *   - hard threshold keeps |s| >= tau (Eq. 20), no coefficient is exempt;
  *   - aggregation weights are uniform; pixels no patch covers keep the
  *     noisy value; the output is FP64 and unclipped.
@@ -569,6 +573,69 @@ int orc_denoise(const uint8_t *img, int h, int w, int c, int64_t stride, int ps,
     free(bnum); free(bcnt); free(brow0); free(brows);
     free(num); free(cnt); free(H); free(ys); free(xs);
     basis_free(&basis);
+    return status;
+}
+
+/* Spatio-temporal grouping of a video (Sec. IV-C): T frames of h x w x c stacked vertically
+ * (frame t occupies rows t*h .. t*h + h - 1 of the stacked image).  The reference at (y, x) of
+ * frame t takes its candidates from the clipped window around (y, x) in every frame f with
+ * |f - t| <= radius; the distance follows Eq. 9 as decided by the reference; the K nearest are
+ * ordered by (distance, frame, row, column).  References: frame-major, then the grid of each
+ * frame (Algorithm 1).  idx[r*K + k] = (f*h + y)*w + x in the stacked image, dist (may be NULL). */
+int orc_block_match_video(const uint8_t *frames, int T, int h, int w, int c, int64_t stride, int ps, int s, int W,
+                          int K, int radius, int gnum, int gden, int32_t *idx, int64_t *dist, int nthreads)
+{
+    int err = check_common(h, w, c, stride, ps, s, W, K);
+    if (err) return err;
+    if (T < 1 || radius < 0) return ORC_EINVAL;
+    int *ys = (int *)malloc(sizeof(int) * (h / s + 2));
+    int *xs = (int *)malloc(sizeof(int) * (w / s + 2));
+    const int ny = orc_ref_grid(h, ps, s, ys), nx = orc_ref_grid(w, ps, s, xs);
+    const int64_t per = (int64_t)ny * nx, n_ref = per * T;
+    bm_ctx_t m = {frames, h * T, w, c, stride, ps, W, K, gnum, gden};
+    const int R = (W - 1) / 2;
+    int status = ORC_OK;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+    {
+        cand_t *cand = (cand_t *)malloc(sizeof(cand_t) * W * W * (2 * radius + 1));
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (int64_t r = 0; r < n_ref; ++r) {
+            const int t = (int)(r / per);
+            const int y = ys[(r % per) / nx], x = xs[(r % per) % nx];
+            const int yr = t * h + y;
+            const int green = orc_gcp_green(frames, stride, c, ps, yr, x, gnum, gden);
+            const int ylo = y - R < 0 ? 0 : y - R, yhi = y + R > h - ps ? h - ps : y + R;
+            const int xlo = x - R < 0 ? 0 : x - R, xhi = x + R > w - ps ? w - ps : x + R;
+            int n = 0;
+            for (int f = t - radius; f <= t + radius; ++f) {
+                if (f < 0 || f >= T) continue;
+                for (int yc = ylo; yc <= yhi; ++yc)
+                    for (int xc = xlo; xc <= xhi; ++xc) {
+                        cand[n].d = patch_dist(&m, green, yr, x, f * h + yc, xc);
+                        cand[n].y = f * h + yc;   /* stacked rows order as (frame, row) */
+                        cand[n].x = xc;
+                        ++n;
+                    }
+            }
+            if (n < K) {
+                status = ORC_ESHAPE;
+                continue;
+            }
+            qsort(cand, n, sizeof(cand_t), cand_cmp);
+            for (int k = 0; k < K; ++k) {
+                idx[r * K + k] = cand[k].y * w + cand[k].x;
+                if (dist) dist[r * K + k] = cand[k].d;
+            }
+        }
+        free(cand);
+    }
+    free(ys);
+    free(xs);
     return status;
 }
 

@@ -401,6 +401,90 @@ def test_smaller_groups_are_prefixes_of_larger_ones(c, seed):
     assert np.array_equal(bi, i32[:, :4]) and np.array_equal(bd, d32[:, :4])
 
 
+# ---- spatio-temporal grouping: Sec. IV-C -------------------------------------
+
+def _brute_video_groups(frames, ps, s, W, K, radius, gnum=6, gden=5):
+    """Brute force over (frame, row, column) with Python tuples: the reference decides the Eq. 9
+    branch, its window is clipped inside the frame, and frames within the radius contribute."""
+    v = frames.astype(np.int64) if frames.ndim == 4 else frames.astype(np.int64)[..., None]
+    T, h, w, c = v.shape
+    ys, xs = _py_grid(h, ps, s), _py_grid(w, ps, s)
+    R = (W - 1) // 2
+    out_i, out_d = [], []
+    for t in range(T):
+        for y in ys:
+            for x in xs:
+                ref = v[t, y:y + ps, x:x + ps]
+                if c == 3:
+                    n = [(ref[:, :, k] ** 2).sum() for k in range(3)]
+                    green = gnum * gnum * n[1] >= gden * gden * max(n[0], n[2])
+                else:
+                    green = True
+
+                def plane(p):
+                    if c == 1:
+                        return p[:, :, 0]
+                    return p[:, :, 1] if green else p.sum(axis=2)
+                rp = plane(ref)
+                cands = []
+                for f in range(max(0, t - radius), min(T - 1, t + radius) + 1):
+                    for yc in range(max(0, y - R), min(h - ps, y + R) + 1):
+                        for xc in range(max(0, x - R), min(w - ps, x + R) + 1):
+                            d = int(((rp - plane(v[f, yc:yc + ps, xc:xc + ps])) ** 2).sum())
+                            cands.append((d, f, yc, xc))
+                cands.sort()
+                out_i.append([(f * h + yc) * w + xc for _, f, yc, xc in cands[:K]])
+                out_d.append([d for d, _, _, _ in cands[:K]])
+    return np.array(out_i), np.array(out_d)
+
+
+@pytest.mark.parametrize("T,h,w,c,K,W,s,radius,seed", [(3, 16, 18, 1, 4, 5, 3, 1, 0), (4, 17, 20, 3, 8, 7, 4, 1, 1),
+                                                        (3, 18, 16, 3, 16, 5, 5, 2, 2), (2, 16, 16, 1, 8, 3, 4, 3, 3)])
+def test_video_block_match_brute_force(T, h, w, c, K, W, s, radius, seed):
+    """Tie-heavy frames (four grey levels, a frame-to-frame copy, shifted content) against the
+    brute force: frame range, clipping and the (distance, frame, row, column) order."""
+    rng = np.random.default_rng(seed)
+    shape = (T, h, w, c) if c == 3 else (T, h, w)
+    v = rng.integers(0, 4, shape).astype(np.uint8) * 60
+    v[1] = v[0]                                # a static pair: equal distances in two frames
+    v[-1, 2:10, 3:11] = v[0, 5:13, 1:9]        # content that moved between frames
+    idx, dist = oracle.block_match_video(v, 8, s, W, K, radius)
+    bi, bd = _brute_video_groups(v, 8, s, W, K, radius)
+    assert np.array_equal(idx, bi)
+    assert np.array_equal(dist, bd)
+
+
+@pytest.mark.parametrize("c", [1, 3])
+def test_video_radius_zero_is_per_frame_grouping(c):
+    rng = np.random.default_rng(20 + c)
+    v = rng.integers(0, 256, (3, 24, 28, c) if c == 3 else (3, 24, 28)).astype(np.uint8)
+    idx, dist = oracle.block_match_video(v, 8, 4, 9, 8, 0)
+    per = len(idx) // 3
+    for t in range(3):
+        i, d = oracle.block_match(v[t], 8, 4, 9, 8)
+        assert np.array_equal(idx[t * per:(t + 1) * per], i + t * 24 * 28)
+        assert np.array_equal(dist[t * per:(t + 1) * per], d)
+
+
+def test_static_video_repeats_each_candidate_once_per_frame():
+    """All frames equal: every candidate distance occurs once in each searched frame, so a group
+    of K = nf * k members holds the first k members of the single-frame group, each followed by
+    its copies in the later frames (ties ordered by frame; the random frame has no tied distances
+    among its first members)."""
+    rng = np.random.default_rng(30)
+    img = rng.integers(0, 256, (20, 24, 3)).astype(np.uint8)
+    v = np.stack([img] * 4)
+    i1, d1 = oracle.block_match(img, 8, 4, 9, 8)
+    iv, dv = oracle.block_match_video(v, 8, 4, 9, 32, 3)   # 4 frames searched by every reference
+    per = len(i1)
+    for t in range(4):
+        got_i, got_d = iv[t * per:(t + 1) * per], dv[t * per:(t + 1) * per]
+        assert np.array_equal(got_d, np.repeat(d1, 4, axis=1))
+        frames = got_i // (20 * 24)
+        assert np.array_equal(frames, np.tile(np.arange(4), (per, 8)))
+        assert np.array_equal(got_i % (20 * 24), np.repeat(i1, 4, axis=1))
+
+
 def test_flat_image_groups_are_raster_order():
     img = np.full((20, 20), 77, np.uint8)
     idx, dist = oracle.block_match(img, 8, 4, 5, 8)
