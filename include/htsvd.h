@@ -167,6 +167,30 @@ htsvd_status htsvd_denoise_bands(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h,
                                  int64_t in_stride, float sigma, const htsvd_params *p, float *d_out,
                                  int64_t out_stride, void *stream);
 
+/* ---- Video (Sec. IV-C) ----
+ * T frames of h x w x c uint8 (c = 1 or 3, HWC) stacked vertically in one buffer: frame t is rows
+ * t*h .. t*h + h - 1 of d_in, in_stride bytes per row.  The patch search runs over space and
+ * time: each reference of frame t (frame-major, then the grid of Algorithm 1) takes the K
+ * nearest patches, by the distance of Eq. 9 as decided by the reference, among the positions of
+ * its clipped search window (p->window) in every frame f with |f - t| <= radius, 0 <= f < T,
+ * ordered by (distance, frame, row, column).  radius = 0 gives the groups of each frame alone.
+ * Errors as for htsvd_block_match, plus HTSVD_ESHAPE for T < 1, HTSVD_EINVAL for a radius
+ * outside [0, 31] and HTSVD_ENOTSUP for more than 2^30 pixels in all. */
+/* Groups: d_idx[r*K + k] = (f*h + y)*w + x of member k of reference r (T * ny * nx references,
+ * int32, device), d_dist (may be NULL) its distance. */
+htsvd_status htsvd_block_match_video(htsvd_ctx *ctx, const uint8_t *d_in, int32_t T, int32_t h, int32_t w,
+                                     int32_t c, int64_t in_stride, int32_t radius, const htsvd_params *p,
+                                     int32_t *d_idx, int32_t *d_dist, void *stream);
+/* Denoises the frames with a known sigma: the spatio-temporal groups are filtered with the
+ * global t-SVD basis of c channels and the Haar transform (Eq. 19-21, in FP64), tau = sigma *
+ * (p->tau_mult, or sqrt(2 ln(c K ps^2))), and aggregated uniformly over the stacked frames
+ * (Algorithm 1) into d_out (float32, T*h rows of out_stride elements).  The filter's patch
+ * matrices follow htsvd_set_band_memory.  Errors: HTSVD_ESTATE (no basis for c),
+ * HTSVD_ENOTSUP (adaptive or ra set), the others as above. */
+htsvd_status htsvd_denoise_video(htsvd_ctx *ctx, const uint8_t *d_in, int32_t T, int32_t h, int32_t w, int32_t c,
+                                 int64_t in_stride, int32_t radius, float sigma, const htsvd_params *p, float *d_out,
+                                 int64_t out_stride, void *stream);
+
 /* ---- RA-Haar-tSVD refinement network (Sec. III-E-2, Eq. 24-25) ----
  * The first Haar row of a group is sqrt(K) times its mean patch p (Eq. 24); a fully connected
  * network refines p (Eq. 25), trained by residual learning on mean patches of noisy/clean

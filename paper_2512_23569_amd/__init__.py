@@ -101,6 +101,8 @@ _SIGS = {
     "htsvd_band_guide": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _vp, _vp]),
     "htsvd_denoise_bands": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _i64, _vp]),
     "htsvd_set_band_memory": (_i32, [_vp, _i64]),
+    "htsvd_block_match_video": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i64, _i32, _PP, _vp, _vp, _vp]),
+    "htsvd_denoise_video": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i64, _i32, _f32, _PP, _vp, _i64, _vp]),
     "htsvd_ra_param_count": (_i32, [_i32]),
     "htsvd_ra_set_weights": (_i32, [_vp, _i32, _vp, _i64]),
     "htsvd_ra_get_weights": (_i32, [_vp, _i32, _vp, _i64]),
@@ -358,6 +360,21 @@ def htsvd_denoise_bands(ctx, d_in, h, w, bands, in_stride, sigma, params, d_out,
                                      _stream(stream)))
 
 
+def htsvd_block_match_video(ctx, d_in, T, h, w, c, in_stride, radius, params, d_idx, d_dist=None, stream=None):
+    import torch
+    _check(lib().htsvd_block_match_video(ctx, _dptr(d_in, torch.uint8, "d_in"), T, h, w, c, in_stride, radius,
+                                         ctypes.byref(params), _dptr(d_idx, torch.int32, "d_idx"),
+                                         _dptr(d_dist, torch.int32, "d_dist"),
+                                         _stream(stream)))
+
+
+def htsvd_denoise_video(ctx, d_in, T, h, w, c, in_stride, radius, sigma, params, d_out, out_stride, stream=None):
+    import torch
+    _check(lib().htsvd_denoise_video(ctx, _dptr(d_in, torch.uint8, "d_in"), T, h, w, c, in_stride, radius,
+                                     float(sigma), ctypes.byref(params), _dptr(d_out, torch.float32, "d_out"),
+                                     out_stride, _stream(stream)))
+
+
 def htsvd_ra_param_count(c: int) -> int:
     return int(lib().htsvd_ra_param_count(c))
 
@@ -550,6 +567,41 @@ class Denoiser:
         if out is None:
             out = torch.empty(cube.shape, dtype=torch.float32, device=cube.device)
         htsvd_denoise_bands(self.ctx, cube, h, w, b, cube.stride(0), sigma, params, out, out.stride(0), stream)
+        return out
+
+    @staticmethod
+    def _video_dims(frames):
+        if frames.dim() == 3:
+            T, h, w = frames.shape
+            c = 1
+        elif frames.dim() == 4:
+            T, h, w, c = frames.shape
+        else:
+            raise ValueError("frames must be (T, h, w) or (T, h, w, c)")
+        if not frames.is_contiguous():
+            raise ValueError("frames must be contiguous")
+        return T, h, w, c
+
+    def block_match_video(self, frames, params, radius, with_dist=True, stream=None):
+        """Spatio-temporal groups of device frames (T, h, w[, c]) uint8: idx (T*ny*nx, K) of
+        (f*h + y)*w + x in the frames stacked vertically, and the distances."""
+        import torch
+        T, h, w, c = self._video_dims(frames)
+        n_ref = T * htsvd_ref_count(h, 8, params.stride) * htsvd_ref_count(w, 8, params.stride)
+        idx = torch.empty((n_ref, params.K), dtype=torch.int32, device=frames.device)
+        dist = torch.empty((n_ref, params.K), dtype=torch.int32, device=frames.device) if with_dist else None
+        htsvd_block_match_video(self.ctx, frames, T, h, w, c, w * c, radius, params, idx, dist, stream)
+        return idx, dist
+
+    def denoise_video(self, frames, sigma, params, radius, out=None, stream=None):
+        """Video denoising with a known sigma: float32 frames of the input's shape."""
+        import torch
+        T, h, w, c = self._video_dims(frames)
+        if out is None:
+            out = torch.empty(frames.shape, dtype=torch.float32, device=frames.device)
+        elif not out.is_contiguous() or out.shape != frames.shape:
+            raise ValueError("out must be contiguous and of the frames' shape")
+        htsvd_denoise_video(self.ctx, frames, T, h, w, c, w * c, radius, sigma, params, out, w * c, stream)
         return out
 
     def guard_count(self):

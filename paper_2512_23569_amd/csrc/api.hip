@@ -77,6 +77,9 @@ struct htsvd_ctx {
     int bands = 0;                          // band count of the hyperspectral basis (0: none)
     double *d_band_maps = nullptr;          // its D, Dinv and slice maps (FP64)
     int64_t band_cap = (int64_t)4 << 30;    // bytes per patch matrix of one pass of the band filter
+    std::vector<double> basis_uv[2];        // host copies of the colour/gray basis (U then V)
+    double *d_video_maps[2] = {nullptr, nullptr};   // its t-product maps for the video filter (FP64)
+    uint64_t video_gen[2] = {0, 0};         // basis generation the video maps were built from
     // Optional per-stage timing with HIP events recorded on the call's stream.
     bool timing = false;
     hipEvent_t ev[2 * HTSVD_N_STAGES] = {};
@@ -479,9 +482,10 @@ htsvd_status run_filter(htsvd_ctx *ctx, const ImageGeom &g, const MethodParams &
     return HTSVD_OK;
 }
 
-// Basis of the hyperspectral path (B bands): the band DFT, its inverse and the per-frequency
-// maps of the t-product (Eq. 4-5), checked for orthogonality slice by slice.
-htsvd_status set_basis_bands(htsvd_ctx *ctx, int B, const double *h_U, const double *h_V) {
+// Maps of the t-product along B channels (Eq. 4-5) for the FP64 filter of arbitrary groups: the
+// channel DFT, its inverse and the per-frequency slice maps, after an orthogonality check of
+// every slice.
+htsvd_status build_band_maps(int B, const double *h_U, const double *h_V, std::vector<double> &maps) {
     typedef std::complex<double> cd;
     const int NF = B / 2 + 1;
     std::vector<cd> Uh((size_t)NF * 64), Vh((size_t)NF * 64);
@@ -508,7 +512,7 @@ htsvd_status set_basis_bands(htsvd_ctx *ctx, int B, const double *h_U, const dou
                 if (std::abs(su - t) > 1e-9 || std::abs(sv - t) > 1e-9)
                     return fail(HTSVD_EINVAL, "basis tensors are not orthogonal");
             }
-    std::vector<double> maps((size_t)2 * B * B + (size_t)NF * 2 * 4096, 0.0);
+    maps.assign((size_t)2 * B * B + (size_t)NF * 2 * 4096, 0.0);
     double *D = maps.data(), *Dinv = D + B * B, *M = Dinv + B * B;
     for (int b = 0; b < B; ++b) {
         D[0 * B + b] = 1.0;
@@ -536,20 +540,51 @@ htsvd_status set_basis_bands(htsvd_ctx *ctx, int B, const double *h_U, const dou
                         M[o] = m.real();
                         M[o + 4096] = m.imag();
                     }
+    return HTSVD_OK;
+}
+
+// Uploads maps into *d (replacing what it held).  Synchronises the device first.
+htsvd_status upload_maps(htsvd_ctx *ctx, const std::vector<double> &maps, double **d) {
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronise before basis upload");
-    if (ctx->d_band_maps) (void)hipFree(ctx->d_band_maps);
-    ctx->d_band_maps = nullptr;
-    ctx->bands = 0;
-    if (hipMalloc(&ctx->d_band_maps, sizeof(double) * maps.size()) != hipSuccess) {
-        ctx->d_band_maps = nullptr;
+    if (*d) (void)hipFree(*d);
+    *d = nullptr;
+    if (hipMalloc(d, sizeof(double) * maps.size()) != hipSuccess) {
+        *d = nullptr;
         (void)hipGetLastError();
         return fail(HTSVD_ENOMEM, "basis allocation");
     }
-    if ((e = hipMemcpy(ctx->d_band_maps, maps.data(), sizeof(double) * maps.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMemcpy(*d, maps.data(), sizeof(double) * maps.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "basis upload");
+    return HTSVD_OK;
+}
+
+// Basis of the hyperspectral path (B bands).
+htsvd_status set_basis_bands(htsvd_ctx *ctx, int B, const double *h_U, const double *h_V) {
+    std::vector<double> maps;
+    htsvd_status s = build_band_maps(B, h_U, h_V, maps);
+    if (s != HTSVD_OK) return s;
+    ctx->bands = 0;
+    if ((s = upload_maps(ctx, maps, &ctx->d_band_maps)) != HTSVD_OK) return s;
     ctx->bands = B;
+    return HTSVD_OK;
+}
+
+// t-product maps of the colour/gray basis for the video filter, rebuilt when the basis changed.
+htsvd_status video_maps(htsvd_ctx *ctx, int c, BandMaps *bm) {
+    const int slot = c == 3;
+    if (!ctx->d_video_maps[slot] || ctx->video_gen[slot] != ctx->basis_gen[slot]) {
+        const std::vector<double> &uv = ctx->basis_uv[slot];
+        std::vector<double> maps;
+        htsvd_status s = build_band_maps(c, uv.data(), uv.data() + 64 * c, maps);
+        if (s != HTSVD_OK) return s;
+        if ((s = upload_maps(ctx, maps, &ctx->d_video_maps[slot])) != HTSVD_OK) return s;
+        ctx->video_gen[slot] = ctx->basis_gen[slot];
+    }
+    bm->D = ctx->d_video_maps[slot];
+    bm->Dinv = bm->D + c * c;
+    bm->M = bm->Dinv + c * c;
     return HTSVD_OK;
 }
 
@@ -735,6 +770,8 @@ void htsvd_destroy(htsvd_ctx *ctx) {
     if (ctx->d_guard) (void)hipFree(ctx->d_guard);
     if (ctx->d_gram) (void)hipFree(ctx->d_gram);
     if (ctx->d_band_maps) (void)hipFree(ctx->d_band_maps);
+    for (int i = 0; i < 2; ++i)
+        if (ctx->d_video_maps[i]) (void)hipFree(ctx->d_video_maps[i]);
     for (int i = 0; i < 2; ++i) {
         RaState &r = ctx->ra[i];
         for (void *q : {(void *)r.w, (void *)r.m, (void *)r.v, (void *)r.grad, (void *)r.frag, (void *)r.frag3t,
@@ -939,6 +976,8 @@ htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double
         return hip_fail(e, "basis upload");
     ctx->has_basis[slot] = true;
     ctx->T64h[slot] = T;
+    ctx->basis_uv[slot].assign(h_U, h_U + 64 * c);
+    ctx->basis_uv[slot].insert(ctx->basis_uv[slot].end(), h_V, h_V + 64 * c);
     ++ctx->basis_gen[slot];
     return HTSVD_OK;
 }
@@ -2006,6 +2045,67 @@ htsvd_status htsvd_denoise_bands(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h,
         if ((e = launch_band_filter(bm, d_in, in_stride, h, w, bands, idx, n_ref, mp.K, (double)sigma * mult,
                                     ctx->band_cap, (char *)ctx->ws + off_ws, d_out, out_stride, st)) != hipSuccess)
             return hip_fail(e, "band filter");
+    }
+    return HTSVD_OK;
+}
+
+// Checks of the video calls: frame geometry and method parameters as for one image, then the
+// frame count, the temporal radius and the size of the stacked frames.
+static htsvd_status validate_video(htsvd_ctx *ctx, const uint8_t *d_in, int32_t T, int32_t h, int32_t w, int32_t c,
+                            int64_t in_stride, int32_t radius, const htsvd_params *p, ImageGeom *g, MethodParams *mp,
+                            bool need_basis) {
+    htsvd_status s = validate(ctx, d_in, h, w, c, in_stride, p, g, mp, need_basis);
+    if (s != HTSVD_OK) return s;
+    if (T < 1) return fail(HTSVD_ESHAPE, "a video needs at least one frame");
+    if (radius < 0 || radius > 31) return fail(HTSVD_EINVAL, "radius must be in [0, 31]");
+    if ((int64_t)T * h * w > (int64_t)1 << 30) return fail(HTSVD_ENOTSUP, "video larger than 2^30 pixels");
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_block_match_video(htsvd_ctx *ctx, const uint8_t *d_in, int32_t T, int32_t h, int32_t w,
+                                     int32_t c, int64_t in_stride, int32_t radius, const htsvd_params *p,
+                                     int32_t *d_idx, int32_t *d_dist, void *stream) {
+    ImageGeom g;
+    MethodParams mp;
+    htsvd_status s = validate_video(ctx, d_in, T, h, w, c, in_stride, radius, p, &g, &mp, false);
+    if (s != HTSVD_OK) return s;
+    if (!d_idx) return fail(HTSVD_EINVAL, "null index output");
+    hipError_t e = launch_block_match_video(g, mp, T, radius, d_idx, d_dist, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "spatio-temporal block matching");
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_denoise_video(htsvd_ctx *ctx, const uint8_t *d_in, int32_t T, int32_t h, int32_t w, int32_t c,
+                                 int64_t in_stride, int32_t radius, float sigma, const htsvd_params *p, float *d_out,
+                                 int64_t out_stride, void *stream) {
+    ImageGeom g;
+    MethodParams mp;
+    htsvd_status s = validate_video(ctx, d_in, T, h, w, c, in_stride, radius, p, &g, &mp, true);
+    if (s != HTSVD_OK) return s;
+    if (!d_out) return fail(HTSVD_EINVAL, "null output");
+    if (out_stride < (int64_t)w * c) return fail(HTSVD_EINVAL, "out_stride < w*c");
+    if (!(sigma > 0.f) || !std::isfinite(sigma)) return fail(HTSVD_EINVAL, "sigma must be > 0");
+    if (p->adaptive || p->ra) return fail(HTSVD_ENOTSUP, "the video path takes a known sigma, no vote or refinement");
+    BandMaps bm;
+    if ((s = video_maps(ctx, c, &bm)) != HTSVD_OK) return s;
+    const int64_t n_ref = (int64_t)T * g.ny * g.nx;
+    const int H = T * h;   // rows of the stacked frames
+    const size_t off_ws = align256(sizeof(int32_t) * n_ref * mp.K);
+    if ((s = ensure_ws(ctx, off_ws + band_ws_bytes(H, w, c, mp.K, n_ref, ctx->band_cap))) != HTSVD_OK) return s;
+    int32_t *idx = (int32_t *)ctx->ws;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    {
+        StageScope sc(ctx, HTSVD_STAGE_BM, st);
+        if ((e = launch_block_match_video(g, mp, T, radius, idx, nullptr, st)) != hipSuccess)
+            return hip_fail(e, "spatio-temporal block matching");
+    }
+    const double mult = p->tau_mult > 0.0 ? p->tau_mult : default_mult(c, mp.K);
+    {
+        StageScope sc(ctx, HTSVD_STAGE_FILTER, st);
+        if ((e = launch_band_filter(bm, d_in, in_stride, H, w, c, idx, n_ref, mp.K, (double)sigma * mult,
+                                    ctx->band_cap, (char *)ctx->ws + off_ws, d_out, out_stride, st)) != hipSuccess)
+            return hip_fail(e, "video filter");
     }
     return HTSVD_OK;
 }

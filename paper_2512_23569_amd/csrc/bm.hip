@@ -19,6 +19,11 @@
 // (distance, row, column).  Each wave then selects the K smallest keys of one reference:
 // the K-th smallest of the 64 lane minima bounds the answer from above, the keys under
 // that bound are compacted and sorted with a wave bitonic network.
+//
+// Video (Sec. IV-C): the frames are stacked vertically, and a reference's candidates are the
+// positions of its clipped window in every frame within a temporal radius.  The workgroup keeps
+// the reference patches of its own frame in registers, stages one frame after another, and
+// merges each frame's K best (distance, frame slot, position) keys into a running list in LDS.
 #include "common.h"
 
 namespace htsvd {
@@ -33,6 +38,13 @@ constexpr int NREF = REF_TILE * REF_TILE;  // 16
 constexpr int BMW = 16;                    // wavefronts per workgroup (four per SIMD)
 constexpr int BMT = BMW * 64;
 constexpr int SEL_CAP = 512;               // >= K * ceil(MAX_CAND / 64) for K <= 32
+constexpr int RUN_K = 32;                  // running list per reference of the video search
+
+// Frames of a video search: g.img is frame 0 of T frames of g.h rows each, frame_bytes apart.
+struct VideoArgs {
+    int T, radius;
+    int64_t frame_bytes;
+};
 
 struct TileInfo {
     int ry[NREF], rx[NREF];        // reference position, ry = -1 if the slot is empty
@@ -47,7 +59,7 @@ struct BmLds {
     int pitch8;     // bytes per row of one int8 plane copy
     int pitch16;    // halves per row of one fp16 plane copy
     int rows;       // plane rows (union rows + 7)
-    int off_p8, off_p16, off_n8, off_n16, off_tab, off_sel, total;
+    int off_p8, off_p16, off_n8, off_n16, off_tab, off_sel, total;   // video: running lists last
 };
 
 __device__ inline uint32_t lds_u32(const unsigned char *base, int byte_off) {
@@ -116,11 +128,23 @@ __device__ void lds_sort(uint64_t *a, int P, int lane) {
     }
 }
 
-// Groups of the 16 references of tile b.
-__device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &mp, const int tiles_x, const int b,
+// Groups of the 16 references of tile b (VIDEO: tile b of the frames' tiles, frame-major).
+template <bool VIDEO>
+__device__ __forceinline__ void bm_tile(const ImageGeom &g0, const MethodParams &mp, const int tiles_x, const int b_in,
                                         const BmLds &L, int32_t *__restrict__ idx_out,
-                                        int32_t *__restrict__ dist_out, unsigned char *smem, TileInfo &ti) {
+                                        int32_t *__restrict__ dist_out, unsigned char *smem, TileInfo &ti,
+                                        const VideoArgs &va) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int b = b_in, t = 0, f_lo = 0, nf = 1;
+    ImageGeom g = g0;   // the reference's frame
+    if constexpr (VIDEO) {
+        const int tiles_frame = ((g0.ny + REF_TILE - 1) / REF_TILE) * tiles_x;
+        t = b_in / tiles_frame;
+        b = b_in - t * tiles_frame;
+        g.img = g0.img + (int64_t)t * va.frame_bytes;
+        f_lo = max(0, t - va.radius);
+        nf = min(va.T - 1, t + va.radius) - f_lo + 1;
+    }
     const int tyi = b / tiles_x, txi = b % tiles_x;
     const int R = (mp.W - 1) / 2;
 
@@ -181,19 +205,41 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
     const int plane8 = L.rows * L.pitch8;
     const int plane16 = L.rows * L.pitch16;
 
+    // Per-lane state of the distance phase, kept across the frames of a video search: the A
+    // fragments of reference i16 and the window and norm of the 4 references of this lane's
+    // accumulators.
+    const int i16 = lane & 15, q = lane >> 4;
+    v4i a8;
+    v8h a16a = {}, a16b = {};
+    bool any_sum = false;
+    int rwy0[4], rwx0[4], rwh[4], rww[4], rgreen[4], rn[4];
+    uint64_t *run = reinterpret_cast<uint64_t *>(smem + L.total - NREF * RUN_K * 8);
+    const int K = mp.K;
+
+    for (int fi = 0; fi < nf; ++fi) {
+    int slot = 0;
+    const uint8_t *fimg = g.img;
+    if constexpr (VIDEO) {
+        // the reference's own frame first (its patches become the A fragments), then the others
+        const int f = fi == 0 ? t : f_lo + fi - 1 + (f_lo + fi - 1 >= t ? 1 : 0);
+        slot = f - f_lo;
+        fimg = g0.img + (int64_t)f * va.frame_bytes;
+        if (fi > 0) __syncthreads();   // the last frame's table and selection scratch are reused
+    }
+
     // ---- stage the shifted planes: one thread per (row, group of 4 columns) ----
     // Dword w of int8 copy k holds the row's pixels 4w + k .. 4w + k + 3, and halves 4w .. 4w + 3
     // of fp16 copy k hold the pixels 4w + k .. 4w + k + 3, so a thread needs pixels 4w .. 4w + 6.
     // Bytes at or beyond the staged width pcol are never read (candidates end at pcol - 1).
     {
         const int nw = (pcol + 3) >> 2;
-        const uint8_t *img_end = g.img + (int64_t)(g.h - 1) * g.stride + (int64_t)g.w * g.c;
+        const uint8_t *img_end = fimg + (int64_t)(g.h - 1) * g.stride + (int64_t)g.w * g.c;
         uint32_t *p8w = reinterpret_cast<uint32_t *>(p8);
         uint32_t *p16w = reinterpret_cast<uint32_t *>(p16);
         for (int e = tid; e < prow * nw; e += BMT) {
             const int r = e / nw, w4 = 4 * (e - r * nw);
             const int npx = min(7, pcol - w4);
-            const uint8_t *a = g.img + (int64_t)(uy0 + r) * g.stride + (int64_t)(ux0 + w4) * g.c;
+            const uint8_t *a = fimg + (int64_t)(uy0 + r) * g.stride + (int64_t)(ux0 + w4) * g.c;
             uint32_t raw[6];   // bytes 0 .. 23 from a
             const uintptr_t ai = (uintptr_t)a;
             const uint32_t *ab = reinterpret_cast<const uint32_t *>(ai & ~(uintptr_t)3);
@@ -241,7 +287,7 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
         }
     }
     __syncthreads();
-    if (tid == 0) {   // read after the norm phase's barriers
+    if (fi == 0 && tid == 0) {   // read after the norm phase's barriers
         int any = 0;
         for (int i = 0; i < NREF; ++i) any |= (ti.ry[i] >= 0 && !ti.green[i]);
         ti.any_sum = any;
@@ -332,11 +378,10 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
 
     // ---- distances on the matrix cores ----
     {
-        const int i16 = lane & 15, q = lane >> 4;
+      if (fi == 0) {
         // A fragments: reference i16, rows 2q, 2q+1 (int8) and rows q, q+4 (fp16).
         int ar = ti.ry[i16] >= 0 ? ti.ry[i16] - uy0 : 0;
         int ac = ti.ry[i16] >= 0 ? ti.rx[i16] - ux0 : 0;
-        v4i a8;
         {
             const int k = ac & 3;
             const unsigned char *base = p8 + k * plane8;
@@ -344,8 +389,7 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
             a8[0] = (int)lds_u32(base, o0); a8[1] = (int)lds_u32(base, o0 + 4);
             a8[2] = (int)lds_u32(base, o1); a8[3] = (int)lds_u32(base, o1 + 4);
         }
-        v8h a16a = {}, a16b = {};
-        const bool any_sum = ti.any_sum != 0;
+        any_sum = ti.any_sum != 0;
         if (any_sum) {
             const int k = ac & 1;
             const _Float16 *base = p16 + k * plane16;
@@ -355,7 +399,6 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
             for (int t = 0; t < 8; ++t) { a16a[t] = ra[t]; a16b[t] = rb[t]; }
         }
         // Per-lane info of the 4 references this lane's accumulators belong to.
-        int rwy0[4], rwx0[4], rwh[4], rww[4], rgreen[4], rn[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int ii = 4 * q + r;
@@ -370,6 +413,17 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
                 rwh[r] = 0;
             }
         }
+      }
+      if constexpr (VIDEO) {
+        // reloaded for every frame: only the norms and the A fragments stay live across frames
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ii = 4 * q + r;
+            rwy0[r] = ti.wy0[ii]; rwx0[r] = ti.wx0[ii];
+            rwh[r] = ti.ry[ii] >= 0 ? ti.wh[ii] : 0; rww[r] = ti.ww[ii];
+            rgreen[r] = ti.green[ii];
+        }
+      }
         const int nU = uh * uw;
         const int nchunks = (nU + 15) >> 4;
         // candidate j = 16 chunk + i16 at (row, column) = (j / uw, j % uw), stepped by 16 BMW
@@ -425,7 +479,6 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
 
     // ---- top-K per reference ----
     uint64_t *sel = reinterpret_cast<uint64_t *>(smem + L.off_sel) + wave * SEL_CAP;
-    const int K = mp.K;
     for (int ii = wave; ii < NREF; ii += BMW) {
         if (ti.ry[ii] < 0) continue;
         const int n = ti.wh[ii] * ti.ww[ii];
@@ -474,7 +527,16 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
             lds_sort(sel, P, lane);
             mine = lane < K ? sel[lane] : ~0ull;
         }
-        if (lane < K) {
+        if constexpr (VIDEO) {
+            // merge into the running list: keys (distance, frame slot, position); only this wave
+            // touches reference ii's list
+            uint64_t v = lane < K ? (((mine >> 10) << 16) | ((uint64_t)slot << 10) | (mine & 1023u)) : ~0ull;
+            if (fi > 0) {
+                if (lane >= K && lane < 2 * K) v = run[ii * RUN_K + lane - K];
+                v = wave_sort64(v, lane);
+            }
+            if (lane < K) run[ii * RUN_K + lane] = v;
+        } else if (lane < K) {
             const int p = (int)(mine & 1023u);
             const int y = ti.wy0[ii] + p / ti.ww[ii], x = ti.wx0[ii] + p % ti.ww[ii];
             const int iy = tyi * REF_TILE + ii / REF_TILE, ix = txi * REF_TILE + ii % REF_TILE;
@@ -483,6 +545,20 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g, const MethodParams &
             if (dist_out) dist_out[r * K + lane] = (int32_t)(mine >> 10);
         }
         wave_lds_sync();
+    }
+    }   // frames
+
+    if constexpr (VIDEO) {
+        for (int ii = wave; ii < NREF; ii += BMW) {
+            if (ti.ry[ii] < 0 || lane >= K) continue;
+            const uint64_t key = run[ii * RUN_K + lane];
+            const int p = (int)(key & 1023u), f = f_lo + (int)((key >> 10) & 63u);
+            const int y = ti.wy0[ii] + p / ti.ww[ii], x = ti.wx0[ii] + p % ti.ww[ii];
+            const int iy = tyi * REF_TILE + ii / REF_TILE, ix = txi * REF_TILE + ii % REF_TILE;
+            const int64_t r = ((int64_t)t * g.ny + iy) * g.nx + ix;
+            idx_out[r * K + lane] = (f * g.h + y) * g.w + x;
+            if (dist_out) dist_out[r * K + lane] = (int32_t)(key >> 16);
+        }
     }
 }
 
@@ -497,7 +573,19 @@ __global__ __launch_bounds__(BMT) void bm_kernel(ImageGeom g, MethodParams mp, i
     const int per = (n_tiles + 7) / 8;
     const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (b >= n_tiles) return;
-    bm_tile(g, mp, tiles_x, b, L, idx_out, dist_out, smem, ti);
+    bm_tile<false>(g, mp, tiles_x, b, L, idx_out, dist_out, smem, ti, VideoArgs{});
+}
+
+// Spatio-temporal form: n_tiles covers the tiles of all frames.
+__global__ __launch_bounds__(BMT) void bm_video_kernel(ImageGeom g, MethodParams mp, int tiles_x, int n_tiles,
+                                                       VideoArgs va, BmLds L, int32_t *__restrict__ idx_out,
+                                                       int32_t *__restrict__ dist_out) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ TileInfo ti;
+    const int per = (n_tiles + 7) / 8;
+    const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (b >= n_tiles) return;
+    bm_tile<true>(g, mp, tiles_x, b, L, idx_out, dist_out, smem, ti, va);
 }
 
 // Persistent form over many images: each workgroup pulls (image, tile) units from a queue.
@@ -516,12 +604,12 @@ __global__ __launch_bounds__(BMT) void bm_kernel_batched(const BatchItem *__rest
         if (u >= total) break;
         const int i = find_unit(unit_start, n_items, u);
         const BatchItem it = items[i];
-        bm_tile(it.g, it.mp, it.bm_tiles_x, u - unit_start[i], L, it.idx, nullptr, smem, ti);
+        bm_tile<false>(it.g, it.mp, it.bm_tiles_x, u - unit_start[i], L, it.idx, nullptr, smem, ti, VideoArgs{});
         __syncthreads();
     }
 }
 
-BmLds bm_lds_layout(int uh_max, int uw_max) {
+BmLds bm_lds_layout(int uh_max, int uw_max, bool video = false) {
     BmLds L;
     L.rows = uh_max + PS - 1;
     L.pitch8 = ((uw_max + PS + 3) / 4) * 4 + 4;
@@ -545,6 +633,7 @@ BmLds bm_lds_layout(int uh_max, int uw_max) {
     const int rs_bytes = 2 * L.rows * uw_max * 4;  // row sums of the norm pass live in the table
     if (tab_bytes < rs_bytes) tab_bytes = rs_bytes;
     off += tab_bytes;
+    if (video) off += NREF * RUN_K * 8;   // the running lists of the video search
     L.total = off;
     return L;
 }
@@ -565,6 +654,29 @@ hipError_t launch_block_match(const ImageGeom &g, const MethodParams &mp, int32_
     // round the grid up to a multiple of 8 so the XCD remap is a bijection onto [0, 8*per)
     const int per = (n_tiles + 7) / 8;
     hipLaunchKernelGGL(bm_kernel, dim3(8 * per), dim3(BMT), L.total, st, g, mp, tiles_x, n_tiles, L, idx, dist);
+    return hipGetLastError();
+}
+
+// Spatio-temporal block matching of T frames of g.h rows stacked from g.img (Sec. IV-C): the
+// candidates of a reference in frame t are its clipped window in frames t - radius .. t + radius
+// (within [0, T)).  idx/dist: T * ny * nx references, frame-major; idx = (f*h + y)*w + x.
+hipError_t launch_block_match_video(const ImageGeom &g, const MethodParams &mp, int T, int radius, int32_t *idx,
+                                    int32_t *dist, hipStream_t st) {
+    const int tiles_y = (g.ny + REF_TILE - 1) / REF_TILE, tiles_x = (g.nx + REF_TILE - 1) / REF_TILE;
+    const int64_t n_tiles64 = (int64_t)tiles_y * tiles_x * T;
+    if (T < 1 || radius < 0 || radius > 31 || mp.K > RUN_K || n_tiles64 > (int64_t)1 << 30)
+        return hipErrorInvalidValue;
+    const int n_tiles = (int)n_tiles64;
+    const int span = (REF_TILE - 1) * g.s + mp.W;
+    const int uh = span < g.h - PS + 1 ? span : g.h - PS + 1;
+    const int uw = span < g.w - PS + 1 ? span : g.w - PS + 1;
+    BmLds L = bm_lds_layout(uh, uw, true);
+    hipError_t e = prepare_dynamic_lds((const void *)bm_video_kernel, L.total, (int)sizeof(TileInfo));
+    if (e != hipSuccess) return e;
+    VideoArgs va{T, radius, (int64_t)g.h * g.stride};
+    const int per = (n_tiles + 7) / 8;
+    hipLaunchKernelGGL(bm_video_kernel, dim3(8 * per), dim3(BMT), L.total, st, g, mp, tiles_x, n_tiles, va, L, idx,
+                       dist);
     return hipGetLastError();
 }
 

@@ -184,6 +184,8 @@ hipError_t prepare_dynamic_lds(const void *kernel, int bytes, int static_bytes);
 // Launchers (stream-ordered, no synchronisation).
 hipError_t launch_block_match(const ImageGeom &g, const MethodParams &mp, int32_t *idx, int32_t *dist,
                               hipStream_t st);
+hipError_t launch_block_match_video(const ImageGeom &g, const MethodParams &mp, int T, int radius, int32_t *idx,
+                                    int32_t *dist, hipStream_t st);
 hipError_t launch_fill_tau(double *tau_ref, int64_t n_ref, const double *sigma_tile, double sigma_const,
                            double mult, const ImageGeom &g, int tile, hipStream_t st);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);

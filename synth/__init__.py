@@ -136,6 +136,31 @@ def make_hsi(h: int, w: int, bands: int, seed: int, n_end: int = 4) -> np.ndarra
     return _quantise(255.0 * np.einsum("hwe,eb->hwb", ab, spec))
 
 
+def make_video(T: int, h: int, w: int, c: int, seed: int, step: int = 2) -> np.ndarray:
+    """Clean uint8 frames (T, h, w[, c]) of a scene in motion: a static background (make_clean of
+    a larger canvas, textured) seen through a window that pans by up to `step` pixels per frame
+    in each direction (a seeded random walk), with a textured object that moves on its own
+    path across it."""
+    rng = _rng(seed)
+    pad = step * T + 8
+    canvas = make_clean(h + 2 * pad, w + 2 * pad, c, seed, texture=True)
+    obj = make_clean(h // 3 + 8, w // 3 + 8, c, seed + 1, texture=True)
+    oy, ox = float(rng.uniform(0, h - obj.shape[0])), float(rng.uniform(0, w - obj.shape[1]))
+    vy, vx = rng.uniform(-1.5, 1.5, 2) * step
+    y, x = pad, pad
+    frames = []
+    for _ in range(T):
+        f = canvas[y:y + h, x:x + w].copy()
+        iy = int(np.clip(round(oy), 0, h - obj.shape[0]))
+        ix = int(np.clip(round(ox), 0, w - obj.shape[1]))
+        f[iy:iy + obj.shape[0], ix:ix + obj.shape[1]] = obj
+        frames.append(f)
+        y = int(np.clip(y + rng.integers(-step, step + 1), 0, 2 * pad))
+        x = int(np.clip(x + rng.integers(-step, step + 1), 0, 2 * pad))
+        oy, ox = oy + vy, ox + vx
+    return np.ascontiguousarray(np.stack(frames))
+
+
 def add_awgn(clean: np.ndarray, sigma: float, seed: int) -> np.ndarray:
     """clean + N(0, sigma^2) in float, rounded half-to-even and clipped to uint8."""
     rng = _rng(seed)

@@ -1,0 +1,145 @@
+"""Video (Sec. IV-C) on the GPU vs the FP64 oracle (needs an MI355X): the spatio-temporal groups
+bit-exact, and the denoised frames to the pixel parity bar."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import assert_pixel_parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dn():
+    import paper_2512_23569_amd as ht
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    d = ht.Denoiser(0, load_network=False)
+    yield d
+    d.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _tie_heavy_video(T, h, w, c, seed):
+    rng = np.random.default_rng(seed)
+    v = (rng.integers(0, 4, (T, h, w, c) if c == 3 else (T, h, w)) * 60).astype(np.uint8)
+    v[:, : h // 5] = 0
+    v[1] = v[0]                                   # equal distances in two frames
+    v[-1, 10:18, 12:20] = v[0, 3:11, 5:13]        # moved content
+    return v
+
+
+# (T, h, w, c, K, W, s, radius): ragged frame sizes, every group size, the widest window,
+# a radius beyond the video's length, a single frame
+CASES = [(3, 40, 48, 3, 16, 15, 4, 1), (5, 37, 45, 1, 8, 21, 3, 2), (2, 64, 72, 3, 32, 31, 4, 1),
+         (4, 33, 41, 3, 4, 9, 5, 3), (3, 30, 38, 1, 32, 13, 2, 5), (1, 48, 40, 3, 16, 15, 4, 2)]
+
+
+@pytest.mark.parametrize("T,h,w,c,K,W,s,radius", CASES)
+def test_video_groups_exact(dn, T, h, w, c, K, W, s, radius):
+    v = synth.add_awgn(synth.make_video(T, h, w, c, 100 + T + h), 25.0, 101 + w)
+    idx, dist = dn.block_match_video(_dev(v), dn.params(c, stride=s, window=W, K=K), radius)
+    torch.cuda.synchronize()
+    oi, od = oracle.block_match_video(v, 8, s, W, K, radius)
+    assert np.array_equal(dist.cpu().numpy(), od)
+    assert np.array_equal(idx.cpu().numpy(), oi)
+
+
+@pytest.mark.parametrize("c,radius", [(3, 1), (1, 2)])
+def test_video_groups_exact_with_ties(dn, c, radius):
+    v = _tie_heavy_video(4, 36, 44, c, 110 + c)
+    idx, dist = dn.block_match_video(_dev(v), dn.params(c, stride=3, window=13, K=16), radius)
+    torch.cuda.synchronize()
+    oi, od = oracle.block_match_video(v, 8, 3, 13, 16, radius)
+    assert np.array_equal(dist.cpu().numpy(), od)
+    assert np.array_equal(idx.cpu().numpy(), oi)
+
+
+def test_video_radius_zero_equals_the_image_matcher(dn):
+    v = synth.add_awgn(synth.make_video(3, 44, 52, 3, 120), 20.0, 121)
+    p = dn.params(3, stride=4, window=15, K=16)
+    iv, dv = dn.block_match_video(_dev(v), p, 0)
+    per = iv.shape[0] // 3
+    for t in range(3):
+        i, d = dn.block_match(_dev(v[t]), p)
+        torch.cuda.synchronize()
+        assert torch.equal(iv[t * per:(t + 1) * per], i + t * 44 * 52)
+        assert torch.equal(dv[t * per:(t + 1) * per], d)
+
+
+@pytest.mark.parametrize("T,h,w,c,K,W,radius,sigma", [(4, 48, 56, 3, 16, 15, 1, 30.0), (3, 40, 44, 1, 8, 13, 1, 25.0),
+                                                      (5, 36, 40, 3, 32, 13, 2, 40.0), (2, 41, 37, 3, 4, 9, 1, 15.0)])
+def test_video_denoise_parity(dn, T, h, w, c, K, W, radius, sigma):
+    clean = synth.make_video(T, h, w, c, 130 + T)
+    noisy = synth.add_awgn(clean, sigma, 131 + T)
+    U, V = oracle.load_basis(os.path.join(ROOT, "paper_2512_23569_amd", "data", "basis_ps8_c%d.f64" % c), 8, c)
+    idx, _ = oracle.block_match_video(noisy, 8, 4, W, K, radius)
+    tau = sigma * oracle.tau_multiplier(c, K)
+    stacked = noisy.reshape((T * h, w) + noisy.shape[3:])
+    ref = oracle.filter_groups(stacked, idx, U, V, tau).reshape(noisy.shape)
+    p = dn.params(c, stride=4, window=W, K=K)
+    gpu = dn.denoise_video(_dev(noisy), sigma, p, radius).cpu().numpy()
+    m = assert_pixel_parity(gpu, ref, clean)
+    print("video T=%d c=%d K=%d radius=%d sigma=%g" % (T, c, K, radius, sigma), m)
+    assert m["psnr_gpu"] > synth.psnr(clean, noisy) + 1.0   # small, textured clips: a modest gain
+
+
+def test_video_follows_the_installed_basis(dn):
+    """The filter's FP64 maps are rebuilt when the basis changes (here: learned from the video)."""
+    import paper_2512_23569_amd as ht
+    T, h, w, c, sigma = 3, 40, 48, 3, 30.0
+    clean = synth.make_video(T, h, w, c, 140)
+    noisy = synth.add_awgn(clean, sigma, 141)
+    p = dn.params(c, stride=4, window=13, K=16)
+    first = dn.denoise_video(_dev(noisy), sigma, p, 1).cpu().numpy()
+    stacked = noisy.reshape(T * h, w, c)
+    U, V = dn.learn_basis(_dev(stacked), stride=4)
+    second = dn.denoise_video(_dev(noisy), sigma, p, 1).cpu().numpy()
+    idx, _ = oracle.block_match_video(noisy, 8, 4, 13, 16, 1)
+    ref = oracle.filter_groups(stacked, idx, oracle.from_slices(U), oracle.from_slices(V),
+                               sigma * oracle.tau_multiplier(c, 16)).reshape(noisy.shape)
+    assert_pixel_parity(second, ref, clean)
+    assert np.abs(first - second).max() > 0.5
+    # the shipped basis again
+    Us, Vs = oracle.load_basis(os.path.join(ROOT, "paper_2512_23569_amd", "data", "basis_ps8_c3.f64"), 8, 3)
+    ht.htsvd_set_basis(dn.ctx, 8, 3, oracle.to_slices(Us), oracle.to_slices(Vs))
+    third = dn.denoise_video(_dev(noisy), sigma, p, 1).cpu().numpy()
+    assert np.array_equal(third, first)
+
+
+def test_video_passes_of_bounded_memory_give_the_same_output(dn):
+    import paper_2512_23569_amd as ht
+    noisy = synth.add_awgn(synth.make_video(3, 40, 48, 3, 150), 30.0, 151)
+    p = dn.params(3, stride=4, window=13, K=16)
+    one = dn.denoise_video(_dev(noisy), 30.0, p, 1)
+    ht.htsvd_set_band_memory(dn.ctx, 1 << 20)
+    try:
+        split = dn.denoise_video(_dev(noisy), 30.0, p, 1)
+    finally:
+        ht.htsvd_set_band_memory(dn.ctx, 4 << 30)
+    torch.cuda.synchronize()
+    assert torch.equal(one, split)
+
+
+def test_video_errors(dn):
+    import paper_2512_23569_amd as ht
+    v = _dev(synth.make_video(2, 32, 32, 3, 160))
+    p = dn.params(3, stride=4, window=13, K=16)
+    with pytest.raises(ht.HtsvdError):
+        dn.block_match_video(v, p, 32)                       # radius beyond 31
+    with pytest.raises(ht.HtsvdError):
+        dn.denoise_video(v, 30.0, p.replace(adaptive=1), 1)  # known sigma only
+    with pytest.raises(ht.HtsvdError):
+        dn.denoise_video(v, 30.0, p.replace(ra=1), 1)
+    with pytest.raises(ht.HtsvdError):
+        dn.denoise_video(v, -1.0, p, 1)
+    with pytest.raises(ht.HtsvdError):                       # window too small for K
+        dn.block_match_video(v, dn.params(3, stride=4, window=3, K=16), 1)
