@@ -50,7 +50,7 @@ def _L():
                                              i32]
         lib.orc_denoise.argtypes = [p, i32, i32, i32, i64, i32, i32, i32, i32, i32, i32, p, p, p, p, dbl, p,
                                     i32, i64, i64, p, p]
-        lib.orc_filter_groups.argtypes = [p, i32, i32, i32, i64, i32, i32, i64, p, p, p, p, p, i32]
+        lib.orc_filter_groups.argtypes = [p, i32, i32, i32, i64, i32, i32, i64, p, p, p, p, p, i32, p, p]
         lib.orc_block_match_video.argtypes = [p, i32, i32, i32, i32, i64, i32, i32, i32, i32, i32, i32, i32, p, p,
                                               i32]
         _lib = lib
@@ -222,9 +222,10 @@ def denoise(img: np.ndarray, U: np.ndarray, V: np.ndarray, tau, ps: int = 8, s: 
 
 
 def filter_groups(img: np.ndarray, idx: np.ndarray, U: np.ndarray, V: np.ndarray, tau, ps: int = 8,
-                  nthreads: int = 0) -> np.ndarray:
+                  nthreads: int = 0, pest=None, ra_on=None) -> np.ndarray:
     """Eq. 19-21 and uniform aggregation of the given groups idx (n_ref, K) of y*w + x, any channel
-    count (hyperspectral tube patches, Sec. IV-D).  U, V: (ps, ps, c).  Returns FP64 (h, w, c)."""
+    count (hyperspectral tube patches, Sec. IV-D; the stacked frames of a video, Sec. IV-C).
+    U, V: (ps, ps, c).  pest / ra_on: RA-Haar-tSVD as in denoise.  Returns FP64 (h, w, c)."""
     a = img if img.ndim == 3 else img[:, :, None]
     a = np.ascontiguousarray(a)
     h, w, c = a.shape
@@ -233,8 +234,14 @@ def filter_groups(img: np.ndarray, idx: np.ndarray, U: np.ndarray, V: np.ndarray
     tau_ref = np.ascontiguousarray(np.broadcast_to(np.asarray(tau, dtype=np.float64), (n_ref,)))
     u, v = to_slices(U), to_slices(V)
     out = np.zeros((h, w, c), dtype=np.float64)
+    pe = ro = None
+    if pest is not None:
+        pe = np.ascontiguousarray(np.asarray(pest, dtype=np.float64).reshape(n_ref, c * ps * ps))
+        ro = np.ascontiguousarray(np.broadcast_to(np.asarray(True if ra_on is None else ra_on, dtype=np.uint8),
+                                                  (n_ref,)))
     _check(_L().orc_filter_groups(_ptr(a), h, w, c, w * c, ps, K, n_ref, _ptr(ix), _ptr(tau_ref), _ptr(u), _ptr(v),
-                                  _ptr(out), nthreads))
+                                  _ptr(out), nthreads, None if pe is None else _ptr(pe),
+                                  None if ro is None else _ptr(ro)))
     return out
 
 

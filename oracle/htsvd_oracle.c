@@ -646,7 +646,7 @@ int orc_block_match_video(const uint8_t *frames, int T, int h, int w, int c, int
  * input value). */
 int orc_filter_groups(const uint8_t *img, int h, int w, int c, int64_t stride, int ps, int K, int64_t n_ref,
                       const int32_t *idx, const double *tau_ref, const double *U, const double *V, double *out,
-                      int nthreads)
+                      int nthreads, const double *pest, const uint8_t *ra_on)
 {
     if (c < 1 || ps < 1 || K < 1 || (K & (K - 1)) || h < ps || w < ps || stride < (int64_t)w * c) return ORC_EINVAL;
     for (int64_t q = 0; q < n_ref * K; ++q) {
@@ -700,7 +700,15 @@ int orc_filter_groups(const uint8_t *img, int h, int w, int c, int64_t stride, i
                     for (int k = 0; k < K; ++k) acc += H[a * K + k] * S[(size_t)k * P + q];
                     Sh[(size_t)a * P + q] = acc;
                 }
-            for (int64_t q = 0; q < (int64_t)K * P; ++q)
+            /* RA-Haar-tSVD (Eq. 24-25), as in orc_denoise: a refined mean p_est gives the first
+             * Haar row sqrt(K) U^T * p_est * V, kept without threshold. */
+            int64_t q_first = 0;
+            if (pest && ra_on && ra_on[r]) {
+                patch_forward(&basis, pest + (size_t)r * P, S, work);
+                for (int q = 0; q < P; ++q) Sh[q] = sqrt((double)K) * S[q];
+                q_first = P;
+            }
+            for (int64_t q = q_first; q < (int64_t)K * P; ++q)
                 if (!(fabs(Sh[q]) >= tau_ref[r])) Sh[q] = 0.0;
             for (int k = 0; k < K; ++k)
                 for (int q = 0; q < P; ++q) {

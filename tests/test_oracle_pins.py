@@ -327,6 +327,34 @@ def test_filter_groups_matches_denoise_and_reconstructs():
     assert np.allclose(oracle.filter_groups(cube, idx7, U7, V7, 0.0), cube.astype(np.float64), atol=1e-9)
 
 
+def test_filter_groups_ra_matches_denoise_and_aggregates_refined_means():
+    """RA-Haar-tSVD in the groups filter (used for the spatio-temporal groups of a video): with the
+    denoiser's groups it is the RA denoiser; at an infinite threshold every member becomes the
+    refined mean of its group (only the first Haar row survives, Eq. 24), so the output is the
+    average of the refined means over the patches covering each pixel."""
+    rng = np.random.default_rng(12)
+    img = synth.add_awgn(synth.make_clean(32, 36, 3, 13), 40.0, 14)
+    U, V = oracle.load_basis(os.path.join(os.path.dirname(GOLD), "..", "paper_2512_23569_amd", "data",
+                                          "basis_ps8_c3.f64"), 8, 3)
+    idx, _ = oracle.block_match(img, 8, 4, 13, 8)
+    n = len(idx)
+    pest = rng.uniform(0, 255, (n, 3, 8, 8))
+    on = rng.integers(0, 2, n).astype(bool)
+    a = oracle.denoise(img, U, V, 90.0, s=4, W=13, K=8, pest=pest, ra_on=on)
+    b = oracle.filter_groups(img, idx, U, V, 90.0, pest=pest, ra_on=on)
+    assert np.allclose(a, b, atol=1e-9)
+    out = oracle.filter_groups(img, idx, U, V, np.inf, pest=pest)
+    h, w = img.shape[:2]
+    num, cnt = np.zeros((h, w, 3)), np.zeros((h, w))
+    for r in range(n):
+        for q in idx[r]:
+            y, x = divmod(int(q), w)
+            num[y:y + 8, x:x + 8] += pest[r].transpose(1, 2, 0)
+            cnt[y:y + 8, x:x + 8] += 1
+    want = np.where(cnt[..., None] > 0, num / np.maximum(cnt, 1)[..., None], img)
+    assert np.allclose(out, want, atol=1e-9)
+
+
 def test_band_guide_rounds_half_up():
     rng = np.random.default_rng(31)
     cube = rng.integers(0, 256, (5, 6, 9)).astype(np.uint8)
