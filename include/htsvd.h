@@ -181,12 +181,16 @@ htsvd_status htsvd_denoise_bands(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h,
 htsvd_status htsvd_block_match_video(htsvd_ctx *ctx, const uint8_t *d_in, int32_t T, int32_t h, int32_t w,
                                      int32_t c, int64_t in_stride, int32_t radius, const htsvd_params *p,
                                      int32_t *d_idx, int32_t *d_dist, void *stream);
-/* Denoises the frames with a known sigma: the spatio-temporal groups are filtered with the
- * global t-SVD basis of c channels and the Haar transform (Eq. 19-21, in FP64), tau = sigma *
- * (p->tau_mult, or sqrt(2 ln(c K ps^2))), and aggregated uniformly over the stacked frames
- * (Algorithm 1) into d_out (float32, T*h rows of out_stride elements).  The filter's patch
- * matrices follow htsvd_set_band_memory.  Errors: HTSVD_ESTATE (no basis for c),
- * HTSVD_ENOTSUP (adaptive or ra set), the others as above. */
+/* Denoises the frames: the spatio-temporal groups are filtered with the global t-SVD basis of c
+ * channels and the Haar transform (Eq. 19-21; the matrix-core transform of htsvd_denoise,
+ * coefficients near the threshold re-decided in FP64) and aggregated uniformly over the stacked
+ * frames (Algorithm 1) into d_out (float32, T*h rows of out_stride elements).  The threshold is
+ * tau = sigma_hat * (p->tau_mult, or sqrt(2 ln(c K ps^2))), with sigma_hat set frame by frame
+ * (Sec. IV-C) as htsvd_denoise sets it for one image: the known sigma; or HTSVD_SIGMA_AUTO, the
+ * frame's per-sub-image estimate (p->estimator); and p->adaptive = 1 adjusts either by the vote
+ * over the frame's spatial groups (Eq. 22-23).  p->ra = 1 refines the spatio-temporal groups'
+ * mean patches as htsvd_denoise does (Sec. III-E-2).  Errors: HTSVD_ESTATE (no basis for c, or
+ * no network for ra or the learned estimator), the others as above. */
 htsvd_status htsvd_denoise_video(htsvd_ctx *ctx, const uint8_t *d_in, int32_t T, int32_t h, int32_t w, int32_t c,
                                  int64_t in_stride, int32_t radius, float sigma, const htsvd_params *p, float *d_out,
                                  int64_t out_stride, void *stream);

@@ -77,9 +77,6 @@ struct htsvd_ctx {
     int bands = 0;                          // band count of the hyperspectral basis (0: none)
     double *d_band_maps = nullptr;          // its D, Dinv and slice maps (FP64)
     int64_t band_cap = (int64_t)4 << 30;    // bytes per patch matrix of one pass of the band filter
-    std::vector<double> basis_uv[2];        // host copies of the colour/gray basis (U then V)
-    double *d_video_maps[2] = {nullptr, nullptr};   // its t-product maps for the video filter (FP64)
-    uint64_t video_gen[2] = {0, 0};         // basis generation the video maps were built from
     // Optional per-stage timing with HIP events recorded on the call's stream.
     bool timing = false;
     hipEvent_t ev[2 * HTSVD_N_STAGES] = {};
@@ -571,23 +568,6 @@ htsvd_status set_basis_bands(htsvd_ctx *ctx, int B, const double *h_U, const dou
     return HTSVD_OK;
 }
 
-// t-product maps of the colour/gray basis for the video filter, rebuilt when the basis changed.
-htsvd_status video_maps(htsvd_ctx *ctx, int c, BandMaps *bm) {
-    const int slot = c == 3;
-    if (!ctx->d_video_maps[slot] || ctx->video_gen[slot] != ctx->basis_gen[slot]) {
-        const std::vector<double> &uv = ctx->basis_uv[slot];
-        std::vector<double> maps;
-        htsvd_status s = build_band_maps(c, uv.data(), uv.data() + 64 * c, maps);
-        if (s != HTSVD_OK) return s;
-        if ((s = upload_maps(ctx, maps, &ctx->d_video_maps[slot])) != HTSVD_OK) return s;
-        ctx->video_gen[slot] = ctx->basis_gen[slot];
-    }
-    bm->D = ctx->d_video_maps[slot];
-    bm->Dinv = bm->D + c * c;
-    bm->M = bm->Dinv + c * c;
-    return HTSVD_OK;
-}
-
 // Rebuilds the network's operand tables from the master weights when they changed (and the
 // folded last layer when the weights or the basis changed).  Host work; synchronises the device.
 htsvd_status ra_prepare(htsvd_ctx *ctx, int c, bool folded) {
@@ -770,8 +750,6 @@ void htsvd_destroy(htsvd_ctx *ctx) {
     if (ctx->d_guard) (void)hipFree(ctx->d_guard);
     if (ctx->d_gram) (void)hipFree(ctx->d_gram);
     if (ctx->d_band_maps) (void)hipFree(ctx->d_band_maps);
-    for (int i = 0; i < 2; ++i)
-        if (ctx->d_video_maps[i]) (void)hipFree(ctx->d_video_maps[i]);
     for (int i = 0; i < 2; ++i) {
         RaState &r = ctx->ra[i];
         for (void *q : {(void *)r.w, (void *)r.m, (void *)r.v, (void *)r.grad, (void *)r.frag, (void *)r.frag3t,
@@ -976,8 +954,6 @@ htsvd_status htsvd_set_basis(htsvd_ctx *ctx, int32_t ps, int32_t c, const double
         return hip_fail(e, "basis upload");
     ctx->has_basis[slot] = true;
     ctx->T64h[slot] = T;
-    ctx->basis_uv[slot].assign(h_U, h_U + 64 * c);
-    ctx->basis_uv[slot].insert(ctx->basis_uv[slot].end(), h_V, h_V + 64 * c);
     ++ctx->basis_gen[slot];
     return HTSVD_OK;
 }
@@ -2084,15 +2060,30 @@ htsvd_status htsvd_denoise_video(htsvd_ctx *ctx, const uint8_t *d_in, int32_t T,
     if (s != HTSVD_OK) return s;
     if (!d_out) return fail(HTSVD_EINVAL, "null output");
     if (out_stride < (int64_t)w * c) return fail(HTSVD_EINVAL, "out_stride < w*c");
-    if (!(sigma > 0.f) || !std::isfinite(sigma)) return fail(HTSVD_EINVAL, "sigma must be > 0");
-    if (p->adaptive || p->ra) return fail(HTSVD_ENOTSUP, "the video path takes a known sigma, no vote or refinement");
-    BandMaps bm;
-    if ((s = video_maps(ctx, c, &bm)) != HTSVD_OK) return s;
-    const int64_t n_ref = (int64_t)T * g.ny * g.nx;
-    const int H = T * h;   // rows of the stacked frames
-    const size_t off_ws = align256(sizeof(int32_t) * n_ref * mp.K);
-    if ((s = ensure_ws(ctx, off_ws + band_ws_bytes(H, w, c, mp.K, n_ref, ctx->band_cap))) != HTSVD_OK) return s;
-    int32_t *idx = (int32_t *)ctx->ws;
+    if (!(sigma > 0.f) && sigma != HTSVD_SIGMA_AUTO) return fail(HTSVD_EINVAL, "sigma must be > 0 or AUTO");
+    if (!std::isfinite(sigma)) return fail(HTSVD_EINVAL, "sigma must be finite");
+    if (p->estimator != 0 && p->estimator != 1) return fail(HTSVD_EINVAL, "estimator must be 0 or 1");
+    const bool learned = sigma == HTSVD_SIGMA_AUTO && p->estimator == 1;
+    // thresholds from each frame's own noise estimate (and vote), as for one image
+    const bool per_frame = !(sigma > 0.f && !p->adaptive);
+    const int tile = p->subimage;
+    // The stacked frames as one image whose reference grid is T*ny x nx (frame-major).
+    ImageGeom gv = g;
+    gv.h = T * h;
+    gv.ny = T * g.ny;
+    const int64_t n_frame = (int64_t)g.ny * g.nx, n_ref = (int64_t)gv.ny * gv.nx, npx = (int64_t)gv.h * w;
+    const size_t off_tau = align256(sizeof(int32_t) * n_ref * mp.K);
+    const size_t off_acc = off_tau + align256(sizeof(double) * n_ref);
+    const size_t off_hist = off_acc + align256(sizeof(unsigned long long) * npx * c);
+    const size_t off_ra = off_hist + align256(sizeof(int) * npx);
+    const size_t off_frame = off_ra + (p->ra ? align256(ra_ws_bytes(gv)) : 0);
+    const size_t frame_ws = per_frame ? plan_ws(nullptr, g, mp.W, mp.K, tile).total : 0;
+    if ((s = ensure_ws(ctx, off_frame + frame_ws)) != HTSVD_OK) return s;
+    char *ws = (char *)ctx->ws;
+    int32_t *idx = (int32_t *)ws;
+    double *tau = (double *)(ws + off_tau);
+    unsigned long long *gacc = (unsigned long long *)(ws + off_acc);
+    int *ghist = (int *)(ws + off_hist);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     {
@@ -2101,10 +2092,46 @@ htsvd_status htsvd_denoise_video(htsvd_ctx *ctx, const uint8_t *d_in, int32_t T,
             return hip_fail(e, "spatio-temporal block matching");
     }
     const double mult = p->tau_mult > 0.0 ? p->tau_mult : default_mult(c, mp.K);
+    if (!per_frame) {
+        if ((e = launch_fill_tau(tau, n_ref, nullptr, (double)sigma, mult, gv, tile, st)) != hipSuccess)
+            return hip_fail(e, "tau");
+    } else {
+        // frame by frame: the noise estimate of the frame's sub-images, adjusted by the vote over
+        // the frame's own (spatial) groups, gives the thresholds of its references
+        for (int t = 0; t < T; ++t) {
+            ImageGeom gt = g;
+            gt.img = d_in + (int64_t)t * h * in_stride;
+            Ws wt = plan_ws(ws + off_frame, gt, mp.W, mp.K, tile);
+            const float *zmap = nullptr;
+            if (learned && (s = run_cnn_map(ctx, gt, st, &zmap)) != HTSVD_OK) return s;
+            if ((s = run_bm(ctx, gt, mp, wt, st)) != HTSVD_OK) return s;
+            if ((s = run_sigma(ctx, gt, mp, p, sigma, wt, zmap, st)) != HTSVD_OK) return s;
+            if (learned)
+                e = launch_fill_tau_learned(tau + t * n_frame, gt, tile, zmap, wt.use_plain, wt.sig_est, wt.sig_hat,
+                                            mult, st);
+            else
+                e = launch_fill_tau(tau + t * n_frame, n_frame, wt.sig_hat, 0.0, mult, gt, tile, st);
+            if (e != hipSuccess) return hip_fail(e, "tau");
+        }
+    }
+    const float *ra_d = nullptr;
+    const uint8_t *ra_f = nullptr;
+    if (p->ra) {
+        Ws wv{};
+        wv.idx = idx;
+        if ((s = run_ra(ctx, gv, mp, wv, tau, ws + off_ra, mult, p->ra_sigma, st, &ra_d, &ra_f)) != HTSVD_OK) return s;
+    }
+    {
+        StageScope sc(ctx, HTSVD_STAGE_CLEAR, st);
+        if ((e = launch_zero(ctx->d_guard, 2 * sizeof(unsigned long long), st)) != hipSuccess ||
+            (e = launch_zero(gacc, sizeof(unsigned long long) * npx * c, st)) != hipSuccess ||
+            (e = launch_zero(ghist, sizeof(int) * npx, st)) != hipSuccess)
+            return hip_fail(e, "zero accumulators");
+    }
     {
         StageScope sc(ctx, HTSVD_STAGE_FILTER, st);
-        if ((e = launch_band_filter(bm, d_in, in_stride, H, w, c, idx, n_ref, mp.K, (double)sigma * mult,
-                                    ctx->band_cap, (char *)ctx->ws + off_ws, d_out, out_stride, st)) != hipSuccess)
+        if ((e = launch_filter_mfma_global(gv, mp.K, ctx->basis[c == 3], idx, tau, gacc, ghist, ctx->d_guard, d_out,
+                                           out_stride, st, ra_d, ra_f)) != hipSuccess)
             return hip_fail(e, "video filter");
     }
     return HTSVD_OK;

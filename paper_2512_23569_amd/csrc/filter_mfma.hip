@@ -21,7 +21,9 @@
 //             matrix with three products (hi.hi + hi.lo + lo.hi); R, G, B follow as above.
 //   Algorithm 1: every reconstructed patch is added (sums and a count) into an LDS copy of the
 //             image region the tile's groups reach; the region goes to the tile's slot of a
-//             global buffer and the gather kernel divides.
+//             global buffer and the gather kernel divides.  Groups whose members lie anywhere
+//             (the spatio-temporal groups of a video) add into global 64-bit fixed-point sums
+//             instead, with a histogram of patch positions for the counts.
 //
 // c = 1 uses the single 64 x 64 map and no channel DFT.
 #include "common.h"
@@ -162,6 +164,10 @@ __device__ inline int to_fixed(float v, float scale) {
     return __float_as_int(t) - __float_as_int(MAGIC);
 }
 
+// Fixed-point shift of the global aggregation: the largest with |v| 2^FS <= 2^22 (to_fixed);
+// the 64-bit sums cannot overflow.
+constexpr int GA_FS = 12;
+
 // 2^e for a small integer exponent (exact).
 __device__ inline float exp2i(int e) { return __int_as_float((e + 127) << 23); }
 
@@ -178,7 +184,9 @@ __device__ inline v8h ldfrag0(const v8h *FL0, int dir, int term, int pair, int l
 //   FL0: LDS copy of the slice-0 fragments (the 64 x 64 map, both directions); FG: the whole
 //   tables (forward at dir 0, inverse at dir 1), read through the caches for the other slices.
 //   The eight wavefronts of a workgroup share both and the tile's LDS region.
-template <int C, int K, bool RA = false>
+//   GA: global aggregation into gacc[pix*C + ch] (units of 2^-GA_FS) and ghist[pix] (patches by
+//   top-left pixel); the tile then only schedules references, and region is unused.
+template <int C, int K, bool RA = false, bool GA = false>
 __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileGeom &tg, const v8h *FL0,
                                                  const v8h *__restrict__ FG, const double *__restrict__ T64,
                                                  const int32_t *__restrict__ idx, const int idx_stride,
@@ -187,7 +195,9 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                                                  unsigned long long *__restrict__ guard_count, const int tile,
                                                  float *region, uint32_t *xbuf_all, MfmaShared &sh,
                                                  const float *__restrict__ ra_d = nullptr,
-                                                 const uint8_t *__restrict__ ra_flag = nullptr) {
+                                                 const uint8_t *__restrict__ ra_flag = nullptr,
+                                                 unsigned long long *__restrict__ gacc = nullptr,
+                                                 int *__restrict__ ghist = nullptr) {
     constexpr int P = 64 * C;
     constexpr int CH = C + 1;
     constexpr int NT = 2 * C;            // 32-column tiles of the 64C coefficients
@@ -203,15 +213,17 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
     // channel sums in units of 2^-FS, then patches by top-left pixel, which become the count.
     int *iregion = reinterpret_cast<int *>(region);
     int *hist = iregion + C * plane;
-    const float fscale = (float)(1 << tg.FS);
-    if (tid == 0) {
-        int r0, r1, c0, c1;
-        region_rows(g, tg, ty, &r0, &r1);
-        region_cols(g, tg, tx, &c0, &c1);
-        sh.r0 = r0;
-        sh.c0 = c0;
+    const float fscale = (float)(1 << (GA ? GA_FS : tg.FS));
+    if constexpr (!GA) {
+        if (tid == 0) {
+            int r0, r1, c0, c1;
+            region_rows(g, tg, ty, &r0, &r1);
+            region_cols(g, tg, tx, &c0, &c1);
+            sh.r0 = r0;
+            sh.c0 = c0;
+        }
+        for (int e = tid; e < relems; e += MW * 64) iregion[e] = 0;
     }
-    for (int e = tid; e < relems; e += MW * 64) iregion[e] = 0;
     __syncthreads();
     const int r0 = sh.r0, c0 = sh.c0;
     const uint8_t *img_end = g.img + (int64_t)(g.h - 1) * g.stride + (int64_t)g.w * C;
@@ -220,7 +232,8 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
     const int nref = ny_t * nx_t;
 
     // pixel of patch position 32 tq + c held by this lane in the output layout
-    const int lane_off[2] = {(c32 >> 3) * tg.RP + (c32 & 7), (4 + (c32 >> 3)) * tg.RP + (c32 & 7)};
+    const int rp = GA ? g.w : tg.RP;   // row pitch of the aggregation target
+    const int lane_off[2] = {(c32 >> 3) * rp + (c32 & 7), (4 + (c32 >> 3)) * rp + (c32 & 7)};
     // MFMA row rho = lane % 32 holds group member mu_in of this step's 32 patches
     const int rho = c32;
     const int mu_in = 16 * ((rho >> 2) & 1) + 4 * (rho >> 3) + (rho & 3);
@@ -238,8 +251,13 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             const int64_t r_in = ref_of(mu_in / K);
             const int32_t lin_in = idx[r_in * idx_stride + (mu_in % K)];
             const int yin = lin_in / g.w, xin = lin_in % g.w;
-            off_in = (yin - r0) * tg.RP + (xin - c0);
-            if (h == 0 && (full || base + mu_in / K < nref)) atomicAdd(hist + off_in, 1);
+            if constexpr (GA) {
+                off_in = lin_in;
+                if (h == 0 && (full || base + mu_in / K < nref)) atomicAdd(ghist + lin_in, 1);
+            } else {
+                off_in = (yin - r0) * tg.RP + (xin - c0);
+                if (h == 0 && (full || base + mu_in / K < nref)) atomicAdd(hist + off_in, 1);
+            }
             const uint8_t *pin = g.img + (int64_t)yin * g.stride + (int64_t)xin * C;
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp) load_row_u8<C>(pin + (int64_t)(2 * sp + h) * g.stride, img_end, raw[sp]);
@@ -594,6 +612,22 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             if (!full && base + gi >= nref) continue;
 #pragma unroll
             for (int tq = 0; tq < 2; ++tq) {
+                if constexpr (GA) {
+                    unsigned long long *dst = gacc + (int64_t)(off + lane_off[tq]) * C;
+                    auto add = [&](int ch, float v) {
+                        atomicAdd(dst + ch, (unsigned long long)(long long)to_fixed(v, fscale));
+                    };
+                    if (C == 3) {
+                        const float p0 = out[tq][r], pr = out[2 + tq][r], pi = out[4 + tq][r];
+                        const float t0 = p0 - pr;
+                        add(0, p0 + 2.f * pr);
+                        add(1, t0 - pi);
+                        add(2, t0 + pi);
+                    } else {
+                        add(0, out[tq][r]);
+                    }
+                    continue;
+                }
                 int *dst = iregion + off + lane_off[tq];
                 if (C == 3) {
                     const float p0 = out[tq][r], pr = out[2 + tq][r], pi = out[4 + tq][r];
@@ -607,6 +641,7 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             }
         }
     }
+    if constexpr (GA) return;   // the caller's barrier follows
     __syncthreads();
     // coverage count of every pixel: 8 x 8 box sum of the patch histogram (separable, in place,
     // one row then one column per thread; prev[] holds the histogram values leaving the window)
@@ -679,6 +714,58 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_kernel(ImageGeom g, TileG
                                    sh, ra_d, ra_flag);
         __syncthreads();
     }
+}
+
+// Groups anywhere in the image (video): tiles of the reference grid only schedule the work;
+// LDS holds the slice-0 fragments and the transpose buffers, no region.
+template <int C, int K, bool RA>
+__global__ __launch_bounds__(MW * 64) void filter_mfma_ga_kernel(ImageGeom g, TileGeom tg, const v8h *__restrict__ F,
+                                                                const double *__restrict__ T64,
+                                                                const int32_t *__restrict__ idx,
+                                                                const double *__restrict__ tau_ref,
+                                                                unsigned long long *__restrict__ gacc,
+                                                                int *__restrict__ ghist,
+                                                                unsigned long long *__restrict__ guard_count,
+                                                                const float *__restrict__ ra_d,
+                                                                const uint8_t *__restrict__ ra_flag) {
+    extern __shared__ __align__(16) float smem[];
+    __shared__ MfmaShared sh;
+    v8h *FL0 = reinterpret_cast<v8h *>(smem);
+    for (int e = threadIdx.x; e < F0_BYTES / 16; e += MW * 64) {
+        const int dt = e / (F0_PAIRS * 64), pl = e % (F0_PAIRS * 64);
+        FL0[e] = F[(dt * Frag<C>::NPAIR) * 64 + pl];
+    }
+    __syncthreads();
+    uint32_t *xb = reinterpret_cast<uint32_t *>(smem + F0_BYTES / 4);
+    const int n_tiles = tg.tiles_y * tg.tiles_x;
+    const int per = (n_tiles + 7) / 8;   // XCD-aware order, as in filter_mfma_kernel
+    for (int v = blockIdx.x; v < 8 * per; v += gridDim.x) {
+        const int tile = (v & 7) * per + (v >> 3);
+        if (tile >= n_tiles) continue;
+        filter_tile_mfma<C, K, RA, true>(g, tg, FL0, F, T64, idx, K, tau_ref, 1.0, nullptr, guard_count, tile,
+                                         nullptr, xb, sh, ra_d, ra_flag, gacc, ghist);
+        __syncthreads();
+    }
+}
+
+// out = sum / (count 2^GA_FS), count = 8 x 8 box sum of the patch histogram; the noisy value
+// where no patch landed.
+template <int C>
+__global__ void ga_normalize_kernel(const unsigned long long *__restrict__ gacc, const int *__restrict__ ghist,
+                                    const uint8_t *__restrict__ img, int64_t stride, int h, int w,
+                                    float *__restrict__ out, int64_t out_stride) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)h * w) return;
+    const int y = (int)(e / w), x = (int)(e % w);
+    int n = 0;
+    for (int dy = 0; dy < PS && dy <= y; ++dy)
+        for (int dx = 0; dx < PS && dx <= x; ++dx) n += ghist[(int64_t)(y - dy) * w + (x - dx)];
+    float *o = out + (int64_t)y * out_stride + (int64_t)x * C;
+    const uint8_t *px = img + (int64_t)y * stride + (int64_t)x * C;
+    const double inv = n > 0 ? 1.0 / ((double)n * (double)(1 << GA_FS)) : 0.0;
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch)
+        o[ch] = n > 0 ? (float)((double)(long long)gacc[e * C + ch] * inv) : (float)px[ch];
 }
 
 template <int C, int K>
@@ -773,6 +860,58 @@ hipError_t launch_filter_mfma(const ImageGeom &g, const TileGeom &tg, int K, con
     HM_CASE(3, 4) HM_CASE(3, 8) HM_CASE(3, 16) HM_CASE(3, 32)
 #undef HM_CASE
     return hipErrorInvalidValue;
+}
+
+template <int C, int K, bool RA>
+static hipError_t launch_mfma_ga_t(const ImageGeom &g, const TileGeom &tg, const BasisDev &b, const int32_t *idx,
+                                   const double *tau_ref, unsigned long long *gacc, int *ghist, unsigned long long *gc,
+                                   const float *ra_d, const uint8_t *ra_flag, hipStream_t st) {
+    const int n_tiles = tg.tiles_y * tg.tiles_x;
+    const int lds = filter_mfma_group_bytes(C);
+    hipError_t e = prepare_dynamic_lds((const void *)filter_mfma_ga_kernel<C, K, RA>, lds, (int)sizeof(MfmaShared));
+    if (e != hipSuccess) return e;
+    int dev = 0, n_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (n_cu < 8) n_cu = 8;
+    const int per = (n_tiles + 7) / 8;
+    const int grid = min(8 * per, (n_cu / 8) * 8);
+    hipLaunchKernelGGL((filter_mfma_ga_kernel<C, K, RA>), dim3(grid), dim3(MW * 64), lds, st, g, tg,
+                       (const v8h *)b.frag, b.T64, idx, tau_ref, gacc, ghist, gc, ra_d, ra_flag);
+    return hipGetLastError();
+}
+
+// Filtering of groups whose members lie anywhere in the image (video: frames stacked vertically,
+// the reference grid T*ny x nx): global aggregation, then the normalisation.  gacc (h*w*C u64)
+// and ghist (h*w int32) must be zero on entry.
+hipError_t launch_filter_mfma_global(const ImageGeom &g, int K, const BasisDev &b, const int32_t *idx,
+                                     const double *tau_ref, unsigned long long *gacc, int *ghist,
+                                     unsigned long long *gc, float *out, int64_t out_stride, hipStream_t st,
+                                     const float *ra_d, const uint8_t *ra_flag) {
+    if (!b.frag) return hipErrorInvalidValue;
+    TileGeom tg{};
+    tg.TY = tg.TX = 8;   // 64 references per scheduling unit
+    tg.tiles_y = (g.ny + tg.TY - 1) / tg.TY;
+    tg.tiles_x = (g.nx + tg.TX - 1) / tg.TX;
+    tg.FS = GA_FS;
+    hipError_t e = hipErrorInvalidValue;
+#define HG_CASE(CC, KK)                                                                                          \
+    if (g.c == CC && K == KK)                                                                                    \
+        e = ra_d ? launch_mfma_ga_t<CC, KK, true>(g, tg, b, idx, tau_ref, gacc, ghist, gc, ra_d, ra_flag, st)     \
+                 : launch_mfma_ga_t<CC, KK, false>(g, tg, b, idx, tau_ref, gacc, ghist, gc, nullptr, nullptr, st);
+    HG_CASE(1, 4) HG_CASE(1, 8) HG_CASE(1, 16) HG_CASE(1, 32)
+    HG_CASE(3, 4) HG_CASE(3, 8) HG_CASE(3, 16) HG_CASE(3, 32)
+#undef HG_CASE
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)g.h * g.w;
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    if (g.c == 3)
+        hipLaunchKernelGGL(ga_normalize_kernel<3>, dim3(grid), dim3(256), 0, st, gacc, ghist, g.img, g.stride, g.h,
+                           g.w, out, out_stride);
+    else
+        hipLaunchKernelGGL(ga_normalize_kernel<1>, dim3(grid), dim3(256), 0, st, gacc, ghist, g.img, g.stride, g.h,
+                           g.w, out, out_stride);
+    return hipGetLastError();
 }
 
 template <int C, int K>

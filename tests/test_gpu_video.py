@@ -8,6 +8,7 @@ import pytest
 import oracle
 import synth
 from helpers import assert_pixel_parity
+from oracle import fcn
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -115,18 +116,95 @@ def test_video_follows_the_installed_basis(dn):
     assert np.array_equal(third, first)
 
 
-def test_video_passes_of_bounded_memory_give_the_same_output(dn):
-    import paper_2512_23569_amd as ht
-    noisy = synth.add_awgn(synth.make_video(3, 40, 48, 3, 150), 30.0, 151)
+def test_video_radius_zero_matches_the_image_denoiser(dn):
+    """Radius 0 groups each frame alone, so every frame is the image denoiser's output up to the
+    rounding of the two aggregations (fixed point at 2^-12 here, 2^-9 or finer per tile there)."""
+    T, h, w = 3, 44, 52
+    noisy = synth.add_awgn(synth.make_video(T, h, w, 3, 150), 30.0, 151)
     p = dn.params(3, stride=4, window=13, K=16)
-    one = dn.denoise_video(_dev(noisy), 30.0, p, 1)
-    ht.htsvd_set_band_memory(dn.ctx, 1 << 20)
+    vid = dn.denoise_video(_dev(noisy), 30.0, p, 0).cpu().numpy()
+    for t in range(T):
+        img = dn.denoise(_dev(noisy[t]), 30.0, p).cpu().numpy()
+        assert np.abs(vid[t] - img).max() <= 4e-3
+
+
+def _ra_weights(c, seed):
+    p = fcn.init_params(c, seed) * 0.3
+    rng = np.random.default_rng(seed + 100)
+    p = p + rng.normal(0, 0.01, p.size) * (p != 0)
+    o = 0
+    for sh in fcn.shapes(c):
+        n = int(np.prod(sh))
+        if len(sh) == 1:
+            p[o:o + n] = rng.normal(0, 0.05, n)
+        o += n
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("c,K,sigma,radius", [(3, 16, 50.0, 1), (1, 8, 45.0, 2), (3, 32, 60.0, 1)])
+def test_video_ra_parity(dn, c, K, sigma, radius):
+    """RA-Haar-tSVD on the spatio-temporal groups: oracle groups, oracle mean patches, the FP64
+    network and the FP64 groups filter with the refined first Haar row."""
+    import paper_2512_23569_amd as ht
+    wts = _ra_weights(c, 30 + K)
+    ht.htsvd_ra_set_weights(dn.ctx, c, wts)
+    T, h, w = 3, 40, 48
+    clean = synth.make_video(T, h, w, c, 160 + K)
+    noisy = synth.add_awgn(clean, sigma, 161 + K)
+    stacked = noisy.reshape((T * h, w) + noisy.shape[3:])
+    U, V = oracle.load_basis(os.path.join(ROOT, "paper_2512_23569_amd", "data", "basis_ps8_c%d.f64" % c), 8, c)
+    idx, _ = oracle.block_match_video(noisy, 8, 4, 13, K, radius)
+    pest = fcn.refine(wts.astype(np.float64), fcn.group_means(stacked, idx).reshape(len(idx), -1), c)
+    tau = sigma * oracle.tau_multiplier(c, K)
+    ref = oracle.filter_groups(stacked, idx, U, V, tau, pest=pest).reshape(noisy.shape)
+    p = dn.params(c, stride=4, window=13, K=K, ra=1)
+    gpu = dn.denoise_video(_dev(noisy), sigma, p, radius).cpu().numpy()
+    m = assert_pixel_parity(gpu, ref, clean)
+    plain = oracle.filter_groups(stacked, idx, U, V, tau).reshape(noisy.shape)
+    print("video RA c=%d K=%d sigma=%g" % (c, K, sigma), m, "mean |RA - plain| %.3f" % np.abs(ref - plain).mean())
+    assert np.abs(ref - plain).mean() > 0.1
+
+
+@pytest.mark.parametrize("c,sigma,known", [(3, 40.0, False), (1, 30.0, True)])
+def test_video_adaptive_parity(dn, c, sigma, known):
+    """A-Haar-tSVD frame by frame (Sec. IV-C): each frame's sub-image noise estimate (or the known
+    sigma) adjusted by the vote over the frame's spatial groups (Eq. 22-23) sets the thresholds of
+    its references; the spatio-temporal groups are filtered with them."""
+    from oracle import estimator as est
+    T, h, w, K, W, s, radius = 3, 136, 160, 16, 15, 4, 1
+    clean = synth.make_video(T, h, w, c, 170 + c)
+    noisy = synth.add_awgn(clean, sigma, 171 + c)
+    p = dn.params(c, stride=s, window=W, K=K, adaptive=1)
+    gpu = dn.denoise_video(_dev(noisy), sigma if known else -1.0, p, radius).cpu().numpy()
+    U, V = oracle.load_basis(os.path.join(ROOT, "paper_2512_23569_amd", "data", "basis_ps8_c%d.f64" % c), 8, c)
+    taus = []
+    for t in range(T):
+        it, _ = oracle.block_match(noisy[t], 8, s, W, K)
+        start = np.full(4, sigma) if known else est.sigma_est_tiles(noisy[t])
+        sig = est.sigma_hat_tiles(noisy[t], it, start, 8, s)
+        taus.append(est.tau_per_ref(sig, h, w, 8, s, c, K))
+    idx, _ = oracle.block_match_video(noisy, 8, s, W, K, radius)
+    stacked = noisy.reshape((T * h, w) + noisy.shape[3:])
+    ref = oracle.filter_groups(stacked, idx, U, V, np.concatenate(taus)).reshape(noisy.shape)
+    m = assert_pixel_parity(gpu, ref, clean)
+    print("video adaptive c=%d sigma=%g known=%s" % (c, sigma, known), m)
+
+
+def test_video_learned_estimator_frame_by_frame():
+    """The learned noise estimator runs frame by frame: at radius 0 every frame is the image
+    denoiser's output with the same estimator (up to the aggregations' rounding)."""
+    import paper_2512_23569_amd as ht
+    d = ht.Denoiser(0)
     try:
-        split = dn.denoise_video(_dev(noisy), 30.0, p, 1)
+        T, h, w = 2, 136, 152
+        noisy = synth.add_awgn(synth.make_video(T, h, w, 3, 180), 35.0, 181)
+        p = d.params(3, stride=4, window=15, K=16, estimator=1, adaptive=1)
+        vid = d.denoise_video(_dev(noisy), ht.HTSVD_SIGMA_AUTO, p, 0).cpu().numpy()
+        for t in range(T):
+            img = d.denoise(_dev(noisy[t]), ht.HTSVD_SIGMA_AUTO, p).cpu().numpy()
+            assert np.abs(vid[t] - img).max() <= 4e-3
     finally:
-        ht.htsvd_set_band_memory(dn.ctx, 4 << 30)
-    torch.cuda.synchronize()
-    assert torch.equal(one, split)
+        d.close()
 
 
 def test_video_errors(dn):
@@ -136,10 +214,14 @@ def test_video_errors(dn):
     with pytest.raises(ht.HtsvdError):
         dn.block_match_video(v, p, 32)                       # radius beyond 31
     with pytest.raises(ht.HtsvdError):
-        dn.denoise_video(v, 30.0, p.replace(adaptive=1), 1)  # known sigma only
+        dn.denoise_video(v, 30.0, p.replace(estimator=2), 1)  # no such estimator
+    d2 = ht.Denoiser(0, load_network=False)
+    try:
+        with pytest.raises(ht.HtsvdError):                   # refinement without a network
+            d2.denoise_video(v, 50.0, p.replace(ra=1), 1)
+    finally:
+        d2.close()
     with pytest.raises(ht.HtsvdError):
-        dn.denoise_video(v, 30.0, p.replace(ra=1), 1)
-    with pytest.raises(ht.HtsvdError):
-        dn.denoise_video(v, -1.0, p, 1)
+        dn.denoise_video(v, -2.0, p, 1)                      # neither a sigma nor AUTO
     with pytest.raises(ht.HtsvdError):                       # window too small for K
         dn.block_match_video(v, dn.params(3, stride=4, window=3, K=16), 1)
