@@ -2130,8 +2130,8 @@ htsvd_status htsvd_denoise_video(htsvd_ctx *ctx, const uint8_t *d_in, int32_t T,
     }
     {
         StageScope sc(ctx, HTSVD_STAGE_FILTER, st);
-        if ((e = launch_filter_mfma_global(gv, mp.K, ctx->basis[c == 3], idx, tau, gacc, ghist, ctx->d_guard, d_out,
-                                           out_stride, st, ra_d, ra_f)) != hipSuccess)
+        if ((e = launch_filter_mfma_global(gv, T, radius, mp.W, mp.K, ctx->basis[c == 3], idx, tau, gacc, ghist,
+                                           ctx->d_guard, d_out, out_stride, st, ra_d, ra_f)) != hipSuccess)
             return hip_fail(e, "video filter");
     }
     return HTSVD_OK;

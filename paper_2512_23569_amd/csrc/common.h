@@ -226,10 +226,11 @@ int filter_mfma_static_bytes();
 hipError_t launch_filter_mfma(const ImageGeom &g, const TileGeom &tg, int K, const BasisDev &b, const int32_t *idx,
                               const double *tau_ref, float *regions, unsigned long long *gc, hipStream_t st,
                               const float *ra_d = nullptr, const uint8_t *ra_flag = nullptr);
-hipError_t launch_filter_mfma_global(const ImageGeom &g, int K, const BasisDev &b, const int32_t *idx,
-                                     const double *tau_ref, unsigned long long *gacc, int *ghist,
+hipError_t launch_filter_mfma_global(const ImageGeom &g, int T, int radius, int W, int K, const BasisDev &b,
+                                     const int32_t *idx, const double *tau_ref, unsigned long long *gacc, int *ghist,
                                      unsigned long long *gc, float *out, int64_t out_stride, hipStream_t st,
-                                     const float *ra_d = nullptr, const uint8_t *ra_flag = nullptr);
+                                     const float *ra_d = nullptr, const uint8_t *ra_flag = nullptr,
+                                     bool force_direct = false);
 hipError_t launch_filter_mfma_batched(int C, int K, const BatchItem *items, int n_items, const int *unit_start,
                                       int lds, const BasisDev &b, unsigned long long *gc, int *queue, int grid,
                                       hipStream_t st);

@@ -164,9 +164,20 @@ __device__ inline int to_fixed(float v, float scale) {
     return __float_as_int(t) - __float_as_int(MAGIC);
 }
 
-// Fixed-point shift of the global aggregation: the largest with |v| 2^FS <= 2^22 (to_fixed);
-// the 64-bit sums cannot overflow.
-constexpr int GA_FS = 12;
+// Fixed-point shift of the global aggregation.  Its 64-bit sums cannot overflow; the int32
+// slot regions of a tile receive at most TY TX K <= 16 * 32 contributions per pixel, each of
+// |v| <= 1024, so 2^11 keeps them below 2^30.
+constexpr int GA_FS = 11;
+constexpr int GA_MAX_TILE = 4;   // largest tile side of the slot regions
+
+// Geometry of a video for the global aggregation: frames of h_frame rows stacked vertically,
+// ny_frame reference rows each; with slot regions (GA == 2) a tile's references lie in one
+// frame t and its LDS region holds, per channel, the frames f_lo .. f_lo + nslot - 1 (f_lo =
+// max(0, t - radius)) as nslot blocks of RH x RP int32 (columns RW used).
+struct VideoTiling {
+    int T = 1, h_frame = 0, ny_frame = 0, radius = 0, nslot = 1;
+    int RH = 0, RW = 0, RP = 0;
+};
 
 // 2^e for a small integer exponent (exact).
 __device__ inline float exp2i(int e) { return __int_as_float((e + 127) << 23); }
@@ -185,8 +196,10 @@ __device__ inline v8h ldfrag0(const v8h *FL0, int dir, int term, int pair, int l
 //   tables (forward at dir 0, inverse at dir 1), read through the caches for the other slices.
 //   The eight wavefronts of a workgroup share both and the tile's LDS region.
 //   GA: global aggregation into gacc[pix*C + ch] (units of 2^-GA_FS) and ghist[pix] (patches by
-//   top-left pixel); the tile then only schedules references, and region is unused.
-template <int C, int K, bool RA = false, bool GA = false>
+//   top-left pixel).  GA == 1: every contribution goes to gacc, the tile only schedules
+//   references and region is unused; GA == 2: the tile (references of one frame) adds into its
+//   LDS slot region first, whose nonzero sums then go to gacc.
+template <int C, int K, bool RA = false, int GA = 0>
 __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileGeom &tg, const v8h *FL0,
                                                  const v8h *__restrict__ FG, const double *__restrict__ T64,
                                                  const int32_t *__restrict__ idx, const int idx_stride,
@@ -197,7 +210,8 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                                                  const float *__restrict__ ra_d = nullptr,
                                                  const uint8_t *__restrict__ ra_flag = nullptr,
                                                  unsigned long long *__restrict__ gacc = nullptr,
-                                                 int *__restrict__ ghist = nullptr) {
+                                                 int *__restrict__ ghist = nullptr,
+                                                 const VideoTiling &vt = VideoTiling{}) {
     constexpr int P = 64 * C;
     constexpr int CH = C + 1;
     constexpr int NT = 2 * C;            // 32-column tiles of the 64C coefficients
@@ -214,6 +228,23 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
     int *iregion = reinterpret_cast<int *>(region);
     int *hist = iregion + C * plane;
     const float fscale = (float)(1 << (GA ? GA_FS : tg.FS));
+    // references of the tile: rows iy0 .. iy0 + ny_t - 1 of the grid; with slot regions the
+    // tiles are cut per frame (frame t_v, its reference rows from iyl0)
+    int iy0 = ty * tg.TY, ny_t = min(tg.TY, g.ny - iy0);
+    int t_v = 0, f_lo = 0;
+    if constexpr (GA == 2) {
+        const int tyf = (vt.ny_frame + tg.TY - 1) / tg.TY;
+        t_v = ty / tyf;
+        const int iyl0 = (ty - t_v * tyf) * tg.TY;
+        iy0 = t_v * vt.ny_frame + iyl0;
+        ny_t = min(tg.TY, vt.ny_frame - iyl0);
+        f_lo = max(0, t_v - vt.radius);
+        if (tid == 0) {
+            sh.r0 = max(0, ref_pos(iyl0, vt.ny_frame, vt.h_frame, g.s) - tg.R);
+            sh.c0 = max(0, ref_pos(tx * tg.TX, g.nx, g.w, g.s) - tg.R);
+        }
+        for (int e = tid; e < C * plane; e += MW * 64) iregion[e] = 0;
+    }
     if constexpr (!GA) {
         if (tid == 0) {
             int r0, r1, c0, c1;
@@ -227,12 +258,12 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
     __syncthreads();
     const int r0 = sh.r0, c0 = sh.c0;
     const uint8_t *img_end = g.img + (int64_t)(g.h - 1) * g.stride + (int64_t)g.w * C;
-    const int iy0 = ty * tg.TY, ix0 = tx * tg.TX;
-    const int ny_t = min(tg.TY, g.ny - iy0), nx_t = min(tg.TX, g.nx - ix0);
+    const int ix0 = tx * tg.TX;
+    const int nx_t = min(tg.TX, g.nx - ix0);
     const int nref = ny_t * nx_t;
 
     // pixel of patch position 32 tq + c held by this lane in the output layout
-    const int rp = GA ? g.w : tg.RP;   // row pitch of the aggregation target
+    const int rp = GA == 1 ? g.w : tg.RP;   // row pitch of the aggregation target
     const int lane_off[2] = {(c32 >> 3) * rp + (c32 & 7), (4 + (c32 >> 3)) * rp + (c32 & 7)};
     // MFMA row rho = lane % 32 holds group member mu_in of this step's 32 patches
     const int rho = c32;
@@ -251,8 +282,12 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             const int64_t r_in = ref_of(mu_in / K);
             const int32_t lin_in = idx[r_in * idx_stride + (mu_in % K)];
             const int yin = lin_in / g.w, xin = lin_in % g.w;
-            if constexpr (GA) {
+            if constexpr (GA == 1) {
                 off_in = lin_in;
+                if (h == 0 && (full || base + mu_in / K < nref)) atomicAdd(ghist + lin_in, 1);
+            } else if constexpr (GA == 2) {
+                const int f = yin / vt.h_frame;   // stacked row -> frame, slot and row in the frame
+                off_in = ((f - f_lo) * vt.RH + (yin - f * vt.h_frame - r0)) * tg.RP + (xin - c0);
                 if (h == 0 && (full || base + mu_in / K < nref)) atomicAdd(ghist + lin_in, 1);
             } else {
                 off_in = (yin - r0) * tg.RP + (xin - c0);
@@ -612,7 +647,7 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             if (!full && base + gi >= nref) continue;
 #pragma unroll
             for (int tq = 0; tq < 2; ++tq) {
-                if constexpr (GA) {
+                if constexpr (GA == 1) {
                     unsigned long long *dst = gacc + (int64_t)(off + lane_off[tq]) * C;
                     auto add = [&](int ch, float v) {
                         atomicAdd(dst + ch, (unsigned long long)(long long)to_fixed(v, fscale));
@@ -641,7 +676,22 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
             }
         }
     }
-    if constexpr (GA) return;   // the caller's barrier follows
+    if constexpr (GA == 1) return;   // the caller's barrier follows
+    if constexpr (GA == 2) {
+        // nonzero sums of the slot region to the global sums (zero adds nothing)
+        __syncthreads();
+        const int slot_elems = vt.RH * tg.RP;
+        for (int e = tid; e < C * plane; e += MW * 64) {
+            const int v = iregion[e];
+            if (v == 0) continue;
+            const int ch = e / plane, q = e - ch * plane;
+            const int slot = q / slot_elems, rq = q - slot * slot_elems;
+            const int row = rq / tg.RP, col = rq - row * tg.RP;
+            const int64_t pix = ((int64_t)(f_lo + slot) * vt.h_frame + r0 + row) * g.w + c0 + col;
+            atomicAdd(gacc + pix * C + ch, (unsigned long long)(long long)v);
+        }
+        return;   // the caller's barrier follows
+    }
     __syncthreads();
     // coverage count of every pixel: 8 x 8 box sum of the patch histogram (separable, in place,
     // one row then one column per thread; prev[] holds the histogram values leaving the window)
@@ -716,10 +766,12 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_kernel(ImageGeom g, TileG
     }
 }
 
-// Groups anywhere in the image (video): tiles of the reference grid only schedule the work;
-// LDS holds the slice-0 fragments and the transpose buffers, no region.
-template <int C, int K, bool RA>
-__global__ __launch_bounds__(MW * 64) void filter_mfma_ga_kernel(ImageGeom g, TileGeom tg, const v8h *__restrict__ F,
+// Groups anywhere in the image (video), global aggregation: GA == 1 the tiles only schedule the
+// work (LDS: the slice-0 fragments and the transpose buffers); GA == 2 each tile also has its
+// slot region after them.
+template <int C, int K, bool RA, int GA>
+__global__ __launch_bounds__(MW * 64) void filter_mfma_ga_kernel(ImageGeom g, TileGeom tg, VideoTiling vt,
+                                                                const v8h *__restrict__ F,
                                                                 const double *__restrict__ T64,
                                                                 const int32_t *__restrict__ idx,
                                                                 const double *__restrict__ tau_ref,
@@ -737,13 +789,14 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_ga_kernel(ImageGeom g, Ti
     }
     __syncthreads();
     uint32_t *xb = reinterpret_cast<uint32_t *>(smem + F0_BYTES / 4);
+    float *region = GA == 2 ? reinterpret_cast<float *>(xb + MW * XWORDS) : nullptr;
     const int n_tiles = tg.tiles_y * tg.tiles_x;
     const int per = (n_tiles + 7) / 8;   // XCD-aware order, as in filter_mfma_kernel
     for (int v = blockIdx.x; v < 8 * per; v += gridDim.x) {
         const int tile = (v & 7) * per + (v >> 3);
         if (tile >= n_tiles) continue;
-        filter_tile_mfma<C, K, RA, true>(g, tg, FL0, F, T64, idx, K, tau_ref, 1.0, nullptr, guard_count, tile,
-                                         nullptr, xb, sh, ra_d, ra_flag, gacc, ghist);
+        filter_tile_mfma<C, K, RA, GA>(g, tg, FL0, F, T64, idx, K, tau_ref, 1.0, nullptr, guard_count, tile,
+                                       region, xb, sh, ra_d, ra_flag, gacc, ghist, vt);
         __syncthreads();
     }
 }
@@ -862,13 +915,13 @@ hipError_t launch_filter_mfma(const ImageGeom &g, const TileGeom &tg, int K, con
     return hipErrorInvalidValue;
 }
 
-template <int C, int K, bool RA>
-static hipError_t launch_mfma_ga_t(const ImageGeom &g, const TileGeom &tg, const BasisDev &b, const int32_t *idx,
-                                   const double *tau_ref, unsigned long long *gacc, int *ghist, unsigned long long *gc,
-                                   const float *ra_d, const uint8_t *ra_flag, hipStream_t st) {
+template <int C, int K, bool RA, int GA>
+static hipError_t launch_mfma_ga_t(const ImageGeom &g, const TileGeom &tg, const VideoTiling &vt, int lds,
+                                   const BasisDev &b, const int32_t *idx, const double *tau_ref,
+                                   unsigned long long *gacc, int *ghist, unsigned long long *gc, const float *ra_d,
+                                   const uint8_t *ra_flag, hipStream_t st) {
     const int n_tiles = tg.tiles_y * tg.tiles_x;
-    const int lds = filter_mfma_group_bytes(C);
-    hipError_t e = prepare_dynamic_lds((const void *)filter_mfma_ga_kernel<C, K, RA>, lds, (int)sizeof(MfmaShared));
+    hipError_t e = prepare_dynamic_lds((const void *)filter_mfma_ga_kernel<C, K, RA, GA>, lds, (int)sizeof(MfmaShared));
     if (e != hipSuccess) return e;
     int dev = 0, n_cu = 0;
     (void)hipGetDevice(&dev);
@@ -876,29 +929,76 @@ static hipError_t launch_mfma_ga_t(const ImageGeom &g, const TileGeom &tg, const
     if (n_cu < 8) n_cu = 8;
     const int per = (n_tiles + 7) / 8;
     const int grid = min(8 * per, (n_cu / 8) * 8);
-    hipLaunchKernelGGL((filter_mfma_ga_kernel<C, K, RA>), dim3(grid), dim3(MW * 64), lds, st, g, tg,
+    hipLaunchKernelGGL((filter_mfma_ga_kernel<C, K, RA, GA>), dim3(grid), dim3(MW * 64), lds, st, g, tg, vt,
                        (const v8h *)b.frag, b.T64, idx, tau_ref, gacc, ghist, gc, ra_d, ra_flag);
     return hipGetLastError();
 }
 
-// Filtering of groups whose members lie anywhere in the image (video: frames stacked vertically,
-// the reference grid T*ny x nx): global aggregation, then the normalisation.  gacc (h*w*C u64)
-// and ghist (h*w int32) must be zero on entry.
-hipError_t launch_filter_mfma_global(const ImageGeom &g, int K, const BasisDev &b, const int32_t *idx,
-                                     const double *tau_ref, unsigned long long *gacc, int *ghist,
+// Tiling of the video filter: the largest tile side (<= GA_MAX_TILE) whose slot region fits in
+// LDS beside the fragments and transpose buffers; 0 when none does (direct global aggregation).
+static int video_tile_side(int C, int h_frame, int w, int s, int W, int nslot, VideoTiling *vt) {
+    const int R = (W - 1) / 2;
+    for (int side = GA_MAX_TILE; side >= 1; --side) {
+        const int RH = min((side - 1) * s + 2 * R + PS, h_frame), RW = min((side - 1) * s + 2 * R + PS, w);
+        const int RP = RW + ((8 - RW % 16) + 16) % 16;   // pitch % 16 == 8, as for the image regions
+        const int bytes = filter_mfma_group_bytes(C) + C * nslot * RH * RP * 4;
+        if (bytes <= filter_lds_budget()) {
+            vt->RH = RH;
+            vt->RW = RW;
+            vt->RP = RP;
+            return side;
+        }
+    }
+    return 0;
+}
+
+// Filtering of groups whose members lie anywhere in the frames of a video (T frames of g.h / T
+// rows stacked vertically, reference grid T*ny x nx frame-major, members within `radius` frames
+// of their reference's): global aggregation, then the normalisation.  gacc (h*w*C u64) and
+// ghist (h*w int32) must be zero on entry.  force_direct skips the slot regions.
+hipError_t launch_filter_mfma_global(const ImageGeom &g, int T, int radius, int W, int K, const BasisDev &b,
+                                     const int32_t *idx, const double *tau_ref, unsigned long long *gacc, int *ghist,
                                      unsigned long long *gc, float *out, int64_t out_stride, hipStream_t st,
-                                     const float *ra_d, const uint8_t *ra_flag) {
-    if (!b.frag) return hipErrorInvalidValue;
+                                     const float *ra_d, const uint8_t *ra_flag, bool force_direct) {
+    if (!b.frag || T < 1 || g.h % T || g.ny % T) return hipErrorInvalidValue;
+    VideoTiling vt;
+    vt.T = T;
+    vt.h_frame = g.h / T;
+    vt.ny_frame = g.ny / T;
+    vt.radius = radius;
+    vt.nslot = min(2 * radius + 1, T);
+    const int side = force_direct ? 0 : video_tile_side(g.c, vt.h_frame, g.w, g.s, W, vt.nslot, &vt);
     TileGeom tg{};
-    tg.TY = tg.TX = 8;   // 64 references per scheduling unit
-    tg.tiles_y = (g.ny + tg.TY - 1) / tg.TY;
-    tg.tiles_x = (g.nx + tg.TX - 1) / tg.TX;
+    tg.R = (W - 1) / 2;
     tg.FS = GA_FS;
+    int lds = filter_mfma_group_bytes(g.c);
+    if (side > 0) {   // frame-aligned tiles with slot regions
+        tg.TY = tg.TX = side;
+        tg.tiles_y = T * ((vt.ny_frame + side - 1) / side);
+        tg.tiles_x = (g.nx + side - 1) / side;
+        tg.RH = vt.nslot * vt.RH;   // one plane per channel: the slots stacked
+        tg.RW = vt.RW;
+        tg.RP = vt.RP;
+        lds += g.c * region_plane(tg) * 4;
+    } else {          // direct: 8 x 8 references of the stacked grid per scheduling unit
+        tg.TY = tg.TX = 8;
+        tg.tiles_y = (g.ny + tg.TY - 1) / tg.TY;
+        tg.tiles_x = (g.nx + tg.TX - 1) / tg.TX;
+    }
     hipError_t e = hipErrorInvalidValue;
 #define HG_CASE(CC, KK)                                                                                          \
-    if (g.c == CC && K == KK)                                                                                    \
-        e = ra_d ? launch_mfma_ga_t<CC, KK, true>(g, tg, b, idx, tau_ref, gacc, ghist, gc, ra_d, ra_flag, st)     \
-                 : launch_mfma_ga_t<CC, KK, false>(g, tg, b, idx, tau_ref, gacc, ghist, gc, nullptr, nullptr, st);
+    if (g.c == CC && K == KK) {                                                                                  \
+        if (side > 0)                                                                                            \
+            e = ra_d ? launch_mfma_ga_t<CC, KK, true, 2>(g, tg, vt, lds, b, idx, tau_ref, gacc, ghist, gc, ra_d,  \
+                                                          ra_flag, st)                                           \
+                     : launch_mfma_ga_t<CC, KK, false, 2>(g, tg, vt, lds, b, idx, tau_ref, gacc, ghist, gc,       \
+                                                           nullptr, nullptr, st);                                \
+        else                                                                                                     \
+            e = ra_d ? launch_mfma_ga_t<CC, KK, true, 1>(g, tg, vt, lds, b, idx, tau_ref, gacc, ghist, gc, ra_d,  \
+                                                          ra_flag, st)                                           \
+                     : launch_mfma_ga_t<CC, KK, false, 1>(g, tg, vt, lds, b, idx, tau_ref, gacc, ghist, gc,       \
+                                                           nullptr, nullptr, st);                                \
+    }
     HG_CASE(1, 4) HG_CASE(1, 8) HG_CASE(1, 16) HG_CASE(1, 32)
     HG_CASE(3, 4) HG_CASE(3, 8) HG_CASE(3, 16) HG_CASE(3, 32)
 #undef HG_CASE

@@ -76,8 +76,13 @@ def test_video_radius_zero_equals_the_image_matcher(dn):
         assert torch.equal(dv[t * per:(t + 1) * per], d)
 
 
+# The filter adds each tile's patches into LDS regions of the frames a tile can reach (tile side 4,
+# 3 with a wider window and radius) and falls back to direct global sums when they do not fit
+# (11 frames within radius 5 at window 31).
 @pytest.mark.parametrize("T,h,w,c,K,W,radius,sigma", [(4, 48, 56, 3, 16, 15, 1, 30.0), (3, 40, 44, 1, 8, 13, 1, 25.0),
-                                                      (5, 36, 40, 3, 32, 13, 2, 40.0), (2, 41, 37, 3, 4, 9, 1, 15.0)])
+                                                      (5, 36, 40, 3, 32, 13, 2, 40.0), (2, 41, 37, 3, 4, 9, 1, 15.0),
+                                                      (5, 44, 52, 3, 16, 21, 2, 30.0), (11, 40, 48, 3, 32, 31, 5, 35.0),
+                                                      (6, 38, 46, 1, 16, 31, 5, 25.0)])
 def test_video_denoise_parity(dn, T, h, w, c, K, W, radius, sigma):
     clean = synth.make_video(T, h, w, c, 130 + T)
     noisy = synth.add_awgn(clean, sigma, 131 + T)
