@@ -43,6 +43,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_mfma_12mp_traffic.json")
 FILTER_SRC = os.path.join(ROOT, "paper_2512_23569_amd", "csrc", "filter_mfma.hip")
 PEAK_F16_MFMA_TFLOPS = 2500.0    # MI355X dense fp16 matrix peak
 GRAM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_kernel_12mp_traffic.json")
+VIDEO_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_mfma_ga_video_7x1080p_traffic.json")
 GRAM_SRC = os.path.join(ROOT, "paper_2512_23569_amd", "csrc", "basis_learn.hip")
 
 
@@ -604,7 +605,8 @@ def bench_video(args):
         "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]},
         "roofline": {"bound": "alu", "kernel": "filter_mfma_ga_kernel<3,32> and its normalisation (filter stage)",
                      "achieved": round(tf, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(tf / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None, "kernel_ms": round(f_avg, 4),
+                     "frac": round(tf / PEAK_FP32_VECTOR_TFLOPS, 4),
+                     "traffic": measured_traffic(n_ref, VIDEO_TRAFFIC_FILE), "kernel_ms": round(f_avg, 4),
                      "flop_per_launch": fl,
                      "mfma": {"dtype": "f16", "executed_tflops": round(mf_tf, 3), "peak": PEAK_F16_MFMA_TFLOPS,
                               "frac": round(mf_tf / PEAK_F16_MFMA_TFLOPS, 4)}},
