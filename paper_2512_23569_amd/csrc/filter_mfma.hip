@@ -164,11 +164,13 @@ __device__ inline int to_fixed(float v, float scale) {
     return __float_as_int(t) - __float_as_int(MAGIC);
 }
 
-// Fixed-point shift of the global aggregation.  Its 64-bit sums cannot overflow; the int32
-// slot regions of a tile receive at most TY TX K <= 16 * 32 contributions per pixel, each of
-// |v| <= 1024, so 2^11 keeps them below 2^30.
-constexpr int GA_FS = 11;
-constexpr int GA_MAX_TILE = 4;   // largest tile side of the slot regions
+// Fixed-point shift of the global aggregation.  Its 64-bit sums cannot overflow; the int32 slot
+// regions of a tile receive at most TY TX K contributions per pixel (one per member of each of
+// the tile's groups), each of |v| <= 1024, so a tiling uses the largest shift <= GA_FS that
+// keeps TY TX K 1024 2^FS below 2^31, and only tilings with a shift of at least GA_MIN_FS.
+constexpr int GA_FS = 12;
+constexpr int GA_MIN_FS = 9;
+constexpr int GA_MAX_TILE = 8;   // largest tile side of the slot regions
 
 // Geometry of a video for the global aggregation: frames of h_frame rows stacked vertically,
 // ny_frame reference rows each; with slot regions (GA == 2) a tile's references lie in one
@@ -195,7 +197,7 @@ __device__ inline v8h ldfrag0(const v8h *FL0, int dir, int term, int pair, int l
 //   FL0: LDS copy of the slice-0 fragments (the 64 x 64 map, both directions); FG: the whole
 //   tables (forward at dir 0, inverse at dir 1), read through the caches for the other slices.
 //   The eight wavefronts of a workgroup share both and the tile's LDS region.
-//   GA: global aggregation into gacc[pix*C + ch] (units of 2^-GA_FS) and ghist[pix] (patches by
+//   GA: global aggregation into gacc[pix*C + ch] (units of 2^-tg.FS) and ghist[pix] (patches by
 //   top-left pixel).  GA == 1: every contribution goes to gacc, the tile only schedules
 //   references and region is unused; GA == 2: the tile (references of one frame) adds into its
 //   LDS slot region first, whose nonzero sums then go to gacc.
@@ -227,7 +229,7 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
     // channel sums in units of 2^-FS, then patches by top-left pixel, which become the count.
     int *iregion = reinterpret_cast<int *>(region);
     int *hist = iregion + C * plane;
-    const float fscale = (float)(1 << (GA ? GA_FS : tg.FS));
+    const float fscale = (float)(1 << tg.FS);
     // references of the tile: rows iy0 .. iy0 + ny_t - 1 of the grid; with slot regions the
     // tiles are cut per frame (frame t_v, its reference rows from iyl0)
     int iy0 = ty * tg.TY, ny_t = min(tg.TY, g.ny - iy0);
@@ -801,11 +803,11 @@ __global__ __launch_bounds__(MW * 64) void filter_mfma_ga_kernel(ImageGeom g, Ti
     }
 }
 
-// out = sum / (count 2^GA_FS), count = 8 x 8 box sum of the patch histogram; the noisy value
+// out = sum / (count 2^fs), count = 8 x 8 box sum of the patch histogram; the noisy value
 // where no patch landed.
 template <int C>
 __global__ void ga_normalize_kernel(const unsigned long long *__restrict__ gacc, const int *__restrict__ ghist,
-                                    const uint8_t *__restrict__ img, int64_t stride, int h, int w,
+                                    const uint8_t *__restrict__ img, int64_t stride, int h, int w, int fs,
                                     float *__restrict__ out, int64_t out_stride) {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= (int64_t)h * w) return;
@@ -815,7 +817,7 @@ __global__ void ga_normalize_kernel(const unsigned long long *__restrict__ gacc,
         for (int dx = 0; dx < PS && dx <= x; ++dx) n += ghist[(int64_t)(y - dy) * w + (x - dx)];
     float *o = out + (int64_t)y * out_stride + (int64_t)x * C;
     const uint8_t *px = img + (int64_t)y * stride + (int64_t)x * C;
-    const double inv = n > 0 ? 1.0 / ((double)n * (double)(1 << GA_FS)) : 0.0;
+    const double inv = n > 0 ? 1.0 / ((double)n * (double)(1 << fs)) : 0.0;
 #pragma unroll
     for (int ch = 0; ch < C; ++ch)
         o[ch] = n > 0 ? (float)((double)(long long)gacc[e * C + ch] * inv) : (float)px[ch];
@@ -934,11 +936,20 @@ static hipError_t launch_mfma_ga_t(const ImageGeom &g, const TileGeom &tg, const
     return hipGetLastError();
 }
 
-// Tiling of the video filter: the largest tile side (<= GA_MAX_TILE) whose slot region fits in
-// LDS beside the fragments and transpose buffers; 0 when none does (direct global aggregation).
-static int video_tile_side(int C, int h_frame, int w, int s, int W, int nslot, VideoTiling *vt) {
+// Largest fixed-point shift (<= GA_FS) for slot regions of side x side references of K members.
+static int ga_shift(int side, int K) {
+    int fs = GA_FS;
+    while (fs > 0 && (double)side * side * K * 1024.0 * (double)(1 << fs) >= 2147483647.0) --fs;
+    return fs;
+}
+
+// Tiling of the video filter: the largest tile side (<= GA_MAX_TILE) whose fixed-point shift is
+// at least GA_MIN_FS and whose slot region fits in LDS beside the fragments and transpose
+// buffers; 0 when none does (direct global aggregation).
+static int video_tile_side(int C, int K, int h_frame, int w, int s, int W, int nslot, VideoTiling *vt) {
     const int R = (W - 1) / 2;
     for (int side = GA_MAX_TILE; side >= 1; --side) {
+        if (ga_shift(side, K) < GA_MIN_FS) continue;
         const int RH = min((side - 1) * s + 2 * R + PS, h_frame), RW = min((side - 1) * s + 2 * R + PS, w);
         const int RP = RW + ((8 - RW % 16) + 16) % 16;   // pitch % 16 == 8, as for the image regions
         const int bytes = filter_mfma_group_bytes(C) + C * nslot * RH * RP * 4;
@@ -967,10 +978,10 @@ hipError_t launch_filter_mfma_global(const ImageGeom &g, int T, int radius, int 
     vt.ny_frame = g.ny / T;
     vt.radius = radius;
     vt.nslot = min(2 * radius + 1, T);
-    const int side = force_direct ? 0 : video_tile_side(g.c, vt.h_frame, g.w, g.s, W, vt.nslot, &vt);
+    const int side = force_direct ? 0 : video_tile_side(g.c, K, vt.h_frame, g.w, g.s, W, vt.nslot, &vt);
     TileGeom tg{};
     tg.R = (W - 1) / 2;
-    tg.FS = GA_FS;
+    tg.FS = side > 0 ? ga_shift(side, K) : GA_FS;
     int lds = filter_mfma_group_bytes(g.c);
     if (side > 0) {   // frame-aligned tiles with slot regions
         tg.TY = tg.TX = side;
@@ -1007,10 +1018,10 @@ hipError_t launch_filter_mfma_global(const ImageGeom &g, int T, int radius, int 
     const unsigned grid = (unsigned)((n + 255) / 256);
     if (g.c == 3)
         hipLaunchKernelGGL(ga_normalize_kernel<3>, dim3(grid), dim3(256), 0, st, gacc, ghist, g.img, g.stride, g.h,
-                           g.w, out, out_stride);
+                           g.w, tg.FS, out, out_stride);
     else
         hipLaunchKernelGGL(ga_normalize_kernel<1>, dim3(grid), dim3(256), 0, st, gacc, ghist, g.img, g.stride, g.h,
-                           g.w, out, out_stride);
+                           g.w, tg.FS, out, out_stride);
     return hipGetLastError();
 }
 
