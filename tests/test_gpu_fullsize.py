@@ -12,6 +12,11 @@ cannot process 12 MP within a test, so it checks what it can compute exactly:
   - denoised pixels of row bands: the oracle processes every reference whose groups can reach
     the band (reference rows within R + ps - 1 of it), so the band's pixels are complete sums;
     the pixel parity bar (>= 99.99% within 1e-2, |dPSNR| <= 0.01 dB) applies to each band.
+
+The video workload the benchmark times (7 frames of 1080 x 1920 RGB, AWGN sigma 30, temporal
+radius 1, stride 4, window 15, K 32) is checked the same way: all spatio-temporal groups
+bit-exact (the oracle matches the whole clip in seconds), and row bands of three frames (top,
+middle, bottom) denoised by the oracle from every group with a member patch in the band.
 """
 import numpy as np
 import pytest
@@ -145,3 +150,27 @@ def test_batch_of_64_sampled_bands(dn, basis3):
         a, b = _ref_rows_for_band(h, y0, y1, s=4)
         ref = oracle.denoise(noisy[i], U, V, tau, s=4, W=31, K=16, r_begin=a * nx, r_end=b * nx)
         _band_parity(outs[i].cpu().numpy(), ref, pairs[i][0], y0, y1)
+
+
+def test_video_full_size_groups_and_bands(dn):
+    import os
+    T, h, w, c, sigma, radius, Kv, Wv, sv = 7, 1080, 1920, 3, 30.0, 1, 32, 15, 4
+    clean = synth.make_video(T, h, w, c, seed=21)
+    noisy = synth.add_awgn(clean, sigma, seed=22)
+    d = torch.from_numpy(noisy).cuda()
+    p = dn.params(c, stride=sv, window=Wv, K=Kv)
+    gi, gd = dn.block_match_video(d, p, radius)
+    gpu = dn.denoise_video(d, sigma, p, radius).cpu().numpy()
+    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    oi, od = oracle.block_match_video(noisy, PS, sv, Wv, Kv, radius)
+    assert np.array_equal(gd, od)
+    assert np.array_equal(gi, oi)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    U, V = oracle.load_basis(os.path.join(root, "paper_2512_23569_amd", "data", "basis_ps8_c3.f64"), 8, 3)
+    tau = sigma * oracle.tau_multiplier(c, Kv)
+    stacked = noisy.reshape(T * h, w, c)
+    frame, row = oi // (h * w), (oi % (h * w)) // w
+    for t, y0, y1 in ((3, 0, 32), (0, 520, 552), (6, h - 32, h)):
+        hit = ((frame == t) & (row + PS - 1 >= y0) & (row <= y1 - 1)).any(axis=1)
+        ref = oracle.filter_groups(stacked, oi[hit], U, V, tau, nthreads=4).reshape(T, h, w, c)
+        _band_parity(gpu[t], ref[t], clean[t], y0, y1)
