@@ -160,9 +160,18 @@ htsvd_status htsvd_band_guide(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, in
  * matrices (K*64*bands doubles per group each) stay below `bytes` each (default 4 GiB, at least
  * 1 MiB, at least one group per pass).  The output does not depend on it. */
 htsvd_status htsvd_set_band_memory(htsvd_ctx *ctx, int64_t bytes);
-/* Denoises the cube with a known sigma into d_out (float32 HWC, out_stride elements per row).
- * Errors: HTSVD_ESTATE (no basis for this band count), HTSVD_ENOTSUP (adaptive or ra set),
- * HTSVD_EINVAL / HTSVD_ESHAPE as for htsvd_denoise. */
+/* Band-wise noise levels (Sec. IV-D): sigma_b of every band, the mean over the band's 128 x 128
+ * sub-images of the plain estimate htsvd_estimate_sigma gives for the band alone.  h_sigma:
+ * `bands` doubles (host).  Synchronises the stream. */
+htsvd_status htsvd_band_sigma(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t bands,
+                              int64_t in_stride, double *h_sigma, void *stream);
+/* Denoises the cube into d_out (float32 HWC, out_stride elements per row) with a known sigma, or
+ * with sigma = HTSVD_SIGMA_AUTO by the band-wise rule of Sec. IV-D: with the levels sigma_b of
+ * htsvd_band_sigma and their mean sigma_mean, the cube is filtered at sigma_mean, and the bands
+ * with sigma_b > 2 sigma_mean take their values from the cube filtered at max_b sigma_b (one
+ * grouping serves both; AUTO synchronises the stream).  Errors: HTSVD_ESTATE (no basis for this
+ * band count), HTSVD_ENOTSUP (adaptive or ra set), HTSVD_EINVAL / HTSVD_ESHAPE as for
+ * htsvd_denoise. */
 htsvd_status htsvd_denoise_bands(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t bands,
                                  int64_t in_stride, float sigma, const htsvd_params *p, float *d_out,
                                  int64_t out_stride, void *stream);

@@ -204,3 +204,19 @@ def tau_per_ref(sigma_tiles: np.ndarray, h: int, w: int, ps: int, s: int, c: int
     tiles = tile_of_refs(ys, xs, h, w, T)
     m = tau_multiplier(c, K, ps) if mult is None else mult
     return np.asarray(sigma_tiles, dtype=np.float64)[tiles] * m
+
+
+def band_sigma(cube: np.ndarray, T: int = 128, ps: int = 8) -> np.ndarray:
+    """Band-wise noise levels of a cube (h, w, B) (Sec. IV-D): sigma_b is the mean, over the
+    band's T x T sub-images, of the plain estimate sigma_est of the band alone."""
+    return np.array([sigma_est_tiles(np.ascontiguousarray(cube[:, :, b]), T, ps).mean()
+                     for b in range(cube.shape[2])])
+
+
+def band_sigma_rule(sig: np.ndarray):
+    """Sec. IV-D: sigma_mean is the mean band level; bands above 2 sigma_mean are severely
+    contaminated and take the result filtered at the highest level, the others the result
+    filtered at sigma_mean.  Returns (sigma_mean, sigma_max, severe mask)."""
+    sig = np.asarray(sig, dtype=np.float64)
+    mean = float(sig.mean())
+    return mean, float(sig.max()), sig > 2.0 * mean

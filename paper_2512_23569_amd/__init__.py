@@ -101,6 +101,7 @@ _SIGS = {
     "htsvd_band_guide": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _vp, _vp]),
     "htsvd_denoise_bands": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _i64, _vp]),
     "htsvd_set_band_memory": (_i32, [_vp, _i64]),
+    "htsvd_band_sigma": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _vp, _vp]),
     "htsvd_block_match_video": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i64, _i32, _PP, _vp, _vp, _vp]),
     "htsvd_denoise_video": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i64, _i32, _f32, _PP, _vp, _i64, _vp]),
     "htsvd_ra_param_count": (_i32, [_i32]),
@@ -349,6 +350,15 @@ def htsvd_band_guide(ctx, d_in, h, w, bands, in_stride, d_guide, stream=None):
                                   _dptr(d_guide, torch.uint8, "d_guide"), _stream(stream)))
 
 
+def htsvd_band_sigma(ctx, d_in, h, w, bands, in_stride, stream=None) -> np.ndarray:
+    """Band-wise noise levels (bands,) FP64 on the host."""
+    import torch
+    out = np.zeros(bands, dtype=np.float64)
+    _check(lib().htsvd_band_sigma(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, bands, in_stride,
+                                  out.ctypes.data_as(_vp), _stream(stream)))
+    return out
+
+
 def htsvd_set_band_memory(ctx, nbytes: int):
     _check(lib().htsvd_set_band_memory(ctx, int(nbytes)))
 
@@ -557,9 +567,15 @@ class Denoiser:
         htsvd_band_guide(self.ctx, cube, h, w, b, cube.stride(0), out, stream)
         return out
 
+    def band_sigma(self, cube, stream=None):
+        """Band-wise noise levels of a device cube (h, w, bands) uint8: (bands,) FP64."""
+        h, w, b = cube.shape
+        return htsvd_band_sigma(self.ctx, cube, h, w, b, cube.stride(0), stream)
+
     def denoise_bands(self, cube, sigma, params, out=None, stream=None):
-        """Hyperspectral denoising of a device cube (h, w, bands) uint8 with a known sigma; the
-        basis for this band count comes from htsvd_set_basis or learn_basis."""
+        """Hyperspectral denoising of a device cube (h, w, bands) uint8 with a known sigma, or
+        HTSVD_SIGMA_AUTO for the band-wise noise rule; the basis for this band count comes from
+        htsvd_set_basis or learn_basis."""
         import torch
         h, w, b = cube.shape
         if cube.stride(2) != 1 or cube.stride(1) != b:

@@ -1964,6 +1964,64 @@ htsvd_status htsvd_ra_train_step(htsvd_ctx *ctx, int32_t c, const float *d_noisy
     return HTSVD_OK;
 }
 
+// Band-wise noise levels (Sec. IV-D): every band through the plain sub-image estimator alone,
+// sigma_b the mean of its sub-images' estimates.  Scratch at `scratch` (band_sigma_bytes);
+// synchronises the stream to return the levels on the host.
+static size_t band_sigma_bytes(int h, int w, int B, int tile) {
+    const int64_t n_tiles = (int64_t)((h + tile - 1) / tile) * ((w + tile - 1) / tile);
+    return align256((size_t)B * h * w) + align256(sizeof(double) * B * n_tiles) +
+           align256(sizeof(int32_t) * sigma_mom_ints() * n_tiles) + align256(sizeof(double) * n_tiles);
+}
+
+static htsvd_status band_sigmas(const uint8_t *d_in, int h, int w, int B, int64_t in_stride, int tile, void *scratch,
+                         std::vector<double> &sig, hipStream_t st) {
+    const int64_t n_tiles = (int64_t)((h + tile - 1) / tile) * ((w + tile - 1) / tile);
+    char *b = (char *)scratch;
+    uint8_t *planes = (uint8_t *)b;
+    double *est = (double *)(b + align256((size_t)B * h * w));
+    int32_t *mom = (int32_t *)((char *)est + align256(sizeof(double) * B * n_tiles));
+    double *cov = (double *)((char *)mom + align256(sizeof(int32_t) * sigma_mom_ints() * n_tiles));
+    hipError_t e = launch_band_planes(d_in, in_stride, h, w, B, planes, st);
+    if (e != hipSuccess) return hip_fail(e, "band planes");
+    for (int k = 0; k < B; ++k) {
+        ImageGeom g{};
+        g.img = planes + (int64_t)k * h * w;
+        g.stride = w;
+        g.h = h;
+        g.w = w;
+        g.c = 1;
+        if ((e = launch_sigma_est(g, tile, mom, cov, est + k * n_tiles, st)) != hipSuccess)
+            return hip_fail(e, "band noise estimate");
+    }
+    std::vector<double> h_est((size_t)B * n_tiles);
+    if ((e = hipMemcpyAsync(h_est.data(), est, sizeof(double) * h_est.size(), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(e, "band noise download");
+    sig.assign(B, 0.0);
+    for (int k = 0; k < B; ++k) {
+        double acc = 0.0;
+        for (int64_t t = 0; t < n_tiles; ++t) acc += h_est[(size_t)k * n_tiles + t];
+        sig[k] = acc / (double)n_tiles;
+    }
+    return HTSVD_OK;
+}
+
+htsvd_status htsvd_band_sigma(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t bands,
+                              int64_t in_stride, double *h_sigma, void *stream) {
+    if (!ctx || !d_in || !h_sigma) return fail(HTSVD_EINVAL, "null argument");
+    if (bands < 1 || bands > MAX_BANDS) return fail(HTSVD_EINVAL, "bands must be in [1, 64]");
+    if (h < PS || w < PS) return fail(HTSVD_ESHAPE, "cube smaller than one patch");
+    if (in_stride < (int64_t)w * bands) return fail(HTSVD_EINVAL, "in_stride < w*bands");
+    if ((int64_t)h * w > (int64_t)1 << 30) return fail(HTSVD_ENOTSUP, "cube larger than 2^30 pixels");
+    htsvd_status s = ensure_ws(ctx, band_sigma_bytes(h, w, bands, 128));
+    if (s != HTSVD_OK) return s;
+    std::vector<double> sig;
+    if ((s = band_sigmas(d_in, h, w, bands, in_stride, 128, ctx->ws, sig, (hipStream_t)stream)) != HTSVD_OK) return s;
+    memcpy(h_sigma, sig.data(), sizeof(double) * bands);
+    return HTSVD_OK;
+}
+
 htsvd_status htsvd_band_guide(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t bands,
                               int64_t in_stride, uint8_t *d_guide, void *stream) {
     if (!ctx || !d_in || !d_guide) return fail(HTSVD_EINVAL, "null argument");
@@ -1990,8 +2048,10 @@ htsvd_status htsvd_denoise_bands(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h,
     if (ctx->bands != bands) return fail(HTSVD_ESTATE, "no basis set for this band count");
     if (in_stride < (int64_t)w * bands) return fail(HTSVD_EINVAL, "in_stride < w*bands");
     if (out_stride < (int64_t)w * bands) return fail(HTSVD_EINVAL, "out_stride < w*bands");
-    if (!(sigma > 0.f) || !std::isfinite(sigma)) return fail(HTSVD_EINVAL, "sigma must be > 0");
-    if (p->adaptive || p->ra) return fail(HTSVD_ENOTSUP, "the band path takes a known sigma, no vote or refinement");
+    if ((!(sigma > 0.f) && sigma != HTSVD_SIGMA_AUTO) || !std::isfinite(sigma))
+        return fail(HTSVD_EINVAL, "sigma must be > 0 or AUTO");
+    if (p->adaptive || p->ra) return fail(HTSVD_ENOTSUP, "the band path takes no vote or refinement");
+    const bool auto_sigma = sigma == HTSVD_SIGMA_AUTO;
     // the grouping checks run on the guide's geometry (one channel)
     ImageGeom g;
     MethodParams mp;
@@ -2000,10 +2060,36 @@ htsvd_status htsvd_denoise_bands(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h,
     const int64_t n_ref = (int64_t)g.ny * g.nx;
     const size_t off_idx = align256((size_t)h * w);
     const size_t off_ws = off_idx + align256(sizeof(int32_t) * n_ref * mp.K);
-    if ((s = ensure_ws(ctx, off_ws + band_ws_bytes(h, w, bands, mp.K, n_ref, ctx->band_cap))) != HTSVD_OK) return s;
+    const size_t off_auto = off_ws + align256(band_ws_bytes(h, w, bands, mp.K, n_ref, ctx->band_cap));
+    const size_t off_sel = off_auto + align256(sizeof(float) * (size_t)h * w * bands);
+    const size_t off_sig = off_sel + 256;
+    if ((s = ensure_ws(ctx, auto_sigma ? off_sig + band_sigma_bytes(h, w, bands, p->subimage) : off_auto)) != HTSVD_OK)
+        return s;
     uint8_t *guide = (uint8_t *)ctx->ws;
     int32_t *idx = (int32_t *)((char *)ctx->ws + off_idx);
     hipStream_t st = (hipStream_t)stream;
+    // Band-wise noise levels (Sec. IV-D): the cube is filtered at the mean level sigma_mean; bands
+    // estimated above 2 sigma_mean take the output filtered at the highest band level instead.
+    double s_lo = sigma, s_hi = sigma;
+    std::vector<uint8_t> severe(bands, 0);
+    bool any_severe = false;
+    if (auto_sigma) {
+        std::vector<double> sig;
+        if ((s = band_sigmas(d_in, h, w, bands, in_stride, p->subimage, (char *)ctx->ws + off_sig, sig, st)) !=
+            HTSVD_OK)
+            return s;
+        double mean = 0.0;
+        s_hi = 0.0;
+        for (int k = 0; k < bands; ++k) {
+            mean += sig[k] / bands;
+            s_hi = std::max(s_hi, sig[k]);
+        }
+        s_lo = mean;
+        for (int k = 0; k < bands; ++k) {
+            severe[k] = sig[k] > 2.0 * mean;
+            any_severe = any_severe || severe[k];
+        }
+    }
     hipError_t e = launch_band_guide(d_in, in_stride, h, w, bands, guide, st);
     if (e != hipSuccess) return hip_fail(e, "band guide");
     g.img = guide;
@@ -2018,9 +2104,22 @@ htsvd_status htsvd_denoise_bands(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h,
     bm.M = bm.Dinv + bands * bands;
     {
         StageScope sc(ctx, HTSVD_STAGE_FILTER, st);
-        if ((e = launch_band_filter(bm, d_in, in_stride, h, w, bands, idx, n_ref, mp.K, (double)sigma * mult,
-                                    ctx->band_cap, (char *)ctx->ws + off_ws, d_out, out_stride, st)) != hipSuccess)
+        if ((e = launch_band_filter(bm, d_in, in_stride, h, w, bands, idx, n_ref, mp.K, s_lo * mult, ctx->band_cap,
+                                    (char *)ctx->ws + off_ws, d_out, out_stride, st)) != hipSuccess)
             return hip_fail(e, "band filter");
+        if (any_severe) {
+            float *alt = (float *)((char *)ctx->ws + off_auto);
+            uint8_t *sel = (uint8_t *)ctx->ws + off_sel;
+            if ((e = launch_band_filter(bm, d_in, in_stride, h, w, bands, idx, n_ref, mp.K, s_hi * mult,
+                                        ctx->band_cap, (char *)ctx->ws + off_ws, alt, (int64_t)w * bands, st)) !=
+                    hipSuccess ||
+                (e = hipMemcpyAsync(sel, severe.data(), bands, hipMemcpyHostToDevice, st)) != hipSuccess ||
+                (e = launch_select_bands(alt, (int64_t)w * bands, sel, h, w, bands, d_out, out_stride, st)) !=
+                    hipSuccess)
+                return hip_fail(e, "band filter at the highest level");
+            // the host vector must outlive the asynchronous copy
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "band selection");
+        }
     }
     return HTSVD_OK;
 }

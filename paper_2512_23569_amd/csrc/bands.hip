@@ -165,6 +165,28 @@ __global__ void normalize_kernel(const unsigned long long *__restrict__ acc, con
               : (float)cube[(int64_t)y * stride + (int64_t)x * B + b];
 }
 
+// Band planes: planes[(b*h + y)*w + x] = cube(y, x, b), for the band-wise noise estimate.
+__global__ void planes_kernel(const uint8_t *__restrict__ cube, int64_t stride, int h, int w, int B,
+                              uint8_t *__restrict__ planes) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= (int64_t)h * w) return;
+    const int y = (int)(q / w), x = (int)(q % w);
+    const uint8_t *p = cube + (int64_t)y * stride + (int64_t)x * B;
+    for (int b = 0; b < B; ++b) planes[(int64_t)b * h * w + q] = p[b];
+}
+
+// out(y, x, b) = alt(y, x, b) for the bands with sel[b] != 0.
+__global__ void select_bands_kernel(const float *__restrict__ alt, int64_t alt_stride, const uint8_t *__restrict__ sel,
+                                    int h, int w, int B, float *__restrict__ out, int64_t out_stride) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)h * w * B) return;
+    const int b = (int)(t % B);
+    if (!sel[b]) return;
+    const int64_t pix = t / B;
+    const int y = (int)(pix / w), x = (int)(pix % w);
+    out[(int64_t)y * out_stride + (int64_t)x * B + b] = alt[(int64_t)y * alt_stride + (int64_t)x * B + b];
+}
+
 unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t gemm(const double *A, int64_t sam, int64_t sak, const double *Bm, int64_t sbk, int64_t sbn, double *Cm,
@@ -209,6 +231,19 @@ hipError_t tproduct(const BandMaps &bm, int B, int64_t n_patch, const double *X,
 }
 
 }  // namespace
+
+hipError_t launch_band_planes(const uint8_t *cube, int64_t stride, int h, int w, int B, uint8_t *planes,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(planes_kernel, dim3(nb((int64_t)h * w, 256)), dim3(256), 0, st, cube, stride, h, w, B, planes);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_bands(const float *alt, int64_t alt_stride, const uint8_t *sel, int h, int w, int B,
+                               float *out, int64_t out_stride, hipStream_t st) {
+    hipLaunchKernelGGL(select_bands_kernel, dim3(nb((int64_t)h * w * B, 256)), dim3(256), 0, st, alt, alt_stride, sel,
+                       h, w, B, out, out_stride);
+    return hipGetLastError();
+}
 
 hipError_t launch_band_guide(const uint8_t *cube, int64_t stride, int h, int w, int B, uint8_t *guide,
                              hipStream_t st) {

@@ -279,6 +279,10 @@ hipError_t launch_fill_tau_learned(double *tau, const ImageGeom &g, int tile, co
 
 // Hyperspectral tube patches (bands.hip).
 hipError_t launch_band_guide(const uint8_t *cube, int64_t stride, int h, int w, int B, uint8_t *guide, hipStream_t st);
+hipError_t launch_band_planes(const uint8_t *cube, int64_t stride, int h, int w, int B, uint8_t *planes,
+                              hipStream_t st);
+hipError_t launch_select_bands(const float *alt, int64_t alt_stride, const uint8_t *sel, int h, int w, int B,
+                               float *out, int64_t out_stride, hipStream_t st);
 // The filter works in chunks of groups whose FP64 patch matrices stay below cap bytes each.
 size_t band_ws_bytes(int h, int w, int B, int K, int64_t n_group, int64_t cap);
 hipError_t launch_band_filter(const BandMaps &bm, const uint8_t *cube, int64_t stride, int h, int w, int B,

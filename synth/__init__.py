@@ -168,6 +168,14 @@ def add_awgn(clean: np.ndarray, sigma: float, seed: int) -> np.ndarray:
     return _quantise(noisy)
 
 
+def add_band_awgn(cube: np.ndarray, sigmas, seed: int) -> np.ndarray:
+    """Gaussian noise of level sigmas[b] on band b of a cube (h, w, B), rounded half-to-even and
+    clipped to uint8 (non-uniform noise across bands)."""
+    rng = _rng(seed)
+    s = np.asarray(sigmas, dtype=np.float64).reshape(1, 1, -1)
+    return _quantise(cube.astype(np.float64) + s * rng.standard_normal(cube.shape))
+
+
 def add_poisson_gaussian(clean: np.ndarray, gain: float, read_sigma: float, seed: int) -> np.ndarray:
     """Signal-dependent noise on the 0..1 scale: y = gain*Poisson(x/gain) + N(0, (read/255)^2).
 

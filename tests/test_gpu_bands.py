@@ -65,8 +65,8 @@ def test_band_errors(dn):
             d2.denoise_bands(cube, 20.0, d2.params(1, stride=4, window=15, K=8))
         U, V = lb.learn(synth.make_hsi(32, 32, 6, 96), 8, 4)
         ht.htsvd_set_basis(d2.ctx, 8, 6, oracle.to_slices(U), oracle.to_slices(V))
-        with pytest.raises(ht.HtsvdError):   # sigma must be known
-            d2.denoise_bands(cube, -1.0, d2.params(1, stride=4, window=15, K=8))
+        with pytest.raises(ht.HtsvdError):   # neither a sigma nor AUTO
+            d2.denoise_bands(cube, -2.0, d2.params(1, stride=4, window=15, K=8))
         bad = oracle.to_slices(U).copy()
         bad[0, 0, 0] += 0.1
         with pytest.raises(ht.HtsvdError):   # not orthogonal
@@ -119,3 +119,38 @@ def test_band_filter_in_passes_is_identical(dn):
         ht.htsvd_set_band_memory(dn.ctx, 4 << 30)
     torch.cuda.synchronize()
     assert torch.equal(one, many)
+
+
+@pytest.mark.parametrize("h,w,bands", [(150, 140, 8), (64, 300, 5)])
+def test_band_sigma_matches_oracle(dn, h, w, bands):
+    """Band-wise noise levels (Sec. IV-D): the plain estimate of every band alone, averaged over
+    its sub-images (partial edge sub-images included)."""
+    levels = np.linspace(8.0, 30.0, bands)
+    cube = synth.add_band_awgn(synth.make_hsi(h, w, bands, 110 + bands), levels, 111)
+    got = dn.band_sigma(_dev(cube))
+    want = oracle.band_sigma(cube)
+    assert np.allclose(got, want, rtol=1e-9, atol=0), (got, want)
+
+
+@pytest.mark.parametrize("levels", [[10, 10, 12, 9, 11, 10, 10, 50], [15.0] * 6])
+def test_band_auto_denoise_parity(dn, levels):
+    """sigma = AUTO: the cube filtered at the mean band level, severe bands (above twice the mean)
+    taken from the cube filtered at the highest level; against the oracle's composition of the
+    same two filterings (its band levels, groups and basis)."""
+    import paper_2512_23569_amd as ht
+    bands, h, w, K, W, s = len(levels), 72, 80, 16, 15, 4
+    clean = synth.make_hsi(h, w, bands, 120 + bands)
+    noisy = synth.add_band_awgn(clean, np.asarray(levels, dtype=np.float64), 121)
+    U, V = lb.learn(noisy, 8, 4)
+    ht.htsvd_set_basis(dn.ctx, 8, bands, oracle.to_slices(U), oracle.to_slices(V))
+    mean, mx, severe = oracle.band_sigma_rule(oracle.band_sigma(noisy))
+    idx, _ = oracle.block_match(oracle.band_guide(noisy), 8, s, W, K)
+    mult = np.sqrt(2.0 * np.log(bands * K * 64))
+    ref = oracle.filter_groups(noisy, idx, U, V, mean * mult)
+    if severe.any():
+        hi = oracle.filter_groups(noisy, idx, U, V, mx * mult)
+        ref[:, :, severe] = hi[:, :, severe]
+    gpu = dn.denoise_bands(_dev(noisy), ht.HTSVD_SIGMA_AUTO, dn.params(1, stride=s, window=W, K=K)).cpu().numpy()
+    m = assert_pixel_parity(gpu, ref, clean)
+    print("band AUTO levels %s: severe %s" % (levels, severe.nonzero()[0]), m)
+    assert severe.any() == (max(levels) > 2 * np.mean(levels))

@@ -429,6 +429,26 @@ def test_smaller_groups_are_prefixes_of_larger_ones(c, seed):
     assert np.array_equal(bi, i32[:, :4]) and np.array_equal(bd, d32[:, :4])
 
 
+def test_band_sigma_rule_hand_cases():
+    """Sec. IV-D: bands above twice the mean level are the severe ones."""
+    mean, mx, severe = oracle.band_sigma_rule([10.0, 10.0, 10.0, 70.0])
+    assert mean == 25.0 and mx == 70.0 and list(severe) == [False, False, False, True]
+    mean, mx, severe = oracle.band_sigma_rule([10.0, 12.0, 14.0])
+    assert mean == 12.0 and mx == 14.0 and not severe.any()
+    _, _, severe = oracle.band_sigma_rule([10.0, 10.0, 20.0])   # 20 > 2 * 13.33 is false
+    assert not severe.any()
+
+
+def test_band_sigma_recovers_band_levels_of_flat_bands():
+    """Flat bands with Gaussian noise of a different level each: the band-wise estimate finds
+    every level (the plain estimator on a noise-only band, within 3%) and flags the severe one."""
+    levels = np.array([5.0, 10.0, 15.0, 10.0, 40.0, 8.0])   # 128 +- 3.2 sigma: no clipping
+    cube = synth.add_band_awgn(np.full((192, 160, 6), 128, np.uint8), levels, 40)
+    sig = oracle.band_sigma(cube)
+    assert np.all(np.abs(sig / levels - 1.0) < 0.03), sig
+    assert list(oracle.band_sigma_rule(sig)[2]) == [False, False, False, False, True, False]
+
+
 # ---- spatio-temporal grouping: Sec. IV-C -------------------------------------
 
 def _brute_video_groups(frames, ps, s, W, K, radius, gnum=6, gden=5):
