@@ -2173,7 +2173,7 @@ htsvd_status htsvd_denoise_video(htsvd_ctx *ctx, const uint8_t *d_in, int32_t T,
     const int64_t n_frame = (int64_t)g.ny * g.nx, n_ref = (int64_t)gv.ny * gv.nx, npx = (int64_t)gv.h * w;
     const size_t off_tau = align256(sizeof(int32_t) * n_ref * mp.K);
     const size_t off_acc = off_tau + align256(sizeof(double) * n_ref);
-    const size_t off_hist = off_acc + align256(sizeof(unsigned long long) * npx * c);
+    const size_t off_hist = off_acc + align256(filter_mfma_global_bytes(gv, T, radius, mp.W, mp.K));
     const size_t off_ra = off_hist + align256(sizeof(int) * npx);
     const size_t off_frame = off_ra + (p->ra ? align256(ra_ws_bytes(gv)) : 0);
     const size_t frame_ws = per_frame ? plan_ws(nullptr, g, mp.W, mp.K, tile).total : 0;
@@ -2181,7 +2181,7 @@ htsvd_status htsvd_denoise_video(htsvd_ctx *ctx, const uint8_t *d_in, int32_t T,
     char *ws = (char *)ctx->ws;
     int32_t *idx = (int32_t *)ws;
     double *tau = (double *)(ws + off_tau);
-    unsigned long long *gacc = (unsigned long long *)(ws + off_acc);
+    void *accum = ws + off_acc;
     int *ghist = (int *)(ws + off_hist);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
@@ -2223,13 +2223,12 @@ htsvd_status htsvd_denoise_video(htsvd_ctx *ctx, const uint8_t *d_in, int32_t T,
     {
         StageScope sc(ctx, HTSVD_STAGE_CLEAR, st);
         if ((e = launch_zero(ctx->d_guard, 2 * sizeof(unsigned long long), st)) != hipSuccess ||
-            (e = launch_zero(gacc, sizeof(unsigned long long) * npx * c, st)) != hipSuccess ||
             (e = launch_zero(ghist, sizeof(int) * npx, st)) != hipSuccess)
             return hip_fail(e, "zero accumulators");
     }
     {
         StageScope sc(ctx, HTSVD_STAGE_FILTER, st);
-        if ((e = launch_filter_mfma_global(gv, T, radius, mp.W, mp.K, ctx->basis[c == 3], idx, tau, gacc, ghist,
+        if ((e = launch_filter_mfma_global(gv, T, radius, mp.W, mp.K, ctx->basis[c == 3], idx, tau, accum, ghist,
                                            ctx->d_guard, d_out, out_stride, st, ra_d, ra_f)) != hipSuccess)
             return hip_fail(e, "video filter");
     }

@@ -226,8 +226,9 @@ int filter_mfma_static_bytes();
 hipError_t launch_filter_mfma(const ImageGeom &g, const TileGeom &tg, int K, const BasisDev &b, const int32_t *idx,
                               const double *tau_ref, float *regions, unsigned long long *gc, hipStream_t st,
                               const float *ra_d = nullptr, const uint8_t *ra_flag = nullptr);
+size_t filter_mfma_global_bytes(const ImageGeom &g, int T, int radius, int W, int K, bool force_direct = false);
 hipError_t launch_filter_mfma_global(const ImageGeom &g, int T, int radius, int W, int K, const BasisDev &b,
-                                     const int32_t *idx, const double *tau_ref, unsigned long long *gacc, int *ghist,
+                                     const int32_t *idx, const double *tau_ref, void *accum, int *ghist,
                                      unsigned long long *gc, float *out, int64_t out_stride, hipStream_t st,
                                      const float *ra_d = nullptr, const uint8_t *ra_flag = nullptr,
                                      bool force_direct = false);

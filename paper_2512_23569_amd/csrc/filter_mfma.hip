@@ -200,7 +200,8 @@ __device__ inline v8h ldfrag0(const v8h *FL0, int dir, int term, int pair, int l
 //   GA: global aggregation into gacc[pix*C + ch] (units of 2^-tg.FS) and ghist[pix] (patches by
 //   top-left pixel).  GA == 1: every contribution goes to gacc, the tile only schedules
 //   references and region is unused; GA == 2: the tile (references of one frame) adds into its
-//   LDS slot region first, whose nonzero sums then go to gacc.
+//   LDS slot region, which then goes to the tile's slot of a global region buffer (at gacc,
+//   C * plane int32 per tile) for ga_gather_kernel.
 template <int C, int K, bool RA = false, int GA = 0>
 __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileGeom &tg, const v8h *FL0,
                                                  const v8h *__restrict__ FG, const double *__restrict__ T64,
@@ -680,18 +681,12 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
     }
     if constexpr (GA == 1) return;   // the caller's barrier follows
     if constexpr (GA == 2) {
-        // nonzero sums of the slot region to the global sums (zero adds nothing)
+        // the slot region to the tile's own slot of the global region buffer (plain stores; the
+        // gather kernel sums the regions covering each pixel)
         __syncthreads();
-        const int slot_elems = vt.RH * tg.RP;
-        for (int e = tid; e < C * plane; e += MW * 64) {
-            const int v = iregion[e];
-            if (v == 0) continue;
-            const int ch = e / plane, q = e - ch * plane;
-            const int slot = q / slot_elems, rq = q - slot * slot_elems;
-            const int row = rq / tg.RP, col = rq - row * tg.RP;
-            const int64_t pix = ((int64_t)(f_lo + slot) * vt.h_frame + r0 + row) * g.w + c0 + col;
-            atomicAdd(gacc + pix * C + ch, (unsigned long long)(long long)v);
-        }
+        int4 *dst = reinterpret_cast<int4 *>(reinterpret_cast<int *>(gacc) + (int64_t)tile * C * plane);
+        const int4 *src = reinterpret_cast<const int4 *>(iregion);
+        for (int e = tid; e < C * plane / 4; e += MW * 64) dst[e] = src[e];
         return;   // the caller's barrier follows
     }
     __syncthreads();
@@ -821,6 +816,57 @@ __global__ void ga_normalize_kernel(const unsigned long long *__restrict__ gacc,
 #pragma unroll
     for (int ch = 0; ch < C; ++ch)
         o[ch] = n > 0 ? (float)((double)(long long)gacc[e * C + ch] * inv) : (float)px[ch];
+}
+
+// Slot regions (GA == 2): pixel (f, y, x) of the stacked frames sums, over the frames t within
+// the radius of f, the regions of frame t's tiles that cover (y, x) at f's slot; the count is
+// the 8 x 8 box sum of the patch histogram.  out = sum / (count 2^fs), or the noisy value.
+template <int C>
+__global__ void ga_gather_kernel(const int *__restrict__ regions, TileGeom tg, VideoTiling vt, int s, int nx,
+                                 const int *__restrict__ ghist, const uint8_t *__restrict__ img, int64_t stride,
+                                 int w, float *__restrict__ out, int64_t out_stride) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int hh = vt.T * vt.h_frame;
+    if (e >= (int64_t)hh * w) return;
+    const int Y = (int)(e / w), x = (int)(e % w);
+    const int f = Y / vt.h_frame, y = Y - f * vt.h_frame;
+    int n = 0;
+    for (int dy = 0; dy < PS && dy <= Y; ++dy)
+        for (int dx = 0; dx < PS && dx <= x; ++dx) n += ghist[(int64_t)(Y - dy) * w + (x - dx)];
+    float *o = out + (int64_t)Y * out_stride + (int64_t)x * C;
+    const uint8_t *px = img + (int64_t)Y * stride + (int64_t)x * C;
+    if (n == 0) {
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) o[ch] = (float)px[ch];
+        return;
+    }
+    const int plane = tg.RH * tg.RP;
+    const int tyf = (vt.ny_frame + tg.TY - 1) / tg.TY;
+    const int span_y = tg.TY * s, span_x = tg.TX * s;
+    // tiles whose region rows r0 .. r0 + RH - 1 can hold y: r0 = max(0, first reference row - R)
+    const int ty_hi = min(tyf - 1, (y + tg.R) / span_y + 1), ty_lo = max(0, (y + tg.R - vt.RH) / span_y - 1);
+    const int tx_hi = min(tg.tiles_x - 1, (x + tg.R) / span_x + 1), tx_lo = max(0, (x + tg.R - vt.RW) / span_x - 1);
+    long long acc[C];
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) acc[ch] = 0;
+    for (int t = max(0, f - vt.radius); t <= min(vt.T - 1, f + vt.radius); ++t) {
+        const int slot = f - max(0, t - vt.radius);
+        for (int tyl = ty_lo; tyl <= ty_hi; ++tyl) {
+            const int r0 = max(0, ref_pos(tyl * tg.TY, vt.ny_frame, vt.h_frame, s) - tg.R);
+            if (y < r0 || y >= r0 + vt.RH) continue;
+            for (int tx = tx_lo; tx <= tx_hi; ++tx) {
+                const int c0 = max(0, ref_pos(tx * tg.TX, nx, w, s) - tg.R);
+                if (x < c0 || x >= c0 + vt.RW) continue;
+                const int *src = regions + ((int64_t)(t * tyf + tyl) * tg.tiles_x + tx) * C * plane +
+                                 (slot * vt.RH + (y - r0)) * tg.RP + (x - c0);
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch) acc[ch] += src[ch * plane];
+            }
+        }
+    }
+    const double inv = 1.0 / ((double)n * (double)(1 << tg.FS));
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) o[ch] = (float)((double)acc[ch] * inv);
 }
 
 template <int C, int K>
@@ -963,40 +1009,66 @@ static int video_tile_side(int C, int K, int h_frame, int w, int s, int W, int n
     return 0;
 }
 
+// Plan of the video filter: frame-aligned tiles with slot regions (side > 0), or the direct
+// global sums (side 0).
+static int plan_video(const ImageGeom &g, int T, int radius, int W, int K, bool force_direct, VideoTiling *vt,
+                      TileGeom *tg) {
+    vt->T = T;
+    vt->h_frame = g.h / T;
+    vt->ny_frame = g.ny / T;
+    vt->radius = radius;
+    vt->nslot = min(2 * radius + 1, T);
+    const int side = force_direct ? 0 : video_tile_side(g.c, K, vt->h_frame, g.w, g.s, W, vt->nslot, vt);
+    *tg = TileGeom{};
+    tg->R = (W - 1) / 2;
+    tg->FS = side > 0 ? ga_shift(side, K) : GA_FS;
+    if (side > 0) {   // frame-aligned tiles with slot regions
+        tg->TY = tg->TX = side;
+        tg->tiles_y = T * ((vt->ny_frame + side - 1) / side);
+        tg->tiles_x = (g.nx + side - 1) / side;
+        tg->RH = vt->nslot * vt->RH;   // one plane per channel: the slots stacked
+        tg->RW = vt->RW;
+        tg->RP = vt->RP;
+    } else {          // direct: 8 x 8 references of the stacked grid per scheduling unit
+        tg->TY = tg->TX = 8;
+        tg->tiles_y = (g.ny + tg->TY - 1) / tg->TY;
+        tg->tiles_x = (g.nx + tg->TX - 1) / tg->TX;
+    }
+    return side;
+}
+
+// Bytes of the accumulation buffer of launch_filter_mfma_global: the tiles' slot regions, or
+// the 64-bit global sums.
+size_t filter_mfma_global_bytes(const ImageGeom &g, int T, int radius, int W, int K, bool force_direct) {
+    if (T < 1 || g.h % T || g.ny % T) return 0;
+    VideoTiling vt;
+    TileGeom tg;
+    const int side = plan_video(g, T, radius, W, K, force_direct, &vt, &tg);
+    if (side > 0) return (size_t)tg.tiles_y * tg.tiles_x * g.c * region_plane(tg) * sizeof(int);
+    return (size_t)g.h * g.w * g.c * sizeof(unsigned long long);
+}
+
 // Filtering of groups whose members lie anywhere in the frames of a video (T frames of g.h / T
 // rows stacked vertically, reference grid T*ny x nx frame-major, members within `radius` frames
-// of their reference's): global aggregation, then the normalisation.  gacc (h*w*C u64) and
+// of their reference's), then the normalisation.  accum: filter_mfma_global_bytes of scratch;
 // ghist (h*w int32) must be zero on entry.  force_direct skips the slot regions.
 hipError_t launch_filter_mfma_global(const ImageGeom &g, int T, int radius, int W, int K, const BasisDev &b,
-                                     const int32_t *idx, const double *tau_ref, unsigned long long *gacc, int *ghist,
+                                     const int32_t *idx, const double *tau_ref, void *accum, int *ghist,
                                      unsigned long long *gc, float *out, int64_t out_stride, hipStream_t st,
                                      const float *ra_d, const uint8_t *ra_flag, bool force_direct) {
     if (!b.frag || T < 1 || g.h % T || g.ny % T) return hipErrorInvalidValue;
     VideoTiling vt;
-    vt.T = T;
-    vt.h_frame = g.h / T;
-    vt.ny_frame = g.ny / T;
-    vt.radius = radius;
-    vt.nslot = min(2 * radius + 1, T);
-    const int side = force_direct ? 0 : video_tile_side(g.c, K, vt.h_frame, g.w, g.s, W, vt.nslot, &vt);
-    TileGeom tg{};
-    tg.R = (W - 1) / 2;
-    tg.FS = side > 0 ? ga_shift(side, K) : GA_FS;
+    TileGeom tg;
+    const int side = plan_video(g, T, radius, W, K, force_direct, &vt, &tg);
     int lds = filter_mfma_group_bytes(g.c);
-    if (side > 0) {   // frame-aligned tiles with slot regions
-        tg.TY = tg.TX = side;
-        tg.tiles_y = T * ((vt.ny_frame + side - 1) / side);
-        tg.tiles_x = (g.nx + side - 1) / side;
-        tg.RH = vt.nslot * vt.RH;   // one plane per channel: the slots stacked
-        tg.RW = vt.RW;
-        tg.RP = vt.RP;
+    unsigned long long *gacc = (unsigned long long *)accum;
+    hipError_t e;
+    if (side > 0) {
         lds += g.c * region_plane(tg) * 4;
-    } else {          // direct: 8 x 8 references of the stacked grid per scheduling unit
-        tg.TY = tg.TX = 8;
-        tg.tiles_y = (g.ny + tg.TY - 1) / tg.TY;
-        tg.tiles_x = (g.nx + tg.TX - 1) / tg.TX;
+    } else if ((e = launch_zero(accum, (size_t)g.h * g.w * g.c * sizeof(unsigned long long), st)) != hipSuccess) {
+        return e;
     }
-    hipError_t e = hipErrorInvalidValue;
+    e = hipErrorInvalidValue;
 #define HG_CASE(CC, KK)                                                                                          \
     if (g.c == CC && K == KK) {                                                                                  \
         if (side > 0)                                                                                            \
@@ -1016,12 +1088,20 @@ hipError_t launch_filter_mfma_global(const ImageGeom &g, int T, int radius, int 
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)g.h * g.w;
     const unsigned grid = (unsigned)((n + 255) / 256);
-    if (g.c == 3)
+    if (side > 0) {
+        if (g.c == 3)
+            hipLaunchKernelGGL(ga_gather_kernel<3>, dim3(grid), dim3(256), 0, st, (const int *)accum, tg, vt, g.s, g.nx,
+                               ghist, g.img, g.stride, g.w, out, out_stride);
+        else
+            hipLaunchKernelGGL(ga_gather_kernel<1>, dim3(grid), dim3(256), 0, st, (const int *)accum, tg, vt, g.s, g.nx,
+                               ghist, g.img, g.stride, g.w, out, out_stride);
+    } else if (g.c == 3) {
         hipLaunchKernelGGL(ga_normalize_kernel<3>, dim3(grid), dim3(256), 0, st, gacc, ghist, g.img, g.stride, g.h,
                            g.w, tg.FS, out, out_stride);
-    else
+    } else {
         hipLaunchKernelGGL(ga_normalize_kernel<1>, dim3(grid), dim3(256), 0, st, gacc, ghist, g.img, g.stride, g.h,
                            g.w, tg.FS, out, out_stride);
+    }
     return hipGetLastError();
 }
 
