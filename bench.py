@@ -620,7 +620,7 @@ def bench_video(args):
                                "known, spatio-temporal grouping over %d frames, stride %d, window %d, K %d"
                                % (T, w, h, c, sigma, 2 * radius + 1, s, W, K), "form": "video"},
         "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]},
-        "roofline": {"bound": "alu", "kernel": "filter_mfma_ga_kernel<3,32> and its normalisation (filter stage)",
+        "roofline": {"bound": "alu", "kernel": "filter_mfma_ga_kernel<3,32,false,2> + ga_gather_kernel<3> (filter stage)",
                      "achieved": round(tf, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tf / PEAK_FP32_VECTOR_TFLOPS, 4),
                      "traffic": measured_traffic(n_ref, VIDEO_TRAFFIC_FILE), "kernel_ms": round(f_avg, 4),
