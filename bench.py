@@ -581,7 +581,7 @@ def bench_video(args):
     stream = torch.cuda.current_stream()
     d_in = torch.from_numpy(noisy).cuda()
     d_out = torch.empty(noisy.shape, dtype=torch.float32, device="cuda")
-    dn = ht.Denoiser(0, load_network=False)
+    dn = ht.Denoiser(0)   # shipped bases and networks (the RA variant below uses them)
     p = dn.params(c, stride=s, window=W, K=K)
 
     def step():
@@ -594,6 +594,15 @@ def bench_video(args):
     out = d_out.cpu().numpy()
     psnr = synth.psnr(clean, out)
     per_frame = [synth.psnr(clean[t], out[t]) for t in range(T)]
+    # the other video forms on the same clip: sigma estimated frame by frame with the vote, and
+    # RA-Haar-tSVD on the spatio-temporal groups (known sigma)
+    variants = {}
+    for name, sg, pv in (("estimated_sigma_vote", ht.HTSVD_SIGMA_AUTO, p.replace(adaptive=1)),
+                         ("ra", sigma, p.replace(ra=1, ra_sigma=25.0))):
+        ms_v = time_steps(lambda: dn.denoise_video(d_in, sg, pv, radius, out=d_out), max(1, args.steps // 2), 1,
+                          stream)
+        variants[name] = {"ms": round(ms_v, 3), "psnr": round(synth.psnr(clean, d_out.cpu().numpy()), 3)}
+    log("video variants: %s" % variants)
     n_ref = T * ht.htsvd_ref_count(h, 8, s) * ht.htsvd_ref_count(w, 8, s)
     f_ms, f_calls = stages["filter"]
     f_avg = f_ms / max(f_calls, 1)
@@ -629,6 +638,7 @@ def bench_video(args):
                               "frac": round(mf_tf / PEAK_F16_MFMA_TFLOPS, 4)}},
         "psnr": {"noisy": round(synth.psnr(clean, noisy), 3), "denoised": round(psnr, 3),
                  "per_frame": [round(v, 3) for v in per_frame]},
+        "variants": variants,
         "input_gen_s": round(gen_s, 1),
     }
     if not args.no_cpu_baseline:
