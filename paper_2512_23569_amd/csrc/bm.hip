@@ -217,335 +217,335 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g0, const MethodParams 
     const int K = mp.K;
 
     for (int fi = 0; fi < nf; ++fi) {
-    int slot = 0;
-    const uint8_t *fimg = g.img;
-    if constexpr (VIDEO) {
-        // the reference's own frame first (its patches become the A fragments), then the others
-        const int f = fi == 0 ? t : f_lo + fi - 1 + (f_lo + fi - 1 >= t ? 1 : 0);
-        slot = f - f_lo;
-        fimg = g0.img + (int64_t)f * va.frame_bytes;
-        if (fi > 0) __syncthreads();   // the last frame's table and selection scratch are reused
-    }
-
-    // ---- stage the shifted planes: one thread per (row, group of 4 columns) ----
-    // Dword w of int8 copy k holds the row's pixels 4w + k .. 4w + k + 3, and halves 4w .. 4w + 3
-    // of fp16 copy k hold the pixels 4w + k .. 4w + k + 3, so a thread needs pixels 4w .. 4w + 6.
-    // Bytes at or beyond the staged width pcol are never read (candidates end at pcol - 1).
-    {
-        const int nw = (pcol + 3) >> 2;
-        const uint8_t *img_end = fimg + (int64_t)(g.h - 1) * g.stride + (int64_t)g.w * g.c;
-        uint32_t *p8w = reinterpret_cast<uint32_t *>(p8);
-        uint32_t *p16w = reinterpret_cast<uint32_t *>(p16);
-        for (int e = tid; e < prow * nw; e += BMT) {
-            const int r = e / nw, w4 = 4 * (e - r * nw);
-            const int npx = min(7, pcol - w4);
-            const uint8_t *a = fimg + (int64_t)(uy0 + r) * g.stride + (int64_t)(ux0 + w4) * g.c;
-            uint32_t raw[6];   // bytes 0 .. 23 from a
-            const uintptr_t ai = (uintptr_t)a;
-            const uint32_t *ab = reinterpret_cast<const uint32_t *>(ai & ~(uintptr_t)3);
-            if (npx == 7 && (const uint8_t *)(ab + 7) <= img_end) {
-                const uint32_t sh = (uint32_t)(ai & 3);
-                uint32_t d[7];
-#pragma unroll
-                for (int i = 0; i < 7; ++i) d[i] = ab[i];
-#pragma unroll
-                for (int i = 0; i < 6; ++i) raw[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
-            } else {   // row end: only the pixels that exist, byte by byte
-#pragma unroll
-                for (int i = 0; i < 6; ++i) raw[i] = 0u;
-                const int nb = npx * g.c;
-                for (int b = 0; b < nb; ++b) raw[b >> 2] |= (uint32_t)a[b] << (8 * (b & 3));
-            }
-            auto byte_at = [&](int i) { return (int)((raw[i >> 2] >> (8 * (i & 3))) & 0xffu); };
-            int v8[7], vs[7];
-#pragma unroll
-            for (int q = 0; q < 7; ++q) {
-                if (g.c == 3) {
-                    const int R = byte_at(3 * q), G = byte_at(3 * q + 1), B = byte_at(3 * q + 2);
-                    v8[q] = G - 128;
-                    vs[q] = R + G + B - 384;
-                } else {
-                    v8[q] = byte_at(q) - 128;
-                    vs[q] = 0;
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                p8w[(k * plane8 + r * L.pitch8 + w4) >> 2] =
-                    (uint32_t)(uint8_t)v8[k] | ((uint32_t)(uint8_t)v8[k + 1] << 8) |
-                    ((uint32_t)(uint8_t)v8[k + 2] << 16) | ((uint32_t)(uint8_t)v8[k + 3] << 24);
-            if (g.c == 3) {
-#pragma unroll
-                for (int k = 0; k < 2; ++k)
-#pragma unroll
-                    for (int hh = 0; hh < 2; ++hh) {
-                        const uint32_t lo = __builtin_bit_cast(uint16_t, (_Float16)vs[2 * hh + k]);
-                        const uint32_t hi = __builtin_bit_cast(uint16_t, (_Float16)vs[2 * hh + k + 1]);
-                        p16w[(k * plane16 + r * L.pitch16 + w4 + 2 * hh) >> 1] = lo | (hi << 16);
-                    }
-            }
+        int slot = 0;
+        const uint8_t *fimg = g.img;
+        if constexpr (VIDEO) {
+            // the reference's own frame first (its patches become the A fragments), then the others
+            const int f = fi == 0 ? t : f_lo + fi - 1 + (f_lo + fi - 1 >= t ? 1 : 0);
+            slot = f - f_lo;
+            fimg = g0.img + (int64_t)f * va.frame_bytes;
+            if (fi > 0) __syncthreads();   // the last frame's table and selection scratch are reused
         }
-    }
-    __syncthreads();
-    if (fi == 0 && tid == 0) {   // read after the norm phase's barriers
-        int any = 0;
-        for (int i = 0; i < NREF; ++i) any |= (ti.ry[i] >= 0 && !ti.green[i]);
-        ti.any_sum = any;
-    }
 
-    // ---- squared norms at every candidate position (horizontal then vertical 8-sums) ----
-    // Four consecutive outputs per thread from one window of 11 values, sliding (exact integers).
-    // Reads past the last valid output stay inside the staged planes and the table; the
-    // outputs they feed are not stored.
-    {
-        int32_t *rs8 = reinterpret_cast<int32_t *>(tab);          // prow x uw, tab is free now
-        int32_t *rs16 = rs8 + prow * uw;
-        const int ng = (uw + 3) >> 2;
-        for (int e = tid; e < prow * ng; e += BMT) {
-            const int r = e / ng, c0 = 4 * (e - r * ng);
-            int q8[11], q16[11];
-            {
-                const uint32_t *w8 = reinterpret_cast<const uint32_t *>(p8 + r * L.pitch8 + c0);
-                const uint32_t b[3] = {w8[0], w8[1], w8[2]};
-#pragma unroll
-                for (int j = 0; j < 11; ++j) {
-                    const int v = (int)(int8_t)(b[j >> 2] >> (8 * (j & 3)));
-                    q8[j] = v * v;
-                }
-            }
-            if (g.c == 3) {
-                const uint32_t *w16 = reinterpret_cast<const uint32_t *>(p16 + r * L.pitch16 + c0);
-                uint32_t b[6];
-#pragma unroll
-                for (int i = 0; i < 6; ++i) b[i] = w16[i];
-#pragma unroll
-                for (int j = 0; j < 11; ++j) {
-                    const int t = (int)__builtin_bit_cast(_Float16, (uint16_t)(b[j >> 1] >> (16 * (j & 1))));
-                    q16[j] = t * t;
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < 11; ++j) q16[j] = 0;
-            }
-            int a = 0, t = 0;
-#pragma unroll
-            for (int j = 0; j < PS; ++j) {
-                a += q8[j];
-                t += q16[j];
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (c0 + k < uw) {
-                    rs8[r * uw + c0 + k] = a;
-                    rs16[r * uw + c0 + k] = t;
-                }
-                if (k < 3) {
-                    a += q8[k + PS] - q8[k];
-                    t += q16[k + PS] - q16[k];
-                }
-            }
-        }
-        __syncthreads();
-        const int nr4 = (uh + 3) >> 2;
-        for (int e = tid; e < nr4 * uw; e += BMT) {
-            const int r4 = 4 * (e / uw), col = e - (r4 >> 2) * uw;
-            int c8[11], c16[11];
-#pragma unroll
-            for (int i = 0; i < 11; ++i) {
-                c8[i] = rs8[(r4 + i) * uw + col];
-                c16[i] = rs16[(r4 + i) * uw + col];
-            }
-            int a = 0, t = 0;
-#pragma unroll
-            for (int i = 0; i < PS; ++i) {
-                a += c8[i];
-                t += c16[i];
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (r4 + k < uh) {
-                    n8[(r4 + k) * uw + col] = a;
-                    n16[(r4 + k) * uw + col] = t;
-                }
-                if (k < 3) {
-                    a += c8[k + PS] - c8[k];
-                    t += c16[k + PS] - c16[k];
-                }
-            }
-        }
-        __syncthreads();
-    }
-
-    // ---- distances on the matrix cores ----
-    {
-      if (fi == 0) {
-        // A fragments: reference i16, rows 2q, 2q+1 (int8) and rows q, q+4 (fp16).
-        int ar = ti.ry[i16] >= 0 ? ti.ry[i16] - uy0 : 0;
-        int ac = ti.ry[i16] >= 0 ? ti.rx[i16] - ux0 : 0;
+        // ---- stage the shifted planes: one thread per (row, group of 4 columns) ----
+        // Dword w of int8 copy k holds the row's pixels 4w + k .. 4w + k + 3, and halves 4w .. 4w + 3
+        // of fp16 copy k hold the pixels 4w + k .. 4w + k + 3, so a thread needs pixels 4w .. 4w + 6.
+        // Bytes at or beyond the staged width pcol are never read (candidates end at pcol - 1).
         {
-            const int k = ac & 3;
-            const unsigned char *base = p8 + k * plane8;
-            const int o0 = (ar + 2 * q) * L.pitch8 + ac - k, o1 = o0 + L.pitch8;
-            a8[0] = (int)lds_u32(base, o0); a8[1] = (int)lds_u32(base, o0 + 4);
-            a8[2] = (int)lds_u32(base, o1); a8[3] = (int)lds_u32(base, o1 + 4);
-        }
-        any_sum = ti.any_sum != 0;
-        if (any_sum) {
-            const int k = ac & 1;
-            const _Float16 *base = p16 + k * plane16;
-            const _Float16 *ra = base + (ar + q) * L.pitch16 + ac - k;
-            const _Float16 *rb = base + (ar + q + 4) * L.pitch16 + ac - k;
+            const int nw = (pcol + 3) >> 2;
+            const uint8_t *img_end = fimg + (int64_t)(g.h - 1) * g.stride + (int64_t)g.w * g.c;
+            uint32_t *p8w = reinterpret_cast<uint32_t *>(p8);
+            uint32_t *p16w = reinterpret_cast<uint32_t *>(p16);
+            for (int e = tid; e < prow * nw; e += BMT) {
+                const int r = e / nw, w4 = 4 * (e - r * nw);
+                const int npx = min(7, pcol - w4);
+                const uint8_t *a = fimg + (int64_t)(uy0 + r) * g.stride + (int64_t)(ux0 + w4) * g.c;
+                uint32_t raw[6];   // bytes 0 .. 23 from a
+                const uintptr_t ai = (uintptr_t)a;
+                const uint32_t *ab = reinterpret_cast<const uint32_t *>(ai & ~(uintptr_t)3);
+                if (npx == 7 && (const uint8_t *)(ab + 7) <= img_end) {
+                    const uint32_t sh = (uint32_t)(ai & 3);
+                    uint32_t d[7];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) { a16a[t] = ra[t]; a16b[t] = rb[t]; }
-        }
-        // Per-lane info of the 4 references this lane's accumulators belong to.
+                    for (int i = 0; i < 7; ++i) d[i] = ab[i];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int ii = 4 * q + r;
-            rwy0[r] = ti.wy0[ii]; rwx0[r] = ti.wx0[ii];
-            rwh[r] = ti.wh[ii]; rww[r] = ti.ww[ii];
-            rgreen[r] = ti.green[ii];
-            if (ti.ry[ii] >= 0) {
-                const int pe = (ti.ry[ii] - uy0) * uw + (ti.rx[ii] - ux0);
-                rn[r] = rgreen[r] ? n8[pe] : n16[pe];
-            } else {
-                rn[r] = 0;
-                rwh[r] = 0;
-            }
-        }
-      }
-      if constexpr (VIDEO) {
-        // reloaded for every frame: only the norms and the A fragments stay live across frames
+                    for (int i = 0; i < 6; ++i) raw[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
+                } else {   // row end: only the pixels that exist, byte by byte
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int ii = 4 * q + r;
-            rwy0[r] = ti.wy0[ii]; rwx0[r] = ti.wx0[ii];
-            rwh[r] = ti.ry[ii] >= 0 ? ti.wh[ii] : 0; rww[r] = ti.ww[ii];
-            rgreen[r] = ti.green[ii];
+                    for (int i = 0; i < 6; ++i) raw[i] = 0u;
+                    const int nb = npx * g.c;
+                    for (int b = 0; b < nb; ++b) raw[b >> 2] |= (uint32_t)a[b] << (8 * (b & 3));
+                }
+                auto byte_at = [&](int i) { return (int)((raw[i >> 2] >> (8 * (i & 3))) & 0xffu); };
+                int v8[7], vs[7];
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    if (g.c == 3) {
+                        const int R = byte_at(3 * q), G = byte_at(3 * q + 1), B = byte_at(3 * q + 2);
+                        v8[q] = G - 128;
+                        vs[q] = R + G + B - 384;
+                    } else {
+                        v8[q] = byte_at(q) - 128;
+                        vs[q] = 0;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    p8w[(k * plane8 + r * L.pitch8 + w4) >> 2] =
+                        (uint32_t)(uint8_t)v8[k] | ((uint32_t)(uint8_t)v8[k + 1] << 8) |
+                        ((uint32_t)(uint8_t)v8[k + 2] << 16) | ((uint32_t)(uint8_t)v8[k + 3] << 24);
+                if (g.c == 3) {
+#pragma unroll
+                    for (int k = 0; k < 2; ++k)
+#pragma unroll
+                        for (int hh = 0; hh < 2; ++hh) {
+                            const uint32_t lo = __builtin_bit_cast(uint16_t, (_Float16)vs[2 * hh + k]);
+                            const uint32_t hi = __builtin_bit_cast(uint16_t, (_Float16)vs[2 * hh + k + 1]);
+                            p16w[(k * plane16 + r * L.pitch16 + w4 + 2 * hh) >> 1] = lo | (hi << 16);
+                        }
+                }
+            }
         }
-      }
-        const int nU = uh * uw;
-        const int nchunks = (nU + 15) >> 4;
-        // candidate j = 16 chunk + i16 at (row, column) = (j / uw, j % uw), stepped by 16 BMW
-        constexpr int JSTEP = 16 * BMW;
-        const int step_r = JSTEP / uw, step_c = JSTEP % uw;
-        int jr = (16 * wave + i16) / uw, jc = (16 * wave + i16) % uw;
-        for (int chunk = wave; chunk < nchunks; chunk += BMW) {
-            const int j = chunk * 16 + i16;
-            const int cr = j < nU ? jr : 0, cc = j < nU ? jc : 0;
-            jr += step_r;
-            jc += step_c;
-            if (jc >= uw) {
-                jc -= uw;
-                ++jr;
+        __syncthreads();
+        if (fi == 0 && tid == 0) {   // read after the norm phase's barriers
+            int any = 0;
+            for (int i = 0; i < NREF; ++i) any |= (ti.ry[i] >= 0 && !ti.green[i]);
+            ti.any_sum = any;
+        }
+
+        // ---- squared norms at every candidate position (horizontal then vertical 8-sums) ----
+        // Four consecutive outputs per thread from one window of 11 values, sliding (exact integers).
+        // Reads past the last valid output stay inside the staged planes and the table; the
+        // outputs they feed are not stored.
+        {
+            int32_t *rs8 = reinterpret_cast<int32_t *>(tab);          // prow x uw, tab is free now
+            int32_t *rs16 = rs8 + prow * uw;
+            const int ng = (uw + 3) >> 2;
+            for (int e = tid; e < prow * ng; e += BMT) {
+                const int r = e / ng, c0 = 4 * (e - r * ng);
+                int q8[11], q16[11];
+                {
+                    const uint32_t *w8 = reinterpret_cast<const uint32_t *>(p8 + r * L.pitch8 + c0);
+                    const uint32_t b[3] = {w8[0], w8[1], w8[2]};
+#pragma unroll
+                    for (int j = 0; j < 11; ++j) {
+                        const int v = (int)(int8_t)(b[j >> 2] >> (8 * (j & 3)));
+                        q8[j] = v * v;
+                    }
+                }
+                if (g.c == 3) {
+                    const uint32_t *w16 = reinterpret_cast<const uint32_t *>(p16 + r * L.pitch16 + c0);
+                    uint32_t b[6];
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) b[i] = w16[i];
+#pragma unroll
+                    for (int j = 0; j < 11; ++j) {
+                        const int t = (int)__builtin_bit_cast(_Float16, (uint16_t)(b[j >> 1] >> (16 * (j & 1))));
+                        q16[j] = t * t;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 11; ++j) q16[j] = 0;
+                }
+                int a = 0, t = 0;
+#pragma unroll
+                for (int j = 0; j < PS; ++j) {
+                    a += q8[j];
+                    t += q16[j];
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (c0 + k < uw) {
+                        rs8[r * uw + c0 + k] = a;
+                        rs16[r * uw + c0 + k] = t;
+                    }
+                    if (k < 3) {
+                        a += q8[k + PS] - q8[k];
+                        t += q16[k + PS] - q16[k];
+                    }
+                }
             }
-            v4i b8;
-            {
-                const int k = cc & 3;
-                const unsigned char *base = p8 + k * plane8;
-                const int o0 = (cr + 2 * q) * L.pitch8 + cc - k, o1 = o0 + L.pitch8;
-                b8[0] = (int)lds_u32(base, o0); b8[1] = (int)lds_u32(base, o0 + 4);
-                b8[2] = (int)lds_u32(base, o1); b8[3] = (int)lds_u32(base, o1 + 4);
+            __syncthreads();
+            const int nr4 = (uh + 3) >> 2;
+            for (int e = tid; e < nr4 * uw; e += BMT) {
+                const int r4 = 4 * (e / uw), col = e - (r4 >> 2) * uw;
+                int c8[11], c16[11];
+#pragma unroll
+                for (int i = 0; i < 11; ++i) {
+                    c8[i] = rs8[(r4 + i) * uw + col];
+                    c16[i] = rs16[(r4 + i) * uw + col];
+                }
+                int a = 0, t = 0;
+#pragma unroll
+                for (int i = 0; i < PS; ++i) {
+                    a += c8[i];
+                    t += c16[i];
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (r4 + k < uh) {
+                        n8[(r4 + k) * uw + col] = a;
+                        n16[(r4 + k) * uw + col] = t;
+                    }
+                    if (k < 3) {
+                        a += c8[k + PS] - c8[k];
+                        t += c16[k + PS] - c16[k];
+                    }
+                }
             }
-            v4i acc8 = {0, 0, 0, 0};
-            acc8 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a8, b8, acc8, 0, 0, 0);
-            v4f acc16 = {0.f, 0.f, 0.f, 0.f};
-            if (any_sum) {
-                // 8 halves from the copy in which they start on a dword (pitch and offsets even)
-                const int k = cc & 1;
-                const _Float16 *base = p16 + k * plane16;
-                const uint32_t *ra = reinterpret_cast<const uint32_t *>(base + (cr + q) * L.pitch16 + cc - k);
-                const uint32_t *rb = reinterpret_cast<const uint32_t *>(base + (cr + q + 4) * L.pitch16 + cc - k);
-                const v8h b16a = __builtin_bit_cast(v8h, make_uint4(ra[0], ra[1], ra[2], ra[3]));
-                const v8h b16b = __builtin_bit_cast(v8h, make_uint4(rb[0], rb[1], rb[2], rb[3]));
-                acc16 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a16a, b16a, acc16, 0, 0, 0);
-                acc16 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a16b, b16b, acc16, 0, 0, 0);
-            }
-            if (j < nU) {
-                const int cy = uy0 + cr, cx = ux0 + cc;
-                const int nb8 = n8[j], nb16 = n16[j];
+            __syncthreads();
+        }
+
+        // ---- distances on the matrix cores ----
+        {
+            if (fi == 0) {
+                // A fragments: reference i16, rows 2q, 2q+1 (int8) and rows q, q+4 (fp16).
+                int ar = ti.ry[i16] >= 0 ? ti.ry[i16] - uy0 : 0;
+                int ac = ti.ry[i16] >= 0 ? ti.rx[i16] - ux0 : 0;
+                {
+                    const int k = ac & 3;
+                    const unsigned char *base = p8 + k * plane8;
+                    const int o0 = (ar + 2 * q) * L.pitch8 + ac - k, o1 = o0 + L.pitch8;
+                    a8[0] = (int)lds_u32(base, o0); a8[1] = (int)lds_u32(base, o0 + 4);
+                    a8[2] = (int)lds_u32(base, o1); a8[3] = (int)lds_u32(base, o1 + 4);
+                }
+                any_sum = ti.any_sum != 0;
+                if (any_sum) {
+                    const int k = ac & 1;
+                    const _Float16 *base = p16 + k * plane16;
+                    const _Float16 *ra = base + (ar + q) * L.pitch16 + ac - k;
+                    const _Float16 *rb = base + (ar + q + 4) * L.pitch16 + ac - k;
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) { a16a[t] = ra[t]; a16b[t] = rb[t]; }
+                }
+                // Per-lane info of the 4 references this lane's accumulators belong to.
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int dy = cy - rwy0[r], dx = cx - rwx0[r];
-                    if ((unsigned)dy < (unsigned)rwh[r] && (unsigned)dx < (unsigned)rww[r]) {
-                        const int d = rgreen[r] ? rn[r] + nb8 - 2 * acc8[r] : rn[r] + nb16 - 2 * (int)acc16[r];
-                        tab[(4 * q + r) * MAX_CAND + dy * rww[r] + dx] = (uint32_t)d;
+                    const int ii = 4 * q + r;
+                    rwy0[r] = ti.wy0[ii]; rwx0[r] = ti.wx0[ii];
+                    rwh[r] = ti.wh[ii]; rww[r] = ti.ww[ii];
+                    rgreen[r] = ti.green[ii];
+                    if (ti.ry[ii] >= 0) {
+                        const int pe = (ti.ry[ii] - uy0) * uw + (ti.rx[ii] - ux0);
+                        rn[r] = rgreen[r] ? n8[pe] : n16[pe];
+                    } else {
+                        rn[r] = 0;
+                        rwh[r] = 0;
+                    }
+                }
+            }
+            if constexpr (VIDEO) {
+                // reloaded for every frame: only the norms and the A fragments stay live across frames
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int ii = 4 * q + r;
+                    rwy0[r] = ti.wy0[ii]; rwx0[r] = ti.wx0[ii];
+                    rwh[r] = ti.ry[ii] >= 0 ? ti.wh[ii] : 0; rww[r] = ti.ww[ii];
+                    rgreen[r] = ti.green[ii];
+                }
+            }
+            const int nU = uh * uw;
+            const int nchunks = (nU + 15) >> 4;
+            // candidate j = 16 chunk + i16 at (row, column) = (j / uw, j % uw), stepped by 16 BMW
+            constexpr int JSTEP = 16 * BMW;
+            const int step_r = JSTEP / uw, step_c = JSTEP % uw;
+            int jr = (16 * wave + i16) / uw, jc = (16 * wave + i16) % uw;
+            for (int chunk = wave; chunk < nchunks; chunk += BMW) {
+                const int j = chunk * 16 + i16;
+                const int cr = j < nU ? jr : 0, cc = j < nU ? jc : 0;
+                jr += step_r;
+                jc += step_c;
+                if (jc >= uw) {
+                    jc -= uw;
+                    ++jr;
+                }
+                v4i b8;
+                {
+                    const int k = cc & 3;
+                    const unsigned char *base = p8 + k * plane8;
+                    const int o0 = (cr + 2 * q) * L.pitch8 + cc - k, o1 = o0 + L.pitch8;
+                    b8[0] = (int)lds_u32(base, o0); b8[1] = (int)lds_u32(base, o0 + 4);
+                    b8[2] = (int)lds_u32(base, o1); b8[3] = (int)lds_u32(base, o1 + 4);
+                }
+                v4i acc8 = {0, 0, 0, 0};
+                acc8 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a8, b8, acc8, 0, 0, 0);
+                v4f acc16 = {0.f, 0.f, 0.f, 0.f};
+                if (any_sum) {
+                    // 8 halves from the copy in which they start on a dword (pitch and offsets even)
+                    const int k = cc & 1;
+                    const _Float16 *base = p16 + k * plane16;
+                    const uint32_t *ra = reinterpret_cast<const uint32_t *>(base + (cr + q) * L.pitch16 + cc - k);
+                    const uint32_t *rb = reinterpret_cast<const uint32_t *>(base + (cr + q + 4) * L.pitch16 + cc - k);
+                    const v8h b16a = __builtin_bit_cast(v8h, make_uint4(ra[0], ra[1], ra[2], ra[3]));
+                    const v8h b16b = __builtin_bit_cast(v8h, make_uint4(rb[0], rb[1], rb[2], rb[3]));
+                    acc16 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a16a, b16a, acc16, 0, 0, 0);
+                    acc16 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a16b, b16b, acc16, 0, 0, 0);
+                }
+                if (j < nU) {
+                    const int cy = uy0 + cr, cx = ux0 + cc;
+                    const int nb8 = n8[j], nb16 = n16[j];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int dy = cy - rwy0[r], dx = cx - rwx0[r];
+                        if ((unsigned)dy < (unsigned)rwh[r] && (unsigned)dx < (unsigned)rww[r]) {
+                            const int d = rgreen[r] ? rn[r] + nb8 - 2 * acc8[r] : rn[r] + nb16 - 2 * (int)acc16[r];
+                            tab[(4 * q + r) * MAX_CAND + dy * rww[r] + dx] = (uint32_t)d;
+                        }
                     }
                 }
             }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // ---- top-K per reference ----
-    uint64_t *sel = reinterpret_cast<uint64_t *>(smem + L.off_sel) + wave * SEL_CAP;
-    for (int ii = wave; ii < NREF; ii += BMW) {
-        if (ti.ry[ii] < 0) continue;
-        const int n = ti.wh[ii] * ti.ww[ii];
-        const uint32_t *row = tab + ii * MAX_CAND;
-        // this lane's candidates p = lane + 64 i, read once; key = (distance, position)
-        constexpr int NPL = (MAX_CAND + 63) / 64;
-        uint32_t dv[NPL];
-        uint32_t dmin = 0xFFFFFFFFu;   // valid distances are below 2^26
+        // ---- top-K per reference ----
+        uint64_t *sel = reinterpret_cast<uint64_t *>(smem + L.off_sel) + wave * SEL_CAP;
+        for (int ii = wave; ii < NREF; ii += BMW) {
+            if (ti.ry[ii] < 0) continue;
+            const int n = ti.wh[ii] * ti.ww[ii];
+            const uint32_t *row = tab + ii * MAX_CAND;
+            // this lane's candidates p = lane + 64 i, read once; key = (distance, position)
+            constexpr int NPL = (MAX_CAND + 63) / 64;
+            uint32_t dv[NPL];
+            uint32_t dmin = 0xFFFFFFFFu;   // valid distances are below 2^26
 #pragma unroll
-        for (int i = 0; i < NPL; ++i) {
-            const int p = lane + 64 * i;
-            dv[i] = p < n ? row[p] : 0xFFFFFFFFu;
-            dmin = min(dmin, dv[i]);
-        }
-        // the lane's smallest key: its smallest distance at the first (smallest) position
-        int pmin = 0;
-#pragma unroll
-        for (int i = NPL - 1; i >= 0; --i) pmin = dv[i] == dmin ? lane + 64 * i : pmin;
-        const uint64_t lmin = dmin == 0xFFFFFFFFu ? ~0ull : (((uint64_t)dmin << 10) | (uint64_t)pmin);
-        const uint64_t sorted = wave_sort64(lmin, lane);
-        const uint64_t theta = readlane_u64(sorted, K - 1);
-        int cnt = 0;
-#pragma unroll
-        for (int i = 0; i < NPL; ++i) {
-            const int p = lane + 64 * i;
-            cnt += (p < n && (((uint64_t)dv[i] << 10) | (uint64_t)p) <= theta);
-        }
-        int total;
-        int off = wave_excl_scan(cnt, lane, &total);
-#pragma unroll
-        for (int i = 0; i < NPL; ++i) {
-            const int p = lane + 64 * i;
-            const uint64_t key = ((uint64_t)dv[i] << 10) | (uint64_t)p;
-            if (p < n && key <= theta) sel[off++] = key;
-        }
-        wave_lds_sync();
-        uint64_t mine;
-        if (total <= 64) {
-            uint64_t v = lane < total ? sel[lane] : ~0ull;
-            mine = wave_sort64(v, lane);
-        } else {
-            int P = 64;
-            while (P < total) P <<= 1;
-            for (int t = total + lane; t < P; t += 64) sel[t] = ~0ull;
-            wave_lds_sync();
-            lds_sort(sel, P, lane);
-            mine = lane < K ? sel[lane] : ~0ull;
-        }
-        if constexpr (VIDEO) {
-            // merge into the running list: keys (distance, frame slot, position); only this wave
-            // touches reference ii's list
-            uint64_t v = lane < K ? (((mine >> 10) << 16) | ((uint64_t)slot << 10) | (mine & 1023u)) : ~0ull;
-            if (fi > 0) {
-                if (lane >= K && lane < 2 * K) v = run[ii * RUN_K + lane - K];
-                v = wave_sort64(v, lane);
+            for (int i = 0; i < NPL; ++i) {
+                const int p = lane + 64 * i;
+                dv[i] = p < n ? row[p] : 0xFFFFFFFFu;
+                dmin = min(dmin, dv[i]);
             }
-            if (lane < K) run[ii * RUN_K + lane] = v;
-        } else if (lane < K) {
-            const int p = (int)(mine & 1023u);
-            const int y = ti.wy0[ii] + p / ti.ww[ii], x = ti.wx0[ii] + p % ti.ww[ii];
-            const int iy = tyi * REF_TILE + ii / REF_TILE, ix = txi * REF_TILE + ii % REF_TILE;
-            const int64_t r = (int64_t)iy * g.nx + ix;
-            idx_out[r * K + lane] = y * g.w + x;
-            if (dist_out) dist_out[r * K + lane] = (int32_t)(mine >> 10);
+            // the lane's smallest key: its smallest distance at the first (smallest) position
+            int pmin = 0;
+#pragma unroll
+            for (int i = NPL - 1; i >= 0; --i) pmin = dv[i] == dmin ? lane + 64 * i : pmin;
+            const uint64_t lmin = dmin == 0xFFFFFFFFu ? ~0ull : (((uint64_t)dmin << 10) | (uint64_t)pmin);
+            const uint64_t sorted = wave_sort64(lmin, lane);
+            const uint64_t theta = readlane_u64(sorted, K - 1);
+            int cnt = 0;
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) {
+                const int p = lane + 64 * i;
+                cnt += (p < n && (((uint64_t)dv[i] << 10) | (uint64_t)p) <= theta);
+            }
+            int total;
+            int off = wave_excl_scan(cnt, lane, &total);
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) {
+                const int p = lane + 64 * i;
+                const uint64_t key = ((uint64_t)dv[i] << 10) | (uint64_t)p;
+                if (p < n && key <= theta) sel[off++] = key;
+            }
+            wave_lds_sync();
+            uint64_t mine;
+            if (total <= 64) {
+                uint64_t v = lane < total ? sel[lane] : ~0ull;
+                mine = wave_sort64(v, lane);
+            } else {
+                int P = 64;
+                while (P < total) P <<= 1;
+                for (int t = total + lane; t < P; t += 64) sel[t] = ~0ull;
+                wave_lds_sync();
+                lds_sort(sel, P, lane);
+                mine = lane < K ? sel[lane] : ~0ull;
+            }
+            if constexpr (VIDEO) {
+                // merge into the running list: keys (distance, frame slot, position); only this wave
+                // touches reference ii's list
+                uint64_t v = lane < K ? (((mine >> 10) << 16) | ((uint64_t)slot << 10) | (mine & 1023u)) : ~0ull;
+                if (fi > 0) {
+                    if (lane >= K && lane < 2 * K) v = run[ii * RUN_K + lane - K];
+                    v = wave_sort64(v, lane);
+                }
+                if (lane < K) run[ii * RUN_K + lane] = v;
+            } else if (lane < K) {
+                const int p = (int)(mine & 1023u);
+                const int y = ti.wy0[ii] + p / ti.ww[ii], x = ti.wx0[ii] + p % ti.ww[ii];
+                const int iy = tyi * REF_TILE + ii / REF_TILE, ix = txi * REF_TILE + ii % REF_TILE;
+                const int64_t r = (int64_t)iy * g.nx + ix;
+                idx_out[r * K + lane] = y * g.w + x;
+                if (dist_out) dist_out[r * K + lane] = (int32_t)(mine >> 10);
+            }
+            wave_lds_sync();
         }
-        wave_lds_sync();
-    }
     }   // frames
 
     if constexpr (VIDEO) {
