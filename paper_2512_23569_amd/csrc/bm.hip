@@ -493,6 +493,37 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g0, const MethodParams 
                 dv[i] = p < n ? row[p] : 0xFFFFFFFFu;
                 dmin = min(dmin, dv[i]);
             }
+            if constexpr (VIDEO) {
+                if (fi > 0) {
+                    // Only keys below the running K-th can enter the list.  When at most 64 - K of
+                    // this frame's candidates are, one sort of them with the list is the merge.
+                    const uint64_t th = run[ii * RUN_K + K - 1];
+                    const uint64_t sk = (uint64_t)slot << 10;
+                    int cnt = 0;
+#pragma unroll
+                    for (int i = 0; i < NPL; ++i) {
+                        const int p = lane + 64 * i;
+                        cnt += (p < n && (((uint64_t)dv[i] << 16) | sk | (uint64_t)p) < th);
+                    }
+                    int total;
+                    int off = wave_excl_scan(cnt, lane, &total);
+                    if (total <= 64 - K) {
+#pragma unroll
+                        for (int i = 0; i < NPL; ++i) {
+                            const int p = lane + 64 * i;
+                            const uint64_t key = ((uint64_t)dv[i] << 16) | sk | (uint64_t)p;
+                            if (p < n && key < th) sel[off++] = key;
+                        }
+                        wave_lds_sync();
+                        uint64_t v = lane < total ? sel[lane]
+                                                  : (lane < total + K ? run[ii * RUN_K + lane - total] : ~0ull);
+                        v = wave_sort64(v, lane);
+                        if (lane < K) run[ii * RUN_K + lane] = v;
+                        wave_lds_sync();
+                        continue;
+                    }
+                }
+            }
             // the lane's smallest key: its smallest distance at the first (smallest) position
             int pmin = 0;
 #pragma unroll
