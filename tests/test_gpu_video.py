@@ -212,6 +212,31 @@ def test_video_learned_estimator_frame_by_frame():
         d.close()
 
 
+def test_video_padded_strides_through_the_c_abi(dn):
+    """Row strides wider than the frames, for the input and the output, through the C entry
+    points: the same groups and the same output bit for bit as the contiguous call."""
+    import paper_2512_23569_amd as ht
+    T, h, w, c, radius = 3, 40, 44, 3, 1
+    v = synth.add_awgn(synth.make_video(T, h, w, c, 190), 30.0, 191)
+    p = dn.params(c, stride=4, window=13, K=16)
+    idx, dist = dn.block_match_video(_dev(v), p, radius)
+    out = dn.denoise_video(_dev(v), 30.0, p, radius)
+    in_stride, out_stride = w * c + 20, w * c + 9
+    padded = np.full((T * h, in_stride), 7, np.uint8)
+    padded[:, :w * c] = v.reshape(T * h, w * c)
+    d_pad = _dev(padded)
+    n_ref = idx.shape[0]
+    idx2 = torch.empty((n_ref, 16), dtype=torch.int32, device="cuda")
+    dist2 = torch.empty((n_ref, 16), dtype=torch.int32, device="cuda")
+    ht.htsvd_block_match_video(dn.ctx, d_pad, T, h, w, c, in_stride, radius, p, idx2, dist2)
+    out2 = torch.full((T * h, out_stride), -5.0, dtype=torch.float32, device="cuda")
+    ht.htsvd_denoise_video(dn.ctx, d_pad, T, h, w, c, in_stride, radius, 30.0, p, out2, out_stride)
+    torch.cuda.synchronize()
+    assert torch.equal(idx, idx2) and torch.equal(dist, dist2)
+    assert torch.equal(out.reshape(T * h, w * c), out2[:, :w * c])
+    assert torch.all(out2[:, w * c:] == -5.0)   # the padding of the output is not written
+
+
 def test_video_errors(dn):
     import paper_2512_23569_amd as ht
     v = _dev(synth.make_video(2, 32, 32, 3, 160))
