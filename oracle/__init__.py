@@ -287,4 +287,5 @@ def load_basis(path: str, ps: int, c: int):
 
 from .estimator import (sigma_est_tiles, chen_tail_sigma2, circulant_spectrum, rank_position,  # noqa: E402
                         vote_samples, sigma_hat_tiles, splitmix64, tile_of_refs, tau_per_ref, band_sigma,
-                        band_sigma_rule)
+                        band_sigma_rule, learned_judge, thresholds, effective_sigma_map,
+                        tau_from_sigma_map, auto_group_size)

@@ -206,6 +206,149 @@ def tau_per_ref(sigma_tiles: np.ndarray, h: int, w: int, ps: int, s: int, c: int
     return np.asarray(sigma_tiles, dtype=np.float64)[tiles] * m
 
 
+# ---- learned noise map -> thresholds (Sec. III-E-1, Eq. 22-23) ------------------------------
+# The paper feeds a CNN's noise estimate into the thresholds and adjusts it per sub-image with
+# the vote of Eq. 23.  Its CNN is not available; the library's network predicts z = log(sigma)
+# for every 8x8 block instead.  The rule below is the reading the library implements:
+#   judge   per 128 x 128 sub-image t, the mean learned sigma m_t over the blocks of t is kept
+#           when sp_t / 1.5 <= m_t <= 1.5 sp_t (sp_t the plain estimate of t; m_t finite and
+#           positive), otherwise the plain estimate stands for the tile: sigma_est_t = m_t or sp_t;
+#   vote    Eq. 23 with sigma_est_t (votes from the tile's sampled groups): sigma_hat_t equals
+#           sigma_est_t / beta on a majority, else sigma_est_t; the vote factor is their ratio;
+#   block   the effective sigma of block b in tile t is exp(z_b) times the vote factor of t where
+#           t kept the map, sigma_hat_t where it did not;
+#   tau     a reference's threshold is the effective sigma of the block holding its top-left
+#           pixel times sqrt(2 ln(c K ps^2)).
+# A block lies in exactly one sub-image because 128 is a multiple of 8.
+
+JUDGE_BOUND = 1.5
+
+
+def blocks_of_tile(t: int, h: int, w: int, T: int = 128, B: int = 8):
+    """Block rows and columns [by0, by1) x [bx0, bx1) of sub-image t (edge tiles partial)."""
+    nty, ntx = tile_grid(h, w, T)
+    ty, tx = divmod(t, ntx)
+    hb, wb = -(-h // B), -(-w // B)
+    bpt = T // B
+    return ty * bpt, min(hb, (ty + 1) * bpt), tx * bpt, min(wb, (tx + 1) * bpt)
+
+
+def judge_tile_sigma(block_sigma: np.ndarray, sp: float, bound: float = JUDGE_BOUND):
+    """The judge on one tile given its blocks' learned sigma values: (sigma_est, use_plain).
+    The mean is the correctly rounded sum (math.fsum) over the number of blocks."""
+    import math
+    v = np.asarray(block_sigma, dtype=np.float64).reshape(-1)
+    mean = math.fsum(v.tolist()) / v.size if v.size else 0.0
+    ok = math.isfinite(mean) and mean > 0.0 and sp > 0.0 and mean <= bound * sp and mean * bound >= sp
+    return (mean, False) if ok else (float(sp), True)
+
+
+def learned_judge(z: np.ndarray, sigma_plain: np.ndarray, h: int, w: int, T: int = 128,
+                  bound: float = JUDGE_BOUND):
+    """Per sub-image: (sigma_est, use_plain) of the learned map z (ceil(h/8) x ceil(w/8) log sigma)
+    judged by the plain estimates sigma_plain."""
+    z = np.asarray(z, dtype=np.float64)
+    nty, ntx = tile_grid(h, w, T)
+    se = np.zeros(nty * ntx)
+    up = np.zeros(nty * ntx, dtype=bool)
+    for t in range(nty * ntx):
+        by0, by1, bx0, bx1 = blocks_of_tile(t, h, w, T)
+        se[t], up[t] = judge_tile_sigma(np.exp(z[by0:by1, bx0:bx1]), float(sigma_plain[t]), bound)
+    return se, up
+
+
+def vote_factor(votes: np.ndarray, nvotes: np.ndarray, beta: float = 1.2) -> np.ndarray:
+    """Eq. 23 as a factor per tile: 1/beta where most sampled groups voted "adjust", else 1."""
+    votes, nvotes = np.asarray(votes), np.asarray(nvotes)
+    return np.where(2 * votes > nvotes, 1.0 / beta, 1.0)
+
+
+def effective_sigma_map(h: int, w: int, sigma_hat: np.ndarray, T: int = 128, z=None, use_plain=None,
+                        factor=None) -> np.ndarray:
+    """Effective sigma per 8x8 block (ceil(h/8) x ceil(w/8)): sigma_hat of the block's tile, or
+    exp(z) of the block times the tile's vote factor where the tile kept the learned map."""
+    nty, ntx = tile_grid(h, w, T)
+    hb, wb = -(-h // 8), -(-w // 8)
+    out = np.zeros((hb, wb))
+    for t in range(nty * ntx):
+        by0, by1, bx0, bx1 = blocks_of_tile(t, h, w, T)
+        if z is None or use_plain[t]:
+            out[by0:by1, bx0:bx1] = sigma_hat[t]
+        else:
+            out[by0:by1, bx0:bx1] = np.exp(np.asarray(z, dtype=np.float64)[by0:by1, bx0:bx1]) * factor[t]
+    return out
+
+
+def tau_from_sigma_map(smap: np.ndarray, h: int, w: int, ps: int, s: int, c: int, K: int,
+                       mult: float | None = None) -> np.ndarray:
+    """tau of every reference r = iy*nx + ix: the effective sigma of the block holding its
+    top-left pixel times the multiplier."""
+    from . import ref_grid, tau_multiplier
+    ys, xs = ref_grid(h, ps, s), ref_grid(w, ps, s)
+    m = tau_multiplier(c, K, ps) if mult is None else mult
+    return (np.asarray(smap)[(ys // 8)[:, None], (xs // 8)[None, :]] * m).reshape(-1)
+
+
+def thresholds(img: np.ndarray, ps: int, s: int, W: int, K: int, z=None, adaptive: bool = True, T: int = 128,
+               n_vote: int = 15, seed: int = 0, beta: float = 1.2, gamma: int = 13, mult: float | None = None,
+               sigma_known: float | None = None, tiles=None):
+    """The noise-level rule on one image, from the pixels to the per-reference thresholds:
+    sigma_est per sub-image (the known level, the plain estimate, or with a learned map z the
+    judged level), the Eq. 23 vote on it (oracle groups of the sampled voters), the effective
+    sigma per 8x8 block and tau per reference.  `tiles` restricts the work to those sub-images
+    (entries of the others are NaN; references outside them get tau NaN).
+    Returns a dict with sigma_plain, sigma_est, use_plain, votes, nvotes, sigma_hat, map, tau."""
+    from . import block_match_list, ref_grid
+    a = img if img.ndim == 3 else img[:, :, None]
+    h, w, c = a.shape
+    nty, ntx = tile_grid(h, w, T)
+    todo = list(range(nty * ntx)) if tiles is None else sorted(set(int(t) for t in tiles))
+    nan = np.full(nty * ntx, np.nan)
+    sp = nan.copy()
+    if sigma_known is not None:
+        sp[todo] = float(sigma_known)
+    else:
+        sp[todo] = sigma_est_tiles(img, T, ps, tiles=todo)[todo]
+    se, up = sp.copy(), np.zeros(nty * ntx, dtype=bool)
+    if z is not None and sigma_known is None:
+        zz = np.asarray(z, dtype=np.float64)
+        for t in todo:
+            by0, by1, bx0, bx1 = blocks_of_tile(t, h, w, T)
+            se[t], up[t] = judge_tile_sigma(np.exp(zz[by0:by1, bx0:bx1]), float(sp[t]))
+    votes = np.zeros(nty * ntx, dtype=np.int64)
+    nvotes = np.zeros(nty * ntx, dtype=np.int64)
+    if adaptive:
+        ys, xs = ref_grid(h, ps, s), ref_grid(w, ps, s)
+        tile_of = tile_of_refs(ys, xs, h, w, T)
+        for t in todo:
+            refs = np.nonzero(tile_of == t)[0]
+            if refs.size == 0:
+                continue
+            voters = vote_samples(refs, t, n_vote, seed)
+            gi, _ = block_match_list(img, voters, ps, s, W, K)
+            votes[t] = sum(rank_position(group_vectors(img, gi[i], ps)) <= gamma for i in range(len(voters)))
+            nvotes[t] = len(voters)
+    f = vote_factor(votes, nvotes, beta)
+    sh = np.where(2 * votes > nvotes, se / beta, se)
+    learned = z is not None and sigma_known is None
+    smap = effective_sigma_map(h, w, sh, T, z=z if learned else None, use_plain=up, factor=f)
+    for t in sorted(set(range(nty * ntx)) - set(todo)):
+        by0, by1, bx0, bx1 = blocks_of_tile(t, h, w, T)
+        smap[by0:by1, bx0:bx1] = np.nan
+    tau = tau_from_sigma_map(smap, h, w, ps, s, c, K, mult)
+    return {"sigma_plain": sp, "sigma_est": se, "use_plain": up, "votes": votes, "nvotes": nvotes,
+            "sigma_hat": sh, "map": smap, "tau": tau}
+
+
+def auto_group_size(sigma_ref: np.ndarray, cutoff: float) -> int:
+    """Group size of an image in the batched auto mode (the library's reading: the K-selection
+    of Sec. IV-A made per image): 16 when the mean effective sigma over its references lies below
+    the cutoff, else 32."""
+    import math
+    v = np.asarray(sigma_ref, dtype=np.float64).reshape(-1)
+    return 16 if math.fsum(v.tolist()) / v.size < cutoff else 32
+
+
 def band_sigma(cube: np.ndarray, T: int = 128, ps: int = 8) -> np.ndarray:
     """Band-wise noise levels of a cube (h, w, B) (Sec. IV-D): sigma_b is the mean, over the
     band's T x T sub-images, of the plain estimate sigma_est of the band alone."""
