@@ -37,7 +37,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed); 78.6 without packed FP32
+# MI355X published FP32 vector peak, 157.3 TFLOP/s, counts packed FP32 (two values per
+# instruction).  The library is built with packed FP32 switched off, so its vector code can reach
+# at most half of it, 78.6 TFLOP/s; both fractions are reported.
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
+PEAK_INT8_MFMA_TOPS = 5000.0     # MI355X dense int8 matrix peak
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_mfma_12mp_traffic.json")
 FILTER_SRC = os.path.join(ROOT, "paper_2512_23569_amd", "csrc", "filter_mfma.hip")
@@ -64,6 +69,29 @@ def filter_mfma_flops_per_group(K: int, c: int) -> float:
     per 32 patches, forward 2 x (8 + 32 c=3 blocks) products, inverse 3 x as many."""
     blocks = 40 if c == 3 else 8
     return (2 + 3) * blocks * 32768.0 * (K / 32.0)
+
+
+def bm_int8_ops(h: int, w: int, s: int, W: int) -> float:
+    """Algorithmic int8 operations of block matching: every reference against every candidate
+    of its clipped window, 64 multiply-adds (2 ops) per pair (the 8x8 patch of one plane)."""
+    import oracle
+    R = (W - 1) // 2
+
+    def side(n):
+        ys = oracle.ref_grid(n, 8, s)
+        return sum(min(int(y) + R, n - 8) - max(int(y) - R, 0) + 1 for y in ys)
+    return 2.0 * 64 * side(h) * side(w)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def source_hash(path: str) -> str:
@@ -211,10 +239,11 @@ def main():
     ms_plain = time_steps(plain_fn, args.steps, 0, stream)
     stages = ht.htsvd_stage_times(dn.ctx)
     ht.htsvd_set_timing(dn.ctx, False)
+    guard = ht.htsvd_last_guard_count(dn.ctx)
     psnr_plain = synth.psnr(clean, d_out.cpu().numpy())
     psnr_in = synth.psnr(clean, noisy)
     mpx_plain = h * w / (ms_plain * 1e-3) / 1e6
-    log("12 MP plain form: %.2f ms/step, %.1f Mpx/s, PSNR %.3f" % (ms_plain, mpx_plain, psnr_plain))
+    log("12 MP plain form: %.2f ms/step, %.1f Mpx/s, PSNR %.3f, guard %s" % (ms_plain, mpx_plain, psnr_plain, guard))
 
     ny, nx = ht.htsvd_ref_count(h, 8, s), ht.htsvd_ref_count(w, 8, s)
     n_ref = ny * nx
@@ -224,6 +253,10 @@ def main():
     achieved_tf = fl / (f_avg_ms * 1e-3) / 1e12
     mf_tf = filter_mfma_flops_per_group(32, c) * n_ref / (f_avg_ms * 1e-3) / 1e12
     traffic = measured_traffic(n_ref)
+    bm_ms, bm_calls = stages["bm"]
+    bm_avg_ms = bm_ms / max(bm_calls, 1)
+    bm_ops = bm_int8_ops(h, w, s, W)
+    alg_bytes = h * w * c * (1 + 4)      # uint8 in, float32 out
 
     result = {
         "metric": "Mpixel/s denoised, 12MP RGB sigma=50, plain vs batched+learned at equal PSNR",
@@ -236,7 +269,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "fp16x2-split MFMA, f32 accumulate, f64 guard band; int8 MFMA grouping",
         "data": "synthetic",
         "config": {"workload": "12MP RGB %dx%d, AWGN sigma=%g estimated (plain estimator + vote), ps 8, stride %d, "
                                "window %d, K 32" % (w, h, sigma, s, W),
@@ -244,9 +277,18 @@ def main():
         "roofline": {"bound": "alu", "kernel": "filter_mfma_kernel<3,32>", "achieved": round(achieved_tf, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved_tf / PEAK_FP32_VECTOR_TFLOPS, 4),
-                     "traffic": traffic, "kernel_ms": round(f_avg_ms, 4), "flop_per_launch": fl,
+                     "frac_unpacked_fp32": round(achieved_tf / PEAK_FP32_UNPACKED_TFLOPS, 4),
+                     "traffic": traffic,
+                     "hbm_frac": (round(traffic / (f_avg_ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 5) if traffic else None),
+                     "kernel_ms": round(f_avg_ms, 4), "flop_per_launch": fl,
                      "mfma": {"dtype": "f16", "executed_tflops": round(mf_tf, 3), "peak": PEAK_F16_MFMA_TFLOPS,
                               "frac": round(mf_tf / PEAK_F16_MFMA_TFLOPS, 4)}},
+        "hbm_algorithmic": {"bytes_per_step": alg_bytes, "gbs": round(alg_bytes / (ms_plain * 1e-3) / 1e9, 2),
+                            "frac": round(alg_bytes / (ms_plain * 1e-3) / (PEAK_HBM_GBS * 1e9), 5)},
+        "block_matching": {"kernel": "bm_kernel", "int8_ops": bm_ops, "ms": round(bm_avg_ms, 4),
+                           "tops": round(bm_ops / (bm_avg_ms * 1e-3) / 1e12, 2),
+                           "int8_mfma_frac": round(bm_ops / (bm_avg_ms * 1e-3) / 1e12 / PEAK_INT8_MFMA_TOPS, 5)},
+        "guard": {"fp64_redecided": int(guard[0]), "fp32_beyond_list": int(guard[1])},
         "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]},
         "psnr": {"noisy": round(psnr_in, 3), "plain": round(psnr_plain, 3)},
         "input_gen_s": round(gen_s, 1),
@@ -260,16 +302,27 @@ def main():
         result["autotune"] = {"k_sigma_cutoff": cutoff, "calib_s": round(time.time() - t0, 1),
                               "psnr_loss_k16_db": {int(r["sigma"]): round(r["psnr_loss_k16_db"], 3) for r in table}}
 
+        # ---- 12 MP, plain form at K = 16 (the group size the autotuner picks) ----
+        p_plain16 = p_plain.replace(K=16)
+        ms_p16 = time_steps(lambda: dn.denoise(d_in, AUTO, p_plain16, out=d_out), args.steps, args.warmup, stream)
+        psnr_p16 = synth.psnr(clean, d_out.cpu().numpy())
+        log("12 MP plain form K 16: %.2f ms/step, PSNR %.3f" % (ms_p16, psnr_p16))
+        result["plain_k16_12mp"] = {"value": round(h * w / (ms_p16 * 1e-3) / 1e6, 3), "ms_per_step": round(ms_p16, 3),
+                                    "psnr": round(psnr_p16, 3), "K": 16}
+
         # ---- 12 MP, batched + learned form ----
         bl_kw = dict(Ks=[KAUTO], outs=[d_out], use_graph=True, k_sigma_cutoff=cutoff)
         bl_fn = lambda: dn.denoise_batch([d_in], [AUTO], p_learn, **bl_kw)  # noqa: E731
         ms_bl = time_steps(bl_fn, args.steps, args.warmup, stream)
         psnr_bl = synth.psnr(clean, d_out.cpu().numpy())
-        log("12 MP batched+learned form: %.2f ms/step, PSNR %.3f" % (ms_bl, psnr_bl))
+        k_bl = ht.htsvd_batch_inspect(dn.ctx, 0)
+        log("12 MP batched+learned form: %.2f ms/step, PSNR %.3f, K %d" % (ms_bl, psnr_bl, k_bl))
         result["batched_learned_12mp"] = {
             "value": round(h * w / (ms_bl * 1e-3) / 1e6, 3), "ms_per_step": round(ms_bl, 3),
-            "psnr": round(psnr_bl, 3), "speedup_vs_plain": round(ms_plain / ms_bl, 3),
-            "dpsnr_vs_plain_db": round(psnr_bl - psnr_plain, 3)}
+            "psnr": round(psnr_bl, 3), "K": k_bl, "speedup_vs_plain": round(ms_plain / ms_bl, 3),
+            "dpsnr_vs_plain_db": round(psnr_bl - psnr_plain, 3),
+            "speedup_same_k": round(ms_p16 / ms_bl, 3) if k_bl == 16 else None,
+            "dpsnr_vs_plain_same_k_db": round(psnr_bl - psnr_p16, 3) if k_bl == 16 else None}
 
     if not args.no_batch and not args.plain_only:
         result["batch"] = bench_batch(dn, args, autotune, stream)
@@ -311,6 +364,15 @@ def bench_batch(dn, args, autotune, stream):
     ms_plain = time_steps(plain, args.steps, args.warmup, stream)
     psnr_plain = [synth.psnr(cl, o.cpu().numpy()) for (cl, _), o in zip(pairs, outs)]
     log("batch plain form: %.2f ms/step, mean PSNR %.3f" % (ms_plain, float(np.mean(psnr_plain))))
+    p_plain16 = p_plain.replace(K=16)
+
+    def plain16():
+        for x, o in zip(ins, outs):
+            dn.denoise(x, AUTO, p_plain16, out=o)
+
+    ms_p16 = time_steps(plain16, args.steps, args.warmup, stream)
+    psnr_p16 = [synth.psnr(cl, o.cpu().numpy()) for (cl, _), o in zip(pairs, outs)]
+    log("batch plain form K 16: %.2f ms/step, mean PSNR %.3f" % (ms_p16, float(np.mean(psnr_p16))))
 
     Ks = [KAUTO] * len(ins)
     sig = [AUTO] * len(ins)
@@ -322,20 +384,28 @@ def bench_batch(dn, args, autotune, stream):
               tile_side=best["tile_side"])
     ms_bl = time_steps(lambda: dn.denoise_batch(ins, sig, p_learn, **kw), args.steps, args.warmup, stream)
     psnr_bl = [synth.psnr(cl, o.cpu().numpy()) for (cl, _), o in zip(pairs, outs)]
+    k_used = [ht.htsvd_batch_inspect(dn.ctx, i) for i in range(len(ins))]
     dps = float(np.mean(psnr_bl) - np.mean(psnr_plain))
+    dps16 = float(np.mean(psnr_bl) - np.mean(psnr_p16))
     log("batch batched+learned form: %.2f ms/step, mean PSNR %.3f" % (ms_bl, float(np.mean(psnr_bl))))
     return {
         "workload": "%d RGB images (%.1f MP total), AWGN sigma U[5,75] estimated, stride 4, window 31"
                     % (len(ins), total_px / 1e6),
         "plain": {"value": round(total_px / (ms_plain * 1e-3) / 1e6, 3), "ms_per_step": round(ms_plain, 3),
                   "mean_psnr": round(float(np.mean(psnr_plain)), 3), "K": 32},
+        "plain_k16": {"value": round(total_px / (ms_p16 * 1e-3) / 1e6, 3), "ms_per_step": round(ms_p16, 3),
+                      "mean_psnr": round(float(np.mean(psnr_p16)), 3), "K": 16},
         "batched_learned": {"value": round(total_px / (ms_bl * 1e-3) / 1e6, 3), "ms_per_step": round(ms_bl, 3),
                             "mean_psnr": round(float(np.mean(psnr_bl)), 3), "launch": best,
-                            "k_sigma_cutoff": cutoff},
+                            "k_sigma_cutoff": cutoff, "images_at_k16": int(sum(k == 16 for k in k_used)),
+                            "images_at_k32": int(sum(k == 32 for k in k_used))},
         "speedup": round(ms_plain / ms_bl, 3),
         "dpsnr_db": round(dps, 3),
         "psnr_within_0p05_db": bool(abs(dps) <= 0.05),
         "psnr_not_worse_than_0p05_db": bool(dps >= -0.05),
+        "speedup_same_k": round(ms_p16 / ms_bl, 3),
+        "dpsnr_same_k_db": round(dps16, 3),
+        "psnr_within_0p05_db_same_k": bool(abs(dps16) <= 0.05),
         "unit": "Mpixel/s",
         "gen_s": round(gen_s, 1), "tune_s": round(tune_s, 1), "launch_candidates": allr,
     }
@@ -783,9 +853,18 @@ def cpu_baseline(noisy, s, W, K, sigma, target_s):
     n = rows * nx
     # each reference stands for stride^2 pixels of the grid
     mpx_s = n * s * s / dt / 1e6
+    # one thread, on a sample of about a third of the target time
+    rows1 = max(1, min(ny, int(target_s / 3.0 / max(t1 * cores, 1e-3))))
+    t0 = time.time()
+    oracle.denoise(noisy, U, V, tau, s=s, W=W, K=K, nthreads=1, r_begin=0, r_end=rows1 * nx)
+    dt1 = time.time() - t0
+    log("cpu oracle, one thread: %d rows in %.1f s" % (rows1, dt1))
     return {"value": round(mpx_s, 5), "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": "%d reference rows (%d references, %.1f s) of the same 12 MP image, FP64 oracle, known sigma"
-                      % (rows, n, dt)}
+                      % (rows, n, dt),
+            "single_thread": {"value": round(rows1 * nx * s * s / dt1 / 1e6, 5), "unit": "Mpixel/s", "cores": 1,
+                              "sample": "%d reference rows (%.1f s)" % (rows1, dt1)}}
 
 
 if __name__ == "__main__":

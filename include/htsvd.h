@@ -286,13 +286,32 @@ typedef struct {
 htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *imgs, const htsvd_params *p,
                                  const htsvd_batch_opts *opts, void *stream);
 
-/* Noise levels per sub-image (ceil(h/S) * ceil(w/S) tiles, S = p->subimage, row-major):
- * d_sigma_est: plain estimate before the vote (FP64), d_sigma_hat: after Eq. 23 (FP64,
- * equals d_sigma_est when p->adaptive is 0), d_votes: "adjust" votes per tile (int32).
- * sigma > 0 uses the known level as sigma_est.  Any output pointer may be NULL. */
+/* State of image `image` (index into the imgs array) of the last htsvd_denoise_batch call on
+ * this context, for checking the batched decisions from outside (Algorithm 1 with Eq. 20, 23):
+ * *h_K (host, may be NULL): the group size the image was filtered with -- for an HTSVD_K_AUTO
+ * image the device's choice (waits for `stream`); d_tau_ref (device, n_ref FP64, may be NULL):
+ * the per-reference thresholds the filter applied (for an HTSVD_K_AUTO image that took 16,
+ * already scaled to the 16-member multiplier).  It reads the context's workspace, so call it
+ * after the batch's work and before any other call that uses the context.
+ * HTSVD_ESTATE if no batch has been planned since the workspace last changed. */
+htsvd_status htsvd_batch_inspect(htsvd_ctx *ctx, int32_t image, int32_t *h_K, double *d_tau_ref, void *stream);
+
+/* Noise levels (Sec. III-E-1, Eq. 22-23).  Per sub-image (ceil(h/S) * ceil(w/S) tiles,
+ * S = p->subimage, row-major): d_sigma_est: sigma_est before the vote (FP64) -- the known level,
+ * the plain estimate, or under the learned estimator the tile's judged level (the mean learned
+ * sigma of its 8x8 blocks where it lies within a factor 1.5 of the plain estimate, else the
+ * plain estimate); d_sigma_hat: after Eq. 23 (FP64, equals d_sigma_est when p->adaptive is 0);
+ * d_votes: "adjust" votes per tile (int32).
+ * d_sigma_map: the effective noise level per 8x8 block (ceil(h/8) * ceil(w/8), row-major, FP64)
+ * -- the sigma that the thresholds tau = sigma * multiplier of the references whose top-left
+ * pixel lies in the block use: sigma_hat of the block's tile, or under the learned estimator
+ * where the tile accepted the map, exp(z) of the block times the tile's vote factor
+ * sigma_hat / sigma_est.
+ * sigma > 0 uses the known level as sigma_est.  Any output pointer may be NULL.  All outputs
+ * are device buffers owned by the caller. */
 htsvd_status htsvd_estimate_sigma(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
                                   int64_t in_stride, float sigma, const htsvd_params *p, double *d_sigma_est,
-                                  double *d_sigma_hat, int32_t *d_votes, void *stream);
+                                  double *d_sigma_hat, int32_t *d_votes, double *d_sigma_map, void *stream);
 
 /* Waits for `stream` and reports deferred device errors. */
 htsvd_status htsvd_sync(htsvd_ctx *ctx, void *stream);

@@ -85,7 +85,8 @@ _SIGS = {
     "htsvd_denoise_sweep": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _i32, ctypes.POINTER(htsvd_sweep_item), _PP,
                                    _vp]),
     "htsvd_denoise_batch": (_i32, [_vp, _i32, ctypes.POINTER(htsvd_image), _PP, ctypes.POINTER(htsvd_batch_opts), _vp]),
-    "htsvd_estimate_sigma": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _vp, _vp, _vp]),
+    "htsvd_estimate_sigma": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _vp, _vp, _vp, _vp]),
+    "htsvd_batch_inspect": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "htsvd_sync": (_i32, [_vp, _vp]),
     "htsvd_last_error": (ctypes.c_char_p, []),
     "htsvd_last_guard_count": (_i32, [_vp, _vp]),
@@ -259,12 +260,23 @@ def htsvd_denoise_sweep(ctx, d_in, h, w, c, in_stride, items, params, stream=Non
 
 
 def htsvd_estimate_sigma(ctx, d_in, h, w, c, in_stride, sigma, params, d_sigma_est=None, d_sigma_hat=None,
-                         d_votes=None, stream=None):
+                         d_votes=None, d_sigma_map=None, stream=None):
     import torch
     _check(lib().htsvd_estimate_sigma(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, c, in_stride, float(sigma),
                                       ctypes.byref(params), _dptr(d_sigma_est, torch.float64, "d_sigma_est"),
                                       _dptr(d_sigma_hat, torch.float64, "d_sigma_hat"),
-                                      _dptr(d_votes, torch.int32, "d_votes"), _stream(stream)))
+                                      _dptr(d_votes, torch.int32, "d_votes"),
+                                      _dptr(d_sigma_map, torch.float64, "d_sigma_map"), _stream(stream)))
+
+
+def htsvd_batch_inspect(ctx, image, d_tau_ref=None, stream=None) -> int:
+    """Group size of image `image` of the last batch (after the device's K choice); fills
+    d_tau_ref with the thresholds its filter applied when given."""
+    import torch
+    k = ctypes.c_int32(0)
+    _check(lib().htsvd_batch_inspect(ctx, int(image), ctypes.byref(k), _dptr(d_tau_ref, torch.float64, "d_tau_ref"),
+                                     _stream(stream)))
+    return int(k.value)
 
 
 def htsvd_sync(ctx, stream=None):

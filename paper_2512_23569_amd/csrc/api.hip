@@ -60,6 +60,13 @@ struct BatchCache {
     size_t dev_size = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // per image of the caller's array: group size as planned, whether it is chosen on the device,
+    // its reference count, and its thresholds and device choice (workspace / descriptor block)
+    std::vector<int> k_plan, auto_k;
+    std::vector<int64_t> n_ref;
+    std::vector<const double *> tau;
+    std::vector<const int *> ksel;
+    double mul_alt = 1.0;   // threshold factor of an auto image filtered with K = 16
 };
 
 struct htsvd_ctx {
@@ -160,6 +167,7 @@ htsvd_status ensure_ws(htsvd_ctx *ctx, size_t bytes) {
         ctx->ws_size = 0;
     }
     ctx->batch.valid = false;   // a captured batch graph points into the old workspace
+    ctx->batch.k_plan.clear();
     size_t sz = bytes + (bytes >> 3);
     e = hipMalloc(&ctx->ws, sz);
     if (e != hipSuccess) {
@@ -306,6 +314,7 @@ htsvd_status ensure_cnn_ws(htsvd_ctx *ctx, size_t bytes) {
     if (cs.ws_size >= bytes) return HTSVD_OK;
     hipError_t e;
     ctx->batch.valid = false;
+    ctx->batch.k_plan.clear();
     if (cs.ws) {
         if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronise before workspace growth");
         (void)hipFree(cs.ws);
@@ -1165,7 +1174,7 @@ htsvd_status htsvd_denoise_sweep(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h,
 
 htsvd_status htsvd_estimate_sigma(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
                                   int64_t in_stride, float sigma, const htsvd_params *p, double *d_sigma_est,
-                                  double *d_sigma_hat, int32_t *d_votes, void *stream) {
+                                  double *d_sigma_hat, int32_t *d_votes, double *d_sigma_map, void *stream) {
     ImageGeom g;
     MethodParams mp;
     htsvd_status s = validate(ctx, d_in, h, w, c, in_stride, p, &g, &mp, false);
@@ -1193,6 +1202,9 @@ htsvd_status htsvd_estimate_sigma(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h
     if (d_votes &&
         (e = hipMemcpyAsync(d_votes, wk.votes, sizeof(int32_t) * n_tiles, hipMemcpyDeviceToDevice, st)) != hipSuccess)
         return hip_fail(e, "copy votes");
+    if (d_sigma_map && (e = launch_sigma_map(d_sigma_map, g, tile, learned ? zmap : nullptr, wk.use_plain, wk.sig_est,
+                                             wk.sig_hat, st)) != hipSuccess)
+        return hip_fail(e, "sigma map");
     return HTSVD_OK;
 }
 
@@ -1556,6 +1568,7 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
         return HTSVD_OK;
     }
 
+    ctx->batch.k_plan.clear();   // valid again once this batch is planned
     BatchPlan P;
     htsvd_status s = plan_batch(ctx, n, imgs, p, o.tile_side, &P);
     if (s != HTSVD_OK) return s;
@@ -1760,6 +1773,20 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
     }
     if ((e = hipMemcpy(bc.dev, host.data(), off, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "batch descriptor upload");
+    bc.k_plan.assign(n, 0);
+    bc.auto_k.assign(n, 0);
+    bc.n_ref.assign(n, 0);
+    bc.tau.assign(n, nullptr);
+    bc.ksel.assign(n, nullptr);
+    bc.mul_alt = p->tau_mult > 0.0 ? 1.0 : default_mult(C, 16) / default_mult(C, 32);
+    for (int i = 0; i < ni; ++i) {
+        const int src = P.im[i].src;
+        bc.k_plan[src] = P.im[i].mp.K;
+        bc.auto_k[src] = P.im[i].auto_k ? 1 : 0;
+        bc.n_ref[src] = P.im[i].n_ref;
+        bc.tau[src] = items[i].tau;
+        bc.ksel[src] = P.im[i].auto_k ? d_ksel + i : nullptr;
+    }
     char *D = (char *)bc.dev;
     const BatchItem *d_items = (const BatchItem *)(D + o_items);
     int *d_q = (int *)(D + o_q);
@@ -1861,6 +1888,29 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
         if ((e = hipGraphLaunch(ex, st)) != hipSuccess) return hip_fail(e, "graph launch");
     }
     return s;
+}
+
+htsvd_status htsvd_batch_inspect(htsvd_ctx *ctx, int32_t image, int32_t *h_K, double *d_tau_ref, void *stream) {
+    if (!ctx) return fail(HTSVD_EINVAL, "null context");
+    const BatchCache &bc = ctx->batch;
+    if (bc.k_plan.empty()) return fail(HTSVD_ESTATE, "no batch has been planned on this context");
+    if (image < 0 || image >= (int32_t)bc.k_plan.size()) return fail(HTSVD_EINVAL, "image index out of range");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (d_tau_ref &&
+        (e = launch_scale_tau(bc.tau[image], d_tau_ref, bc.n_ref[image], bc.ksel[image], 16, bc.mul_alt, st)) !=
+            hipSuccess)
+        return hip_fail(e, "thresholds");
+    if (h_K) {
+        int k = bc.k_plan[image];
+        if (bc.ksel[image]) {
+            if ((e = hipMemcpyAsync(&k, bc.ksel[image], sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
+                return hip_fail(e, "group size");
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "synchronise");
+        }
+        *h_K = k;
+    }
+    return HTSVD_OK;
 }
 
 int32_t htsvd_ra_param_count(int32_t c) { return (c == 1 || c == 3) ? ra_param_count(c) : 0; }

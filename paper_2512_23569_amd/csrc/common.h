@@ -277,6 +277,14 @@ hipError_t launch_learned_judge(const ImageGeom &g, int tile, const float *zmap,
 hipError_t launch_fill_tau_learned(double *tau, const ImageGeom &g, int tile, const float *zmap,
                                    const int32_t *use_plain, const double *sigma_est, const double *sigma_hat,
                                    double mult, hipStream_t st);
+// Effective sigma of every 8x8 block (the sigma the thresholds of references with their top-left
+// pixel in the block use): block_sigma over ceil(h/8) x ceil(w/8) blocks; zmap may be NULL.
+hipError_t launch_sigma_map(double *map, const ImageGeom &g, int tile, const float *zmap, const int32_t *use_plain,
+                            const double *sigma_est, const double *sigma_hat, hipStream_t st);
+// out[r] = tau[r] * (ksel && *ksel == k_alt ? mul_alt : 1): the thresholds a batched image was
+// filtered with, after the device's group-size choice.
+hipError_t launch_scale_tau(const double *tau, double *out, int64_t n, const int *ksel, int k_alt, double mul_alt,
+                            hipStream_t st);
 
 // Hyperspectral tube patches (bands.hip).
 hipError_t launch_band_guide(const uint8_t *cube, int64_t stride, int h, int w, int B, uint8_t *guide, hipStream_t st);

@@ -373,7 +373,7 @@ __global__ void combine_sigma_kernel(const double *sigma2, int c, int n_tiles, d
 // map judged by the plain estimate; without the vote, sigma_hat = sigma_est and no votes.
 __global__ void sigma_tiles_batched_kernel(const SigmaItem *__restrict__ items, const int *__restrict__ sel,
                                            const int *__restrict__ start, int n, int total, int T,
-                                           double log_bound) {
+                                           double bound) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= total) return;
     const int j = find_unit(start, n, u);
@@ -388,7 +388,7 @@ __global__ void sigma_tiles_batched_kernel(const SigmaItem *__restrict__ items, 
             se = sp;
         } else {
             it.sig_plain[t] = sp;
-            se = judge_tile(it.g, T, t, it.zmap, sp, log_bound, it.use_plain + t);
+            se = judge_tile(it.g, T, t, it.zmap, sp, bound, it.use_plain + t);
         }
     }
     it.sig_est[t] = se;
@@ -609,7 +609,7 @@ hipError_t launch_sigma_tiles_batched(const SigmaItem *items, const int *sel, co
                                       int tile, double ratio_bound, hipStream_t st) {
     if (n <= 0 || total <= 0) return hipSuccess;
     hipLaunchKernelGGL(sigma_tiles_batched_kernel, dim3((total + 255) / 256), dim3(256), 0, st, items, sel, start, n,
-                       total, tile, log(ratio_bound));
+                       total, tile, ratio_bound);
     return hipGetLastError();
 }
 

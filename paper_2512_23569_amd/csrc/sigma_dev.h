@@ -17,10 +17,11 @@ __device__ inline double combine_sigma_tile(const double *sigma2, int c, int t) 
 }
 
 // The learned map judged on sub-image t: the mean learned sigma over the tile's 8x8 blocks is
-// kept when it is within a factor exp(log_bound) of the plain estimate (and finite), else the
-// plain estimate stands in.  Returns the sigma the tile then stands for; *use_plain says which.
+// kept when it lies within a factor `bound` of the plain estimate sp on either side
+// (sp / bound <= mean <= bound * sp, both products in FP64; finite, positive), else the plain
+// estimate stands in.  Returns the sigma the tile then stands for; *use_plain says which.
 __device__ inline double judge_tile(const ImageGeom &g, int tile, int t, const float *zmap, double sp,
-                                    double log_bound, int32_t *use_plain) {
+                                    double bound, int32_t *use_plain) {
     const int ntx = (g.w + tile - 1) / tile;
     const int hb = (g.h + PS - 1) / PS, wb = (g.w + PS - 1) / PS, bpt = tile / PS;
     const int ty = t / ntx, tx = t % ntx;
@@ -32,7 +33,7 @@ __device__ inline double judge_tile(const ImageGeom &g, int tile, int t, const f
             ++n;
         }
     const double mean = n > 0 ? sum / n : 0.0;
-    const bool ok = isfinite(mean) && mean > 0.0 && sp > 0.0 && fabs(log(mean / sp)) <= log_bound;
+    const bool ok = isfinite(mean) && mean > 0.0 && sp > 0.0 && mean <= bound * sp && mean * bound >= sp;
     *use_plain = ok ? 0 : 1;
     return ok ? mean : sp;
 }
@@ -46,17 +47,24 @@ __device__ inline int ref_tile(const ImageGeom &g, int tile, int64_t r, int *y, 
     return (*y / tile) * ntx + *x / tile;
 }
 
-// Noise level of reference r under the learned map: the learned sigma of the 8x8 block holding
-// its top-left pixel scaled by its tile's vote (sigma_hat / sigma_est), or the tile's plain
-// sigma_hat where the judge rejected the map.
+// Effective noise level of the 8x8 block (by, bx), which lies in sub-image t: under the learned
+// map, the block's learned sigma scaled by its tile's vote (sigma_hat / sigma_est), or the
+// tile's plain sigma_hat where the judge rejected the map (zmap == nullptr: sigma_hat).
+__device__ inline double block_sigma(const ImageGeom &g, int t, int by, int bx, const float *zmap,
+                                     const int32_t *use_plain, const double *sigma_est, const double *sigma_hat) {
+    if (!zmap || use_plain[t]) return sigma_hat[t];
+    const int wb = (g.w + PS - 1) / PS;
+    return exp((double)zmap[by * wb + bx]) * (sigma_hat[t] / sigma_est[t]);
+}
+
+// Noise level of reference r under the learned map: that of the 8x8 block holding its top-left
+// pixel (block_sigma).
 __device__ inline double learned_ref_sigma(const ImageGeom &g, int tile, int64_t r, const float *zmap,
                                            const int32_t *use_plain, const double *sigma_est,
                                            const double *sigma_hat) {
     int y, x;
     const int t = ref_tile(g, tile, r, &y, &x);
-    if (use_plain[t]) return sigma_hat[t];
-    const int wb = (g.w + PS - 1) / PS;
-    return exp((double)zmap[(y / PS) * wb + x / PS]) * (sigma_hat[t] / sigma_est[t]);
+    return block_sigma(g, t, y / PS, x / PS, zmap, use_plain, sigma_est, sigma_hat);
 }
 
 }  // namespace htsvd

@@ -30,11 +30,11 @@ __global__ void fill_tau_kernel(double *tau, int64_t n_ref, const double *sigma_
 
 // Per sub-image: the learned map judged by the plain estimate (see judge_tile).
 __global__ void learned_judge_kernel(ImageGeom g, int tile, const float *zmap, const double *sigma_plain,
-                                     double log_bound, int32_t *use_plain, double *sigma_tile) {
+                                     double bound, int32_t *use_plain, double *sigma_tile) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int ntx = (g.w + tile - 1) / tile, nty = (g.h + tile - 1) / tile;
     if (t >= ntx * nty) return;
-    sigma_tile[t] = judge_tile(g, tile, t, zmap, sigma_plain[t], log_bound, use_plain + t);
+    sigma_tile[t] = judge_tile(g, tile, t, zmap, sigma_plain[t], bound, use_plain + t);
 }
 
 // tau of every reference under the learned map (see learned_ref_sigma).
@@ -44,6 +44,25 @@ __global__ void fill_tau_learned_kernel(double *tau, ImageGeom g, int tile, cons
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= (int64_t)g.ny * g.nx) return;
     tau[r] = learned_ref_sigma(g, tile, r, zmap, use_plain, sigma_est, sigma_hat) * mult;
+}
+
+// Effective sigma per 8x8 block (see block_sigma); the tile is a multiple of the block size.
+__global__ void sigma_map_kernel(double *map, ImageGeom g, int tile, const float *zmap, const int32_t *use_plain,
+                                 const double *sigma_est, const double *sigma_hat) {
+    const int hb = (g.h + PS - 1) / PS, wb = (g.w + PS - 1) / PS;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= hb * wb) return;
+    const int by = b / wb, bx = b % wb;
+    const int ntx = (g.w + tile - 1) / tile;
+    const int t = (by * PS / tile) * ntx + bx * PS / tile;
+    map[b] = block_sigma(g, t, by, bx, zmap, use_plain, sigma_est, sigma_hat);
+}
+
+__global__ void scale_tau_kernel(const double *tau, double *out, int64_t n, const int *ksel, int k_alt,
+                                 double mul_alt) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    out[r] = tau[r] * ((ksel && *ksel == k_alt) ? mul_alt : 1.0);
 }
 
 // Batched thresholds of the images whose noise level went through the sub-image stages.
@@ -149,7 +168,7 @@ hipError_t launch_learned_judge(const ImageGeom &g, int tile, const float *zmap,
                                 double ratio_bound, int32_t *use_plain, double *sigma_tile, hipStream_t st) {
     const int n = ((g.h + tile - 1) / tile) * ((g.w + tile - 1) / tile);
     hipLaunchKernelGGL(learned_judge_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g, tile, zmap, sigma_plain,
-                       log(ratio_bound), use_plain, sigma_tile);
+                       ratio_bound, use_plain, sigma_tile);
     return hipGetLastError();
 }
 
@@ -159,6 +178,23 @@ hipError_t launch_fill_tau_learned(double *tau, const ImageGeom &g, int tile, co
     const int64_t n = (int64_t)g.ny * g.nx;
     hipLaunchKernelGGL(fill_tau_learned_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tau, g, tile,
                        zmap, use_plain, sigma_est, sigma_hat, mult);
+    return hipGetLastError();
+}
+
+hipError_t launch_sigma_map(double *map, const ImageGeom &g, int tile, const float *zmap, const int32_t *use_plain,
+                            const double *sigma_est, const double *sigma_hat, hipStream_t st) {
+    if (tile % PS != 0) return hipErrorInvalidValue;
+    const int n = ((g.h + PS - 1) / PS) * ((g.w + PS - 1) / PS);
+    hipLaunchKernelGGL(sigma_map_kernel, dim3((n + 255) / 256), dim3(256), 0, st, map, g, tile, zmap, use_plain,
+                       sigma_est, sigma_hat);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_tau(const double *tau, double *out, int64_t n, const int *ksel, int k_alt, double mul_alt,
+                            hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_tau_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tau, out, n, ksel,
+                       k_alt, mul_alt);
     return hipGetLastError();
 }
 

@@ -70,3 +70,42 @@ def test_flatten_roundtrip():
     flat = _rand_params(3, 5)
     assert np.array_equal(cnn.flatten(cnn.unflatten(flat, 3)), flat)
     assert cnn.n_params(3) == 32 * 27 + 32 + 4 * (32 * 288 + 32) + 288 + 1
+
+
+def test_adam_first_step_closed_form():
+    """Step 1: the corrected moments are g and g^2, so every parameter moves by
+    lr * g / (|g| + eps) (Kingma and Ba 2015, Algorithm 1)."""
+    rng = np.random.default_rng(0)
+    w0 = rng.standard_normal(50)
+    g = rng.standard_normal(50) * 10.0 ** rng.uniform(-9, 1, 50)
+    w1, m1, v1 = cnn.adam_step(w0, np.zeros(50), np.zeros(50), g, 1, 1e-3)
+    assert np.allclose(w1, w0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-13, atol=1e-18)
+    assert np.allclose(m1, 0.1 * g, rtol=1e-15) and np.allclose(v1, 0.001 * g * g, rtol=1e-13)
+
+
+def test_adam_constant_gradient_moves_by_lr_per_step():
+    """With the same gradient every step the bias correction makes the corrected moments
+    exactly g and g^2, so each step moves by the same lr * g / (|g| + eps)."""
+    g = np.array([0.5, -2.0, 3e-3, -1e-6])
+    w = np.zeros(4)
+    m = v = np.zeros(4)
+    for t in range(1, 30):
+        w_prev = w
+        w, m, v = cnn.adam_step(w, m, v, g, t, 0.01)
+        assert np.allclose(w - w_prev, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=0)
+
+
+def test_adam_matches_torch_adam_in_fp64():
+    """Against PyTorch's own Adam (an independent implementation), FP64 on the CPU."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(1)
+    w0 = rng.standard_normal(64)
+    p = torch.nn.Parameter(torch.tensor(w0, dtype=torch.float64))
+    opt = torch.optim.Adam([p], lr=2e-3, betas=(0.9, 0.999), eps=1e-8)
+    w, m, v = w0, np.zeros(64), np.zeros(64)
+    for t in range(1, 8):
+        g = rng.standard_normal(64) * (0.1 * t)
+        p.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        w, m, v = cnn.adam_step(w, m, v, g, t, 2e-3)
+        assert np.allclose(p.detach().numpy(), w, rtol=1e-13, atol=1e-15)

@@ -4,8 +4,9 @@ Tolerances: activations are stored in bf16 (8 significant bits, unit roundoff 2^
 the oracle mirrors that rounding (round to nearest even after every ReLU) and uses the same
 bf16-rounded parameters; what remains is FP32-vs-FP64 accumulation order, which can move an
 activation across a bf16 rounding boundary (one bf16 ulp, 2^-8 relative) and propagate
-through at most five layers.  The checks therefore allow |dz| <= 0.03 on log(sigma) and a
-gradient cosine >= 0.999 with relative L2 error <= 3e-2."""
+through at most five layers.  The checks therefore allow |dz| <= 0.03 on log(sigma); the
+gradients are compared entry by entry (bar stated at the test), and the optimiser against an
+FP64 Adam."""
 import os
 
 import numpy as np
@@ -60,28 +61,84 @@ def test_forward_matches_oracle(dn, h, w, c, seed):
     assert np.max(np.abs(z - ref[0])) <= 0.03, np.max(np.abs(z - ref[0]))
 
 
+# Element-wise gradient bar.  The oracle mirrors the bf16 rounding of the stored activations, so
+# what differs is the FP32 accumulation order, which moves an activation across a bf16 rounding
+# boundary only when it lies within ~1e-7 of one; such an activation changes by one bf16 ulp
+# (2^-8 relative) and every gradient sum it enters by at most that much of the term.  The bar per
+# entry is |g - g_ref| <= 2^-8 |g_ref| + 2^-8 rms(g_ref of its tensor), and at least 99.9% of the
+# entries of every weight and bias tensor must meet it.  The targets are placed 0.5 away from
+# the oracle's outputs, so no output sits at the kink of the L1 loss (the GPU's log sigma is
+# within 0.03 of the oracle's).
+GRAD_RTOL = 2.0 ** -8
+GRAD_ATOL_RMS = 2.0 ** -8
+GRAD_FRAC = 0.999
+
+
 @pytest.mark.parametrize("c", [3, 1])
 def test_gradients_match_oracle(dn, c):
     import paper_2512_23569_amd as ht
     p = _params(c, 40 + c)
     ht.htsvd_cnn_set_weights(dn.ctx, c, p)
     n, size = 4, 48
-    crops, labels = [], []
+    crops = []
     for i in range(n):
         x, y, _ = synth.sigma_crop(100 + i, size, c)
         crops.append(x.reshape(size, size, c))
-        labels.append(y)
     X = np.stack(crops)
-    Y = np.stack(labels).astype(np.float32)
+    z_ref, _ = cnn.forward(to_bf16(p), X, c, act_round=to_bf16)
+    rng = np.random.default_rng(50 + c)
+    Y = (z_ref + np.where(rng.random(z_ref.shape) < 0.5, -0.5, 0.5)).astype(np.float32)
     g = torch.zeros(ht.htsvd_cnn_param_count(c), dtype=torch.float32, device="cuda")
     loss = ht.htsvd_cnn_gradients(dn.ctx, torch.from_numpy(X).cuda(), n, size, size, c,
                                   torch.from_numpy(Y).cuda(), g)
     gg = g.cpu().numpy().astype(np.float64)
     ref_loss, ref_g = cnn.loss_and_grad(to_bf16(p), X, Y.astype(np.float64), c, act_round=to_bf16)
-    assert abs(loss - ref_loss) <= 1e-3 * max(1.0, ref_loss)
+    assert abs(loss - ref_loss) <= 1e-4 * max(1.0, ref_loss)
+    off = 0
+    worst = []
+    for ci, co, st, relu in cnn.layer_shapes(c):
+        for size_t in (co * 9 * ci, co):
+            a, r = gg[off:off + size_t], ref_g[off:off + size_t]
+            rms = float(np.sqrt(np.mean(r * r)))
+            ok = np.abs(a - r) <= GRAD_RTOL * np.abs(r) + GRAD_ATOL_RMS * rms
+            worst.append((float(np.mean(ok)), float(np.max(np.abs(a - r)) / max(rms, 1e-300))))
+            assert np.mean(ok) >= GRAD_FRAC, (off, size_t, float(np.mean(ok)))
+            off += size_t
+    print("gradient entries within the bar per tensor (fraction, max |d| / rms):", worst)
     cos = float(gg @ ref_g / (np.linalg.norm(gg) * np.linalg.norm(ref_g)))
     rel = float(np.linalg.norm(gg - ref_g) / np.linalg.norm(ref_g))
-    assert cos >= 0.999 and rel <= 3e-2, (cos, rel)
+    assert cos >= 0.9999 and rel <= 2e-2, (cos, rel)
+
+
+def test_adam_steps_match_oracle(dn):
+    """Two GPU training steps against the oracle's FP64 Adam (Kingma and Ba 2015) applied to the
+    gradients the GPU reports at the same weights (the optimiser alone is checked here; the
+    gradients are checked above).  Bar: FP32 weights within 2^-22 |w| + 1e-5 lr."""
+    import paper_2512_23569_amd as ht
+    c, n, size, lr = 3, 4, 48, 1e-3
+    p = _params(c, 77)
+    ht.htsvd_cnn_set_weights(dn.ctx, c, p)          # also clears the moments and the step count
+    batches = []
+    for b in range(2):
+        X, Y = [], []
+        for i in range(n):
+            x, y, _ = synth.sigma_crop(900 + 10 * b + i, size, c)
+            X.append(x.reshape(size, size, c))
+            Y.append(y)
+        batches.append((torch.from_numpy(np.stack(X)).cuda(), torch.from_numpy(np.stack(Y).astype(np.float32)).cuda()))
+    w = ht.htsvd_cnn_get_weights(dn.ctx, c).astype(np.float64)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    for t, (X, Y) in enumerate(batches, start=1):
+        g = torch.zeros(w.size, dtype=torch.float32, device="cuda")
+        ht.htsvd_cnn_gradients(dn.ctx, X, n, size, size, c, Y, g)
+        ht.htsvd_cnn_train_step(dn.ctx, X, n, size, size, c, Y, lr)
+        w_gpu = ht.htsvd_cnn_get_weights(dn.ctx, c).astype(np.float64)
+        w_ref, m, v = cnn.adam_step(w, m, v, g.cpu().numpy().astype(np.float64), t, lr)
+        d = np.abs(w_gpu - w_ref)
+        assert np.all(d <= 2.0 ** -22 * np.abs(w_ref) + 1e-5 * lr), (t, float(np.max(d)))
+        assert np.any(w_gpu != w)                    # the step moved the weights
+        w = w_gpu
 
 
 def test_training_reduces_loss_and_checkpoint_resumes(dn, tmp_path):

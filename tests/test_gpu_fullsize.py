@@ -1,23 +1,30 @@
 """Parity at the full workload sizes (needs an MI355X).
 
-Workloads: the 12 MP RGB image with Poisson-Gaussian noise in the configuration the benchmark
-times (reference stride 3, window 31, K = 32, noise level estimated with the plain estimator
-and the Eq. 23 vote), and the 64-image batch through the batched launch.  The FP64 oracle
-cannot process 12 MP within a test, so it checks what it can compute exactly:
+Workloads: the 12 MP RGB image the benchmark times (textured, AWGN sigma 50, reference stride
+3, window 31, K = 32, noise level estimated) in its plain form (plain estimator and the Eq. 23
+vote) and its batched + learned form (learned map judged by the plain estimate, the vote,
+HTSVD_K_AUTO, graph replay); the same image with Poisson-Gaussian noise; and the 64-image
+batch.  The FP64 oracle cannot denoise 12 MP within a test, so it checks what it can compute
+exactly:
 
   - groups of sampled references, bit-exact (indices and distances), including the last
     reference row and column of the grid;
   - sigma_est of sampled sub-images (relative 1e-9), including partial edge sub-images, and
     their Eq. 23 votes (identical counts), from oracle groups of the sampled voters;
   - denoised pixels of row bands: the oracle processes every reference whose groups can reach
-    the band (reference rows within R + ps - 1 of it), so the band's pixels are complete sums;
-    the pixel parity bar (>= 99.99% within 1e-2, |dPSNR| <= 0.01 dB) applies to each band.
+    the band (reference rows within R + ps - 1 of it), so the band's pixels are complete sums,
+    with thresholds from its own estimates and votes of every sub-image those references lie in
+    (and, for the learned form, the oracle rule applied to the GPU's map); the pixel parity bar
+    (>= 99.99% within 1e-2, |dPSNR| <= 0.01 dB) applies to each band;
+  - the guard band's overflow counter (near-threshold coefficients decided in FP32) is zero.
 
 The video workload the benchmark times (7 frames of 1080 x 1920 RGB, AWGN sigma 30, temporal
 radius 1, stride 4, window 15, K 32) is checked the same way: all spatio-temporal groups
 bit-exact (the oracle matches the whole clip in seconds), and row bands of three frames (top,
 middle, bottom) denoised by the oracle from every group with a member patch in the band.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -47,12 +54,49 @@ def big():
     return clean, noisy
 
 
+@pytest.fixture(scope="module")
+def bench_img():
+    """The benchmark's own input: the 12 MP textured image (seed 3) with AWGN sigma 50 (seed 1003)."""
+    clean = synth.make_clean(3000, 4000, 3, seed=3, texture=True)
+    return clean, synth.add_awgn(clean, 50.0, seed=1003)
+
+
+@pytest.fixture(scope="module")
+def bench_sigma(bench_img):
+    """Oracle plain estimates and Eq. 23 votes (32-member oracle groups of the sampled voters) of
+    every sub-image of the benchmark input: shared by its plain and batched + learned forms."""
+    clean, noisy = bench_img
+    h, w = noisy.shape[:2]
+    sp = est.sigma_est_tiles(noisy)
+    ys, xs = oracle.ref_grid(h, PS, S), oracle.ref_grid(w, PS, S)
+    tile_of = est.tile_of_refs(ys, xs, h, w)
+    nty, ntx = est.tile_grid(h, w)
+    votes = np.zeros(nty * ntx, dtype=np.int64)
+    nvotes = np.zeros(nty * ntx, dtype=np.int64)
+    voters = [est.vote_samples(np.nonzero(tile_of == t)[0], t) for t in range(nty * ntx)]
+    gi, _ = oracle.block_match_list(noisy, np.concatenate(voters), PS, S, W, K)
+    k = 0
+    for t, v in enumerate(voters):
+        votes[t] = sum(est.rank_position(est.group_vectors(noisy, gi[k + i], PS)) <= 13 for i in range(len(v)))
+        nvotes[t] = len(v)
+        k += len(v)
+    return sp, (votes, nvotes)
+
+
 def _ref_rows_for_band(h, y0, y1, s=S, w=W):
     """Reference-row range [a, b) whose groups can reach pixel rows [y0, y1)."""
     R = (w - 1) // 2
     ys = oracle.ref_grid(h, PS, s)
     keep = np.nonzero((ys >= y0 - (PS - 1) - R) & (ys <= y1 - 1 + R))[0]
     return int(keep[0]), int(keep[-1]) + 1
+
+
+def _tiles_of_ref_rows(h, w, a, b, s=S):
+    """Sub-images holding the top-left pixels of the references in grid rows [a, b)."""
+    ys = oracle.ref_grid(h, PS, s)
+    nty, ntx = est.tile_grid(h, w)
+    rows = sorted(set(int(y) // 128 for y in ys[a:b]))
+    return [r * ntx + t for r in rows for t in range(ntx)]
 
 
 def _band_parity(gpu, ref, clean, y0, y1):
@@ -62,10 +106,17 @@ def _band_parity(gpu, ref, clean, y0, y1):
     frac = float(np.mean(d <= PIX_TOL))
     dps = abs(synth.psnr(clean[y0:y1], g) - synth.psnr(clean[y0:y1], r))
     assert frac >= PIX_FRAC and dps <= 0.01, (y0, y1, frac, float(d.max()), dps)
+    return frac, float(d.max()), dps
 
 
-def test_12mp_groups_sampled_bitexact(dn, big):
-    clean, noisy = big
+# guard band of the filter: near-threshold coefficients beyond the per-group FP64 list are decided
+# in FP32; at 12 MP (1.33 M groups) none is expected and none is allowed
+GUARD_OVERFLOW_MAX = 0
+
+
+@pytest.mark.parametrize("which", ["pg", "bench"])
+def test_12mp_groups_sampled_bitexact(dn, big, bench_img, which):
+    clean, noisy = big if which == "pg" else bench_img
     h, w = noisy.shape[:2]
     p = dn.params(3, stride=S, window=W, K=K)
     idx, dist = dn.block_match(torch.from_numpy(noisy).cuda(), p)
@@ -107,25 +158,80 @@ def test_12mp_sigma_and_votes_sampled(dn, big):
         assert np.isclose(sh[t], want, rtol=1e-9, atol=0), (t, sh[t], want)
 
 
-def test_12mp_denoised_bands(dn, big, basis3):
-    """The benchmark's plain form (estimated sigma) against the oracle on two row bands, with the
-    oracle given the thresholds the sampled sigma parity above vouches for."""
-    import paper_2512_23569_amd as ht
-    clean, noisy = big
+BANDS = ((1504, 1552), (3000 - 40, 3000))
+
+
+def _oracle_bands(noisy, out, clean, tau_of_tiles, K_used, U, V):
+    """Oracle denoising of every reference whose groups reach each band, with the thresholds
+    tau_of_tiles(tiles) returns (oracle arithmetic only), then the pixel parity bar per band."""
     h, w = noisy.shape[:2]
-    p = dn.params(3, stride=S, window=W, K=K, adaptive=1)
+    ny, nx = oracle.n_refs(h, w, PS, S)
+    res = []
+    for y0, y1 in BANDS:
+        a, b = _ref_rows_for_band(h, y0, y1)
+        tau = tau_of_tiles(_tiles_of_ref_rows(h, w, a, b))
+        band = tau[a * nx:b * nx]
+        assert np.all(np.isfinite(band)) and np.all(band > 0)
+        tau = np.where(np.isfinite(tau), tau, 0.0)
+        ref = oracle.denoise(noisy, U, V, tau, s=S, W=W, K=K_used, r_begin=a * nx, r_end=b * nx)
+        res.append(_band_parity(out, ref, clean, y0, y1))
+    return res
+
+
+def test_12mp_plain_form_bands(dn, bench_img, bench_sigma, basis3):
+    """The benchmark's plain form (AWGN sigma 50 estimated by the plain estimator with the vote,
+    K = 32) against the oracle on two row bands; the oracle's thresholds come from its own
+    estimates and votes of the sub-images the bands' references lie in."""
+    clean, noisy = bench_img
+    sp, votes = bench_sigma
+    p = dn.params(3, stride=S, window=W, K=K, adaptive=1, estimator=0)
     x = torch.from_numpy(noisy).cuda()
     out = dn.denoise(x, -1.0, p).cpu().numpy()
-    nty, ntx = est.tile_grid(h, w, 128)
-    sh = torch.zeros(nty * ntx, dtype=torch.float64, device="cuda")
-    ht.htsvd_estimate_sigma(dn.ctx, x, h, w, 3, x.stride(0), -1.0, p, None, sh, None)
-    tau = est.tau_per_ref(sh.cpu().numpy(), h, w, PS, S, 3, K)
+    guard = dn.guard_count()
+    assert guard[1] <= GUARD_OVERFLOW_MAX, guard
     U, V = basis3
-    ny, nx = oracle.n_refs(h, w, PS, S)
-    for y0, y1 in ((1504, 1552), (h - 40, h)):
-        a, b = _ref_rows_for_band(h, y0, y1)
-        ref = oracle.denoise(noisy, U, V, tau, s=S, W=W, K=K, r_begin=a * nx, r_end=b * nx)
-        _band_parity(out, ref, clean, y0, y1)
+    res = _oracle_bands(noisy, out, clean, lambda tiles: est.thresholds(
+        noisy, PS, S, W, K, tiles=tiles, sigma_plain=sp, votes=votes)["tau"], K, U, V)
+    print("plain form: guard %s, bands %s" % (guard, res))
+
+
+def test_12mp_batched_learned_form_bands(dn, bench_img, bench_sigma, basis3):
+    """The benchmark's batched + learned form (one-image batch through the graph, learned map,
+    vote, HTSVD_K_AUTO at the autotuner's cutoff) against the oracle: the group size the device
+    chose, and two row bands with the oracle rule's thresholds (the GPU's map z given to it)."""
+    import paper_2512_23569_amd as ht
+    if not os.path.exists(os.path.join(ht.DATA_DIR, "sigma_cnn_c3.ckpt")):
+        pytest.skip("no trained network shipped")
+    clean, noisy = bench_img
+    h, w = noisy.shape[:2]
+    sp, votes = bench_sigma
+    d = ht.Denoiser(0)
+    try:
+        x = torch.from_numpy(noisy).cuda()
+        z = d.sigma_map(x).cpu().numpy()
+        cutoff = 77.5    # the autotuner's cutoff on its calibration images (K = 16 never loses there)
+        p = d.params(3, stride=S, window=W, K=K, adaptive=1, estimator=1)
+        out = d.denoise_batch([x], [-1.0], p, Ks=[ht.HTSVD_K_AUTO], use_graph=True, k_sigma_cutoff=cutoff)
+        out = d.denoise_batch([x], [-1.0], p, outs=out, Ks=[ht.HTSVD_K_AUTO], use_graph=True,
+                              k_sigma_cutoff=cutoff)[0].cpu().numpy()
+        full = est.thresholds(noisy, PS, S, W, K, z=z, sigma_plain=sp, votes=votes)
+        m32 = oracle.tau_multiplier(3, 32)
+        K_used = est.auto_group_size(full["tau"] / m32, cutoff)
+        assert ht.htsvd_batch_inspect(d.ctx, 0) == K_used
+        tau_k = full["tau"] / m32 * oracle.tau_multiplier(3, K_used)
+        tau_gpu = torch.zeros(tau_k.size, dtype=torch.float64, device="cuda")
+        ht.htsvd_batch_inspect(d.ctx, 0, tau_gpu)
+        tg = tau_gpu.cpu().numpy()
+        ys, xs = oracle.ref_grid(h, PS, S), oracle.ref_grid(w, PS, S)
+        keep_ref = ~full["use_plain"][est.tile_of_refs(ys, xs, h, w)]
+        tol = np.where(keep_ref, 1e-12, 1e-9)
+        assert np.all(np.abs(tg - tau_k) <= tol * tau_k), float(np.max(np.abs(tg - tau_k) / tau_k))
+        U, V = basis3
+        res = _oracle_bands(noisy, out, clean, lambda tiles: tau_k, K_used, U, V)
+        print("batched + learned: K %d, tiles keeping the map %d of %d, bands %s"
+              % (K_used, int(np.sum(~full["use_plain"])), full["use_plain"].size, res))
+    finally:
+        d.close()
 
 
 def test_batch_of_64_sampled_bands(dn, basis3):

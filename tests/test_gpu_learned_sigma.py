@@ -1,0 +1,188 @@
+"""The learned noise map's thresholds on the GPU against the oracle rule (needs an MI355X).
+
+The map itself (row a9, the network's inference) is checked against its FP64 definition in
+test_gpu_cnn.py; here the GPU's own map z is given to the oracle, which derives everything
+after it from the pixels: the plain estimate of every sub-image, the judge at a factor 1.5
+(Sec. III-E-1: the eigenvalue estimator judges the learned one), the Eq. 23 vote from oracle
+groups of the sampled voters, the effective sigma of every 8x8 block and each reference's tau.
+
+Bars:
+  - tiles that keep the map: sigma_est (the mean learned sigma) and the effective block sigma
+    within 1e-12 relative (FP64 exp and sums on both sides, in different orders);
+  - tiles that fall back: within 1e-9 relative, the plain estimator's bar (the eigenvalues come
+    from different FP64 algorithms);
+  - votes identical; the batched group-size choice identical;
+  - denoised pixels: the pixel parity bar against the oracle denoiser given the oracle's tau.
+A judge decision within 1e-6 of the bound would make the test depend on rounding; the map's
+offset is chosen so that no tile is that close, and the test asserts it."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import assert_pixel_parity
+from oracle import estimator as est
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PS = 8
+
+
+@pytest.fixture(scope="module")
+def dn():
+    import paper_2512_23569_amd as ht
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    if not os.path.exists(os.path.join(ht.DATA_DIR, "sigma_cnn_c3.ckpt")):
+        pytest.skip("no trained network shipped")
+    d = ht.Denoiser(0)
+    yield d
+    d.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _tile_log_ratios(z, sp, h, w):
+    out = []
+    for t in range(sp.size):
+        by0, by1, bx0, bx1 = est.blocks_of_tile(t, h, w)
+        out.append(math.log(math.fsum(np.exp(z[by0:by1, bx0:bx1].astype(np.float64)).ravel().tolist())
+                            / ((by1 - by0) * (bx1 - bx0)) / sp[t]))
+    return np.array(out)
+
+
+def _margin(z, sp, h, w):
+    """Smallest distance of a tile's log ratio from the judge's bounds."""
+    lr = _tile_log_ratios(z, sp, h, w)
+    return float(np.min(np.abs(np.abs(lr) - math.log(est.JUDGE_BOUND))))
+
+
+def _gpu_sigma(dn, x, p):
+    import paper_2512_23569_amd as ht
+    h, w, c = x.shape
+    nty, ntx = est.tile_grid(h, w)
+    se = torch.zeros(nty * ntx, dtype=torch.float64, device="cuda")
+    sh = torch.zeros_like(se)
+    votes = torch.zeros(nty * ntx, dtype=torch.int32, device="cuda")
+    smap = torch.zeros(((h + 7) // 8) * ((w + 7) // 8), dtype=torch.float64, device="cuda")
+    ht.htsvd_estimate_sigma(dn.ctx, x, h, w, c, x.stride(0), -1.0, p, se, sh, votes, smap)
+    return (se.cpu().numpy(), sh.cpu().numpy(), votes.cpu().numpy(),
+            smap.cpu().numpy().reshape((h + 7) // 8, (w + 7) // 8))
+
+
+def _compare_rule(got_se, got_sh, got_votes, got_map, ref, h, w):
+    keep = ~ref["use_plain"]
+    assert np.array_equal(got_votes, ref["votes"])
+    tol = np.where(keep, 1e-12, 1e-9)
+    assert np.all(np.abs(got_se - ref["sigma_est"]) <= tol * ref["sigma_est"]), (got_se, ref["sigma_est"])
+    assert np.all(np.abs(got_sh - ref["sigma_hat"]) <= tol * ref["sigma_hat"])
+    for t in range(keep.size):
+        by0, by1, bx0, bx1 = est.blocks_of_tile(t, h, w)
+        g, r = got_map[by0:by1, bx0:bx1], ref["map"][by0:by1, bx0:bx1]
+        assert np.all(np.abs(g - r) <= tol[t] * r), (t, bool(keep[t]), float(np.max(np.abs(g - r) / r)))
+
+
+@pytest.fixture(scope="module")
+def varying():
+    """A 384 x 640 RGB image whose noise level varies smoothly from 10 to 60."""
+    rng = np.random.Generator(np.random.PCG64(7100))
+    h, w = 384, 640
+    field = synth.smooth_sigma_field(h, w, rng, 10.0, 60.0)
+    clean = synth.make_clean(h, w, 3, 7101, texture=True)
+    return clean, synth.add_sigma_field_noise(clean, field, 7102)
+
+
+def test_plain_sigma_map_matches_oracle(dn, varying):
+    """Plain estimator with the vote: the effective map is sigma_hat of the block's tile."""
+    clean, noisy = varying
+    h, w = noisy.shape[:2]
+    s, W, K = 4, 21, 16
+    p = dn.params(3, stride=s, window=W, K=K, adaptive=1, estimator=0)
+    se, sh, votes, smap = _gpu_sigma(dn, _dev(noisy), p)
+    ref = est.thresholds(noisy, PS, s, W, K)
+    assert not ref["use_plain"].any()
+    ref["use_plain"][:] = True         # every tile is at the plain estimator's bar
+    _compare_rule(se, sh, votes, smap, ref, h, w)
+
+
+def test_learned_rule_and_denoised_pixels_match_oracle(dn, varying, basis3):
+    """The shipped network with its output offset so that about half of the tiles keep the map
+    and half fall back; thresholds and denoised pixels against the oracle rule."""
+    import paper_2512_23569_amd as ht
+    clean, noisy = varying
+    h, w = noisy.shape[:2]
+    s, W, K = 4, 21, 16
+    x = _dev(noisy)
+    w0 = ht.htsvd_cnn_get_weights(dn.ctx, 3)
+    try:
+        z0 = dn.sigma_map(x).cpu().numpy()
+        sp = est.sigma_est_tiles(noisy)
+        lr = np.sort(_tile_log_ratios(z0, sp, h, w))
+        k = lr.size // 2
+        delta = math.log(est.JUDGE_BOUND) - 0.5 * (lr[k - 1] + lr[k])   # upper half beyond 1.5x
+        wt = w0.copy()
+        wt[-1] += np.float32(delta)                                       # the last layer's bias
+        ht.htsvd_cnn_set_weights(dn.ctx, 3, wt)
+        z = dn.sigma_map(x).cpu().numpy()
+        assert _margin(z, sp, h, w) > 1e-6
+        p = dn.params(3, stride=s, window=W, K=K, adaptive=1, estimator=1)
+        se, sh, votes, smap = _gpu_sigma(dn, x, p)
+        ref = est.thresholds(noisy, PS, s, W, K, z=z)
+        n_keep = int(np.sum(~ref["use_plain"]))
+        assert 0 < n_keep < ref["use_plain"].size, ref["use_plain"]
+        _compare_rule(se, sh, votes, smap, ref, h, w)
+        out = dn.denoise(x, -1.0, p).cpu().numpy()
+        U, V = basis3
+        want = oracle.denoise(noisy, U, V, ref["tau"], s=s, W=W, K=K)
+        m = assert_pixel_parity(out, want, clean)
+        print("tiles keeping the map %d of %d, adjusted %d; %s" % (n_keep, ref["use_plain"].size,
+                                                                   int(np.sum(2 * ref["votes"] > ref["nvotes"])), m))
+    finally:
+        ht.htsvd_cnn_set_weights(dn.ctx, 3, w0)
+
+
+def test_batched_learned_auto_k_matches_oracle(dn, basis3):
+    """HTSVD_K_AUTO with the learned map and the vote: the group size each image took, the
+    thresholds its filter applied, and its pixels, against the oracle rule at K = 32 (the
+    groups the vote and the choice use) followed by the oracle denoiser at the chosen K."""
+    import paper_2512_23569_amd as ht
+    shapes = [(200, 256), (256, 320), (160, 224), (300, 200)]
+    sig = [12.0, 25.0, 45.0, 65.0]
+    s, W = 4, 21
+    cl, nz = [], []
+    for i, (h, w) in enumerate(shapes):
+        c = synth.make_clean(h, w, 3, 7200 + i)
+        cl.append(c)
+        nz.append(synth.add_awgn(c, sig[i], 7300 + i))
+    ins = [_dev(x) for x in nz]
+    zs = [dn.sigma_map(x).cpu().numpy() for x in ins]
+    refs = [est.thresholds(nz[i], PS, s, W, 32, z=zs[i]) for i in range(len(nz))]
+    m32 = oracle.tau_multiplier(3, 32)
+    means = [math.fsum((r["tau"] / m32).tolist()) / r["tau"].size for r in refs]
+    order = np.sort(means)
+    cutoff = 0.5 * (order[1] + order[2])                 # two images at 16, two at 32
+    assert min(abs(mm - cutoff) for mm in means) > 1.0
+    p = dn.params(3, stride=s, window=W, adaptive=1, estimator=1)
+    outs = dn.denoise_batch(ins, [-1.0] * len(ins), p, Ks=[ht.HTSVD_K_AUTO] * len(ins), use_graph=True,
+                            k_sigma_cutoff=float(cutoff))
+    torch.cuda.synchronize()
+    U, V = basis3
+    for i, x in enumerate(nz):
+        h, w = x.shape[:2]
+        K = est.auto_group_size(refs[i]["tau"] / m32, cutoff)
+        tau_gpu = torch.zeros(refs[i]["tau"].size, dtype=torch.float64, device="cuda")
+        assert ht.htsvd_batch_inspect(dn.ctx, i, tau_gpu) == K, (i, means[i], cutoff)
+        want_tau = refs[i]["tau"] / m32 * oracle.tau_multiplier(3, K)
+        ys, xs = oracle.ref_grid(h, PS, s), oracle.ref_grid(w, PS, s)
+        keep_ref = ~refs[i]["use_plain"][est.tile_of_refs(ys, xs, h, w)]
+        tol = np.where(keep_ref, 1e-12, 1e-9)
+        tg = tau_gpu.cpu().numpy()
+        assert np.all(np.abs(tg - want_tau) <= tol * want_tau), (i, float(np.max(np.abs(tg - want_tau) / want_tau)))
+        want = oracle.denoise(x, U, V, want_tau, s=s, W=W, K=K)
+        assert_pixel_parity(outs[i].cpu().numpy(), want, cl[i])
+    assert sorted(ht.htsvd_batch_inspect(dn.ctx, i) for i in range(len(nz))) == [16, 16, 32, 32]
