@@ -15,6 +15,7 @@ Network (same definition as the library's kernels, written independently):
   layer 5 3x3 conv 32->32, stride 1, padding 1, ReLU
   layer 6 3x3 conv 32->1,  stride 1, padding 1            -> z = log(sigma), sigma on 0..255
   loss    mean over blocks of |z - log(sigma_target)|
+  update  Adam (adam_step) on FP32 master weights, bf16 copies for the forward pass
 A convolution is y[n,yo,xo,co] = b[co] + sum_{ky,kx,ci} w[co,ky,kx,ci] * xpad[n, s*yo+ky, s*xo+kx, ci]
 with xpad the input padded by one zero pixel on every side; Ho = ceil(H/s).
 Parameters are flat FP32/FP64 in layer order, each layer w[co][ky][kx][ci] then b[co].
@@ -130,6 +131,20 @@ def loss_and_grad(flat: np.ndarray, u8_nhwc: np.ndarray, target_log: np.ndarray,
         dy = dx
     grads.reverse()
     return loss, flatten(grads)
+
+
+def adam_step(w: np.ndarray, m: np.ndarray, v: np.ndarray, g: np.ndarray, t: int, lr: float, b1: float = 0.9,
+              b2: float = 0.999, eps: float = 1e-8):
+    """One Adam update (Kingma and Ba, "Adam: A Method for Stochastic Optimization", ICLR 2015,
+    Algorithm 1) in FP64, step number t >= 1: the biased first and second moment estimates are
+    updated with the gradient g, corrected by 1 - b^t, and the parameters move by
+    lr * m_hat / (sqrt(v_hat) + eps).  Returns the new (w, m, v)."""
+    w, m, v, g = (np.asarray(a, dtype=np.float64) for a in (w, m, v, g))
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    m_hat = m / (1.0 - b1 ** t)
+    v_hat = v / (1.0 - b2 ** t)
+    return w - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
 
 
 def block_targets(sigma_field: np.ndarray, B: int = 8) -> np.ndarray:

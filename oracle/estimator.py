@@ -291,14 +291,17 @@ def tau_from_sigma_map(smap: np.ndarray, h: int, w: int, ps: int, s: int, c: int
 
 def thresholds(img: np.ndarray, ps: int, s: int, W: int, K: int, z=None, adaptive: bool = True, T: int = 128,
                n_vote: int = 15, seed: int = 0, beta: float = 1.2, gamma: int = 13, mult: float | None = None,
-               sigma_known: float | None = None, tiles=None):
+               sigma_known: float | None = None, tiles=None, sigma_plain=None, votes=None):
     """The noise-level rule on one image, from the pixels to the per-reference thresholds:
     sigma_est per sub-image (the known level, the plain estimate, or with a learned map z the
     judged level), the Eq. 23 vote on it (oracle groups of the sampled voters), the effective
     sigma per 8x8 block and tau per reference.  `tiles` restricts the work to those sub-images
-    (entries of the others are NaN; references outside them get tau NaN).
+    (entries of the others are NaN; references outside them get tau NaN).  sigma_plain (plain
+    estimates per tile) and votes ((votes, nvotes) per tile, from groups of K members) may be
+    passed in when already computed by this module for the same image.
     Returns a dict with sigma_plain, sigma_est, use_plain, votes, nvotes, sigma_hat, map, tau."""
     from . import block_match_list, ref_grid
+    votes_given = votes
     a = img if img.ndim == 3 else img[:, :, None]
     h, w, c = a.shape
     nty, ntx = tile_grid(h, w, T)
@@ -307,6 +310,8 @@ def thresholds(img: np.ndarray, ps: int, s: int, W: int, K: int, z=None, adaptiv
     sp = nan.copy()
     if sigma_known is not None:
         sp[todo] = float(sigma_known)
+    elif sigma_plain is not None:
+        sp[todo] = np.asarray(sigma_plain, dtype=np.float64)[todo]
     else:
         sp[todo] = sigma_est_tiles(img, T, ps, tiles=todo)[todo]
     se, up = sp.copy(), np.zeros(nty * ntx, dtype=bool)
@@ -317,7 +322,10 @@ def thresholds(img: np.ndarray, ps: int, s: int, W: int, K: int, z=None, adaptiv
             se[t], up[t] = judge_tile_sigma(np.exp(zz[by0:by1, bx0:bx1]), float(sp[t]))
     votes = np.zeros(nty * ntx, dtype=np.int64)
     nvotes = np.zeros(nty * ntx, dtype=np.int64)
-    if adaptive:
+    if adaptive and votes_given is not None:
+        votes[todo] = np.asarray(votes_given[0])[todo]
+        nvotes[todo] = np.asarray(votes_given[1])[todo]
+    elif adaptive:
         ys, xs = ref_grid(h, ps, s), ref_grid(w, ps, s)
         tile_of = tile_of_refs(ys, xs, h, w, T)
         for t in todo:
