@@ -140,6 +140,23 @@ htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32
                            int64_t in_stride, float sigma, const htsvd_params *p, float *d_out,
                            int64_t out_stride, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): htsvd_denoise with every scratch buffer it needs
+ * (groups, thresholds, the filter's aggregation regions, the noise-level arrays) taken from a
+ * fixed device array of HTSVD_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs
+ * on, from htsvd_create until the process ends.  It allocates nothing (no hipMalloc, hipFree or
+ * allocating library call); the caller still owns d_in and d_out.  Arguments, layout and
+ * results are those of htsvd_denoise, with sigma known or HTSVD_SIGMA_AUTO with the plain
+ * estimator (p->estimator 0) and p->ra 0 (HTSVD_ENOTSUP otherwise).  An image whose scratch
+ * exceeds the array returns HTSVD_ENOMEM before anything is launched (at stride 4, window 31,
+ * K 32 an RGB image of about one megapixel fits).  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other threads, other contexts) race on it, so
+ * issue them one at a time per device. */
+#define HTSVD_NOALLOC_SCRATCH_BYTES (64u << 20)
+htsvd_status htsvd_denoise_noalloc(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                                   int64_t in_stride, float sigma, const htsvd_params *p, float *d_out,
+                                   int64_t out_stride, void *stream);
+
 /* Denoising with a caller-provided threshold per reference (tau of reference r in
  * d_tau_ref[r], FP64, n_ref entries).  Used to check the transform path against the oracle. */
 htsvd_status htsvd_denoise_tau(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,

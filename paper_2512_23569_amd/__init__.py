@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhtsvd.so")
 DATA_DIR = os.path.join(_HERE, "data")
 
 HTSVD_OK, HTSVD_EINVAL, HTSVD_ESHAPE, HTSVD_ENOMEM, HTSVD_EDEVICE, HTSVD_ENOTSUP, HTSVD_ESTATE = 0, -1, -2, -3, -4, -5, -6
+HTSVD_NOALLOC_SCRATCH_BYTES = 64 << 20
 HTSVD_SIGMA_AUTO = -1.0
 HTSVD_K_AUTO = -1
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EDEVICE", -5: "ENOTSUP", -6: "ESTATE"}
@@ -82,6 +83,7 @@ _SIGS = {
     "htsvd_block_match": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _PP, _vp, _vp, _vp]),
     "htsvd_denoise": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _i64, _vp]),
     "htsvd_denoise_tau": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _vp, _PP, _vp, _i64, _vp]),
+    "htsvd_denoise_noalloc": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _f32, _PP, _vp, _i64, _vp]),
     "htsvd_denoise_sweep": (_i32, [_vp, _vp, _i32, _i32, _i32, _i64, _i32, ctypes.POINTER(htsvd_sweep_item), _PP,
                                    _vp]),
     "htsvd_denoise_batch": (_i32, [_vp, _i32, ctypes.POINTER(htsvd_image), _PP, ctypes.POINTER(htsvd_batch_opts), _vp]),
@@ -233,6 +235,14 @@ def htsvd_denoise(ctx, d_in, h, w, c, in_stride, sigma, params, d_out, out_strid
     _check(lib().htsvd_denoise(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, c, in_stride, float(sigma),
                                ctypes.byref(params), _dptr(d_out, torch.float32, "d_out"), out_stride,
                                _stream(stream)))
+
+
+def htsvd_denoise_noalloc(ctx, d_in, h, w, c, in_stride, sigma, params, d_out, out_stride, stream=None):
+    """htsvd_denoise with its scratch in the library's fixed per-GPU array (no allocation)."""
+    import torch
+    _check(lib().htsvd_denoise_noalloc(ctx, _dptr(d_in, torch.uint8, "d_in"), h, w, c, in_stride, float(sigma),
+                                       ctypes.byref(params), _dptr(d_out, torch.float32, "d_out"), out_stride,
+                                       _stream(stream)))
 
 
 def htsvd_denoise_tau(ctx, d_in, h, w, c, in_stride, d_tau_ref, params, d_out, out_stride, stream=None):

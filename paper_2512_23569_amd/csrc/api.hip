@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,38 @@ int bm_lds_bytes(int s, int W, int h, int w);
 }  // namespace htsvd
 
 using namespace htsvd;
+
+// Scratch of htsvd_denoise_noalloc: a fixed device array, one copy per GPU, held until the
+// process ends.  Host code never uses the array's name as an address (on the host it names a
+// stand-in, not device memory): htsvd_create looks up each device's address once, with that
+// device current, and the entry point passes that address to the kernels.
+static __device__ __align__(256) unsigned char scratch[HTSVD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+void *g_scratch_addr[SCRATCH_MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+
+// Device address of `scratch` on `device` (looked up by htsvd_create), or nullptr.
+void *scratch_ptr(int device) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_addr[device];
+}
+
+// Records the address on the current device `device`; false if the lookup failed.
+bool lookup_scratch(int device, hipError_t *err) {
+    *err = hipSuccess;
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return false;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_addr[device]) return true;
+    void *ptr = nullptr;
+    *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess || !ptr) return false;
+    g_scratch_addr[device] = ptr;
+    return true;
+}
+}  // namespace
 
 // RA-Haar-tSVD refinement network: FP32 master weights with Adam state, and the fp16 hi/lo
 // operand tables the inference kernel reads (plain, and with the last layer folded with the
@@ -733,6 +766,9 @@ htsvd_status htsvd_create(htsvd_ctx **out, int device) {
     *out = nullptr;
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipError_t se;
+    if (!lookup_scratch(device, &se))
+        return se != hipSuccess ? hip_fail(se, "scratch address") : fail(HTSVD_ENOTSUP, "device index too large");
     htsvd_ctx *ctx = new htsvd_ctx();
     ctx->device = device;
     e = hipMalloc(&ctx->d_guard, 2 * sizeof(unsigned long long));
@@ -1072,9 +1108,16 @@ htsvd_status htsvd_denoise_tau(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, i
     return run_filter(ctx, g, mp, wk, d_tau_ref, d_out, out_stride, st, ra_d, ra_f);
 }
 
-htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
-                           int64_t in_stride, float sigma, const htsvd_params *p, float *d_out,
-                           int64_t out_stride, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// htsvd_denoise on the context's workspace (fixed_ws == nullptr, grown on demand), or on a
+// caller-fixed block of fixed_cap bytes that is never grown (the no-allocation entry point:
+// plain or known sigma, no RA, so that no other buffer is needed).
+htsvd_status denoise_impl(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c, int64_t in_stride,
+                          float sigma, const htsvd_params *p, float *d_out, int64_t out_stride, void *stream,
+                          void *fixed_ws, size_t fixed_cap) {
     ImageGeom g;
     MethodParams mp;
     htsvd_status s = validate(ctx, d_in, h, w, c, in_stride, p, &g, &mp, true);
@@ -1087,8 +1130,18 @@ htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32
     const int tile = p->subimage;
     Ws w0 = plan_ws(nullptr, g, mp.W, mp.K, tile);
     const size_t off_ra = align256(w0.total);
-    if ((s = ensure_ws(ctx, off_ra + (p->ra ? ra_ws_bytes(g) : 0))) != HTSVD_OK) return s;
-    Ws wk = plan_ws(ctx->ws, g, mp.W, mp.K, tile);
+    void *base = fixed_ws;
+    if (fixed_ws) {
+        if (learned) return fail(HTSVD_ENOTSUP, "the no-allocation call takes the plain estimator or a known sigma");
+        if (p->ra) return fail(HTSVD_ENOTSUP, "the no-allocation call does not run RA-Haar-tSVD");
+        if (w0.total > fixed_cap)
+            return fail(HTSVD_ENOMEM, "the image needs " + std::to_string(w0.total) + " bytes of scratch; the "
+                                      "fixed array holds " + std::to_string(fixed_cap));
+    } else {
+        if ((s = ensure_ws(ctx, off_ra + (p->ra ? ra_ws_bytes(g) : 0))) != HTSVD_OK) return s;
+        base = ctx->ws;
+    }
+    Ws wk = plan_ws(base, g, mp.W, mp.K, tile);
     const double mult = p->tau_mult > 0.0 ? p->tau_mult : default_mult(c, mp.K);
     hipStream_t st = (hipStream_t)stream;
     const float *zmap = nullptr;
@@ -1111,6 +1164,26 @@ htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32
                      HTSVD_OK)
         return s;
     return run_filter(ctx, g, mp, wk, wk.tau, d_out, out_stride, st, ra_d, ra_f);
+}
+
+}  // namespace
+
+extern "C" {
+
+htsvd_status htsvd_denoise(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                           int64_t in_stride, float sigma, const htsvd_params *p, float *d_out,
+                           int64_t out_stride, void *stream) {
+    return denoise_impl(ctx, d_in, h, w, c, in_stride, sigma, p, d_out, out_stride, stream, nullptr, 0);
+}
+
+htsvd_status htsvd_denoise_noalloc(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
+                                   int64_t in_stride, float sigma, const htsvd_params *p, float *d_out,
+                                   int64_t out_stride, void *stream) {
+    if (!ctx) return fail(HTSVD_EINVAL, "null context");
+    void *ptr = scratch_ptr(ctx->device);
+    if (!ptr) return fail(HTSVD_ESTATE, "no scratch address for this device");
+    return denoise_impl(ctx, d_in, h, w, c, in_stride, sigma, p, d_out, out_stride, stream, ptr,
+                        (size_t)HTSVD_NOALLOC_SCRATCH_BYTES);
 }
 
 htsvd_status htsvd_denoise_sweep(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h, int32_t w, int32_t c,
