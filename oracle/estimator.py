@@ -350,8 +350,8 @@ def thresholds(img: np.ndarray, ps: int, s: int, W: int, K: int, z=None, adaptiv
 
 def auto_group_size(sigma_ref: np.ndarray, cutoff: float) -> int:
     """Group size of an image in the batched auto mode (the library's reading: the K-selection
-    of Sec. IV-A made per image): 16 when the mean effective sigma over its references lies below
-    the cutoff, else 32."""
+    of Sec. IV-A made per image): 16 when the mean effective sigma over its references, before the
+    Eq. 23 vote, lies below the cutoff, else 32.  The vote then runs on groups of that size."""
     import math
     v = np.asarray(sigma_ref, dtype=np.float64).reshape(-1)
     return 16 if math.fsum(v.tolist()) / v.size < cutoff else 32

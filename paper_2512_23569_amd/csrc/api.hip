@@ -1724,7 +1724,9 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
     const size_t o_q = reserve(sizeof(int) * (1 + P.classes.size()));
     // noise-level stage tables over the images whose sigma is estimated or adjusted
     std::vector<SigmaItem> sitems;
+    std::vector<int> sitem_img;   // image (index into P.im) of each item
     std::vector<int> cov_sel, tile_sel, ref_sel, cov_st{0}, tile_st{0}, ref_st{0};
+    std::vector<int> aref_sel, aref_st{0};   // auto-K images among them (level before the vote)
     constexpr int NVK = 4;
     const int vK[NVK] = {4, 8, 16, 32};
     std::vector<int> vote_sel[NVK], vote_st[NVK];
@@ -1750,8 +1752,10 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
         si.votes = w.votes;
         si.use_plain = w.use_plain;
         si.zmap = b.learned ? (const float *)((char *)ctx->ws + b.off_z) : nullptr;
+        si.ksel = nullptr;   // set to the device choice below for auto images
         const int k = (int)sitems.size();
         sitems.push_back(si);
+        sitem_img.push_back(i);
         if (si.mode != SIGMA_KNOWN) {
             cov_sel.push_back(k);
             cov_st.push_back(cov_st.back() + si.n_tiles * b.g.c);
@@ -1759,14 +1763,21 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
         tile_sel.push_back(k);
         tile_st.push_back(tile_st.back() + si.n_tiles);
         if (si.adaptive) {
-            int v = 0;
-            while (v < NVK && vK[v] != si.K) ++v;
-            if (v == NVK) return fail(HTSVD_ENOTSUP, "group size without a vote kernel");
-            vote_sel[v].push_back(k);
-            vote_st[v].push_back(vote_st[v].back() + si.n_tiles);
+            // an auto image votes with the groups of the size chosen for it (16 or 32): it is listed
+            // for both, and the vote launch of the other size skips it
+            for (int v = 0; v < NVK; ++v) {
+                if (!(vK[v] == si.K || (b.auto_k && vK[v] == 16))) continue;
+                vote_sel[v].push_back(k);
+                vote_st[v].push_back(vote_st[v].back() + si.n_tiles);
+            }
+            if (std::find(vK, vK + NVK, si.K) == vK + NVK) return fail(HTSVD_ENOTSUP, "group size without a vote kernel");
         }
         ref_sel.push_back(k);
         ref_st.push_back(ref_st.back() + (int)b.n_ref);
+        if (b.auto_k) {
+            aref_sel.push_back(k);
+            aref_st.push_back(aref_st.back() + (int)b.n_ref);
+        }
     }
     const size_t o_sitems = reserve(sizeof(SigmaItem) * std::max<size_t>(1, sitems.size()));
     // per size class of learned images: their input pointers and row strides
@@ -1779,6 +1790,7 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
     const size_t o_cov_sel = reserve_ints(cov_sel), o_cov_st = reserve_ints(cov_st);
     const size_t o_tile_sel = reserve_ints(tile_sel), o_tile_st = reserve_ints(tile_st);
     const size_t o_ref_sel = reserve_ints(ref_sel), o_ref_st = reserve_ints(ref_st);
+    const size_t o_aref_sel = reserve_ints(aref_sel), o_aref_st = reserve_ints(aref_st);
     size_t o_vote_sel[NVK], o_vote_st[NVK];
     for (int v = 0; v < NVK; ++v) {
         o_vote_sel[v] = reserve_ints(vote_sel[v]);
@@ -1811,6 +1823,8 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
     for (size_t k = 0; k < P.classes.size(); ++k)
         for (size_t j = 0; j < cls_items[k].size(); ++j)
             if (P.im[cls_src[k][j]].auto_k) cls_items[k][j].ksel = d_ksel + cls_src[k][j];
+    for (size_t k = 0; k < sitems.size(); ++k)
+        if (P.im[sitem_img[k]].auto_k) sitems[k].ksel = d_ksel + sitem_img[k];
     std::vector<unsigned char> host(off, 0);
     memcpy(host.data() + o_items, items.data(), sizeof(BatchItem) * ni);
     for (size_t k = 0; k < P.classes.size(); ++k) {
@@ -1840,6 +1854,8 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
     put_ints(o_tile_st, tile_st);
     put_ints(o_ref_sel, ref_sel);
     put_ints(o_ref_st, ref_st);
+    put_ints(o_aref_sel, aref_sel);
+    put_ints(o_aref_st, aref_st);
     for (int v = 0; v < NVK; ++v) {
         put_ints(o_vote_sel[v], vote_sel[v]);
         put_ints(o_vote_st[v], vote_st[v]);
@@ -1915,6 +1931,21 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
             if ((e2 = launch_sigma_tiles_batched(S, I(o_tile_sel), I(o_tile_st), (int)tile_sel.size(), tile_st.back(),
                                                  T, JUDGE_RATIO, ls)) != hipSuccess)
                 return hip_fail(e2, "batched sigma tiles");
+            // auto-K images: thresholds at the level before the vote, from which the group size is
+            // chosen; the vote then runs on the groups of that size
+            if ((e2 = launch_fill_tau_sigma_batched(S, I(o_aref_sel), I(o_aref_st), (int)aref_sel.size(),
+                                                    aref_st.back(), T, ls)) != hipSuccess)
+                return hip_fail(e2, "batched thresholds before the vote");
+        }
+        if ((e2 = launch_select_k(d_items, (const int *)(D + o_auto), (int)auto_list.size(), k_chunks,
+                                  (double *)(D + o_kpart), (const double *)(D + o_mult), (double)o.k_sigma_cutoff,
+                                  (int *)(D + o_ksel), ls)) != hipSuccess)
+            return hip_fail(e2, "group size selection");
+        if (!sitems.empty()) {
+            StageScope sc(ctx, HTSVD_STAGE_SIGMA, ls);
+            const int T = p->subimage;
+            const SigmaItem *S = (const SigmaItem *)(D + o_sitems);
+            auto I = [&](size_t o2) { return (const int *)(D + o2); };
             for (int v = 0; v < NVK; ++v)
                 if ((e2 = launch_vote_batched(vK[v], S, I(o_vote_sel[v]), I(o_vote_st[v]), (int)vote_sel[v].size(),
                                               vote_st[v].back(), T, p->n_vote, p->vote_seed, p->gamma_rank, p->beta,
@@ -1924,10 +1955,6 @@ htsvd_status htsvd_denoise_batch(htsvd_ctx *ctx, int32_t n, const htsvd_image *i
                                                     ls)) != hipSuccess)
                 return hip_fail(e2, "batched thresholds");
         }
-        if ((e2 = launch_select_k(d_items, (const int *)(D + o_auto), (int)auto_list.size(), k_chunks,
-                                  (double *)(D + o_kpart), (const double *)(D + o_mult), (double)o.k_sigma_cutoff,
-                                  (int *)(D + o_ksel), ls)) != hipSuccess)
-            return hip_fail(e2, "group size selection");
         for (size_t k = 0; k < P.classes.size(); ++k) {
             const int units = cls_start[k].back();
             if ((e2 = launch_filter_batched(C, P.classes[k], (const BatchItem *)(D + o_citems[k]), (int)cls_items[k].size(),

@@ -94,7 +94,9 @@ struct BatchItem {
 enum SigmaMode { SIGMA_KNOWN = 0, SIGMA_PLAIN = 1, SIGMA_LEARNED = 2 };
 struct SigmaItem {
     ImageGeom g;
-    int K;                  // members per stored group (the vote reads the first K of each)
+    int K;                  // members per stored group
+    const int *ksel;        // group size chosen on the device (auto images; the vote reads the first
+                            // *ksel members of each group), or nullptr: the vote reads all K
     int mode;               // SigmaMode
     int adaptive;           // Eq. 22-23 vote on
     int n_tiles;            // sub-images

@@ -370,7 +370,7 @@ __global__ void combine_sigma_kernel(const double *sigma2, int c, int n_tiles, d
 }
 
 // Batched per-sub-image stage: sigma_est from a known sigma, the plain estimate, or the learned
-// map judged by the plain estimate; without the vote, sigma_hat = sigma_est and no votes.
+// map judged by the plain estimate; sigma_hat = sigma_est until the vote (if on) replaces it.
 __global__ void sigma_tiles_batched_kernel(const SigmaItem *__restrict__ items, const int *__restrict__ sel,
                                            const int *__restrict__ start, int n, int total, int T,
                                            double bound) {
@@ -392,10 +392,8 @@ __global__ void sigma_tiles_batched_kernel(const SigmaItem *__restrict__ items, 
         }
     }
     it.sig_est[t] = se;
-    if (!it.adaptive) {
-        it.sig_hat[t] = se;
-        it.votes[t] = 0;
-    }
+    it.sig_hat[t] = se;   // the level before the vote (the vote, when on, replaces it)
+    if (!it.adaptive) it.votes[t] = 0;
 }
 
 __global__ void fill_const_kernel(double *p, int n, double v) {
@@ -442,8 +440,8 @@ struct VoteShared {
 };
 
 template <int K>
-__device__ __forceinline__ void vote_tile(VoteShared<K> &sh, const ImageGeom g, const int32_t *__restrict__ idx, int T, int t,
-                                 int n_vote, uint64_t seed, int gamma_rank, double beta,
+__device__ __forceinline__ void vote_tile(VoteShared<K> &sh, const ImageGeom g, const int32_t *__restrict__ idx,
+                                 int idx_stride, int T, int t, int n_vote, uint64_t seed, int gamma_rank, double beta,
                                  const double *__restrict__ sigma_est, double *__restrict__ sigma_hat,
                                  int32_t *__restrict__ votes) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -486,7 +484,7 @@ __device__ __forceinline__ void vote_tile(VoteShared<K> &sh, const ImageGeom g, 
             int v[K];
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                const int32_t lin = idx[r * K + m];
+                const int32_t lin = idx[r * idx_stride + m];
                 const int y = lin / g.w, x = lin % g.w;
                 v[m] = g.img[(int64_t)(y + a) * g.stride + (int64_t)(x + b) * g.c + ch];
             }
@@ -533,7 +531,7 @@ __global__ __launch_bounds__(256) void vote_kernel(ImageGeom g, const int32_t *_
                                                    const double *__restrict__ sigma_est, double *__restrict__ sigma_hat,
                                                    int32_t *__restrict__ votes) {
     __shared__ VoteShared<K> sh;
-    vote_tile<K>(sh, g, idx, T, blockIdx.x, n_vote, seed, gamma_rank, beta, sigma_est, sigma_hat, votes);
+    vote_tile<K>(sh, g, idx, K, T, blockIdx.x, n_vote, seed, gamma_rank, beta, sigma_est, sigma_hat, votes);
 }
 
 template <int K>
@@ -544,8 +542,11 @@ __global__ __launch_bounds__(256) void vote_kernel_batched(const SigmaItem *__re
     __shared__ VoteShared<K> sh;
     const int j = find_unit(start, n, blockIdx.x);
     const SigmaItem &it = items[sel[j]];
-    vote_tile<K>(sh, it.g, it.idx, T, blockIdx.x - start[j], n_vote, seed, gamma_rank, beta, it.sig_est, it.sig_hat,
-                 it.votes);
+    // an image whose group size is chosen on the device is listed for both sizes; the launch of
+    // the other size leaves it (the condition is uniform over the workgroup)
+    if (it.ksel && *it.ksel != K) return;
+    vote_tile<K>(sh, it.g, it.idx, it.K, T, blockIdx.x - start[j], n_vote, seed, gamma_rank, beta, it.sig_est,
+                 it.sig_hat, it.votes);
 }
 
 }  // namespace

@@ -214,22 +214,30 @@ def test_12mp_batched_learned_form_bands(dn, bench_img, bench_sigma, basis3):
         out = d.denoise_batch([x], [-1.0], p, Ks=[ht.HTSVD_K_AUTO], use_graph=True, k_sigma_cutoff=cutoff)
         out = d.denoise_batch([x], [-1.0], p, outs=out, Ks=[ht.HTSVD_K_AUTO], use_graph=True,
                               k_sigma_cutoff=cutoff)[0].cpu().numpy()
-        full = est.thresholds(noisy, PS, S, W, K, z=z, sigma_plain=sp, votes=votes)
+        pre = est.thresholds(noisy, PS, S, W, K, z=z, sigma_plain=sp, adaptive=False)
         m32 = oracle.tau_multiplier(3, 32)
-        K_used = est.auto_group_size(full["tau"] / m32, cutoff)
+        K_used = est.auto_group_size(pre["tau"] / m32, cutoff)
         assert ht.htsvd_batch_inspect(d.ctx, 0) == K_used
-        tau_k = full["tau"] / m32 * oracle.tau_multiplier(3, K_used)
-        tau_gpu = torch.zeros(tau_k.size, dtype=torch.float64, device="cuda")
+        tau_gpu = torch.zeros(pre["tau"].size, dtype=torch.float64, device="cuda")
         ht.htsvd_batch_inspect(d.ctx, 0, tau_gpu)
         tg = tau_gpu.cpu().numpy()
         ys, xs = oracle.ref_grid(h, PS, S), oracle.ref_grid(w, PS, S)
-        keep_ref = ~full["use_plain"][est.tile_of_refs(ys, xs, h, w)]
-        tol = np.where(keep_ref, 1e-12, 1e-9)
-        assert np.all(np.abs(tg - tau_k) <= tol * tau_k), float(np.max(np.abs(tg - tau_k) / tau_k))
+        tile_of = est.tile_of_refs(ys, xs, h, w)
+        ny, nx = oracle.n_refs(h, w, PS, S)
+        def tau_of_tiles(tiles):
+            # the vote of the sampled tiles on groups of the chosen size (the first K_used members)
+            votes_k = votes if K_used == 32 else None
+            r = est.thresholds(noisy, PS, S, W, K_used, z=z, sigma_plain=sp, votes=votes_k, tiles=tiles)
+            sel = np.isfinite(r["tau"])
+            keep_ref = ~r["use_plain"][tile_of[sel]]
+            tol = np.where(keep_ref, 1e-12, 1e-9)
+            assert np.all(np.abs(tg[sel] - r["tau"][sel]) <= tol * r["tau"][sel]), \
+                float(np.max(np.abs(tg[sel] - r["tau"][sel]) / r["tau"][sel]))
+            return r["tau"]
+
         U, V = basis3
-        res = _oracle_bands(noisy, out, clean, lambda tiles: tau_k, K_used, U, V)
-        print("batched + learned: K %d, tiles keeping the map %d of %d, bands %s"
-              % (K_used, int(np.sum(~full["use_plain"])), full["use_plain"].size, res))
+        res = _oracle_bands(noisy, out, clean, tau_of_tiles, K_used, U, V)
+        print("batched + learned: K %d, bands %s" % (K_used, res))
     finally:
         d.close()
 

@@ -148,8 +148,9 @@ def test_learned_rule_and_denoised_pixels_match_oracle(dn, varying, basis3):
 
 def test_batched_learned_auto_k_matches_oracle(dn, basis3):
     """HTSVD_K_AUTO with the learned map and the vote: the group size each image took, the
-    thresholds its filter applied, and its pixels, against the oracle rule at K = 32 (the
-    groups the vote and the choice use) followed by the oracle denoiser at the chosen K."""
+    thresholds its filter applied, and its pixels, against the oracle rule: the group size from
+    the mean level before the vote, then the vote on the groups of that size (the first K of
+    the 32-member groups are the K-member groups), then the oracle denoiser at that size."""
     import paper_2512_23569_amd as ht
     shapes = [(200, 256), (256, 320), (160, 224), (300, 200)]
     sig = [12.0, 25.0, 45.0, 65.0]
@@ -161,9 +162,9 @@ def test_batched_learned_auto_k_matches_oracle(dn, basis3):
         nz.append(synth.add_awgn(c, sig[i], 7300 + i))
     ins = [_dev(x) for x in nz]
     zs = [dn.sigma_map(x).cpu().numpy() for x in ins]
-    refs = [est.thresholds(nz[i], PS, s, W, 32, z=zs[i]) for i in range(len(nz))]
+    pre = [est.thresholds(nz[i], PS, s, W, 32, z=zs[i], adaptive=False) for i in range(len(nz))]
     m32 = oracle.tau_multiplier(3, 32)
-    means = [math.fsum((r["tau"] / m32).tolist()) / r["tau"].size for r in refs]
+    means = [math.fsum((r["tau"] / m32).tolist()) / r["tau"].size for r in pre]
     order = np.sort(means)
     cutoff = 0.5 * (order[1] + order[2])                 # two images at 16, two at 32
     assert min(abs(mm - cutoff) for mm in means) > 1.0
@@ -174,15 +175,15 @@ def test_batched_learned_auto_k_matches_oracle(dn, basis3):
     U, V = basis3
     for i, x in enumerate(nz):
         h, w = x.shape[:2]
-        K = est.auto_group_size(refs[i]["tau"] / m32, cutoff)
-        tau_gpu = torch.zeros(refs[i]["tau"].size, dtype=torch.float64, device="cuda")
+        K = est.auto_group_size(pre[i]["tau"] / m32, cutoff)
+        ref = est.thresholds(x, PS, s, W, K, z=zs[i], sigma_plain=pre[i]["sigma_plain"])
+        tau_gpu = torch.zeros(ref["tau"].size, dtype=torch.float64, device="cuda")
         assert ht.htsvd_batch_inspect(dn.ctx, i, tau_gpu) == K, (i, means[i], cutoff)
-        want_tau = refs[i]["tau"] / m32 * oracle.tau_multiplier(3, K)
         ys, xs = oracle.ref_grid(h, PS, s), oracle.ref_grid(w, PS, s)
-        keep_ref = ~refs[i]["use_plain"][est.tile_of_refs(ys, xs, h, w)]
+        keep_ref = ~ref["use_plain"][est.tile_of_refs(ys, xs, h, w)]
         tol = np.where(keep_ref, 1e-12, 1e-9)
         tg = tau_gpu.cpu().numpy()
-        assert np.all(np.abs(tg - want_tau) <= tol * want_tau), (i, float(np.max(np.abs(tg - want_tau) / want_tau)))
-        want = oracle.denoise(x, U, V, want_tau, s=s, W=W, K=K)
+        assert np.all(np.abs(tg - ref["tau"]) <= tol * ref["tau"]), (i, float(np.max(np.abs(tg - ref["tau"]) / ref["tau"])))
+        want = oracle.denoise(x, U, V, ref["tau"], s=s, W=W, K=K)
         assert_pixel_parity(outs[i].cpu().numpy(), want, cl[i])
     assert sorted(ht.htsvd_batch_inspect(dn.ctx, i) for i in range(len(nz))) == [16, 16, 32, 32]
