@@ -71,32 +71,14 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v, int j, int lane) {
-    const uint32_t lo = xor_lane((uint32_t)v, j, lane), hi = xor_lane((uint32_t)(v >> 32), j, lane);
-    return ((uint64_t)hi << 32) | lo;
-}
-
 __device__ inline uint64_t readlane_u64(uint64_t v, int l) {
     uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
     uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Ascending bitonic sort of one u64 per lane across the 64 lanes of a wave.
-__device__ inline uint64_t wave_sort64(uint64_t v, int lane) {
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            uint64_t p = xor_lane_u64(v, j, lane);
-            bool up = (lane & k) == 0;
-            bool lower = (lane & j) == 0;
-            uint64_t mn = v < p ? v : p, mx = v < p ? p : v;
-            v = (lower == up) ? mn : mx;
-        }
-    }
-    return v;
-}
+// Ascending sort of one u64 per lane across the 64 lanes of a wave.
+__device__ inline uint64_t wave_sort64(uint64_t v, int lane) { return wave_sort_asc<uint64_t>(v, lane); }
 
 __device__ inline int wave_excl_scan(int v, int lane, int *total) {
     int x = v;
@@ -109,14 +91,15 @@ __device__ inline int wave_excl_scan(int v, int lane, int *total) {
     return x - v;
 }
 
-// Ascending bitonic sort of P (power of two <= SEL_CAP) u64 keys in LDS by one wave.
-__device__ void lds_sort(uint64_t *a, int P, int lane) {
+// Ascending bitonic sort of P (power of two <= SEL_CAP) keys in LDS by one wave.
+template <typename T>
+__device__ void lds_sort(T *a, int P, int lane) {
     for (int k = 2; k <= P; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int t = lane; t < P / 2; t += 64) {
                 int i = 2 * t - (t & (j - 1));
                 int m = i + j;
-                uint64_t x = a[i], y = a[m];
+                T x = a[i], y = a[m];
                 bool up = (i & k) == 0;
                 if ((x > y) == up) {
                     a[i] = y;
@@ -528,6 +511,50 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g0, const MethodParams 
             int pmin = 0;
 #pragma unroll
             for (int i = NPL - 1; i >= 0; --i) pmin = dv[i] == dmin ? lane + 64 * i : pmin;
+            if (!VIDEO && ti.green[ii]) {
+                // green or gray distances are below 2^22 (64 * 255^2) and positions below 1024, so
+                // the key (distance, position) fits 32 bits and stays below the empty key ~0
+                const uint32_t lmin32 = dmin == 0xFFFFFFFFu ? ~0u : ((dmin << 10) | (uint32_t)pmin);
+                const uint32_t sorted32 = wave_sort_asc<uint32_t>(lmin32, lane);
+                const uint32_t theta32 = __builtin_amdgcn_readlane(sorted32, K - 1);
+                int cnt32 = 0;
+#pragma unroll
+                for (int i = 0; i < NPL; ++i) {
+                    const int p = lane + 64 * i;
+                    cnt32 += (p < n && ((dv[i] << 10) | (uint32_t)p) <= theta32);
+                }
+                int total32;
+                int off32 = wave_excl_scan(cnt32, lane, &total32);
+                uint32_t *sel32 = reinterpret_cast<uint32_t *>(sel);
+#pragma unroll
+                for (int i = 0; i < NPL; ++i) {
+                    const int p = lane + 64 * i;
+                    const uint32_t key = (dv[i] << 10) | (uint32_t)p;
+                    if (p < n && key <= theta32) sel32[off32++] = key;
+                }
+                wave_lds_sync();
+                uint32_t mine32;
+                if (total32 <= 64) {
+                    mine32 = wave_sort_asc<uint32_t>(lane < total32 ? sel32[lane] : ~0u, lane);
+                } else {
+                    int P = 64;
+                    while (P < total32) P <<= 1;
+                    for (int t = total32 + lane; t < P; t += 64) sel32[t] = ~0u;
+                    wave_lds_sync();
+                    lds_sort(sel32, P, lane);
+                    mine32 = lane < K ? sel32[lane] : ~0u;
+                }
+                if (lane < K) {
+                    const int p = (int)(mine32 & 1023u);
+                    const int y = ti.wy0[ii] + p / ti.ww[ii], x = ti.wx0[ii] + p % ti.ww[ii];
+                    const int iy = tyi * REF_TILE + ii / REF_TILE, ix = txi * REF_TILE + ii % REF_TILE;
+                    const int64_t r = (int64_t)iy * g.nx + ix;
+                    idx_out[r * K + lane] = y * g.w + x;
+                    if (dist_out) dist_out[r * K + lane] = (int32_t)(mine32 >> 10);
+                }
+                wave_lds_sync();
+                continue;
+            }
             const uint64_t lmin = dmin == 0xFFFFFFFFu ? ~0ull : (((uint64_t)dmin << 10) | (uint64_t)pmin);
             const uint64_t sorted = wave_sort64(lmin, lane);
             const uint64_t theta = readlane_u64(sorted, K - 1);

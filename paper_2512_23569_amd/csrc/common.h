@@ -144,6 +144,53 @@ __device__ __forceinline__ uint32_t xor_lane(uint32_t v, int j, int lane) {
     return (lane & 32) ? r[0] : r[1];
 }
 
+// Value of v in lane lane ^ (k - 1), k = 2, 4, ..., 64: the mirror image of the lane within its
+// aligned block of k lanes (quad permutations, the half-row and row mirrors of DPP, then the
+// row swaps for the blocks of 32 and 64).
+__device__ __forceinline__ uint32_t mirror_lane(uint32_t v, int k, int lane) {
+    if (k == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);   // [1,0,3,2]
+    if (k == 4) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x1B, 0xF, 0xF, true);   // [3,2,1,0]
+    if (k == 8) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true);  // half-row mirror
+    const uint32_t m = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true);  // row mirror: ^15
+    if (k == 16) return m;
+    const uint32_t m2 = xor_lane(m, 16, lane);   // lane ^ 31
+    if (k == 32) return m2;
+    return xor_lane(m2, 32, lane);               // lane ^ 63
+}
+
+// Ascending sort of one key per lane across the 64 lanes (bitonic network in the form whose
+// every comparator is ascending: each merge of two sorted halves of a block of k lanes starts
+// with lane i against its mirror i ^ (k - 1), then half-cleaners i ^ j; the lower lane of a
+// pair keeps the minimum).  T is uint32_t or uint64_t.
+template <typename T>
+__device__ __forceinline__ T lane_exchange(T v, int k_or_j, int lane, bool mirror) {
+    if constexpr (sizeof(T) == 4) {
+        return mirror ? mirror_lane(v, k_or_j, lane) : xor_lane(v, k_or_j, lane);
+    } else {
+        const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+        const uint32_t plo = mirror ? mirror_lane(lo, k_or_j, lane) : xor_lane(lo, k_or_j, lane);
+        const uint32_t phi = mirror ? mirror_lane(hi, k_or_j, lane) : xor_lane(hi, k_or_j, lane);
+        return ((uint64_t)phi << 32) | plo;
+    }
+}
+
+template <typename T>
+__device__ inline T wave_sort_asc(T v, int lane) {
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+        {
+            const T p = lane_exchange<T>(v, k, lane, true);
+            v = (lane & (k >> 1)) ? (v < p ? p : v) : (p < v ? p : v);
+        }
+#pragma unroll
+        for (int j = k >> 2; j > 0; j >>= 1) {
+            const T p = lane_exchange<T>(v, j, lane, false);
+            v = (lane & j) ? (v < p ? p : v) : (p < v ? p : v);
+        }
+    }
+    return v;
+}
+
 // Value of v in lane l (l uniform over the wavefront), as a scalar.
 __device__ __forceinline__ double readlane_f64(double v, int l) {
     const uint64_t b = __builtin_bit_cast(uint64_t, v);

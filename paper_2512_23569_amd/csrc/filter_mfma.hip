@@ -17,8 +17,9 @@
 //   threshold keep |s| >= tau (Eq. 20); values within 0.05 of tau are re-decided in FP64 from the
 //             uint8 group and the FP64 transform.
 //   inverse   the kept coefficients, recombined as s0 = S0+S1+S2, sr = 2S0-S1-S2, d = S2-S1,
-//             are transposed through LDS into the A-operand layout and multiplied by the inverse
-//             matrix with three products (hi.hi + hi.lo + lo.hi); R, G, B follow as above.
+//             are split into fp16 hi (nearest) + lo, transposed through LDS into the A-operand
+//             layout and multiplied by the inverse matrix with three products
+//             (hi.hi + hi.lo + lo.hi); R, G, B follow as above.
 //   Algorithm 1: every reconstructed patch is added (sums and a count) into an LDS copy of the
 //             image region the tile's groups reach; the region goes to the tile's slot of a
 //             global buffer and the gather kernel divides.  Groups whose members lie anywhere
@@ -597,7 +598,9 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
                 const int tlo = sl == 0 ? 0 : 2, ntile = sl == 0 ? 2 : 4;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    // hi = v rounded to fp16 (nearest), lo = the rest (toward zero), one word
+                    // hi = v rounded to fp16 (nearest), lo = the rest (toward zero), one word.
+                    // Rounding keeps |lo| <= 2^-11 |v|; a hi cut toward zero (one AND) doubles the
+                    // residual and missed the pixel bar on the large refined rows of RA-Haar-tSVD.
                     const float v = acc[sl][r];
                     const float hf = (float)(_Float16)v;
                     xbuf[(16 * h + r) * XS + c32] = pack_rtz(hf, v - hf);
