@@ -609,12 +609,17 @@ __device__ __forceinline__ void filter_tile_mfma(const ImageGeom &g, const TileG
 #pragma unroll
                 for (int ss = 0; ss < 2; ++ss) {
                     v8h ahi, alo;
+                    uint32_t any = 0;
 #pragma unroll
                     for (int jj = 0; jj < 8; ++jj) {
                         const uint32_t wd = xbuf[mu_in * XS + 16 * ss + 8 * h + jj];
+                        any |= wd;
                         ahi[jj] = __builtin_bit_cast(_Float16, (uint16_t)(wd & 0xffffu));
                         alo[jj] = __builtin_bit_cast(_Float16, (uint16_t)(wd >> 16));
                     }
+                    // a block of 16 coefficient positions that thresholding killed in all 32 patches
+                    // adds nothing: its products are skipped (wave-uniform; the sums are unchanged)
+                    if (!__builtin_amdgcn_ballot_w64(any != 0u)) continue;
 #pragma unroll
                     for (int tt = 0; tt < ntile; ++tt) {
                         const int t = tlo + tt;
