@@ -162,6 +162,8 @@ static int basis_init(basis_t *b, const double *U, const double *V, int ps, int 
     double *bVt = (double *)malloc(sizeof(double) * N * N);
     if (!b->bU || !b->bUt || !b->bV0 || !b->bVt0 || !bV || !bVt) {
         free(bV); free(bVt);
+        free(b->bU); free(b->bUt); free(b->bV0); free(b->bVt0);
+        b->bU = b->bUt = b->bV0 = b->bVt0 = NULL;
         return ORC_ENOMEM;
     }
     orc_bcirc(U, ps, c, b->bU);
@@ -361,6 +363,7 @@ int orc_block_match(const uint8_t *img, int h, int w, int c, int64_t stride, int
         for (int r = 0; r < ny * nx; ++r) {
             int e = group_one(&m, ys[r / nx], xs[r % nx], cand, gy, gx, gd);
             if (e) {
+                #pragma omp atomic write
                 status = e;
                 continue;
             }
@@ -403,11 +406,13 @@ int orc_block_match_list(const uint8_t *img, int h, int w, int c, int64_t stride
         for (int64_t i = 0; i < n; ++i) {
             const int64_t r = refs[i];
             if (r < 0 || r >= (int64_t)ny * nx) {
+                #pragma omp atomic write
                 status = ORC_EINVAL;
                 continue;
             }
             int e = group_one(&m, ys[r / nx], xs[r % nx], cand, gy, gx, gd);
             if (e) {
+                #pragma omp atomic write
                 status = e;
                 continue;
             }
@@ -441,16 +446,19 @@ int orc_denoise(const uint8_t *img, int h, int w, int c, int64_t stride, int ps,
     if (err) return err;
     int *ys = (int *)malloc(sizeof(int) * (h / s + 2));
     int *xs = (int *)malloc(sizeof(int) * (w / s + 2));
+    double *H = (double *)malloc(sizeof(double) * K * K);
+    basis_t basis;
+    if (!ys || !xs || !H || basis_init(&basis, U, V, ps, c)) {
+        free(ys); free(xs); free(H);
+        return ORC_ENOMEM;
+    }
     const int ny = orc_ref_grid(h, ps, s, ys), nx = orc_ref_grid(w, ps, s, xs);
     const int64_t n_ref = (int64_t)ny * nx;
     if (r_end < 0 || r_end > n_ref) r_end = n_ref;
     if (r_begin < 0) r_begin = 0;
     const int R = (W - 1) / 2;
     const int P = ps * ps * c; /* values per patch */
-    double *H = (double *)malloc(sizeof(double) * K * K);
     orc_haar(K, H);
-    basis_t basis;
-    if (basis_init(&basis, U, V, ps, c)) return ORC_ENOMEM;
     bm_ctx_t m = {img, h, w, c, stride, ps, W, K, gnum, gden};
 
     double *num = (double *)calloc((size_t)h * w * c, sizeof(double));
@@ -497,6 +505,7 @@ int orc_denoise(const uint8_t *img, int h, int w, int c, int64_t stride, int ps,
                 const int y = ys[r / nx], x = xs[r % nx];
                 int e = group_one(&m, y, x, cand, gy, gx, NULL);
                 if (e) {
+                    #pragma omp atomic write
                     status = e;
                     continue;
                 }
@@ -623,6 +632,7 @@ int orc_block_match_video(const uint8_t *frames, int T, int h, int w, int c, int
                     }
             }
             if (n < K) {
+                #pragma omp atomic write
                 status = ORC_ESHAPE;
                 continue;
             }
@@ -655,9 +665,12 @@ int orc_filter_groups(const uint8_t *img, int h, int w, int c, int64_t stride, i
     }
     const int P = ps * ps * c;
     double *H = (double *)malloc(sizeof(double) * K * K);
-    orc_haar(K, H);
     basis_t basis;
-    if (basis_init(&basis, U, V, ps, c)) return ORC_ENOMEM;
+    if (!H || basis_init(&basis, U, V, ps, c)) {
+        free(H);
+        return ORC_ENOMEM;
+    }
+    orc_haar(K, H);
     double *num = (double *)calloc((size_t)h * w * c, sizeof(double));
     int64_t *cnt = (int64_t *)calloc((size_t)h * w, sizeof(int64_t));
     int nt = 1;

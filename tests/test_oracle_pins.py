@@ -8,6 +8,7 @@ import scipy.fft
 
 import oracle
 import synth
+from helpers import tie_heavy_image
 
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 R2 = 1.0 / np.sqrt(2.0)
@@ -733,3 +734,37 @@ def test_vote_majority_and_adjustment():
     yes = sum(1 for a in ranks[0] if a <= 13)
     assert votes[0] == yes and nv[0] == 15
     assert sig[0] == (10.0 / 1.2 if 2 * yes > 15 else 10.0)
+
+
+def test_block_match_list_of_every_reference_equals_block_match():
+    """The listed-reference entry point of the oracle runs the same rule as the whole-image one:
+    listing every reference (in a shuffled order) gives the same groups and distances row by row."""
+    img = tie_heavy_image(37, 45, 3, 11)
+    idx, dist = oracle.block_match(img, 8, 3, 15, 8)
+    refs = np.random.default_rng(0).permutation(idx.shape[0])
+    li, ld = oracle.block_match_list(img, refs, 8, 3, 15, 8)
+    assert np.array_equal(li, idx[refs]) and np.array_equal(ld, dist[refs])
+    g = tie_heavy_image(30, 33, 1, 12)
+    idx, dist = oracle.block_match(g, 8, 2, 11, 4)
+    li, ld = oracle.block_match_list(g, np.arange(idx.shape[0]), 8, 2, 11, 4)
+    assert np.array_equal(li, idx) and np.array_equal(ld, dist)
+
+
+def test_row_band_denoising_stitches_to_the_whole_image(basis3):
+    """orc_denoise restricted to the references whose groups can reach a band of pixel rows gives
+    that band exactly as the whole-image run (every contribution to those pixels is included)."""
+    U, V = basis3
+    clean, noisy, _ = synth.make_cfg("rgb512_awgn50", h=120, w=96)
+    s, W, K = 3, 15, 8
+    tau = 50.0 * oracle.tau_multiplier(3, K)
+    full = oracle.denoise(noisy, U, V, tau, s=s, W=W, K=K)
+    ny, nx = oracle.n_refs(120, 96, 8, s)
+    ys = oracle.ref_grid(120, 8, s)
+    R = (W - 1) // 2
+    for y0, y1 in ((40, 56), (0, 10), (110, 120)):
+        keep = np.nonzero((ys >= y0 - 7 - R) & (ys <= y1 - 1 + R))[0]
+        a, b = int(keep[0]), int(keep[-1]) + 1
+        band = oracle.denoise(noisy, U, V, tau, s=s, W=W, K=K, r_begin=a * nx, r_end=b * nx)
+        assert np.allclose(band[y0:y1], full[y0:y1], rtol=0, atol=1e-9), (y0, y1)
+        if a > 0:   # rows the band's references do not reach keep the noisy value
+            assert np.array_equal(band[:max(0, int(ys[a]) - R)], noisy[:max(0, int(ys[a]) - R)].astype(np.float64))
