@@ -38,6 +38,10 @@ constexpr int NREF = REF_TILE * REF_TILE;  // 16
 constexpr int BMW = 16;                    // wavefronts per workgroup (four per SIMD)
 constexpr int BMT = BMW * 64;
 constexpr int SEL_CAP = 512;               // >= K * ceil(MAX_CAND / 64) for K <= 32
+// Words per reference row of the distance table: 964 = 4 (mod 64), so the four references a
+// quarter-wave writes for 16 consecutive candidates land on disjoint LDS banks.
+constexpr int TAB_STRIDE = 964;
+static_assert(TAB_STRIDE >= MAX_CAND, "table rows hold a whole window");
 constexpr int RUN_K = 32;                  // running list per reference of the video search
 
 // Frames of a video search: g.img is frame 0 of T frames of g.h rows each, frame_bytes apart.
@@ -59,6 +63,7 @@ struct BmLds {
     int pitch8;     // bytes per row of one int8 plane copy
     int pitch16;    // halves per row of one fp16 plane copy
     int rows;       // plane rows (union rows + 7)
+    int plane8;     // bytes between the int8 plane copies (a row multiple plus a bank offset)
     int off_p8, off_p16, off_n8, off_n16, off_tab, off_sel, total;   // video: running lists last
 };
 
@@ -185,7 +190,7 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g0, const MethodParams 
     int32_t *n8 = reinterpret_cast<int32_t *>(smem + L.off_n8);
     int32_t *n16 = reinterpret_cast<int32_t *>(smem + L.off_n16);
     uint32_t *tab = reinterpret_cast<uint32_t *>(smem + L.off_tab);
-    const int plane8 = L.rows * L.pitch8;
+    const int plane8 = L.plane8;
     const int plane16 = L.rows * L.pitch16;
 
     // Per-lane state of the distance phase, kept across the frames of a video search: the A
@@ -452,7 +457,7 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g0, const MethodParams 
                         const int dy = cy - rwy0[r], dx = cx - rwx0[r];
                         if ((unsigned)dy < (unsigned)rwh[r] && (unsigned)dx < (unsigned)rww[r]) {
                             const int d = rgreen[r] ? rn[r] + nb8 - 2 * acc8[r] : rn[r] + nb16 - 2 * (int)acc16[r];
-                            tab[(4 * q + r) * MAX_CAND + dy * rww[r] + dx] = (uint32_t)d;
+                            tab[(4 * q + r) * TAB_STRIDE + dy * rww[r] + dx] = (uint32_t)d;
                         }
                     }
                 }
@@ -465,7 +470,7 @@ __device__ __forceinline__ void bm_tile(const ImageGeom &g0, const MethodParams 
         for (int ii = wave; ii < NREF; ii += BMW) {
             if (ti.ry[ii] < 0) continue;
             const int n = ti.wh[ii] * ti.ww[ii];
-            const uint32_t *row = tab + ii * MAX_CAND;
+            const uint32_t *row = tab + ii * TAB_STRIDE;
             // this lane's candidates p = lane + 64 i, read once; key = (distance, position)
             constexpr int NPL = (MAX_CAND + 63) / 64;
             uint32_t dv[NPL];
@@ -670,10 +675,18 @@ __global__ __launch_bounds__(BMT) void bm_kernel_batched(const BatchItem *__rest
 BmLds bm_lds_layout(int uh_max, int uw_max, bool video = false) {
     BmLds L;
     L.rows = uh_max + PS - 1;
-    L.pitch8 = ((uw_max + PS + 3) / 4) * 4 + 4;
+    // The int8 planes: rows of 96 bytes (enough for a union of 64 columns plus the patch and the
+    // dword reads past it) and copies 16 bytes past a row multiple apart.  With these offsets the
+    // 64 lanes' dword reads of a distance step (16 consecutive candidates x 4 row pairs, each
+    // candidate in the copy where it starts on a dword) spread over the LDS banks (at most 1.5
+    // reads per bank against 2 to 4 for tightly packed rows, whether 32 or 64 banks serve a
+    // half or a whole wave).
+    const int pitch_min = ((uw_max + PS + 3) / 4) * 4 + 4;
+    L.pitch8 = pitch_min > 96 ? pitch_min : 96;
+    L.plane8 = L.rows * L.pitch8 + 16;
     L.pitch16 = ((uw_max + PS + 1) / 2) * 2 + 2;
     int off = 0;
-    L.off_p8 = off;  off += 4 * L.rows * L.pitch8;
+    L.off_p8 = off;  off += 4 * L.plane8;
     off = (off + 15) & ~15;
     L.off_p16 = off; off += 2 * L.rows * L.pitch16 * 2;
     off = (off + 15) & ~15;
@@ -687,7 +700,7 @@ BmLds bm_lds_layout(int uh_max, int uw_max, bool video = false) {
     if (region < sel_bytes) region = sel_bytes;
     off = (region + 15) & ~15;
     L.off_tab = off;
-    int tab_bytes = NREF * MAX_CAND * 4;
+    int tab_bytes = NREF * TAB_STRIDE * 4;
     const int rs_bytes = 2 * L.rows * uw_max * 4;  // row sums of the norm pass live in the table
     if (tab_bytes < rs_bytes) tab_bytes = rs_bytes;
     off += tab_bytes;
