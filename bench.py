@@ -521,18 +521,28 @@ def bench_sweep(dn, args, clean, d_in, stream, s, W, sigma, gen_s):
     print(json.dumps(result), flush=True)
 
 
-PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_FP64_MFMA_TFLOPS = 78.6      # dense FP64 matrix-core peak of the MI355X
 
 
 def band_flops_per_patch(B: int) -> float:
     """FP64 FLOPs of the band t-product of one patch, forward and inverse: per direction the
-    band DFT and its inverse (64 x B x B each) and the slice maps (64 x 64 for the real
-    slices, four 64 x 64 real products for each complex one)."""
+    band DFT and its inverse (64 x B x B real products each) and per frequency the two 8 x 8 x 8
+    slice products (complex: 4 real multiply-adds per complex one; real for f = 0 and f = B/2)."""
     nf = B // 2 + 1
     n_real = 1 + (1 if B % 2 == 0 else 0)
-    maps = 2 * 64 * 64 * (n_real + 4 * (nf - n_real))
+    maps = 2 * 2 * 512 * (n_real + 4 * (nf - n_real))
     dft = 2 * 2 * 64 * B * B
     return 2.0 * (maps + dft)
+
+
+def band_mfma_flops_per_patch(B: int) -> float:
+    """FP64 FLOPs the matrix cores execute per patch (both directions): the band DFTs padded to
+    32 or 64 bands and every slice product as four 16 x 16 x 4 steps per patch (real 16 x 16
+    embeddings of the complex 8 x 8 matrices, also for the real slices)."""
+    nb = 32 if B <= 32 else 64
+    dft = 2 * 2 * 64 * nb * nb
+    maps = (B // 2 + 1) * 4 * (2 * 16 * 16 * 4)
+    return 2.0 * (dft + maps)
 
 
 def bench_bands(args):
@@ -605,9 +615,11 @@ def bench_bands(args):
                                % (w, h, B, sigma, B), "form": "bands"},
         "denoise_ms": round(ms_den, 3),
         "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]},
-        "roofline": {"bound": "alu", "kernel": "band filter (gemm_kernel FP64 products)", "achieved": round(tf, 3),
-                     "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_VECTOR_TFLOPS, 4),
-                     "traffic": None, "kernel_ms": round(f_avg, 4), "flop_per_launch": band_flops_per_patch(B) * n_patch},
+        "roofline": {"bound": "mfma", "kernel": "band filter stage (band_tproduct_kernel<32> forward and inverse, "
+                                                "haar_threshold_kernel<16>; FP64 matrix cores)", "achieved": round(tf, 3),
+                     "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_MFMA_TFLOPS, 4),
+                     "traffic": None, "kernel_ms": round(f_avg, 4), "flop_per_launch": band_flops_per_patch(B) * n_patch,
+                     "mfma_executed_tflops": round(band_mfma_flops_per_patch(B) * n_patch / (f_avg * 1e-3) / 1e12, 3)},
         "psnr": {"noisy": round(synth.psnr(clean, noisy), 3), "denoised": round(psnr, 3)},
         "band_wise_sigma": {"levels": "10..20, bands 5, 17, 28 at 60", "ms": round(ms_auto, 3),
                             "estimated_severe": [int(b) for b in np.nonzero(band_sig > 2 * band_sig.mean())[0]],

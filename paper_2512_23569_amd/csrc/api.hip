@@ -551,34 +551,47 @@ htsvd_status build_band_maps(int B, const double *h_U, const double *h_V, std::v
                 if (std::abs(su - t) > 1e-9 || std::abs(sv - t) > 1e-9)
                     return fail(HTSVD_EINVAL, "basis tensors are not orthogonal");
             }
-    maps.assign((size_t)2 * B * B + (size_t)NF * 2 * 4096, 0.0);
-    double *D = maps.data(), *Dinv = D + B * B, *M = Dinv + B * B;
+    const int NB = band_nb(B);
+    maps.assign((size_t)2 * NB * NB + (size_t)2 * NF * 512, 0.0);
+    double *D = maps.data(), *Dinv = D + NB * NB, *frag = Dinv + NB * NB;
     for (int b = 0; b < B; ++b) {
-        D[0 * B + b] = 1.0;
-        Dinv[b * B + 0] = 1.0 / B;
+        D[0 * NB + b] = 1.0;
+        Dinv[b * NB + 0] = 1.0 / B;
         for (int f = 1; f < NF; ++f) {
             const double a = 2.0 * M_PI * (double)((f * b) % B) / B;
             if (2 * f == B) {   // the real slice of an even band count
-                D[(B - 1) * B + b] = std::cos(a);
-                Dinv[b * B + B - 1] = std::cos(a) / B;
+                D[(B - 1) * NB + b] = std::cos(a);
+                Dinv[b * NB + B - 1] = std::cos(a) / B;
             } else {
-                D[(2 * f - 1) * B + b] = std::cos(a);
-                D[(2 * f) * B + b] = -std::sin(a);
-                Dinv[b * B + 2 * f - 1] = 2.0 * std::cos(a) / B;
-                Dinv[b * B + 2 * f] = -2.0 * std::sin(a) / B;
+                D[(2 * f - 1) * NB + b] = std::cos(a);
+                D[(2 * f) * NB + b] = -std::sin(a);
+                Dinv[b * NB + 2 * f - 1] = 2.0 * std::cos(a) / B;
+                Dinv[b * NB + 2 * f] = -2.0 * std::sin(a) / B;
             }
         }
     }
-    for (int f = 0; f < NF; ++f)
-        for (int ip = 0; ip < 8; ++ip)
-            for (int jp = 0; jp < 8; ++jp)
-                for (int i = 0; i < 8; ++i)
-                    for (int j = 0; j < 8; ++j) {
-                        const cd m = std::conj(Uh[(size_t)f * 64 + i * 8 + ip]) * Vh[(size_t)f * 64 + j * 8 + jp];
-                        const size_t o = (size_t)f * 2 * 4096 + (size_t)(ip * 8 + jp) * 64 + (i * 8 + j);
-                        M[o] = m.real();
-                        M[o + 4096] = m.imag();
-                    }
+    // Slice products of frequency f: forward T = L P with L(a, b) = conj(U(b, a)), then Y = T R with
+    // R = V; inverse L = U, R(a, b) = conj(V(b, a)).  Real embeddings: L as [[Lr, -Li], [Li, Lr]]
+    // acting on [Pr; Pi], R as [[Rr, Ri], [-Ri, Rr]] acting on [Tr | Ti] from the right.  Operand
+    // lanes of v_mfma_f64_16x16x4f64: A(m, k) in lane m + 16 (k mod 4), B(k, n) in lane n + 16 (k mod 4).
+    for (int dir = 0; dir < 2; ++dir)
+        for (int f = 0; f < NF; ++f) {
+            const cd *U = Uh.data() + (size_t)f * 64, *V = Vh.data() + (size_t)f * 64;
+            auto L = [&](int a, int b) { return dir == 0 ? std::conj(U[b * 8 + a]) : U[a * 8 + b]; };
+            auto R = [&](int a, int b) { return dir == 0 ? V[a * 8 + b] : std::conj(V[b * 8 + a]); };
+            double *fr = frag + ((size_t)dir * NF + f) * 512;
+            for (int st = 0; st < 4; ++st)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int m = lane & 15, k = 4 * st + (lane >> 4);
+                    // left factor: row m = (ri', a), column k = (ri, b)
+                    const cd l = L(m & 7, k & 7);
+                    const int rm = m >> 3, rk = k >> 3;
+                    fr[st * 64 + lane] = rm == rk ? l.real() : (rm == 0 ? -l.imag() : l.imag());
+                    // right factor: row k = (ri, a), column m = (ri', b)
+                    const cd r = R(k & 7, m & 7);
+                    fr[(4 + st) * 64 + lane] = rk == rm ? r.real() : (rk == 0 ? r.imag() : -r.imag());
+                }
+        }
     return HTSVD_OK;
 }
 
@@ -2249,9 +2262,11 @@ htsvd_status htsvd_denoise_bands(htsvd_ctx *ctx, const uint8_t *d_in, int32_t h,
     }
     const double mult = p->tau_mult > 0.0 ? p->tau_mult : std::sqrt(2.0 * std::log((double)bands * mp.K * PS * PS));
     BandMaps bm;
+    bm.nb = band_nb(bands);
     bm.D = ctx->d_band_maps;
-    bm.Dinv = bm.D + bands * bands;
-    bm.M = bm.Dinv + bands * bands;
+    bm.Dinv = bm.D + bm.nb * bm.nb;
+    bm.frag_fwd = bm.Dinv + bm.nb * bm.nb;
+    bm.frag_inv = bm.frag_fwd + (size_t)(bands / 2 + 1) * 512;
     {
         StageScope sc(ctx, HTSVD_STAGE_FILTER, st);
         if ((e = launch_band_filter(bm, d_in, in_stride, h, w, bands, idx, n_ref, mp.K, s_lo * mult, ctx->band_cap,

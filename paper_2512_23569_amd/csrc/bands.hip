@@ -1,19 +1,16 @@
 // Hyperspectral tube patches (Sec. IV-D): Haar-tSVD on an h x w x B cube with 8 x 8 x B patches.
 //
 // Grouping runs on a gray guide, the band mean rounded half up (the block matcher of the other
-// paths, Eq. 9 on one channel).  The members of every group are gathered into a patch matrix
-// X (n = group*K + member, e = 8i + j, b = band; FP64, the full-rate vector precision of this
-// device, so that keep/kill decisions agree with an FP64 reference without a guard band), and
-// the t-product S = U^T * P * V
-// (Eq. 19) is taken along the band axis through its DFT (Eq. 4-5), as three dense products:
-//   band DFT      Xd = X D^T                 (B Fourier reals Re0, Re1, Im1, ..., each stored as
-//                                             one contiguous block over the rows n*64 + e)
-//   slice maps    per frequency f, vec(S_hat_f) = M_f vec(P_hat_f), M_f((i',j'),(i,j)) =
-//                 conj(U_hat_f(i,i')) V_hat_f(j,j') (64 x 64, real for f = 0 and f = B/2)
-//   inverse DFT   S = Sd Dinv^T              (the real slices S^(k), where the threshold acts)
-// then the Haar transform along each group with the hard threshold (Eq. 20), the inverse path
-// with M_f^H (Eq. 21), and uniform aggregation (Algorithm 1) in 64-bit fixed point (exact sums,
-// so the result does not depend on the order of the additions).
+// paths, Eq. 9 on one channel).  The transform runs in FP64 (so that keep/kill decisions agree
+// with an FP64 reference without a guard band).  The t-product S = U^T * P * V (Eq. 19) is taken
+// along the band axis through its DFT (Eq. 4-5): the real band DFT of each of the 64 tubes of a
+// patch, per frequency f the 8 x 8 complex slice products U_hat_f^H P_hat_f V_hat_f, and the
+// inverse band DFT, all in one kernel per direction with the patch spectra in LDS
+// (band_tproduct_kernel).  The member coefficients S (member n at S[n*64*B + b*64 + e]) are the
+// only patch matrix in HBM: the Haar transform along each group with the hard threshold (Eq. 20)
+// works on them in place, and the inverse kernel (Eq. 21, with U_hat_f and V_hat_f^H) adds its
+// estimates to uniform aggregation sums (Algorithm 1) in 64-bit fixed point (exact sums, so the
+// result does not depend on the order of the additions).
 #include "common.h"
 
 namespace htsvd {
@@ -33,81 +30,248 @@ __global__ void guide_kernel(const uint8_t *__restrict__ cube, int64_t stride, i
     guide[q] = (uint8_t)((s + B / 2) / B);
 }
 
-// X[(n*64 + e)*B + b] = cube(y_n + i, x_n + j, b), n = r*K + k.
-__global__ void gather_kernel(const uint8_t *__restrict__ cube, int64_t stride, int w, int B,
-                              const int32_t *__restrict__ idx, int64_t n_patch, double *__restrict__ X) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= n_patch * 64 * B) return;
-    const int b = (int)(t % B);
-    const int64_t ne = t / B;
-    const int e = (int)(ne & 63);
-    const int64_t n = ne >> 6;
-    const int32_t lin = idx[n];
-    X[t] = (double)cube[(int64_t)(lin / w + (e >> 3)) * stride + (int64_t)(lin % w + (e & 7)) * B + b];
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Patches per workgroup and the LDS layout of their spectra: value (i, j) of component c of patch
+// p at Z[p*ZP + c*64 + zpos(c, i, j)].  The XOR of j with a function of i, the rotation of the odd
+// components by 16 and the patch stride of 16 modulo 32 doubles keep the accesses of the three
+// phases free of bank conflicts (64 banks of 4 bytes: a wave's 32-lane halves reach 32 distinct
+// double slots).  The inverse kernel reuses a patch's slots for its estimates as Z[p*ZP + e*ES + b]
+// (ES = 2 modulo 32), read with the band index fastest.
+template <int NB> struct BandTile {
+    static constexpr int PP = NB == 32 ? 4 : 2;        // patches per workgroup (256 threads)
+    static constexpr int HALVES = 4 / PP;              // waves sharing one patch in the DFT phases
+    static constexpr int CBW = NB / 16 / HALVES;       // 16-row blocks of the DFT outputs per wave
+    static constexpr int KS = NB / 4;                  // k-steps of a DFT product
+    static constexpr int ES = NB + 2;                  // estimate stride of the inverse kernel
+    static constexpr int ZP = ES * 64 + 16;            // doubles per patch
+};
+
+__device__ inline int zpos(int c, int i, int j) {
+    return (8 * i + (j ^ (((i >> 2) << 1) ^ (((i >> 1) & 1) << 2))) + 16 * (c & 1)) & 63;
 }
 
-// C(m, n) (+)= sum_k A(m, k) B(k, n): A(m, k) at A[m*sam + k*sak], B(k, n) at Bm[k*sbk + n*sbn],
-// C(m, n) at Cm[m*scm + n*scn]; 64 x 64 tiles, 4 x 4 outputs per thread, FP64.
-__global__ __launch_bounds__(256) void gemm_kernel(const double *__restrict__ A, int64_t sam, int64_t sak,
-                                                   const double *__restrict__ Bm, int64_t sbk, int64_t sbn,
-                                                   double *__restrict__ Cm, int64_t scm, int64_t scn, int64_t M, int N,
-                                                   int Kd, double alpha, int accumulate) {
-    __shared__ double As[16][64 + 1];
-    __shared__ double Bs[16][64 + 1];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int64_t m0 = (int64_t)blockIdx.x * 64;   // rows on x: the grid's y extent is limited
-    const int n0 = blockIdx.y * 64;
-    double acc[4][4] = {};
-    for (int k0 = 0; k0 < Kd; k0 += 16) {
-        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int kk = e / 64, mm = e % 64;
-            const int gk = k0 + kk;
-            const int64_t gm = m0 + mm;
-            As[kk][mm] = (gm < M && gk < Kd) ? A[gm * sam + (int64_t)gk * sak] : 0.0;
-            const int gn = n0 + mm;
-            Bs[kk][mm] = (gn < N && gk < Kd) ? Bm[(int64_t)gk * sbk + (int64_t)gn * sbn] : 0.0;
+// One direction of the t-product along the bands for PP patches per workgroup (Eq. 4-5, 19, 21),
+// every product on v_mfma_f64_16x16x4f64 (lanes: A(m, k) in m + 16 (k mod 4), B(k, n) in
+// n + 16 (k mod 4), result (m, n) in register m / 4 of lane n + 16 (m mod 4)):
+//   1. band DFT  Z(c, e) = sum_b D(c, b) x(b, e): D as the A operand, held in registers for the
+//      whole kernel, the patch's values at the 64 positions e as the B operand;
+//   2. per frequency f (one wave) and pair of patches, the slice products T = L * P_f and
+//      Y_f = T * R, with complex 8 x 8 matrices in their real 16 x 16 embeddings:
+//        L on the left,  [[Lr, -Li], [Li, Lr]] times P stacked as [Pr; Pi] (columns: 2 patches x 8);
+//        R on the right, T laid out as [Tr | Ti] (rows: 2 patches x 8) times [[Rr, Ri], [-Ri, Rr]];
+//      T goes back to the LDS slots of P_f and Y_f to the same slots (the slots of f belong to
+//      one wave, and its LDS accesses execute in order);
+//   3. inverse band DFT  y(b, e) = sum_c Dinv(b, c) Z(c, e), Dinv in registers.
+// Forward (INV = false): x from the cube through the group indices, L = U_hat_f^H, R = V_hat_f,
+// y stored to S[(n*B + b)*64 + e].  Inverse (INV = true): x from S, L = U_hat_f, R = V_hat_f^H,
+// y clamped and added in fixed point to the uniform aggregation sums (Algorithm 1).
+template <int NB, bool INV>
+__global__ __launch_bounds__(256) void band_tproduct_kernel(const uint8_t *__restrict__ cube, int64_t stride, int w,
+                                                            int B, const int32_t *__restrict__ idx, int64_t n_patch,
+                                                            const double *__restrict__ D,
+                                                            const double *__restrict__ Dinv,
+                                                            const double *__restrict__ frag, double *__restrict__ S,
+                                                            unsigned long long *__restrict__ acc,
+                                                            int *__restrict__ cnt) {
+    using T = BandTile<NB>;
+    constexpr int PP = T::PP, ZP = T::ZP, ES = T::ES, CBW = T::CBW, KS = T::KS;
+    __shared__ double Z[PP * ZP];
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int q = lane >> 4, col = lane & 15;
+    const int64_t n0 = (int64_t)blockIdx.x * PP;
+    // wave -> (patch, half of the 16-row output blocks) in the DFT phases
+    const int p = wave % PP, half = wave / PP;
+    const int64_t n = n0 + p;
+    const bool valid = n < n_patch;
+
+    // 1. band DFT
+    {
+        double a[CBW][KS];
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) a[cb][s] = D[(16 * (half * CBW + cb) + col) * NB + 4 * s + q];
+        const uint8_t *px = cube;
+        if (!INV && valid) {
+            const int32_t lin = idx[n];
+            px = cube + (int64_t)(lin / w) * stride + (int64_t)(lin % w) * B;
         }
-        __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            double av[4], bv[4];
+        for (int blk = 0; blk < 4; ++blk) {
+            const int e = 16 * blk + col;
+            double x[KS];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = As[kk][ty * 4 + i];
+            for (int s = 0; s < KS; ++s) {
+                const int b = 4 * s + q;
+                if (INV)
+                    x[s] = (valid && b < B) ? S[(n * B + b) * 64 + e] : 0.0;
+                else
+                    x[s] = (valid && b < B) ? (double)px[(int64_t)(e >> 3) * stride + (e & 7) * B + b] : 0.0;
+            }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx * 4 + j];
+            for (int cb = 0; cb < CBW; ++cb) {
+                dbl4 t = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int s = 0; s < KS; ++s) t = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cb][s], x[s], t, 0, 0, 0);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t gm = m0 + ty * 4 + i;
-            const int gn = n0 + tx * 4 + j;
-            if (gm < M && gn < N) {
-                double *c = Cm + gm * scm + (int64_t)gn * scn;
-                *c = accumulate ? *c + alpha * acc[i][j] : alpha * acc[i][j];
+                for (int r = 0; r < 4; ++r) {
+                    const int c = 16 * (half * CBW + cb) + q + 4 * r;
+                    if (c < B) Z[p * ZP + c * 64 + zpos(c, e >> 3, e & 7)] = t[r];
+                }
             }
         }
+    }
+    __syncthreads();
+
+    // 2. slice products on the matrix cores: wave -> frequencies f = wave (mod 4), each for every
+    //    pair of patches (the operands of f are loaded once, those of the next f ahead of use)
+    {
+        constexpr int NPAIR = PP / 2;
+        const int NF = B / 2 + 1;
+        double fr[8], nx[8];
+        if (wave < NF) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) nx[v] = frag[(size_t)wave * 512 + v * 64 + lane];
+        }
+        for (int f = wave; f < NF; f += 4) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) fr[v] = nx[v];
+            if (f + 4 < NF) {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) nx[v] = frag[(size_t)(f + 4) * 512 + v * 64 + lane];
+            }
+            const bool real = f == 0 || 2 * f == B;
+            const int cre = f == 0 ? 0 : (2 * f == B ? B - 1 : 2 * f - 1), cim = 2 * f;
+            dbl4 t[NPAIR];
+            // T = L * [Pr; Pi]: B operand rows k = 4s + q = (ri, i), columns col = (p, j)
+#pragma unroll
+            for (int pr = 0; pr < NPAIR; ++pr) {
+                const double *zb = Z + (2 * pr) * ZP;
+                double v[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int ri = s >> 1, i = 4 * (s & 1) + q, c = ri ? cim : cre;
+                    v[s] = (ri && real) ? 0.0 : zb[(col >> 3) * ZP + c * 64 + zpos(c, i, col & 7)];
+                }
+                t[pr] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < 4; ++s) t[pr] = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[s], v[s], t[pr], 0, 0, 0);
+            }
+            // result rows q + 4r = (ri', i'), columns (p, j)
+#pragma unroll
+            for (int pr = 0; pr < NPAIR; ++pr) {
+                double *zb = Z + (2 * pr) * ZP;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int ri = r >> 1, i = q + 4 * (r & 1), c = ri ? cim : cre;
+                    if (!(ri && real)) zb[(col >> 3) * ZP + c * 64 + zpos(c, i, col & 7)] = t[pr][r];
+                }
+            }
+            // Y = [Tr | Ti] * R: A operand rows col = (p, i'), columns k = 4s + q = (ri, j)
+#pragma unroll
+            for (int pr = 0; pr < NPAIR; ++pr) {
+                const double *zb = Z + (2 * pr) * ZP;
+                double v[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int ri = s >> 1, j = 4 * (s & 1) + q, c = ri ? cim : cre;
+                    v[s] = (ri && real) ? 0.0 : zb[(col >> 3) * ZP + c * 64 + zpos(c, col & 7, j)];
+                }
+                t[pr] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < 4; ++s) t[pr] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[s], fr[4 + s], t[pr], 0, 0, 0);
+            }
+            // result rows q + 4r = (p, i'), columns col = (ri', j')
+#pragma unroll
+            for (int pr = 0; pr < NPAIR; ++pr) {
+                double *zb = Z + (2 * pr) * ZP;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int pp = r >> 1, i = q + 4 * (r & 1), ri = col >> 3, c = ri ? cim : cre;
+                    if (!(ri && real)) zb[pp * ZP + c * 64 + zpos(c, i, col & 7)] = t[pr][r];
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // 3. inverse band DFT
+    double y[4][CBW][4];
+    {
+        double a[CBW][KS];
+#pragma unroll
+        for (int bb = 0; bb < CBW; ++bb)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) a[bb][s] = Dinv[(16 * (half * CBW + bb) + col) * NB + 4 * s + q];
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) {
+            const int e = 16 * blk + col;
+            double z[KS];
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int c = 4 * s + q;
+                z[s] = c < B ? Z[p * ZP + c * 64 + zpos(c, e >> 3, e & 7)] : 0.0;
+            }
+#pragma unroll
+            for (int bb = 0; bb < CBW; ++bb) {
+                dbl4 t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) t = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bb][s], z[s], t, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) y[blk][bb][r] = t[r];
+            }
+        }
+    }
+    if (!INV) {
+        if (valid) {
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+                for (int bb = 0; bb < CBW; ++bb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int b = 16 * (half * CBW + bb) + q + 4 * r;
+                        if (b < B) S[(n * B + b) * 64 + 16 * blk + col] = y[blk][bb][r];
+                    }
+        }
+        return;
+    }
+    __syncthreads();   // every spectrum read before the estimates replace it
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+        for (int bb = 0; bb < CBW; ++bb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int b = 16 * (half * CBW + bb) + q + 4 * r;
+                if (b < B) Z[p * ZP + (16 * blk + col) * ES + b] = y[blk][bb][r];
+            }
+    __syncthreads();
+    // aggregation with the band index fastest, so that a wave's atomics cover contiguous words
+    const int np = (int)std::min<int64_t>(PP, n_patch - n0);
+    for (int t = tid; t < np * 64 * B; t += 256) {
+        const int b = t % B, pe = t / B, pp = pe >> 6, ee = pe & 63;
+        const int32_t lin = idx[n0 + pp];
+        const int64_t pix = (int64_t)(lin / w + (ee >> 3)) * w + (lin % w + (ee & 7));
+        const double v = fmin(fmax(Z[pp * ZP + ee * ES + b], -1024.0), 1024.0);
+        const long long qv = __double2ll_rn(v * (double)(1 << BFS));
+        atomicAdd(acc + pix * B + b, (unsigned long long)qv);
+        if (b == 0) atomicAdd(cnt + pix, 1);
+    }
 }
 
 // Haar transform along each group (orthonormal butterflies), hard threshold |s| >= tau, inverse.
-// One thread per (group, position e, slice b); S[((g*K + k)*64 + e)*B + b].
+// One thread per (group, position q of the 64 x B values of a patch); member k of group g holds
+// position q at S[(g*K + k)*64*B + q].
 template <int K>
 __global__ void haar_threshold_kernel(double *__restrict__ S, int64_t n_group, int B, double tau) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= n_group * 64 * B) return;
-    const int b = (int)(t % B);
-    const int64_t ge = t / B;
-    const int e = (int)(ge & 63);
-    const int64_t g = ge >> 6;
-    double v[K];
     const int64_t stride_k = (int64_t)64 * B;
-    double *base = S + ((g * K) * 64 + e) * B + b;
+    if (t >= n_group * stride_k) return;
+    const int64_t g = t / stride_k, q = t % stride_k;
+    double v[K];
+    double *base = S + g * K * stride_k + q;
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = base[k * stride_k];
     constexpr double R2 = 0.70710678118654752440;
@@ -132,23 +296,6 @@ __global__ void haar_threshold_kernel(double *__restrict__ S, int64_t n_group, i
         }
 #pragma unroll
     for (int k = 0; k < K; ++k) base[k * stride_k] = v[k];
-}
-
-// Uniform aggregation in 64-bit fixed point; counts per pixel from the band-0 thread.
-__global__ void aggregate_kernel(const double *__restrict__ Pe, const int32_t *__restrict__ idx, int64_t n_patch,
-                                 int w, int B, unsigned long long *__restrict__ acc, int *__restrict__ cnt) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= n_patch * 64 * B) return;
-    const int b = (int)(t % B);
-    const int64_t ne = t / B;
-    const int e = (int)(ne & 63);
-    const int64_t n = ne >> 6;
-    const int32_t lin = idx[n];
-    const int64_t pix = (int64_t)(lin / w + (e >> 3)) * w + (lin % w + (e & 7));
-    const double v = fmin(fmax(Pe[t], -1024.0), 1024.0);
-    const long long q = __double2ll_rn(v * (double)(1 << BFS));
-    atomicAdd(acc + pix * B + b, (unsigned long long)q);
-    if (b == 0) atomicAdd(cnt + pix, 1);
 }
 
 __global__ void normalize_kernel(const unsigned long long *__restrict__ acc, const int *__restrict__ cnt,
@@ -189,45 +336,26 @@ __global__ void select_bands_kernel(const float *__restrict__ alt, int64_t alt_s
 
 unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-hipError_t gemm(const double *A, int64_t sam, int64_t sak, const double *Bm, int64_t sbk, int64_t sbn, double *Cm,
-                int64_t scm, int64_t scn, int64_t M, int N, int Kd, double alpha, bool accumulate, hipStream_t st) {
-    hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)((M + 63) / 64), nb(N, 64)), dim3(256), 0, st, A, sam, sak, Bm, sbk,
-                       sbn, Cm, scm, scn, M, N, Kd, alpha, accumulate ? 1 : 0);
+template <int NB>
+hipError_t launch_tproduct(const BandMaps &bm, bool inverse, const uint8_t *cube, int64_t stride, int w, int B,
+                           const int32_t *idx, int64_t n_patch, double *S, unsigned long long *acc, int *cnt,
+                           hipStream_t st) {
+    const unsigned grid = nb(n_patch, BandTile<NB>::PP);
+    if (inverse)
+        hipLaunchKernelGGL((band_tproduct_kernel<NB, true>), dim3(grid), dim3(256), 0, st, cube, stride, w, B, idx,
+                           n_patch, bm.D, bm.Dinv, bm.frag_inv, S, acc, cnt);
+    else
+        hipLaunchKernelGGL((band_tproduct_kernel<NB, false>), dim3(grid), dim3(256), 0, st, cube, stride, w, B, idx,
+                           n_patch, bm.D, bm.Dinv, bm.frag_fwd, S, acc, cnt);
     return hipGetLastError();
 }
 
-// One direction of the t-product on the patch matrix (rows n*64 + e, B columns):
-//   X -> Xd = X D^T -> per frequency the slice maps into Sd -> Y = Sd Dinv^T.
-// Xd and Sd hold one contiguous block of rows per Fourier component, so the slice maps read and
-// write whole rows.  Forward uses M_f, inverse M_f^H (M stored as real and imaginary 64 x 64
-// parts per slice).
-hipError_t tproduct(const BandMaps &bm, int B, int64_t n_patch, const double *X, double *Xd, double *Sd, double *Y,
-                    bool inverse, hipStream_t st) {
-    const int64_t rows = n_patch * 64;
-    hipError_t e;
-    if ((e = gemm(X, B, 1, bm.D, 1, B, Xd, 1, rows, rows, B, B, 1.0, false, st)) != hipSuccess) return e;
-    const int NF = B / 2 + 1;
-    for (int f = 0; f < NF; ++f) {
-        const double *Mr = bm.M + (size_t)f * 2 * 4096, *Mi = Mr + 4096;
-        const bool real = f == 0 || 2 * f == B;
-        const int cr = f == 0 ? 0 : 2 * f - 1, ci = 2 * f;   // columns of Re, Im of frequency f
-        // C(n, e') = sum_e A(n, e) M(e', e)  [forward]   or   M(e, e')  [inverse, M^T; M^H flips Mi's sign]
-        const int64_t sbk = inverse ? 64 : 1, sbn = inverse ? 1 : 64;
-        const double *ar = Xd + cr * rows, *ai = Xd + ci * rows;
-        double *cre = Sd + cr * rows, *cim = Sd + ci * rows;
-        if (real) {
-            if ((e = gemm(ar, 64, 1, Mr, sbk, sbn, cre, 64, 1, n_patch, 64, 64, 1.0, false, st)) != hipSuccess) return e;
-            continue;
-        }
-        const double si = inverse ? -1.0 : 1.0;   // Im of M or of M^H
-        // Re out = Mr Re - (si Mi) Im;  Im out = (si Mi) Re + Mr Im
-        if ((e = gemm(ar, 64, 1, Mr, sbk, sbn, cre, 64, 1, n_patch, 64, 64, 1.0, false, st)) != hipSuccess ||
-            (e = gemm(ai, 64, 1, Mi, sbk, sbn, cre, 64, 1, n_patch, 64, 64, -si, true, st)) != hipSuccess ||
-            (e = gemm(ar, 64, 1, Mi, sbk, sbn, cim, 64, 1, n_patch, 64, 64, si, false, st)) != hipSuccess ||
-            (e = gemm(ai, 64, 1, Mr, sbk, sbn, cim, 64, 1, n_patch, 64, 64, 1.0, true, st)) != hipSuccess)
-            return e;
-    }
-    return gemm(Sd, 1, rows, bm.Dinv, 1, B, Y, B, 1, rows, B, B, 1.0, false, st);
+hipError_t tproduct(const BandMaps &bm, bool inverse, const uint8_t *cube, int64_t stride, int w, int B,
+                    const int32_t *idx, int64_t n_patch, double *S, unsigned long long *acc, int *cnt,
+                    hipStream_t st) {
+    if (bm.nb != band_nb(B)) return hipErrorInvalidValue;
+    return B <= 32 ? launch_tproduct<32>(bm, inverse, cube, stride, w, B, idx, n_patch, S, acc, cnt, st)
+                   : launch_tproduct<64>(bm, inverse, cube, stride, w, B, idx, n_patch, S, acc, cnt, st);
 }
 
 }  // namespace
@@ -251,7 +379,7 @@ hipError_t launch_band_guide(const uint8_t *cube, int64_t stride, int h, int w, 
     return hipGetLastError();
 }
 
-// Groups per pass of the filter: each of the three FP64 patch matrices stays below cap bytes.
+// Groups per pass of the filter: the FP64 patch matrix S stays below cap bytes.
 int64_t band_chunk_groups(int B, int K, int64_t n_group, int64_t cap) {
     const int64_t per = (int64_t)K * 64 * B * (int64_t)sizeof(double);
     return std::max<int64_t>(1, std::min<int64_t>(n_group, cap / per));
@@ -260,17 +388,19 @@ int64_t band_chunk_groups(int B, int K, int64_t n_group, int64_t cap) {
 size_t band_ws_bytes(int h, int w, int B, int K, int64_t n_group, int64_t cap) {
     const int64_t n_patch = band_chunk_groups(B, K, n_group, cap) * K;
     const size_t mat = sizeof(double) * (size_t)n_patch * 64 * B;
-    return 3 * ((mat + 255) & ~(size_t)255) + (((size_t)h * w * B * 8 + 255) & ~(size_t)255) +
+    return ((mat + 255) & ~(size_t)255) + (((size_t)h * w * B * 8 + 255) & ~(size_t)255) +
            (((size_t)h * w * 4 + 255) & ~(size_t)255);
 }
 
+// Per pass: the forward t-product of every member into S, the Haar transform with the hard
+// threshold along each group, and the inverse t-product with aggregation; then normalisation.
 hipError_t launch_band_filter(const BandMaps &bm, const uint8_t *cube, int64_t stride, int h, int w, int B,
                               const int32_t *idx, int64_t n_group, int K, double tau, int64_t cap, void *ws,
                               float *out, int64_t out_stride, hipStream_t st) {
     const int64_t chunk = band_chunk_groups(B, K, n_group, cap);
     const size_t mat = ((sizeof(double) * (size_t)(chunk * K) * 64 * B) + 255) & ~(size_t)255;
-    double *X = (double *)ws, *Xd = (double *)((char *)ws + mat), *Sd = (double *)((char *)ws + 2 * mat);
-    unsigned long long *acc = (unsigned long long *)((char *)ws + 3 * mat);
+    double *S = (double *)ws;
+    unsigned long long *acc = (unsigned long long *)((char *)ws + mat);
     int *cnt = (int *)((char *)acc + (((size_t)h * w * B * 8 + 255) & ~(size_t)255));
     hipError_t e;
     if ((e = launch_zero(acc, (size_t)h * w * B * 8, st)) != hipSuccess) return e;
@@ -278,20 +408,16 @@ hipError_t launch_band_filter(const BandMaps &bm, const uint8_t *cube, int64_t s
     for (int64_t g0 = 0; g0 < n_group; g0 += chunk) {
         const int64_t ng = std::min<int64_t>(chunk, n_group - g0), n_patch = ng * K;
         const int32_t *ix = idx + g0 * K;
-        const int64_t nel = n_patch * 64 * B;
-        hipLaunchKernelGGL(gather_kernel, dim3(nb(nel, 256)), dim3(256), 0, st, cube, stride, w, B, ix, n_patch, X);
-        if ((e = tproduct(bm, B, n_patch, X, Xd, Sd, X, false, st)) != hipSuccess) return e;   // S into X
+        if ((e = tproduct(bm, false, cube, stride, w, B, ix, n_patch, S, acc, cnt, st)) != hipSuccess) return e;
         const int64_t nt = ng * 64 * B;
         switch (K) {
-            case 4: hipLaunchKernelGGL(haar_threshold_kernel<4>, dim3(nb(nt, 256)), dim3(256), 0, st, X, ng, B, tau); break;
-            case 8: hipLaunchKernelGGL(haar_threshold_kernel<8>, dim3(nb(nt, 256)), dim3(256), 0, st, X, ng, B, tau); break;
-            case 16: hipLaunchKernelGGL(haar_threshold_kernel<16>, dim3(nb(nt, 256)), dim3(256), 0, st, X, ng, B, tau); break;
-            case 32: hipLaunchKernelGGL(haar_threshold_kernel<32>, dim3(nb(nt, 256)), dim3(256), 0, st, X, ng, B, tau); break;
+            case 4: hipLaunchKernelGGL(haar_threshold_kernel<4>, dim3(nb(nt, 256)), dim3(256), 0, st, S, ng, B, tau); break;
+            case 8: hipLaunchKernelGGL(haar_threshold_kernel<8>, dim3(nb(nt, 256)), dim3(256), 0, st, S, ng, B, tau); break;
+            case 16: hipLaunchKernelGGL(haar_threshold_kernel<16>, dim3(nb(nt, 256)), dim3(256), 0, st, S, ng, B, tau); break;
+            case 32: hipLaunchKernelGGL(haar_threshold_kernel<32>, dim3(nb(nt, 256)), dim3(256), 0, st, S, ng, B, tau); break;
             default: return hipErrorInvalidValue;
         }
-        if ((e = tproduct(bm, B, n_patch, X, Xd, Sd, X, true, st)) != hipSuccess) return e;    // estimates into X
-        hipLaunchKernelGGL(aggregate_kernel, dim3(nb(nel, 256)), dim3(256), 0, st, X, ix, n_patch, w, B, acc, cnt);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = tproduct(bm, true, cube, stride, w, B, ix, n_patch, S, acc, cnt, st)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(normalize_kernel, dim3(nb((int64_t)h * w * B, 256)), dim3(256), 0, st, acc, cnt, cube, stride, h,
                        w, B, out, out_stride);

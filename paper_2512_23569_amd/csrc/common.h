@@ -40,12 +40,18 @@ struct BasisDev {
     const void *frag;  // MFMA operand fragments of the per-slice transform matrices (fp16 hi/lo)
 };
 
-// Maps of the t-product along B bands (bands.hip): the real band DFT D (B x B, rows Re0, Re1,
-// Im1, ..., and Re(B/2) last for even B), its inverse Dinv (B x B), and per frequency f <= B/2
-// the real and imaginary 64 x 64 parts of M_f((i',j'),(i,j)) = conj(U_hat_f(i,i')) V_hat_f(j,j').
+// Maps of the t-product along B bands (bands.hip): the real band DFT D (rows Re0, Re1, Im1, ...,
+// and Re(B/2) last for even B; D[c*nb + b]) and its inverse Dinv (Dinv[b*nb + c]), both nb x nb
+// with zeros beyond B, and per frequency f <= B/2 the v_mfma_f64_16x16x4f64 operands of the two
+// slice products of each direction (forward U_hat_f^H * P * V_hat_f, inverse U_hat_f * S *
+// V_hat_f^H) in their real 16 x 16 embeddings: frag[f*512 + s*64 + lane] is the left factor's A
+// operand of k-step s (s < 4) and the right factor's B operand of k-step s - 4 (s >= 4).
 struct BandMaps {
-    const double *D = nullptr, *Dinv = nullptr, *M = nullptr;
+    const double *D = nullptr, *Dinv = nullptr, *frag_fwd = nullptr, *frag_inv = nullptr;
+    int nb = 32;
 };
+// Padded band count of the band kernels: 32 for B <= 32, else 64.
+inline int band_nb(int B) { return B <= 32 ? 32 : 64; }
 
 // Device copy of the RA-Haar-tSVD refinement network for inference (ra.hip).
 struct RaWeightsDev {

@@ -37,7 +37,10 @@ def test_guide_and_groups_exact(dn, bands):
     assert np.array_equal(idx.cpu().numpy(), oi) and np.array_equal(dist.cpu().numpy(), od)
 
 
-@pytest.mark.parametrize("bands,K,sigma,s", [(31, 16, 20.0, 4), (8, 8, 30.0, 3), (5, 32, 15.0, 4), (2, 4, 25.0, 2)])
+# 32 bands fill the 32-wide band DFT of the kernel; 40 and 64 take the 64-wide one (two patches
+# per workgroup); even band counts carry the real slice f = B/2
+@pytest.mark.parametrize("bands,K,sigma,s", [(31, 16, 20.0, 4), (8, 8, 30.0, 3), (5, 32, 15.0, 4), (2, 4, 25.0, 2),
+                                             (32, 16, 20.0, 4), (40, 8, 25.0, 4), (64, 4, 20.0, 4)])
 def test_band_denoise_parity(dn, bands, K, sigma, s):
     import paper_2512_23569_amd as ht
     h, w = 56, 64
