@@ -150,68 +150,85 @@ __global__ __launch_bounds__(GR_THREADS) void gram_kernel(const uint8_t *__restr
     }
 }
 
-// The same sums for a runtime channel count C (hyperspectral bands, up to 64): every thread owns
-// one entry pair (a <= b) of the A x A matrix, A = 8C, over one of gridDim.z slices of the
-// vectors, which the block stages 64 at a time in LDS as bytes with their weights; the slices
-// are added with 64-bit integer atomics (exact, so in any order).
-constexpr int GB_CHUNK = 64;
+// The same sums for a runtime channel count C (hyperspectral bands, up to 64), taken before the
+// regrouping by column: the row sums over the vectors v = X(y..y+7, x+j, :) of every reference
+// (y, x) and offset j, the column sums over X(y+i, x..x+7, :), without weights.  A block owns a
+// 64 x 64 tile pair (ta <= tb) of the A x A matrix (A = 8C) and a slice of the vectors; it stages
+// 64 vectors at a time in LDS, the bytes of 4 consecutive vectors packed in one word per entry
+// (P[group][entry]), and each thread adds a 4 x 4 block of entries with v_dot4_u32_u8 (four
+// byte products per instruction).  Per chunk the 32-bit partial is at most 64 * 255^2; the
+// blocks add 64-bit totals with integer atomics (exact, so in any order).
+constexpr int GB_VEC = 64;            // vectors per staged chunk
+constexpr int GB_GROUPS = GB_VEC / 4;
 
 __global__ __launch_bounds__(256) void gram_bands_kernel(const uint8_t *__restrict__ img, int64_t stride, int h,
                                                          int w, int C, int s, int ny, int nx,
                                                          unsigned long long *__restrict__ out) {
-    extern __shared__ uint8_t gb_smem[];
+    __shared__ uint32_t P[2][GB_GROUPS][64];
     const int A = 8 * C;
-    uint8_t *sv = gb_smem;                                        // GB_CHUNK x A bytes
-    int *sm = reinterpret_cast<int *>(gb_smem + GB_CHUNK * A);    // GB_CHUNK weights
     const int g = blockIdx.y;
-    const int64_t n_vec = g == 0 ? (int64_t)ny * w : (int64_t)nx * h;
-    const int64_t n_pairs = (int64_t)A * (A + 1) / 2;
-    const int64_t pair = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    // pair -> (a, b), a <= b, row-major over the upper triangle
-    int a = 0, b = 0;
-    if (pair < n_pairs) {
-        int64_t rem = pair;
-        while (rem >= A - a) {
-            rem -= A - a;
-            ++a;
-        }
-        b = a + (int)rem;
+    // tile pair (ta, tb), ta <= tb, row-major over the upper triangle of the tile grid
+    const int nt = (A + 63) / 64;
+    int ta = 0, rem = blockIdx.x;
+    while (rem >= nt - ta) {
+        rem -= nt - ta;
+        ++ta;
     }
-    unsigned long long tot = 0;
-    const int64_t n_chunks = (n_vec + GB_CHUNK - 1) / GB_CHUNK;
+    const int tb = ta + rem;
+    const int64_t n_vec = (int64_t)ny * nx * 8;
+    const int64_t n_chunks = (n_vec + GB_VEC - 1) / GB_VEC;
     const int64_t c_begin = n_chunks * blockIdx.z / gridDim.z, c_end = n_chunks * (blockIdx.z + 1) / gridDim.z;
-    for (int64_t q0 = c_begin * GB_CHUNK; q0 < c_end * GB_CHUNK; q0 += GB_CHUNK) {
-        const int nv = (int)min<int64_t>(GB_CHUNK, n_vec - q0);
-        for (int e = threadIdx.x; e < nv * A; e += 256) {
-            const int v = e / A, ai = e % A, ch = ai / 8, i = ai % 8;
-            const int64_t q = q0 + v;
-            uint8_t val;
-            if (g == 0) {
-                const int iy = (int)(q / w), col = (int)(q % w);
-                val = img[(int64_t)(ref_pos(iy, ny, h, s) + i) * stride + (int64_t)col * C + ch];
-            } else {
-                const int row = (int)(q / nx), ix = (int)(q % nx);
-                val = img[(int64_t)row * stride + (int64_t)(ref_pos(ix, nx, w, s) + i) * C + ch];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    unsigned long long tot[4][4] = {};
+    for (int64_t ck = c_begin; ck < c_end; ++ck) {
+        // staging: 2 x 16 x 64 words, one per (tile side, 4-vector group, entry)
+        for (int t = threadIdx.x; t < 2 * GB_GROUPS * 64; t += 256) {
+            const int side = t / (GB_GROUPS * 64), k = (t / 64) % GB_GROUPS, ai = t % 64;
+            const int a = (side ? tb : ta) * 64 + ai;
+            const int64_t q = ck * GB_VEC + 4 * k;   // first of 4 vectors with the same reference
+            uint32_t word = 0;
+            if (a < A && q < n_vec) {
+                const int iy = (int)(q / ((int64_t)nx * 8)), rm = (int)(q % ((int64_t)nx * 8));
+                const int ix = rm / 8, off = rm % 8, ch = a / 8, e = a % 8;
+                const int y = ref_pos(iy, ny, h, s), x = ref_pos(ix, nx, w, s);
+                // g = 0: entry e is the row offset, the 4 vectors are columns x+off..x+off+3;
+                // g = 1: entry e is the column offset, the 4 vectors are rows y+off..y+off+3
+                const uint8_t *px = g == 0 ? img + (int64_t)(y + e) * stride + (int64_t)(x + off) * C + ch
+                                           : img + (int64_t)(y + off) * stride + (int64_t)(x + e) * C + ch;
+                const int64_t step = g == 0 ? C : stride;
+                word = (uint32_t)px[0] | ((uint32_t)px[step] << 8) | ((uint32_t)px[2 * step] << 16) |
+                       ((uint32_t)px[3 * step] << 24);
             }
-            sv[v * A + ai] = val;
-        }
-        for (int v = threadIdx.x; v < nv; v += 256) {
-            const int64_t q = q0 + v;
-            sm[v] = g == 0 ? cover_count((int)(q % w), w, nx, s) : cover_count((int)(q / nx), h, ny, s);
+            P[side][k][ai] = word;
         }
         __syncthreads();
-        if (pair < n_pairs) {
-            uint32_t acc = 0;   // <= 64 vectors of weight <= 9: below 2^32
-            for (int v = 0; v < nv; ++v) acc += (uint32_t)sm[v] * sv[v * A + a] * sv[v * A + b];
-            tot += acc;
+        uint32_t acc[4][4] = {};
+#pragma unroll 4
+        for (int k = 0; k < GB_GROUPS; ++k) {
+            const uint4 pa = *reinterpret_cast<const uint4 *>(&P[0][k][ty * 4]);
+            const uint4 pb = *reinterpret_cast<const uint4 *>(&P[1][k][tx * 4]);
+            const uint32_t va[4] = {pa.x, pa.y, pa.z, pa.w}, vb[4] = {pb.x, pb.y, pb.z, pb.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_udot4(va[i], vb[j], acc[i][j], false);
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tot[i][j] += acc[i][j];
         __syncthreads();
     }
-    if (pair < n_pairs && tot) {
-        unsigned long long *og = out + (size_t)g * C * C * 64;
-        atomicAdd(og + ((a / 8) * C + b / 8) * 64 + (a % 8) * 8 + b % 8, tot);
-        if (a != b) atomicAdd(og + ((b / 8) * C + a / 8) * 64 + (b % 8) * 8 + a % 8, tot);
-    }
+    unsigned long long *og = out + (size_t)g * C * C * 64;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int a = ta * 64 + ty * 4 + i, b = tb * 64 + tx * 4 + j;
+            if (a >= A || b >= A || tot[i][j] == 0) continue;
+            atomicAdd(og + ((a / 8) * C + b / 8) * 64 + (a % 8) * 8 + b % 8, tot[i][j]);
+            if (ta != tb) atomicAdd(og + ((b / 8) * C + a / 8) * 64 + (b % 8) * 8 + a % 8, tot[i][j]);
+        }
 }
 
 }  // namespace
@@ -221,17 +238,12 @@ hipError_t launch_gram(const uint8_t *img, int64_t stride, int h, int w, int c, 
     hipError_t e = launch_zero(out, sizeof(int64_t) * 2 * c * c * 64, st);
     if (e != hipSuccess) return e;
     if (c != 1 && c != 3) {
-        const int A = 8 * c;
-        const int64_t n_pairs = (int64_t)A * (A + 1) / 2;
-        const int lds = GB_CHUNK * A + GB_CHUNK * 4;
-        if ((e = prepare_dynamic_lds((const void *)gram_bands_kernel, lds, 0)) != hipSuccess) return e;
-        // enough vector slices for about 2048 workgroups, each with at least 16 chunks
-        const int64_t n_vec = std::max<int64_t>((int64_t)ny * w, (int64_t)nx * h);
-        const int64_t pair_blocks = (n_pairs + 255) / 256;
-        const int64_t zs = std::max<int64_t>(1, std::min<int64_t>((2048 + 2 * pair_blocks - 1) / (2 * pair_blocks),
-                                                                   (n_vec + 16 * GB_CHUNK - 1) / (16 * GB_CHUNK)));
-        hipLaunchKernelGGL(gram_bands_kernel, dim3((unsigned)pair_blocks, 2, (unsigned)zs), dim3(256), lds, st, img,
-                           stride, h, w, c, s, ny, nx, reinterpret_cast<unsigned long long *>(out));
+        const int nt = (8 * c + 63) / 64, n_tp = nt * (nt + 1) / 2;
+        // vector slices for about 1024 workgroups, each with at least 8 chunks
+        const int64_t n_chunks = ((int64_t)ny * nx * 8 + GB_VEC - 1) / GB_VEC;
+        const int64_t zs = std::max<int64_t>(1, std::min<int64_t>((1024 + 2 * n_tp - 1) / (2 * n_tp), n_chunks / 8));
+        hipLaunchKernelGGL(gram_bands_kernel, dim3((unsigned)n_tp, 2, (unsigned)zs), dim3(256), 0, st, img, stride, h,
+                           w, c, s, ny, nx, reinterpret_cast<unsigned long long *>(out));
         return hipGetLastError();
     }
     const int64_t n_vec = std::max<int64_t>((int64_t)ny * w, (int64_t)nx * h);
