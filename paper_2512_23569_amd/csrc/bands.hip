@@ -39,7 +39,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // double slots).  The inverse kernel reuses a patch's slots for its estimates as Z[p*ZP + e*ES + b]
 // (ES = 2 modulo 32), read with the band index fastest.
 template <int NB> struct BandTile {
-    static constexpr int PP = NB == 32 ? 4 : 2;        // patches per workgroup (256 threads)
+    static constexpr int PP = 2;                       // patches per workgroup (256 threads)
     static constexpr int HALVES = 4 / PP;              // waves sharing one patch in the DFT phases
     static constexpr int CBW = NB / 16 / HALVES;       // 16-row blocks of the DFT outputs per wave
     static constexpr int KS = NB / 4;                  // k-steps of a DFT product
