@@ -2130,41 +2130,45 @@ htsvd_status htsvd_ra_train_step(htsvd_ctx *ctx, int32_t c, const float *d_noisy
 // Band-wise noise levels (Sec. IV-D): every band through the plain sub-image estimator alone,
 // sigma_b the mean of its sub-images' estimates.  Scratch at `scratch` (band_sigma_bytes);
 // synchronises the stream to return the levels on the host.
+constexpr int BAND_SIGMA_UNITS = 4096;   // (sub-image, band) units per launch: 68 MB of moments
+
 static size_t band_sigma_bytes(int h, int w, int B, int tile) {
-    const int64_t n_tiles = (int64_t)((h + tile - 1) / tile) * ((w + tile - 1) / tile);
-    return align256((size_t)B * h * w) + align256(sizeof(double) * B * n_tiles) +
-           align256(sizeof(int32_t) * sigma_mom_ints() * n_tiles) + align256(sizeof(double) * n_tiles);
+    const int64_t units = (int64_t)((h + tile - 1) / tile) * ((w + tile - 1) / tile) * B;
+    return align256(sizeof(double) * units) +
+           align256(sizeof(int32_t) * sigma_mom_ints() * std::min<int64_t>(units, BAND_SIGMA_UNITS));
 }
 
+// The cube is estimated as one B-channel image: unit t*B + b is band b of sub-image t, the same
+// moments and eigenvalues as the band's plane alone, in launches of at most BAND_SIGMA_UNITS.
 static htsvd_status band_sigmas(const uint8_t *d_in, int h, int w, int B, int64_t in_stride, int tile, void *scratch,
                          std::vector<double> &sig, hipStream_t st) {
-    const int64_t n_tiles = (int64_t)((h + tile - 1) / tile) * ((w + tile - 1) / tile);
-    char *b = (char *)scratch;
-    uint8_t *planes = (uint8_t *)b;
-    double *est = (double *)(b + align256((size_t)B * h * w));
-    int32_t *mom = (int32_t *)((char *)est + align256(sizeof(double) * B * n_tiles));
-    double *cov = (double *)((char *)mom + align256(sizeof(int32_t) * sigma_mom_ints() * n_tiles));
-    hipError_t e = launch_band_planes(d_in, in_stride, h, w, B, planes, st);
-    if (e != hipSuccess) return hip_fail(e, "band planes");
-    for (int k = 0; k < B; ++k) {
-        ImageGeom g{};
-        g.img = planes + (int64_t)k * h * w;
-        g.stride = w;
-        g.h = h;
-        g.w = w;
-        g.c = 1;
-        if ((e = launch_sigma_est(g, tile, mom, cov, est + k * n_tiles, st)) != hipSuccess)
-            return hip_fail(e, "band noise estimate");
+    const int64_t n_tiles = (int64_t)((h + tile - 1) / tile) * ((w + tile - 1) / tile), units = n_tiles * B;
+    double *s2 = (double *)scratch;
+    int32_t *mom = (int32_t *)((char *)scratch + align256(sizeof(double) * units));
+    ImageGeom g{};
+    g.img = d_in;
+    g.stride = in_stride;
+    g.h = h;
+    g.w = w;
+    g.c = B;
+    for (int64_t u0 = 0; u0 < units; u0 += BAND_SIGMA_UNITS) {
+        const int n = (int)std::min<int64_t>(BAND_SIGMA_UNITS, units - u0);
+        hipError_t e = launch_sigma2_units(g, tile, (int)u0, n, mom, s2 + u0, st);
+        if (e != hipSuccess) return hip_fail(e, "band noise estimate");
     }
-    std::vector<double> h_est((size_t)B * n_tiles);
-    if ((e = hipMemcpyAsync(h_est.data(), est, sizeof(double) * h_est.size(), hipMemcpyDeviceToHost, st)) !=
+    std::vector<double> h_s2((size_t)units);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(h_s2.data(), s2, sizeof(double) * h_s2.size(), hipMemcpyDeviceToHost, st)) !=
             hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
         return hip_fail(e, "band noise download");
     sig.assign(B, 0.0);
     for (int k = 0; k < B; ++k) {
         double acc = 0.0;
-        for (int64_t t = 0; t < n_tiles; ++t) acc += h_est[(size_t)k * n_tiles + t];
+        for (int64_t t = 0; t < n_tiles; ++t) {
+            const double v = h_s2[(size_t)t * B + k];
+            acc += v > 0.0 ? std::sqrt(v) : 0.0;
+        }
         sig[k] = acc / (double)n_tiles;
     }
     return HTSVD_OK;

@@ -312,16 +312,6 @@ __global__ void normalize_kernel(const unsigned long long *__restrict__ acc, con
               : (float)cube[(int64_t)y * stride + (int64_t)x * B + b];
 }
 
-// Band planes: planes[(b*h + y)*w + x] = cube(y, x, b), for the band-wise noise estimate.
-__global__ void planes_kernel(const uint8_t *__restrict__ cube, int64_t stride, int h, int w, int B,
-                              uint8_t *__restrict__ planes) {
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q >= (int64_t)h * w) return;
-    const int y = (int)(q / w), x = (int)(q % w);
-    const uint8_t *p = cube + (int64_t)y * stride + (int64_t)x * B;
-    for (int b = 0; b < B; ++b) planes[(int64_t)b * h * w + q] = p[b];
-}
-
 // out(y, x, b) = alt(y, x, b) for the bands with sel[b] != 0.
 __global__ void select_bands_kernel(const float *__restrict__ alt, int64_t alt_stride, const uint8_t *__restrict__ sel,
                                     int h, int w, int B, float *__restrict__ out, int64_t out_stride) {
@@ -359,12 +349,6 @@ hipError_t tproduct(const BandMaps &bm, bool inverse, const uint8_t *cube, int64
 }
 
 }  // namespace
-
-hipError_t launch_band_planes(const uint8_t *cube, int64_t stride, int h, int w, int B, uint8_t *planes,
-                              hipStream_t st) {
-    hipLaunchKernelGGL(planes_kernel, dim3(nb((int64_t)h * w, 256)), dim3(256), 0, st, cube, stride, h, w, B, planes);
-    return hipGetLastError();
-}
 
 hipError_t launch_select_bands(const float *alt, int64_t alt_stride, const uint8_t *sel, int h, int w, int B,
                                float *out, int64_t out_stride, hipStream_t st) {

@@ -250,6 +250,10 @@ hipError_t launch_idx_prefix(const int32_t *in, int kin, int32_t *out, int kout,
 // Noise estimation (plain): per sub-image covariance eigenvalues and the tail rule.
 // mom: sigma_mom_ints() int32 per (sub-image, channel) of scratch; cov_work: c doubles per sub-image.
 int sigma_mom_ints();
+// The per-(sub-image, channel) noise variances of units unit0 .. unit0 + n_units - 1 (unit
+// t*c + ch) into sigma2[0 .. n_units); mom holds n_units * sigma_mom_ints() int32.
+hipError_t launch_sigma2_units(const ImageGeom &g, int tile, int unit0, int n_units, int32_t *mom, double *sigma2,
+                               hipStream_t st);
 hipError_t launch_sigma_est(const ImageGeom &g, int tile, int32_t *mom, double *cov_work, double *sigma_est,
                             hipStream_t st);
 hipError_t launch_vote(const ImageGeom &g, const MethodParams &mp, const int32_t *idx, int tile, int n_vote,
@@ -343,8 +347,6 @@ hipError_t launch_scale_tau(const double *tau, double *out, int64_t n, const int
 
 // Hyperspectral tube patches (bands.hip).
 hipError_t launch_band_guide(const uint8_t *cube, int64_t stride, int h, int w, int B, uint8_t *guide, hipStream_t st);
-hipError_t launch_band_planes(const uint8_t *cube, int64_t stride, int h, int w, int B, uint8_t *planes,
-                              hipStream_t st);
 hipError_t launch_select_bands(const float *alt, int64_t alt_stride, const uint8_t *sel, int h, int w, int B,
                                float *out, int64_t out_stride, hipStream_t st);
 // The filter works in chunks of groups whose FP64 patch matrices stay below cap bytes each.

@@ -318,23 +318,25 @@ __device__ inline double tile_patches(const ImageGeom &g, int T, int t) {
     return (double)(y1 - y0 + 1) * (double)(x1 - x0 + 1);
 }
 
-// One workgroup per (sub-image, channel): block u = t * c + ch.
-__global__ __launch_bounds__(256) void mom_kernel(ImageGeom g, int T, int32_t *__restrict__ mom) {
+// One workgroup per (sub-image, channel): unit u = t * c + ch = unit0 + block.
+__global__ __launch_bounds__(256) void mom_kernel(ImageGeom g, int T, int unit0, int32_t *__restrict__ mom) {
     extern __shared__ __align__(16) unsigned char smem[];
-    mom_tile(smem, g, T, blockIdx.x / g.c, blockIdx.x % g.c, mom + (int64_t)blockIdx.x * MOM_INTS);
+    const int u = unit0 + (int)blockIdx.x;
+    mom_tile(smem, g, T, u / g.c, u % g.c, mom + (int64_t)blockIdx.x * MOM_INTS);
 }
 
 // One wavefront per (sub-image, channel), EIG_WAVES per workgroup.
 constexpr int EIG_WAVES = 4;
 
-__global__ __launch_bounds__(64 * EIG_WAVES, 2) void eig_kernel(ImageGeom g, int T, int n_units,
+// Units unit0 .. unit0 + n_units - 1; mom and sigma2 indexed from unit0.
+__global__ __launch_bounds__(64 * EIG_WAVES, 2) void eig_kernel(ImageGeom g, int T, int unit0, int n_units,
                                                              const int32_t *__restrict__ mom,
                                                              double *__restrict__ sigma2) {
     __shared__ double vec[EIG_WAVES][3 * 64];
     const int wave = threadIdx.x >> 6;
     const int u = blockIdx.x * EIG_WAVES + wave;
     if (u >= n_units) return;
-    eig_tile(vec[wave], mom + (int64_t)u * MOM_INTS, tile_patches(g, T, u / g.c), sigma2 + u);
+    eig_tile(vec[wave], mom + (int64_t)u * MOM_INTS, tile_patches(g, T, (unit0 + u) / g.c), sigma2 + u);
 }
 
 // Batched: units (item, sub-image, channel) of the list; mom is indexed by the global unit.
@@ -554,19 +556,26 @@ __global__ __launch_bounds__(256) void vote_kernel_batched(const SigmaItem *__re
 int cov_lds_bytes() { return COV_LDS; }
 int sigma_mom_ints() { return MOM_INTS; }
 
+hipError_t launch_sigma2_units(const ImageGeom &g, int tile, int unit0, int n_units, int32_t *mom, double *sigma2,
+                               hipStream_t st) {
+    if (tile != 128) return hipErrorInvalidValue;
+    if (n_units <= 0) return hipSuccess;
+    const int lds = cov_lds_bytes();
+    hipError_t e = prepare_dynamic_lds((const void *)mom_kernel, lds, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mom_kernel, dim3(n_units), dim3(256), lds, st, g, tile, unit0, mom);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(eig_kernel, dim3((n_units + EIG_WAVES - 1) / EIG_WAVES), dim3(64 * EIG_WAVES), 0, st, g, tile,
+                       unit0, n_units, (const int32_t *)mom, sigma2);
+    return hipGetLastError();
+}
+
 hipError_t launch_sigma_est(const ImageGeom &g, int tile, int32_t *mom, double *work, double *sigma_est,
                             hipStream_t st) {
     if (tile != 128) return hipErrorInvalidValue;
     const int n_tiles = ((g.h + tile - 1) / tile) * ((g.w + tile - 1) / tile);
-    const int units = n_tiles * g.c;
-    const int lds = cov_lds_bytes();
-    hipError_t e = prepare_dynamic_lds((const void *)mom_kernel, lds, 0);
+    hipError_t e = launch_sigma2_units(g, tile, 0, n_tiles * g.c, mom, work, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mom_kernel, dim3(units), dim3(256), lds, st, g, tile, mom);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(eig_kernel, dim3((units + EIG_WAVES - 1) / EIG_WAVES), dim3(64 * EIG_WAVES), 0, st, g, tile,
-                       units, (const int32_t *)mom, work);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(combine_sigma_kernel, dim3((n_tiles + 255) / 256), dim3(256), 0, st, work, g.c, n_tiles,
                        sigma_est);
     return hipGetLastError();
