@@ -45,6 +45,7 @@ template <int NB> struct BandTile {
     static constexpr int KS = NB / 4;                  // k-steps of a DFT product
     static constexpr int ES = NB + 2;                  // estimate stride of the inverse kernel
     static constexpr int ZP = ES * 64 + 16;            // doubles per patch
+    static constexpr int ROWB = ((8 * NB + 15) / 16 + 1) * 16;   // staged bytes per patch row
 };
 
 __device__ inline int zpos(int c, int i, int j) {
@@ -55,7 +56,8 @@ __device__ inline int zpos(int c, int i, int j) {
 // every product on v_mfma_f64_16x16x4f64 (lanes: A(m, k) in m + 16 (k mod 4), B(k, n) in
 // n + 16 (k mod 4), result (m, n) in register m / 4 of lane n + 16 (m mod 4)):
 //   1. band DFT  Z(c, e) = sum_b D(c, b) x(b, e): D as the A operand, held in registers for the
-//      whole kernel, the patch's values at the 64 positions e as the B operand;
+//      whole kernel, the patch's values at the 64 positions e as the B operand (forward: the
+//      8 B contiguous bytes of each patch row first staged in LDS with aligned 16-byte loads);
 //   2. per frequency f (one wave) and pair of patches, the slice products T = L * P_f and
 //      Y_f = T * R, with complex 8 x 8 matrices in their real 16 x 16 embeddings:
 //        L on the left,  [[Lr, -Li], [Li, Lr]] times P stacked as [Pr; Pi] (columns: 2 patches x 8);
@@ -67,7 +69,8 @@ __device__ inline int zpos(int c, int i, int j) {
 // y stored to S[(n*B + b)*64 + e].  Inverse (INV = true): x from S, L = U_hat_f, R = V_hat_f^H,
 // y clamped and added in fixed point to the uniform aggregation sums (Algorithm 1).
 template <int NB, bool INV>
-__global__ __launch_bounds__(256) void band_tproduct_kernel(const uint8_t *__restrict__ cube, int64_t stride, int w,
+__global__ __launch_bounds__(256) void band_tproduct_kernel(const uint8_t *__restrict__ cube,
+                                                            const uint8_t *__restrict__ cube_end, int64_t stride, int w,
                                                             int B, const int32_t *__restrict__ idx, int64_t n_patch,
                                                             const double *__restrict__ D,
                                                             const double *__restrict__ Dinv,
@@ -75,8 +78,9 @@ __global__ __launch_bounds__(256) void band_tproduct_kernel(const uint8_t *__res
                                                             unsigned long long *__restrict__ acc,
                                                             int *__restrict__ cnt) {
     using T = BandTile<NB>;
-    constexpr int PP = T::PP, ZP = T::ZP, ES = T::ES, CBW = T::CBW, KS = T::KS;
+    constexpr int PP = T::PP, ZP = T::ZP, ES = T::ES, CBW = T::CBW, KS = T::KS, ROWB = T::ROWB;
     __shared__ double Z[PP * ZP];
+    __shared__ __align__(16) uint8_t stg[INV ? 16 : PP * 8 * ROWB];
     const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int q = lane >> 4, col = lane & 15;
     const int64_t n0 = (int64_t)blockIdx.x * PP;
@@ -92,10 +96,32 @@ __global__ __launch_bounds__(256) void band_tproduct_kernel(const uint8_t *__res
         for (int cb = 0; cb < CBW; ++cb)
 #pragma unroll
             for (int s = 0; s < KS; ++s) a[cb][s] = D[(16 * (half * CBW + cb) + col) * NB + 4 * s + q];
-        const uint8_t *px = cube;
-        if (!INV && valid) {
-            const int32_t lin = idx[n];
-            px = cube + (int64_t)(lin / w) * stride + (int64_t)(lin % w) * B;
+        // forward: rows of the workgroup's patches into LDS, 16-byte chunks from the aligned
+        // address below each row; a chunk not wholly inside the cube is copied byte by byte
+        uintptr_t rbase = 0;   // address of the patch's first row: row i starts (rbase + i stride) mod 16 into its slot
+        if (!INV) {
+            constexpr int CH = ROWB / 16;
+            for (int t = tid; t < PP * 8 * CH; t += 256) {
+                const int pp = t / (8 * CH), i = (t / CH) % 8, k = t % CH;
+                if (n0 + pp >= n_patch) continue;
+                const int32_t lin = idx[n0 + pp];
+                const uint8_t *seg = cube + (int64_t)(lin / w + i) * stride + (int64_t)(lin % w) * B;
+                const uint8_t *seg_end = seg + 8 * B;
+                const uint8_t *ck = (const uint8_t *)((uintptr_t)seg & ~(uintptr_t)15) + 16 * k;
+                if (ck >= seg_end) continue;
+                uint8_t *dst = stg + (pp * 8 + i) * ROWB + 16 * k;
+                if (ck >= cube && ck + 16 <= cube_end) {
+                    *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(ck);
+                } else {
+                    for (int j = 0; j < 16; ++j)
+                        if (ck + j >= seg && ck + j < seg_end) dst[j] = ck[j];
+                }
+            }
+            if (valid) {
+                const int32_t lin = idx[n];
+                rbase = (uintptr_t)(cube + (int64_t)(lin / w) * stride + (int64_t)(lin % w) * B);
+            }
+            __syncthreads();
         }
 #pragma unroll
         for (int blk = 0; blk < 4; ++blk) {
@@ -107,7 +133,10 @@ __global__ __launch_bounds__(256) void band_tproduct_kernel(const uint8_t *__res
                 if (INV)
                     x[s] = (valid && b < B) ? S[(n * B + b) * 64 + e] : 0.0;
                 else
-                    x[s] = (valid && b < B) ? (double)px[(int64_t)(e >> 3) * stride + (e & 7) * B + b] : 0.0;
+                    x[s] = (valid && b < B) ? (double)stg[(p * 8 + (e >> 3)) * ROWB +
+                                                          (int)((rbase + (uintptr_t)((e >> 3) * stride)) & 15) +
+                                                          (e & 7) * B + b]
+                                            : 0.0;
             }
 #pragma unroll
             for (int cb = 0; cb < CBW; ++cb) {
@@ -327,25 +356,26 @@ __global__ void select_bands_kernel(const float *__restrict__ alt, int64_t alt_s
 unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <int NB>
-hipError_t launch_tproduct(const BandMaps &bm, bool inverse, const uint8_t *cube, int64_t stride, int w, int B,
-                           const int32_t *idx, int64_t n_patch, double *S, unsigned long long *acc, int *cnt,
+hipError_t launch_tproduct(const BandMaps &bm, bool inverse, const uint8_t *cube, int64_t stride, int h, int w,
+                           int B, const int32_t *idx, int64_t n_patch, double *S, unsigned long long *acc, int *cnt,
                            hipStream_t st) {
     const unsigned grid = nb(n_patch, BandTile<NB>::PP);
+    const uint8_t *cube_end = cube + (int64_t)(h - 1) * stride + (int64_t)w * B;   // one past the last pixel
     if (inverse)
-        hipLaunchKernelGGL((band_tproduct_kernel<NB, true>), dim3(grid), dim3(256), 0, st, cube, stride, w, B, idx,
-                           n_patch, bm.D, bm.Dinv, bm.frag_inv, S, acc, cnt);
+        hipLaunchKernelGGL((band_tproduct_kernel<NB, true>), dim3(grid), dim3(256), 0, st, cube, cube_end, stride, w,
+                           B, idx, n_patch, bm.D, bm.Dinv, bm.frag_inv, S, acc, cnt);
     else
-        hipLaunchKernelGGL((band_tproduct_kernel<NB, false>), dim3(grid), dim3(256), 0, st, cube, stride, w, B, idx,
-                           n_patch, bm.D, bm.Dinv, bm.frag_fwd, S, acc, cnt);
+        hipLaunchKernelGGL((band_tproduct_kernel<NB, false>), dim3(grid), dim3(256), 0, st, cube, cube_end, stride, w,
+                           B, idx, n_patch, bm.D, bm.Dinv, bm.frag_fwd, S, acc, cnt);
     return hipGetLastError();
 }
 
-hipError_t tproduct(const BandMaps &bm, bool inverse, const uint8_t *cube, int64_t stride, int w, int B,
+hipError_t tproduct(const BandMaps &bm, bool inverse, const uint8_t *cube, int64_t stride, int h, int w, int B,
                     const int32_t *idx, int64_t n_patch, double *S, unsigned long long *acc, int *cnt,
                     hipStream_t st) {
     if (bm.nb != band_nb(B)) return hipErrorInvalidValue;
-    return B <= 32 ? launch_tproduct<32>(bm, inverse, cube, stride, w, B, idx, n_patch, S, acc, cnt, st)
-                   : launch_tproduct<64>(bm, inverse, cube, stride, w, B, idx, n_patch, S, acc, cnt, st);
+    return B <= 32 ? launch_tproduct<32>(bm, inverse, cube, stride, h, w, B, idx, n_patch, S, acc, cnt, st)
+                   : launch_tproduct<64>(bm, inverse, cube, stride, h, w, B, idx, n_patch, S, acc, cnt, st);
 }
 
 }  // namespace
@@ -392,7 +422,7 @@ hipError_t launch_band_filter(const BandMaps &bm, const uint8_t *cube, int64_t s
     for (int64_t g0 = 0; g0 < n_group; g0 += chunk) {
         const int64_t ng = std::min<int64_t>(chunk, n_group - g0), n_patch = ng * K;
         const int32_t *ix = idx + g0 * K;
-        if ((e = tproduct(bm, false, cube, stride, w, B, ix, n_patch, S, acc, cnt, st)) != hipSuccess) return e;
+        if ((e = tproduct(bm, false, cube, stride, h, w, B, ix, n_patch, S, acc, cnt, st)) != hipSuccess) return e;
         const int64_t nt = ng * 64 * B;
         switch (K) {
             case 4: hipLaunchKernelGGL(haar_threshold_kernel<4>, dim3(nb(nt, 256)), dim3(256), 0, st, S, ng, B, tau); break;
@@ -401,7 +431,7 @@ hipError_t launch_band_filter(const BandMaps &bm, const uint8_t *cube, int64_t s
             case 32: hipLaunchKernelGGL(haar_threshold_kernel<32>, dim3(nb(nt, 256)), dim3(256), 0, st, S, ng, B, tau); break;
             default: return hipErrorInvalidValue;
         }
-        if ((e = tproduct(bm, true, cube, stride, w, B, ix, n_patch, S, acc, cnt, st)) != hipSuccess) return e;
+        if ((e = tproduct(bm, true, cube, stride, h, w, B, ix, n_patch, S, acc, cnt, st)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(normalize_kernel, dim3(nb((int64_t)h * w * B, 256)), dim3(256), 0, st, acc, cnt, cube, stride, h,
                        w, B, out, out_stride);
