@@ -50,6 +50,8 @@ PEAK_F16_MFMA_TFLOPS = 2500.0    # MI355X dense fp16 matrix peak
 GRAM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_kernel_12mp_traffic.json")
 VIDEO_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_mfma_ga_video_7x1080p_traffic.json")
 GRAM_SRC = os.path.join(ROOT, "paper_2512_23569_amd", "csrc", "basis_learn.hip")
+BAND_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band_filter_512x512x31_traffic.json")
+BAND_SRC = os.path.join(ROOT, "paper_2512_23569_amd", "csrc", "bands.hip")
 
 
 def log(msg):
@@ -618,7 +620,8 @@ def bench_bands(args):
         "roofline": {"bound": "mfma", "kernel": "band filter stage (band_tproduct_kernel<32> forward and inverse, "
                                                 "haar_threshold_kernel<16>; FP64 matrix cores)", "achieved": round(tf, 3),
                      "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_MFMA_TFLOPS, 4),
-                     "traffic": None, "kernel_ms": round(f_avg, 4), "flop_per_launch": band_flops_per_patch(B) * n_patch,
+                     "traffic": measured_traffic(n_patch, BAND_TRAFFIC_FILE, BAND_SRC, "src_sha256_16", "n_patch"),
+                     "kernel_ms": round(f_avg, 4), "flop_per_launch": band_flops_per_patch(B) * n_patch,
                      "mfma_executed_tflops": round(band_mfma_flops_per_patch(B) * n_patch / (f_avg * 1e-3) / 1e12, 3)},
         "psnr": {"noisy": round(synth.psnr(clean, noisy), 3), "denoised": round(psnr, 3)},
         "band_wise_sigma": {"levels": "10..20, bands 5, 17, 28 at 60", "ms": round(ms_auto, 3),
