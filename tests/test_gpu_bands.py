@@ -178,3 +178,25 @@ def test_band_unaligned_strided_cube_is_identical(dn, bands):
     got = dn.denoise_bands(view, 20.0, p)
     torch.cuda.synchronize()
     assert torch.equal(got, want)
+
+
+def test_band_full_size_row_band_parity(dn):
+    """The benchmark's cube at full size (512 x 512 x 31, AWGN 30, stride 4, window 21, K 16:
+    258,064 patches in one pass): rows 248-263 of the GPU output against the oracle's groups
+    filter over every group with a member reaching those rows (the only groups that contribute
+    to them), with the oracle's learned basis installed on both sides."""
+    import paper_2512_23569_amd as ht
+    h, w, bands, sigma = 512, 512, 31, 30.0
+    clean = synth.make_hsi(h, w, bands, seed=7)
+    noisy = synth.add_awgn(clean, sigma, seed=8)
+    U, V = lb.learn(noisy, 8, 4)
+    ht.htsvd_set_basis(dn.ctx, 8, bands, oracle.to_slices(U), oracle.to_slices(V))
+    gpu = dn.denoise_bands(_dev(noisy), sigma, dn.params(1, stride=4, window=21, K=16)).cpu().numpy()
+    idx, _ = oracle.block_match(oracle.band_guide(noisy), 8, 4, 21, 16)
+    r0, r1 = 248, 264
+    rows = idx // w
+    sel = np.any((rows <= r1 - 1) & (rows + 7 >= r0), axis=1)
+    tau = sigma * np.sqrt(2.0 * np.log(bands * 16 * 64))
+    ref = oracle.filter_groups(noisy, idx[sel], U, V, tau)
+    m = assert_pixel_parity(gpu[r0:r1], ref[r0:r1], clean[r0:r1])
+    print("full-size band rows %d-%d, %d groups:" % (r0, r1 - 1, int(sel.sum())), m)
