@@ -52,6 +52,8 @@ VIDEO_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_mfma_ga_video_7x1080
 GRAM_SRC = os.path.join(ROOT, "paper_2512_23569_amd", "csrc", "basis_learn.hip")
 BAND_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band_filter_512x512x31_traffic.json")
 BAND_SRC = os.path.join(ROOT, "paper_2512_23569_amd", "csrc", "bands.hip")
+RA_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fcn_fwd_12mp_traffic.json")
+RA_SRC = os.path.join(ROOT, "paper_2512_23569_amd", "csrc", "ra.hip")
 
 
 def log(msg):
@@ -459,7 +461,8 @@ def bench_ra(dn, args, clean, noisy, d_in, d_out, p_plain, stream, s, W, sigma, 
         "plain_ms": round(ms_plain, 3),
         "roofline": {"bound": "mfma", "kernel": "fcn_fwd_kernel<3>", "achieved": round(exe_tf, 3),
                      "peak": PEAK_F16_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": round(exe_tf / PEAK_F16_MFMA_TFLOPS, 4),
-                     "traffic": None, "kernel_ms": round(ms_net, 4), "algorithmic_fp32_tflops": round(alg_tf, 3),
+                     "traffic": measured_traffic(n_ref, RA_TRAFFIC_FILE, RA_SRC, "src_sha256_16", "n_ref"),
+                     "kernel_ms": round(ms_net, 4), "algorithmic_fp32_tflops": round(alg_tf, 3),
                      "macs_per_launch": macs},
         "psnr": {"noisy": round(synth.psnr(clean, noisy), 3), "plain": round(psnr_plain, 3), "ra": round(psnr_ra, 3)},
         "input_gen_s": round(gen_s, 1),
@@ -495,6 +498,12 @@ def bench_sweep(dn, args, clean, d_in, stream, s, W, sigma, gen_s):
     ms_single = time_steps(singles, args.steps, args.warmup, stream)
     best = max(psnrs, key=psnrs.get)
     n_out = len(settings) * h * w
+    # roofline of the filter launches: mean algorithmic FLOPs of a launch over the settings
+    n_ref = ht.htsvd_ref_count(h, 8, s) * ht.htsvd_ref_count(w, 8, s)
+    f_ms, f_calls = stages["filter"]
+    f_avg = f_ms / max(f_calls, 1)
+    flop_launch = sum(filter_flops_per_group(K, c) for _, K in settings) * n_ref / len(settings)
+    tf = flop_launch / (f_avg * 1e-3) / 1e12
     log("sweep of %d settings: %.2f ms (one call each: %.2f ms), best %s %.3f dB"
         % (len(settings), ms_sweep, ms_single, best, psnrs[best]))
     result = {
@@ -516,6 +525,11 @@ def bench_sweep(dn, args, clean, d_in, stream, s, W, sigma, gen_s):
         "single_calls_ms": round(ms_single, 3),
         "speedup_vs_single_calls": round(ms_single / ms_sweep, 3),
         "stages_ms_per_launch": {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]},
+        "roofline": {"bound": "alu", "kernel": "filter_mfma_kernel<3,16> and <3,32> (five settings each)",
+                     "achieved": round(tf, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf / PEAK_FP32_VECTOR_TFLOPS, 4),
+                     "frac_unpacked_fp32": round(tf / PEAK_FP32_UNPACKED_TFLOPS, 4), "traffic": None,
+                     "kernel_ms": round(f_avg, 4), "flop_per_launch": flop_launch},
         "psnr": psnrs,
         "best_setting": best,
         "input_gen_s": round(gen_s, 1),
