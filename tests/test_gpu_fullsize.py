@@ -195,6 +195,45 @@ def test_12mp_plain_form_bands(dn, bench_img, bench_sigma, basis3):
     print("plain form: guard %s, bands %s" % (guard, res))
 
 
+def test_12mp_ra_form_bands(dn, bench_img, bench_sigma, basis3):
+    """The benchmark's RA-Haar-tSVD form (the plain form with the shipped refinement network,
+    every group above sigma 30 refined) against the oracle on two row bands: oracle groups and
+    mean patches, the FP64 network, the oracle's own thresholds."""
+    import paper_2512_23569_amd as ht
+    from oracle import fcn
+    path = os.path.join(ht.DATA_DIR, "ra_fcn_c3.f32")
+    if not os.path.exists(path):
+        pytest.skip("no trained RA network shipped")
+    w32 = np.fromfile(path, dtype="<f4")
+    ht.htsvd_ra_set_weights(dn.ctx, 3, w32)
+    clean, noisy = bench_img
+    h, w = noisy.shape[:2]
+    sp, votes = bench_sigma
+    p = dn.params(3, stride=S, window=W, K=K, adaptive=1, estimator=0, ra=1)
+    out = dn.denoise(torch.from_numpy(noisy).cuda(), -1.0, p).cpu().numpy()
+    guard = dn.guard_count()
+    assert guard[1] <= GUARD_OVERFLOW_MAX, guard
+    U, V = basis3
+    ny, nx = oracle.n_refs(h, w, PS, S)
+    m = oracle.tau_multiplier(3, K)
+    res = []
+    for y0, y1 in BANDS:
+        a, b = _ref_rows_for_band(h, y0, y1)
+        tau = est.thresholds(noisy, PS, S, W, K, tiles=_tiles_of_ref_rows(h, w, a, b), sigma_plain=sp,
+                             votes=votes)["tau"]
+        refs = np.arange(a * nx, b * nx)
+        assert np.all(np.isfinite(tau[refs])) and np.all(tau[refs] > 0)
+        tau = np.where(np.isfinite(tau), tau, 0.0)
+        gi, _ = oracle.block_match_list(noisy, refs, PS, S, W, K)
+        pest = np.zeros((ny * nx, 3 * PS * PS))
+        pest[refs] = fcn.refine(w32.astype(np.float64), fcn.group_means(noisy, gi).reshape(len(refs), -1), 3)
+        ra_on = np.zeros(ny * nx, dtype=bool)
+        ra_on[refs] = tau[refs] / m > 30.0
+        ref = oracle.denoise(noisy, U, V, tau, s=S, W=W, K=K, r_begin=a * nx, r_end=b * nx, pest=pest, ra_on=ra_on)
+        res.append(_band_parity(out, ref, clean, y0, y1) + (int(ra_on[refs].sum()), len(refs)))
+    print("RA form: guard %s, bands (frac, max, dPSNR, refined, refs) %s" % (guard, res))
+
+
 def test_12mp_batched_learned_form_bands(dn, bench_img, bench_sigma, basis3):
     """The benchmark's batched + learned form (one-image batch through the graph, learned map,
     vote, HTSVD_K_AUTO at the autotuner's cutoff) against the oracle: the group size the device
