@@ -135,6 +135,28 @@ def test_band_sigma_matches_oracle(dn, h, w, bands):
     assert np.allclose(got, want, rtol=1e-9, atol=0), (got, want)
 
 
+def test_band_sigma_full_size(dn):
+    """The benchmark's band-wise workload at full size (512 x 512 x 31, levels 10-20 with bands 5,
+    17 and 28 at 60): every band's level against the oracle."""
+    levels = np.linspace(10.0, 20.0, 31)
+    levels[[5, 17, 28]] = 60.0
+    cube = synth.add_band_awgn(synth.make_hsi(512, 512, 31, seed=7), levels, seed=9)
+    got = dn.band_sigma(_dev(cube))
+    want = oracle.band_sigma(cube)
+    assert np.allclose(got, want, rtol=1e-9, atol=0), (got, want)
+
+
+def test_band_sigma_in_several_launches(dn):
+    """1100 x 1100 x 64: 81 sub-images x 64 bands = 5,184 units, more than one launch takes, so
+    the estimates come from two launches; sampled bands against the oracle on each band alone
+    (a band's level depends on that band only)."""
+    cube = synth.add_band_awgn(synth.make_hsi(1100, 1100, 64, seed=21), np.linspace(5.0, 40.0, 64), seed=22)
+    got = dn.band_sigma(_dev(cube))
+    for k in (0, 21, 42, 63):
+        want = oracle.band_sigma(np.ascontiguousarray(cube[:, :, k:k + 1]))[0]
+        assert np.isclose(got[k], want, rtol=1e-9, atol=0), (k, got[k], want)
+
+
 @pytest.mark.parametrize("levels", [[10, 10, 12, 9, 11, 10, 10, 50], [15.0] * 6])
 def test_band_auto_denoise_parity(dn, levels):
     """sigma = AUTO: the cube filtered at the mean band level, severe bands (above twice the mean)
