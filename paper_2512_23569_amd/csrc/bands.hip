@@ -55,8 +55,8 @@ __device__ inline int zpos(int c, int i, int j) {
 // One direction of the t-product along the bands for PP patches per workgroup (Eq. 4-5, 19, 21),
 // every product on v_mfma_f64_16x16x4f64 (lanes: A(m, k) in m + 16 (k mod 4), B(k, n) in
 // n + 16 (k mod 4), result (m, n) in register m / 4 of lane n + 16 (m mod 4)):
-//   1. band DFT  Z(c, e) = sum_b D(c, b) x(b, e): D as the A operand, held in registers for the
-//      whole kernel, the patch's values at the 64 positions e as the B operand (forward: the
+//   1. band DFT  Z(c, e) = sum_b D(c, b) x(b, e): D as the A operand, held in registers across
+//      the phase, the patch's values at the 64 positions e as the B operand (forward: the
 //      8 B contiguous bytes of each patch row first staged in LDS with aligned 16-byte loads);
 //   2. per frequency f (one wave) and pair of patches, the slice products T = L * P_f and
 //      Y_f = T * R, with complex 8 x 8 matrices in their real 16 x 16 embeddings:
